@@ -1,0 +1,176 @@
+"""CPU oracle for the DBSCAN hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product library never loads it; it shares no code
+with the GPU path (its C source is compiled by gcc on its own).
+
+Functions
+---------
+dbscan(points, eps, min_pts)      labels, section 3.1 definition (C, grid +
+                                  sequential union-find, see dbscan_oracle.c)
+core_flags(points, eps, min_pts)  |N_eps(x)| >= minPts per point (C)
+neighbour_counts(points, eps)     |N_eps(x)| per point, self included (C)
+pair_count(points, eps)           number of unordered eps-pairs (C)
+morton63(points)                  the 63-bit Morton code of every point,
+                                  section 4.2.2 (numpy, plain definition)
+morton_order(codes)               stable sort permutation of the codes
+                                  (numpy's stable argsort)
+
+Status codes mirror the library's: 0 ok, -1 invalid argument, -2 non-finite
+coordinate, -3 out of memory.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dbscan_oracle.c")
+_LIB = os.path.join(_HERE, "_build", "liboracle.so")
+
+# The predicate must be evaluated exactly as written: no contraction into
+# fused multiply-adds, no fast-math, subnormals kept (x86-64 SSE, no -m flags).
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+          "-fPIC", "-shared", "-Wall", "-Wextra"]
+
+
+def build(extra_flags=(), out=None) -> str:
+    """Compile the oracle with gcc; returns the path of the shared object."""
+    out = out or _LIB
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["gcc", *CFLAGS, *extra_flags, _SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__({-1: "invalid argument", -2: "non-finite coordinate",
+                          -3: "out of memory"}.get(code, f"status {code}"))
+        self.code = code
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    path = path or _LIB
+    if not os.path.exists(path):
+        build(out=path)
+    lib = ctypes.CDLL(path)
+    f32p = ctypes.POINTER(ctypes.c_float)
+    lib.oracle_dbscan.argtypes = [f32p, ctypes.c_int64, ctypes.c_float,
+                                  ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_uint8)]
+    lib.oracle_dbscan.restype = ctypes.c_int
+    lib.oracle_neighbour_counts.argtypes = [f32p, ctypes.c_int64, ctypes.c_float,
+                                            ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_neighbour_counts.restype = ctypes.c_int
+    lib.oracle_pair_count.argtypes = [f32p, ctypes.c_int64, ctypes.c_float,
+                                      ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_pair_count.restype = ctypes.c_int
+    lib.oracle_version.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = None
+
+
+def _get():
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+def _as_points(points) -> np.ndarray:
+    p = np.ascontiguousarray(points, dtype=np.float32)
+    if p.ndim != 2 or p.shape[1] != 3:
+        raise ValueError("points must be float32[N,3]")
+    return p
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def dbscan(points, eps, min_pts, lib=None, return_core=False):
+    """Labels (int32[N], -1 for noise, else the smallest member index)."""
+    lib = lib or _get()
+    p = _as_points(points)
+    n = p.shape[0]
+    lab = np.empty(n, dtype=np.int32)
+    core = np.empty(n, dtype=np.uint8)
+    st = lib.oracle_dbscan(_ptr(p, ctypes.c_float), n, ctypes.c_float(eps),
+                           int(min_pts), _ptr(lab, ctypes.c_int32),
+                           _ptr(core, ctypes.c_uint8))
+    if st != 0:
+        raise OracleError(st)
+    return (lab, core.astype(bool)) if return_core else lab
+
+
+def core_flags(points, eps, min_pts, lib=None) -> np.ndarray:
+    return neighbour_counts(points, eps, lib) >= int(min_pts)
+
+
+def neighbour_counts(points, eps, lib=None) -> np.ndarray:
+    lib = lib or _get()
+    p = _as_points(points)
+    cnt = np.empty(p.shape[0], dtype=np.int64)
+    st = lib.oracle_neighbour_counts(_ptr(p, ctypes.c_float), p.shape[0],
+                                     ctypes.c_float(eps), _ptr(cnt, ctypes.c_int64))
+    if st != 0:
+        raise OracleError(st)
+    return cnt
+
+
+def pair_count(points, eps, lib=None) -> int:
+    lib = lib or _get()
+    p = _as_points(points)
+    out = ctypes.c_int64(0)
+    st = lib.oracle_pair_count(_ptr(p, ctypes.c_float), p.shape[0],
+                               ctypes.c_float(eps), ctypes.byref(out))
+    if st != 0:
+        raise OracleError(st)
+    return int(out.value)
+
+
+# ---- Morton codes (section 4.2.2), plain definition in numpy -------------
+
+MORTON_BITS = 21  # per axis: 3 x 21 = 63 bits of a 64-bit code
+
+
+def morton_quantise(points) -> np.ndarray:
+    """Per-axis grid coordinate q_a = min(floor((p_a - lo_a) * s_a), 2^21-1)
+    with s_a = 2^21 / (hi_a - lo_a) (s_a = 0 for a zero extent), all in
+    float32, where lo/hi are the per-axis min/max of the points (the scene
+    bounding volume of section 3.2)."""
+    p = _as_points(points)
+    lo = p.min(axis=0)
+    hi = p.max(axis=0)
+    ext = (hi - lo).astype(np.float32)
+    s = np.zeros(3, dtype=np.float32)
+    nz = ext > 0
+    s[nz] = np.float32(1 << MORTON_BITS) / ext[nz]
+    t = (p - lo).astype(np.float32) * s
+    q = np.floor(t).astype(np.int64)
+    return np.minimum(q, (1 << MORTON_BITS) - 1).astype(np.uint64)
+
+
+def morton63(points) -> np.ndarray:
+    """63-bit Morton code: bit b of the x, y, z grid coordinates goes to bit
+    3b+2, 3b+1, 3b of the code."""
+    q = morton_quantise(points)
+    code = np.zeros(q.shape[0], dtype=np.uint64)
+    for b in range(MORTON_BITS):
+        for a in range(3):
+            bit = (q[:, a] >> np.uint64(b)) & np.uint64(1)
+            code |= bit << np.uint64(3 * b + 2 - a)
+    return code
+
+
+def morton_order(codes) -> np.ndarray:
+    """Permutation sorting the codes, ties kept in input order."""
+    return np.argsort(np.asarray(codes), kind="stable")
