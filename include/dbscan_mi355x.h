@@ -1,0 +1,151 @@
+/*
+ * dbscan_mi355x.h -- C ABI of the MI355X (gfx950) DBSCAN library.
+ *
+ * The operation (Prokopenko et al., "Advances in ArborX to support exascale
+ * applications", section 3.1): given n points X in 3D, eps and minPts,
+ *   N_eps(x) = { y in X : |x - y| <= eps }   (x itself included),
+ *   x is a core point iff |N_eps(x)| >= minPts,
+ *   clusters are the sets of core points connected through eps-neighbours,
+ *   together with the non-core points within eps of one of their cores
+ *   (border points); all other points are noise.
+ * It is computed as in section 4.3.3 (FDBSCAN: a linear BVH over the points
+ * with tree traversal fused with union-find) or section 4.3.4
+ * (FDBSCAN-DenseBox: dense grid cells of side eps/sqrt(3) taken whole).
+ *
+ * Exact results.  The distance test is the binary32 evaluation of
+ * ((dx*dx + dy*dy) + dz*dz) <= fl(eps*eps), every operation rounded to
+ * nearest even, no fused multiply-add, subnormals kept.  A border point
+ * belongs to the cluster of its core neighbour with the smallest input
+ * index; a cluster is labelled with the smallest input index among its
+ * members (core and border); noise is -1.  Labels are therefore unique and
+ * identical across algorithms, block sizes and runs.
+ *
+ * Conventions for every call below:
+ *   - points are float32, row-major [n][3] (x0,y0,z0,x1,...), 4-byte aligned;
+ *     labels are int32[n]; "device" pointers are HIP device memory of the
+ *     current device, "host" pointers ordinary host memory;
+ *   - the caller owns every buffer; the library keeps no pointer after a
+ *     call returns;
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *     on it and the call returns once it has completed, so every status is
+ *     synchronous;
+ *   - the return value is a status code (DBSCAN_OK or a negative error),
+ *     never an exception; dbscan_last_error() gives a message for the
+ *     calling thread's last failure.
+ */
+#ifndef DBSCAN_MI355X_H
+#define DBSCAN_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------- */
+#define DBSCAN_OK 0
+#define DBSCAN_EINVAL (-1)     /* bad argument: null pointer with n > 0, n < 0,
+                                  n >= 2^30, eps NaN/inf/negative, eps*eps not
+                                  finite, min_pts < 1, bad option; labels untouched */
+#define DBSCAN_ENONFINITE (-2) /* a coordinate is NaN or infinite; labels unspecified */
+#define DBSCAN_ENOMEM (-3)     /* device memory allocation failed */
+#define DBSCAN_EDEVICE (-4)    /* HIP runtime error or a kernel-side failure */
+#define DBSCAN_ETOOBIG (-5)    /* the job needs more device memory than the
+                                  context's budget allows */
+
+/* ---- algorithms and options -------------------------------------------------- */
+#define DBSCAN_ALGO_AUTO 0      /* currently FDBSCAN */
+#define DBSCAN_ALGO_FDBSCAN 1   /* section 4.3.3 */
+#define DBSCAN_ALGO_DENSEBOX 2  /* section 4.3.4 */
+
+#define DBSCAN_FLAG_TIMING 1u   /* record per-phase times (dbscan_phase_times) */
+
+typedef struct dbscan_options {
+  int32_t algorithm;        /* DBSCAN_ALGO_* */
+  int32_t dense_threshold;  /* DenseBox: points that make a cell dense;
+                               0 = min_pts; values below min_pts are EINVAL */
+  int32_t block_size;       /* traversal workgroup size: 0 = default, else a
+                               multiple of 64 in [64, 1024] */
+  uint32_t flags;           /* DBSCAN_FLAG_* */
+} dbscan_options;
+
+/* A context owns device scratch memory (grown on demand up to its budget and
+ * reused by later calls) and per-phase timing events.  Not thread-safe: use
+ * one context per host thread. */
+typedef struct dbscan_ctx dbscan_ctx;
+
+/* Create a context on HIP device `device`; `hbm_budget_bytes` caps its
+ * scratch memory (0 = no cap).  Returns DBSCAN_OK and sets *out. */
+int dbscan_ctx_create(int device, uint64_t hbm_budget_bytes, dbscan_ctx** out);
+/* Release a context and its device memory (NULL is ignored). */
+int dbscan_ctx_destroy(dbscan_ctx* ctx);
+/* Bytes of scratch a job of n points needs (what admission checks). */
+uint64_t dbscan_scratch_bytes(int64_t n, int32_t min_pts, int32_t algorithm);
+
+/* Cluster n device-resident points; labels (device) in input order.
+ * Uses a per-device default context without a budget. */
+int dbscan_cluster(const float* points, int64_t n, float eps, int32_t min_pts,
+                   int32_t* labels, void* stream);
+
+/* As dbscan_cluster, with an explicit context and options (NULL = defaults). */
+int dbscan_cluster_ex(dbscan_ctx* ctx, const float* points, int64_t n, float eps,
+                      int32_t min_pts, int32_t* labels, void* stream,
+                      const dbscan_options* opts);
+
+/* Host buffers: copies points to the device, clusters, copies labels back. */
+int dbscan_cluster_host(const float* host_points, int64_t n, float eps,
+                        int32_t min_pts, int32_t* host_labels);
+
+/* Per-phase device times (ms) of the context's last call made with
+ * DBSCAN_FLAG_TIMING, in the order of dbscan_phase_name(); returns how many
+ * were written (at most max). */
+int dbscan_phase_times(const dbscan_ctx* ctx, float* ms, int32_t max);
+/* Name of phase k ("bounds_morton", "sort", ...), NULL past the last. */
+const char* dbscan_phase_name(int32_t k);
+
+/* ---- stages of the path, exposed for testing ------------------------------- */
+
+/* 63-bit Morton codes of n device points (section 4.2.2): per-axis grid
+ * coordinate min(floor((p - lo) * (2^21 / (hi - lo))), 2^21 - 1) in binary32
+ * (0 for a zero extent), lo/hi the per-axis min/max; bit b of x, y, z goes to
+ * bit 3b+2, 3b+1, 3b.  codes: device uint64[n]. */
+int dbscan_morton_codes(dbscan_ctx* ctx, const float* points, int64_t n,
+                        uint64_t* codes, void* stream);
+
+/* Stable LSD radix sort of device (keys, vals) in place by all 64 key bits;
+ * vals is a permutation carried along. */
+int dbscan_sort_pairs(dbscan_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n,
+                      void* stream);
+
+/* Build the linear BVH of n device points inside the context and copy it out
+ * (section 3.2, 4.2.1).  All outputs are device buffers:
+ *   perm   uint32[n]      input index of the leaf at each sorted position
+ *   leaf   float[n][4]    x, y, z and the leaf's rope (int bits)
+ *   nodes  float[n-1][8]  lo xyz, left (int bits), hi xyz, rope (int bits)
+ *   root   int32[1]       root reference
+ * References: k >= 0 internal node k, (j | 0x80000000) leaf j, -1 sentinel. */
+int dbscan_build_tree(dbscan_ctx* ctx, const float* points, int64_t n,
+                      uint32_t* perm, float* leaf, float* nodes, int32_t* root,
+                      void* stream);
+
+/* Core flags |N_eps(x)| >= min_pts (device uint8[n], input order), computed
+ * by the early-terminating counting traversal (sections 4.1.2, 4.3.2). */
+int dbscan_core_flags(dbscan_ctx* ctx, const float* points, int64_t n, float eps,
+                      int32_t min_pts, uint8_t* core, void* stream);
+
+/* Number of unordered pairs {i, j}, i != j, within eps, found by the pair
+ * traversal (section 4.2.3), which reports each pair exactly once.
+ * count: host pointer. */
+int dbscan_pair_count(dbscan_ctx* ctx, const float* points, int64_t n, float eps,
+                      int64_t* count, void* stream);
+
+/* ---- diagnostics ------------------------------------------------------------ */
+const char* dbscan_strerror(int status);
+const char* dbscan_last_error(void);
+const char* dbscan_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DBSCAN_MI355X_H */

@@ -1,0 +1,217 @@
+"""MI355X-native DBSCAN (FDBSCAN, section 4.3.3 of "Advances in ArborX to
+support exascale applications"), Python binding of the C ABI declared in
+``include/dbscan_mi355x.h``.
+
+Argument marshalling only: every step of the clustering runs in the HIP
+kernels of ``libdbscan_mi355x.so``.  PyTorch supplies device memory and the
+current stream.  If the shared library is missing the import of any entry
+point raises: there is no CPU fallback.
+
+    import torch, paper_2409_10743_amd as dbx
+    labels = dbx.cluster(points_cuda_f32_nx3, eps=0.2, min_pts=2)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["cluster", "Context", "DbscanError", "library_path", "load_library",
+           "PHASES", "ALGO"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libdbscan_mi355x.so"
+
+ALGO = {"auto": 0, "fdbscan": 1, "densebox": 2}
+FLAG_TIMING = 1
+STATUS = {0: "ok", -1: "invalid argument", -2: "non-finite coordinate",
+          -3: "out of device memory", -4: "device error", -5: "job exceeds budget"}
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, _LIB_NAME)
+
+
+class DbscanError(RuntimeError):
+    def __init__(self, code: int, detail: str = ""):
+        super().__init__(f"{STATUS.get(code, code)} ({code}): {detail}")
+        self.code = code
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("algorithm", ctypes.c_int32), ("dense_threshold", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          "`python -m paper_2409_10743_amd.csrc.build`")
+    L = ctypes.CDLL(path)
+    vp, i64, i32, f32, u64 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                              ctypes.c_float, ctypes.c_uint64)
+    sig = {
+        "dbscan_ctx_create": ([ctypes.c_int, u64, ctypes.POINTER(vp)], ctypes.c_int),
+        "dbscan_ctx_destroy": ([vp], ctypes.c_int),
+        "dbscan_scratch_bytes": ([i64, i32, i32], u64),
+        "dbscan_cluster": ([vp, i64, f32, i32, vp, vp], ctypes.c_int),
+        "dbscan_cluster_ex": ([vp, vp, i64, f32, i32, vp, vp, ctypes.POINTER(_Options)],
+                              ctypes.c_int),
+        "dbscan_cluster_host": ([vp, i64, f32, i32, vp], ctypes.c_int),
+        "dbscan_phase_times": ([vp, ctypes.POINTER(f32), i32], ctypes.c_int),
+        "dbscan_phase_name": ([i32], ctypes.c_char_p),
+        "dbscan_morton_codes": ([vp, vp, i64, vp, vp], ctypes.c_int),
+        "dbscan_sort_pairs": ([vp, vp, vp, i64, vp], ctypes.c_int),
+        "dbscan_build_tree": ([vp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
+        "dbscan_core_flags": ([vp, vp, i64, f32, i32, vp, vp], ctypes.c_int),
+        "dbscan_pair_count": ([vp, vp, i64, f32, ctypes.POINTER(i64), vp], ctypes.c_int),
+        "dbscan_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "dbscan_last_error": ([], ctypes.c_char_p),
+        "dbscan_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != 0:
+        raise DbscanError(code, load_library().dbscan_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _points(points):
+    torch = _torch()
+    if not isinstance(points, torch.Tensor) or not points.is_cuda:
+        raise TypeError("points must be a CUDA (HIP) torch tensor")
+    if points.dtype != torch.float32 or points.dim() != 2 or points.shape[1] != 3:
+        raise TypeError("points must be float32 [N, 3]")
+    return points.contiguous()
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(_torch().cuda.current_stream(device).cuda_stream)
+
+
+PHASES = ("bounds_morton", "sort", "gather", "build", "count", "pairs", "finalize")
+
+
+class Context:
+    """Device scratch (arena) + timing events, reused across calls."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        L = load_library()
+        h = ctypes.c_void_p()
+        _check(L.dbscan_ctx_create(int(device), int(budget_bytes), ctypes.byref(h)))
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().dbscan_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def cluster(self, points, eps: float, min_pts: int, algorithm: str = "auto",
+                block_size: int = 0, dense_threshold: int = 0, timing: bool = False,
+                out=None):
+        torch = _torch()
+        p = _points(points)
+        n = p.shape[0]
+        labels = out if out is not None else torch.empty(n, dtype=torch.int32, device=p.device)
+        o = _Options(ALGO[algorithm], int(dense_threshold), int(block_size),
+                     FLAG_TIMING if timing else 0)
+        _check(load_library().dbscan_cluster_ex(
+            self.handle, ctypes.c_void_p(p.data_ptr()), n, ctypes.c_float(eps), int(min_pts),
+            ctypes.c_void_p(labels.data_ptr()), _stream(p.device), ctypes.byref(o)))
+        return labels
+
+    def phase_times(self) -> dict:
+        buf = (ctypes.c_float * len(PHASES))()
+        k = load_library().dbscan_phase_times(self.handle, buf, len(PHASES))
+        return {PHASES[i]: float(buf[i]) for i in range(k)}
+
+    # ---- stages, for testing -------------------------------------------
+    def morton_codes(self, points):
+        torch = _torch()
+        p = _points(points)
+        codes = torch.empty(p.shape[0], dtype=torch.int64, device=p.device)
+        _check(load_library().dbscan_morton_codes(
+            self.handle, ctypes.c_void_p(p.data_ptr()), p.shape[0],
+            ctypes.c_void_p(codes.data_ptr()), _stream(p.device)))
+        return codes
+
+    def sort_pairs(self, keys, vals):
+        """Sort int64 keys (as unsigned) with int32 values, in place."""
+        torch = _torch()
+        assert keys.dtype == torch.int64 and vals.dtype == torch.int32
+        assert keys.is_contiguous() and vals.is_contiguous() and keys.numel() == vals.numel()
+        _check(load_library().dbscan_sort_pairs(
+            self.handle, ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()),
+            keys.numel(), _stream(keys.device)))
+        return keys, vals
+
+    def build_tree(self, points):
+        torch = _torch()
+        p = _points(points)
+        n = p.shape[0]
+        dev = p.device
+        perm = torch.empty(n, dtype=torch.int32, device=dev)
+        leaf = torch.empty((n, 4), dtype=torch.float32, device=dev)
+        nodes = torch.empty((max(n - 1, 1), 8), dtype=torch.float32, device=dev)
+        root = torch.empty(1, dtype=torch.int32, device=dev)
+        _check(load_library().dbscan_build_tree(
+            self.handle, ctypes.c_void_p(p.data_ptr()), n, ctypes.c_void_p(perm.data_ptr()),
+            ctypes.c_void_p(leaf.data_ptr()), ctypes.c_void_p(nodes.data_ptr()),
+            ctypes.c_void_p(root.data_ptr()), _stream(dev)))
+        return perm, leaf, nodes[: max(n - 1, 0)], root
+
+    def core_flags(self, points, eps: float, min_pts: int):
+        torch = _torch()
+        p = _points(points)
+        core = torch.empty(p.shape[0], dtype=torch.uint8, device=p.device)
+        _check(load_library().dbscan_core_flags(
+            self.handle, ctypes.c_void_p(p.data_ptr()), p.shape[0], ctypes.c_float(eps),
+            int(min_pts), ctypes.c_void_p(core.data_ptr()), _stream(p.device)))
+        return core
+
+    def pair_count(self, points, eps: float) -> int:
+        p = _points(points)
+        out = ctypes.c_int64(0)
+        _check(load_library().dbscan_pair_count(
+            self.handle, ctypes.c_void_p(p.data_ptr()), p.shape[0], ctypes.c_float(eps),
+            ctypes.byref(out), _stream(p.device)))
+        return int(out.value)
+
+
+def cluster(points, eps: float, min_pts: int, out=None):
+    """Labels (int32 CUDA tensor, input order): -1 for noise, otherwise the
+    smallest input index in the point's cluster.  Uses the device's default
+    context."""
+    torch = _torch()
+    p = _points(points)
+    n = p.shape[0]
+    labels = out if out is not None else torch.empty(n, dtype=torch.int32, device=p.device)
+    _check(load_library().dbscan_cluster(
+        ctypes.c_void_p(p.data_ptr()), n, ctypes.c_float(eps), int(min_pts),
+        ctypes.c_void_p(labels.data_ptr()), _stream(p.device)))
+    return labels

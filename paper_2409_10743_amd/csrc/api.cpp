@@ -1,0 +1,514 @@
+// C ABI and host-side pipeline of the DBSCAN library (FDBSCAN path).
+//
+// One call enqueues the whole path on the caller's stream and waits once at
+// the end for a 4-byte status word:
+//   prep -> scene bounds -> Morton codes (+ digit histograms) -> radix sort
+//   -> sorted leaves -> Apetrei build -> ropes -> [counting, minPts > 2]
+//   -> pair traversal + union-find -> labels
+// All scratch comes from the context's arena (one device allocation, grown
+// on demand, reused by later calls), so a warmed context allocates nothing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "../../include/dbscan_mi355x.h"
+#include "pipeline.hpp"
+
+using namespace dbx;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(DBSCAN_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int NPHASES = 7;
+const char* const kPhaseNames[NPHASES] = {"bounds_morton", "sort",  "gather",  "build",
+                                          "count",         "pairs", "finalize"};
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Byte offsets of every buffer of a job inside the arena.
+struct Layout {
+  size_t keys_a, keys_b, vals_a, vals_b, leaf, nodes, parent, minlab, flag, bestcore;
+  size_t zero;        // start of the region zeroed by k_prep
+  size_t hist, tile_ctr, status, count, sort_status;
+  size_t zero_words;  // 32-bit words from `zero`
+  size_t bounds, root;
+  size_t total;
+};
+
+Layout make_layout(uint32_t n, bool need_bestcore) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o += align_up(std::max<size_t>(bytes, 4)); return at; };
+  L.keys_a = take(size_t(n) * 8);
+  L.keys_b = take(size_t(n) * 8);  // after the sort: union-find scratch of the build
+  L.vals_a = take(size_t(n) * 4);
+  L.vals_b = take(size_t(n) * 4);
+  L.leaf = take(size_t(n) * 16);
+  L.nodes = take(size_t(n > 1 ? n - 1 : 1) * sizeof(Node));
+  L.parent = take(size_t(n) * 4);
+  L.minlab = take(size_t(n) * 4);
+  L.flag = take(size_t(n));
+  L.bestcore = need_bestcore ? take(size_t(n) * 8) : 0;
+  L.bounds = take(8 * 4);
+  L.root = take(4);
+  // zeroed region: hist | tile counters | status word | pair count | look-back
+  L.zero = o;
+  L.hist = take(SORT_PASSES * RADIX * 4);
+  L.tile_ctr = take(SORT_PASSES * 4);
+  L.status = take(4);
+  L.count = take(8);
+  L.sort_status = take(sort_status_words(n) * 4);
+  L.zero_words = (o - L.zero) / 4;
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct dbscan_ctx {
+  int device = 0;
+  uint64_t budget = 0;
+  char* arena = nullptr;
+  size_t cap = 0;
+  uint32_t* host_status = nullptr;  // pinned
+  hipEvent_t ev[NPHASES + 1] = {};
+  float times[NPHASES] = {};
+  int ntimes = 0;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int ensure_arena(dbscan_ctx* c, size_t bytes) {
+  if (c->budget && bytes > c->budget)
+    return fail(DBSCAN_ETOOBIG, "job needs " + std::to_string(bytes) +
+                                    " bytes of scratch, budget is " + std::to_string(c->budget));
+  if (bytes <= c->cap) return DBSCAN_OK;
+  if (c->arena) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(c->arena));
+    c->arena = nullptr;
+    c->cap = 0;
+  }
+  size_t want = bytes + bytes / 8;  // headroom so slightly larger jobs reuse it
+  if (c->budget && want > c->budget) want = bytes;
+  if (hipMalloc(&c->arena, want) != hipSuccess) {
+    (void)hipGetLastError();
+    c->arena = nullptr;
+    return fail(DBSCAN_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  }
+  c->cap = want;
+  return DBSCAN_OK;
+}
+
+int check_args(const void* pts, int64_t n, float eps, int32_t min_pts, const void* out) {
+  if (n < 0) return fail(DBSCAN_EINVAL, "n < 0");
+  if (n > int64_t(SORT_MAX_N)) return fail(DBSCAN_EINVAL, "n must be below 2^30");
+  if (n > 0 && (pts == nullptr || out == nullptr)) return fail(DBSCAN_EINVAL, "null pointer");
+  if (!(eps >= 0.0f) || std::isinf(eps)) return fail(DBSCAN_EINVAL, "eps must be finite and >= 0");
+  volatile float e2 = eps * eps;
+  if (std::isinf(e2)) return fail(DBSCAN_EINVAL, "eps*eps overflows binary32");
+  if (min_pts < 1) return fail(DBSCAN_EINVAL, "min_pts must be >= 1");
+  return DBSCAN_OK;
+}
+
+int check_opts(const dbscan_options& o, int32_t min_pts) {
+  if (o.algorithm < DBSCAN_ALGO_AUTO || o.algorithm > DBSCAN_ALGO_DENSEBOX)
+    return fail(DBSCAN_EINVAL, "unknown algorithm");
+  if (o.dense_threshold != 0 && o.dense_threshold < min_pts)
+    return fail(DBSCAN_EINVAL, "dense_threshold below min_pts");
+  if (o.block_size != 0 && (o.block_size < 64 || o.block_size > 1024 || o.block_size % 64))
+    return fail(DBSCAN_EINVAL, "block_size must be a multiple of 64 in [64, 1024]");
+  return DBSCAN_OK;
+}
+
+template <class T>
+T* at(dbscan_ctx* c, size_t off) {
+  return reinterpret_cast<T*>(c->arena + off);
+}
+
+// Everything up to and including the ropes: the BVH over the sorted points.
+struct Index {
+  Layout L;
+  uint64_t* keys;
+  uint32_t* perm;
+  float4* leaf;
+  Node* nodes;
+  int32_t* root;
+  uint32_t* status;
+};
+
+void record(dbscan_ctx* c, bool timing, int k, hipStream_t s) {
+  if (timing) (void)hipEventRecord(c->ev[k], s);
+}
+
+int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore, bool timing,
+                hipStream_t s, Index* out) {
+  Layout L = make_layout(n, need_bestcore);
+  int st = ensure_arena(c, L.total);
+  if (st != DBSCAN_OK) return st;
+  out->L = L;
+  uint64_t* ka = at<uint64_t>(c, L.keys_a);
+  uint64_t* kb = at<uint64_t>(c, L.keys_b);
+  uint32_t* va = at<uint32_t>(c, L.vals_a);
+  uint32_t* vb = at<uint32_t>(c, L.vals_b);
+  uint32_t* bounds = at<uint32_t>(c, L.bounds);
+  uint32_t* status = at<uint32_t>(c, L.status);
+  SortScratch sc{at<uint32_t>(c, L.hist), at<uint32_t>(c, L.tile_ctr),
+                 at<uint32_t>(c, L.sort_status), status};
+
+  record(c, timing, 0, s);
+  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, s);
+  launch_bounds(pts, n, bounds, status, s);
+  launch_morton(pts, n, bounds, ka, sc.hist, s);
+  record(c, timing, 1, s);
+  bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, s);
+  uint64_t* keys = in_a ? ka : kb;
+  uint32_t* perm = in_a ? va : vb;
+  // the other key buffer is free now: it holds the build's scratch
+  int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
+  int32_t* right = other + n;
+  record(c, timing, 2, s);
+  launch_gather(pts, perm, n, at<float4>(c, L.leaf), at<int32_t>(c, L.parent),
+                at<int32_t>(c, L.minlab), at<uint8_t>(c, L.flag),
+                need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr, other, s);
+  record(c, timing, 3, s);
+  launch_build(keys, at<float4>(c, L.leaf), n, at<Node>(c, L.nodes), right, other,
+               at<int32_t>(c, L.root), status, s);
+  launch_ropes(at<Node>(c, L.nodes), at<float4>(c, L.leaf), right, n, status, s);
+  record(c, timing, 4, s);
+  out->keys = keys;
+  out->perm = perm;
+  out->leaf = at<float4>(c, L.leaf);
+  out->nodes = at<Node>(c, L.nodes);
+  out->root = at<int32_t>(c, L.root);
+  out->status = status;
+  HIP_TRY(hipGetLastError());
+  return DBSCAN_OK;
+}
+
+// Wait for the stream and turn the device status word into a status code.
+int finish(dbscan_ctx* c, const uint32_t* dev_status, bool timing, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(c->host_status, dev_status, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipGetLastError());
+  if (timing) {
+    for (int k = 0; k < NPHASES; ++k) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]) != hipSuccess) ms = 0.f;
+      c->times[k] = ms;
+    }
+    c->ntimes = NPHASES;
+    (void)hipGetLastError();
+  }
+  uint32_t w = *c->host_status;
+  if (w & STATUS_NONFINITE) return fail(DBSCAN_ENONFINITE, "non-finite coordinate");
+  if (w & STATUS_SORT_STALL) return fail(DBSCAN_EDEVICE, "a sort look-back wait hit its bound");
+  if (w & STATUS_TREE) return fail(DBSCAN_EDEVICE, "malformed tree detected on the device");
+  return DBSCAN_OK;
+}
+
+int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t min_pts,
+                int32_t* labels, hipStream_t s, const dbscan_options& o) {
+  const bool timing = (o.flags & DBSCAN_FLAG_TIMING) != 0;
+  const int block = o.block_size ? o.block_size : 256;
+  const float e2 = eps * eps;
+  const bool core_mode = min_pts > 2;
+  Index ix;
+  int st = build_index(c, pts, n, core_mode, timing, s, &ix);
+  if (st != DBSCAN_OK) return st;
+  const Layout& L = ix.L;
+  uint8_t* flag = at<uint8_t>(c, L.flag);
+  int32_t* parent = at<int32_t>(c, L.parent);
+  unsigned long long* bestcore = core_mode ? at<unsigned long long>(c, L.bestcore) : nullptr;
+  if (core_mode)
+    launch_count(ix.nodes, ix.leaf, n, ix.root, e2, min_pts, flag, ix.status, block, s);
+  record(c, timing, 5, s);
+  if (core_mode)
+    launch_pairs_core(ix.nodes, ix.leaf, n, e2, flag, ix.perm, parent, bestcore, ix.status,
+                      block, s);
+  else
+    launch_pairs_fof(ix.nodes, ix.leaf, n, e2, parent, flag, ix.status, block, s);
+  record(c, timing, 6, s);
+  launch_finalize(n, min_pts, flag, bestcore, ix.perm, parent, at<int32_t>(c, L.minlab), labels, s);
+  record(c, timing, 7, s);
+  HIP_TRY(hipGetLastError());
+  return finish(c, ix.status, timing, s);
+}
+
+std::mutex g_default_mu;
+dbscan_ctx* g_default[64] = {};
+
+int default_ctx(dbscan_ctx** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(DBSCAN_EDEVICE, "device id out of range");
+  std::lock_guard<std::mutex> g(g_default_mu);
+  if (!g_default[dev]) {
+    int st = dbscan_ctx_create(dev, 0, &g_default[dev]);
+    if (st != DBSCAN_OK) return st;
+  }
+  *out = g_default[dev];
+  return DBSCAN_OK;
+}
+
+dbscan_options defaults() {
+  dbscan_options o{};
+  o.algorithm = DBSCAN_ALGO_AUTO;
+  return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dbscan_ctx_create(int device, uint64_t hbm_budget_bytes, dbscan_ctx** out) {
+  if (!out) return fail(DBSCAN_EINVAL, "null out pointer");
+  int count = 0;
+  HIP_TRY(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(DBSCAN_EINVAL, "no such device");
+  DeviceGuard g(device);
+  dbscan_ctx* c = new dbscan_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->host_status), 64) != hipSuccess) {
+    delete c;
+    return fail(DBSCAN_ENOMEM, "hipHostMalloc failed");
+  }
+  for (auto& e : c->ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      dbscan_ctx_destroy(c);
+      return fail(DBSCAN_EDEVICE, "hipEventCreate failed");
+    }
+  }
+  *out = c;
+  return DBSCAN_OK;
+}
+
+int dbscan_ctx_destroy(dbscan_ctx* c) {
+  if (!c) return DBSCAN_OK;
+  DeviceGuard g(c->device);
+  if (c->arena) (void)hipFree(c->arena);
+  if (c->host_status) (void)hipHostFree(c->host_status);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+  return DBSCAN_OK;
+}
+
+uint64_t dbscan_scratch_bytes(int64_t n, int32_t min_pts, int32_t algorithm) {
+  (void)algorithm;
+  if (n < 0 || n > int64_t(SORT_MAX_N)) return 0;
+  return make_layout(uint32_t(n), min_pts > 2).total;
+}
+
+int dbscan_cluster_ex(dbscan_ctx* c, const float* points, int64_t n, float eps, int32_t min_pts,
+                      int32_t* labels, void* stream, const dbscan_options* opts) {
+  if (!c) return fail(DBSCAN_EINVAL, "null context");
+  int st = check_args(points, n, eps, min_pts, labels);
+  if (st != DBSCAN_OK) return st;
+  dbscan_options o = opts ? *opts : defaults();
+  st = check_opts(o, min_pts);
+  if (st != DBSCAN_OK) return st;
+  if (n == 0) return DBSCAN_OK;
+  if (o.algorithm == DBSCAN_ALGO_DENSEBOX)
+    return fail(DBSCAN_EINVAL, "DenseBox is not available in this build");
+  DeviceGuard g(c->device);
+  return run_fdbscan(c, points, uint32_t(n), eps, min_pts, labels,
+                     reinterpret_cast<hipStream_t>(stream), o);
+}
+
+int dbscan_cluster(const float* points, int64_t n, float eps, int32_t min_pts, int32_t* labels,
+                   void* stream) {
+  int st = check_args(points, n, eps, min_pts, labels);
+  if (st != DBSCAN_OK || n == 0) return st;
+  dbscan_ctx* c = nullptr;
+  st = default_ctx(&c);
+  if (st != DBSCAN_OK) return st;
+  return dbscan_cluster_ex(c, points, n, eps, min_pts, labels, stream, nullptr);
+}
+
+int dbscan_cluster_host(const float* host_points, int64_t n, float eps, int32_t min_pts,
+                        int32_t* host_labels) {
+  int st = check_args(host_points, n, eps, min_pts, host_labels);
+  if (st != DBSCAN_OK || n == 0) return st;
+  float* dp = nullptr;
+  int32_t* dl = nullptr;
+  if (hipMalloc(&dp, size_t(n) * 12) != hipSuccess || hipMalloc(&dl, size_t(n) * 4) != hipSuccess) {
+    (void)hipGetLastError();
+    if (dp) (void)hipFree(dp);
+    return fail(DBSCAN_ENOMEM, "hipMalloc of the host-call buffers failed");
+  }
+  st = DBSCAN_OK;
+  if (hipMemcpy(dp, host_points, size_t(n) * 12, hipMemcpyHostToDevice) != hipSuccess)
+    st = fail(DBSCAN_EDEVICE, "host-to-device copy failed");
+  if (st == DBSCAN_OK) st = dbscan_cluster(dp, n, eps, min_pts, dl, nullptr);
+  if (st == DBSCAN_OK &&
+      hipMemcpy(host_labels, dl, size_t(n) * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    st = fail(DBSCAN_EDEVICE, "device-to-host copy failed");
+  (void)hipFree(dp);
+  (void)hipFree(dl);
+  return st;
+}
+
+int dbscan_phase_times(const dbscan_ctx* c, float* ms, int32_t max) {
+  if (!c || !ms || max < 0) return 0;
+  int k = std::min<int>(max, c->ntimes);
+  for (int i = 0; i < k; ++i) ms[i] = c->times[i];
+  return k;
+}
+
+const char* dbscan_phase_name(int32_t k) {
+  return (k >= 0 && k < NPHASES) ? kPhaseNames[k] : nullptr;
+}
+
+int dbscan_morton_codes(dbscan_ctx* c, const float* points, int64_t n, uint64_t* codes,
+                        void* stream) {
+  if (!c) return fail(DBSCAN_EINVAL, "null context");
+  int st = check_args(points, n, 0.0f, 1, codes);
+  if (st != DBSCAN_OK || n == 0) return st;
+  DeviceGuard g(c->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Layout L = make_layout(uint32_t(n), false);
+  st = ensure_arena(c, L.total);
+  if (st != DBSCAN_OK) return st;
+  uint32_t* bounds = at<uint32_t>(c, L.bounds);
+  uint32_t* status = at<uint32_t>(c, L.status);
+  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, s);
+  launch_bounds(points, uint32_t(n), bounds, status, s);
+  launch_morton(points, uint32_t(n), bounds, codes, at<uint32_t>(c, L.hist), s);
+  HIP_TRY(hipGetLastError());
+  return finish(c, status, false, s);
+}
+
+int dbscan_sort_pairs(dbscan_ctx* c, uint64_t* keys, uint32_t* vals, int64_t n, void* stream) {
+  if (!c) return fail(DBSCAN_EINVAL, "null context");
+  if (n < 0 || n > int64_t(SORT_MAX_N)) return fail(DBSCAN_EINVAL, "n out of range");
+  if (n > 0 && (!keys || !vals)) return fail(DBSCAN_EINVAL, "null pointer");
+  if (n == 0) return DBSCAN_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Layout L = make_layout(uint32_t(n), false);
+  int st = ensure_arena(c, L.total);
+  if (st != DBSCAN_OK) return st;
+  uint32_t* status = at<uint32_t>(c, L.status);
+  SortScratch sc{at<uint32_t>(c, L.hist), at<uint32_t>(c, L.tile_ctr),
+                 at<uint32_t>(c, L.sort_status), status};
+  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, at<uint32_t>(c, L.bounds), s);
+  launch_digit_histogram(keys, uint32_t(n), sc.hist, s);
+  bool in_a = launch_radix_sort(keys, at<uint64_t>(c, L.keys_b), vals, at<uint32_t>(c, L.vals_b),
+                                uint32_t(n), 0, false, sc, s);
+  if (!in_a) {
+    HIP_TRY(hipMemcpyAsync(keys, at<uint64_t>(c, L.keys_b), size_t(n) * 8,
+                           hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(vals, at<uint32_t>(c, L.vals_b), size_t(n) * 4,
+                           hipMemcpyDeviceToDevice, s));
+  }
+  HIP_TRY(hipGetLastError());
+  return finish(c, status, false, s);
+}
+
+int dbscan_build_tree(dbscan_ctx* c, const float* points, int64_t n, uint32_t* perm, float* leaf,
+                      float* nodes, int32_t* root, void* stream) {
+  if (!c) return fail(DBSCAN_EINVAL, "null context");
+  int st = check_args(points, n, 0.0f, 1, perm);
+  if (st != DBSCAN_OK) return st;
+  if (n > 0 && (!leaf || !root || (n > 1 && !nodes))) return fail(DBSCAN_EINVAL, "null pointer");
+  if (n == 0) return DBSCAN_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Index ix;
+  st = build_index(c, points, uint32_t(n), false, false, s, &ix);
+  if (st != DBSCAN_OK) return st;
+  HIP_TRY(hipMemcpyAsync(perm, ix.perm, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(leaf, ix.leaf, size_t(n) * 16, hipMemcpyDeviceToDevice, s));
+  if (n > 1)
+    HIP_TRY(hipMemcpyAsync(nodes, ix.nodes, size_t(n - 1) * sizeof(Node), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(root, ix.root, 4, hipMemcpyDeviceToDevice, s));
+  return finish(c, ix.status, false, s);
+}
+
+int dbscan_core_flags(dbscan_ctx* c, const float* points, int64_t n, float eps, int32_t min_pts,
+                      uint8_t* core, void* stream) {
+  if (!c) return fail(DBSCAN_EINVAL, "null context");
+  int st = check_args(points, n, eps, min_pts, core);
+  if (st != DBSCAN_OK || n == 0) return st;
+  DeviceGuard g(c->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Index ix;
+  st = build_index(c, points, uint32_t(n), false, false, s, &ix);
+  if (st != DBSCAN_OK) return st;
+  uint8_t* flag = at<uint8_t>(c, ix.L.flag);
+  launch_count(ix.nodes, ix.leaf, uint32_t(n), ix.root, eps * eps, min_pts, flag, ix.status,
+               256, s);
+  launch_scatter_u8(flag, ix.perm, uint32_t(n), core, s);
+  HIP_TRY(hipGetLastError());
+  return finish(c, ix.status, false, s);
+}
+
+int dbscan_pair_count(dbscan_ctx* c, const float* points, int64_t n, float eps, int64_t* count,
+                      void* stream) {
+  if (!c) return fail(DBSCAN_EINVAL, "null context");
+  int st = check_args(points, n, eps, 1, count);
+  if (st != DBSCAN_OK) return st;
+  if (n == 0) { *count = 0; return DBSCAN_OK; }
+  DeviceGuard g(c->device);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Index ix;
+  st = build_index(c, points, uint32_t(n), false, false, s, &ix);
+  if (st != DBSCAN_OK) return st;
+  unsigned long long* dcount = at<unsigned long long>(c, ix.L.count);
+  launch_pairs_count(ix.nodes, ix.leaf, uint32_t(n), eps * eps, dcount, ix.status, 256, s);
+  unsigned long long* h = reinterpret_cast<unsigned long long*>(c->host_status + 2);
+  HIP_TRY(hipMemcpyAsync(h, dcount, 8, hipMemcpyDeviceToHost, s));
+  st = finish(c, ix.status, false, s);
+  if (st == DBSCAN_OK) *count = int64_t(*h);
+  return st;
+}
+
+const char* dbscan_strerror(int status) {
+  switch (status) {
+    case DBSCAN_OK: return "ok";
+    case DBSCAN_EINVAL: return "invalid argument";
+    case DBSCAN_ENONFINITE: return "non-finite coordinate";
+    case DBSCAN_ENOMEM: return "out of device memory";
+    case DBSCAN_EDEVICE: return "device error";
+    case DBSCAN_ETOOBIG: return "job exceeds the memory budget";
+    default: return "unknown status";
+  }
+}
+
+const char* dbscan_last_error(void) { return g_last_error.c_str(); }
+
+const char* dbscan_version(void) { return "dbscan-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

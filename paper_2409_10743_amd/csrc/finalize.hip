@@ -1,0 +1,84 @@
+// Label finalisation: turn the union-find forest into one label per point,
+// in input order.  The paper leaves this step implicit; the labelling rule
+// here (section 3.1 definitions, with the border rule made deterministic):
+//   - a core point belongs to the cluster of its union-find root;
+//   - a non-core point with a core neighbour (a border point) belongs to the
+//     cluster of its smallest-input-index core neighbour;
+//   - every other point is noise, label -1;
+//   - a cluster's label is the smallest input index among its members.
+// With minPts <= 2 every point with a neighbour is core (minPts = 1: every
+// point), so there are no border points.
+#include "pipeline.hpp"
+
+namespace dbx {
+
+namespace {
+
+// Find without compression: after the pair phase the forest no longer
+// changes, so plain loads see a consistent ancestor chain.
+__device__ __forceinline__ int32_t root_of(const int32_t* parent, int32_t x) {
+  int32_t p = parent[x];
+  while (p != x) { x = p; p = parent[x]; }
+  return x;
+}
+
+// First pass: cluster root of every point (or -1), and the smallest input
+// index per root.  The root is written over parent[i]; that only shortens
+// other points' chains (a root is an ancestor), and noise points are
+// singletons nobody else's chain passes through.
+__global__ __launch_bounds__(256) void k_final_roots(
+    uint32_t n, int32_t min_pts, const uint8_t* __restrict__ flag,
+    const unsigned long long* __restrict__ bestcore, const uint32_t* __restrict__ perm,
+    int32_t* parent, int32_t* __restrict__ minlab) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t r;
+  if (min_pts <= 2) {
+    r = (min_pts == 1 || flag[i]) ? root_of(parent, int32_t(i)) : -1;
+  } else if (flag[i]) {  // core
+    r = root_of(parent, int32_t(i));
+  } else {
+    unsigned long long b = bestcore[i];
+    r = b == ~0ull ? -1 : root_of(parent, int32_t(uint32_t(b)));
+  }
+  if (r >= 0) atomicMin(minlab + r, int32_t(perm[i]));
+  parent[i] = r;
+}
+
+__global__ __launch_bounds__(256) void k_final_labels(uint32_t n, const uint32_t* __restrict__ perm,
+                                                     const int32_t* __restrict__ root,
+                                                     const int32_t* __restrict__ minlab,
+                                                     int32_t* __restrict__ labels) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t r = root[i];
+  const uint32_t o = perm[i];
+  if (o < n) labels[o] = r < 0 ? -1 : minlab[r];
+}
+
+__global__ __launch_bounds__(256) void k_scatter_u8(const uint8_t* __restrict__ src,
+                                                   const uint32_t* __restrict__ perm, uint32_t n,
+                                                   uint8_t* __restrict__ dst) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && perm[i] < n) dst[perm[i]] = src[i];
+}
+
+}  // namespace
+
+void launch_scatter_u8(const uint8_t* src, const uint32_t* perm, uint32_t n, uint8_t* dst,
+                       hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_scatter_u8, dim3((n + 255) / 256), dim3(256), 0, s, src, perm, n, dst);
+}
+
+void launch_finalize(uint32_t n, int32_t min_pts, const uint8_t* flag,
+                     const unsigned long long* bestcore, const uint32_t* perm, int32_t* parent,
+                     int32_t* minlab, int32_t* labels, hipStream_t s) {
+  if (n == 0) return;
+  const uint32_t g = (n + 255) / 256;
+  hipLaunchKernelGGL(k_final_roots, dim3(g), dim3(256), 0, s, n, min_pts, flag, bestcore, perm,
+                     parent, minlab);
+  hipLaunchKernelGGL(k_final_labels, dim3(g), dim3(256), 0, s, n, perm, parent, minlab, labels);
+}
+
+}  // namespace dbx

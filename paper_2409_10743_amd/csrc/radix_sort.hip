@@ -1,0 +1,215 @@
+// Stable LSD radix sort of (u64 key, u32 value) pairs for the Morton codes
+// of section 4.2.2 (64-bit codes make the sort "slightly" slower than 32-bit
+// ones; here it is 8 passes of 8-bit digits over 63 used bits).
+//
+// One kernel per digit pass ("onesweep"): every workgroup takes the next
+// tile id from an atomic counter, ranks its 4096 keys by digit in LDS,
+// publishes its per-digit counts, and finds the counts of all earlier tiles
+// by decoupled look-back.  Tile ids come from the counter, not blockIdx, so
+// a tile only ever waits on tiles that are already running: the wait always
+// ends.  It is also bounded: a stalled wait flags the run as failed rather
+// than spinning forever.  Keys and values are staged in LDS in digit order
+// so the global writes go out as runs of consecutive addresses.
+#include <algorithm>
+
+#include "pipeline.hpp"
+
+namespace dbx {
+
+namespace {
+
+constexpr int WAVES = SORT_THREADS / 64;
+constexpr uint32_t ST_AGG = 1u << 30;   // tile's own count published
+constexpr uint32_t ST_INC = 2u << 30;   // inclusive prefix published
+constexpr uint32_t ST_VAL = (1u << 30) - 1;
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+// Exclusive prefix sum of one value per thread over a 256-thread block.
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_tmp) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_tmp[wave] = x;
+  __syncthreads();
+  uint32_t add = 0;
+  for (int w = 0; w < wave; ++w) add += s_tmp[w];
+  __syncthreads();
+  return x - v + add;
+}
+
+__global__ __launch_bounds__(256) void k_digit_hist(const uint64_t* __restrict__ keys,
+                                                   uint32_t n, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t sh[SORT_PASSES * RADIX];
+  for (int t = threadIdx.x; t < SORT_PASSES * RADIX; t += blockDim.x) sh[t] = 0;
+  __syncthreads();
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    uint64_t k = keys[i];
+#pragma unroll
+    for (int p = 0; p < SORT_PASSES; ++p)
+      atomicAdd(&sh[p * RADIX + ((k >> (8 * p)) & 0xff)], 1u);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < SORT_PASSES * RADIX; t += blockDim.x)
+    if (sh[t]) atomicAdd(&hist[t], sh[t]);
+}
+
+template <bool IOTA>
+__global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
+    const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout,
+    const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout, uint32_t n,
+    int shift, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
+    uint32_t* __restrict__ tile_ctr, uint32_t* __restrict__ err) {
+  __shared__ uint64_t s_keys[SORT_TILE];
+  __shared__ uint32_t s_vals[SORT_TILE];
+  __shared__ uint32_t s_whist[WAVES][RADIX];  // per-wave digit counts, then prefixes
+  __shared__ uint32_t s_base[RADIX];          // global offset - local offset
+  __shared__ uint32_t s_loff[RADIX];          // local (in-tile) digit offsets
+  __shared__ uint32_t s_tmp[WAVES];
+  __shared__ uint32_t s_tile;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
+  for (int w = 0; w < WAVES; ++w) s_whist[w][tid] = 0;
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  const uint32_t tile_base = tile * SORT_TILE;
+  const uint32_t wbase = tile_base + wave * (64 * SORT_ITEMS);
+
+  uint64_t key[SORT_ITEMS];
+  uint32_t val[SORT_ITEMS];
+  uint32_t rank[SORT_ITEMS];
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+#pragma unroll
+  for (int k = 0; k < SORT_ITEMS; ++k) {
+    uint32_t idx = wbase + k * 64 + lane;
+    bool ok = idx < n;
+    key[k] = ok ? kin[idx] : ~0ull;
+    val[k] = ok ? (IOTA ? idx : vin[idx]) : 0u;
+  }
+
+  // rank each key among the keys of this wave with the same digit; the
+  // order of keys inside a wave is (item, lane), i.e. their input order
+#pragma unroll
+  for (int k = 0; k < SORT_ITEMS; ++k) {
+    uint32_t idx = wbase + k * 64 + lane;
+    bool ok = idx < n;
+    uint32_t d = uint32_t(key[k] >> shift) & 0xff;
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      uint64_t m = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? m : ~m;
+    }
+    int leader = ok ? 63 - __clzll(peers) : lane;
+    uint32_t old = 0;
+    if (ok && lane == leader) {
+      old = s_whist[wave][d];
+      s_whist[wave][d] = old + __popcll(peers);
+    }
+    old = __shfl(old, leader, 64);
+    rank[k] = old + __popcll(peers & lt_mask);
+  }
+  __syncthreads();
+
+  // per digit (one thread each): wave prefixes, tile count, look-back
+  const int d = tid;
+  uint32_t total = 0;
+#pragma unroll
+  for (int w = 0; w < WAVES; ++w) {
+    uint32_t c = s_whist[w][d];
+    s_whist[w][d] = total;
+    total += c;
+  }
+  uint32_t excl = 0;
+  uint32_t* st = status + size_t(tile) * RADIX + d;
+  if (tile == 0) {
+    st_agent(st, ST_INC | total);
+  } else {
+    st_agent(st, ST_AGG | total);
+    int32_t j = int32_t(tile) - 1;
+    uint32_t spins = 0;
+    while (j >= 0) {
+      uint32_t v = ld_agent(status + size_t(j) * RADIX + d);
+      uint32_t f = v & ~ST_VAL;
+      if (f == 0) {
+        if (++spins > SPIN_LIMIT) { atomicOr(err, STATUS_SORT_STALL); break; }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      excl += v & ST_VAL;
+      if (f == ST_INC) break;
+      --j;
+    }
+    st_agent(st, ST_INC | ((excl + total) & ST_VAL));
+  }
+  // global digit start for this pass: exclusive scan of the digit counts
+  uint32_t gstart = block_exclusive_scan(ghist[d], s_tmp);
+  uint32_t loff = block_exclusive_scan(total, s_tmp);
+  s_loff[d] = loff;
+  s_base[d] = gstart + excl - loff;
+  __syncthreads();
+
+  // stage keys and values in digit order
+#pragma unroll
+  for (int k = 0; k < SORT_ITEMS; ++k) {
+    uint32_t idx = wbase + k * 64 + lane;
+    if (idx < n) {
+      uint32_t dd = uint32_t(key[k] >> shift) & 0xff;
+      uint32_t p = s_loff[dd] + s_whist[wave][dd] + rank[k];
+      s_keys[p] = key[k];
+      s_vals[p] = val[k];
+    }
+  }
+  __syncthreads();
+  const uint32_t tile_n = min(uint32_t(SORT_TILE), n - tile_base);
+  for (uint32_t p = tid; p < tile_n; p += SORT_THREADS) {
+    uint64_t kk = s_keys[p];
+    uint32_t dd = uint32_t(kk >> shift) & 0xff;
+    uint32_t dst = s_base[dd] + p;
+    if (dst < n) {  // always true unless a look-back wait was cut short
+      kout[dst] = kk;
+      vout[dst] = s_vals[p];
+    }
+  }
+}
+
+}  // namespace
+
+void launch_digit_histogram(const uint64_t* keys, uint32_t n, uint32_t* hist,
+                            hipStream_t s) {
+  if (n == 0) return;
+  uint32_t blocks = std::min((n + 255) / 256, 2048u);
+  hipLaunchKernelGGL(k_digit_hist, dim3(blocks), dim3(256), 0, s, keys, n, hist);
+}
+
+bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
+                       uint32_t n, int first_pass, bool iota_vals,
+                       const SortScratch& sc, hipStream_t s) {
+  bool in_a = true;
+  if (n == 0) return true;
+  const uint32_t tiles = sort_tiles(n);
+  for (int p = first_pass; p < SORT_PASSES; ++p) {
+    const uint64_t* kin = in_a ? ka : kb;
+    uint64_t* kout = in_a ? kb : ka;
+    const uint32_t* vin = in_a ? va : vb;
+    uint32_t* vout = in_a ? vb : va;
+    uint32_t* st = sc.status + size_t(p) * tiles * RADIX;
+    if (p == first_pass && iota_vals)
+      hipLaunchKernelGGL(k_onesweep<true>, dim3(tiles), dim3(SORT_THREADS), 0, s, kin,
+                         kout, vin, vout, n, 8 * p, sc.hist + p * RADIX, st,
+                         sc.tile_ctr + p, sc.err);
+    else
+      hipLaunchKernelGGL(k_onesweep<false>, dim3(tiles), dim3(SORT_THREADS), 0, s, kin,
+                         kout, vin, vout, n, 8 * p, sc.hist + p * RADIX, st,
+                         sc.tile_ctr + p, sc.err);
+    in_a = !in_a;
+  }
+  return in_a;
+}
+
+}  // namespace dbx

@@ -1,0 +1,282 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Integer / index / label outputs must match bit for bit.  Stages are checked
+first (Morton codes, sort, tree structure, pair count, core flags) so that a
+failure names the stage, then full labels on hand-built, boundary, seeded
+and full-size inputs.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+torch = pytest.importorskip("torch")
+import paper_2409_10743_amd as dbx  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+F32 = np.float32
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = dbx.Context(0)
+    yield c
+    c.close()
+
+
+def dev(p):
+    return torch.from_numpy(np.ascontiguousarray(p, dtype=F32)).cuda()
+
+
+def run(ctx, p, eps, mp, **kw):
+    return ctx.cluster(dev(p), float(eps), mp, **kw).cpu().numpy()
+
+
+def clumpy(n, seed, k=8):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cen = rng.random((k, 3))
+    p = cen[rng.integers(0, k, n)] + rng.standard_normal((n, 3)) * 0.02
+    m = n // 5
+    p[:m] = rng.random((m, 3))
+    return p[rng.permutation(n)].astype(F32)
+
+
+SIZES = [1, 2, 3, 64, 255, 4095, 4096, 4097, 50001]
+
+
+# ---- stages ----------------------------------------------------------------
+
+@pytest.mark.parametrize("n", SIZES + [300007])
+def test_morton_codes_match_oracle(ctx, n):
+    p = clumpy(n, n)
+    got = ctx.morton_codes(dev(p)).cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(got, oracle.morton63(p))
+
+
+def test_morton_zero_extent_axis(ctx):
+    p = clumpy(5000, 9)
+    p[:, 1] = F32(3.5)
+    got = ctx.morton_codes(dev(p)).cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(got, oracle.morton63(p))
+
+
+@pytest.mark.parametrize("n", [1, 5, 4096, 4097, 12345, 1 << 20])
+def test_sort_is_stable_and_complete(ctx, n):
+    rng = np.random.Generator(np.random.PCG64(n))
+    keys = rng.integers(0, 2 ** 63, n, dtype=np.uint64)
+    keys[: n // 3] = keys[rng.integers(0, max(1, n // 50), n // 3)]   # many ties
+    if n > 10:
+        keys[5] = np.uint64(2 ** 64 - 1)                               # top bit set
+    vals = np.arange(n, dtype=np.int32)[rng.permutation(n)]
+    k = torch.from_numpy(keys.view(np.int64).copy()).cuda()
+    v = torch.from_numpy(vals.copy()).cuda()
+    ctx.sort_pairs(k, v)
+    order = np.argsort(keys, kind="stable")
+    np.testing.assert_array_equal(k.cpu().numpy().view(np.uint64), keys[order])
+    np.testing.assert_array_equal(v.cpu().numpy(), vals[order])
+
+
+def _walk(nodes, leaf, root, n):
+    """Pre-order walk that always descends: internal -> left child, leaf ->
+    its rope.  Returns the visit sequence (node refs)."""
+    left = nodes[:, 3].view(np.int32) if n > 1 else None
+    lrope = leaf[:, 3].view(np.int32)
+    seq = []
+    node = int(root)
+    while node != -1:
+        seq.append(node)
+        if len(seq) > 2 * n + 5:
+            raise AssertionError("walk does not terminate")
+        node = int(lrope[node & 0x7FFFFFFF]) if node < -1 else int(left[node])
+    return seq
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 4097, 50001])
+def test_tree_structure(ctx, n):
+    p = clumpy(n, 100 + n)
+    perm, leaf, nodes, root = ctx.build_tree(dev(p))
+    perm, leaf, nodes = perm.cpu().numpy(), leaf.cpu().numpy(), nodes.cpu().numpy()
+    root = int(root.cpu().numpy()[0])
+    # leaves are the points in stable Morton order
+    np.testing.assert_array_equal(perm, oracle.morton_order(oracle.morton63(p)))
+    np.testing.assert_array_equal(leaf[:, :3], p[perm])
+    seq = _walk(nodes, leaf, root, n)
+    assert len(seq) == 2 * n - 1
+    lv = [s & 0x7FFFFFFF for s in seq if s < -1]
+    assert lv == list(range(n))                        # leaves in order, once each
+    iv = sorted(s for s in seq if s >= 0)
+    assert iv == list(range(n - 1))                    # every internal node once
+    if n > 1:
+        rope = nodes[:, 7].view(np.int32)
+        left = nodes[:, 3].view(np.int32)
+        lrope = leaf[:, 3].view(np.int32)
+
+        def box(ref):
+            if ref < -1:
+                q = leaf[ref & 0x7FFFFFFF, :3]
+                return q, q
+            return nodes[ref, 0:3], nodes[ref, 4:7]
+
+        for k in range(n - 1):
+            lc = int(left[k])
+            rc = int(lrope[lc & 0x7FFFFFFF]) if lc < -1 else int(rope[lc])
+            (a0, a1), (b0, b1) = box(lc), box(rc)
+            np.testing.assert_array_equal(nodes[k, 0:3], np.minimum(a0, b0))
+            np.testing.assert_array_equal(nodes[k, 4:7], np.maximum(a1, b1))
+        np.testing.assert_array_equal(nodes[root, 0:3], p.min(0))
+        np.testing.assert_array_equal(nodes[root, 4:7], p.max(0))
+
+
+@pytest.mark.parametrize("n,eps", [(2, 0.5), (4097, 0.03), (50001, 0.02), (300007, 0.01)])
+def test_pair_traversal_finds_each_pair_once(ctx, n, eps):
+    p = clumpy(n, 7 + n)
+    assert ctx.pair_count(dev(p), eps) == oracle.pair_count(p, F32(eps))
+
+
+@pytest.mark.parametrize("mp", [1, 2, 3, 5, 10, 50])
+def test_core_flags(ctx, mp):
+    p = clumpy(40000, 5)
+    got = ctx.core_flags(dev(p), 0.02, mp).cpu().numpy().astype(bool)
+    np.testing.assert_array_equal(got, oracle.core_flags(p, F32(0.02), mp))
+
+
+# ---- labels ----------------------------------------------------------------
+
+def _pts(*rows):
+    return np.array(rows, dtype=F32).reshape(-1, 3)
+
+
+def test_hand_cases(ctx):
+    # exact boundary, one ulp beyond
+    assert run(ctx, _pts((0, 0, 0), (0.5, 0, 0)), 0.5, 2).tolist() == [0, 0]
+    x = np.nextafter(F32(0.5), F32(1))
+    assert run(ctx, _pts((0, 0, 0), (x, 0, 0)), 0.5, 2).tolist() == [-1, -1]
+    # chain at exact spacing, and just below it
+    c = np.zeros((1000, 3), F32)
+    c[:, 0] = np.arange(1000, dtype=F32) * F32(0.25)
+    assert (run(ctx, c, 0.25, 2) == 0).all()
+    assert (run(ctx, c, np.nextafter(F32(0.25), F32(0)), 2) == -1).all()
+    # subnormal threshold, underflow at eps = 0, overflow
+    assert run(ctx, _pts((0, 0, 0), (2e-20, 0, 0)), F32(1e-20), 2).tolist() == [-1, -1]
+    assert run(ctx, _pts((0, 0, 0), (1e-20, 0, 0)), F32(1e-20), 2).tolist() == [0, 0]
+    assert run(ctx, _pts((1e-30, 0, 0), (2e-30, 0, 0), (5e-30, 0, 0)), 0.0, 2).tolist() == [0, 0, 0]
+    assert run(ctx, _pts((0, 0, 0), (1e-22, 0, 0)), 0.0, 2).tolist() == [-1, -1]
+    assert run(ctx, _pts((-1e30, 0, 0), (1e30, 0, 0), (1e30, 0, 0)), 1e18, 2).tolist() == [-1, 1, 1]
+    # tiny inputs
+    assert run(ctx, _pts((1, 2, 3)), 1.0, 1).tolist() == [0]
+    assert run(ctx, _pts((1, 2, 3)), 1.0, 2).tolist() == [-1]
+
+
+def test_border_rules(ctx):
+    A = [(0.0, 0, 0), (-0.1, 0, 0), (-0.2, 0, 0), (-0.3, 0, 0)]
+    B = [(2.0, 0, 0), (2.1, 0, 0), (2.2, 0, 0), (2.3, 0, 0)]
+    b = [(1.0, 0, 0)]
+    for pts in (B + A + b, A + B + b, b + B + A, b + A + B):
+        p = _pts(*pts)
+        np.testing.assert_array_equal(run(ctx, p, 1.0, 4), oracle.dbscan(p, F32(1.0), 4))
+
+
+def test_fp_boundary_golden_cases(ctx):
+    with open(os.path.join(GOLDEN, "fp_boundary_cases.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            t = line.split()
+            v = [F32(float.fromhex(x)) for x in t[1:8]]
+            p = np.array([v[0:3], v[3:6]], F32)
+            exp = [0, 0] if int(t[8]) else [-1, -1]
+            assert run(ctx, p, v[6], 2).tolist() == exp, line
+
+
+@pytest.mark.parametrize("k", [1, 7, 3000])
+def test_identical_points(ctx, k):
+    """All points equal: one cluster (minPts <= k); union-find contention on
+    k(k-1)/2 pairs."""
+    p = np.tile(_pts((0.3, -1.25, 7.0)), (k, 1))
+    assert (run(ctx, p, 0.0, min(k, 5)) == 0).all()
+    assert (run(ctx, p, 0.0, k + 1) == -1).all()
+
+
+def test_dense_ball_one_cluster(ctx):
+    rng = np.random.Generator(np.random.PCG64(14))
+    d = rng.standard_normal((5000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    p = (d * rng.random((5000, 1)) * 0.1).astype(F32)
+    for mp in (2, 10):
+        assert (run(ctx, p, 1.0, mp) == 0).all()
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("mp", [1, 2, 3, 5, 10])
+def test_random_clumpy_labels(ctx, seed, mp):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = int(rng.integers(10, 20000))
+    p = clumpy(n, seed)
+    eps = F32(rng.uniform(0.005, 0.05))
+    np.testing.assert_array_equal(run(ctx, p, eps, mp), oracle.dbscan(p, eps, mp))
+
+
+@pytest.mark.parametrize("mp", [2, 5, 10])
+def test_clumps32k(ctx, mp):
+    p = datagen.config_points("clumps32k")
+    np.testing.assert_array_equal(run(ctx, p, F32(0.006), mp), oracle.dbscan(p, F32(0.006), mp))
+
+
+def test_ragged_and_block_sizes_deterministic(ctx):
+    p = clumpy(70001, 3)
+    ref = oracle.dbscan(p, F32(0.01), 4)
+    for bs in (64, 128, 256, 512, 1024):
+        np.testing.assert_array_equal(run(ctx, p, 0.01, 4, block_size=bs), ref)
+
+
+def test_default_context_and_host_entry(ctx):
+    p = clumpy(9000, 4)
+    ref = oracle.dbscan(p, F32(0.02), 3)
+    np.testing.assert_array_equal(dbx.cluster(dev(p), 0.02, 3).cpu().numpy(), ref)
+    lib = dbx.load_library()
+    lab = np.empty(p.shape[0], np.int32)
+    import ctypes
+    st = lib.dbscan_cluster_host(p.ctypes.data_as(ctypes.c_void_p), p.shape[0],
+                                 ctypes.c_float(0.02), 3, lab.ctypes.data_as(ctypes.c_void_p))
+    assert st == 0
+    np.testing.assert_array_equal(lab, ref)
+
+
+def test_nonfinite_rejected(ctx):
+    p = clumpy(1000, 1)
+    p[500, 1] = np.nan
+    with pytest.raises(dbx.DbscanError) as e:
+        run(ctx, p, 0.01, 2)
+    assert e.value.code == -2
+    p[500, 1] = np.inf
+    with pytest.raises(dbx.DbscanError) as e:
+        run(ctx, p, 0.01, 2)
+    assert e.value.code == -2
+    # the context still works afterwards
+    q = clumpy(1000, 2)
+    np.testing.assert_array_equal(run(ctx, q, 0.02, 2), oracle.dbscan(q, F32(0.02), 2))
+
+
+def test_budget_too_small():
+    c = dbx.Context(0, budget_bytes=1 << 20)
+    with pytest.raises(dbx.DbscanError) as e:
+        c.cluster(dev(clumpy(100000, 1)), 0.01, 2)
+    assert e.value.code == -5
+    c.close()
+
+
+# ---- full size -----------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def halo16m():
+    p = datagen.config_points("halo16M")
+    return p, oracle.dbscan(p, F32(0.2), 2)
+
+
+def test_halo16m_minpts2_bit_exact(ctx, halo16m):
+    p, ref = halo16m
+    np.testing.assert_array_equal(run(ctx, p, F32(0.2), 2), ref)
