@@ -107,7 +107,10 @@ def _stream(device) -> ctypes.c_void_p:
     return ctypes.c_void_p(_torch().cuda.current_stream(device).cuda_stream)
 
 
-PHASES = ("bounds_morton", "sort", "gather", "build", "count", "pairs", "finalize")
+# one timing slot per kernel launch, in launch order
+PHASES = ("prep", "bounds", "morton", "sort0", "sort1", "sort2", "sort3", "sort4", "sort5",
+          "sort6", "sort7", "gather", "build", "ropes", "count", "pairs", "final_roots",
+          "final_labels")
 
 
 class Context:

@@ -37,15 +37,22 @@ int fail(int code, const std::string& msg) {
       return fail(DBSCAN_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int NPHASES = 7;
-const char* const kPhaseNames[NPHASES] = {"bounds_morton", "sort",  "gather",  "build",
-                                          "count",         "pairs", "finalize"};
+// One timing slot per kernel launch of a run (a slot a run skips reads 0).
+enum Phase {
+  PH_PREP, PH_BOUNDS, PH_MORTON, PH_SORT0, PH_GATHER = PH_SORT0 + SORT_PASSES, PH_BUILD,
+  PH_ROPES, PH_COUNT, PH_PAIRS, PH_FINAL_ROOTS, PH_FINAL_LABELS, NPHASES
+};
+const char* const kPhaseNames[NPHASES] = {
+    "prep",   "bounds", "morton", "sort0", "sort1", "sort2", "sort3",       "sort4",
+    "sort5",  "sort6",  "sort7",  "gather", "build", "ropes", "count", "pairs",
+    "final_roots", "final_labels"};
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Byte offsets of every buffer of a job inside the arena.
 struct Layout {
-  size_t keys_a, keys_b, vals_a, vals_b, leaf, nodes, parent, minlab, flag, bestcore;
+  size_t keys_a, keys_b, vals_a, vals_b, leaf, nodes, parent, minlab, flag, bestcore, pending;
+  uint32_t pending_entries;
   size_t zero;        // start of the region zeroed by k_prep
   size_t hist, tile_ctr, status, count, sort_status;
   size_t zero_words;  // 32-bit words from `zero`
@@ -67,6 +74,8 @@ Layout make_layout(uint32_t n, bool need_bestcore) {
   L.minlab = take(size_t(n) * 4);
   L.flag = take(size_t(n));
   L.bestcore = need_bestcore ? take(size_t(n) * 8) : 0;
+  L.pending_entries = uint32_t(build_pending_entries(n));
+  L.pending = take(size_t(L.pending_entries) * 16);
   L.bounds = take(8 * 4);
   L.root = take(4);
   // zeroed region: hist | tile counters | status word | pair count | look-back
@@ -92,6 +101,7 @@ struct dbscan_ctx {
   hipEvent_t ev[NPHASES + 1] = {};
   float times[NPHASES] = {};
   int ntimes = 0;
+  int next_mark = 0;
 };
 
 namespace {
@@ -167,8 +177,24 @@ struct Index {
   uint32_t* status;
 };
 
-void record(dbscan_ctx* c, bool timing, int k, hipStream_t s) {
-  if (timing) (void)hipEventRecord(c->ev[k], s);
+// ev[0] is recorded before the first kernel, ev[k + 1] after phase k; a
+// phase that does not run is marked right after the previous one.
+void start_timing(dbscan_ctx* c, bool timing, hipStream_t s) {
+  c->next_mark = 0;
+  if (timing) (void)hipEventRecord(c->ev[0], s);
+}
+void mark(dbscan_ctx* c, bool timing, int phase, hipStream_t s) {
+  if (!timing) return;
+  for (int k = c->next_mark; k <= phase; ++k) (void)hipEventRecord(c->ev[k + 1], s);
+  c->next_mark = phase + 1;
+}
+struct SortMarks {
+  dbscan_ctx* c;
+  hipStream_t s;
+};
+void sort_mark(void* arg, int pass) {
+  auto* m = static_cast<SortMarks*>(arg);
+  mark(m->c, true, PH_SORT0 + pass, m->s);
 }
 
 int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore, bool timing,
@@ -186,26 +212,32 @@ int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore,
   SortScratch sc{at<uint32_t>(c, L.hist), at<uint32_t>(c, L.tile_ctr),
                  at<uint32_t>(c, L.sort_status), status};
 
-  record(c, timing, 0, s);
+  start_timing(c, timing, s);
   launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, s);
+  mark(c, timing, PH_PREP, s);
   launch_bounds(pts, n, bounds, status, s);
+  mark(c, timing, PH_BOUNDS, s);
   launch_morton(pts, n, bounds, ka, sc.hist, s);
-  record(c, timing, 1, s);
-  bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, s);
+  mark(c, timing, PH_MORTON, s);
+  SortMarks sm{c, s};
+  bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, s,
+                                timing ? sort_mark : nullptr, &sm);
   uint64_t* keys = in_a ? ka : kb;
   uint32_t* perm = in_a ? va : vb;
-  // the other key buffer is free now: it holds the build's scratch
+  // the other key and value buffers are free now: the build's scratch
   int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
   int32_t* right = other + n;
-  record(c, timing, 2, s);
+  int32_t* rend = reinterpret_cast<int32_t*>(in_a ? vb : va);
   launch_gather(pts, perm, n, at<float4>(c, L.leaf), at<int32_t>(c, L.parent),
                 at<int32_t>(c, L.minlab), at<uint8_t>(c, L.flag),
-                need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr, other, s);
-  record(c, timing, 3, s);
-  launch_build(keys, at<float4>(c, L.leaf), n, at<Node>(c, L.nodes), right, other,
-               at<int32_t>(c, L.root), status, s);
-  launch_ropes(at<Node>(c, L.nodes), at<float4>(c, L.leaf), right, n, status, s);
-  record(c, timing, 4, s);
+                need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr,
+                at<int4>(c, L.pending), L.pending_entries, s);
+  mark(c, timing, PH_GATHER, s);
+  launch_build(keys, at<float4>(c, L.leaf), n, at<Node>(c, L.nodes), right, other, rend,
+               at<int32_t>(c, L.root), at<int4>(c, L.pending), status, s);
+  mark(c, timing, PH_BUILD, s);
+  launch_ropes(at<Node>(c, L.nodes), at<float4>(c, L.leaf), right, rend, n, status, s);
+  mark(c, timing, PH_ROPES, s);
   out->keys = keys;
   out->perm = perm;
   out->leaf = at<float4>(c, L.leaf);
@@ -252,15 +284,18 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
   unsigned long long* bestcore = core_mode ? at<unsigned long long>(c, L.bestcore) : nullptr;
   if (core_mode)
     launch_count(ix.nodes, ix.leaf, n, ix.root, e2, min_pts, flag, ix.status, block, s);
-  record(c, timing, 5, s);
+  mark(c, timing, PH_COUNT, s);
   if (core_mode)
     launch_pairs_core(ix.nodes, ix.leaf, n, e2, flag, ix.perm, parent, bestcore, ix.status,
                       block, s);
   else
     launch_pairs_fof(ix.nodes, ix.leaf, n, e2, parent, flag, ix.status, block, s);
-  record(c, timing, 6, s);
-  launch_finalize(n, min_pts, flag, bestcore, ix.perm, parent, at<int32_t>(c, L.minlab), labels, s);
-  record(c, timing, 7, s);
+  mark(c, timing, PH_PAIRS, s);
+  int32_t* minlab = at<int32_t>(c, L.minlab);
+  launch_final_roots(n, min_pts, flag, bestcore, ix.perm, parent, minlab, s);
+  mark(c, timing, PH_FINAL_ROOTS, s);
+  launch_final_labels(n, ix.perm, parent, minlab, labels, s);
+  mark(c, timing, PH_FINAL_LABELS, s);
   HIP_TRY(hipGetLastError());
   return finish(c, ix.status, timing, s);
 }

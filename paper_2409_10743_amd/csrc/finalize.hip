@@ -71,14 +71,19 @@ void launch_scatter_u8(const uint8_t* src, const uint32_t* perm, uint32_t n, uin
   hipLaunchKernelGGL(k_scatter_u8, dim3((n + 255) / 256), dim3(256), 0, s, src, perm, n, dst);
 }
 
-void launch_finalize(uint32_t n, int32_t min_pts, const uint8_t* flag,
-                     const unsigned long long* bestcore, const uint32_t* perm, int32_t* parent,
-                     int32_t* minlab, int32_t* labels, hipStream_t s) {
+void launch_final_roots(uint32_t n, int32_t min_pts, const uint8_t* flag,
+                        const unsigned long long* bestcore, const uint32_t* perm,
+                        int32_t* parent, int32_t* minlab, hipStream_t s) {
   if (n == 0) return;
-  const uint32_t g = (n + 255) / 256;
-  hipLaunchKernelGGL(k_final_roots, dim3(g), dim3(256), 0, s, n, min_pts, flag, bestcore, perm,
-                     parent, minlab);
-  hipLaunchKernelGGL(k_final_labels, dim3(g), dim3(256), 0, s, n, perm, parent, minlab, labels);
+  hipLaunchKernelGGL(k_final_roots, dim3((n + 255) / 256), dim3(256), 0, s, n, min_pts, flag,
+                     bestcore, perm, parent, minlab);
+}
+
+void launch_final_labels(uint32_t n, const uint32_t* perm, const int32_t* root,
+                         const int32_t* minlab, int32_t* labels, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_final_labels, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, root,
+                     minlab, labels);
 }
 
 }  // namespace dbx

@@ -117,8 +117,10 @@ __global__ __launch_bounds__(256) void k_gather(
     const float* __restrict__ pts, const uint32_t* __restrict__ perm, uint32_t n,
     float4* __restrict__ leaf, int32_t* __restrict__ parent, int32_t* __restrict__ minlab,
     uint8_t* __restrict__ flag, unsigned long long* __restrict__ bestcore,
-    int32_t* __restrict__ other) {
+    int4* __restrict__ pending, uint32_t pending_entries) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint32_t k = i; k < pending_entries; k += gridDim.x * blockDim.x)
+    pending[k] = make_int4(SENTINEL, 0, 0, 0);
   if (i >= n) return;
   uint32_t o = min(perm[i], n - 1);  // a permutation unless the sort failed
   const float* p = pts + size_t(3) * o;
@@ -127,7 +129,6 @@ __global__ __launch_bounds__(256) void k_gather(
   minlab[i] = 0x7fffffff;
   flag[i] = 0;
   if (bestcore) bestcore[i] = ~0ull;
-  other[i] = -1;
 }
 
 uint32_t stream_blocks(uint32_t n) { return std::max(1u, std::min((n + 255) / 256, 4096u)); }
@@ -154,10 +155,11 @@ void launch_morton(const float* pts, uint32_t n, const uint32_t* bounds, uint64_
 
 void launch_gather(const float* pts, const uint32_t* perm, uint32_t n, float4* leaf,
                    int32_t* parent, int32_t* minlab, uint8_t* flag,
-                   unsigned long long* bestcore, int32_t* other, hipStream_t s) {
+                   unsigned long long* bestcore, int4* pending, uint32_t pending_entries,
+                   hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, s, pts, perm, n, leaf,
-                     parent, minlab, flag, bestcore, other);
+                     parent, minlab, flag, bestcore, pending, pending_entries);
 }
 
 }  // namespace dbx

@@ -58,14 +58,17 @@ __global__ __launch_bounds__(256) void k_digit_hist(const uint64_t* __restrict__
 }
 
 template <bool IOTA>
-__global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
+__global__ __launch_bounds__(SORT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_onesweep(
     const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout,
     const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout, uint32_t n,
     int shift, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
     uint32_t* __restrict__ tile_ctr, uint32_t* __restrict__ err) {
-  __shared__ uint64_t s_keys[SORT_TILE];
-  __shared__ uint32_t s_vals[SORT_TILE];
-  __shared__ uint32_t s_whist[WAVES][RADIX];  // per-wave digit counts, then prefixes
+  __shared__ uint64_t s_buf[SORT_TILE];       // keys, then values, in digit order
+  // per-wave digit counts, then prefixes; once every key's position is
+  // known the same bytes hold the digit of the key at each position
+  __shared__ uint32_t s_whist[WAVES][RADIX];
+  static_assert(sizeof(s_whist) >= SORT_TILE, "digit bytes alias the wave counters");
+  uint8_t* const s_dig = reinterpret_cast<uint8_t*>(&s_whist[0][0]);
   __shared__ uint32_t s_base[RADIX];          // global offset - local offset
   __shared__ uint32_t s_loff[RADIX];          // local (in-tile) digit offsets
   __shared__ uint32_t s_tmp[WAVES];
@@ -80,16 +83,13 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
   const uint32_t wbase = tile_base + wave * (64 * SORT_ITEMS);
 
   uint64_t key[SORT_ITEMS];
-  uint32_t val[SORT_ITEMS];
   uint32_t rank[SORT_ITEMS];
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
 #pragma unroll
   for (int k = 0; k < SORT_ITEMS; ++k) {
     uint32_t idx = wbase + k * 64 + lane;
-    bool ok = idx < n;
-    key[k] = ok ? kin[idx] : ~0ull;
-    val[k] = ok ? (IOTA ? idx : vin[idx]) : 0u;
+    key[k] = idx < n ? kin[idx] : ~0ull;
   }
 
   // rank each key among the keys of this wave with the same digit; the
@@ -154,27 +154,40 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
   s_base[d] = gstart + excl - loff;
   __syncthreads();
 
-  // stage keys and values in digit order
+  // in-tile position of every key (rank[] becomes the position)
+#pragma unroll
+  for (int k = 0; k < SORT_ITEMS; ++k) {
+    uint32_t dd = uint32_t(key[k] >> shift) & 0xff;
+    rank[k] += s_loff[dd] + s_whist[wave][dd];
+  }
+  __syncthreads();
+  // stage the keys in digit order
 #pragma unroll
   for (int k = 0; k < SORT_ITEMS; ++k) {
     uint32_t idx = wbase + k * 64 + lane;
     if (idx < n) {
-      uint32_t dd = uint32_t(key[k] >> shift) & 0xff;
-      uint32_t p = s_loff[dd] + s_whist[wave][dd] + rank[k];
-      s_keys[p] = key[k];
-      s_vals[p] = val[k];
+      s_buf[rank[k]] = key[k];
+      s_dig[rank[k]] = uint8_t(key[k] >> shift);
     }
   }
   __syncthreads();
   const uint32_t tile_n = min(uint32_t(SORT_TILE), n - tile_base);
   for (uint32_t p = tid; p < tile_n; p += SORT_THREADS) {
-    uint64_t kk = s_keys[p];
-    uint32_t dd = uint32_t(kk >> shift) & 0xff;
-    uint32_t dst = s_base[dd] + p;
-    if (dst < n) {  // always true unless a look-back wait was cut short
-      kout[dst] = kk;
-      vout[dst] = s_vals[p];
-    }
+    uint32_t dst = s_base[s_dig[p]] + p;
+    if (dst < n) kout[dst] = s_buf[p];  // always true unless a wait was cut short
+  }
+  __syncthreads();
+  // then the values through the same buffer
+  uint32_t* s_val = reinterpret_cast<uint32_t*>(s_buf);
+#pragma unroll
+  for (int k = 0; k < SORT_ITEMS; ++k) {
+    uint32_t idx = wbase + k * 64 + lane;
+    if (idx < n) s_val[rank[k]] = IOTA ? idx : vin[idx];
+  }
+  __syncthreads();
+  for (uint32_t p = tid; p < tile_n; p += SORT_THREADS) {
+    uint32_t dst = s_base[s_dig[p]] + p;
+    if (dst < n) vout[dst] = s_val[p];
   }
 }
 
@@ -189,7 +202,8 @@ void launch_digit_histogram(const uint64_t* keys, uint32_t n, uint32_t* hist,
 
 bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
                        uint32_t n, int first_pass, bool iota_vals,
-                       const SortScratch& sc, hipStream_t s) {
+                       const SortScratch& sc, hipStream_t s,
+                       void (*after_pass)(void*, int), void* arg) {
   bool in_a = true;
   if (n == 0) return true;
   const uint32_t tiles = sort_tiles(n);
@@ -207,6 +221,7 @@ bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
       hipLaunchKernelGGL(k_onesweep<false>, dim3(tiles), dim3(SORT_THREADS), 0, s, kin,
                          kout, vin, vout, n, 8 * p, sc.hist + p * RADIX, st,
                          sc.tile_ctr + p, sc.err);
+    if (after_pass) after_pass(arg, p);
     in_a = !in_a;
   }
   return in_a;
