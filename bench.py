@@ -17,6 +17,16 @@ CPU oracle (single-threaded C) on the same field and checks the GPU labels
 against it bit for bit.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3]
+
+Besides the headline line (plain FDBSCAN on the 2^24-point field) the same
+JSON line carries, unless switched off:
+  "densebox": the DenseBox variant on the same field;
+  "batched":  4,096 independent single-halo sets (~133M points, eps 0.05,
+              minPts 5) in one batched call vs one plain call per set;
+  "serving":  an open-loop replay of Poisson arrivals (200 jobs/s, sizes
+              log-uniform in [1e3, 2^24], minPts in {2,5,10}) through the
+              continuous-batching server: p50/p99 latency and Mpoints/s,
+              beside a FIFO single-slot replay without batching.
 """
 from __future__ import annotations
 
@@ -42,27 +52,33 @@ BYTES_PER_POINT = {
     "bounds": 12.0,                 # read xyz
     "morton": 12.0 + 8.0,           # read xyz, write code
     "sort": 24.0,                   # per pass: read code+index, write code+index
-    "gather": 4 + 12 + 16 + 4 + 4 + 1 + 4,  # read perm, xyz; write leaf, parent,
-                                            # minlab, flag, build slot
-    "build": 8 + 16 + 32 + 4 + 4,   # codes, leaves, node, right child, slot
-    "ropes": 4 + 4 + 4 + 4,         # range end, right child, rope (nodes + leaves)
+    "scatter": 12 + 4 + 16 + 4 + 4 + 1,  # read xyz, position; write leaf, parent,
+                                         # minlab, flag
+    "build_frame": 8 + 16 + 16 + 32 + 4 + 4,  # codes, leaves in, leaves out (with
+                                              # ropes), nodes, right child, exchange slot
+    "build_levels": 0.0,            # a few nodes per 256-leaf frame
+    "ropes": 0.0,                   # only the listed nodes whose rope the build left open
     "count": 16 + 32 + 1,           # leaves, nodes, core flag
     "pairs": 16 + 32 + 4 + 4 + 1,   # leaves, nodes, parent read/write, member flag
     "final_roots": 1 + 4 + 4 + 4 + 4,
     "final_labels": 4 + 4 + 4 + 4,
 }
-# the first sort pass reads no values (they are the identity)
+# the first sort pass reads no values (they are the identity); the last also
+# writes each point's sorted position (4 bytes)
 FIRST_SORT_PASS_BYTES = 20.0
+LAST_SORT_PASS_EXTRA = 4.0
 
 KERNEL_OF_PHASE = {f"sort{p}": "sort" for p in range(8)}
 KERNEL_NAME = {  # device function names, as rocprofv3 reports them
-    "sort": "k_onesweep", "pairs": "k_pairs", "build": "k_build", "gather": "k_gather",
+    "sort": "k_onesweep", "pairs": "k_pairs", "build_frame": "k_build_frame",
+    "build_levels": "k_build_level", "scatter": "k_scatter",
     "morton": "k_morton", "bounds": "k_bounds", "ropes": "k_ropes", "count": "k_count",
     "final_roots": "k_final_roots", "final_labels": "k_final_labels", "prep": "k_prep",
 }
 KERNEL_SOURCE = {
     "sort": "radix_sort.hip", "pairs": "traverse.hip", "count": "traverse.hip",
-    "build": "lbvh.hip", "ropes": "lbvh.hip", "gather": "morton.hip", "morton": "morton.hip",
+    "build_frame": "lbvh.hip", "build_levels": "lbvh.hip", "ropes": "lbvh.hip",
+    "scatter": "morton.hip", "morton": "morton.hip",
     "bounds": "morton.hip", "prep": "morton.hip", "final_roots": "finalize.hip",
     "final_labels": "finalize.hip",
 }
@@ -125,6 +141,10 @@ def main():
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline plain FDBSCAN measurement")
+    ap.add_argument("--serving-seconds", type=float, default=60.0)
+    ap.add_argument("--baseline-seconds", type=float, default=20.0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -180,7 +200,8 @@ def main():
     dom = max(per_kernel, key=per_kernel.get)
     launch_ms = per_kernel[dom] / max(1, launches.get(dom, 1))
     if dom == "sort":
-        bytes_launch = n * (FIRST_SORT_PASS_BYTES + 7 * BYTES_PER_POINT["sort"]) / 8.0
+        bytes_launch = n * (FIRST_SORT_PASS_BYTES + 7 * BYTES_PER_POINT["sort"]
+                            + LAST_SORT_PASS_EXTRA) / 8.0
     else:
         bytes_launch = n * BYTES_PER_POINT[dom]
     achieved = bytes_launch / (launch_ms / 1000.0) / 1e9
@@ -216,7 +237,143 @@ def main():
                       f"({t_cpu:.1f} s)"}
         same = bool(np.array_equal(labels.cpu().numpy(), ref))
         out["parity"] = "bit-exact" if same else "MISMATCH"
+
+    if not args.no_extras and args.workload == "halo16M":
+        out["densebox"] = bench_densebox(ctx, d, eps, mp, args.steps, labels)
+        del d, labels
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(ctx)
+        torch.cuda.empty_cache()
+        out["serving"] = bench_serving(args.serving_seconds, args.baseline_seconds)
     print(json.dumps(out), flush=True)
+
+
+def bench_densebox(ctx, d, eps, mp, steps, ref_labels):
+    import torch
+    lab = torch.empty_like(ref_labels)
+    for _ in range(2):
+        ctx.cluster(d, float(eps), mp, algorithm="densebox", out=lab)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.cluster(d, float(eps), mp, algorithm="densebox", out=lab)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    n = d.shape[0]
+    return {"ms_per_step": round(ms, 4), "mpoints_per_s": round(n / ms / 1e3, 2),
+            "labels_equal_fdbscan": bool(torch.equal(lab, ref_labels))}
+
+
+def bench_batched(ctx, steps=3):
+    """4,096 sets in one batched call vs one plain call per set."""
+    import torch
+
+    import datagen
+    log("[bench] generating subhalo4096 ...")
+    cfg = datagen.CONFIGS["subhalo4096"]
+    pts, off = datagen.subhalo_sets(cfg["num_sets"], cfg["seed"])
+    n = int(off[-1])
+    eps, mp = float(cfg["eps"]), cfg["min_pts"]
+    d = torch.from_numpy(pts).cuda()
+    del pts
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx.cluster_batched(d, off, eps, mp, out=lab)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.cluster_batched(d, off, eps, mp, out=lab)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / steps
+    # one call per set, in sequence on one stream (launch overheads included)
+    lab2 = torch.empty_like(lab)
+    for s in range(8):
+        ctx.cluster(d[off[s]:off[s + 1]], eps, mp, out=lab2[off[s]:off[s + 1]])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(len(off) - 1):
+        ctx.cluster(d[off[s]:off[s + 1]], eps, mp, out=lab2[off[s]:off[s + 1]])
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t0
+    # per-set labels are set-local in both
+    same = bool(torch.equal(lab, lab2))
+    return {"workload": "subhalo4096", "sets": len(off) - 1, "points": n, "eps": eps,
+            "min_pts": mp, "batched_ms": round(t_b * 1e3, 3),
+            "batched_mpoints_per_s": round(n / t_b / 1e6, 2),
+            "per_set_calls_ms": round(t_p * 1e3, 3),
+            "per_set_calls_mpoints_per_s": round(n / t_p / 1e6, 2),
+            "speedup": round(t_p / t_b, 2), "labels_equal": same}
+
+
+def _replay(server, jobs, pools, seconds, pinned_labels):
+    """Submit jobs at their arrival times (open loop) for `seconds`; returns
+    the tickets.  Label buffers come from a ring of pinned host buffers and
+    are recycled once a job is done."""
+    import collections
+    free = collections.deque(range(len(pinned_labels)))
+    pending = collections.deque()
+    tickets = []
+    t0 = time.perf_counter()
+    for j in jobs:
+        if j.t_arrival > seconds:
+            break
+        while True:  # recycle finished buffers
+            while pending and server.poll(pending[0][0]) is not None:
+                free.append(pending.popleft()[1])
+            if free:
+                break
+            server.wait(pending[0][0], 1.0)
+        delay = t0 + j.t_arrival - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        b = free.popleft()
+        p = pools[j.pool][j.start:j.start + j.n]
+        t = server.submit(p, float(j.eps), j.min_pts, out=pinned_labels[b][:j.n])
+        pending.append((t, b))
+        tickets.append(t)
+    for t, _ in pending:
+        server.wait(t, -1.0)
+    return tickets
+
+
+def bench_serving(seconds, baseline_seconds):
+    import torch
+
+    import datagen
+    import paper_2409_10743_amd as dbx
+    log("[bench] generating serving pools ...")
+    pools = []
+    for k in range(8):
+        a = torch.empty((1 << 24, 3), dtype=torch.float32, pin_memory=True)
+        a.numpy()[:] = datagen.serving_pool(k)
+        pools.append(a.numpy())
+    ring = [torch.empty(1 << 24, dtype=torch.int32, pin_memory=True).numpy() for _ in range(24)]
+    jobs = datagen.serving_trace()
+    res = {"trace": "Poisson 200 jobs/s, sizes log-uniform [1e3, 2^24], minPts {2,5,10}, "
+                    "eps 0.2 x mean spacing", "seconds": seconds}
+    # warm the device arenas with the largest job size
+    big = max(jobs, key=lambda j: j.n)
+    for slots, cut, key, secs in ((4, 1 << 18, "continuous_batching", seconds),
+                                  (1, 1, "fifo_one_at_a_time", baseline_seconds)):
+        srv = dbx.Server(0, slots=slots, batch_cut=cut, budget_bytes=200 * 10 ** 9)
+        warm = [srv.submit(pools[k][:big.n], float(big.eps), 10, out=ring[k][:big.n])
+                for k in range(slots)]  # one per slot: every arena sized for the largest job
+        for t in warm:
+            srv.wait(t, -1)
+        log(f"[bench] serving replay {key}: {secs:.0f} s")
+        tickets = _replay(srv, jobs, pools, secs, ring)
+        lat = np.array([np.subtract(*srv.job_times(t)[::-1]) for t in tickets])
+        npts = sum(j.n for j in jobs[:len(tickets)])
+        t_first = srv.job_times(tickets[0])[0]
+        t_last = max(srv.job_times(t)[1] for t in tickets)
+        st = srv.stats()
+        res[key] = {"jobs": len(tickets), "seconds_of_trace": secs,
+                    "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                    "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                    "mpoints_per_s": round(npts / (t_last - t_first) / 1e6, 2),
+                    "batched_calls": st["batches"], "jobs_in_batches": st["batched_jobs"],
+                    "failed": st["failed"]}
+        srv.close()
+    return res
 
 
 if __name__ == "__main__":

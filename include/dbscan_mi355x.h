@@ -92,6 +92,18 @@ int dbscan_cluster_ex(dbscan_ctx* ctx, const float* points, int64_t n, float eps
                       int32_t min_pts, int32_t* labels, void* stream,
                       const dbscan_options* opts);
 
+/* Batched: num_sets independent sets, set k = points[offsets[k] .. offsets[k+1])
+ * (offsets: host int64[num_sets + 1], offsets[0] = 0, non-decreasing,
+ * offsets[num_sets] < 2^30), each clustered with its own eps[k] and
+ * min_pts[k] (host arrays) in one pass of the whole path: one sort, one
+ * build in which every set is a subtree, one traversal.  labels (device
+ * int32[offsets[num_sets]]) are set-local: -1 or the smallest index within
+ * the set of the point's cluster, exactly what dbscan_cluster returns for
+ * that set alone.  FDBSCAN only (DENSEBOX is EINVAL); num_sets <= 2^20. */
+int dbscan_cluster_batched(dbscan_ctx* ctx, const float* points, const int64_t* offsets,
+                           int32_t num_sets, const float* eps, const int32_t* min_pts,
+                           int32_t* labels, void* stream, const dbscan_options* opts);
+
 /* Host buffers: copies points to the device, clusters, copies labels back. */
 int dbscan_cluster_host(const float* host_points, int64_t n, float eps,
                         int32_t min_pts, int32_t* host_labels);
@@ -100,8 +112,60 @@ int dbscan_cluster_host(const float* host_points, int64_t n, float eps,
  * DBSCAN_FLAG_TIMING, in the order of dbscan_phase_name(); returns how many
  * were written (at most max). */
 int dbscan_phase_times(const dbscan_ctx* ctx, float* ms, int32_t max);
-/* Name of phase k ("bounds_morton", "sort", ...), NULL past the last. */
+/* Name of timing slot k (one per kernel launch of a run: "prep", "bounds",
+ * "morton", "sort0".."sort7", "scatter", "cells", "build_frame", "build_levels",
+ * "ropes", "count", "pairs", "final_roots", "final_labels"; a slot a run does
+ * not use reads 0 ms), NULL past the last. */
 const char* dbscan_phase_name(int32_t k);
+
+/* ---- serving: continuous batching of arriving jobs -------------------------- */
+/* A server runs jobs that arrive one at a time (host buffers) on one GPU.
+ * Work of several jobs is on the device at once (`slots` worker threads, each
+ * with its own stream and resident device arena); small jobs (n < batch_cut)
+ * waiting in the queue are clustered together in one batched call (the
+ * batched entry point above); a job starts only when the device bytes it
+ * needs fit in hbm_budget_bytes next to the jobs in flight.  Results are
+ * identical to dbscan_cluster on each job alone.  Thread-safe. */
+typedef struct dbscan_server dbscan_server;
+
+typedef struct dbscan_server_options {
+  int32_t device;            /* HIP device */
+  int32_t slots;             /* concurrent jobs or batches, 0 = 4 (max 64) */
+  uint64_t hbm_budget_bytes; /* cap on device bytes of jobs in flight, 0 = none */
+  int64_t batch_cut;         /* jobs with fewer points are batched, 0 = 2^18 */
+  int64_t batch_max_points;  /* points per batched call, 0 = 2^24 */
+  int32_t batch_max_jobs;    /* jobs per batched call, 0 = 1024 */
+  int32_t fake_executor;     /* 1: no GPU; a job "runs" for fake_us_per_mpoint
+                                microseconds per million points and returns all
+                                labels -1 (scheduler tests on the CPU) */
+  double fake_us_per_mpoint;
+} dbscan_server_options;
+
+typedef struct dbscan_serving_stats {
+  uint64_t submitted, completed, failed, points;
+  uint64_t batches, batched_jobs;   /* batched calls made, jobs they held */
+  uint64_t peak_in_flight_bytes;
+  double p50_ms, p99_ms, mean_ms, max_ms;  /* latency: completion - submit */
+  double mpoints_per_s;             /* points / (last completion - first submit) */
+} dbscan_serving_stats;
+
+int dbscan_server_create(const dbscan_server_options* opts, dbscan_server** out);
+/* Queue a job; host_pts float32[n][3] and host_labels int32[n] must stay
+ * valid until the job is done.  Invalid arguments fail here (EINVAL) and
+ * nothing is queued.  *ticket identifies the job. */
+int dbscan_server_submit(dbscan_server* srv, const float* host_pts, int64_t n, float eps,
+                         int32_t min_pts, int32_t* host_labels, uint64_t* ticket);
+/* 1 and *job_status = the job's status when done, 0 while pending. */
+int dbscan_server_poll(dbscan_server* srv, uint64_t ticket, int32_t* job_status);
+/* As poll, blocking up to timeout_s seconds (negative = no limit). */
+int dbscan_server_wait(dbscan_server* srv, uint64_t ticket, double timeout_s,
+                       int32_t* job_status);
+/* Submit and completion times (seconds, steady clock) of a finished job. */
+int dbscan_server_job_times(dbscan_server* srv, uint64_t ticket, double* submit_s,
+                            double* done_s);
+int dbscan_server_stats(dbscan_server* srv, dbscan_serving_stats* out);
+/* Finishes the queued jobs, then stops the workers and frees the server. */
+int dbscan_server_destroy(dbscan_server* srv);
 
 /* ---- stages of the path, exposed for testing ------------------------------- */
 

@@ -15,7 +15,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["cluster", "Context", "DbscanError", "library_path", "load_library",
+__all__ = ["cluster", "Context", "Server", "DbscanError", "library_path", "load_library",
            "PHASES", "ALGO"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -42,6 +42,22 @@ class _Options(ctypes.Structure):
                 ("block_size", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
+class _ServerOptions(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("batch_cut", ctypes.c_int64),
+                ("batch_max_points", ctypes.c_int64), ("batch_max_jobs", ctypes.c_int32),
+                ("fake_executor", ctypes.c_int32), ("fake_us_per_mpoint", ctypes.c_double)]
+
+
+class _ServingStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("points", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("batched_jobs", ctypes.c_uint64),
+                ("peak_in_flight_bytes", ctypes.c_uint64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("mpoints_per_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -65,6 +81,9 @@ def load_library() -> ctypes.CDLL:
         "dbscan_cluster_ex": ([vp, vp, i64, f32, i32, vp, vp, ctypes.POINTER(_Options)],
                               ctypes.c_int),
         "dbscan_cluster_host": ([vp, i64, f32, i32, vp], ctypes.c_int),
+        "dbscan_cluster_batched": ([vp, vp, ctypes.POINTER(i64), i32, ctypes.POINTER(f32),
+                                    ctypes.POINTER(i32), vp, vp, ctypes.POINTER(_Options)],
+                                   ctypes.c_int),
         "dbscan_phase_times": ([vp, ctypes.POINTER(f32), i32], ctypes.c_int),
         "dbscan_phase_name": ([i32], ctypes.c_char_p),
         "dbscan_morton_codes": ([vp, vp, i64, vp, vp], ctypes.c_int),
@@ -72,6 +91,15 @@ def load_library() -> ctypes.CDLL:
         "dbscan_build_tree": ([vp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
         "dbscan_core_flags": ([vp, vp, i64, f32, i32, vp, vp], ctypes.c_int),
         "dbscan_pair_count": ([vp, vp, i64, f32, ctypes.POINTER(i64), vp], ctypes.c_int),
+        "dbscan_server_create": ([ctypes.POINTER(_ServerOptions), ctypes.POINTER(vp)],
+                                 ctypes.c_int),
+        "dbscan_server_submit": ([vp, vp, i64, f32, i32, vp, ctypes.POINTER(u64)], ctypes.c_int),
+        "dbscan_server_poll": ([vp, u64, ctypes.POINTER(i32)], ctypes.c_int),
+        "dbscan_server_wait": ([vp, u64, ctypes.c_double, ctypes.POINTER(i32)], ctypes.c_int),
+        "dbscan_server_job_times": ([vp, u64, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "dbscan_server_stats": ([vp, ctypes.POINTER(_ServingStats)], ctypes.c_int),
+        "dbscan_server_destroy": ([vp], ctypes.c_int),
         "dbscan_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "dbscan_last_error": ([], ctypes.c_char_p),
         "dbscan_version": ([], ctypes.c_char_p),
@@ -109,8 +137,8 @@ def _stream(device) -> ctypes.c_void_p:
 
 # one timing slot per kernel launch, in launch order
 PHASES = ("prep", "bounds", "morton", "sort0", "sort1", "sort2", "sort3", "sort4", "sort5",
-          "sort6", "sort7", "gather", "build", "ropes", "count", "pairs", "final_roots",
-          "final_labels")
+          "sort6", "sort7", "scatter", "cells", "build_frame", "build_levels", "ropes", "count",
+          "pairs", "final_roots", "final_labels")
 
 
 class Context:
@@ -145,6 +173,33 @@ class Context:
                      FLAG_TIMING if timing else 0)
         _check(load_library().dbscan_cluster_ex(
             self.handle, ctypes.c_void_p(p.data_ptr()), n, ctypes.c_float(eps), int(min_pts),
+            ctypes.c_void_p(labels.data_ptr()), _stream(p.device), ctypes.byref(o)))
+        return labels
+
+    def cluster_batched(self, points, offsets, eps, min_pts, block_size: int = 0,
+                        timing: bool = False, out=None):
+        """Cluster the sets points[offsets[k]:offsets[k+1]] independently in
+        one pass; ``eps`` and ``min_pts`` are scalars or one value per set.
+        Labels are set-local (-1 noise, else the smallest index within the
+        set of the point's cluster)."""
+        import numpy as np
+        torch = _torch()
+        p = _points(points)
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        k = off.size - 1
+        e = np.ascontiguousarray(np.broadcast_to(np.float32(eps) if np.ndim(eps) == 0
+                                                 else np.asarray(eps, np.float32), (k,)),
+                                 dtype=np.float32)
+        m = np.ascontiguousarray(np.broadcast_to(np.asarray(min_pts, np.int32), (k,)),
+                                 dtype=np.int32)
+        labels = out if out is not None else torch.empty(p.shape[0], dtype=torch.int32,
+                                                         device=p.device)
+        o = _Options(ALGO["fdbscan"], 0, int(block_size), FLAG_TIMING if timing else 0)
+        _check(load_library().dbscan_cluster_batched(
+            self.handle, ctypes.c_void_p(p.data_ptr()),
+            off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), k,
+            e.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+            m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
             ctypes.c_void_p(labels.data_ptr()), _stream(p.device), ctypes.byref(o)))
         return labels
 
@@ -204,6 +259,80 @@ class Context:
             self.handle, ctypes.c_void_p(p.data_ptr()), p.shape[0], ctypes.c_float(eps),
             ctypes.byref(out), _stream(p.device)))
         return int(out.value)
+
+
+class Server:
+    """Continuous-batching job server (C++ scheduler in the library).  Jobs
+    are host arrays (numpy float32 [n, 3]); results land in host int32
+    arrays.  With ``fake_us_per_mpoint`` set, no GPU is used: jobs "run" for
+    that many microseconds per million points and return all -1 labels."""
+
+    def __init__(self, device: int = 0, slots: int = 4, budget_bytes: int = 0,
+                 batch_cut: int = 0, batch_max_points: int = 0, batch_max_jobs: int = 0,
+                 fake_us_per_mpoint=None):
+        o = _ServerOptions(int(device), int(slots), int(budget_bytes), int(batch_cut),
+                           int(batch_max_points), int(batch_max_jobs),
+                           1 if fake_us_per_mpoint is not None else 0,
+                           float(fake_us_per_mpoint or 0.0))
+        h = ctypes.c_void_p()
+        _check(load_library().dbscan_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, points, eps: float, min_pts: int, out=None) -> int:
+        import numpy as np
+        p = np.ascontiguousarray(points, dtype=np.float32)
+        if p.ndim != 2 or p.shape[1] != 3:
+            raise TypeError("points must be float32 [N, 3]")
+        lab = out if out is not None else np.empty(p.shape[0], dtype=np.int32)
+        t = ctypes.c_uint64(0)
+        _check(load_library().dbscan_server_submit(
+            self.handle, ctypes.c_void_p(p.ctypes.data), p.shape[0], ctypes.c_float(eps),
+            int(min_pts), ctypes.c_void_p(lab.ctypes.data), ctypes.byref(t)))
+        self._keep[t.value] = (p, lab)
+        return t.value
+
+    def labels(self, ticket: int):
+        return self._keep[ticket][1]
+
+    def poll(self, ticket: int):
+        """None while pending, else the job's status code."""
+        st = ctypes.c_int32(0)
+        r = load_library().dbscan_server_poll(self.handle, ticket, ctypes.byref(st))
+        if r < 0:
+            raise DbscanError(r, "unknown ticket")
+        return None if r == 0 else st.value
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        st = ctypes.c_int32(0)
+        r = load_library().dbscan_server_wait(self.handle, ticket, float(timeout),
+                                              ctypes.byref(st))
+        if r < 0:
+            raise DbscanError(r, "unknown ticket")
+        return None if r == 0 else st.value
+
+    def job_times(self, ticket: int):
+        a, b = ctypes.c_double(0), ctypes.c_double(0)
+        _check(load_library().dbscan_server_job_times(self.handle, ticket, ctypes.byref(a),
+                                                      ctypes.byref(b)))
+        return a.value, b.value
+
+    def stats(self) -> dict:
+        st = _ServingStats()
+        _check(load_library().dbscan_server_stats(self.handle, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in _ServingStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().dbscan_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def cluster(points, eps: float, min_pts: int, out=None):

@@ -39,19 +39,27 @@ int fail(int code, const std::string& msg) {
 
 // One timing slot per kernel launch of a run (a slot a run skips reads 0).
 enum Phase {
-  PH_PREP, PH_BOUNDS, PH_MORTON, PH_SORT0, PH_GATHER = PH_SORT0 + SORT_PASSES, PH_BUILD,
-  PH_ROPES, PH_COUNT, PH_PAIRS, PH_FINAL_ROOTS, PH_FINAL_LABELS, NPHASES
+  PH_PREP, PH_BOUNDS, PH_MORTON, PH_SORT0, PH_SCATTER = PH_SORT0 + SORT_PASSES, PH_CELLS,
+  PH_BUILD_FRAME, PH_BUILD_LEVELS, PH_ROPES, PH_COUNT, PH_PAIRS, PH_FINAL_ROOTS,
+  PH_FINAL_LABELS, NPHASES
 };
+// "morton" is the point codes (FDBSCAN) or the cell codes (DenseBox);
+// "cells" (DenseBox only) covers run heads, scans, cell stats, primitives.
 const char* const kPhaseNames[NPHASES] = {
-    "prep",   "bounds", "morton", "sort0", "sort1", "sort2", "sort3",       "sort4",
-    "sort5",  "sort6",  "sort7",  "gather", "build", "ropes", "count", "pairs",
-    "final_roots", "final_labels"};
+    "prep",  "bounds",  "morton",      "sort0",        "sort1",  "sort2",
+    "sort3", "sort4",   "sort5",       "sort6",        "sort7",  "scatter",
+    "cells", "build_frame", "build_levels", "ropes", "count", "pairs", "final_roots",
+    "final_labels"};
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Byte offsets of every buffer of a job inside the arena.
 struct Layout {
-  size_t keys_a, keys_b, vals_a, vals_b, leaf, nodes, parent, minlab, flag, bestcore, pending;
+  size_t keys_a, keys_b, vals_a, vals_b, leaf, nodes, parent, minlab, flag, bestcore, pending,
+      fixups, nfix;
+  // DenseBox only (0 otherwise)
+  size_t cid, head, cell_start, cell_lo, cell_hi, cell_minorig, cell_dense, prim_count,
+      prim_start, prims, pkey, scan1, scan2, scan_ctr, ncells, nprims;
   uint32_t pending_entries;
   size_t zero;        // start of the region zeroed by k_prep
   size_t hist, tile_ctr, status, count, sort_status;
@@ -60,7 +68,7 @@ struct Layout {
   size_t total;
 };
 
-Layout make_layout(uint32_t n, bool need_bestcore) {
+Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t at = o; o += align_up(std::max<size_t>(bytes, 4)); return at; };
@@ -76,6 +84,20 @@ Layout make_layout(uint32_t n, bool need_bestcore) {
   L.bestcore = need_bestcore ? take(size_t(n) * 8) : 0;
   L.pending_entries = uint32_t(build_pending_entries(n));
   L.pending = take(size_t(L.pending_entries) * 16);
+  L.fixups = take(size_t(n) * 2 * 8);
+  if (densebox) {
+    L.cid = take(size_t(n) * 4);
+    L.head = take(size_t(n) * 4);
+    L.cell_start = take((size_t(n) + 1) * 4);
+    L.cell_lo = take(size_t(n) * 16);
+    L.cell_hi = take(size_t(n) * 16);
+    L.cell_minorig = need_bestcore ? take(size_t(n) * 8) : 0;
+    L.cell_dense = take(size_t(n));
+    L.prim_count = take(size_t(n) * 4);
+    L.prim_start = take(size_t(n) * 4);
+    L.prims = take(size_t(n) * sizeof(Node));
+    L.pkey = take(size_t(n) * 8);
+  }
   L.bounds = take(8 * 4);
   L.root = take(4);
   // zeroed region: hist | tile counters | status word | pair count | look-back
@@ -84,6 +106,14 @@ Layout make_layout(uint32_t n, bool need_bestcore) {
   L.tile_ctr = take(SORT_PASSES * 4);
   L.status = take(4);
   L.count = take(8);
+  L.nfix = take(4);
+  if (densebox) {
+    L.scan_ctr = take(8);
+    L.ncells = take(8);  // ncells and nprims side by side: read back together
+    L.nprims = L.ncells + 4;
+    L.scan1 = take(scan_status_words(n) * 4);
+    L.scan2 = take(scan_status_words(n) * 4);
+  }
   L.sort_status = take(sort_status_words(n) * 4);
   L.zero_words = (o - L.zero) / 4;
   L.total = o;
@@ -98,6 +128,8 @@ struct dbscan_ctx {
   char* arena = nullptr;
   size_t cap = 0;
   uint32_t* host_status = nullptr;  // pinned
+  char* stage = nullptr;            // pinned staging for per-set parameters
+  size_t stage_cap = 0;
   hipEvent_t ev[NPHASES + 1] = {};
   float times[NPHASES] = {};
   int ntimes = 0;
@@ -196,6 +228,10 @@ void sort_mark(void* arg, int pass) {
   auto* m = static_cast<SortMarks*>(arg);
   mark(m->c, true, PH_SORT0 + pass, m->s);
 }
+void build_mark(void* arg, int level) {  // level 1 = the frame kernel
+  auto* m = static_cast<SortMarks*>(arg);
+  if (level == 1) mark(m->c, true, PH_BUILD_FRAME, m->s);
+}
 
 int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore, bool timing,
                 hipStream_t s, Index* out) {
@@ -220,23 +256,29 @@ int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore,
   launch_morton(pts, n, bounds, ka, sc.hist, s);
   mark(c, timing, PH_MORTON, s);
   SortMarks sm{c, s};
+  // the last pass also records each point's sorted position in `inv`,
+  // which shares memory with `parent` (set only after inv is consumed)
+  uint32_t* inv = at<uint32_t>(c, L.parent);
   bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, s,
-                                timing ? sort_mark : nullptr, &sm);
+                                timing ? sort_mark : nullptr, &sm, inv);
   uint64_t* keys = in_a ? ka : kb;
   uint32_t* perm = in_a ? va : vb;
-  // the other key and value buffers are free now: the build's scratch
+  // the other key buffer is free now: the build's scratch
   int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
   int32_t* right = other + n;
-  int32_t* rend = reinterpret_cast<int32_t*>(in_a ? vb : va);
-  launch_gather(pts, perm, n, at<float4>(c, L.leaf), at<int32_t>(c, L.parent),
+  launch_scatter(pts, inv, n, at<float4>(c, L.leaf), at<int32_t>(c, L.parent),
                 at<int32_t>(c, L.minlab), at<uint8_t>(c, L.flag),
                 need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr,
                 at<int4>(c, L.pending), L.pending_entries, s);
-  mark(c, timing, PH_GATHER, s);
-  launch_build(keys, at<float4>(c, L.leaf), n, at<Node>(c, L.nodes), right, other, rend,
-               at<int32_t>(c, L.root), at<int4>(c, L.pending), status, s);
-  mark(c, timing, PH_BUILD, s);
-  launch_ropes(at<Node>(c, L.nodes), at<float4>(c, L.leaf), right, rend, n, status, s);
+  mark(c, timing, PH_SCATTER, s);
+  int2* fixups = at<int2>(c, L.fixups);
+  uint32_t* nfix = at<uint32_t>(c, L.nfix);
+  launch_build(keys, 64, at<float4>(c, L.leaf), n, at<Node>(c, L.nodes), right, other,
+               at<int32_t>(c, L.root), at<int4>(c, L.pending), fixups, nfix, status, s,
+               timing ? build_mark : nullptr, &sm);
+  mark(c, timing, PH_BUILD_LEVELS, s);
+  launch_ropes(keys, 64, at<Node>(c, L.nodes), at<float4>(c, L.leaf), right, fixups, nfix, n,
+               status, s);
   mark(c, timing, PH_ROPES, s);
   out->keys = keys;
   out->perm = perm;
@@ -300,6 +342,212 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
   return finish(c, ix.status, timing, s);
 }
 
+// FDBSCAN-DenseBox (section 4.3.4): cells of side eps/sqrt(3), dense cells
+// taken whole, a BVH over dense cells and the remaining points.  One host
+// wait (for the number of primitives) sizes the build.
+int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t min_pts,
+                 int32_t* labels, hipStream_t s, const dbscan_options& o) {
+  const bool timing = (o.flags & DBSCAN_FLAG_TIMING) != 0;
+  const int block = o.block_size ? o.block_size : 256;
+  const float e2 = eps * eps;
+  const bool core_mode = min_pts > 2;
+  const int32_t thresh = o.dense_threshold ? o.dense_threshold : min_pts;
+  // side h = eps / sqrt(3), shrunk a little so rounding rarely makes a full
+  // cell's diagonal exceed eps (the dense test on the actual box decides)
+  const double h = double(eps) / std::sqrt(3.0) * (1.0 - 1e-4);
+  const float inv_h = h > 0 ? float(1.0 / h) : INFINITY;
+
+  Layout L = make_layout(n, core_mode, true);
+  int st = ensure_arena(c, L.total);
+  if (st != DBSCAN_OK) return st;
+  uint64_t* ka = at<uint64_t>(c, L.keys_a);
+  uint64_t* kb = at<uint64_t>(c, L.keys_b);
+  uint32_t* va = at<uint32_t>(c, L.vals_a);
+  uint32_t* vb = at<uint32_t>(c, L.vals_b);
+  uint32_t* bounds = at<uint32_t>(c, L.bounds);
+  uint32_t* status = at<uint32_t>(c, L.status);
+  SortScratch sc{at<uint32_t>(c, L.hist), at<uint32_t>(c, L.tile_ctr),
+                 at<uint32_t>(c, L.sort_status), status};
+  float4* spts = at<float4>(c, L.leaf);  // points in cell order
+  int32_t* parent = at<int32_t>(c, L.parent);
+  uint8_t* flag = at<uint8_t>(c, L.flag);
+  int32_t* minlab = at<int32_t>(c, L.minlab);
+  unsigned long long* bestcore = core_mode ? at<unsigned long long>(c, L.bestcore) : nullptr;
+
+  start_timing(c, timing, s);
+  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, s);
+  mark(c, timing, PH_PREP, s);
+  launch_bounds(pts, n, bounds, status, s);
+  mark(c, timing, PH_BOUNDS, s);
+  launch_cell_keys(pts, n, bounds, inv_h, ka, sc.hist, s);
+  mark(c, timing, PH_MORTON, s);
+  SortMarks sm{c, s};
+  uint32_t* inv = at<uint32_t>(c, L.parent);
+  const bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, s,
+                                      timing ? sort_mark : nullptr, &sm, inv);
+  const uint64_t* keys = in_a ? ka : kb;
+  const uint32_t* perm = in_a ? va : vb;
+  int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
+  int32_t* right = other + n;
+  launch_scatter(pts, inv, n, spts, parent, minlab, flag, bestcore, at<int4>(c, L.pending),
+                 L.pending_entries, s);
+  mark(c, timing, PH_SCATTER, s);
+
+  uint32_t* scan_ctr = at<uint32_t>(c, L.scan_ctr);
+  uint32_t* ncells = at<uint32_t>(c, L.ncells);
+  uint32_t* nprims = at<uint32_t>(c, L.nprims);
+  uint32_t* cell_start = at<uint32_t>(c, L.cell_start);
+  uint32_t* cid = at<uint32_t>(c, L.cid);
+  launch_cells(keys, n, at<uint32_t>(c, L.head), cid, ncells, cell_start,
+               at<uint32_t>(c, L.scan1), scan_ctr, status, s);
+  unsigned long long* cell_minorig =
+      core_mode ? at<unsigned long long>(c, L.cell_minorig) : nullptr;
+  float4* cell_lo = at<float4>(c, L.cell_lo);
+  float4* cell_hi = at<float4>(c, L.cell_hi);
+  uint8_t* cell_dense = at<uint8_t>(c, L.cell_dense);
+  uint32_t* prim_count = at<uint32_t>(c, L.prim_count);
+  uint32_t* prim_start = at<uint32_t>(c, L.prim_start);
+  launch_cell_stats(spts, perm, n, ncells, cell_start, e2, thresh, cell_lo, cell_hi,
+                    cell_minorig, cell_dense, prim_count, s);
+  launch_scan(prim_count, prim_start, n, nprims, at<uint32_t>(c, L.scan2), scan_ctr + 1, status,
+              s);
+  HIP_TRY(hipMemcpyAsync(c->host_status + 4, ncells, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const uint32_t np = c->host_status[5];
+  if (np == 0 || np > n || c->host_status[4] > n)
+    return fail(DBSCAN_EDEVICE, "cell construction produced an invalid count");
+  Node* prims = at<Node>(c, L.prims);
+  uint64_t* pkey = at<uint64_t>(c, L.pkey);
+  launch_make_prims(spts, keys, n, cid, cell_start, prim_start, cell_dense, cell_lo, cell_hi,
+                    prims, pkey, parent, flag, s);
+  mark(c, timing, PH_CELLS, s);
+
+  Node* nodes = at<Node>(c, L.nodes);
+  int32_t* root = at<int32_t>(c, L.root);
+  int2* fixups = at<int2>(c, L.fixups);
+  uint32_t* nfix = at<uint32_t>(c, L.nfix);
+  launch_build_boxes(pkey, prims, np, nodes, right, other, root, at<int4>(c, L.pending), fixups,
+                     nfix, status, s);
+  mark(c, timing, PH_BUILD_LEVELS, s);
+  launch_ropes_boxes(pkey, nodes, prims, right, fixups, nfix, np, status, s);
+  mark(c, timing, PH_ROPES, s);
+  if (core_mode)
+    launch_count_db(nodes, prims, np, spts, n, cell_start, root, e2, min_pts, flag, status, block,
+                    s);
+  mark(c, timing, PH_COUNT, s);
+  launch_pairs_db(nodes, prims, np, spts, n, cell_start, perm, cell_minorig, e2, core_mode,
+                  parent, flag, bestcore, status, block, s);
+  mark(c, timing, PH_PAIRS, s);
+  launch_final_roots(n, min_pts, flag, bestcore, perm, parent, minlab, s);
+  mark(c, timing, PH_FINAL_ROOTS, s);
+  launch_final_labels(n, perm, parent, minlab, labels, s);
+  mark(c, timing, PH_FINAL_LABELS, s);
+  HIP_TRY(hipGetLastError());
+  return finish(c, status, timing, s);
+}
+
+// Many independent sets in one pass (keys tagged with the set id).
+int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t num_sets,
+                const float* h_eps, const int32_t* h_minpts, int32_t* labels, hipStream_t s,
+                const dbscan_options& o) {
+  const bool timing = (o.flags & DBSCAN_FLAG_TIMING) != 0;
+  const int block = o.block_size ? o.block_size : 256;
+  const uint32_t n = uint32_t(h_off[num_sets]);
+  int set_bits = 1;
+  while ((1u << set_bits) < num_sets) ++set_bits;
+  const int bits = std::min(MORTON_BITS, (63 - set_bits) / 3);
+  const int set_shift = 3 * bits;
+  bool any_core = false;
+  for (uint32_t k = 0; k < num_sets; ++k) any_core |= h_minpts[k] > 2;
+
+  Layout L = make_layout(n, any_core);
+  // per-set arrays after the job's buffers: offsets, e2, minPts, roots
+  const size_t off_b = align_up(L.total);
+  const size_t e2_b = off_b + align_up((size_t(num_sets) + 1) * 8);
+  const size_t mp_b = e2_b + align_up(size_t(num_sets) * 4);
+  const size_t root_b = mp_b + align_up(size_t(num_sets) * 4);
+  const size_t total = root_b + align_up(size_t(num_sets) * 4);
+  int st = ensure_arena(c, total);
+  if (st != DBSCAN_OK) return st;
+  const size_t stage_bytes = (size_t(num_sets) + 1) * 8 + size_t(num_sets) * 8;
+  if (c->stage_cap < stage_bytes) {
+    HIP_TRY(hipStreamSynchronize(s));  // the old staging buffer may still be read
+    if (c->stage) (void)hipHostFree(c->stage);
+    c->stage = nullptr;
+    c->stage_cap = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->stage), stage_bytes) != hipSuccess)
+      return fail(DBSCAN_ENOMEM, "hipHostMalloc of the per-set staging buffer failed");
+    c->stage_cap = stage_bytes;
+  }
+  int64_t* s_off = reinterpret_cast<int64_t*>(c->stage);
+  float* s_e2 = reinterpret_cast<float*>(s_off + num_sets + 1);
+  int32_t* s_mp = reinterpret_cast<int32_t*>(s_e2 + num_sets);
+  std::memcpy(s_off, h_off, (size_t(num_sets) + 1) * 8);
+  for (uint32_t k = 0; k < num_sets; ++k) {
+    s_e2[k] = h_eps[k] * h_eps[k];
+    s_mp[k] = h_minpts[k];
+  }
+  int64_t* d_off = at<int64_t>(c, off_b);
+  float* d_e2 = at<float>(c, e2_b);
+  int32_t* d_mp = at<int32_t>(c, mp_b);
+  int32_t* d_root = at<int32_t>(c, root_b);
+  HIP_TRY(hipMemcpyAsync(d_off, s_off, (size_t(num_sets) + 1) * 8, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_e2, s_e2, size_t(num_sets) * 4, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_mp, s_mp, size_t(num_sets) * 4, hipMemcpyHostToDevice, s));
+
+  uint64_t* ka = at<uint64_t>(c, L.keys_a);
+  uint64_t* kb = at<uint64_t>(c, L.keys_b);
+  uint32_t* va = at<uint32_t>(c, L.vals_a);
+  uint32_t* vb = at<uint32_t>(c, L.vals_b);
+  uint32_t* bounds = at<uint32_t>(c, L.bounds);
+  uint32_t* status = at<uint32_t>(c, L.status);
+  SortScratch sc{at<uint32_t>(c, L.hist), at<uint32_t>(c, L.tile_ctr),
+                 at<uint32_t>(c, L.sort_status), status};
+  float4* leaf = at<float4>(c, L.leaf);
+  int32_t* parent = at<int32_t>(c, L.parent);
+  uint8_t* flag = at<uint8_t>(c, L.flag);
+  int32_t* minlab = at<int32_t>(c, L.minlab);
+  unsigned long long* bestcore = any_core ? at<unsigned long long>(c, L.bestcore) : nullptr;
+
+  start_timing(c, timing, s);
+  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, s);
+  mark(c, timing, PH_PREP, s);
+  mark(c, timing, PH_BOUNDS, s);
+  launch_set_morton(pts, d_off, num_sets, bits, set_shift, ka, sc.hist, d_root, status, s);
+  mark(c, timing, PH_MORTON, s);
+  SortMarks sm{c, s};
+  uint32_t* inv = reinterpret_cast<uint32_t*>(parent);
+  const bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, s,
+                                      timing ? sort_mark : nullptr, &sm, inv);
+  const uint64_t* keys = in_a ? ka : kb;
+  const uint32_t* perm = in_a ? va : vb;
+  int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
+  int32_t* right = other + n;
+  launch_scatter(pts, inv, n, leaf, parent, minlab, flag, bestcore, at<int4>(c, L.pending),
+                 L.pending_entries, s);
+  mark(c, timing, PH_SCATTER, s);
+  mark(c, timing, PH_CELLS, s);
+  Node* nodes = at<Node>(c, L.nodes);
+  int2* fixups = at<int2>(c, L.fixups);
+  uint32_t* nfix = at<uint32_t>(c, L.nfix);
+  launch_build(keys, set_shift, leaf, n, nodes, right, other, d_root, at<int4>(c, L.pending),
+               fixups, nfix, status, s, timing ? build_mark : nullptr, &sm);
+  mark(c, timing, PH_BUILD_LEVELS, s);
+  launch_ropes(keys, set_shift, nodes, leaf, right, fixups, nfix, n, status, s);
+  mark(c, timing, PH_ROPES, s);
+  if (any_core)
+    launch_count_sets(nodes, leaf, n, keys, set_shift, d_root, d_e2, d_mp, flag, status, block, s);
+  mark(c, timing, PH_COUNT, s);
+  launch_pairs_sets(nodes, leaf, n, keys, set_shift, d_e2, d_mp, perm, parent, flag, bestcore,
+                    status, block, s);
+  mark(c, timing, PH_PAIRS, s);
+  launch_final_sets(n, keys, set_shift, d_mp, d_off, flag, bestcore, perm, parent, minlab, labels,
+                    s);
+  mark(c, timing, PH_FINAL_LABELS, s);
+  HIP_TRY(hipGetLastError());
+  return finish(c, status, timing, s);
+}
+
 std::mutex g_default_mu;
 dbscan_ctx* g_default[64] = {};
 
@@ -354,6 +602,7 @@ int dbscan_ctx_destroy(dbscan_ctx* c) {
   DeviceGuard g(c->device);
   if (c->arena) (void)hipFree(c->arena);
   if (c->host_status) (void)hipHostFree(c->host_status);
+  if (c->stage) (void)hipHostFree(c->stage);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   delete c;
@@ -361,9 +610,8 @@ int dbscan_ctx_destroy(dbscan_ctx* c) {
 }
 
 uint64_t dbscan_scratch_bytes(int64_t n, int32_t min_pts, int32_t algorithm) {
-  (void)algorithm;
   if (n < 0 || n > int64_t(SORT_MAX_N)) return 0;
-  return make_layout(uint32_t(n), min_pts > 2).total;
+  return make_layout(uint32_t(n), min_pts > 2, algorithm == DBSCAN_ALGO_DENSEBOX).total;
 }
 
 int dbscan_cluster_ex(dbscan_ctx* c, const float* points, int64_t n, float eps, int32_t min_pts,
@@ -375,10 +623,37 @@ int dbscan_cluster_ex(dbscan_ctx* c, const float* points, int64_t n, float eps, 
   st = check_opts(o, min_pts);
   if (st != DBSCAN_OK) return st;
   if (n == 0) return DBSCAN_OK;
-  if (o.algorithm == DBSCAN_ALGO_DENSEBOX)
-    return fail(DBSCAN_EINVAL, "DenseBox is not available in this build");
   DeviceGuard g(c->device);
+  if (o.algorithm == DBSCAN_ALGO_DENSEBOX)
+    return run_densebox(c, points, uint32_t(n), eps, min_pts, labels,
+                        reinterpret_cast<hipStream_t>(stream), o);
   return run_fdbscan(c, points, uint32_t(n), eps, min_pts, labels,
+                     reinterpret_cast<hipStream_t>(stream), o);
+}
+
+int dbscan_cluster_batched(dbscan_ctx* c, const float* points, const int64_t* offsets,
+                           int32_t num_sets, const float* eps, const int32_t* min_pts,
+                           int32_t* labels, void* stream, const dbscan_options* opts) {
+  if (!c) return fail(DBSCAN_EINVAL, "null context");
+  if (num_sets < 0 || num_sets > (1 << 20)) return fail(DBSCAN_EINVAL, "num_sets out of range");
+  if (num_sets == 0) return DBSCAN_OK;
+  if (!offsets || !eps || !min_pts) return fail(DBSCAN_EINVAL, "null pointer");
+  if (offsets[0] != 0) return fail(DBSCAN_EINVAL, "offsets[0] must be 0");
+  for (int32_t k = 0; k < num_sets; ++k)
+    if (offsets[k + 1] < offsets[k]) return fail(DBSCAN_EINVAL, "offsets must not decrease");
+  const int64_t n = offsets[num_sets];
+  dbscan_options o = opts ? *opts : defaults();
+  for (int32_t k = 0; k < num_sets; ++k) {
+    int st = check_args(points, n, eps[k], min_pts[k], labels);
+    if (st != DBSCAN_OK) return st;
+    st = check_opts(o, min_pts[k]);
+    if (st != DBSCAN_OK) return st;
+  }
+  if (o.algorithm == DBSCAN_ALGO_DENSEBOX)
+    return fail(DBSCAN_EINVAL, "batched calls run FDBSCAN");
+  if (n == 0) return DBSCAN_OK;
+  DeviceGuard g(c->device);
+  return run_batched(c, points, offsets, uint32_t(num_sets), eps, min_pts, labels,
                      reinterpret_cast<hipStream_t>(stream), o);
 }
 

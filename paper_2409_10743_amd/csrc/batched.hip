@@ -1,0 +1,281 @@
+// Batched clustering: many independent point sets (given as CSR offsets)
+// clustered in one pass of the whole path, each with its own eps and minPts,
+// each result identical to clustering that set alone (labels are set-local
+// input indices).
+//
+// The sets share one key space: key = (set id << set_shift) | Morton code of
+// the point within its own set's bounding box (set_shift/3 bits per axis).
+// One radix sort orders all points, one build makes every set a complete
+// subtree (a boundary between sets has a larger delta than any boundary
+// inside a set), ropes are cut at set ends, and each traversal lane reads its
+// set's parameters and subtree root from its key's top bits.
+#include <algorithm>
+
+#include "pipeline.hpp"
+
+namespace dbx {
+
+namespace {
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffffu;
+  x = (x | (x << 32)) & 0x001f00000000ffffull;
+  x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+__device__ __forceinline__ float block_min(float v, float* s_red) {
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float r = s_red[0];
+  for (int w = 1; w < int(blockDim.x >> 6); ++w) r = fminf(r, s_red[w]);
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ float block_max(float v, float* s_red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float r = s_red[0];
+  for (int w = 1; w < int(blockDim.x >> 6); ++w) r = fmaxf(r, s_red[w]);
+  __syncthreads();
+  return r;
+}
+
+// One workgroup per set: the set's bounding box, then its keys (set id in
+// the top bits, `bits` per axis of Morton code below) and digit histograms.
+__global__ __launch_bounds__(256) void k_set_morton(const float* __restrict__ pts,
+                                                   const int64_t* __restrict__ offsets,
+                                                   int bits, int set_shift,
+                                                   uint64_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ hist,
+                                                   int32_t* __restrict__ set_root,
+                                                   uint32_t* __restrict__ status) {
+  __shared__ uint32_t sh[SORT_PASSES * RADIX];
+  __shared__ float s_red[4];
+  const uint32_t set = blockIdx.x;
+  if (threadIdx.x == 0) set_root[set] = SENTINEL;  // the build sets it (non-empty sets)
+  const uint32_t b = uint32_t(offsets[set]), e = uint32_t(offsets[set + 1]);
+  if (b >= e) return;
+  for (int t = threadIdx.x; t < SORT_PASSES * RADIX; t += blockDim.x) sh[t] = 0;
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (uint32_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float v = pts[size_t(3) * i + a];
+      bad |= !isfinite(v);
+      lo[a] = fminf(lo[a], v);
+      hi[a] = fmaxf(hi[a], v);
+    }
+  }
+  if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(status, STATUS_NONFINITE);
+  float s[3];
+  const float cells = float((1u << bits) - 1u);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = block_min(lo[a], s_red);
+    hi[a] = block_max(hi[a], s_red);
+    const float ext = hi[a] - lo[a];
+    s[a] = ext > 0.0f ? float(1u << bits) / ext : 0.0f;
+  }
+  const uint64_t tag = uint64_t(set) << set_shift;
+  for (uint32_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+    uint32_t q[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma clang fp contract(off)
+      float t = (pts[size_t(3) * i + a] - lo[a]) * s[a];
+      t = fminf(fmaxf(floorf(t), 0.0f), cells);  // NaN -> 0
+      q[a] = uint32_t(t);
+    }
+    const uint64_t code = tag | (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    keys[i] = code;
+#pragma unroll
+    for (int p = 0; p < SORT_PASSES; ++p)
+      atomicAdd(&sh[p * RADIX + ((code >> (8 * p)) & 0xff)], 1u);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < SORT_PASSES * RADIX; t += blockDim.x)
+    if (sh[t]) atomicAdd(&hist[t], sh[t]);
+}
+
+__device__ __forceinline__ Node load_node(const Node* __restrict__ nodes, int32_t k) {
+  const float4* p = reinterpret_cast<const float4*>(nodes + k);
+  const float4 a = p[0], b = p[1];
+  Node nd;
+  nd.lox = a.x; nd.loy = a.y; nd.loz = a.z; nd.left = __float_as_int(a.w);
+  nd.hix = b.x; nd.hiy = b.y; nd.hiz = b.z; nd.rope = __float_as_int(b.w);
+  return nd;
+}
+
+__device__ __forceinline__ bool bad_ref(int32_t node, uint32_t n, uint32_t& steps) {
+  if (++steps > 2 * n) return true;
+  return is_leaf(node) ? uint32_t(leaf_index(node)) >= n : uint32_t(node) >= n - 1;
+}
+
+__device__ __forceinline__ uint32_t query_index() {
+  return xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
+
+// Counting for the points of sets with minPts > 2, from their set's root.
+__global__ void k_count_sets(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
+                             uint32_t n, const uint64_t* __restrict__ keys, int set_shift,
+                             const int32_t* __restrict__ set_root,
+                             const float* __restrict__ set_e2,
+                             const int32_t* __restrict__ set_minpts,
+                             uint8_t* __restrict__ flag, uint32_t* __restrict__ err) {
+  const uint32_t i = query_index();
+  if (i >= n) return;
+  const uint32_t set = uint32_t(keys[i] >> set_shift);
+  const int32_t min_pts = set_minpts[set];
+  if (min_pts <= 2) return;
+  const float e2 = set_e2[set];
+  const float4 q = leaf[i];
+  int32_t cnt = 0;
+  int32_t node = set_root[set];
+  uint32_t steps = 0;
+  while (node != SENTINEL) {
+    if (bad_ref(node, n, steps)) { atomicOr(err, STATUS_TREE); break; }
+    if (!is_leaf(node)) {
+      const Node nd = load_node(nodes, node);
+      node = box_sq_dist(q.x, q.y, q.z, nd) <= e2 ? nd.left : nd.rope;
+    } else {
+      const float4 p = leaf[leaf_index(node)];
+      if (sq_dist(q.x, q.y, q.z, p.x, p.y, p.z) <= e2 && ++cnt >= min_pts) break;
+      node = __float_as_int(p.w);
+    }
+  }
+  flag[i] = cnt >= min_pts;
+}
+
+// Pair traversal; each lane runs the minPts <= 2 or the minPts > 2 rule of
+// its own set (both ends of a pair are always in the same set).
+__global__ void k_pairs_sets(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
+                             uint32_t n, const uint64_t* __restrict__ keys, int set_shift,
+                             const float* __restrict__ set_e2,
+                             const int32_t* __restrict__ set_minpts,
+                             const uint32_t* __restrict__ perm, int32_t* parent, uint8_t* flag,
+                             unsigned long long* bestcore, uint32_t* err) {
+  const uint32_t i = query_index();
+  if (i >= n) return;
+  const uint32_t set = uint32_t(keys[i] >> set_shift);
+  const float e2 = set_e2[set];
+  const bool core_mode = set_minpts[set] > 2;
+  const float4 q = leaf[i];
+  const bool ci = core_mode ? flag[i] != 0 : true;
+  bool found = false;
+  int32_t node = __float_as_int(q.w);
+  uint32_t steps = 0;
+  while (node != SENTINEL) {
+    if (bad_ref(node, n, steps)) { atomicOr(err, STATUS_TREE); break; }
+    if (!is_leaf(node)) {
+      const Node nd = load_node(nodes, node);
+      node = box_sq_dist(q.x, q.y, q.z, nd) <= e2 ? nd.left : nd.rope;
+      continue;
+    }
+    const int32_t j = leaf_index(node);
+    const float4 p = leaf[j];
+    node = __float_as_int(p.w);
+    if (sq_dist(q.x, q.y, q.z, p.x, p.y, p.z) > e2) continue;
+    if (!core_mode) {
+      found = true;
+      uf_union(parent, int32_t(i), j);
+      flag[j] = 1;
+      continue;
+    }
+    const bool cj = flag[j] != 0;
+    if (ci && cj) uf_union(parent, int32_t(i), j);
+    else if (ci) atomicMin(bestcore + j, (static_cast<unsigned long long>(perm[i]) << 32) | i);
+    else if (cj)
+      atomicMin(bestcore + i, (static_cast<unsigned long long>(perm[j]) << 32) | uint32_t(j));
+  }
+  if (!core_mode && found) flag[i] = 1;
+}
+
+// Find without compression (the forest no longer changes).
+__device__ __forceinline__ int32_t root_of(const int32_t* parent, int32_t x) {
+  int32_t p = parent[x];
+  while (p != x) { x = p; p = parent[x]; }
+  return x;
+}
+
+__global__ __launch_bounds__(256) void k_final_roots_sets(
+    uint32_t n, const uint64_t* __restrict__ keys, int set_shift,
+    const int32_t* __restrict__ set_minpts, const uint8_t* __restrict__ flag,
+    const unsigned long long* __restrict__ bestcore, const uint32_t* __restrict__ perm,
+    int32_t* parent, int32_t* __restrict__ minlab) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t mp = set_minpts[uint32_t(keys[i] >> set_shift)];
+  int32_t r;
+  if (mp <= 2) {
+    r = (mp == 1 || flag[i]) ? root_of(parent, int32_t(i)) : -1;
+  } else if (flag[i]) {
+    r = root_of(parent, int32_t(i));
+  } else {
+    const unsigned long long b = bestcore[i];
+    r = b == ~0ull ? -1 : root_of(parent, int32_t(uint32_t(b)));
+  }
+  if (r >= 0) atomicMin(minlab + r, int32_t(perm[i]));
+  parent[i] = r;
+}
+
+__global__ __launch_bounds__(256) void k_final_labels_sets(
+    uint32_t n, const uint64_t* __restrict__ keys, int set_shift,
+    const int64_t* __restrict__ offsets, const uint32_t* __restrict__ perm,
+    const int32_t* __restrict__ root, const int32_t* __restrict__ minlab,
+    int32_t* __restrict__ labels) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t r = root[i];
+  const uint32_t o = perm[i];
+  const int32_t base = int32_t(offsets[uint32_t(keys[i] >> set_shift)]);
+  if (o < n) labels[o] = r < 0 ? -1 : minlab[r] - base;
+}
+
+}  // namespace
+
+void launch_set_morton(const float* pts, const int64_t* offsets, uint32_t num_sets, int bits,
+                       int set_shift, uint64_t* keys, uint32_t* hist, int32_t* set_root,
+                       uint32_t* status, hipStream_t s) {
+  if (num_sets == 0) return;
+  hipLaunchKernelGGL(k_set_morton, dim3(num_sets), dim3(256), 0, s, pts, offsets, bits, set_shift,
+                     keys, hist, set_root, status);
+}
+
+void launch_count_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
+                       int set_shift, const int32_t* set_root, const float* set_e2,
+                       const int32_t* set_minpts, uint8_t* flag, uint32_t* err, int block,
+                       hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_count_sets, dim3((n + block - 1) / block), dim3(block), 0, s, nodes, leaf,
+                     n, keys, set_shift, set_root, set_e2, set_minpts, flag, err);
+}
+
+void launch_pairs_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
+                       int set_shift, const float* set_e2, const int32_t* set_minpts,
+                       const uint32_t* perm, int32_t* parent, uint8_t* flag,
+                       unsigned long long* bestcore, uint32_t* err, int block, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_pairs_sets, dim3((n + block - 1) / block), dim3(block), 0, s, nodes, leaf,
+                     n, keys, set_shift, set_e2, set_minpts, perm, parent, flag, bestcore, err);
+}
+
+void launch_final_sets(uint32_t n, const uint64_t* keys, int set_shift, const int32_t* set_minpts,
+                       const int64_t* offsets, const uint8_t* flag,
+                       const unsigned long long* bestcore, const uint32_t* perm, int32_t* parent,
+                       int32_t* minlab, int32_t* labels, hipStream_t s) {
+  if (n == 0) return;
+  const uint32_t g = (n + 255) / 256;
+  hipLaunchKernelGGL(k_final_roots_sets, dim3(g), dim3(256), 0, s, n, keys, set_shift,
+                     set_minpts, flag, bestcore, perm, parent, minlab);
+  hipLaunchKernelGGL(k_final_labels_sets, dim3(g), dim3(256), 0, s, n, keys, set_shift, offsets,
+                     perm, parent, minlab, labels);
+}
+
+}  // namespace dbx

@@ -32,11 +32,61 @@
 // holding the node in its left subtree.  That ancestor is internal node r,
 // r being the last leaf the node covers, so rope = right(r), or the sentinel
 // when r = n-1 (the right-most path).  No reordering of nodes is needed.
+// Batched sets: the keys carry the set id in their top bits (`set_shift`),
+// so a boundary between sets has a larger delta than any boundary inside a
+// set and every set is one complete subtree.  Ropes are cut at set ends
+// (sets overlap in space, so boxes would not keep a walk inside its set),
+// and the node spanning exactly a set is recorded as that set's root.  With
+// no set bits (set_shift = 64) the only such node is the root.
+// Level 1 knows right(r) whenever that child was finished inside the frame,
+// which holds for nearly every node: it writes those leaves and nodes whole,
+// once.  The rest (nodes whose r is the frame's last leaf or whose right(r)
+// crosses the frame edge, and nodes finished at higher levels) are listed
+// and patched by k_ropes after the last level.
+#include <algorithm>
+
 #include "pipeline.hpp"
 
 namespace dbx {
 
 namespace {
+
+// Leaves are points (FDBSCAN: float4 x, y, z, rope) or boxes (DenseBox
+// primitives: Node records whose `left` holds the payload).
+struct PointLeaves {
+  float4* leaf;
+  __device__ void load(int32_t j, float4& lo, float4& hi) const { lo = hi = leaf[j]; }
+  // whole record, coalesced, when the frame writes its leaves out
+  __device__ void write_out(int32_t j, const float4& lo, const float4&, int32_t rope) const {
+    leaf[j] = make_float4(lo.x, lo.y, lo.z, __int_as_float(rope));
+  }
+  __device__ void set_rope(int32_t j, int32_t rope) const { leaf[j].w = __int_as_float(rope); }
+};
+struct BoxLeaves {
+  Node* prim;
+  __device__ void load(int32_t j, float4& lo, float4& hi) const {
+    const float4* q = reinterpret_cast<const float4*>(prim + j);
+    lo = q[0];
+    hi = q[1];
+  }
+  __device__ void write_out(int32_t j, const float4&, const float4&, int32_t rope) const {
+    prim[j].rope = rope;
+  }
+  __device__ void set_rope(int32_t j, int32_t rope) const { prim[j].rope = rope; }
+};
+
+__device__ __forceinline__ uint64_t set_mask_of(int set_shift) {
+  return set_shift < 64 ? (~0ull << set_shift) : 0ull;
+}
+// does a set end at leaf q (q < n - 1)?
+__device__ __forceinline__ bool set_cut(const uint64_t* __restrict__ keys, int32_t q,
+                                        uint64_t mask) {
+  return ((keys[q] ^ keys[q + 1]) & mask) != 0;
+}
+__device__ __forceinline__ uint32_t set_of(const uint64_t* __restrict__ keys, int32_t l,
+                                           int set_shift) {
+  return set_shift < 64 ? uint32_t(keys[l] >> set_shift) : 0u;
+}
 
 __device__ __forceinline__ uint64_t delta(const uint64_t* __restrict__ keys, int32_t i) {
   uint64_t a = keys[i], b = keys[i + 1];
@@ -46,9 +96,11 @@ __device__ __forceinline__ uint64_t delta(const uint64_t* __restrict__ keys, int
 // One climb step at interior parent `par` of the node `node` = [l, r]:
 // link it, exchange, and, for the second arrival, finish the parent.
 // Returns false when the climb stops here (first arrival, or a bad tree).
-__device__ __forceinline__ bool climb_step(const float4* __restrict__ leaf, Node* nodes,
-                                           int32_t* right, int32_t* other, int32_t* rend,
-                                           uint32_t* err,
+template <class Leaves>
+__device__ __forceinline__ bool climb_step(const Leaves& lv, Node* nodes,
+                                           int32_t* right, int32_t* other, int2* fixups,
+                                           uint32_t* nfix, uint32_t* err, const uint64_t* keys,
+                                           int set_shift, int32_t* set_root,
                                            int32_t last, bool is_left, int32_t par,
                                            int32_t& node, int32_t& l, int32_t& r, float& lox,
                                            float& loy, float& loz, float& hix, float& hiy,
@@ -65,8 +117,9 @@ __device__ __forceinline__ bool climb_step(const float4* __restrict__ leaf, Node
   if (!sib_ok || l < 0 || r > last || l > r) { atomicOr(err, STATUS_TREE); return false; }
   float slx, sly, slz, shx, shy, shz;
   if (is_leaf(sib)) {
-    float4 q = leaf[leaf_index(sib)];
-    slx = shx = q.x; sly = shy = q.y; slz = shz = q.z;
+    float4 ql, qh;
+    lv.load(leaf_index(sib), ql, qh);
+    slx = ql.x; sly = ql.y; slz = ql.z; shx = qh.x; shy = qh.y; shz = qh.z;
   } else {
     const Node& sn = nodes[sib];
     slx = sn.lox; sly = sn.loy; slz = sn.loz; shx = sn.hix; shy = sn.hiy; shz = sn.hiz;
@@ -76,8 +129,11 @@ __device__ __forceinline__ bool climb_step(const float4* __restrict__ leaf, Node
   Node& pn = nodes[par];
   pn.lox = lox; pn.loy = loy; pn.loz = loz;
   pn.hix = hix; pn.hiy = hiy; pn.hiz = hiz;
-  rend[par] = r;  // range end, turned into the rope by k_ropes
+  fixups[atomicAdd(nfix, 1u)] = make_int2(par, r);  // rope set by k_ropes
   node = par;
+  const uint64_t mask = set_mask_of(set_shift);
+  if ((l == 0 || set_cut(keys, l - 1, mask)) && (r == last || set_cut(keys, r, mask)))
+    set_root[set_of(keys, l, set_shift)] = par;
   return true;
 }
 
@@ -88,37 +144,56 @@ __device__ __forceinline__ bool climb_step(const float4* __restrict__ leaf, Node
 // state later levels need: the exchange slot of every split in the frame
 // (-1 for the frame's right edge), child references set so far, and the
 // range end of every finished node.
+// Appends one entry per lane with `want` set; all lanes of the wave call it.
+__device__ __forceinline__ void wave_append(int2* list, uint32_t* count, bool want, int2 e) {
+  const uint64_t m = __ballot(want);
+  if (m == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll(static_cast<long long>(m)) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(count, uint32_t(__popcll(m)));
+  base = __shfl(base, leader, 64);
+  const uint64_t below = lane ? (m & (~0ull >> (64 - lane))) : 0ull;
+  if (want) list[base + __popcll(below)] = e;
+}
+
+template <class Leaves>
 __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
-    const uint64_t* __restrict__ keys, const float4* __restrict__ leaf, uint32_t n,
+    const uint64_t* __restrict__ keys, Leaves lv, uint32_t n, int set_shift,
     Node* __restrict__ nodes, int32_t* __restrict__ right, int32_t* __restrict__ other,
-    int32_t* __restrict__ rend, int32_t* __restrict__ root, int4* __restrict__ pend_out,
-    uint32_t* __restrict__ err) {
+    int32_t* __restrict__ set_root, int4* __restrict__ pend_out, int2* __restrict__ fixups,
+    uint32_t* __restrict__ nfix, uint32_t* __restrict__ err) {
   __shared__ uint64_t s_delta[BUILD_LEAVES + 1];  // boundary f0-1+j at j
-  __shared__ float4 s_leaf[BUILD_LEAVES];
+  __shared__ float4 s_leaf[BUILD_LEAVES], s_leafhi[BUILD_LEAVES];
   __shared__ float4 s_lo[BUILD_LEAVES], s_hi[BUILD_LEAVES];
   __shared__ int32_t s_other[BUILD_LEAVES], s_left[BUILD_LEAVES], s_right[BUILD_LEAVES],
       s_end[BUILD_LEAVES];
+  __shared__ uint8_t s_cut[BUILD_LEAVES + 1];  // a set ends at boundary f0-1+j
   const int32_t t = threadIdx.x;
   const int32_t last = int32_t(n) - 1;
   const int32_t f0 = int32_t(blockIdx.x) * BUILD_LEAVES;
   const int32_t f1 = min(f0 + BUILD_LEAVES, int32_t(n));
   const int32_t m = f1 - f0;
+  const uint64_t mask = set_mask_of(set_shift);
   for (int32_t j = t; j <= m; j += BUILD_BLOCK) {
     const int32_t b = f0 - 1 + j;
-    s_delta[j] = (b >= 0 && b < last) ? delta(keys, b) : 0ull;
+    const bool ok = b >= 0 && b < last;
+    s_delta[j] = ok ? delta(keys, b) : 0ull;
+    s_cut[j] = ok ? set_cut(keys, b, mask) : 1;
   }
-  if (t < m) s_leaf[t] = leaf[f0 + t];
+  if (t < m) lv.load(f0 + t, s_leaf[t], s_leafhi[t]);
   s_other[t] = -1;
   s_left[t] = SENTINEL;
   s_right[t] = SENTINEL;
   s_end[t] = -1;
   __syncthreads();
+  // does [l, r] span a whole set? (l - 1 and r are set ends; both in frame)
+  auto spans = [&](int32_t l, int32_t r) { return s_cut[l - f0] && s_cut[r - f0 + 1]; };
   if (t < m) {
-    if (n == 1) {
-      *root = leaf_ref(0);
-    } else {
+    if (spans(f0 + t, f0 + t)) set_root[set_of(keys, f0 + t, set_shift)] = leaf_ref(f0 + t);
+    if (n > 1) {
       int32_t node = leaf_ref(f0 + t), l = f0 + t, r = f0 + t;
-      float4 lo = s_leaf[t], hi = lo;
+      float4 lo = s_leaf[t], hi = s_leafhi[t];
       for (;;) {
         const bool is_left =
             (l == 0) || (r != last && s_delta[r - f0 + 1] < s_delta[l - 1 - f0 + 1]);
@@ -139,47 +214,70 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
         const int32_t si = is_leaf(sib) ? leaf_index(sib) - f0 : sib - f0;
         if (si < 0 || si >= m || l > r) { atomicOr(err, STATUS_TREE); break; }
         const float4 slo = is_leaf(sib) ? s_leaf[si] : s_lo[si];
-        const float4 shi = is_leaf(sib) ? s_leaf[si] : s_hi[si];
+        const float4 shi = is_leaf(sib) ? s_leafhi[si] : s_hi[si];
         lo.x = fminf(lo.x, slo.x); lo.y = fminf(lo.y, slo.y); lo.z = fminf(lo.z, slo.z);
         hi.x = fmaxf(hi.x, shi.x); hi.y = fmaxf(hi.y, shi.y); hi.z = fmaxf(hi.z, shi.z);
         s_lo[k] = lo;
         s_hi[k] = hi;
         s_end[k] = r;
         node = par;
-        if (l == 0 && r == last) { *root = par; break; }
+        if (spans(l, r)) set_root[set_of(keys, l, set_shift)] = par;
+        if (l == 0 && r == last) break;
       }
     }
   }
   __syncthreads();
-  // write out split f0 + t (the frame's right edge split only resets its slot)
+  // Write out split f0 + t (internal node) and leaf f0 + t with their ropes
+  // where right(r) is known here; the frame's right edge split only resets
+  // its exchange slot for the next level.
   const int32_t p = f0 + t;
-  if (t < m && p < last) {
-    if (t == m - 1) {
-      other[p] = -1;
-    } else {
-      other[p] = s_other[t];
-      if (s_right[t] != SENTINEL) right[p] = s_right[t];
-      if (s_end[t] >= 0) {
-        const float4 lo = s_lo[t], hi = s_hi[t];
-        reinterpret_cast<float4*>(nodes + p)[0] =
-            make_float4(lo.x, lo.y, lo.z, __int_as_float(s_left[t]));
-        reinterpret_cast<float4*>(nodes + p)[1] = make_float4(hi.x, hi.y, hi.z, 0.0f);
-        rend[p] = s_end[t];
-      } else if (s_left[t] != SENTINEL) {
-        nodes[p].left = s_left[t];
+  // right child of split q if it was finished in this frame, else -2
+  auto known_right = [&](int32_t q) -> int32_t {
+    if (q == last || s_cut[q - f0 + 1]) return SENTINEL;  // right-most path of the set
+    if (q < f0 || q > f1 - 2) return -2;
+    return s_right[q - f0] != SENTINEL ? s_right[q - f0] : -2;
+  };
+  bool fix_leaf = false, fix_node = false;
+  int32_t node_end = -1;
+  if (t < m && n > 1) {
+    const int32_t lr = known_right(p);
+    lv.write_out(p, s_leaf[t], s_leafhi[t], lr == -2 ? SENTINEL : lr);
+    fix_leaf = lr == -2;
+    if (p < last) {
+      if (t == m - 1) {
+        other[p] = -1;
+      } else {
+        other[p] = s_other[t];
+        if (s_right[t] != SENTINEL) right[p] = s_right[t];
+        if (s_end[t] >= 0) {
+          node_end = s_end[t];
+          const int32_t nr = known_right(node_end);
+          fix_node = nr == -2;
+          const float4 lo = s_lo[t], hi = s_hi[t];
+          reinterpret_cast<float4*>(nodes + p)[0] =
+              make_float4(lo.x, lo.y, lo.z, __int_as_float(s_left[t]));
+          reinterpret_cast<float4*>(nodes + p)[1] =
+              make_float4(hi.x, hi.y, hi.z, __int_as_float(nr == -2 ? SENTINEL : nr));
+        } else if (s_left[t] != SENTINEL) {
+          nodes[p].left = s_left[t];
+        }
       }
     }
   }
+  wave_append(fixups, nfix, fix_leaf, make_int2(leaf_ref(p), p));
+  wave_append(fixups, nfix, fix_node, make_int2(p, node_end));
 }
 
 // Levels k > 1 of the build: thread = one of the 2 * 128 nodes handed up by
 // the 128 level-(k-1) frames inside this block's frame.  nodes/right/other
 // are written and read by different threads of the same launch, ordered by
 // the exchange: no __restrict__ on them.
+template <class Leaves>
 __global__ __launch_bounds__(BUILD_BLOCK) void k_build_level(
-    const uint64_t* __restrict__ keys, const float4* __restrict__ leaf, uint32_t n, int level,
-    Node* nodes, int32_t* right, int32_t* other, int32_t* rend, int32_t* root,
-    const int4* __restrict__ pend_in, int4* __restrict__ pend_out, uint32_t* err) {
+    const uint64_t* __restrict__ keys, Leaves lv, uint32_t n, int level, int set_shift,
+    Node* nodes, int32_t* right, int32_t* other, int32_t* set_root,
+    const int4* __restrict__ pend_in, int4* __restrict__ pend_out, int2* fixups, uint32_t* nfix,
+    uint32_t* err) {
   const int32_t last = int32_t(n) - 1;
   const uint64_t frame = uint64_t(BUILD_LEAVES) << (BUILD_FANOUT_LOG2 * (level - 1));
   const int64_t f0 = int64_t(blockIdx.x) * int64_t(frame);
@@ -193,8 +291,9 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_level(
     l = e.y;
     r = e.z;
     if (is_leaf(node)) {
-      const float4 p = leaf[leaf_index(node)];
-      lox = hix = p.x; loy = hiy = p.y; loz = hiz = p.z;
+      float4 ql, qh;
+      lv.load(leaf_index(node), ql, qh);
+      lox = ql.x; loy = ql.y; loz = ql.z; hix = qh.x; hiy = qh.y; hiz = qh.z;
     } else {
       const Node& nd = nodes[node];
       lox = nd.lox; loy = nd.loy; loz = nd.loz; hix = nd.hix; hiy = nd.hiy; hiz = nd.hiz;
@@ -208,30 +307,34 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_level(
       pend_out[size_t(blockIdx.x) * 2 + (is_left ? 1 : 0)] = make_int4(node, l, r, 0);
       return;
     }
-    if (!climb_step(leaf, nodes, right, other, rend, err, last, is_left, par, node, l, r, lox,
-                    loy, loz, hix, hiy, hiz))
+    if (!climb_step(lv, nodes, right, other, fixups, nfix, err, keys, set_shift, set_root, last,
+                    is_left, par, node, l, r, lox, loy, loz, hix, hiy, hiz))
       return;
-    if (l == 0 && r == last) { *root = node; return; }
+    if (l == 0 && r == last) return;
   }
 }
 
-__global__ __launch_bounds__(256) void k_ropes(Node* __restrict__ nodes, float4* __restrict__ leaf,
+template <class Leaves>
+__global__ __launch_bounds__(256) void k_ropes(Node* __restrict__ nodes, Leaves lv,
+                                              const uint64_t* __restrict__ keys, int set_shift,
                                               const int32_t* __restrict__ right,
-                                              const int32_t* __restrict__ rend, uint32_t n,
+                                              const int2* __restrict__ fixups,
+                                              const uint32_t* __restrict__ nfix, uint32_t n,
                                               uint32_t* __restrict__ err) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < 2 || t >= 2 * n - 1) return;
+  const uint32_t count = min(*nfix, 2 * n);
   const int32_t last = int32_t(n) - 1;
-  if (t < n - 1) {
-    int32_t r = rend[t];
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < count;
+       k += gridDim.x * blockDim.x) {
+    const int2 e = fixups[k];
+    int32_t r = e.y;
     if (r < 0 || r > last) {  // only if the build failed
       atomicOr(err, STATUS_TREE);
       r = last;
     }
-    nodes[t].rope = (r == last) ? SENTINEL : right[r];
-  } else {
-    int32_t j = int32_t(t - (n - 1));
-    leaf[j].w = __int_as_float(j == last ? SENTINEL : right[j]);
+    const int32_t rope =
+        (r == last || set_cut(keys, r, set_mask_of(set_shift))) ? SENTINEL : right[r];
+    if (is_leaf(e.x)) lv.set_rope(leaf_index(e.x), rope);
+    else nodes[e.x].rope = rope;
   }
 }
 
@@ -260,34 +363,69 @@ size_t build_pending_entries(uint32_t n) {
   return total;
 }
 
-void launch_build(const uint64_t* keys, const float4* leaf, uint32_t n, Node* nodes,
-                  int32_t* right, int32_t* other, int32_t* rend, int32_t* root, int4* pending,
-                  uint32_t* err, hipStream_t s) {
+namespace {
+template <class Leaves>
+void build_impl(const uint64_t* keys, int set_shift, Leaves lv, uint32_t n, Node* nodes,
+                int32_t* right, int32_t* other, int32_t* root, int4* pending, int2* fixups,
+                uint32_t* nfix, uint32_t* err, hipStream_t s, void (*after_level)(void*, int),
+                void* arg) {
   if (n == 0) return;
   const int levels = build_levels(n);
   uint64_t frame = BUILD_LEAVES;
   const int4* pin = nullptr;
   int4* pout = pending;
-  for (int lv = 1; lv <= levels; ++lv) {
+  for (int lv_i = 1; lv_i <= levels; ++lv_i) {
     const uint32_t frames = uint32_t((n + frame - 1) / frame);
-    if (lv == 1)
-      hipLaunchKernelGGL(k_build_frame, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys, leaf, n,
-                         nodes, right, other, rend, root, pout, err);
+    if (lv_i == 1)
+      hipLaunchKernelGGL(k_build_frame<Leaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys, lv,
+                         n, set_shift, nodes, right, other, root, pout, fixups, nfix, err);
     else
-      hipLaunchKernelGGL(k_build_level, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys, leaf, n, lv,
-                         nodes, right, other, rend, root, pin, pout, err);
+      hipLaunchKernelGGL(k_build_level<Leaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys, lv,
+                         n, lv_i, set_shift, nodes, right, other, root, pin, pout, fixups, nfix,
+                         err);
+    if (after_level) after_level(arg, lv_i);
     pin = pout;
     pout += level_region(frames);
     frame <<= BUILD_FANOUT_LOG2;
   }
 }
 
-void launch_ropes(Node* nodes, float4* leaf, const int32_t* right, const int32_t* rend,
-                  uint32_t n, uint32_t* err, hipStream_t s) {
+template <class Leaves>
+void ropes_impl(Node* nodes, Leaves lv, const uint64_t* keys, int set_shift,
+                const int32_t* right, const int2* fixups, const uint32_t* nfix, uint32_t n,
+                uint32_t* err, hipStream_t s) {
   if (n < 2) return;
-  uint32_t t = 2 * n - 1;
-  hipLaunchKernelGGL(k_ropes, dim3((t + 255) / 256), dim3(256), 0, s, nodes, leaf, right, rend, n,
-                     err);
+  const uint32_t blocks = std::min<uint32_t>((2 * n + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_ropes<Leaves>, dim3(blocks), dim3(256), 0, s, nodes, lv, keys, set_shift,
+                     right, fixups, nfix, n, err);
+}
+}  // namespace
+
+void launch_build(const uint64_t* keys, int set_shift, float4* leaf, uint32_t n, Node* nodes,
+                  int32_t* right, int32_t* other, int32_t* set_root, int4* pending,
+                  int2* fixups, uint32_t* nfix, uint32_t* err, hipStream_t s,
+                  void (*after_level)(void*, int), void* arg) {
+  build_impl(keys, set_shift, PointLeaves{leaf}, n, nodes, right, other, set_root, pending,
+             fixups, nfix, err, s, after_level, arg);
+}
+
+void launch_build_boxes(const uint64_t* keys, Node* prims, uint32_t n, Node* nodes,
+                        int32_t* right, int32_t* other, int32_t* root, int4* pending,
+                        int2* fixups, uint32_t* nfix, uint32_t* err, hipStream_t s) {
+  build_impl(keys, 64, BoxLeaves{prims}, n, nodes, right, other, root, pending, fixups, nfix,
+             err, s, nullptr, nullptr);
+}
+
+void launch_ropes(const uint64_t* keys, int set_shift, Node* nodes, float4* leaf,
+                  const int32_t* right, const int2* fixups, const uint32_t* nfix, uint32_t n,
+                  uint32_t* err, hipStream_t s) {
+  ropes_impl(nodes, PointLeaves{leaf}, keys, set_shift, right, fixups, nfix, n, err, s);
+}
+
+void launch_ropes_boxes(const uint64_t* keys, Node* nodes, Node* prims, const int32_t* right,
+                        const int2* fixups, const uint32_t* nfix, uint32_t n, uint32_t* err,
+                        hipStream_t s) {
+  ropes_impl(nodes, BoxLeaves{prims}, keys, 64, right, fixups, nfix, n, err, s);
 }
 
 }  // namespace dbx

@@ -1,5 +1,9 @@
 // Scene bounds, 64-bit Morton codes and the sorted leaf array.
 //
+// The leaves are written by scattering the points (read in input order) to
+// their sorted positions: on this GPU a random 16-byte write costs about a
+// 32-byte sector, a random 12-byte read a whole 128-byte line.
+//
 // Section 3.2: the scene bounding volume encloses all objects; LBVH orders
 // the objects along a Z-curve.  Section 4.2.2: 64-bit codes (21 bits per
 // axis here) instead of 32-bit ones, which leave far fewer points sharing a
@@ -113,18 +117,18 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
     if (sh[t]) atomicAdd(&hist[t], sh[t]);
 }
 
-__global__ __launch_bounds__(256) void k_gather(
-    const float* __restrict__ pts, const uint32_t* __restrict__ perm, uint32_t n,
-    float4* __restrict__ leaf, int32_t* __restrict__ parent, int32_t* __restrict__ minlab,
-    uint8_t* __restrict__ flag, unsigned long long* __restrict__ bestcore,
-    int4* __restrict__ pending, uint32_t pending_entries) {
+__global__ __launch_bounds__(256) void k_scatter(
+    const float* __restrict__ pts, const uint32_t* inv, uint32_t n, float4* __restrict__ leaf,
+    int32_t* parent, int32_t* __restrict__ minlab, uint8_t* __restrict__ flag,
+    unsigned long long* __restrict__ bestcore, int4* __restrict__ pending,
+    uint32_t pending_entries) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   for (uint32_t k = i; k < pending_entries; k += gridDim.x * blockDim.x)
     pending[k] = make_int4(SENTINEL, 0, 0, 0);
   if (i >= n) return;
-  uint32_t o = min(perm[i], n - 1);  // a permutation unless the sort failed
-  const float* p = pts + size_t(3) * o;
-  leaf[i] = make_float4(p[0], p[1], p[2], __int_as_float(SENTINEL));
+  const uint32_t s = inv[i];  // read before parent[i] (which may alias inv) is set
+  const float* p = pts + size_t(3) * i;
+  if (s < n) leaf[s] = make_float4(p[0], p[1], p[2], __int_as_float(SENTINEL));
   parent[i] = int32_t(i);
   minlab[i] = 0x7fffffff;
   flag[i] = 0;
@@ -153,12 +157,12 @@ void launch_morton(const float* pts, uint32_t n, const uint32_t* bounds, uint64_
                      hist);
 }
 
-void launch_gather(const float* pts, const uint32_t* perm, uint32_t n, float4* leaf,
-                   int32_t* parent, int32_t* minlab, uint8_t* flag,
-                   unsigned long long* bestcore, int4* pending, uint32_t pending_entries,
-                   hipStream_t s) {
+void launch_scatter(const float* pts, const uint32_t* inv, uint32_t n, float4* leaf,
+                    int32_t* parent, int32_t* minlab, uint8_t* flag,
+                    unsigned long long* bestcore, int4* pending, uint32_t pending_entries,
+                    hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, s, pts, perm, n, leaf,
+  hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, pts, inv, n, leaf,
                      parent, minlab, flag, bestcore, pending, pending_entries);
 }
 

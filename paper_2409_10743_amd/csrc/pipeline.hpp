@@ -15,16 +15,24 @@ constexpr uint32_t STATUS_TREE = 4u;   // malformed tree or traversal bound hit
 
 // ---- radix sort (radix_sort.hip) ------------------------------------------
 constexpr int SORT_THREADS = 256;
-constexpr int SORT_ITEMS = 12;
-constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;  // keys per tile
+constexpr int SORT_ITEMS = 16;                        // default keys per thread
+constexpr int SORT_ITEMS_MIN = 8;                     // smallest tile variant
+constexpr int SORT_TILE_MIN = SORT_THREADS * SORT_ITEMS_MIN;
 constexpr int RADIX = 256;
 constexpr int SORT_PASSES = 8;                          // 8-bit digits of 64
 constexpr uint32_t SORT_MAX_N = (1u << 30) - 1;         // 30-bit look-back counts
 
-inline uint32_t sort_tiles(uint32_t n) { return (n + SORT_TILE - 1) / SORT_TILE; }
-// words of look-back state needed for all passes of one sort of n keys
+// Keys per thread of the sort's pass kernel: 16 unless the environment
+// variable DBX_SORT_ITEMS (8, 12 or 16) overrides it for tuning runs.
+int sort_items();
+inline uint32_t sort_tiles(uint32_t n, int items) {
+  const uint32_t tile = uint32_t(SORT_THREADS * items);
+  return (n + tile - 1) / tile;
+}
+// words of look-back state for all passes of one sort of n keys (sized for
+// the smallest tile, so any variant fits)
 inline size_t sort_status_words(uint32_t n) {
-  return size_t(SORT_PASSES) * sort_tiles(n) * RADIX;
+  return size_t(SORT_PASSES) * sort_tiles(n, SORT_ITEMS_MIN) * RADIX;
 }
 
 struct SortScratch {
@@ -42,13 +50,16 @@ void launch_digit_histogram(const uint64_t* keys, uint32_t n, uint32_t* hist,
 // alternate between the A and B buffers, starting from A.  If `iota_vals`,
 // the input values are taken to be 0..n-1 and `va` is not read.  Returns
 // true when the result ends in the A buffers.
-// `after_pass(arg, p)`, if given, is called after pass p is enqueued.
+// `after_pass(arg, p)`, if given, is called after pass p is enqueued.  If
+// `inv` is given, the last pass also writes inv[v] = final position of v
+// (for values that are a permutation of 0..n-1).
 bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
                        uint32_t n, int first_pass, bool iota_vals,
                        const SortScratch& sc, hipStream_t s,
-                       void (*after_pass)(void*, int) = nullptr, void* arg = nullptr);
+                       void (*after_pass)(void*, int) = nullptr, void* arg = nullptr,
+                       uint32_t* inv = nullptr);
 
-// ---- bounds, Morton codes, gather (morton.hip) ----------------------------
+// ---- bounds, Morton codes, leaf scatter (morton.hip) -----------------------
 // bounds[0..2] lo (ordered-int encoding), bounds[3..5] hi
 void launch_prep(uint32_t* zero_region, size_t zero_words, uint32_t* bounds,
                  hipStream_t s);
@@ -56,12 +67,14 @@ void launch_bounds(const float* pts, uint32_t n, uint32_t* bounds,
                    uint32_t* status, hipStream_t s);
 void launch_morton(const float* pts, uint32_t n, const uint32_t* bounds,
                    uint64_t* keys, uint32_t* hist, hipStream_t s);
-// Sorted float4 leaves + per-point state initialisation; also fills the
-// build's hand-over entries with -1.
-void launch_gather(const float* pts, const uint32_t* perm, uint32_t n,
-                   float4* leaf, int32_t* parent, int32_t* minlab,
-                   uint8_t* flag, unsigned long long* bestcore,
-                   int4* pending, uint32_t pending_entries, hipStream_t s);
+// Points to sorted leaves, leaf[inv[o]] = point o (rope unset), reading the
+// points in input order; also initialises the per-point state and fills the
+// build's hand-over entries with -1.  `inv` may alias `parent`: each thread
+// reads inv[o] before writing parent[o].
+void launch_scatter(const float* pts, const uint32_t* inv, uint32_t n,
+                    float4* leaf, int32_t* parent, int32_t* minlab,
+                    uint8_t* flag, unsigned long long* bestcore,
+                    int4* pending, uint32_t pending_entries, hipStream_t s);
 
 // ---- LBVH (lbvh.hip) --------------------------------------------------------
 constexpr int BUILD_LEAVES = 256;        // leaves per level-1 frame
@@ -72,12 +85,29 @@ int build_levels(uint32_t n);
 // int4 entries of hand-over state the build needs (all levels), -1 filled
 size_t build_pending_entries(uint32_t n);
 // right[k]: right child of internal node k; other[k]: exchange slot (set
-// up by the build itself); rend[k]: last leaf under internal node k.
-void launch_build(const uint64_t* keys, const float4* leaf, uint32_t n,
-                  Node* nodes, int32_t* right, int32_t* other, int32_t* rend,
-                  int32_t* root, int4* pending, uint32_t* err, hipStream_t s);
-void launch_ropes(Node* nodes, float4* leaf, const int32_t* right,
-                  const int32_t* rend, uint32_t n, uint32_t* err, hipStream_t s);
+// up by the build itself).  The build also sets every rope it can resolve
+// inside a level-1 frame; the others go on `fixups` (node reference, last
+// leaf under it; count in *nfix, zeroed before the build).
+// Keys may carry a set id in bits [set_shift, 64) (batched sets; 64 = a
+// single set): ropes are then cut at set ends and set_root[s] receives the
+// root of set s's subtree (for a single set, set_root[0] = the root).
+// `after_level(arg, lv)`, if given, is called after level lv is enqueued.
+void launch_build(const uint64_t* keys, int set_shift, float4* leaf, uint32_t n, Node* nodes,
+                  int32_t* right, int32_t* other, int32_t* set_root, int4* pending,
+                  int2* fixups, uint32_t* nfix, uint32_t* err, hipStream_t s,
+                  void (*after_level)(void*, int) = nullptr, void* arg = nullptr);
+// Sets the ropes of the nodes on the fix-up list.
+void launch_ropes(const uint64_t* keys, int set_shift, Node* nodes, float4* leaf,
+                  const int32_t* right, const int2* fixups, const uint32_t* nfix, uint32_t n,
+                  uint32_t* err, hipStream_t s);
+// The same over box leaves (DenseBox primitives: Node records, payload in
+// `left`, rope in `rope`), single set.
+void launch_build_boxes(const uint64_t* keys, Node* prims, uint32_t n, Node* nodes,
+                        int32_t* right, int32_t* other, int32_t* root, int4* pending,
+                        int2* fixups, uint32_t* nfix, uint32_t* err, hipStream_t s);
+void launch_ropes_boxes(const uint64_t* keys, Node* nodes, Node* prims, const int32_t* right,
+                        const int2* fixups, const uint32_t* nfix, uint32_t n, uint32_t* err,
+                        hipStream_t s);
 
 // ---- traversals (traverse.hip) ---------------------------------------------
 void launch_count(const Node* nodes, const float4* leaf, uint32_t n,
@@ -109,5 +139,59 @@ void launch_final_labels(uint32_t n, const uint32_t* perm, const int32_t* root,
 // dst[perm[i]] = src[i]: from sorted order back to input order
 void launch_scatter_u8(const uint8_t* src, const uint32_t* perm, uint32_t n,
                        uint8_t* dst, hipStream_t s);
+
+// ---- DenseBox (densebox.hip) -----------------------------------------------
+// Cell keys (Morton code of the grid cell, side max(1/inv_h, extent/2^21))
+// plus the digit histograms of the sort.
+void launch_cell_keys(const float* pts, uint32_t n, const uint32_t* bounds, float inv_h,
+                      uint64_t* keys, uint32_t* hist, hipStream_t s);
+// words of look-back state of one exclusive scan of n values (zeroed)
+size_t scan_status_words(uint32_t n);
+void launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total,
+                 uint32_t* status, uint32_t* tile_ctr, uint32_t* err, hipStream_t s);
+// Run heads of the sorted cell keys -> cid (cell of each sorted point),
+// *ncells, cell_start[0..ncells] (cell_start[ncells] = n).
+void launch_cells(const uint64_t* sorted_keys, uint32_t n, uint32_t* head, uint32_t* cid,
+                  uint32_t* ncells, uint32_t* cell_start, uint32_t* scan_status,
+                  uint32_t* scan_ctr, uint32_t* err, hipStream_t s);
+void launch_cell_stats(const float4* pts, const uint32_t* perm, uint32_t n,
+                       const uint32_t* ncells, const uint32_t* cell_start, float e2,
+                       int32_t thresh, float4* cell_lo, float4* cell_hi,
+                       unsigned long long* cell_minorig, uint8_t* cell_dense,
+                       uint32_t* prim_count, hipStream_t s);
+void launch_make_prims(const float4* pts, const uint64_t* keys, uint32_t n, const uint32_t* cid,
+                       const uint32_t* cell_start, const uint32_t* prim_start,
+                       const uint8_t* cell_dense, const float4* cell_lo, const float4* cell_hi,
+                       Node* prims, uint64_t* pkey, int32_t* parent, uint8_t* flag,
+                       hipStream_t s);
+void launch_count_db(const Node* nodes, const Node* prims, uint32_t nprims, const float4* pts,
+                     uint32_t n, const uint32_t* cell_start, const int32_t* root, float e2,
+                     int32_t min_pts, uint8_t* flag, uint32_t* err, int block, hipStream_t s);
+void launch_pairs_db(const Node* nodes, const Node* prims, uint32_t nprims, const float4* pts,
+                     uint32_t n, const uint32_t* cell_start, const uint32_t* perm,
+                     const unsigned long long* cell_minorig, float e2, bool core_mode,
+                     int32_t* parent, uint8_t* flag, unsigned long long* bestcore, uint32_t* err,
+                     int block, hipStream_t s);
+
+// ---- batched sets (batched.hip) -----------------------------------------------
+// Keys of every set: (set id << set_shift) | Morton code with `bits` bits per
+// axis inside the set's own bounding box; set_root[s] = -1 for every set.
+void launch_set_morton(const float* pts, const int64_t* offsets, uint32_t num_sets, int bits,
+                       int set_shift, uint64_t* keys, uint32_t* hist, int32_t* set_root,
+                       uint32_t* status, hipStream_t s);
+void launch_count_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
+                       int set_shift, const int32_t* set_root, const float* set_e2,
+                       const int32_t* set_minpts, uint8_t* flag, uint32_t* err, int block,
+                       hipStream_t s);
+void launch_pairs_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
+                       int set_shift, const float* set_e2, const int32_t* set_minpts,
+                       const uint32_t* perm, int32_t* parent, uint8_t* flag,
+                       unsigned long long* bestcore, uint32_t* err, int block, hipStream_t s);
+// labels are set-local: smallest input index in the cluster minus the
+// set's offset
+void launch_final_sets(uint32_t n, const uint64_t* keys, int set_shift, const int32_t* set_minpts,
+                       const int64_t* offsets, const uint8_t* flag,
+                       const unsigned long long* bestcore, const uint32_t* perm, int32_t* parent,
+                       int32_t* minlab, int32_t* labels, hipStream_t s);
 
 }  // namespace dbx

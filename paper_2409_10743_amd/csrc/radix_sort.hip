@@ -11,6 +11,7 @@
 // than spinning forever.  Keys and values are staged in LDS in digit order
 // so the global writes go out as runs of consecutive addresses.
 #include <algorithm>
+#include <cstdlib>
 
 #include "pipeline.hpp"
 
@@ -57,17 +58,19 @@ __global__ __launch_bounds__(256) void k_digit_hist(const uint64_t* __restrict__
     if (sh[t]) atomicAdd(&hist[t], sh[t]);
 }
 
-template <bool IOTA>
-__global__ __launch_bounds__(SORT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_onesweep(
+// inv (optional, last pass only): inv[value] = the value's final position.
+template <bool IOTA, int ITEMS>
+__global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
     const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout,
     const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout, uint32_t n,
     int shift, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
-    uint32_t* __restrict__ tile_ctr, uint32_t* __restrict__ err) {
-  __shared__ uint64_t s_buf[SORT_TILE];       // keys, then values, in digit order
+    uint32_t* __restrict__ tile_ctr, uint32_t* __restrict__ err, uint32_t* __restrict__ inv) {
+  constexpr int TILE = SORT_THREADS * ITEMS;
+  __shared__ uint64_t s_buf[TILE];            // keys, then values, in digit order
   // per-wave digit counts, then prefixes; once every key's position is
   // known the same bytes hold the digit of the key at each position
   __shared__ uint32_t s_whist[WAVES][RADIX];
-  static_assert(sizeof(s_whist) >= SORT_TILE, "digit bytes alias the wave counters");
+  static_assert(sizeof(s_whist) >= TILE, "digit bytes alias the wave counters");
   uint8_t* const s_dig = reinterpret_cast<uint8_t*>(&s_whist[0][0]);
   __shared__ uint32_t s_base[RADIX];          // global offset - local offset
   __shared__ uint32_t s_loff[RADIX];          // local (in-tile) digit offsets
@@ -79,15 +82,15 @@ __global__ __launch_bounds__(SORT_THREADS) __attribute__((amdgpu_waves_per_eu(4,
   for (int w = 0; w < WAVES; ++w) s_whist[w][tid] = 0;
   __syncthreads();
   const uint32_t tile = s_tile;
-  const uint32_t tile_base = tile * SORT_TILE;
-  const uint32_t wbase = tile_base + wave * (64 * SORT_ITEMS);
+  const uint32_t tile_base = tile * TILE;
+  const uint32_t wbase = tile_base + wave * (64 * ITEMS);
 
-  uint64_t key[SORT_ITEMS];
-  uint32_t rank[SORT_ITEMS];
+  uint64_t key[ITEMS];
+  uint32_t rank[ITEMS];
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
 #pragma unroll
-  for (int k = 0; k < SORT_ITEMS; ++k) {
+  for (int k = 0; k < ITEMS; ++k) {
     uint32_t idx = wbase + k * 64 + lane;
     key[k] = idx < n ? kin[idx] : ~0ull;
   }
@@ -95,7 +98,7 @@ __global__ __launch_bounds__(SORT_THREADS) __attribute__((amdgpu_waves_per_eu(4,
   // rank each key among the keys of this wave with the same digit; the
   // order of keys inside a wave is (item, lane), i.e. their input order
 #pragma unroll
-  for (int k = 0; k < SORT_ITEMS; ++k) {
+  for (int k = 0; k < ITEMS; ++k) {
     uint32_t idx = wbase + k * 64 + lane;
     bool ok = idx < n;
     uint32_t d = uint32_t(key[k] >> shift) & 0xff;
@@ -156,14 +159,14 @@ __global__ __launch_bounds__(SORT_THREADS) __attribute__((amdgpu_waves_per_eu(4,
 
   // in-tile position of every key (rank[] becomes the position)
 #pragma unroll
-  for (int k = 0; k < SORT_ITEMS; ++k) {
+  for (int k = 0; k < ITEMS; ++k) {
     uint32_t dd = uint32_t(key[k] >> shift) & 0xff;
     rank[k] += s_loff[dd] + s_whist[wave][dd];
   }
   __syncthreads();
   // stage the keys in digit order
 #pragma unroll
-  for (int k = 0; k < SORT_ITEMS; ++k) {
+  for (int k = 0; k < ITEMS; ++k) {
     uint32_t idx = wbase + k * 64 + lane;
     if (idx < n) {
       s_buf[rank[k]] = key[k];
@@ -171,7 +174,7 @@ __global__ __launch_bounds__(SORT_THREADS) __attribute__((amdgpu_waves_per_eu(4,
     }
   }
   __syncthreads();
-  const uint32_t tile_n = min(uint32_t(SORT_TILE), n - tile_base);
+  const uint32_t tile_n = min(uint32_t(TILE), n - tile_base);
   for (uint32_t p = tid; p < tile_n; p += SORT_THREADS) {
     uint32_t dst = s_base[s_dig[p]] + p;
     if (dst < n) kout[dst] = s_buf[p];  // always true unless a wait was cut short
@@ -180,14 +183,18 @@ __global__ __launch_bounds__(SORT_THREADS) __attribute__((amdgpu_waves_per_eu(4,
   // then the values through the same buffer
   uint32_t* s_val = reinterpret_cast<uint32_t*>(s_buf);
 #pragma unroll
-  for (int k = 0; k < SORT_ITEMS; ++k) {
+  for (int k = 0; k < ITEMS; ++k) {
     uint32_t idx = wbase + k * 64 + lane;
     if (idx < n) s_val[rank[k]] = IOTA ? idx : vin[idx];
   }
   __syncthreads();
   for (uint32_t p = tid; p < tile_n; p += SORT_THREADS) {
     uint32_t dst = s_base[s_dig[p]] + p;
-    if (dst < n) vout[dst] = s_val[p];
+    if (dst < n) {
+      const uint32_t v = s_val[p];
+      vout[dst] = v;
+      if (inv && v < n) inv[v] = dst;
+    }
   }
 }
 
@@ -200,27 +207,51 @@ void launch_digit_histogram(const uint64_t* keys, uint32_t n, uint32_t* hist,
   hipLaunchKernelGGL(k_digit_hist, dim3(blocks), dim3(256), 0, s, keys, n, hist);
 }
 
+int sort_items() {
+  static const int items = [] {
+    const char* e = std::getenv("DBX_SORT_ITEMS");
+    int v = e ? std::atoi(e) : SORT_ITEMS;
+    return (v == 8 || v == 12 || v == 16) ? v : SORT_ITEMS;
+  }();
+  return items;
+}
+
+namespace {
+template <int ITEMS>
+void sort_pass(bool iota, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
+               uint32_t* vout, uint32_t n, int p, const SortScratch& sc, uint32_t* st,
+               uint32_t* inv, hipStream_t s) {
+  const uint32_t tiles = sort_tiles(n, ITEMS);
+  if (iota)
+    hipLaunchKernelGGL((k_onesweep<true, ITEMS>), dim3(tiles), dim3(SORT_THREADS), 0, s, kin,
+                       kout, vin, vout, n, 8 * p, sc.hist + p * RADIX, st, sc.tile_ctr + p,
+                       sc.err, inv);
+  else
+    hipLaunchKernelGGL((k_onesweep<false, ITEMS>), dim3(tiles), dim3(SORT_THREADS), 0, s, kin,
+                       kout, vin, vout, n, 8 * p, sc.hist + p * RADIX, st, sc.tile_ctr + p,
+                       sc.err, inv);
+}
+}  // namespace
+
 bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
                        uint32_t n, int first_pass, bool iota_vals,
                        const SortScratch& sc, hipStream_t s,
-                       void (*after_pass)(void*, int), void* arg) {
+                       void (*after_pass)(void*, int), void* arg, uint32_t* inv) {
   bool in_a = true;
   if (n == 0) return true;
-  const uint32_t tiles = sort_tiles(n);
+  const int items = sort_items();
+  const uint32_t words = sort_tiles(n, items) * RADIX;
   for (int p = first_pass; p < SORT_PASSES; ++p) {
     const uint64_t* kin = in_a ? ka : kb;
     uint64_t* kout = in_a ? kb : ka;
     const uint32_t* vin = in_a ? va : vb;
     uint32_t* vout = in_a ? vb : va;
-    uint32_t* st = sc.status + size_t(p) * tiles * RADIX;
-    if (p == first_pass && iota_vals)
-      hipLaunchKernelGGL(k_onesweep<true>, dim3(tiles), dim3(SORT_THREADS), 0, s, kin,
-                         kout, vin, vout, n, 8 * p, sc.hist + p * RADIX, st,
-                         sc.tile_ctr + p, sc.err);
-    else
-      hipLaunchKernelGGL(k_onesweep<false>, dim3(tiles), dim3(SORT_THREADS), 0, s, kin,
-                         kout, vin, vout, n, 8 * p, sc.hist + p * RADIX, st,
-                         sc.tile_ctr + p, sc.err);
+    uint32_t* st = sc.status + size_t(p) * words;
+    const bool iota = p == first_pass && iota_vals;
+    uint32_t* pinv = p == SORT_PASSES - 1 ? inv : nullptr;
+    if (items == 8) sort_pass<8>(iota, kin, kout, vin, vout, n, p, sc, st, pinv, s);
+    else if (items == 12) sort_pass<12>(iota, kin, kout, vin, vout, n, p, sc, st, pinv, s);
+    else sort_pass<16>(iota, kin, kout, vin, vout, n, p, sc, st, pinv, s);
     if (after_pass) after_pass(arg, p);
     in_a = !in_a;
   }
