@@ -58,6 +58,7 @@ BYTES_PER_POINT = {
                                               # ropes), nodes, right child, exchange slot
     "build_levels": 0.0,            # a few nodes per 256-leaf frame
     "ropes": 0.0,                   # only the listed nodes whose rope the build left open
+    "cells": 0.0,                   # DenseBox only
     "count": 16 + 32 + 1,           # leaves, nodes, core flag
     "pairs": 16 + 32 + 4 + 4 + 1,   # leaves, nodes, parent read/write, member flag
     "final_roots": 1 + 4 + 4 + 4 + 4,
@@ -71,13 +72,14 @@ LAST_SORT_PASS_EXTRA = 4.0
 KERNEL_OF_PHASE = {f"sort{p}": "sort" for p in range(8)}
 KERNEL_NAME = {  # device function names, as rocprofv3 reports them
     "sort": "k_onesweep", "pairs": "k_pairs", "build_frame": "k_build_frame",
-    "build_levels": "k_build_level", "scatter": "k_scatter",
+    "build_levels": "k_build_level", "scatter": "k_scatter", "cells": "k_cell_stats",
     "morton": "k_morton", "bounds": "k_bounds", "ropes": "k_ropes", "count": "k_count",
     "final_roots": "k_final_roots", "final_labels": "k_final_labels", "prep": "k_prep",
 }
 KERNEL_SOURCE = {
     "sort": "radix_sort.hip", "pairs": "traverse.hip", "count": "traverse.hip",
     "build_frame": "lbvh.hip", "build_levels": "lbvh.hip", "ropes": "lbvh.hip",
+    "cells": "densebox.hip",
     "scatter": "morton.hip", "morton": "morton.hip",
     "bounds": "morton.hip", "prep": "morton.hip", "final_roots": "finalize.hip",
     "final_labels": "finalize.hip",

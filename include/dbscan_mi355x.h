@@ -118,6 +118,20 @@ int dbscan_phase_times(const dbscan_ctx* ctx, float* ms, int32_t max);
  * not use reads 0 ms), NULL past the last. */
 const char* dbscan_phase_name(int32_t k);
 
+/* ---- autotuning ---------------------------------------------------------------- */
+/* Run the call on the given input once per candidate option set (traversal
+ * workgroup sizes 64/128/256/512; for DenseBox also dense thresholds minPts,
+ * 2*minPts, 4*minPts), time each (best of two after a warm-up, HIP events on
+ * `stream`) and return the fastest in *best (its time in *best_ms).  The
+ * candidates cannot change the labels, which end in `labels` (device). */
+int dbscan_autotune(dbscan_ctx* ctx, const float* points, int64_t n, float eps,
+                    int32_t min_pts, int32_t algorithm, int32_t* labels,
+                    dbscan_options* best, float* best_ms, void* stream);
+int dbscan_autotune_batched(dbscan_ctx* ctx, const float* points, const int64_t* offsets,
+                            int32_t num_sets, const float* eps, const int32_t* min_pts,
+                            int32_t* labels, dbscan_options* best, float* best_ms,
+                            void* stream);
+
 /* ---- serving: continuous batching of arriving jobs -------------------------- */
 /* A server runs jobs that arrive one at a time (host buffers) on one GPU.
  * Work of several jobs is on the device at once (`slots` worker threads, each

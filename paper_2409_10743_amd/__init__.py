@@ -100,6 +100,11 @@ def load_library() -> ctypes.CDLL:
                                      ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "dbscan_server_stats": ([vp, ctypes.POINTER(_ServingStats)], ctypes.c_int),
         "dbscan_server_destroy": ([vp], ctypes.c_int),
+        "dbscan_autotune": ([vp, vp, i64, f32, i32, i32, vp, ctypes.POINTER(_Options),
+                             ctypes.POINTER(f32), vp], ctypes.c_int),
+        "dbscan_autotune_batched": ([vp, vp, ctypes.POINTER(i64), i32, ctypes.POINTER(f32),
+                                     ctypes.POINTER(i32), vp, ctypes.POINTER(_Options),
+                                     ctypes.POINTER(f32), vp], ctypes.c_int),
         "dbscan_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "dbscan_last_error": ([], ctypes.c_char_p),
         "dbscan_version": ([], ctypes.c_char_p),
@@ -202,6 +207,38 @@ class Context:
             m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
             ctypes.c_void_p(labels.data_ptr()), _stream(p.device), ctypes.byref(o)))
         return labels
+
+    def autotune(self, points, eps: float, min_pts: int, algorithm: str = "fdbscan"):
+        """Fastest (block_size, dense_threshold) for this input, with its time
+        in ms; see dbscan_autotune."""
+        torch = _torch()
+        p = _points(points)
+        lab = torch.empty(p.shape[0], dtype=torch.int32, device=p.device)
+        o, ms = _Options(), ctypes.c_float(0)
+        _check(load_library().dbscan_autotune(
+            self.handle, ctypes.c_void_p(p.data_ptr()), p.shape[0], ctypes.c_float(eps),
+            int(min_pts), ALGO[algorithm], ctypes.c_void_p(lab.data_ptr()), ctypes.byref(o),
+            ctypes.byref(ms), _stream(p.device)))
+        return {"block_size": o.block_size, "dense_threshold": o.dense_threshold,
+                "ms": ms.value}
+
+    def autotune_batched(self, points, offsets, eps, min_pts):
+        import numpy as np
+        torch = _torch()
+        p = _points(points)
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        k = off.size - 1
+        e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.float32), (k,)))
+        m = np.ascontiguousarray(np.broadcast_to(np.asarray(min_pts, np.int32), (k,)))
+        lab = torch.empty(p.shape[0], dtype=torch.int32, device=p.device)
+        o, ms = _Options(), ctypes.c_float(0)
+        _check(load_library().dbscan_autotune_batched(
+            self.handle, ctypes.c_void_p(p.data_ptr()),
+            off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), k,
+            e.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+            m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.c_void_p(lab.data_ptr()),
+            ctypes.byref(o), ctypes.byref(ms), _stream(p.device)))
+        return {"block_size": o.block_size, "ms": ms.value}
 
     def phase_times(self) -> dict:
         buf = (ctypes.c_float * len(PHASES))()

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/dbscan_mi355x.h"
 #include "pipeline.hpp"
@@ -133,7 +134,7 @@ struct dbscan_ctx {
   hipEvent_t ev[NPHASES + 1] = {};
   float times[NPHASES] = {};
   int ntimes = 0;
-  int next_mark = 0;
+  bool recorded[NPHASES + 1] = {};
 };
 
 namespace {
@@ -209,16 +210,19 @@ struct Index {
   uint32_t* status;
 };
 
-// ev[0] is recorded before the first kernel, ev[k + 1] after phase k; a
-// phase that does not run is marked right after the previous one.
+// ev[0] is recorded before the first kernel, ev[k + 1] right after phase
+// k's kernels; a phase's time runs from the previous recorded event, and a
+// phase that records nothing reads 0.
 void start_timing(dbscan_ctx* c, bool timing, hipStream_t s) {
-  c->next_mark = 0;
-  if (timing) (void)hipEventRecord(c->ev[0], s);
+  for (auto& r : c->recorded) r = false;
+  if (!timing) return;
+  (void)hipEventRecord(c->ev[0], s);
+  c->recorded[0] = true;
 }
 void mark(dbscan_ctx* c, bool timing, int phase, hipStream_t s) {
   if (!timing) return;
-  for (int k = c->next_mark; k <= phase; ++k) (void)hipEventRecord(c->ev[k + 1], s);
-  c->next_mark = phase + 1;
+  (void)hipEventRecord(c->ev[phase + 1], s);
+  c->recorded[phase + 1] = true;
 }
 struct SortMarks {
   dbscan_ctx* c;
@@ -296,9 +300,13 @@ int finish(dbscan_ctx* c, const uint32_t* dev_status, bool timing, hipStream_t s
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipGetLastError());
   if (timing) {
+    int prev = 0;
     for (int k = 0; k < NPHASES; ++k) {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]) != hipSuccess) ms = 0.f;
+      if (c->recorded[k + 1]) {
+        if (hipEventElapsedTime(&ms, c->ev[prev], c->ev[k + 1]) != hipSuccess) ms = 0.f;
+        prev = k + 1;
+      }
       c->times[k] = ms;
     }
     c->ntimes = NPHASES;
@@ -572,6 +580,58 @@ dbscan_options defaults() {
 
 }  // namespace
 
+// ---- autotuning -------------------------------------------------------------
+namespace {
+template <class Run>
+int tune(dbscan_ctx* c, hipStream_t s, const std::vector<dbscan_options>& cands,
+         dbscan_options* best, float* best_ms, Run run) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float bm = 0;
+  int bi = -1, st = DBSCAN_OK;
+  for (size_t k = 0; k < cands.size() && st == DBSCAN_OK; ++k) {
+    st = run(cands[k]);  // warm: sizes the arena, loads the code
+    float t = 1e30f;
+    for (int r = 0; r < 2 && st == DBSCAN_OK; ++r) {
+      (void)hipEventRecord(e0, s);
+      st = run(cands[k]);
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      t = std::min(t, ms);
+    }
+    if (st == DBSCAN_OK && (bi < 0 || t < bm)) { bm = t; bi = int(k); }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != DBSCAN_OK) return st;
+  *best = cands[size_t(bi)];
+  if (best_ms) *best_ms = bm;
+  (void)c;
+  return DBSCAN_OK;
+}
+
+std::vector<dbscan_options> candidates(int32_t algorithm, int32_t min_pts) {
+  std::vector<dbscan_options> v;
+  for (int bs : {64, 128, 256, 512}) {
+    dbscan_options o{};
+    o.algorithm = algorithm;
+    o.block_size = bs;
+    if (algorithm == DBSCAN_ALGO_DENSEBOX) {
+      for (int f : {1, 2, 4}) {
+        o.dense_threshold = min_pts * f;
+        v.push_back(o);
+      }
+    } else {
+      v.push_back(o);
+    }
+  }
+  return v;
+}
+}  // namespace
+
 extern "C" {
 
 int dbscan_ctx_create(int device, uint64_t hbm_budget_bytes, dbscan_ctx** out) {
@@ -803,6 +863,39 @@ int dbscan_pair_count(dbscan_ctx* c, const float* points, int64_t n, float eps, 
   st = finish(c, ix.status, false, s);
   if (st == DBSCAN_OK) *count = int64_t(*h);
   return st;
+}
+
+int dbscan_autotune(dbscan_ctx* c, const float* points, int64_t n, float eps, int32_t min_pts,
+                    int32_t algorithm, int32_t* labels, dbscan_options* best, float* best_ms,
+                    void* stream) {
+  if (!c || !best) return fail(DBSCAN_EINVAL, "null pointer");
+  int st = check_args(points, n, eps, min_pts, labels);
+  if (st != DBSCAN_OK) return st;
+  if (algorithm < DBSCAN_ALGO_AUTO || algorithm > DBSCAN_ALGO_DENSEBOX)
+    return fail(DBSCAN_EINVAL, "unknown algorithm");
+  const int32_t algo = algorithm == DBSCAN_ALGO_AUTO ? DBSCAN_ALGO_FDBSCAN : algorithm;
+  if (n == 0) {
+    *best = candidates(algo, min_pts)[0];
+    if (best_ms) *best_ms = 0;
+    return DBSCAN_OK;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return tune(c, s, candidates(algo, min_pts), best, best_ms, [&](const dbscan_options& o) {
+    return dbscan_cluster_ex(c, points, n, eps, min_pts, labels, stream, &o);
+  });
+}
+
+int dbscan_autotune_batched(dbscan_ctx* c, const float* points, const int64_t* offsets,
+                            int32_t num_sets, const float* eps, const int32_t* min_pts,
+                            int32_t* labels, dbscan_options* best, float* best_ms,
+                            void* stream) {
+  if (!c || !best) return fail(DBSCAN_EINVAL, "null pointer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return tune(c, s, candidates(DBSCAN_ALGO_FDBSCAN, 1), best, best_ms,
+              [&](const dbscan_options& o) {
+                return dbscan_cluster_batched(c, points, offsets, num_sets, eps, min_pts, labels,
+                                              stream, &o);
+              });
 }
 
 const char* dbscan_strerror(int status) {

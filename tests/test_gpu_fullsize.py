@@ -1,0 +1,44 @@
+"""The 2^27-point halo field (box [0,512)^3, eps 0.2) at full size on the
+GPU: every label satisfies the canonical-form properties, and labels in
+sub-cubes are checked exactly against the oracle (tests/localcheck.py)."""
+import numpy as np
+import pytest
+
+import datagen
+import localcheck
+
+torch = pytest.importorskip("torch")
+import paper_2409_10743_amd as dbx  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+F32 = np.float32
+CUBES = [((100, 100, 100), (116, 116, 116)), ((300, 40, 470), (316, 56, 486)),
+         ((0, 0, 0), (14, 14, 14))]
+
+
+@pytest.fixture(scope="module")
+def field():
+    p = datagen.config_points("halo134M")
+    return p, torch.from_numpy(p).cuda()
+
+
+def canonical_form(lab):
+    """-1 or a label c with lab[c] == c and every member index >= c."""
+    n = lab.shape[0]
+    v = np.flatnonzero(lab >= 0)
+    assert lab.min() >= -1 and lab.max() < n
+    assert (lab[lab[v]] == lab[v]).all()
+    assert (v >= lab[v]).all()
+
+
+@pytest.mark.parametrize("algo,mp", [("fdbscan", 2), ("fdbscan", 10), ("densebox", 2)])
+def test_halo134m(field, algo, mp):
+    p, d = field
+    ctx = dbx.Context(0)
+    lab = ctx.cluster(d, 0.2, mp, algorithm=algo).cpu().numpy()
+    ctx.close()
+    canonical_form(lab)
+    checked = 0
+    for lo, hi in CUBES:
+        checked += localcheck.check_cube(p, lab, lo, hi, F32(0.2), mp, margin=1.0)
+    assert checked > 10000

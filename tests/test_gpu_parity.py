@@ -280,3 +280,14 @@ def halo16m():
 def test_halo16m_minpts2_bit_exact(ctx, halo16m):
     p, ref = halo16m
     np.testing.assert_array_equal(run(ctx, p, F32(0.2), 2), ref)
+
+
+def test_autotune_returns_options_that_keep_labels(ctx):
+    p = clumpy(60000, 21)
+    ref = oracle.dbscan(p, F32(0.01), 4)
+    for algo in ("fdbscan", "densebox"):
+        best = ctx.autotune(dev(p), 0.01, 4, algorithm=algo)
+        assert best["block_size"] in (64, 128, 256, 512) and best["ms"] > 0
+        got = run(ctx, p, 0.01, 4, algorithm=algo, block_size=best["block_size"],
+                  dense_threshold=best["dense_threshold"])
+        np.testing.assert_array_equal(got, ref)

@@ -347,3 +347,21 @@ def test_pins_catch_planted_mistake(mutant):
                             out=os.path.join(d, "liboracle_mutant.so"))
         lib = oracle.load(path)
         assert _pin_failures(lib), f"mutant {mutant} passed every pin"
+
+
+# ---- the local spot-check used at sizes too large for the whole-field oracle
+
+def test_local_check_agrees_with_whole_field_oracle():
+    import localcheck
+    p = datagen.halo_field(1 << 18, 256.0 * (1 / 64) ** (1 / 3), 5)
+    for mp in (2, 3):
+        full = oracle.dbscan(p, F32(0.2), mp)
+        checked = localcheck.check_cube(p, full, (10, 10, 10), (30, 30, 30), 0.2, mp, 4.0)
+        assert checked > 1000
+        bad = full.copy()
+        inner = np.all((p > 12) & (p < 28), axis=1)
+        lab_k = np.flatnonzero(inner & (full >= 0))
+        k = lab_k[0] if lab_k.size else np.flatnonzero(inner)[0]
+        bad[k] = -1 if full[k] >= 0 else int(k)  # a clustered point as noise, or vice versa
+        with pytest.raises(AssertionError):
+            localcheck.check_cube(p, bad, (10, 10, 10), (30, 30, 30), 0.2, mp, 4.0)
