@@ -52,8 +52,8 @@ BYTES_PER_POINT = {
     "bounds": 12.0,                 # read xyz
     "morton": 12.0 + 8.0,           # read xyz, write code
     "sort": 24.0,                   # per pass: read code+index, write code+index
-    "scatter": 12 + 4 + 16 + 4 + 4 + 1,  # read xyz, position; write leaf, parent,
-                                         # minlab, flag
+    "gather": 4 + 12 + 16 + 4 + 4 + 1,  # read index, xyz; write leaf, parent,
+                                        # minlab, flag
     "build_frame": 8 + 16 + 16 + 32 + 4 + 4,  # codes, leaves in, leaves out (with
                                               # ropes), nodes, right child, exchange slot
     "build_levels": 0.0,            # a few nodes per 256-leaf frame
@@ -64,15 +64,13 @@ BYTES_PER_POINT = {
     "final_roots": 1 + 4 + 4 + 4 + 4,
     "final_labels": 4 + 4 + 4 + 4,
 }
-# the first sort pass reads no values (they are the identity); the last also
-# writes each point's sorted position (4 bytes)
+# the first sort pass reads no values (they are the identity)
 FIRST_SORT_PASS_BYTES = 20.0
-LAST_SORT_PASS_EXTRA = 4.0
 
 KERNEL_OF_PHASE = {f"sort{p}": "sort" for p in range(8)}
 KERNEL_NAME = {  # device function names, as rocprofv3 reports them
     "sort": "k_onesweep", "pairs": "k_pairs", "build_frame": "k_build_frame",
-    "build_levels": "k_build_level", "scatter": "k_scatter", "cells": "k_cell_stats",
+    "build_levels": "k_build_level", "gather": "k_gather", "cells": "k_cell_stats",
     "morton": "k_morton", "bounds": "k_bounds", "ropes": "k_ropes", "count": "k_count",
     "final_roots": "k_final_roots", "final_labels": "k_final_labels", "prep": "k_prep",
 }
@@ -80,7 +78,7 @@ KERNEL_SOURCE = {
     "sort": "radix_sort.hip", "pairs": "traverse.hip", "count": "traverse.hip",
     "build_frame": "lbvh.hip", "build_levels": "lbvh.hip", "ropes": "lbvh.hip",
     "cells": "densebox.hip",
-    "scatter": "morton.hip", "morton": "morton.hip",
+    "gather": "morton.hip", "morton": "morton.hip",
     "bounds": "morton.hip", "prep": "morton.hip", "final_roots": "finalize.hip",
     "final_labels": "finalize.hip",
 }
@@ -202,8 +200,7 @@ def main():
     dom = max(per_kernel, key=per_kernel.get)
     launch_ms = per_kernel[dom] / max(1, launches.get(dom, 1))
     if dom == "sort":
-        bytes_launch = n * (FIRST_SORT_PASS_BYTES + 7 * BYTES_PER_POINT["sort"]
-                            + LAST_SORT_PASS_EXTRA) / 8.0
+        bytes_launch = n * (FIRST_SORT_PASS_BYTES + 7 * BYTES_PER_POINT["sort"]) / 8.0
     else:
         bytes_launch = n * BYTES_PER_POINT[dom]
     achieved = bytes_launch / (launch_ms / 1000.0) / 1e9
@@ -225,6 +222,13 @@ def main():
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "sort_keys_per_s": round(n / (sort_ms / 1000.0), 1) if sort_ms > 0 else None,
     }
+
+    # node visits of one pair traversal (outside the timed region): what the
+    # pairs kernel's time is spent on
+    ts = ctx.traversal_stats(d, float(eps))
+    out["traversal"] = {k: v for k, v in ts.items()}
+    out["traversal"].update({"internal_visits_per_point": round(ts["internal_visits"] / n, 2),
+                             "leaf_tests_per_point": round(ts["leaf_tests"] / n, 2)})
 
     if not args.no_cpu_baseline:
         import oracle

@@ -216,6 +216,10 @@ int dbscan_core_flags(dbscan_ctx* ctx, const float* points, int64_t n, float eps
  * count: host pointer. */
 int dbscan_pair_count(dbscan_ctx* ctx, const float* points, int64_t n, float eps,
                       int64_t* count, void* stream);
+/* The same traversal with counters: out3[0] pairs, out3[1] internal-node
+ * visits, out3[2] leaf tests, summed over all queries (host int64[3]). */
+int dbscan_traversal_stats(dbscan_ctx* ctx, const float* points, int64_t n, float eps,
+                           int64_t* out3, void* stream);
 
 /* ---- diagnostics ------------------------------------------------------------ */
 const char* dbscan_strerror(int status);

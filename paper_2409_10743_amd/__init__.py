@@ -91,6 +91,7 @@ def load_library() -> ctypes.CDLL:
         "dbscan_build_tree": ([vp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
         "dbscan_core_flags": ([vp, vp, i64, f32, i32, vp, vp], ctypes.c_int),
         "dbscan_pair_count": ([vp, vp, i64, f32, ctypes.POINTER(i64), vp], ctypes.c_int),
+        "dbscan_traversal_stats": ([vp, vp, i64, f32, ctypes.POINTER(i64), vp], ctypes.c_int),
         "dbscan_server_create": ([ctypes.POINTER(_ServerOptions), ctypes.POINTER(vp)],
                                  ctypes.c_int),
         "dbscan_server_submit": ([vp, vp, i64, f32, i32, vp, ctypes.POINTER(u64)], ctypes.c_int),
@@ -142,7 +143,7 @@ def _stream(device) -> ctypes.c_void_p:
 
 # one timing slot per kernel launch, in launch order
 PHASES = ("prep", "bounds", "morton", "sort0", "sort1", "sort2", "sort3", "sort4", "sort5",
-          "sort6", "sort7", "scatter", "cells", "build_frame", "build_levels", "ropes", "count",
+          "sort6", "sort7", "gather", "cells", "build_frame", "build_levels", "ropes", "count",
           "pairs", "final_roots", "final_labels")
 
 
@@ -288,6 +289,14 @@ class Context:
             self.handle, ctypes.c_void_p(p.data_ptr()), p.shape[0], ctypes.c_float(eps),
             int(min_pts), ctypes.c_void_p(core.data_ptr()), _stream(p.device)))
         return core
+
+    def traversal_stats(self, points, eps: float) -> dict:
+        p = _points(points)
+        out = (ctypes.c_int64 * 3)()
+        _check(load_library().dbscan_traversal_stats(
+            self.handle, ctypes.c_void_p(p.data_ptr()), p.shape[0], ctypes.c_float(eps), out,
+            _stream(p.device)))
+        return {"pairs": out[0], "internal_visits": out[1], "leaf_tests": out[2]}
 
     def pair_count(self, points, eps: float) -> int:
         p = _points(points)

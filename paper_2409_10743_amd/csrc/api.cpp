@@ -40,7 +40,7 @@ int fail(int code, const std::string& msg) {
 
 // One timing slot per kernel launch of a run (a slot a run skips reads 0).
 enum Phase {
-  PH_PREP, PH_BOUNDS, PH_MORTON, PH_SORT0, PH_SCATTER = PH_SORT0 + SORT_PASSES, PH_CELLS,
+  PH_PREP, PH_BOUNDS, PH_MORTON, PH_SORT0, PH_GATHER = PH_SORT0 + SORT_PASSES, PH_CELLS,
   PH_BUILD_FRAME, PH_BUILD_LEVELS, PH_ROPES, PH_COUNT, PH_PAIRS, PH_FINAL_ROOTS,
   PH_FINAL_LABELS, NPHASES
 };
@@ -48,7 +48,7 @@ enum Phase {
 // "cells" (DenseBox only) covers run heads, scans, cell stats, primitives.
 const char* const kPhaseNames[NPHASES] = {
     "prep",  "bounds",  "morton",      "sort0",        "sort1",  "sort2",
-    "sort3", "sort4",   "sort5",       "sort6",        "sort7",  "scatter",
+    "sort3", "sort4",   "sort5",       "sort6",        "sort7",  "gather",
     "cells", "build_frame", "build_levels", "ropes", "count", "pairs", "final_roots",
     "final_labels"};
 
@@ -57,7 +57,7 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 // Byte offsets of every buffer of a job inside the arena.
 struct Layout {
   size_t keys_a, keys_b, vals_a, vals_b, leaf, nodes, parent, minlab, flag, bestcore, pending,
-      fixups, nfix;
+      fixups, fix_cnt;
   // DenseBox only (0 otherwise)
   size_t cid, head, cell_start, cell_lo, cell_hi, cell_minorig, cell_dense, prim_count,
       prim_start, prims, pkey, scan1, scan2, scan_ctr, ncells, nprims;
@@ -77,7 +77,7 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
   L.keys_b = take(size_t(n) * 8);  // after the sort: union-find scratch of the build
   L.vals_a = take(size_t(n) * 4);
   L.vals_b = take(size_t(n) * 4);
-  L.leaf = take(size_t(n) * 16);
+  L.leaf = take((size_t(n) + 1) * 16);  // + one padding record read by the walks
   L.nodes = take(size_t(n > 1 ? n - 1 : 1) * sizeof(Node));
   L.parent = take(size_t(n) * 4);
   L.minlab = take(size_t(n) * 4);
@@ -85,7 +85,8 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
   L.bestcore = need_bestcore ? take(size_t(n) * 8) : 0;
   L.pending_entries = uint32_t(build_pending_entries(n));
   L.pending = take(size_t(L.pending_entries) * 16);
-  L.fixups = take(size_t(n) * 2 * 8);
+  L.fixups = take(build_fix_entries(n) * 8);
+  L.fix_cnt = take(size_t(build_frames(n)) * 4);
   if (densebox) {
     L.cid = take(size_t(n) * 4);
     L.head = take(size_t(n) * 4);
@@ -106,8 +107,7 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
   L.hist = take(SORT_PASSES * RADIX * 4);
   L.tile_ctr = take(SORT_PASSES * 4);
   L.status = take(4);
-  L.count = take(8);
-  L.nfix = take(4);
+  L.count = take(3 * 8);  // pairs, internal-node visits, leaf tests
   if (densebox) {
     L.scan_ctr = take(8);
     L.ncells = take(8);  // ncells and nprims side by side: read back together
@@ -260,28 +260,25 @@ int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore,
   launch_morton(pts, n, bounds, ka, sc.hist, s);
   mark(c, timing, PH_MORTON, s);
   SortMarks sm{c, s};
-  // the last pass also records each point's sorted position in `inv`,
-  // which shares memory with `parent` (set only after inv is consumed)
-  uint32_t* inv = at<uint32_t>(c, L.parent);
   bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, s,
-                                timing ? sort_mark : nullptr, &sm, inv);
+                                timing ? sort_mark : nullptr, &sm);
   uint64_t* keys = in_a ? ka : kb;
   uint32_t* perm = in_a ? va : vb;
   // the other key buffer is free now: the build's scratch
   int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
   int32_t* right = other + n;
-  launch_scatter(pts, inv, n, at<float4>(c, L.leaf), at<int32_t>(c, L.parent),
+  launch_gather(pts, perm, n, at<float4>(c, L.leaf), at<int32_t>(c, L.parent),
                 at<int32_t>(c, L.minlab), at<uint8_t>(c, L.flag),
                 need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr,
                 at<int4>(c, L.pending), L.pending_entries, s);
-  mark(c, timing, PH_SCATTER, s);
+  mark(c, timing, PH_GATHER, s);
   int2* fixups = at<int2>(c, L.fixups);
-  uint32_t* nfix = at<uint32_t>(c, L.nfix);
+  uint32_t* fix_cnt = at<uint32_t>(c, L.fix_cnt);
   launch_build(keys, 64, at<float4>(c, L.leaf), n, at<Node>(c, L.nodes), right, other,
-               at<int32_t>(c, L.root), at<int4>(c, L.pending), fixups, nfix, status, s,
+               at<int32_t>(c, L.root), at<int4>(c, L.pending), fixups, fix_cnt, status, s,
                timing ? build_mark : nullptr, &sm);
   mark(c, timing, PH_BUILD_LEVELS, s);
-  launch_ropes(keys, 64, at<Node>(c, L.nodes), at<float4>(c, L.leaf), right, fixups, nfix, n,
+  launch_ropes(keys, 64, at<Node>(c, L.nodes), at<float4>(c, L.leaf), right, fixups, fix_cnt, n,
                status, s);
   mark(c, timing, PH_ROPES, s);
   out->keys = keys;
@@ -390,16 +387,15 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
   launch_cell_keys(pts, n, bounds, inv_h, ka, sc.hist, s);
   mark(c, timing, PH_MORTON, s);
   SortMarks sm{c, s};
-  uint32_t* inv = at<uint32_t>(c, L.parent);
   const bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, s,
-                                      timing ? sort_mark : nullptr, &sm, inv);
+                                      timing ? sort_mark : nullptr, &sm);
   const uint64_t* keys = in_a ? ka : kb;
   const uint32_t* perm = in_a ? va : vb;
   int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
   int32_t* right = other + n;
-  launch_scatter(pts, inv, n, spts, parent, minlab, flag, bestcore, at<int4>(c, L.pending),
-                 L.pending_entries, s);
-  mark(c, timing, PH_SCATTER, s);
+  launch_gather(pts, perm, n, spts, parent, minlab, flag, bestcore, at<int4>(c, L.pending),
+                L.pending_entries, s);
+  mark(c, timing, PH_GATHER, s);
 
   uint32_t* scan_ctr = at<uint32_t>(c, L.scan_ctr);
   uint32_t* ncells = at<uint32_t>(c, L.ncells);
@@ -433,11 +429,11 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
   Node* nodes = at<Node>(c, L.nodes);
   int32_t* root = at<int32_t>(c, L.root);
   int2* fixups = at<int2>(c, L.fixups);
-  uint32_t* nfix = at<uint32_t>(c, L.nfix);
+  uint32_t* fix_cnt = at<uint32_t>(c, L.fix_cnt);
   launch_build_boxes(pkey, prims, np, nodes, right, other, root, at<int4>(c, L.pending), fixups,
-                     nfix, status, s);
+                     fix_cnt, status, s);
   mark(c, timing, PH_BUILD_LEVELS, s);
-  launch_ropes_boxes(pkey, nodes, prims, right, fixups, nfix, np, status, s);
+  launch_ropes_boxes(pkey, nodes, prims, right, fixups, fix_cnt, np, status, s);
   mark(c, timing, PH_ROPES, s);
   if (core_mode)
     launch_count_db(nodes, prims, np, spts, n, cell_start, root, e2, min_pts, flag, status, block,
@@ -524,24 +520,23 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
   launch_set_morton(pts, d_off, num_sets, bits, set_shift, ka, sc.hist, d_root, status, s);
   mark(c, timing, PH_MORTON, s);
   SortMarks sm{c, s};
-  uint32_t* inv = reinterpret_cast<uint32_t*>(parent);
   const bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, s,
-                                      timing ? sort_mark : nullptr, &sm, inv);
+                                      timing ? sort_mark : nullptr, &sm);
   const uint64_t* keys = in_a ? ka : kb;
   const uint32_t* perm = in_a ? va : vb;
   int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
   int32_t* right = other + n;
-  launch_scatter(pts, inv, n, leaf, parent, minlab, flag, bestcore, at<int4>(c, L.pending),
-                 L.pending_entries, s);
-  mark(c, timing, PH_SCATTER, s);
+  launch_gather(pts, perm, n, leaf, parent, minlab, flag, bestcore, at<int4>(c, L.pending),
+                L.pending_entries, s);
+  mark(c, timing, PH_GATHER, s);
   mark(c, timing, PH_CELLS, s);
   Node* nodes = at<Node>(c, L.nodes);
   int2* fixups = at<int2>(c, L.fixups);
-  uint32_t* nfix = at<uint32_t>(c, L.nfix);
+  uint32_t* fix_cnt = at<uint32_t>(c, L.fix_cnt);
   launch_build(keys, set_shift, leaf, n, nodes, right, other, d_root, at<int4>(c, L.pending),
-               fixups, nfix, status, s, timing ? build_mark : nullptr, &sm);
+               fixups, fix_cnt, status, s, timing ? build_mark : nullptr, &sm);
   mark(c, timing, PH_BUILD_LEVELS, s);
-  launch_ropes(keys, set_shift, nodes, leaf, right, fixups, nfix, n, status, s);
+  launch_ropes(keys, set_shift, nodes, leaf, right, fixups, fix_cnt, n, status, s);
   mark(c, timing, PH_ROPES, s);
   if (any_core)
     launch_count_sets(nodes, leaf, n, keys, set_shift, d_root, d_e2, d_mp, flag, status, block, s);
@@ -847,10 +842,19 @@ int dbscan_core_flags(dbscan_ctx* c, const float* points, int64_t n, float eps, 
 
 int dbscan_pair_count(dbscan_ctx* c, const float* points, int64_t n, float eps, int64_t* count,
                       void* stream) {
+  int64_t st3[3];
+  int st = dbscan_traversal_stats(c, points, n, eps, st3, stream);
+  if (st == DBSCAN_OK && count) *count = st3[0];
+  return st;
+}
+
+int dbscan_traversal_stats(dbscan_ctx* c, const float* points, int64_t n, float eps,
+                           int64_t* out3, void* stream) {
+  int64_t* count = out3;
   if (!c) return fail(DBSCAN_EINVAL, "null context");
   int st = check_args(points, n, eps, 1, count);
   if (st != DBSCAN_OK) return st;
-  if (n == 0) { *count = 0; return DBSCAN_OK; }
+  if (n == 0) { count[0] = count[1] = count[2] = 0; return DBSCAN_OK; }
   DeviceGuard g(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index ix;
@@ -859,9 +863,10 @@ int dbscan_pair_count(dbscan_ctx* c, const float* points, int64_t n, float eps, 
   unsigned long long* dcount = at<unsigned long long>(c, ix.L.count);
   launch_pairs_count(ix.nodes, ix.leaf, uint32_t(n), eps * eps, dcount, ix.status, 256, s);
   unsigned long long* h = reinterpret_cast<unsigned long long*>(c->host_status + 2);
-  HIP_TRY(hipMemcpyAsync(h, dcount, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h, dcount, 24, hipMemcpyDeviceToHost, s));
   st = finish(c, ix.status, false, s);
-  if (st == DBSCAN_OK) *count = int64_t(*h);
+  if (st == DBSCAN_OK)
+    for (int k = 0; k < 3; ++k) count[k] = int64_t(h[k]);
   return st;
 }
 

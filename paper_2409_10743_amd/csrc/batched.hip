@@ -11,7 +11,7 @@
 // set's parameters and subtree root from its key's top bits.
 #include <algorithm>
 
-#include "pipeline.hpp"
+#include "walk.hpp"
 
 namespace dbx {
 
@@ -104,97 +104,93 @@ __global__ __launch_bounds__(256) void k_set_morton(const float* __restrict__ pt
     if (sh[t]) atomicAdd(&hist[t], sh[t]);
 }
 
-__device__ __forceinline__ Node load_node(const Node* __restrict__ nodes, int32_t k) {
-  const float4* p = reinterpret_cast<const float4*>(nodes + k);
-  const float4 a = p[0], b = p[1];
-  Node nd;
-  nd.lox = a.x; nd.loy = a.y; nd.loz = a.z; nd.left = __float_as_int(a.w);
-  nd.hix = b.x; nd.hiy = b.y; nd.hiz = b.z; nd.rope = __float_as_int(b.w);
-  return nd;
-}
-
-__device__ __forceinline__ bool bad_ref(int32_t node, uint32_t n, uint32_t& steps) {
-  if (++steps > 2 * n) return true;
-  return is_leaf(node) ? uint32_t(leaf_index(node)) >= n : uint32_t(node) >= n - 1;
-}
-
-__device__ __forceinline__ uint32_t query_index() {
-  return xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-}
-
 // Counting for the points of sets with minPts > 2, from their set's root.
+struct CountSets {
+  const uint64_t* keys;
+  int set_shift;
+  const int32_t* set_root;
+  const float* set_e2;
+  const int32_t* set_minpts;
+  uint8_t* flag;
+  float r2;
+  int32_t min_pts, cnt;
+  __device__ int32_t begin(uint32_t i, const float4&) {
+    const uint32_t set = uint32_t(keys[i] >> set_shift);
+    min_pts = set_minpts[set];
+    r2 = set_e2[set];
+    cnt = 0;
+    return min_pts > 2 ? set_root[set] : SENTINEL;
+  }
+  __device__ float e2() const { return r2; }
+  __device__ void visit(bool) {}
+  __device__ bool hit(uint32_t, int32_t, const float4&) { return ++cnt >= min_pts; }
+  __device__ void end(uint32_t i) {
+    if (min_pts > 2) flag[i] = cnt >= min_pts;  // minPts <= 2: the pair phase sets it
+  }
+};
+
 __global__ void k_count_sets(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
-                             uint32_t n, const uint64_t* __restrict__ keys, int set_shift,
-                             const int32_t* __restrict__ set_root,
+                             uint32_t n, uint32_t chunk, const uint64_t* __restrict__ keys,
+                             int set_shift, const int32_t* __restrict__ set_root,
                              const float* __restrict__ set_e2,
                              const int32_t* __restrict__ set_minpts,
                              uint8_t* __restrict__ flag, uint32_t* __restrict__ err) {
-  const uint32_t i = query_index();
-  if (i >= n) return;
-  const uint32_t set = uint32_t(keys[i] >> set_shift);
-  const int32_t min_pts = set_minpts[set];
-  if (min_pts <= 2) return;
-  const float e2 = set_e2[set];
-  const float4 q = leaf[i];
-  int32_t cnt = 0;
-  int32_t node = set_root[set];
-  uint32_t steps = 0;
-  while (node != SENTINEL) {
-    if (bad_ref(node, n, steps)) { atomicOr(err, STATUS_TREE); break; }
-    if (!is_leaf(node)) {
-      const Node nd = load_node(nodes, node);
-      node = box_sq_dist(q.x, q.y, q.z, nd) <= e2 ? nd.left : nd.rope;
-    } else {
-      const float4 p = leaf[leaf_index(node)];
-      if (sq_dist(q.x, q.y, q.z, p.x, p.y, p.z) <= e2 && ++cnt >= min_pts) break;
-      node = __float_as_int(p.w);
-    }
-  }
-  flag[i] = cnt >= min_pts;
+  CountSets v{keys, set_shift, set_root, set_e2, set_minpts, flag, 0.f, 0, 0};
+  wave_walks(nodes, leaf, n, chunk, v, err);
 }
 
 // Pair traversal; each lane runs the minPts <= 2 or the minPts > 2 rule of
 // its own set (both ends of a pair are always in the same set).
-__global__ void k_pairs_sets(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
-                             uint32_t n, const uint64_t* __restrict__ keys, int set_shift,
-                             const float* __restrict__ set_e2,
-                             const int32_t* __restrict__ set_minpts,
-                             const uint32_t* __restrict__ perm, int32_t* parent, uint8_t* flag,
-                             unsigned long long* bestcore, uint32_t* err) {
-  const uint32_t i = query_index();
-  if (i >= n) return;
-  const uint32_t set = uint32_t(keys[i] >> set_shift);
-  const float e2 = set_e2[set];
-  const bool core_mode = set_minpts[set] > 2;
-  const float4 q = leaf[i];
-  const bool ci = core_mode ? flag[i] != 0 : true;
-  bool found = false;
-  int32_t node = __float_as_int(q.w);
-  uint32_t steps = 0;
-  while (node != SENTINEL) {
-    if (bad_ref(node, n, steps)) { atomicOr(err, STATUS_TREE); break; }
-    if (!is_leaf(node)) {
-      const Node nd = load_node(nodes, node);
-      node = box_sq_dist(q.x, q.y, q.z, nd) <= e2 ? nd.left : nd.rope;
-      continue;
-    }
-    const int32_t j = leaf_index(node);
-    const float4 p = leaf[j];
-    node = __float_as_int(p.w);
-    if (sq_dist(q.x, q.y, q.z, p.x, p.y, p.z) > e2) continue;
+struct PairSets {
+  const uint64_t* keys;
+  int set_shift;
+  const float* set_e2;
+  const int32_t* set_minpts;
+  const uint32_t* perm;
+  int32_t* parent;
+  uint8_t* flag;
+  unsigned long long* bestcore;
+  float r2;
+  bool core_mode, ci, found;
+  __device__ int32_t begin(uint32_t i, const float4& q) {
+    const uint32_t set = uint32_t(keys[i] >> set_shift);
+    r2 = set_e2[set];
+    core_mode = set_minpts[set] > 2;
+    ci = core_mode ? flag[i] != 0 : true;
+    found = false;
+    return __float_as_int(q.w);
+  }
+  __device__ float e2() const { return r2; }
+  __device__ void visit(bool) {}
+  __device__ bool hit(uint32_t i, int32_t j, const float4&) {
     if (!core_mode) {
       found = true;
       uf_union(parent, int32_t(i), j);
       flag[j] = 1;
-      continue;
+      return false;
     }
     const bool cj = flag[j] != 0;
     if (ci && cj) uf_union(parent, int32_t(i), j);
     else if (ci) atomicMin(bestcore + j, (static_cast<unsigned long long>(perm[i]) << 32) | i);
     else if (cj)
       atomicMin(bestcore + i, (static_cast<unsigned long long>(perm[j]) << 32) | uint32_t(j));
+    return false;
   }
-  if (!core_mode && found) flag[i] = 1;
+  __device__ void end(uint32_t i) {
+    if (!core_mode && found) flag[i] = 1;
+  }
+};
+
+__global__ void k_pairs_sets(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
+                             uint32_t n, uint32_t chunk, const uint64_t* __restrict__ keys,
+                             int set_shift,
+                             const float* __restrict__ set_e2,
+                             const int32_t* __restrict__ set_minpts,
+                             const uint32_t* __restrict__ perm, int32_t* parent, uint8_t* flag,
+                             unsigned long long* bestcore, uint32_t* err) {
+  PairSets v{keys, set_shift, set_e2, set_minpts, perm, parent, flag, bestcore,
+             0.f, false, true, false};
+  wave_walks(nodes, leaf, n, chunk, v, err);
 }
 
 // Find without compression (the forest no longer changes).
@@ -253,8 +249,8 @@ void launch_count_sets(const Node* nodes, const float4* leaf, uint32_t n, const 
                        const int32_t* set_minpts, uint8_t* flag, uint32_t* err, int block,
                        hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_count_sets, dim3((n + block - 1) / block), dim3(block), 0, s, nodes, leaf,
-                     n, keys, set_shift, set_root, set_e2, set_minpts, flag, err);
+  hipLaunchKernelGGL(k_count_sets, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
+                     n, walk_chunk_size(), keys, set_shift, set_root, set_e2, set_minpts, flag, err);
 }
 
 void launch_pairs_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
@@ -262,8 +258,8 @@ void launch_pairs_sets(const Node* nodes, const float4* leaf, uint32_t n, const 
                        const uint32_t* perm, int32_t* parent, uint8_t* flag,
                        unsigned long long* bestcore, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_pairs_sets, dim3((n + block - 1) / block), dim3(block), 0, s, nodes, leaf,
-                     n, keys, set_shift, set_e2, set_minpts, perm, parent, flag, bestcore, err);
+  hipLaunchKernelGGL(k_pairs_sets, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
+                     n, walk_chunk_size(), keys, set_shift, set_e2, set_minpts, perm, parent, flag, bestcore, err);
 }
 
 void launch_final_sets(uint32_t n, const uint64_t* keys, int set_shift, const int32_t* set_minpts,

@@ -96,10 +96,28 @@ __device__ __forceinline__ uint64_t delta(const uint64_t* __restrict__ keys, int
 // One climb step at interior parent `par` of the node `node` = [l, r]:
 // link it, exchange, and, for the second arrival, finish the parent.
 // Returns false when the climb stops here (first arrival, or a bad tree).
+// Fix-up list: each level-1 frame owns FIX_PER_FRAME entries and a count.
+// An internal node p goes into the region of the frame holding leaf p; a
+// frame holds at most 256 leaves and 256 splits, so its region never
+// overflows for a well-formed tree.  Nodes finished above level 1 take a
+// slot with an atomic on their frame's count: these atomics are spread over
+// all frames, never one shared counter.
+struct FixList {
+  int2* entries;
+  uint32_t* cnt;
+  uint32_t* err;
+  __device__ void push(int32_t p, int2 e) const {
+    const uint32_t f = uint32_t(p) / BUILD_LEAVES;
+    const uint32_t k = atomicAdd(cnt + f, 1u);
+    if (k < FIX_PER_FRAME) entries[size_t(f) * FIX_PER_FRAME + k] = e;
+    else atomicOr(err, STATUS_TREE);
+  }
+};
+
 template <class Leaves>
 __device__ __forceinline__ bool climb_step(const Leaves& lv, Node* nodes,
-                                           int32_t* right, int32_t* other, int2* fixups,
-                                           uint32_t* nfix, uint32_t* err, const uint64_t* keys,
+                                           int32_t* right, int32_t* other, const FixList& fx,
+                                           uint32_t* err, const uint64_t* keys,
                                            int set_shift, int32_t* set_root,
                                            int32_t last, bool is_left, int32_t par,
                                            int32_t& node, int32_t& l, int32_t& r, float& lox,
@@ -129,7 +147,7 @@ __device__ __forceinline__ bool climb_step(const Leaves& lv, Node* nodes,
   Node& pn = nodes[par];
   pn.lox = lox; pn.loy = loy; pn.loz = loz;
   pn.hix = hix; pn.hiy = hiy; pn.hiz = hiz;
-  fixups[atomicAdd(nfix, 1u)] = make_int2(par, r);  // rope set by k_ropes
+  fx.push(par, make_int2(par, r));  // rope set by k_ropes
   node = par;
   const uint64_t mask = set_mask_of(set_shift);
   if ((l == 0 || set_cut(keys, l - 1, mask)) && (r == last || set_cut(keys, r, mask)))
@@ -144,14 +162,15 @@ __device__ __forceinline__ bool climb_step(const Leaves& lv, Node* nodes,
 // state later levels need: the exchange slot of every split in the frame
 // (-1 for the frame's right edge), child references set so far, and the
 // range end of every finished node.
-// Appends one entry per lane with `want` set; all lanes of the wave call it.
-__device__ __forceinline__ void wave_append(int2* list, uint32_t* count, bool want, int2 e) {
+// Appends one entry per lane with `want` set to the frame's own list
+// (count in LDS); all lanes of the wave call it.
+__device__ __forceinline__ void wave_append(int2* list, uint32_t* lds_count, bool want, int2 e) {
   const uint64_t m = __ballot(want);
   if (m == 0) return;
   const int lane = threadIdx.x & 63;
   const int leader = __ffsll(static_cast<long long>(m)) - 1;
   uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(count, uint32_t(__popcll(m)));
+  if (lane == leader) base = atomicAdd(lds_count, uint32_t(__popcll(m)));
   base = __shfl(base, leader, 64);
   const uint64_t below = lane ? (m & (~0ull >> (64 - lane))) : 0ull;
   if (want) list[base + __popcll(below)] = e;
@@ -161,9 +180,10 @@ template <class Leaves>
 __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
     const uint64_t* __restrict__ keys, Leaves lv, uint32_t n, int set_shift,
     Node* __restrict__ nodes, int32_t* __restrict__ right, int32_t* __restrict__ other,
-    int32_t* __restrict__ set_root, int4* __restrict__ pend_out, int2* __restrict__ fixups,
-    uint32_t* __restrict__ nfix, uint32_t* __restrict__ err) {
+    int32_t* __restrict__ set_root, int4* __restrict__ pend_out, int2* __restrict__ fix_frame,
+    uint32_t* __restrict__ fix_cnt, uint32_t* __restrict__ err) {
   __shared__ uint64_t s_delta[BUILD_LEAVES + 1];  // boundary f0-1+j at j
+  __shared__ uint32_t s_fix_cnt;
   __shared__ float4 s_leaf[BUILD_LEAVES], s_leafhi[BUILD_LEAVES];
   __shared__ float4 s_lo[BUILD_LEAVES], s_hi[BUILD_LEAVES];
   __shared__ int32_t s_other[BUILD_LEAVES], s_left[BUILD_LEAVES], s_right[BUILD_LEAVES],
@@ -186,6 +206,7 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
   s_left[t] = SENTINEL;
   s_right[t] = SENTINEL;
   s_end[t] = -1;
+  if (t == 0) s_fix_cnt = 0;
   __syncthreads();
   // does [l, r] span a whole set? (l - 1 and r are set ends; both in frame)
   auto spans = [&](int32_t l, int32_t r) { return s_cut[l - f0] && s_cut[r - f0 + 1]; };
@@ -264,8 +285,11 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
       }
     }
   }
-  wave_append(fixups, nfix, fix_leaf, make_int2(leaf_ref(p), p));
-  wave_append(fixups, nfix, fix_node, make_int2(p, node_end));
+  int2* mine = fix_frame + size_t(blockIdx.x) * FIX_PER_FRAME;
+  wave_append(mine, &s_fix_cnt, fix_leaf, make_int2(leaf_ref(p), p));
+  wave_append(mine, &s_fix_cnt, fix_node, make_int2(p, node_end));
+  __syncthreads();
+  if (t == 0) fix_cnt[blockIdx.x] = s_fix_cnt;  // later levels add to it
 }
 
 // Levels k > 1 of the build: thread = one of the 2 * 128 nodes handed up by
@@ -276,8 +300,9 @@ template <class Leaves>
 __global__ __launch_bounds__(BUILD_BLOCK) void k_build_level(
     const uint64_t* __restrict__ keys, Leaves lv, uint32_t n, int level, int set_shift,
     Node* nodes, int32_t* right, int32_t* other, int32_t* set_root,
-    const int4* __restrict__ pend_in, int4* __restrict__ pend_out, int2* fixups, uint32_t* nfix,
-    uint32_t* err) {
+    const int4* __restrict__ pend_in, int4* __restrict__ pend_out, int2* fix_frame,
+    uint32_t* fix_cnt, uint32_t* err) {
+  const FixList fx{fix_frame, fix_cnt, err};
   const int32_t last = int32_t(n) - 1;
   const uint64_t frame = uint64_t(BUILD_LEAVES) << (BUILD_FANOUT_LOG2 * (level - 1));
   const int64_t f0 = int64_t(blockIdx.x) * int64_t(frame);
@@ -307,32 +332,36 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_level(
       pend_out[size_t(blockIdx.x) * 2 + (is_left ? 1 : 0)] = make_int4(node, l, r, 0);
       return;
     }
-    if (!climb_step(lv, nodes, right, other, fixups, nfix, err, keys, set_shift, set_root, last,
+    if (!climb_step(lv, nodes, right, other, fx, err, keys, set_shift, set_root, last,
                     is_left, par, node, l, r, lox, loy, loz, hix, hiy, hiz))
       return;
     if (l == 0 && r == last) return;
   }
 }
 
+// One wave per level-1 frame: set the ropes of the frame's fix-up entries.
 template <class Leaves>
 __global__ __launch_bounds__(256) void k_ropes(Node* __restrict__ nodes, Leaves lv,
                                               const uint64_t* __restrict__ keys, int set_shift,
                                               const int32_t* __restrict__ right,
-                                              const int2* __restrict__ fixups,
-                                              const uint32_t* __restrict__ nfix, uint32_t n,
+                                              const int2* __restrict__ fix_frame,
+                                              const uint32_t* __restrict__ fix_cnt, uint32_t n,
                                               uint32_t* __restrict__ err) {
-  const uint32_t count = min(*nfix, 2 * n);
+  const uint32_t frames = (n + BUILD_LEAVES - 1) / BUILD_LEAVES;
+  const uint32_t f = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+  if (f >= frames) return;
+  const uint32_t count = min(fix_cnt[f], uint32_t(FIX_PER_FRAME));
+  const int2* list = fix_frame + size_t(f) * FIX_PER_FRAME;
   const int32_t last = int32_t(n) - 1;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < count;
-       k += gridDim.x * blockDim.x) {
-    const int2 e = fixups[k];
+  const uint64_t mask = set_mask_of(set_shift);
+  for (uint32_t k = threadIdx.x & 63; k < count; k += 64) {
+    const int2 e = list[k];
     int32_t r = e.y;
     if (r < 0 || r > last) {  // only if the build failed
       atomicOr(err, STATUS_TREE);
       r = last;
     }
-    const int32_t rope =
-        (r == last || set_cut(keys, r, set_mask_of(set_shift))) ? SENTINEL : right[r];
+    const int32_t rope = (r == last || set_cut(keys, r, mask)) ? SENTINEL : right[r];
     if (is_leaf(e.x)) lv.set_rope(leaf_index(e.x), rope);
     else nodes[e.x].rope = rope;
   }
@@ -367,7 +396,7 @@ namespace {
 template <class Leaves>
 void build_impl(const uint64_t* keys, int set_shift, Leaves lv, uint32_t n, Node* nodes,
                 int32_t* right, int32_t* other, int32_t* root, int4* pending, int2* fixups,
-                uint32_t* nfix, uint32_t* err, hipStream_t s, void (*after_level)(void*, int),
+                uint32_t* fix_cnt, uint32_t* err, hipStream_t s, void (*after_level)(void*, int),
                 void* arg) {
   if (n == 0) return;
   const int levels = build_levels(n);
@@ -378,11 +407,11 @@ void build_impl(const uint64_t* keys, int set_shift, Leaves lv, uint32_t n, Node
     const uint32_t frames = uint32_t((n + frame - 1) / frame);
     if (lv_i == 1)
       hipLaunchKernelGGL(k_build_frame<Leaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys, lv,
-                         n, set_shift, nodes, right, other, root, pout, fixups, nfix, err);
+                         n, set_shift, nodes, right, other, root, pout, fixups, fix_cnt, err);
     else
       hipLaunchKernelGGL(k_build_level<Leaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys, lv,
-                         n, lv_i, set_shift, nodes, right, other, root, pin, pout, fixups, nfix,
-                         err);
+                         n, lv_i, set_shift, nodes, right, other, root, pin, pout, fixups,
+                         fix_cnt, err);
     if (after_level) after_level(arg, lv_i);
     pin = pout;
     pout += level_region(frames);
@@ -392,40 +421,40 @@ void build_impl(const uint64_t* keys, int set_shift, Leaves lv, uint32_t n, Node
 
 template <class Leaves>
 void ropes_impl(Node* nodes, Leaves lv, const uint64_t* keys, int set_shift,
-                const int32_t* right, const int2* fixups, const uint32_t* nfix, uint32_t n,
+                const int32_t* right, const int2* fixups, const uint32_t* fix_cnt, uint32_t n,
                 uint32_t* err, hipStream_t s) {
   if (n < 2) return;
-  const uint32_t blocks = std::min<uint32_t>((2 * n + 255) / 256, 2048);
-  hipLaunchKernelGGL(k_ropes<Leaves>, dim3(blocks), dim3(256), 0, s, nodes, lv, keys, set_shift,
-                     right, fixups, nfix, n, err);
+  const uint32_t frames = (n + BUILD_LEAVES - 1) / BUILD_LEAVES;
+  hipLaunchKernelGGL(k_ropes<Leaves>, dim3((frames + 3) / 4), dim3(256), 0, s, nodes, lv, keys,
+                     set_shift, right, fixups, fix_cnt, n, err);
 }
 }  // namespace
 
 void launch_build(const uint64_t* keys, int set_shift, float4* leaf, uint32_t n, Node* nodes,
                   int32_t* right, int32_t* other, int32_t* set_root, int4* pending,
-                  int2* fixups, uint32_t* nfix, uint32_t* err, hipStream_t s,
+                  int2* fixups, uint32_t* fix_cnt, uint32_t* err, hipStream_t s,
                   void (*after_level)(void*, int), void* arg) {
   build_impl(keys, set_shift, PointLeaves{leaf}, n, nodes, right, other, set_root, pending,
-             fixups, nfix, err, s, after_level, arg);
+             fixups, fix_cnt, err, s, after_level, arg);
 }
 
 void launch_build_boxes(const uint64_t* keys, Node* prims, uint32_t n, Node* nodes,
                         int32_t* right, int32_t* other, int32_t* root, int4* pending,
-                        int2* fixups, uint32_t* nfix, uint32_t* err, hipStream_t s) {
-  build_impl(keys, 64, BoxLeaves{prims}, n, nodes, right, other, root, pending, fixups, nfix,
+                        int2* fixups, uint32_t* fix_cnt, uint32_t* err, hipStream_t s) {
+  build_impl(keys, 64, BoxLeaves{prims}, n, nodes, right, other, root, pending, fixups, fix_cnt,
              err, s, nullptr, nullptr);
 }
 
 void launch_ropes(const uint64_t* keys, int set_shift, Node* nodes, float4* leaf,
-                  const int32_t* right, const int2* fixups, const uint32_t* nfix, uint32_t n,
+                  const int32_t* right, const int2* fixups, const uint32_t* fix_cnt, uint32_t n,
                   uint32_t* err, hipStream_t s) {
-  ropes_impl(nodes, PointLeaves{leaf}, keys, set_shift, right, fixups, nfix, n, err, s);
+  ropes_impl(nodes, PointLeaves{leaf}, keys, set_shift, right, fixups, fix_cnt, n, err, s);
 }
 
 void launch_ropes_boxes(const uint64_t* keys, Node* nodes, Node* prims, const int32_t* right,
-                        const int2* fixups, const uint32_t* nfix, uint32_t n, uint32_t* err,
+                        const int2* fixups, const uint32_t* fix_cnt, uint32_t n, uint32_t* err,
                         hipStream_t s) {
-  ropes_impl(nodes, BoxLeaves{prims}, keys, 64, right, fixups, nfix, n, err, s);
+  ropes_impl(nodes, BoxLeaves{prims}, keys, 64, right, fixups, fix_cnt, n, err, s);
 }
 
 }  // namespace dbx

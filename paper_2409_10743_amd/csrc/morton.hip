@@ -1,8 +1,5 @@
 // Scene bounds, 64-bit Morton codes and the sorted leaf array.
-//
-// The leaves are written by scattering the points (read in input order) to
-// their sorted positions: on this GPU a random 16-byte write costs about a
-// 32-byte sector, a random 12-byte read a whole 128-byte line.
+
 //
 // Section 3.2: the scene bounding volume encloses all objects; LBVH orders
 // the objects along a Z-curve.  Section 4.2.2: 64-bit codes (21 bits per
@@ -37,19 +34,60 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
+__device__ __forceinline__ void take_axis(float* lo, float* hi, uint32_t axis, float v) {
+  // axis in {0, 1, 2}; selects instead of a dynamic register index
+  lo[0] = axis == 0 ? fminf(lo[0], v) : lo[0];
+  hi[0] = axis == 0 ? fmaxf(hi[0], v) : hi[0];
+  lo[1] = axis == 1 ? fminf(lo[1], v) : lo[1];
+  hi[1] = axis == 1 ? fmaxf(hi[1], v) : hi[1];
+  lo[2] = axis == 2 ? fminf(lo[2], v) : lo[2];
+  hi[2] = axis == 2 ? fmaxf(hi[2], v) : hi[2];
+}
+
+// Per-axis min/max of the n points and a non-finite flag.  With a 16-byte
+// aligned array the coordinates are read as float4s: the 4 values of float4
+// number v are coordinates v, v+1, v+2, v (mod 3) of the flat x,y,z array,
+// since 4v = v (mod 3).
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ pts, uint32_t n,
                                                uint32_t* __restrict__ bounds,
                                                uint32_t* __restrict__ status) {
   float lo[3] = {INFINITY, INFINITY, INFINITY};
   float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   bool bad = false;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  const uint64_t gid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  if (VEC) {
+    const uint64_t total = 3ull * n, nv = total / 4;
+    const float4* p4 = reinterpret_cast<const float4*>(pts);
+    for (uint64_t v = gid; v < nv; v += stride) {
+      const float4 x = p4[v];
+      bad |= !(isfinite(x.x) && isfinite(x.y) && isfinite(x.z) && isfinite(x.w));
+      const uint32_t r = uint32_t(v % 3);
+      const float m = fminf(x.x, x.w), M = fmaxf(x.x, x.w);
+      // axis r: x.x and x.w; axis r+1: x.y; axis r+2: x.z
+      const float l0 = r == 0 ? m : (r == 1 ? x.z : x.y), h0 = r == 0 ? M : (r == 1 ? x.z : x.y);
+      const float l1 = r == 1 ? m : (r == 2 ? x.z : x.y), h1 = r == 1 ? M : (r == 2 ? x.z : x.y);
+      const float l2 = r == 2 ? m : (r == 0 ? x.z : x.y), h2 = r == 2 ? M : (r == 0 ? x.z : x.y);
+      lo[0] = fminf(lo[0], l0); hi[0] = fmaxf(hi[0], h0);
+      lo[1] = fminf(lo[1], l1); hi[1] = fmaxf(hi[1], h1);
+      lo[2] = fminf(lo[2], l2); hi[2] = fmaxf(hi[2], h2);
+    }
+    if (gid == 0)
+      for (uint64_t e = nv * 4; e < total; ++e) {
+        const float v = pts[e];
+        bad |= !isfinite(v);
+        take_axis(lo, hi, uint32_t(e % 3), v);
+      }
+  } else {
+    for (uint64_t i = gid; i < n; i += stride) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      float v = pts[size_t(3) * i + a];
-      bad |= !isfinite(v);
-      lo[a] = fminf(lo[a], v);
-      hi[a] = fmaxf(hi[a], v);
+      for (int a = 0; a < 3; ++a) {
+        float v = pts[3 * i + a];
+        bad |= !isfinite(v);
+        lo[a] = fminf(lo[a], v);
+        hi[a] = fmaxf(hi[a], v);
+      }
     }
   }
   __shared__ float s_lo[3][4], s_hi[3][4];
@@ -88,6 +126,21 @@ __device__ __forceinline__ uint32_t quantise(float p, float lo, float s) {
   return uint32_t(t);
 }
 
+__device__ __forceinline__ uint64_t morton_of(float x, float y, float z, const float* lo,
+                                              const float* s) {
+  return (spread3(quantise(x, lo[0], s[0])) << 2) | (spread3(quantise(y, lo[1], s[1])) << 1) |
+         spread3(quantise(z, lo[2], s[2]));
+}
+
+__device__ __forceinline__ void count_digits(uint32_t* sh, uint64_t code) {
+#pragma unroll
+  for (int q = 0; q < SORT_PASSES; ++q) atomicAdd(&sh[q * RADIX + ((code >> (8 * q)) & 0xff)], 1u);
+}
+
+// Codes of all points plus the digit counts of every sort pass.  With a
+// 16-byte aligned point array a thread codes 4 points from 3 float4 loads
+// and writes their keys as two 16-byte stores.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, uint32_t n,
                                                const uint32_t* __restrict__ bounds,
                                                uint64_t* __restrict__ keys,
@@ -102,33 +155,52 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
     s[a] = ext > 0.0f ? float(1u << MORTON_BITS) / ext : 0.0f;  // IEEE division
   }
   __syncthreads();
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  uint32_t first_scalar = 0;
+  if (VEC) {
+    const uint32_t groups = n / 4;
+    const float4* p4 = reinterpret_cast<const float4*>(pts);
+    ulonglong2* k2 = reinterpret_cast<ulonglong2*>(keys);
+    for (uint32_t g = gid; g < groups; g += stride) {
+      const float4 a = p4[3 * size_t(g)], b = p4[3 * size_t(g) + 1], c = p4[3 * size_t(g) + 2];
+      const uint64_t c0 = morton_of(a.x, a.y, a.z, lo, s);
+      const uint64_t c1 = morton_of(a.w, b.x, b.y, lo, s);
+      const uint64_t c2 = morton_of(b.z, b.w, c.x, lo, s);
+      const uint64_t c3 = morton_of(c.y, c.z, c.w, lo, s);
+      k2[2 * size_t(g)] = make_ulonglong2(c0, c1);
+      k2[2 * size_t(g) + 1] = make_ulonglong2(c2, c3);
+      count_digits(sh, c0);
+      count_digits(sh, c1);
+      count_digits(sh, c2);
+      count_digits(sh, c3);
+    }
+    first_scalar = groups * 4;
+  }
+  for (uint32_t i = first_scalar + gid; i < n; i += stride) {
     const float* p = pts + size_t(3) * i;
-    uint64_t code = (spread3(quantise(p[0], lo[0], s[0])) << 2) |
-                    (spread3(quantise(p[1], lo[1], s[1])) << 1) |
-                    spread3(quantise(p[2], lo[2], s[2]));
+    const uint64_t code = morton_of(p[0], p[1], p[2], lo, s);
     keys[i] = code;
-#pragma unroll
-    for (int q = 0; q < SORT_PASSES; ++q)
-      atomicAdd(&sh[q * RADIX + ((code >> (8 * q)) & 0xff)], 1u);
+    count_digits(sh, code);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < SORT_PASSES * RADIX; t += blockDim.x)
     if (sh[t]) atomicAdd(&hist[t], sh[t]);
 }
 
-__global__ __launch_bounds__(256) void k_scatter(
-    const float* __restrict__ pts, const uint32_t* inv, uint32_t n, float4* __restrict__ leaf,
-    int32_t* parent, int32_t* __restrict__ minlab, uint8_t* __restrict__ flag,
-    unsigned long long* __restrict__ bestcore, int4* __restrict__ pending,
-    uint32_t pending_entries) {
+__global__ __launch_bounds__(256) void k_gather(
+    const float* __restrict__ pts, const uint32_t* __restrict__ perm, uint32_t n,
+    float4* __restrict__ leaf, int32_t* __restrict__ parent, int32_t* __restrict__ minlab,
+    uint8_t* __restrict__ flag, unsigned long long* __restrict__ bestcore,
+    int4* __restrict__ pending, uint32_t pending_entries) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   for (uint32_t k = i; k < pending_entries; k += gridDim.x * blockDim.x)
     pending[k] = make_int4(SENTINEL, 0, 0, 0);
+  if (i == 0) leaf[n] = make_float4(0.f, 0.f, 0.f, __int_as_float(SENTINEL));  // padding
   if (i >= n) return;
-  const uint32_t s = inv[i];  // read before parent[i] (which may alias inv) is set
-  const float* p = pts + size_t(3) * i;
-  if (s < n) leaf[s] = make_float4(p[0], p[1], p[2], __int_as_float(SENTINEL));
+  const uint32_t o = min(perm[i], n - 1);  // a permutation unless the sort failed
+  const float* p = pts + size_t(3) * o;
+  leaf[i] = make_float4(p[0], p[1], p[2], __int_as_float(SENTINEL));
   parent[i] = int32_t(i);
   minlab[i] = 0x7fffffff;
   flag[i] = 0;
@@ -147,22 +219,32 @@ void launch_prep(uint32_t* zero_region, size_t zero_words, uint32_t* bounds, hip
 void launch_bounds(const float* pts, uint32_t n, uint32_t* bounds, uint32_t* status,
                    hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_bounds, dim3(stream_blocks(n)), dim3(256), 0, s, pts, n, bounds, status);
+  if (reinterpret_cast<uintptr_t>(pts) % 16 == 0)
+    hipLaunchKernelGGL(k_bounds<true>, dim3(stream_blocks(n)), dim3(256), 0, s, pts, n, bounds,
+                       status);
+  else
+    hipLaunchKernelGGL(k_bounds<false>, dim3(stream_blocks(n)), dim3(256), 0, s, pts, n, bounds,
+                       status);
 }
 
 void launch_morton(const float* pts, uint32_t n, const uint32_t* bounds, uint64_t* keys,
                    uint32_t* hist, hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_morton, dim3(stream_blocks(n)), dim3(256), 0, s, pts, n, bounds, keys,
-                     hist);
+  // keys come from the arena (256-byte aligned); the points may not be
+  if (reinterpret_cast<uintptr_t>(pts) % 16 == 0 && reinterpret_cast<uintptr_t>(keys) % 16 == 0)
+    hipLaunchKernelGGL(k_morton<true>, dim3(stream_blocks(n)), dim3(256), 0, s, pts, n, bounds,
+                       keys, hist);
+  else
+    hipLaunchKernelGGL(k_morton<false>, dim3(stream_blocks(n)), dim3(256), 0, s, pts, n, bounds,
+                       keys, hist);
 }
 
-void launch_scatter(const float* pts, const uint32_t* inv, uint32_t n, float4* leaf,
-                    int32_t* parent, int32_t* minlab, uint8_t* flag,
-                    unsigned long long* bestcore, int4* pending, uint32_t pending_entries,
-                    hipStream_t s) {
+void launch_gather(const float* pts, const uint32_t* perm, uint32_t n, float4* leaf,
+                   int32_t* parent, int32_t* minlab, uint8_t* flag,
+                   unsigned long long* bestcore, int4* pending, uint32_t pending_entries,
+                   hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, pts, inv, n, leaf,
+  hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, s, pts, perm, n, leaf,
                      parent, minlab, flag, bestcore, pending, pending_entries);
 }
 

@@ -50,14 +50,11 @@ void launch_digit_histogram(const uint64_t* keys, uint32_t n, uint32_t* hist,
 // alternate between the A and B buffers, starting from A.  If `iota_vals`,
 // the input values are taken to be 0..n-1 and `va` is not read.  Returns
 // true when the result ends in the A buffers.
-// `after_pass(arg, p)`, if given, is called after pass p is enqueued.  If
-// `inv` is given, the last pass also writes inv[v] = final position of v
-// (for values that are a permutation of 0..n-1).
+// `after_pass(arg, p)`, if given, is called after pass p is enqueued.
 bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
                        uint32_t n, int first_pass, bool iota_vals,
                        const SortScratch& sc, hipStream_t s,
-                       void (*after_pass)(void*, int) = nullptr, void* arg = nullptr,
-                       uint32_t* inv = nullptr);
+                       void (*after_pass)(void*, int) = nullptr, void* arg = nullptr);
 
 // ---- bounds, Morton codes, leaf scatter (morton.hip) -----------------------
 // bounds[0..2] lo (ordered-int encoding), bounds[3..5] hi
@@ -67,46 +64,50 @@ void launch_bounds(const float* pts, uint32_t n, uint32_t* bounds,
                    uint32_t* status, hipStream_t s);
 void launch_morton(const float* pts, uint32_t n, const uint32_t* bounds,
                    uint64_t* keys, uint32_t* hist, hipStream_t s);
-// Points to sorted leaves, leaf[inv[o]] = point o (rope unset), reading the
-// points in input order; also initialises the per-point state and fills the
-// build's hand-over entries with -1.  `inv` may alias `parent`: each thread
-// reads inv[o] before writing parent[o].
-void launch_scatter(const float* pts, const uint32_t* inv, uint32_t n,
-                    float4* leaf, int32_t* parent, int32_t* minlab,
-                    uint8_t* flag, unsigned long long* bestcore,
-                    int4* pending, uint32_t pending_entries, hipStream_t s);
+// Sorted leaves, leaf[i] = point perm[i] (rope unset), plus the padding
+// record leaf[n] (leaf holds n + 1 records); also initialises the
+// per-point state and fills the build's hand-over entries with -1.
+void launch_gather(const float* pts, const uint32_t* perm, uint32_t n,
+                   float4* leaf, int32_t* parent, int32_t* minlab,
+                   uint8_t* flag, unsigned long long* bestcore,
+                   int4* pending, uint32_t pending_entries, hipStream_t s);
 
 // ---- LBVH (lbvh.hip) --------------------------------------------------------
 constexpr int BUILD_LEAVES = 256;        // leaves per level-1 frame
 constexpr int BUILD_FANOUT_LOG2 = 7;     // frames per next-level frame: 128
 constexpr int BUILD_BLOCK = 256;         // = BUILD_LEAVES = 2 << BUILD_FANOUT_LOG2
 static_assert(BUILD_BLOCK == BUILD_LEAVES && BUILD_BLOCK == (2 << BUILD_FANOUT_LOG2), "");
+constexpr int FIX_PER_FRAME = 2 * BUILD_LEAVES;  // fix-up entries per level-1 frame
 int build_levels(uint32_t n);
+inline uint32_t build_frames(uint32_t n) { return (n + BUILD_LEAVES - 1) / BUILD_LEAVES; }
+// int2 entries of the fix-up list (FIX_PER_FRAME per level-1 frame)
+inline size_t build_fix_entries(uint32_t n) { return size_t(build_frames(n)) * FIX_PER_FRAME; }
 // int4 entries of hand-over state the build needs (all levels), -1 filled
 size_t build_pending_entries(uint32_t n);
 // right[k]: right child of internal node k; other[k]: exchange slot (set
 // up by the build itself).  The build also sets every rope it can resolve
-// inside a level-1 frame; the others go on `fixups` (node reference, last
-// leaf under it; count in *nfix, zeroed before the build).
+// inside a level-1 frame; the others go on the fix-up list `fixups`
+// (build_fix_entries(n) entries: node reference, last leaf under it) with
+// one count per level-1 frame in fix_cnt[build_frames(n)] (set by the build).
 // Keys may carry a set id in bits [set_shift, 64) (batched sets; 64 = a
 // single set): ropes are then cut at set ends and set_root[s] receives the
 // root of set s's subtree (for a single set, set_root[0] = the root).
 // `after_level(arg, lv)`, if given, is called after level lv is enqueued.
 void launch_build(const uint64_t* keys, int set_shift, float4* leaf, uint32_t n, Node* nodes,
                   int32_t* right, int32_t* other, int32_t* set_root, int4* pending,
-                  int2* fixups, uint32_t* nfix, uint32_t* err, hipStream_t s,
+                  int2* fixups, uint32_t* fix_cnt, uint32_t* err, hipStream_t s,
                   void (*after_level)(void*, int) = nullptr, void* arg = nullptr);
 // Sets the ropes of the nodes on the fix-up list.
 void launch_ropes(const uint64_t* keys, int set_shift, Node* nodes, float4* leaf,
-                  const int32_t* right, const int2* fixups, const uint32_t* nfix, uint32_t n,
+                  const int32_t* right, const int2* fixups, const uint32_t* fix_cnt, uint32_t n,
                   uint32_t* err, hipStream_t s);
 // The same over box leaves (DenseBox primitives: Node records, payload in
 // `left`, rope in `rope`), single set.
 void launch_build_boxes(const uint64_t* keys, Node* prims, uint32_t n, Node* nodes,
                         int32_t* right, int32_t* other, int32_t* root, int4* pending,
-                        int2* fixups, uint32_t* nfix, uint32_t* err, hipStream_t s);
+                        int2* fixups, uint32_t* fix_cnt, uint32_t* err, hipStream_t s);
 void launch_ropes_boxes(const uint64_t* keys, Node* nodes, Node* prims, const int32_t* right,
-                        const int2* fixups, const uint32_t* nfix, uint32_t n, uint32_t* err,
+                        const int2* fixups, const uint32_t* fix_cnt, uint32_t n, uint32_t* err,
                         hipStream_t s);
 
 // ---- traversals (traverse.hip) ---------------------------------------------

@@ -58,22 +58,18 @@ __global__ __launch_bounds__(256) void k_digit_hist(const uint64_t* __restrict__
     if (sh[t]) atomicAdd(&hist[t], sh[t]);
 }
 
-// inv (optional, last pass only): inv[value] = the value's final position.
 template <bool IOTA, int ITEMS>
 __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
     const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout,
     const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout, uint32_t n,
     int shift, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
-    uint32_t* __restrict__ tile_ctr, uint32_t* __restrict__ err, uint32_t* __restrict__ inv) {
+    uint32_t* __restrict__ tile_ctr, uint32_t* __restrict__ err) {
   constexpr int TILE = SORT_THREADS * ITEMS;
-  __shared__ uint64_t s_buf[TILE];            // keys, then values, in digit order
-  // per-wave digit counts, then prefixes; once every key's position is
-  // known the same bytes hold the digit of the key at each position
+  __shared__ uint64_t s_keys[TILE];           // keys and values in digit order
+  __shared__ uint32_t s_vals[TILE];
+  // per-wave digit counts, then each wave's first slot per digit in the
+  // tile; after staging, row 0 holds the global offset minus the tile offset
   __shared__ uint32_t s_whist[WAVES][RADIX];
-  static_assert(sizeof(s_whist) >= TILE, "digit bytes alias the wave counters");
-  uint8_t* const s_dig = reinterpret_cast<uint8_t*>(&s_whist[0][0]);
-  __shared__ uint32_t s_base[RADIX];          // global offset - local offset
-  __shared__ uint32_t s_loff[RADIX];          // local (in-tile) digit offsets
   __shared__ uint32_t s_tmp[WAVES];
   __shared__ uint32_t s_tile;
 
@@ -86,6 +82,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
   const uint32_t wbase = tile_base + wave * (64 * ITEMS);
 
   uint64_t key[ITEMS];
+  uint32_t val[ITEMS];  // loaded with the keys, early: its latency hides behind the ranking
   uint32_t rank[ITEMS];
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
@@ -93,6 +90,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
   for (int k = 0; k < ITEMS; ++k) {
     uint32_t idx = wbase + k * 64 + lane;
     key[k] = idx < n ? kin[idx] : ~0ull;
+    val[k] = IOTA ? idx : (idx < n ? vin[idx] : 0u);
   }
 
   // rank each key among the keys of this wave with the same digit; the
@@ -153,47 +151,33 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
   // global digit start for this pass: exclusive scan of the digit counts
   uint32_t gstart = block_exclusive_scan(ghist[d], s_tmp);
   uint32_t loff = block_exclusive_scan(total, s_tmp);
-  s_loff[d] = loff;
-  s_base[d] = gstart + excl - loff;
+  for (int w = 0; w < WAVES; ++w) s_whist[w][d] += loff;
   __syncthreads();
 
-  // in-tile position of every key (rank[] becomes the position)
+  // stage keys and values in digit order, then write runs of equal digits
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
-    uint32_t dd = uint32_t(key[k] >> shift) & 0xff;
-    rank[k] += s_loff[dd] + s_whist[wave][dd];
-  }
-  __syncthreads();
-  // stage the keys in digit order
-#pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    uint32_t idx = wbase + k * 64 + lane;
+    const uint32_t idx = wbase + k * 64 + lane;
     if (idx < n) {
-      s_buf[rank[k]] = key[k];
-      s_dig[rank[k]] = uint8_t(key[k] >> shift);
+      const uint32_t dd = uint32_t(key[k] >> shift) & 0xff;
+      const uint32_t p = s_whist[wave][dd] + rank[k];
+      s_keys[p] = key[k];
+      s_vals[p] = val[k];
     }
   }
   __syncthreads();
+  // the per-wave slots are no longer needed: row 0 now holds the offsets
+  // (keeps LDS at 53 KB, three blocks per CU)
+  s_whist[0][d] = gstart + excl - loff;
+  __syncthreads();
+  const uint32_t* s_base = s_whist[0];
   const uint32_t tile_n = min(uint32_t(TILE), n - tile_base);
   for (uint32_t p = tid; p < tile_n; p += SORT_THREADS) {
-    uint32_t dst = s_base[s_dig[p]] + p;
-    if (dst < n) kout[dst] = s_buf[p];  // always true unless a wait was cut short
-  }
-  __syncthreads();
-  // then the values through the same buffer
-  uint32_t* s_val = reinterpret_cast<uint32_t*>(s_buf);
-#pragma unroll
-  for (int k = 0; k < ITEMS; ++k) {
-    uint32_t idx = wbase + k * 64 + lane;
-    if (idx < n) s_val[rank[k]] = IOTA ? idx : vin[idx];
-  }
-  __syncthreads();
-  for (uint32_t p = tid; p < tile_n; p += SORT_THREADS) {
-    uint32_t dst = s_base[s_dig[p]] + p;
-    if (dst < n) {
-      const uint32_t v = s_val[p];
-      vout[dst] = v;
-      if (inv && v < n) inv[v] = dst;
+    const uint64_t kk = s_keys[p];
+    const uint32_t dst = s_base[uint32_t(kk >> shift) & 0xff] + p;
+    if (dst < n) {  // always true unless a look-back wait was cut short
+      kout[dst] = kk;
+      vout[dst] = s_vals[p];
     }
   }
 }
@@ -220,23 +204,23 @@ namespace {
 template <int ITEMS>
 void sort_pass(bool iota, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
                uint32_t* vout, uint32_t n, int p, const SortScratch& sc, uint32_t* st,
-               uint32_t* inv, hipStream_t s) {
+               hipStream_t s) {
   const uint32_t tiles = sort_tiles(n, ITEMS);
   if (iota)
     hipLaunchKernelGGL((k_onesweep<true, ITEMS>), dim3(tiles), dim3(SORT_THREADS), 0, s, kin,
                        kout, vin, vout, n, 8 * p, sc.hist + p * RADIX, st, sc.tile_ctr + p,
-                       sc.err, inv);
+                       sc.err);
   else
     hipLaunchKernelGGL((k_onesweep<false, ITEMS>), dim3(tiles), dim3(SORT_THREADS), 0, s, kin,
                        kout, vin, vout, n, 8 * p, sc.hist + p * RADIX, st, sc.tile_ctr + p,
-                       sc.err, inv);
+                       sc.err);
 }
 }  // namespace
 
 bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
                        uint32_t n, int first_pass, bool iota_vals,
                        const SortScratch& sc, hipStream_t s,
-                       void (*after_pass)(void*, int), void* arg, uint32_t* inv) {
+                       void (*after_pass)(void*, int), void* arg) {
   bool in_a = true;
   if (n == 0) return true;
   const int items = sort_items();
@@ -248,10 +232,9 @@ bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
     uint32_t* vout = in_a ? vb : va;
     uint32_t* st = sc.status + size_t(p) * words;
     const bool iota = p == first_pass && iota_vals;
-    uint32_t* pinv = p == SORT_PASSES - 1 ? inv : nullptr;
-    if (items == 8) sort_pass<8>(iota, kin, kout, vin, vout, n, p, sc, st, pinv, s);
-    else if (items == 12) sort_pass<12>(iota, kin, kout, vin, vout, n, p, sc, st, pinv, s);
-    else sort_pass<16>(iota, kin, kout, vin, vout, n, p, sc, st, pinv, s);
+    if (items == 8) sort_pass<8>(iota, kin, kout, vin, vout, n, p, sc, st, s);
+    else if (items == 12) sort_pass<12>(iota, kin, kout, vin, vout, n, p, sc, st, s);
+    else sort_pass<16>(iota, kin, kout, vin, vout, n, p, sc, st, s);
     if (after_pass) after_pass(arg, p);
     in_a = !in_a;
   }

@@ -1,0 +1,127 @@
+// The stackless rope walk shared by every point traversal (sections 4.1,
+// 4.2): at an internal node whose box is within eps of the query go to its
+// left child, otherwise follow its rope; at a leaf test the point, then
+// follow the leaf's rope; stop at the sentinel.
+//
+// One wave runs the walks of a chunk of consecutive (Morton-ordered)
+// queries.  A lane whose walk ends takes the chunk's next query at once, so
+// the wave does not idle until its longest walk of 64 is over.  Internal
+// nodes and leaves go through the same step: a leaf is read as the box
+// [p, p] (same load, same test; the box bound of a point box is exactly the
+// point's squared distance), so the lanes of a wave never split into a leaf
+// path and a node path, each paying its own memory latency.
+//
+// The visitor V holds the per-lane state of the lane's current query:
+//   int32_t begin(uint32_t i, const float4& q)  first node of query i
+//   float   e2() const                          squared radius (this query)
+//   void    visit(bool leaf)                    every step (statistics)
+//   bool    hit(uint32_t i, int32_t j, const float4& q)
+//                                               leaf j within eps; true ends
+//                                               the walk early
+//   void    end(uint32_t i)                     the walk of query i is over
+#pragma once
+
+#include "pipeline.hpp"
+
+namespace dbx {
+
+// Queries of one wave's chunk: 64 x walk_queries_per_lane(), which is 1
+// unless the environment variable DBX_WALK_QPL (1, 2, 4 or 8) overrides it
+// for tuning runs.  More per lane keeps lanes busier but spreads the queries
+// in flight over a longer stretch of the tree, which costs L2 hits.
+uint32_t walk_queries_per_lane();
+inline uint32_t walk_chunk_size() { return 64u * walk_queries_per_lane(); }
+
+inline uint32_t walk_grid(uint32_t n, int block) {
+  const uint32_t chunk = walk_chunk_size();
+  const uint64_t waves = (uint64_t(n) + chunk - 1) / chunk;
+  const uint32_t per_block = uint32_t(block) / 64;
+  return uint32_t((waves + per_block - 1) / per_block);
+}
+
+// Box bound of `q` against the box [a.xyz, b.xyz]: the same arithmetic as
+// box_sq_dist (no FMA, ((x + y) + z)).
+__device__ __forceinline__ float box_sq_dist4(const float4& q, const float4& a, const float4& b) {
+#pragma clang fp contract(off)
+  const float gx = fmaxf(fmaxf(a.x - q.x, q.x - b.x), 0.0f);
+  const float gy = fmaxf(fmaxf(a.y - q.y, q.y - b.y), 0.0f);
+  const float gz = fmaxf(fmaxf(a.z - q.z, q.z - b.z), 0.0f);
+  const float xx = gx * gx;
+  const float yy = gy * gy;
+  const float zz = gz * gz;
+  const float s = xx + yy;
+  return s + zz;
+}
+
+// Chunk of this wave: [c0, c1).  The grid is walk_grid(n, blockDim.x)
+// blocks; blocks are dealt to XCDs so each XCD walks one contiguous
+// stretch of queries (nearby queries share tree nodes in its L2).
+__device__ __forceinline__ void walk_chunk(uint32_t n, uint32_t chunk, uint32_t& c0,
+                                           uint32_t& c1) {
+  const uint32_t wave = xcd_tile(blockIdx.x, gridDim.x) * (blockDim.x / 64) + threadIdx.x / 64;
+  const uint64_t b = uint64_t(wave) * chunk;
+  c0 = uint32_t(b < n ? b : n);
+  c1 = uint32_t(b + chunk < n ? b + chunk : n);
+}
+
+// `leaf` must have one readable float4 past leaf n-1 (a leaf step reads 32
+// bytes, like a node step, and ignores the second half).
+template <class V>
+__device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
+                                           const float4* __restrict__ leaf, uint32_t n,
+                                           uint32_t chunk, V& v, uint32_t* err) {
+  uint32_t c0, c1;
+  walk_chunk(n, chunk, c0, c1);
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  uint32_t head = c0;  // next unstarted query of the chunk (wave-uniform)
+  uint32_t i = 0;
+  bool have = false;   // lane holds query i whose end() is still due
+  int32_t node = SENTINEL;
+  uint32_t steps = 0;
+  float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (;;) {
+    const bool need = node == SENTINEL;
+    const uint64_t m = __ballot(need);
+    if (m != 0) {
+      if (need) {
+        if (have) { v.end(i); have = false; }
+        const uint32_t idx = head + uint32_t(__popcll(m & lt));
+        if (idx < c1) {
+          i = idx;
+          have = true;
+          q = leaf[i];
+          node = v.begin(i, q);
+          steps = 0;
+        }
+      }
+      const uint32_t h = head + uint32_t(__popcll(m));
+      head = h < c1 ? h : c1;
+    }
+    const bool act = node != SENTINEL;
+    if (__ballot(act) == 0 && head >= c1) break;
+    if (!act) continue;
+    // a walk visits every node at most once: more than 2n steps, or a
+    // reference outside the arrays, means a malformed tree
+    const bool lf = is_leaf(node);
+    if (++steps > 2 * n ||
+        (lf ? uint32_t(leaf_index(node)) >= n : uint32_t(node) >= n - 1)) {
+      atomicOr(err, STATUS_TREE);
+      node = SENTINEL;
+      continue;
+    }
+    const float4* p = lf ? leaf + leaf_index(node) : reinterpret_cast<const float4*>(nodes + node);
+    const float4 a = p[0];
+    float4 b = p[1];
+    if (lf) b = a;
+    v.visit(lf);
+    const bool near = box_sq_dist4(q, a, b) <= v.e2();
+    // internal: left child (a.w) or rope (b.w); leaf: its rope (a.w = b.w)
+    int32_t next = (near && !lf) ? __float_as_int(a.w) : __float_as_int(b.w);
+    if (near && lf && v.hit(i, leaf_index(node), q)) next = SENTINEL;
+    node = next;
+  }
+  if (have) v.end(i);
+}
+
+}  // namespace dbx

@@ -12,8 +12,8 @@ import paper_2409_10743_amd as dbx  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 F32 = np.float32
-CUBES = [((100, 100, 100), (116, 116, 116)), ((300, 40, 470), (316, 56, 486)),
-         ((0, 0, 0), (14, 14, 14))]
+CUBES = [((100, 100, 100), (124, 124, 124)), ((300, 40, 460), (324, 64, 484)),
+         ((0, 0, 0), (20, 20, 20))]
 
 
 @pytest.fixture(scope="module")
@@ -41,4 +41,4 @@ def test_halo134m(field, algo, mp):
     checked = 0
     for lo, hi in CUBES:
         checked += localcheck.check_cube(p, lab, lo, hi, F32(0.2), mp, margin=1.0)
-    assert checked > 10000
+    assert checked > 20000  # about 35,000 points lie in the trusted inner regions

@@ -57,6 +57,36 @@ def test_morton_codes_match_oracle(ctx, n):
     np.testing.assert_array_equal(got, oracle.morton63(p))
 
 
+@pytest.mark.parametrize("n", [1, 6, 4097, 50001])
+def test_unaligned_points(ctx, n):
+    """A point array that is not 16-byte aligned takes the scalar load path
+    of the bounds and Morton kernels: same codes, same labels."""
+    p = clumpy(n, 77 + n)
+    buf = torch.zeros((n + 1, 3), dtype=torch.float32, device="cuda")
+    buf[1:] = dev(p)
+    view = buf[1:]
+    assert view.data_ptr() % 16 != 0
+    got = ctx.morton_codes(view).cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(got, oracle.morton63(p))
+    lab = ctx.cluster(view, 0.02, 3).cpu().numpy()
+    np.testing.assert_array_equal(lab, oracle.dbscan(p, F32(0.02), 3))
+    buf[n, 2] = float("nan")  # last coordinate: the scalar tail
+    with pytest.raises(dbx.DbscanError):
+        ctx.cluster(view, 0.02, 3)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 7])
+def test_nonfinite_in_vector_tail(ctx, n):
+    """Every coordinate position of small arrays, which lie in the float4
+    part or the scalar tail of the bounds kernel, is checked."""
+    p = clumpy(n, 5)
+    for k in range(3 * n):
+        q = p.copy()
+        q.reshape(-1)[k] = np.inf
+        with pytest.raises(dbx.DbscanError):
+            ctx.cluster(dev(q), 0.02, 2)
+
+
 def test_morton_zero_extent_axis(ctx):
     p = clumpy(5000, 9)
     p[:, 1] = F32(3.5)
@@ -135,6 +165,18 @@ def test_tree_structure(ctx, n):
 def test_pair_traversal_finds_each_pair_once(ctx, n, eps):
     p = clumpy(n, 7 + n)
     assert ctx.pair_count(dev(p), eps) == oracle.pair_count(p, F32(eps))
+
+
+def test_traversal_stats_counts(ctx):
+    """The instrumented traversal finds the same pairs; every pair is one
+    leaf test that passed, and each query but the last visits at least one
+    node (its leaf's rope)."""
+    n, eps = 50001, 0.02
+    p = clumpy(n, 31)
+    st = ctx.traversal_stats(dev(p), eps)
+    assert st["pairs"] == oracle.pair_count(p, F32(eps))
+    assert st["leaf_tests"] >= st["pairs"]
+    assert st["internal_visits"] + st["leaf_tests"] >= n - 1
 
 
 @pytest.mark.parametrize("mp", [1, 2, 3, 5, 10, 50])
