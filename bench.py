@@ -61,8 +61,8 @@ BYTES_PER_POINT = {
     "cells": 0.0,                   # DenseBox only
     "count": 16 + 32 + 1,           # leaves, nodes, core flag
     "pairs": 16 + 32 + 4 + 4 + 1,   # leaves, nodes, parent read/write, member flag
-    "final_roots": 1 + 4 + 4 + 4 + 4,
-    "final_labels": 4 + 4 + 4 + 4,
+    "final_roots": 1 + 4 + 4 + 4 + 4,  # flag, parent, perm + minlab (clustered), root, label -1
+    "final_labels": 4.0,            # root; + perm, minlab, label for clustered points only
 }
 # the first sort pass reads no values (they are the identity)
 FIRST_SORT_PASS_BYTES = 20.0
@@ -74,8 +74,9 @@ KERNEL_NAME = {  # device function names, as rocprofv3 reports them
     "morton": "k_morton", "bounds": "k_bounds", "ropes": "k_ropes", "count": "k_count",
     "final_roots": "k_final_roots", "final_labels": "k_final_labels", "prep": "k_prep",
 }
-KERNEL_SOURCE = {
-    "sort": "radix_sort.hip", "pairs": "traverse.hip", "count": "traverse.hip",
+KERNEL_SOURCE = {  # files whose text decides the kernel's code (plus common.hpp)
+    "sort": "radix_sort.hip", "pairs": ("traverse.hip", "walk.hpp"),
+    "count": ("traverse.hip", "walk.hpp"),
     "build_frame": "lbvh.hip", "build_levels": "lbvh.hip", "ropes": "lbvh.hip",
     "cells": "densebox.hip",
     "gather": "morton.hip", "morton": "morton.hip",
@@ -90,10 +91,11 @@ def log(*a):
 
 
 def source_sha(kernel: str) -> str:
-    src = os.path.join(ROOT, "paper_2409_10743_amd", "csrc", KERNEL_SOURCE[kernel])
+    srcs = KERNEL_SOURCE[kernel]
+    srcs = (srcs,) if isinstance(srcs, str) else srcs
     h = hashlib.sha256()
-    for f in (src, os.path.join(ROOT, "paper_2409_10743_amd", "csrc", "common.hpp")):
-        h.update(open(f, "rb").read())
+    for f in (*srcs, "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2409_10743_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -228,6 +230,7 @@ def main():
     ts = ctx.traversal_stats(d, float(eps))
     out["traversal"] = {k: v for k, v in ts.items()}
     out["traversal"].update({"internal_visits_per_point": round(ts["internal_visits"] / n, 2),
+                             "descents_per_point": round(ts["descents"] / n, 2),
                              "leaf_tests_per_point": round(ts["leaf_tests"] / n, 2)})
 
     if not args.no_cpu_baseline:

@@ -216,10 +216,11 @@ int dbscan_core_flags(dbscan_ctx* ctx, const float* points, int64_t n, float eps
  * count: host pointer. */
 int dbscan_pair_count(dbscan_ctx* ctx, const float* points, int64_t n, float eps,
                       int64_t* count, void* stream);
-/* The same traversal with counters: out3[0] pairs, out3[1] internal-node
- * visits, out3[2] leaf tests, summed over all queries (host int64[3]). */
+/* The same traversal with counters, summed over all queries (host int64[4]):
+ * out4[0] pairs, out4[1] internal-node visits, out4[2] of those whose box
+ * was within eps (the walk descended), out4[3] leaf tests. */
 int dbscan_traversal_stats(dbscan_ctx* ctx, const float* points, int64_t n, float eps,
-                           int64_t* out3, void* stream);
+                           int64_t* out4, void* stream);
 
 /* ---- diagnostics ------------------------------------------------------------ */
 const char* dbscan_strerror(int status);

@@ -292,11 +292,12 @@ class Context:
 
     def traversal_stats(self, points, eps: float) -> dict:
         p = _points(points)
-        out = (ctypes.c_int64 * 3)()
+        out = (ctypes.c_int64 * 4)()
         _check(load_library().dbscan_traversal_stats(
             self.handle, ctypes.c_void_p(p.data_ptr()), p.shape[0], ctypes.c_float(eps), out,
             _stream(p.device)))
-        return {"pairs": out[0], "internal_visits": out[1], "leaf_tests": out[2]}
+        return {"pairs": out[0], "internal_visits": out[1], "descents": out[2],
+                "leaf_tests": out[3]}
 
     def pair_count(self, points, eps: float) -> int:
         p = _points(points)

@@ -107,7 +107,7 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
   L.hist = take(SORT_PASSES * RADIX * 4);
   L.tile_ctr = take(SORT_PASSES * 4);
   L.status = take(4);
-  L.count = take(3 * 8);  // pairs, internal-node visits, leaf tests
+  L.count = take(4 * 8);  // pairs, internal-node visits, descents, leaf tests
   if (densebox) {
     L.scan_ctr = take(8);
     L.ncells = take(8);  // ncells and nprims side by side: read back together
@@ -339,7 +339,7 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
     launch_pairs_fof(ix.nodes, ix.leaf, n, e2, parent, flag, ix.status, block, s);
   mark(c, timing, PH_PAIRS, s);
   int32_t* minlab = at<int32_t>(c, L.minlab);
-  launch_final_roots(n, min_pts, flag, bestcore, ix.perm, parent, minlab, s);
+  launch_final_roots(n, min_pts, flag, bestcore, ix.perm, parent, minlab, labels, s);
   mark(c, timing, PH_FINAL_ROOTS, s);
   launch_final_labels(n, ix.perm, parent, minlab, labels, s);
   mark(c, timing, PH_FINAL_LABELS, s);
@@ -442,7 +442,7 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
   launch_pairs_db(nodes, prims, np, spts, n, cell_start, perm, cell_minorig, e2, core_mode,
                   parent, flag, bestcore, status, block, s);
   mark(c, timing, PH_PAIRS, s);
-  launch_final_roots(n, min_pts, flag, bestcore, perm, parent, minlab, s);
+  launch_final_roots(n, min_pts, flag, bestcore, perm, parent, minlab, labels, s);
   mark(c, timing, PH_FINAL_ROOTS, s);
   launch_final_labels(n, perm, parent, minlab, labels, s);
   mark(c, timing, PH_FINAL_LABELS, s);
@@ -842,19 +842,19 @@ int dbscan_core_flags(dbscan_ctx* c, const float* points, int64_t n, float eps, 
 
 int dbscan_pair_count(dbscan_ctx* c, const float* points, int64_t n, float eps, int64_t* count,
                       void* stream) {
-  int64_t st3[3];
-  int st = dbscan_traversal_stats(c, points, n, eps, st3, stream);
-  if (st == DBSCAN_OK && count) *count = st3[0];
+  int64_t st4[4];
+  int st = dbscan_traversal_stats(c, points, n, eps, st4, stream);
+  if (st == DBSCAN_OK && count) *count = st4[0];
   return st;
 }
 
 int dbscan_traversal_stats(dbscan_ctx* c, const float* points, int64_t n, float eps,
-                           int64_t* out3, void* stream) {
-  int64_t* count = out3;
+                           int64_t* out4, void* stream) {
+  int64_t* count = out4;
   if (!c) return fail(DBSCAN_EINVAL, "null context");
   int st = check_args(points, n, eps, 1, count);
   if (st != DBSCAN_OK) return st;
-  if (n == 0) { count[0] = count[1] = count[2] = 0; return DBSCAN_OK; }
+  if (n == 0) { count[0] = count[1] = count[2] = count[3] = 0; return DBSCAN_OK; }
   DeviceGuard g(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index ix;
@@ -863,10 +863,10 @@ int dbscan_traversal_stats(dbscan_ctx* c, const float* points, int64_t n, float 
   unsigned long long* dcount = at<unsigned long long>(c, ix.L.count);
   launch_pairs_count(ix.nodes, ix.leaf, uint32_t(n), eps * eps, dcount, ix.status, 256, s);
   unsigned long long* h = reinterpret_cast<unsigned long long*>(c->host_status + 2);
-  HIP_TRY(hipMemcpyAsync(h, dcount, 24, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h, dcount, 32, hipMemcpyDeviceToHost, s));
   st = finish(c, ix.status, false, s);
   if (st == DBSCAN_OK)
-    for (int k = 0; k < 3; ++k) count[k] = int64_t(h[k]);
+    for (int k = 0; k < 4; ++k) count[k] = int64_t(h[k]);
   return st;
 }
 

@@ -122,7 +122,7 @@ struct CountSets {
     return min_pts > 2 ? set_root[set] : SENTINEL;
   }
   __device__ float e2() const { return r2; }
-  __device__ void visit(bool) {}
+  __device__ void visit(bool, bool) {}
   __device__ bool hit(uint32_t, int32_t, const float4&) { return ++cnt >= min_pts; }
   __device__ void end(uint32_t i) {
     if (min_pts > 2) flag[i] = cnt >= min_pts;  // minPts <= 2: the pair phase sets it
@@ -130,13 +130,14 @@ struct CountSets {
 };
 
 __global__ void k_count_sets(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
-                             uint32_t n, uint32_t chunk, const uint64_t* __restrict__ keys,
+                             uint32_t n, WalkCfg wc,
+                             const uint64_t* __restrict__ keys,
                              int set_shift, const int32_t* __restrict__ set_root,
                              const float* __restrict__ set_e2,
                              const int32_t* __restrict__ set_minpts,
                              uint8_t* __restrict__ flag, uint32_t* __restrict__ err) {
   CountSets v{keys, set_shift, set_root, set_e2, set_minpts, flag, 0.f, 0, 0};
-  wave_walks(nodes, leaf, n, chunk, v, err);
+  wave_walks(nodes, leaf, n, wc, v, err);
 }
 
 // Pair traversal; each lane runs the minPts <= 2 or the minPts > 2 rule of
@@ -161,7 +162,7 @@ struct PairSets {
     return __float_as_int(q.w);
   }
   __device__ float e2() const { return r2; }
-  __device__ void visit(bool) {}
+  __device__ void visit(bool, bool) {}
   __device__ bool hit(uint32_t i, int32_t j, const float4&) {
     if (!core_mode) {
       found = true;
@@ -182,7 +183,8 @@ struct PairSets {
 };
 
 __global__ void k_pairs_sets(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
-                             uint32_t n, uint32_t chunk, const uint64_t* __restrict__ keys,
+                             uint32_t n, WalkCfg wc,
+                             const uint64_t* __restrict__ keys,
                              int set_shift,
                              const float* __restrict__ set_e2,
                              const int32_t* __restrict__ set_minpts,
@@ -190,7 +192,7 @@ __global__ void k_pairs_sets(const Node* __restrict__ nodes, const float4* __res
                              unsigned long long* bestcore, uint32_t* err) {
   PairSets v{keys, set_shift, set_e2, set_minpts, perm, parent, flag, bestcore,
              0.f, false, true, false};
-  wave_walks(nodes, leaf, n, chunk, v, err);
+  wave_walks(nodes, leaf, n, wc, v, err);
 }
 
 // Find without compression (the forest no longer changes).
@@ -204,9 +206,10 @@ __global__ __launch_bounds__(256) void k_final_roots_sets(
     uint32_t n, const uint64_t* __restrict__ keys, int set_shift,
     const int32_t* __restrict__ set_minpts, const uint8_t* __restrict__ flag,
     const unsigned long long* __restrict__ bestcore, const uint32_t* __restrict__ perm,
-    int32_t* parent, int32_t* __restrict__ minlab) {
+    int32_t* parent, int32_t* __restrict__ minlab, int32_t* __restrict__ labels) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  labels[i] = -1;  // the second pass writes clustered points only
   const int32_t mp = set_minpts[uint32_t(keys[i] >> set_shift)];
   int32_t r;
   if (mp <= 2) {
@@ -229,9 +232,10 @@ __global__ __launch_bounds__(256) void k_final_labels_sets(
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int32_t r = root[i];
+  if (r < 0) return;  // noise: already -1
   const uint32_t o = perm[i];
   const int32_t base = int32_t(offsets[uint32_t(keys[i] >> set_shift)]);
-  if (o < n) labels[o] = r < 0 ? -1 : minlab[r] - base;
+  if (o < n) labels[o] = minlab[r] - base;
 }
 
 }  // namespace
@@ -250,7 +254,7 @@ void launch_count_sets(const Node* nodes, const float4* leaf, uint32_t n, const 
                        hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_count_sets, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     n, walk_chunk_size(), keys, set_shift, set_root, set_e2, set_minpts, flag, err);
+                     n, walk_cfg(), keys, set_shift, set_root, set_e2, set_minpts, flag, err);
 }
 
 void launch_pairs_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
@@ -259,7 +263,8 @@ void launch_pairs_sets(const Node* nodes, const float4* leaf, uint32_t n, const 
                        unsigned long long* bestcore, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs_sets, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     n, walk_chunk_size(), keys, set_shift, set_e2, set_minpts, perm, parent, flag, bestcore, err);
+                     n, walk_cfg(), keys, set_shift, set_e2, set_minpts, perm, parent, flag,
+                     bestcore, err);
 }
 
 void launch_final_sets(uint32_t n, const uint64_t* keys, int set_shift, const int32_t* set_minpts,
@@ -269,7 +274,7 @@ void launch_final_sets(uint32_t n, const uint64_t* keys, int set_shift, const in
   if (n == 0) return;
   const uint32_t g = (n + 255) / 256;
   hipLaunchKernelGGL(k_final_roots_sets, dim3(g), dim3(256), 0, s, n, keys, set_shift,
-                     set_minpts, flag, bestcore, perm, parent, minlab);
+                     set_minpts, flag, bestcore, perm, parent, minlab, labels);
   hipLaunchKernelGGL(k_final_labels_sets, dim3(g), dim3(256), 0, s, n, keys, set_shift, offsets,
                      perm, parent, minlab, labels);
 }

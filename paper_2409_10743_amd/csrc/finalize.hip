@@ -25,13 +25,18 @@ __device__ __forceinline__ int32_t root_of(const int32_t* parent, int32_t x) {
 // First pass: cluster root of every point (or -1), and the smallest input
 // index per root.  The root is written over parent[i]; that only shortens
 // other points' chains (a root is an ancestor), and noise points are
-// singletons nobody else's chain passes through.
+// singletons nobody else's chain passes through.  It also sets every label
+// to -1 (coalesced: input index i, whatever point sits at sorted position
+// i), so the second pass only writes the labels of clustered points: for
+// sparse fields most points are noise, and those scattered 4-byte writes
+// are the expensive part.
 __global__ __launch_bounds__(256) void k_final_roots(
     uint32_t n, int32_t min_pts, const uint8_t* __restrict__ flag,
     const unsigned long long* __restrict__ bestcore, const uint32_t* __restrict__ perm,
-    int32_t* parent, int32_t* __restrict__ minlab) {
+    int32_t* parent, int32_t* __restrict__ minlab, int32_t* __restrict__ labels) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  labels[i] = -1;
   int32_t r;
   if (min_pts <= 2) {
     r = (min_pts == 1 || flag[i]) ? root_of(parent, int32_t(i)) : -1;
@@ -52,8 +57,9 @@ __global__ __launch_bounds__(256) void k_final_labels(uint32_t n, const uint32_t
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int32_t r = root[i];
+  if (r < 0) return;  // noise: already -1
   const uint32_t o = perm[i];
-  if (o < n) labels[o] = r < 0 ? -1 : minlab[r];
+  if (o < n) labels[o] = minlab[r];
 }
 
 __global__ __launch_bounds__(256) void k_scatter_u8(const uint8_t* __restrict__ src,
@@ -73,10 +79,10 @@ void launch_scatter_u8(const uint8_t* src, const uint32_t* perm, uint32_t n, uin
 
 void launch_final_roots(uint32_t n, int32_t min_pts, const uint8_t* flag,
                         const unsigned long long* bestcore, const uint32_t* perm,
-                        int32_t* parent, int32_t* minlab, hipStream_t s) {
+                        int32_t* parent, int32_t* minlab, int32_t* labels, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_final_roots, dim3((n + 255) / 256), dim3(256), 0, s, n, min_pts, flag,
-                     bestcore, perm, parent, minlab);
+                     bestcore, perm, parent, minlab, labels);
 }
 
 void launch_final_labels(uint32_t n, const uint32_t* perm, const int32_t* root,

@@ -130,11 +130,12 @@ void launch_pairs_count(const Node* nodes, const float4* leaf, uint32_t n,
                         int block, hipStream_t s);
 
 // ---- labels (finalize.hip) --------------------------------------------------
-// 1) cluster root per point (written over parent; -1 = noise) and the
-//    smallest input index per root;  2) labels in input order.
+// 1) cluster root per point (written over parent; -1 = noise), the
+//    smallest input index per root, and every label set to -1;
+// 2) labels of the clustered points, in input order.
 void launch_final_roots(uint32_t n, int32_t min_pts, const uint8_t* flag,
                         const unsigned long long* bestcore, const uint32_t* perm,
-                        int32_t* parent, int32_t* minlab, hipStream_t s);
+                        int32_t* parent, int32_t* minlab, int32_t* labels, hipStream_t s);
 void launch_final_labels(uint32_t n, const uint32_t* perm, const int32_t* root,
                          const int32_t* minlab, int32_t* labels, hipStream_t s);
 // dst[perm[i]] = src[i]: from sorted order back to input order

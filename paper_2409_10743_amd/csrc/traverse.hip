@@ -27,16 +27,17 @@ struct CountCore {
   uint8_t* is_core;
   __device__ int32_t begin(uint32_t, const float4&) { cnt = 0; return root; }
   __device__ float e2() const { return r2; }
-  __device__ void visit(bool) {}
+  __device__ void visit(bool, bool) {}
   __device__ bool hit(uint32_t, int32_t, const float4&) { return ++cnt >= min_pts; }
   __device__ void end(uint32_t i) { is_core[i] = cnt >= min_pts; }
 };
 
 __global__ void k_count(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
-                        uint32_t n, uint32_t chunk, const int32_t* __restrict__ root, float e2,
-                        int32_t min_pts, uint8_t* __restrict__ is_core, uint32_t* err) {
+                        uint32_t n, WalkCfg wc,
+                        const int32_t* __restrict__ root, float e2, int32_t min_pts,
+                        uint8_t* __restrict__ is_core, uint32_t* err) {
   CountCore v{*root, min_pts, 0, e2, is_core};
-  wave_walks(nodes, leaf, n, chunk, v, err);
+  wave_walks(nodes, leaf, n, wc, v, err);
 }
 
 enum PairMode { FOF = 0, CORE = 1, COUNT = 2 };
@@ -51,15 +52,22 @@ struct PairVisit {
   uint8_t* member;
   unsigned long long* bestcore;
   bool ci, found;
-  unsigned long long pairs, visits, leaves;  // COUNT only
+  unsigned long long pairs, visits, descents, leaves;  // COUNT only
   __device__ int32_t begin(uint32_t i, const float4& q) {
     found = false;
     if (MODE == CORE) ci = is_core[i] != 0;
     return __float_as_int(q.w);
   }
   __device__ float e2() const { return r2; }
-  __device__ void visit(bool lf) {
-    if (MODE == COUNT) { if (lf) ++leaves; else ++visits; }
+  __device__ void visit(bool lf, bool near) {
+    if (MODE == COUNT) {
+      if (lf) {
+        ++leaves;
+      } else {
+        ++visits;
+        if (near) ++descents;
+      }
+    }
   }
   __device__ bool hit(uint32_t i, int32_t j, const float4&) {
     if (MODE == FOF) {
@@ -84,22 +92,17 @@ struct PairVisit {
 
 template <int MODE>
 __global__ void k_pairs(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
-                        uint32_t n, uint32_t chunk, float e2,
+                        uint32_t n, WalkCfg wc, float e2,
                         const uint8_t* __restrict__ is_core, const uint32_t* __restrict__ perm,
                         int32_t* parent, uint8_t* member, unsigned long long* bestcore,
                         unsigned long long* count, uint32_t* err) {
-  PairVisit<MODE> v{e2, is_core, perm, parent, member, bestcore, true, false, 0, 0, 0};
-  wave_walks(nodes, leaf, n, chunk, v, err);
-  if (MODE == COUNT) {  // count[0] pairs, count[1] internal visits, count[2] leaf tests
-    for (int o = 32; o > 0; o >>= 1) {
-      v.pairs += __shfl_xor(v.pairs, o, 64);
-      v.visits += __shfl_xor(v.visits, o, 64);
-      v.leaves += __shfl_xor(v.leaves, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-      if (v.pairs) atomicAdd(count, v.pairs);
-      if (v.visits) atomicAdd(count + 1, v.visits);
-      if (v.leaves) atomicAdd(count + 2, v.leaves);
+  PairVisit<MODE> v{e2, is_core, perm, parent, member, bestcore, true, false, 0, 0, 0, 0};
+  wave_walks(nodes, leaf, n, wc, v, err);
+  if (MODE == COUNT) {  // pairs, internal visits, descents, leaf tests
+    unsigned long long c[4] = {v.pairs, v.visits, v.descents, v.leaves};
+    for (int k = 0; k < 4; ++k) {
+      for (int o = 32; o > 0; o >>= 1) c[k] += __shfl_xor(c[k], o, 64);
+      if ((threadIdx.x & 63) == 0 && c[k]) atomicAdd(count + k, c[k]);
     }
   }
 }
@@ -109,10 +112,19 @@ __global__ void k_pairs(const Node* __restrict__ nodes, const float4* __restrict
 uint32_t walk_queries_per_lane() {
   static const uint32_t q = [] {
     const char* e = std::getenv("DBX_WALK_QPL");
-    const int v = e ? std::atoi(e) : 1;
-    return uint32_t((v == 1 || v == 2 || v == 4 || v == 8) ? v : 1);
+    const int v = e ? std::atoi(e) : 4;
+    return uint32_t((v == 1 || v == 2 || v == 4 || v == 8) ? v : 4);
   }();
   return q;
+}
+
+uint32_t walk_refill_at() {
+  static const uint32_t r = [] {
+    const char* e = std::getenv("DBX_WALK_REFILL");
+    const int v = e ? std::atoi(e) : 48;
+    return uint32_t(v >= 1 && v <= 64 ? v : 48);
+  }();
+  return r;
 }
 
 void launch_count(const Node* nodes, const float4* leaf, uint32_t n, const int32_t* root,
@@ -120,7 +132,7 @@ void launch_count(const Node* nodes, const float4* leaf, uint32_t n, const int32
                   hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_count, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf, n,
-                     walk_chunk_size(), root,
+                     walk_cfg(), root,
                      e2, min_pts, is_core, err);
 }
 
@@ -128,7 +140,7 @@ void launch_pairs_fof(const Node* nodes, const float4* leaf, uint32_t n, float e
                       int32_t* parent, uint8_t* member, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<FOF>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf, n,
-                     walk_chunk_size(), e2, nullptr, nullptr, parent, member, nullptr, nullptr, err);
+                     walk_cfg(), e2, nullptr, nullptr, parent, member, nullptr, nullptr, err);
 }
 
 void launch_pairs_core(const Node* nodes, const float4* leaf, uint32_t n, float e2,
@@ -136,14 +148,14 @@ void launch_pairs_core(const Node* nodes, const float4* leaf, uint32_t n, float 
                        unsigned long long* bestcore, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<CORE>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf, n,
-                     walk_chunk_size(), e2, is_core, perm, parent, nullptr, bestcore, nullptr, err);
+                     walk_cfg(), e2, is_core, perm, parent, nullptr, bestcore, nullptr, err);
 }
 
 void launch_pairs_count(const Node* nodes, const float4* leaf, uint32_t n, float e2,
                         unsigned long long* count, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<COUNT>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     n, walk_chunk_size(), e2, nullptr, nullptr, nullptr, nullptr, nullptr, count, err);
+                     n, walk_cfg(), e2, nullptr, nullptr, nullptr, nullptr, nullptr, count, err);
 }
 
 }  // namespace dbx

@@ -14,7 +14,7 @@
 // The visitor V holds the per-lane state of the lane's current query:
 //   int32_t begin(uint32_t i, const float4& q)  first node of query i
 //   float   e2() const                          squared radius (this query)
-//   void    visit(bool leaf)                    every step (statistics)
+//   void    visit(bool leaf, bool near)         every step (statistics)
 //   bool    hit(uint32_t i, int32_t j, const float4& q)
 //                                               leaf j within eps; true ends
 //                                               the walk early
@@ -25,7 +25,7 @@
 
 namespace dbx {
 
-// Queries of one wave's chunk: 64 x walk_queries_per_lane(), which is 1
+// Queries of one wave's chunk: 64 x walk_queries_per_lane(), which is 4
 // unless the environment variable DBX_WALK_QPL (1, 2, 4 or 8) overrides it
 // for tuning runs.  More per lane keeps lanes busier but spreads the queries
 // in flight over a longer stretch of the tree, which costs L2 hits.
@@ -64,14 +64,26 @@ __device__ __forceinline__ void walk_chunk(uint32_t n, uint32_t chunk, uint32_t&
   c1 = uint32_t(b + chunk < n ? b + chunk : n);
 }
 
+// Lanes are refilled only once fewer than walk_refill_at() of the 64 are
+// still walking (48 unless DBX_WALK_REFILL, 1..64, overrides it); in
+// between, the wave runs a tight per-lane loop.
+uint32_t walk_refill_at();
+
+struct WalkCfg {
+  uint32_t chunk;      // queries per wave
+  uint32_t refill_at;  // refill once fewer lanes than this are walking
+};
+inline WalkCfg walk_cfg() { return WalkCfg{walk_chunk_size(), walk_refill_at()}; }
+
 // `leaf` must have one readable float4 past leaf n-1 (a leaf step reads 32
 // bytes, like a node step, and ignores the second half).
 template <class V>
 __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
                                            const float4* __restrict__ leaf, uint32_t n,
-                                           uint32_t chunk, V& v, uint32_t* err) {
+                                           WalkCfg wc, V& v, uint32_t* err) {
   uint32_t c0, c1;
-  walk_chunk(n, chunk, c0, c1);
+  walk_chunk(n, wc.chunk, c0, c1);
+  const uint32_t refill_at = wc.refill_at;
   const int lane = threadIdx.x & 63;
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   uint32_t head = c0;  // next unstarted query of the chunk (wave-uniform)
@@ -81,45 +93,51 @@ __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
   uint32_t steps = 0;
   float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
   for (;;) {
+    // hand the chunk's next queries to the idle lanes
     const bool need = node == SENTINEL;
     const uint64_t m = __ballot(need);
-    if (m != 0) {
-      if (need) {
-        if (have) { v.end(i); have = false; }
-        const uint32_t idx = head + uint32_t(__popcll(m & lt));
-        if (idx < c1) {
-          i = idx;
-          have = true;
-          q = leaf[i];
-          node = v.begin(i, q);
-          steps = 0;
-        }
+    if (need) {
+      if (have) { v.end(i); have = false; }
+      const uint32_t idx = head + uint32_t(__popcll(m & lt));
+      if (idx < c1) {
+        i = idx;
+        have = true;
+        q = leaf[i];
+        node = v.begin(i, q);
+        steps = 0;
       }
-      const uint32_t h = head + uint32_t(__popcll(m));
-      head = h < c1 ? h : c1;
     }
-    const bool act = node != SENTINEL;
-    if (__ballot(act) == 0 && head >= c1) break;
-    if (!act) continue;
-    // a walk visits every node at most once: more than 2n steps, or a
-    // reference outside the arrays, means a malformed tree
-    const bool lf = is_leaf(node);
-    if (++steps > 2 * n ||
-        (lf ? uint32_t(leaf_index(node)) >= n : uint32_t(node) >= n - 1)) {
-      atomicOr(err, STATUS_TREE);
-      node = SENTINEL;
-      continue;
+    const uint32_t h = head + uint32_t(__popcll(m));
+    head = h < c1 ? h : c1;
+    if (__ballot(node != SENTINEL) == 0) {
+      if (head >= c1) break;
+      continue;  // every new walk was empty: hand out more
     }
-    const float4* p = lf ? leaf + leaf_index(node) : reinterpret_cast<const float4*>(nodes + node);
-    const float4 a = p[0];
-    float4 b = p[1];
-    if (lf) b = a;
-    v.visit(lf);
-    const bool near = box_sq_dist4(q, a, b) <= v.e2();
-    // internal: left child (a.w) or rope (b.w); leaf: its rope (a.w = b.w)
-    int32_t next = (near && !lf) ? __float_as_int(a.w) : __float_as_int(b.w);
-    if (near && lf && v.hit(i, leaf_index(node), q)) next = SENTINEL;
-    node = next;
+    // walk; stop early to refill once enough lanes are idle (and there is
+    // something left to hand out)
+    while (node != SENTINEL) {
+      // a walk visits every node at most once: more than 2n steps, or a
+      // reference outside the arrays, means a malformed tree
+      const bool lf = is_leaf(node);
+      if (++steps > 2 * n ||
+          (lf ? uint32_t(leaf_index(node)) >= n : uint32_t(node) >= n - 1)) {
+        atomicOr(err, STATUS_TREE);
+        node = SENTINEL;
+        break;
+      }
+      const float4* p =
+          lf ? leaf + leaf_index(node) : reinterpret_cast<const float4*>(nodes + node);
+      const float4 a = p[0];
+      float4 b = p[1];
+      if (lf) b = a;
+      const bool near = box_sq_dist4(q, a, b) <= v.e2();
+      v.visit(lf, near);
+      // internal: left child (a.w) or rope (b.w); leaf: its rope (a.w = b.w)
+      int32_t next = (near && !lf) ? __float_as_int(a.w) : __float_as_int(b.w);
+      if (near && lf && v.hit(i, leaf_index(node), q)) next = SENTINEL;
+      node = next;
+      if (head < c1 && uint32_t(__popcll(__ballot(node != SENTINEL))) < refill_at) break;
+    }
   }
   if (have) v.end(i);
 }

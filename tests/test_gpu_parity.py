@@ -176,7 +176,9 @@ def test_traversal_stats_counts(ctx):
     st = ctx.traversal_stats(dev(p), eps)
     assert st["pairs"] == oracle.pair_count(p, F32(eps))
     assert st["leaf_tests"] >= st["pairs"]
+    assert st["internal_visits"] >= st["descents"]
     assert st["internal_visits"] + st["leaf_tests"] >= n - 1
+    assert st["descents"] > 0  # pairs exist, so some walks entered subtrees
 
 
 @pytest.mark.parametrize("mp", [1, 2, 3, 5, 10, 50])
