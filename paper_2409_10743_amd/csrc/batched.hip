@@ -254,7 +254,7 @@ void launch_count_sets(const Node* nodes, const float4* leaf, uint32_t n, const 
                        hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_count_sets, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     n, walk_cfg(), keys, set_shift, set_root, set_e2, set_minpts, flag, err);
+                     n, walk_cfg(n), keys, set_shift, set_root, set_e2, set_minpts, flag, err);
 }
 
 void launch_pairs_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
@@ -263,7 +263,7 @@ void launch_pairs_sets(const Node* nodes, const float4* leaf, uint32_t n, const 
                        unsigned long long* bestcore, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs_sets, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     n, walk_cfg(), keys, set_shift, set_e2, set_minpts, perm, parent, flag,
+                     n, walk_cfg(n), keys, set_shift, set_e2, set_minpts, perm, parent, flag,
                      bestcore, err);
 }
 

@@ -60,8 +60,7 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ pts, u
   if (VEC) {
     const uint64_t total = 3ull * n, nv = total / 4;
     const float4* p4 = reinterpret_cast<const float4*>(pts);
-    for (uint64_t v = gid; v < nv; v += stride) {
-      const float4 x = p4[v];
+    auto take4 = [&](const float4& x, uint64_t v) {
       bad |= !(isfinite(x.x) && isfinite(x.y) && isfinite(x.z) && isfinite(x.w));
       const uint32_t r = uint32_t(v % 3);
       const float m = fminf(x.x, x.w), M = fmaxf(x.x, x.w);
@@ -72,7 +71,18 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ pts, u
       lo[0] = fminf(lo[0], l0); hi[0] = fmaxf(hi[0], h0);
       lo[1] = fminf(lo[1], l1); hi[1] = fmaxf(hi[1], h1);
       lo[2] = fminf(lo[2], l2); hi[2] = fmaxf(hi[2], h2);
+    };
+    // four loads in flight per thread
+    uint64_t v = gid;
+    for (; v + 3 * stride < nv; v += 4 * stride) {
+      const float4 x0 = p4[v], x1 = p4[v + stride], x2 = p4[v + 2 * stride],
+                   x3 = p4[v + 3 * stride];
+      take4(x0, v);
+      take4(x1, v + stride);
+      take4(x2, v + 2 * stride);
+      take4(x3, v + 3 * stride);
     }
+    for (; v < nv; v += stride) take4(p4[v], v);
     if (gid == 0)
       for (uint64_t e = nv * 4; e < total; ++e) {
         const float v = pts[e];
@@ -162,8 +172,7 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
     const uint32_t groups = n / 4;
     const float4* p4 = reinterpret_cast<const float4*>(pts);
     ulonglong2* k2 = reinterpret_cast<ulonglong2*>(keys);
-    for (uint32_t g = gid; g < groups; g += stride) {
-      const float4 a = p4[3 * size_t(g)], b = p4[3 * size_t(g) + 1], c = p4[3 * size_t(g) + 2];
+    auto code4 = [&](uint32_t g, const float4& a, const float4& b, const float4& c) {
       const uint64_t c0 = morton_of(a.x, a.y, a.z, lo, s);
       const uint64_t c1 = morton_of(a.w, b.x, b.y, lo, s);
       const uint64_t c2 = morton_of(b.z, b.w, c.x, lo, s);
@@ -174,6 +183,19 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
       count_digits(sh, c1);
       count_digits(sh, c2);
       count_digits(sh, c3);
+    };
+    // two groups (six loads) in flight per thread
+    uint32_t g = gid;
+    for (; uint64_t(g) + stride < groups; g += 2 * stride) {
+      const size_t f = 3 * size_t(g), h = 3 * size_t(g + stride);
+      const float4 a0 = p4[f], b0 = p4[f + 1], c0 = p4[f + 2];
+      const float4 a1 = p4[h], b1 = p4[h + 1], c1 = p4[h + 2];
+      code4(g, a0, b0, c0);
+      code4(g + stride, a1, b1, c1);
+    }
+    for (; g < groups; g += stride) {
+      const size_t f = 3 * size_t(g);
+      code4(g, p4[f], p4[f + 1], p4[f + 2]);
     }
     first_scalar = groups * 4;
   }
@@ -207,7 +229,9 @@ __global__ __launch_bounds__(256) void k_gather(
   if (bestcore) bestcore[i] = ~0ull;
 }
 
-uint32_t stream_blocks(uint32_t n) { return std::max(1u, std::min((n + 255) / 256, 4096u)); }
+// Reductions into a few global words (bounds, digit counts): 1024 blocks of
+// 256 threads keep every CU busy while bounding the closing global atomics.
+uint32_t reduce_blocks(uint32_t n) { return std::max(1u, std::min((n + 1023) / 1024, 1024u)); }
 
 }  // namespace
 
@@ -220,10 +244,10 @@ void launch_bounds(const float* pts, uint32_t n, uint32_t* bounds, uint32_t* sta
                    hipStream_t s) {
   if (n == 0) return;
   if (reinterpret_cast<uintptr_t>(pts) % 16 == 0)
-    hipLaunchKernelGGL(k_bounds<true>, dim3(stream_blocks(n)), dim3(256), 0, s, pts, n, bounds,
+    hipLaunchKernelGGL(k_bounds<true>, dim3(reduce_blocks(n)), dim3(256), 0, s, pts, n, bounds,
                        status);
   else
-    hipLaunchKernelGGL(k_bounds<false>, dim3(stream_blocks(n)), dim3(256), 0, s, pts, n, bounds,
+    hipLaunchKernelGGL(k_bounds<false>, dim3(reduce_blocks(n)), dim3(256), 0, s, pts, n, bounds,
                        status);
 }
 
@@ -232,10 +256,10 @@ void launch_morton(const float* pts, uint32_t n, const uint32_t* bounds, uint64_
   if (n == 0) return;
   // keys come from the arena (256-byte aligned); the points may not be
   if (reinterpret_cast<uintptr_t>(pts) % 16 == 0 && reinterpret_cast<uintptr_t>(keys) % 16 == 0)
-    hipLaunchKernelGGL(k_morton<true>, dim3(stream_blocks(n)), dim3(256), 0, s, pts, n, bounds,
+    hipLaunchKernelGGL(k_morton<true>, dim3(reduce_blocks(n)), dim3(256), 0, s, pts, n, bounds,
                        keys, hist);
   else
-    hipLaunchKernelGGL(k_morton<false>, dim3(stream_blocks(n)), dim3(256), 0, s, pts, n, bounds,
+    hipLaunchKernelGGL(k_morton<false>, dim3(reduce_blocks(n)), dim3(256), 0, s, pts, n, bounds,
                        keys, hist);
 }
 

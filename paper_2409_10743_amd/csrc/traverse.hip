@@ -52,9 +52,11 @@ struct PairVisit {
   uint8_t* member;
   unsigned long long* bestcore;
   bool ci, found;
-  unsigned long long pairs, visits, descents, leaves;  // COUNT only
+  uint32_t pairs, visits, descents, leaves;  // COUNT only: this query's counts
+  unsigned long long tot[4];                 // COUNT only: this lane's totals
   __device__ int32_t begin(uint32_t i, const float4& q) {
     found = false;
+    if (MODE == COUNT) pairs = visits = descents = leaves = 0;
     if (MODE == CORE) ci = is_core[i] != 0;
     return __float_as_int(q.w);
   }
@@ -87,8 +89,17 @@ struct PairVisit {
   }
   __device__ void end(uint32_t i) {
     if (MODE == FOF && found) member[i] = 1;
+    if (MODE == COUNT) {  // a query's counts are below 2n, so 32 bits hold them
+      tot[0] += pairs; tot[1] += visits; tot[2] += descents; tot[3] += leaves;
+    }
   }
 };
+
+// one atomic per wave with the wave's sum
+__device__ __forceinline__ void wave_add(unsigned long long* dst, unsigned long long x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  if ((threadIdx.x & 63) == 0 && x) atomicAdd(dst, x);
+}
 
 template <int MODE>
 __global__ void k_pairs(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
@@ -96,26 +107,27 @@ __global__ void k_pairs(const Node* __restrict__ nodes, const float4* __restrict
                         const uint8_t* __restrict__ is_core, const uint32_t* __restrict__ perm,
                         int32_t* parent, uint8_t* member, unsigned long long* bestcore,
                         unsigned long long* count, uint32_t* err) {
-  PairVisit<MODE> v{e2, is_core, perm, parent, member, bestcore, true, false, 0, 0, 0, 0};
+  PairVisit<MODE> v{e2, is_core, perm, parent, member, bestcore, true, false, 0, 0, 0, 0,
+                    {0, 0, 0, 0}};
   wave_walks(nodes, leaf, n, wc, v, err);
   if (MODE == COUNT) {  // pairs, internal visits, descents, leaf tests
-    unsigned long long c[4] = {v.pairs, v.visits, v.descents, v.leaves};
-    for (int k = 0; k < 4; ++k) {
-      for (int o = 32; o > 0; o >>= 1) c[k] += __shfl_xor(c[k], o, 64);
-      if ((threadIdx.x & 63) == 0 && c[k]) atomicAdd(count + k, c[k]);
-    }
+    wave_add(count, v.tot[0]);
+    wave_add(count + 1, v.tot[1]);
+    wave_add(count + 2, v.tot[2]);
+    wave_add(count + 3, v.tot[3]);
   }
 }
 
 }  // namespace
 
-uint32_t walk_queries_per_lane() {
-  static const uint32_t q = [] {
+uint32_t walk_queries_per_lane(uint32_t n) {
+  static const int forced = [] {
     const char* e = std::getenv("DBX_WALK_QPL");
-    const int v = e ? std::atoi(e) : 4;
-    return uint32_t((v == 1 || v == 2 || v == 4 || v == 8) ? v : 4);
+    const int v = e ? std::atoi(e) : 0;
+    return (v == 1 || v == 2 || v == 4 || v == 8) ? v : 0;
   }();
-  return q;
+  if (forced) return uint32_t(forced);
+  return n >= (1u << 23) ? 4u : n >= (1u << 22) ? 2u : 1u;
 }
 
 uint32_t walk_refill_at() {
@@ -132,7 +144,7 @@ void launch_count(const Node* nodes, const float4* leaf, uint32_t n, const int32
                   hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_count, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf, n,
-                     walk_cfg(), root,
+                     walk_cfg(n), root,
                      e2, min_pts, is_core, err);
 }
 
@@ -140,7 +152,7 @@ void launch_pairs_fof(const Node* nodes, const float4* leaf, uint32_t n, float e
                       int32_t* parent, uint8_t* member, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<FOF>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf, n,
-                     walk_cfg(), e2, nullptr, nullptr, parent, member, nullptr, nullptr, err);
+                     walk_cfg(n), e2, nullptr, nullptr, parent, member, nullptr, nullptr, err);
 }
 
 void launch_pairs_core(const Node* nodes, const float4* leaf, uint32_t n, float e2,
@@ -148,14 +160,14 @@ void launch_pairs_core(const Node* nodes, const float4* leaf, uint32_t n, float 
                        unsigned long long* bestcore, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<CORE>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf, n,
-                     walk_cfg(), e2, is_core, perm, parent, nullptr, bestcore, nullptr, err);
+                     walk_cfg(n), e2, is_core, perm, parent, nullptr, bestcore, nullptr, err);
 }
 
 void launch_pairs_count(const Node* nodes, const float4* leaf, uint32_t n, float e2,
                         unsigned long long* count, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<COUNT>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     n, walk_cfg(), e2, nullptr, nullptr, nullptr, nullptr, nullptr, count, err);
+                     n, walk_cfg(n), e2, nullptr, nullptr, nullptr, nullptr, nullptr, count, err);
 }
 
 }  // namespace dbx

@@ -25,15 +25,17 @@
 
 namespace dbx {
 
-// Queries of one wave's chunk: 64 x walk_queries_per_lane(), which is 4
-// unless the environment variable DBX_WALK_QPL (1, 2, 4 or 8) overrides it
-// for tuning runs.  More per lane keeps lanes busier but spreads the queries
-// in flight over a longer stretch of the tree, which costs L2 hits.
-uint32_t walk_queries_per_lane();
-inline uint32_t walk_chunk_size() { return 64u * walk_queries_per_lane(); }
+// Queries of one wave's chunk: 64 x walk_queries_per_lane(n).  More per
+// lane keeps lanes busier (a lane takes a new query when its walk ends) but
+// spreads the queries in flight over a longer stretch of the tree, which
+// costs L2 hits, and for small n it leaves CUs idle: 4 per lane from 2^23
+// queries, 2 from 2^22, else 1, unless the environment variable
+// DBX_WALK_QPL (1, 2, 4 or 8) overrides it for tuning runs.
+uint32_t walk_queries_per_lane(uint32_t n);
+inline uint32_t walk_chunk_size(uint32_t n) { return 64u * walk_queries_per_lane(n); }
 
 inline uint32_t walk_grid(uint32_t n, int block) {
-  const uint32_t chunk = walk_chunk_size();
+  const uint32_t chunk = walk_chunk_size(n);
   const uint64_t waves = (uint64_t(n) + chunk - 1) / chunk;
   const uint32_t per_block = uint32_t(block) / 64;
   return uint32_t((waves + per_block - 1) / per_block);
@@ -73,7 +75,7 @@ struct WalkCfg {
   uint32_t chunk;      // queries per wave
   uint32_t refill_at;  // refill once fewer lanes than this are walking
 };
-inline WalkCfg walk_cfg() { return WalkCfg{walk_chunk_size(), walk_refill_at()}; }
+inline WalkCfg walk_cfg(uint32_t n) { return WalkCfg{walk_chunk_size(n), walk_refill_at()}; }
 
 // `leaf` must have one readable float4 past leaf n-1 (a leaf step reads 32
 // bytes, like a node step, and ignores the second half).
@@ -114,29 +116,34 @@ __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
       continue;  // every new walk was empty: hand out more
     }
     // walk; stop early to refill once enough lanes are idle (and there is
-    // something left to hand out)
-    while (node != SENTINEL) {
+    // something left to hand out).  The loop is wave-uniform: idle lanes
+    // read leaf 0 (always readable) so that the loads need no branch.
+    for (;;) {
+      bool act = node != SENTINEL;
+      const bool lf = is_leaf(node);
       // a walk visits every node at most once: more than 2n steps, or a
       // reference outside the arrays, means a malformed tree
-      const bool lf = is_leaf(node);
-      if (++steps > 2 * n ||
-          (lf ? uint32_t(leaf_index(node)) >= n : uint32_t(node) >= n - 1)) {
+      if (act && (++steps > 2 * n ||
+                  (lf ? uint32_t(leaf_index(node)) >= n : uint32_t(node) >= n - 1))) {
         atomicOr(err, STATUS_TREE);
         node = SENTINEL;
-        break;
+        act = false;
       }
-      const float4* p =
-          lf ? leaf + leaf_index(node) : reinterpret_cast<const float4*>(nodes + node);
-      const float4 a = p[0];
-      float4 b = p[1];
-      if (lf) b = a;
-      const bool near = box_sq_dist4(q, a, b) <= v.e2();
-      v.visit(lf, near);
-      // internal: left child (a.w) or rope (b.w); leaf: its rope (a.w = b.w)
-      int32_t next = (near && !lf) ? __float_as_int(a.w) : __float_as_int(b.w);
-      if (near && lf && v.hit(i, leaf_index(node), q)) next = SENTINEL;
-      node = next;
-      if (head < c1 && uint32_t(__popcll(__ballot(node != SENTINEL))) < refill_at) break;
+      const float4* p = !act ? leaf
+                        : lf ? leaf + leaf_index(node)
+                             : reinterpret_cast<const float4*>(nodes + node);
+      const float4 a = p[0], p1 = p[1];
+      const float4 b = lf ? a : p1;
+      if (act) {
+        const bool near = box_sq_dist4(q, a, b) <= v.e2();
+        v.visit(lf, near);
+        // internal: left child (a.w) or rope (b.w); leaf: its rope (a.w = b.w)
+        int32_t next = (near && !lf) ? __float_as_int(a.w) : __float_as_int(b.w);
+        if (near && lf && v.hit(i, leaf_index(node), q)) next = SENTINEL;
+        node = next;
+      }
+      const uint32_t busy = uint32_t(__popcll(__ballot(node != SENTINEL)));
+      if (busy == 0 || (head < c1 && busy < refill_at)) break;
     }
   }
   if (have) v.end(i);
