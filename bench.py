@@ -54,10 +54,9 @@ BYTES_PER_POINT = {
     "sort": 24.0,                   # per pass: read code+index, write code+index
     "gather": 4 + 12 + 16 + 4 + 4 + 1,  # read index, xyz; write leaf, parent,
                                         # minlab, flag
-    "build_frame": 8 + 16 + 16 + 32 + 4 + 4,  # codes, leaves in, leaves out (with
-                                              # ropes), nodes, right child, exchange slot
+    "build_frame": 8 + 16 + 16 + 32 + 4,  # codes, leaves in, leaves and nodes out (with
+                                          # ropes), exchange slots of pending splits
     "build_levels": 0.0,            # a few nodes per 256-leaf frame
-    "ropes": 0.0,                   # only the listed nodes whose rope the build left open
     "cells": 0.0,                   # DenseBox only
     "count": 16 + 32 + 1,           # leaves, nodes, core flag
     "pairs": 16 + 32 + 4 + 4 + 1,   # leaves, nodes, parent read/write, member flag
@@ -71,13 +70,13 @@ KERNEL_OF_PHASE = {f"sort{p}": "sort" for p in range(8)}
 KERNEL_NAME = {  # device function names, as rocprofv3 reports them
     "sort": "k_onesweep", "pairs": "k_pairs", "build_frame": "k_build_frame",
     "build_levels": "k_build_level", "gather": "k_gather", "cells": "k_cell_stats",
-    "morton": "k_morton", "bounds": "k_bounds", "ropes": "k_ropes", "count": "k_count",
+    "morton": "k_morton", "bounds": "k_bounds", "count": "k_count",
     "final_roots": "k_final_roots", "final_labels": "k_final_labels", "prep": "k_prep",
 }
 KERNEL_SOURCE = {  # files whose text decides the kernel's code (plus common.hpp)
     "sort": "radix_sort.hip", "pairs": ("traverse.hip", "walk.hpp"),
     "count": ("traverse.hip", "walk.hpp"),
-    "build_frame": "lbvh.hip", "build_levels": "lbvh.hip", "ropes": "lbvh.hip",
+    "build_frame": "lbvh.hip", "build_levels": "lbvh.hip",
     "cells": "densebox.hip",
     "gather": "morton.hip", "morton": "morton.hip",
     "bounds": "morton.hip", "prep": "morton.hip", "final_roots": "finalize.hip",

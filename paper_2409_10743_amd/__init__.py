@@ -143,8 +143,8 @@ def _stream(device) -> ctypes.c_void_p:
 
 # one timing slot per kernel launch, in launch order
 PHASES = ("prep", "bounds", "morton", "sort0", "sort1", "sort2", "sort3", "sort4", "sort5",
-          "sort6", "sort7", "gather", "cells", "build_frame", "build_levels", "ropes", "count",
-          "pairs", "final_roots", "final_labels")
+          "sort6", "sort7", "gather", "cells", "build_frame", "build_levels", "count", "pairs",
+          "final_roots", "final_labels")
 
 
 class Context:

@@ -3,7 +3,7 @@
 // One call enqueues the whole path on the caller's stream and waits once at
 // the end for a 4-byte status word:
 //   prep -> scene bounds -> Morton codes (+ digit histograms) -> radix sort
-//   -> sorted leaves -> Apetrei build -> ropes -> [counting, minPts > 2]
+//   -> sorted leaves -> Apetrei build (Karras order, ropes) -> [counting, minPts > 2]
 //   -> pair traversal + union-find -> labels
 // All scratch comes from the context's arena (one device allocation, grown
 // on demand, reused by later calls), so a warmed context allocates nothing.
@@ -41,7 +41,7 @@ int fail(int code, const std::string& msg) {
 // One timing slot per kernel launch of a run (a slot a run skips reads 0).
 enum Phase {
   PH_PREP, PH_BOUNDS, PH_MORTON, PH_SORT0, PH_GATHER = PH_SORT0 + SORT_PASSES, PH_CELLS,
-  PH_BUILD_FRAME, PH_BUILD_LEVELS, PH_ROPES, PH_COUNT, PH_PAIRS, PH_FINAL_ROOTS,
+  PH_BUILD_FRAME, PH_BUILD_LEVELS, PH_COUNT, PH_PAIRS, PH_FINAL_ROOTS,
   PH_FINAL_LABELS, NPHASES
 };
 // "morton" is the point codes (FDBSCAN) or the cell codes (DenseBox);
@@ -49,15 +49,14 @@ enum Phase {
 const char* const kPhaseNames[NPHASES] = {
     "prep",  "bounds",  "morton",      "sort0",        "sort1",  "sort2",
     "sort3", "sort4",   "sort5",       "sort6",        "sort7",  "gather",
-    "cells", "build_frame", "build_levels", "ropes", "count", "pairs", "final_roots",
+    "cells", "build_frame", "build_levels", "count", "pairs", "final_roots",
     "final_labels"};
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Byte offsets of every buffer of a job inside the arena.
 struct Layout {
-  size_t keys_a, keys_b, vals_a, vals_b, leaf, nodes, parent, minlab, flag, bestcore, pending,
-      fixups, fix_cnt;
+  size_t keys_a, keys_b, vals_a, vals_b, leaf, nodes, parent, minlab, flag, bestcore, pending;
   // DenseBox only (0 otherwise)
   size_t cid, head, cell_start, cell_lo, cell_hi, cell_minorig, cell_dense, prim_count,
       prim_start, prims, pkey, scan1, scan2, scan_ctr, ncells, nprims;
@@ -85,8 +84,6 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
   L.bestcore = need_bestcore ? take(size_t(n) * 8) : 0;
   L.pending_entries = uint32_t(build_pending_entries(n));
   L.pending = take(size_t(L.pending_entries) * 16);
-  L.fixups = take(build_fix_entries(n) * 8);
-  L.fix_cnt = take(size_t(build_frames(n)) * 4);
   if (densebox) {
     L.cid = take(size_t(n) * 4);
     L.head = take(size_t(n) * 4);
@@ -203,6 +200,7 @@ T* at(dbscan_ctx* c, size_t off) {
 struct Index {
   Layout L;
   uint64_t* keys;
+  uint32_t* bounds;
   uint32_t* perm;
   float4* leaf;
   Node* nodes;
@@ -266,22 +264,17 @@ int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore,
   uint32_t* perm = in_a ? va : vb;
   // the other key buffer is free now: the build's scratch
   int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
-  int32_t* right = other + n;
   launch_gather(pts, perm, n, at<float4>(c, L.leaf), at<int32_t>(c, L.parent),
                 at<int32_t>(c, L.minlab), at<uint8_t>(c, L.flag),
                 need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr,
                 at<int4>(c, L.pending), L.pending_entries, s);
   mark(c, timing, PH_GATHER, s);
-  int2* fixups = at<int2>(c, L.fixups);
-  uint32_t* fix_cnt = at<uint32_t>(c, L.fix_cnt);
-  launch_build(keys, 64, at<float4>(c, L.leaf), n, at<Node>(c, L.nodes), right, other,
-               at<int32_t>(c, L.root), at<int4>(c, L.pending), fixups, fix_cnt, status, s,
+  launch_build(keys, 64, at<float4>(c, L.leaf), n, at<Node>(c, L.nodes), other,
+               at<int32_t>(c, L.root), at<int4>(c, L.pending), status, s,
                timing ? build_mark : nullptr, &sm);
   mark(c, timing, PH_BUILD_LEVELS, s);
-  launch_ropes(keys, 64, at<Node>(c, L.nodes), at<float4>(c, L.leaf), right, fixups, fix_cnt, n,
-               status, s);
-  mark(c, timing, PH_ROPES, s);
   out->keys = keys;
+  out->bounds = bounds;
   out->perm = perm;
   out->leaf = at<float4>(c, L.leaf);
   out->nodes = at<Node>(c, L.nodes);
@@ -330,13 +323,15 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
   int32_t* parent = at<int32_t>(c, L.parent);
   unsigned long long* bestcore = core_mode ? at<unsigned long long>(c, L.bestcore) : nullptr;
   if (core_mode)
-    launch_count(ix.nodes, ix.leaf, n, ix.root, e2, min_pts, flag, ix.status, block, s);
+    launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, n, ix.root, e2, min_pts, flag,
+                 ix.status, block, s);
   mark(c, timing, PH_COUNT, s);
   if (core_mode)
-    launch_pairs_core(ix.nodes, ix.leaf, n, e2, flag, ix.perm, parent, bestcore, ix.status,
-                      block, s);
+    launch_pairs_core(ix.nodes, ix.leaf, ix.keys, ix.bounds, n, e2, flag, ix.perm, parent,
+                      bestcore, ix.status, block, s);
   else
-    launch_pairs_fof(ix.nodes, ix.leaf, n, e2, parent, flag, ix.status, block, s);
+    launch_pairs_fof(ix.nodes, ix.leaf, ix.keys, ix.bounds, n, e2, parent, flag, ix.status,
+                     block, s);
   mark(c, timing, PH_PAIRS, s);
   int32_t* minlab = at<int32_t>(c, L.minlab);
   launch_final_roots(n, min_pts, flag, bestcore, ix.perm, parent, minlab, labels, s);
@@ -392,7 +387,6 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
   const uint64_t* keys = in_a ? ka : kb;
   const uint32_t* perm = in_a ? va : vb;
   int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
-  int32_t* right = other + n;
   launch_gather(pts, perm, n, spts, parent, minlab, flag, bestcore, at<int4>(c, L.pending),
                 L.pending_entries, s);
   mark(c, timing, PH_GATHER, s);
@@ -428,13 +422,8 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
 
   Node* nodes = at<Node>(c, L.nodes);
   int32_t* root = at<int32_t>(c, L.root);
-  int2* fixups = at<int2>(c, L.fixups);
-  uint32_t* fix_cnt = at<uint32_t>(c, L.fix_cnt);
-  launch_build_boxes(pkey, prims, np, nodes, right, other, root, at<int4>(c, L.pending), fixups,
-                     fix_cnt, status, s);
+  launch_build_boxes(pkey, prims, np, nodes, other, root, at<int4>(c, L.pending), status, s);
   mark(c, timing, PH_BUILD_LEVELS, s);
-  launch_ropes_boxes(pkey, nodes, prims, right, fixups, fix_cnt, np, status, s);
-  mark(c, timing, PH_ROPES, s);
   if (core_mode)
     launch_count_db(nodes, prims, np, spts, n, cell_start, root, e2, min_pts, flag, status, block,
                     s);
@@ -525,19 +514,14 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
   const uint64_t* keys = in_a ? ka : kb;
   const uint32_t* perm = in_a ? va : vb;
   int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
-  int32_t* right = other + n;
   launch_gather(pts, perm, n, leaf, parent, minlab, flag, bestcore, at<int4>(c, L.pending),
                 L.pending_entries, s);
   mark(c, timing, PH_GATHER, s);
   mark(c, timing, PH_CELLS, s);
   Node* nodes = at<Node>(c, L.nodes);
-  int2* fixups = at<int2>(c, L.fixups);
-  uint32_t* fix_cnt = at<uint32_t>(c, L.fix_cnt);
-  launch_build(keys, set_shift, leaf, n, nodes, right, other, d_root, at<int4>(c, L.pending),
-               fixups, fix_cnt, status, s, timing ? build_mark : nullptr, &sm);
+  launch_build(keys, set_shift, leaf, n, nodes, other, d_root, at<int4>(c, L.pending), status, s,
+               timing ? build_mark : nullptr, &sm);
   mark(c, timing, PH_BUILD_LEVELS, s);
-  launch_ropes(keys, set_shift, nodes, leaf, right, fixups, fix_cnt, n, status, s);
-  mark(c, timing, PH_ROPES, s);
   if (any_core)
     launch_count_sets(nodes, leaf, n, keys, set_shift, d_root, d_e2, d_mp, flag, status, block, s);
   mark(c, timing, PH_COUNT, s);
@@ -833,8 +817,8 @@ int dbscan_core_flags(dbscan_ctx* c, const float* points, int64_t n, float eps, 
   st = build_index(c, points, uint32_t(n), false, false, s, &ix);
   if (st != DBSCAN_OK) return st;
   uint8_t* flag = at<uint8_t>(c, ix.L.flag);
-  launch_count(ix.nodes, ix.leaf, uint32_t(n), ix.root, eps * eps, min_pts, flag, ix.status,
-               256, s);
+  launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, uint32_t(n), ix.root, eps * eps, min_pts,
+               flag, ix.status, 256, s);
   launch_scatter_u8(flag, ix.perm, uint32_t(n), core, s);
   HIP_TRY(hipGetLastError());
   return finish(c, ix.status, false, s);
@@ -861,7 +845,8 @@ int dbscan_traversal_stats(dbscan_ctx* c, const float* points, int64_t n, float 
   st = build_index(c, points, uint32_t(n), false, false, s, &ix);
   if (st != DBSCAN_OK) return st;
   unsigned long long* dcount = at<unsigned long long>(c, ix.L.count);
-  launch_pairs_count(ix.nodes, ix.leaf, uint32_t(n), eps * eps, dcount, ix.status, 256, s);
+  launch_pairs_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, uint32_t(n), eps * eps, dcount,
+                     ix.status, 256, s);
   unsigned long long* h = reinterpret_cast<unsigned long long*>(c->host_status + 2);
   HIP_TRY(hipMemcpyAsync(h, dcount, 32, hipMemcpyDeviceToHost, s));
   st = finish(c, ix.status, false, s);

@@ -17,16 +17,6 @@ namespace dbx {
 
 namespace {
 
-__device__ __forceinline__ uint64_t spread3(uint32_t v) {
-  uint64_t x = v & 0x1fffffu;
-  x = (x | (x << 32)) & 0x001f00000000ffffull;
-  x = (x | (x << 16)) & 0x001f0000ff0000ffull;
-  x = (x | (x << 8)) & 0x100f00f00f00f00full;
-  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
-  x = (x | (x << 2)) & 0x1249249249249249ull;
-  return x;
-}
-
 __device__ __forceinline__ float block_min(float v, float* s_red) {
   for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
   if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
@@ -106,6 +96,8 @@ __global__ __launch_bounds__(256) void k_set_morton(const float* __restrict__ pt
 
 // Counting for the points of sets with minPts > 2, from their set's root.
 struct CountSets {
+  static constexpr bool kBounded = false;
+  __device__ uint64_t khi() const { return ~0ull; }
   const uint64_t* keys;
   int set_shift;
   const int32_t* set_root;
@@ -137,12 +129,14 @@ __global__ void k_count_sets(const Node* __restrict__ nodes, const float4* __res
                              const int32_t* __restrict__ set_minpts,
                              uint8_t* __restrict__ flag, uint32_t* __restrict__ err) {
   CountSets v{keys, set_shift, set_root, set_e2, set_minpts, flag, 0.f, 0, 0};
-  wave_walks(nodes, leaf, n, wc, v, err);
+  wave_walks(nodes, leaf, keys, n, wc, v, err);
 }
 
 // Pair traversal; each lane runs the minPts <= 2 or the minPts > 2 rule of
 // its own set (both ends of a pair are always in the same set).
 struct PairSets {
+  static constexpr bool kBounded = false;
+  __device__ uint64_t khi() const { return ~0ull; }
   const uint64_t* keys;
   int set_shift;
   const float* set_e2;
@@ -192,7 +186,7 @@ __global__ void k_pairs_sets(const Node* __restrict__ nodes, const float4* __res
                              unsigned long long* bestcore, uint32_t* err) {
   PairSets v{keys, set_shift, set_e2, set_minpts, perm, parent, flag, bestcore,
              0.f, false, true, false};
-  wave_walks(nodes, leaf, n, wc, v, err);
+  wave_walks(nodes, leaf, keys, n, wc, v, err);
 }
 
 // Find without compression (the forest no longer changes).

@@ -6,8 +6,10 @@
 //   leaf j (0 <= j < n), 16 bytes:             float x, y, z; int rope
 //     (the leaf array is the points in Morton order; the rope sits in .w)
 //   node references: k >= 0 internal, (j | LEAF_BIT) a leaf, SENTINEL = -1.
-// Internal node k is the one whose split lies between leaves k and k+1
-// (the Apetrei numbering), so every reference fits in 32 bits for n < 2^31.
+// Internal nodes are in Karras' order: the node covering leaves [l, r] is
+// number r if it is its parent's left child, number l if the right child,
+// and the root is number 0; so a rope target's number is its first leaf.
+// Every reference fits in 32 bits for n < 2^31.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -111,6 +113,33 @@ __device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) 
   }
 }
 
+// ---- Morton codes (section 4.2.2) ------------------------------------------
+// spread the low 21 bits of v to every third bit of a 64-bit word
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffffu;
+  x = (x | (x << 32)) & 0x001f00000000ffffull;
+  x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+// grid coordinate of p on one axis: min(floor((p - lo) * s), 2^21 - 1) in
+// binary32, s = 2^21 / extent (0 for a zero extent); monotone in p
+__device__ __forceinline__ uint32_t quantise(float p, float lo, float s) {
+#pragma clang fp contract(off)
+  float t = (p - lo) * s;
+  t = fminf(fmaxf(floorf(t), 0.0f), float((1u << MORTON_BITS) - 1));  // NaN -> 0
+  return uint32_t(t);
+}
+
+__device__ __forceinline__ uint64_t morton_of(float x, float y, float z, const float* lo,
+                                              const float* s) {
+  return (spread3(quantise(x, lo[0], s[0])) << 2) | (spread3(quantise(y, lo[1], s[1])) << 1) |
+         spread3(quantise(z, lo[2], s[2]));
+}
+
 // Ordered-integer view of a float for atomic min/max of scene bounds.
 __device__ __forceinline__ uint32_t f2ord(float f) {
   uint32_t u = __float_as_uint(f);
@@ -122,6 +151,32 @@ __host__ __device__ inline float ord2f(uint32_t u) {
   __builtin_memcpy(&f, &b, 4);
   return f;
 }
+
+// The grid the Morton codes quantise to, from the scene bounds words
+// (bounds[0..2] lo, [3..5] hi, ordered ints).
+struct MortonGrid {
+  float lo[3], s[3];
+  __device__ void load(const uint32_t* bounds) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = ord2f(bounds[a]);
+      const float ext = ord2f(bounds[3 + a]) - lo[a];
+      s[a] = ext > 0.0f ? float(1u << MORTON_BITS) / ext : 0.0f;  // IEEE division
+    }
+  }
+  __device__ uint64_t code(float x, float y, float z) const { return morton_of(x, y, z, lo, s); }
+  // A code no smaller than that of any point p with sq_dist(q, p) <= e2.
+  // Such a p has |p_a - q_a| <= sqrt(e2) (1 + 3u) on every axis (u = 2^-24),
+  // so p_a <= h_a = q_a + pad (pad covers that and the rounding of the sum,
+  // and an absolute 1e-22 for e2 that underflow); quantise() and the
+  // interleaving are monotone, so code(p) <= code(h).
+  __device__ uint64_t upper_code(const float4& q, float e2) const {
+    const float pad = sqrtf(e2) * 1.0001f + 1e-22f;
+    const float hx = q.x + (pad + fabsf(q.x) * 1e-6f);
+    const float hy = q.y + (pad + fabsf(q.y) * 1e-6f);
+    const float hz = q.z + (pad + fabsf(q.z) * 1e-6f);
+    return code(hx, hy, hz);
+  }
+};
 
 // XCD-aware block order: the hardware deals consecutive workgroups to the
 // 8 XCDs round-robin; remap so each XCD works on one contiguous stretch of

@@ -38,16 +38,6 @@ constexpr uint32_t ST_INC = 2u << 30;
 constexpr uint32_t ST_VAL = (1u << 30) - 1;
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
-__device__ __forceinline__ uint64_t spread3(uint32_t v) {
-  uint64_t x = v & 0x1fffffu;
-  x = (x | (x << 32)) & 0x001f00000000ffffull;
-  x = (x | (x << 16)) & 0x001f0000ff0000ffull;
-  x = (x | (x << 8)) & 0x100f00f00f00f00full;
-  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
-  x = (x | (x << 2)) & 0x1249249249249249ull;
-  return x;
-}
-
 // Cell key: Morton code of the cell coordinates, so sorting by it orders
 // the cells along the Z-curve.  Side max(h, extent / 2^21) per axis.
 __global__ __launch_bounds__(256) void k_cell_keys(const float* __restrict__ pts, uint32_t n,

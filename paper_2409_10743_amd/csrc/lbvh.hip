@@ -1,18 +1,39 @@
 // Linear BVH over Morton-sorted leaves: Apetrei's bottom-up construction
-// (section 4.2.1: faster than Karras' build) followed by a separate pass that
-// sets the ropes used by the stackless traversal.
+// (section 4.2.1: faster than Karras' build), with the internal nodes laid
+// out in Karras' order and the ropes of the stackless traversal written by
+// the same pass.
 //
 // Construction.  delta(i) measures how different leaves i and i+1 are: the
 // XOR of their codes, and for equal codes the XOR of the positions i^(i+1)
 // (ranked below every differing pair), which splits runs of equal codes
-// evenly.  A node covering leaves [l, r] is the left child of internal node
-// r when l = 0 or (r < n-1 and delta(r) < delta(l-1)), otherwise the right
-// child of internal node l-1.  Ties go to the smaller boundary index, a
-// strict order, so every internal node gets exactly one left and one right
-// child.  Each child swaps its outer range bound into a per-parent slot
+// evenly.  A node covering leaves [l, r] is the left child of the node split
+// at r when l = 0 or (r < n-1 and delta(r) < delta(l-1)), otherwise the
+// right child of the node split at l-1.  Ties go to the smaller boundary
+// index, a strict order, so every split gets exactly one left and one right
+// child.  Each child swaps its outer range bound into a per-split slot
 // (initially -1) with one acquire-release exchange: the first to arrive
 // leaves, the second learns the parent's full range from the value it gets
-// back, sees its sibling's box, writes the parent's box and climbs on.
+// back, reads its sibling's box, finishes the parent and climbs on.
+//
+// Node order.  Internal nodes are numbered as in Karras' layout, which
+// ArborX recovers after Apetrei's build (section 4.2.1): the node covering
+// [l, r] is number r if it is the left child of its parent and number l if
+// it is the right child, and the root is number 0.  So the children of the
+// node split between leaves g and g+1 are number g (or leaf g) and number
+// g+1 (or leaf g+1), and the numbers 0..n-2 are each used once.  A node's
+// number is known as soon as it is finished: the thread that finishes it
+// decides right away on which side of its parent it lies, and writes its
+// record then.
+//
+// Ropes.  The rope of a node or leaf is where a stackless, left-first
+// pre-order walk goes after its subtree: the right child of the lowest
+// ancestor holding it in its left subtree, i.e. the right child of the split
+// at its last leaf r.  That child covers [r+1, ...]; it is leaf r+1 exactly
+// when leaf r+1 is a right child (r+1 is the last leaf, or delta(r+1) is not
+// below delta(r)), else internal node r+1.  A rope is therefore a function
+// of r and two deltas, written with the record: the sentinel when r is the
+// last leaf (of its set), else r+1 as a leaf or a node.  A rope target's
+// number is always its first leaf, which the traversal uses to stop early.
 //
 // Frames.  gfx950 has one L2 per XCD, so an exchange between threads of
 // different workgroups needs agent scope, i.e. an L2 write-back before and
@@ -27,22 +48,12 @@
 // edge), which runs after a kernel boundary, so everything earlier levels
 // wrote is visible there.  The last level is one frame holding all leaves.
 //
-// Ropes.  The rope of a node is where a stackless, left-first pre-order
-// walk goes after the node's subtree: the right child of the lowest ancestor
-// holding the node in its left subtree.  That ancestor is internal node r,
-// r being the last leaf the node covers, so rope = right(r), or the sentinel
-// when r = n-1 (the right-most path).  No reordering of nodes is needed.
 // Batched sets: the keys carry the set id in their top bits (`set_shift`),
 // so a boundary between sets has a larger delta than any boundary inside a
 // set and every set is one complete subtree.  Ropes are cut at set ends
 // (sets overlap in space, so boxes would not keep a walk inside its set),
 // and the node spanning exactly a set is recorded as that set's root.  With
 // no set bits (set_shift = 64) the only such node is the root.
-// Level 1 knows right(r) whenever that child was finished inside the frame,
-// which holds for nearly every node: it writes those leaves and nodes whole,
-// once.  The rest (nodes whose r is the frame's last leaf or whose right(r)
-// crosses the frame edge, and nodes finished at higher levels) are listed
-// and patched by k_ropes after the last level.
 #include <algorithm>
 
 #include "pipeline.hpp"
@@ -93,109 +104,65 @@ __device__ __forceinline__ uint64_t delta(const uint64_t* __restrict__ keys, int
   return a == b ? uint64_t(uint32_t(i) ^ uint32_t(i + 1)) : ((a ^ b) + (1ull << 32));
 }
 
-// One climb step at interior parent `par` of the node `node` = [l, r]:
-// link it, exchange, and, for the second arrival, finish the parent.
-// Returns false when the climb stops here (first arrival, or a bad tree).
-// Fix-up list: each level-1 frame owns FIX_PER_FRAME entries and a count.
-// An internal node p goes into the region of the frame holding leaf p; a
-// frame holds at most 256 leaves and 256 splits, so its region never
-// overflows for a well-formed tree.  Nodes finished above level 1 take a
-// slot with an atomic on their frame's count: these atomics are spread over
-// all frames, never one shared counter.
-struct FixList {
-  int2* entries;
-  uint32_t* cnt;
-  uint32_t* err;
-  __device__ void push(int32_t p, int2 e) const {
-    const uint32_t f = uint32_t(p) / BUILD_LEAVES;
-    const uint32_t k = atomicAdd(cnt + f, 1u);
-    if (k < FIX_PER_FRAME) entries[size_t(f) * FIX_PER_FRAME + k] = e;
-    else atomicOr(err, STATUS_TREE);
-  }
-};
+// Is [l, r] the left child of its parent (split at r) rather than the right
+// child (split at l - 1)?  d_r = delta(r), d_lm1 = delta(l - 1); each is
+// only used where it exists.
+__device__ __forceinline__ bool left_side(int32_t l, int32_t r, int32_t last, uint64_t d_r,
+                                          uint64_t d_lm1) {
+  return l == 0 || (r != last && d_r < d_lm1);
+}
 
-template <class Leaves>
-__device__ __forceinline__ bool climb_step(const Leaves& lv, Node* nodes,
-                                           int32_t* right, int32_t* other, const FixList& fx,
-                                           uint32_t* err, const uint64_t* keys,
-                                           int set_shift, int32_t* set_root,
-                                           int32_t last, bool is_left, int32_t par,
-                                           int32_t& node, int32_t& l, int32_t& r, float& lox,
-                                           float& loy, float& loz, float& hix, float& hiy,
-                                           float& hiz) {
-  if (is_left) nodes[par].left = node;
-  else right[par] = node;
-  const int32_t bound = __hip_atomic_exchange(other + par, is_left ? l : r, __ATOMIC_ACQ_REL,
-                                              __HIP_MEMORY_SCOPE_WORKGROUP);
-  if (bound < 0) return false;  // first arrival: the sibling finishes the parent
-  int32_t sib;
-  if (is_left) { r = bound; sib = right[par]; }
-  else { l = bound; sib = nodes[par].left; }
-  const bool sib_ok = is_leaf(sib) ? leaf_index(sib) <= last : (sib >= 0 && sib < last);
-  if (!sib_ok || l < 0 || r > last || l > r) { atomicOr(err, STATUS_TREE); return false; }
-  float slx, sly, slz, shx, shy, shz;
-  if (is_leaf(sib)) {
-    float4 ql, qh;
-    lv.load(leaf_index(sib), ql, qh);
-    slx = ql.x; sly = ql.y; slz = ql.z; shx = qh.x; shy = qh.y; shz = qh.z;
-  } else {
-    const Node& sn = nodes[sib];
-    slx = sn.lox; sly = sn.loy; slz = sn.loz; shx = sn.hix; shy = sn.hiy; shz = sn.hiz;
-  }
-  lox = fminf(lox, slx); loy = fminf(loy, sly); loz = fminf(loz, slz);
-  hix = fmaxf(hix, shx); hiy = fmaxf(hiy, shy); hiz = fmaxf(hiz, shz);
-  Node& pn = nodes[par];
-  pn.lox = lox; pn.loy = loy; pn.loz = loz;
-  pn.hix = hix; pn.hiy = hiy; pn.hiz = hiz;
-  fx.push(par, make_int2(par, r));  // rope set by k_ropes
-  node = par;
-  const uint64_t mask = set_mask_of(set_shift);
-  if ((l == 0 || set_cut(keys, l - 1, mask)) && (r == last || set_cut(keys, r, mask)))
-    set_root[set_of(keys, l, set_shift)] = par;
-  return true;
+// left child of the node [l, r] split at g: [l, g], number g or leaf g
+__device__ __forceinline__ int32_t left_ref(int32_t l, int32_t g) {
+  return l == g ? leaf_ref(g) : g;
+}
+
+// rope of a node or leaf whose last leaf is r; cut: a set ends at r,
+// d_r = delta(r), d_r1 = delta(r + 1) (only used where they exist)
+__device__ __forceinline__ int32_t rope_of(int32_t r, int32_t last, bool cut, uint64_t d_r,
+                                           uint64_t d_r1) {
+  if (r == last || cut) return SENTINEL;
+  const bool leaf_next = r + 1 == last || !(d_r1 < d_r);
+  return leaf_next ? leaf_ref(r + 1) : r + 1;
+}
+
+__device__ __forceinline__ void write_node(Node* nodes, int32_t k, const float4& lo,
+                                           const float4& hi, int32_t left, int32_t rope) {
+  float4* q = reinterpret_cast<float4*>(nodes + k);
+  q[0] = make_float4(lo.x, lo.y, lo.z, __int_as_float(left));
+  q[1] = make_float4(hi.x, hi.y, hi.z, __int_as_float(rope));
+}
+
+__device__ __forceinline__ void grow(float4& lo, float4& hi, const float4& slo,
+                                     const float4& shi) {
+  lo.x = fminf(lo.x, slo.x); lo.y = fminf(lo.y, slo.y); lo.z = fminf(lo.z, slo.z);
+  hi.x = fmaxf(hi.x, shi.x); hi.y = fmaxf(hi.y, shi.y); hi.z = fmaxf(hi.z, shi.z);
 }
 
 // Level 1 of the build, all in LDS: one workgroup per 256-leaf frame.  The
-// frame's delta values, leaves, exchange slots, child references and boxes
-// live in LDS (the exchange is an LDS swap); at the end the frame's
-// internal nodes go out to memory in one coalesced pass, together with the
-// state later levels need: the exchange slot of every split in the frame
-// (-1 for the frame's right edge), child references set so far, and the
-// range end of every finished node.
-// Appends one entry per lane with `want` set to the frame's own list
-// (count in LDS); all lanes of the wave call it.
-__device__ __forceinline__ void wave_append(int2* list, uint32_t* lds_count, bool want, int2 e) {
-  const uint64_t m = __ballot(want);
-  if (m == 0) return;
-  const int lane = threadIdx.x & 63;
-  const int leader = __ffsll(static_cast<long long>(m)) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = atomicAdd(lds_count, uint32_t(__popcll(m)));
-  base = __shfl(base, leader, 64);
-  const uint64_t below = lane ? (m & (~0ull >> (64 - lane))) : 0ull;
-  if (want) list[base + __popcll(below)] = e;
-}
-
+// frame's deltas, leaves, exchange slots and finished nodes (by number:
+// every node finished here has both range ends, so its number, in the
+// frame) live in LDS; the exchange is an LDS swap.  At the end the frame's
+// leaves and nodes go out whole, ropes included, in one coalesced pass,
+// with the exchange slots later levels still need.
 template <class Leaves>
 __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
     const uint64_t* __restrict__ keys, Leaves lv, uint32_t n, int set_shift,
-    Node* __restrict__ nodes, int32_t* __restrict__ right, int32_t* __restrict__ other,
-    int32_t* __restrict__ set_root, int4* __restrict__ pend_out, int2* __restrict__ fix_frame,
-    uint32_t* __restrict__ fix_cnt, uint32_t* __restrict__ err) {
-  __shared__ uint64_t s_delta[BUILD_LEAVES + 1];  // boundary f0-1+j at j
-  __shared__ uint32_t s_fix_cnt;
+    Node* __restrict__ nodes, int32_t* __restrict__ other, int32_t* __restrict__ set_root,
+    int4* __restrict__ pend_out, uint32_t* __restrict__ err) {
+  __shared__ uint64_t s_delta[BUILD_LEAVES + 2];  // delta of boundary f0-1+j at j
+  __shared__ uint8_t s_cut[BUILD_LEAVES + 2];     // a set ends at boundary f0-1+j
   __shared__ float4 s_leaf[BUILD_LEAVES], s_leafhi[BUILD_LEAVES];
-  __shared__ float4 s_lo[BUILD_LEAVES], s_hi[BUILD_LEAVES];
-  __shared__ int32_t s_other[BUILD_LEAVES], s_left[BUILD_LEAVES], s_right[BUILD_LEAVES],
-      s_end[BUILD_LEAVES];
-  __shared__ uint8_t s_cut[BUILD_LEAVES + 1];  // a set ends at boundary f0-1+j
+  __shared__ float4 s_lo[BUILD_LEAVES], s_hi[BUILD_LEAVES];  // node number f0+k
+  __shared__ int32_t s_left[BUILD_LEAVES], s_end[BUILD_LEAVES];  // its left child, last leaf
+  __shared__ int32_t s_other[BUILD_LEAVES];  // exchange slot of split f0+k; -2 once finished
   const int32_t t = threadIdx.x;
   const int32_t last = int32_t(n) - 1;
   const int32_t f0 = int32_t(blockIdx.x) * BUILD_LEAVES;
   const int32_t f1 = min(f0 + BUILD_LEAVES, int32_t(n));
   const int32_t m = f1 - f0;
   const uint64_t mask = set_mask_of(set_shift);
-  for (int32_t j = t; j <= m; j += BUILD_BLOCK) {
+  for (int32_t j = t; j <= m + 1; j += BUILD_BLOCK) {
     const int32_t b = f0 - 1 + j;
     const bool ok = b >= 0 && b < last;
     s_delta[j] = ok ? delta(keys, b) : 0ull;
@@ -203,167 +170,146 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
   }
   if (t < m) lv.load(f0 + t, s_leaf[t], s_leafhi[t]);
   s_other[t] = -1;
-  s_left[t] = SENTINEL;
-  s_right[t] = SENTINEL;
   s_end[t] = -1;
-  if (t == 0) s_fix_cnt = 0;
   __syncthreads();
-  // does [l, r] span a whole set? (l - 1 and r are set ends; both in frame)
+  auto D = [&](int32_t b) { return s_delta[b - f0 + 1]; };  // b in [f0-1, f1]
+  // does [l, r] span a whole set? (l - 1 and r are set ends)
   auto spans = [&](int32_t l, int32_t r) { return s_cut[l - f0] && s_cut[r - f0 + 1]; };
   if (t < m) {
-    if (spans(f0 + t, f0 + t)) set_root[set_of(keys, f0 + t, set_shift)] = leaf_ref(f0 + t);
+    const int32_t j0 = f0 + t;
+    if (spans(j0, j0)) set_root[set_of(keys, j0, set_shift)] = leaf_ref(j0);
     if (n > 1) {
-      int32_t node = leaf_ref(f0 + t), l = f0 + t, r = f0 + t;
+      int32_t l = j0, r = j0, g = -1;  // g: split of the node, -1 for the leaf
       float4 lo = s_leaf[t], hi = s_leafhi[t];
       for (;;) {
-        const bool is_left =
-            (l == 0) || (r != last && s_delta[r - f0 + 1] < s_delta[l - 1 - f0 + 1]);
+        const bool is_left = left_side(l, r, last, D(r), D(l - 1));
+        if (g >= 0) {  // finished here: its number is known now
+          const int32_t k = (is_left ? r : l) - f0;
+          s_lo[k] = lo;
+          s_hi[k] = hi;
+          s_left[k] = left_ref(l, g);
+          s_end[k] = r;
+          if (spans(l, r)) set_root[set_of(keys, l, set_shift)] = k + f0;
+        }
         const int32_t par = is_left ? r : l - 1;
         if (par < f0 || par > f1 - 2) {  // frame edge: hand over to level 2
-          pend_out[size_t(blockIdx.x) * 2 + (is_left ? 1 : 0)] = make_int4(node, l, r, 0);
+          const int32_t ref = g < 0 ? leaf_ref(l) : (is_left ? r : l);
+          pend_out[size_t(blockIdx.x) * 2 + (is_left ? 1 : 0)] = make_int4(ref, l, r, 0);
           break;
         }
         const int32_t k = par - f0;
-        if (is_left) s_left[k] = node;
-        else s_right[k] = node;
         const int32_t bound = __hip_atomic_exchange(s_other + k, is_left ? l : r,
                                                     __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (bound < 0) break;
-        int32_t sib;
-        if (is_left) { r = bound; sib = s_right[k]; }
-        else { l = bound; sib = s_left[k]; }
-        const int32_t si = is_leaf(sib) ? leaf_index(sib) - f0 : sib - f0;
-        if (si < 0 || si >= m || l > r) { atomicOr(err, STATUS_TREE); break; }
-        const float4 slo = is_leaf(sib) ? s_leaf[si] : s_lo[si];
-        const float4 shi = is_leaf(sib) ? s_leafhi[si] : s_hi[si];
-        lo.x = fminf(lo.x, slo.x); lo.y = fminf(lo.y, slo.y); lo.z = fminf(lo.z, slo.z);
-        hi.x = fmaxf(hi.x, shi.x); hi.y = fmaxf(hi.y, shi.y); hi.z = fmaxf(hi.z, shi.z);
-        s_lo[k] = lo;
-        s_hi[k] = hi;
-        s_end[k] = r;
-        node = par;
-        if (spans(l, r)) set_root[set_of(keys, l, set_shift)] = par;
-        if (l == 0 && r == last) break;
-      }
-    }
-  }
-  __syncthreads();
-  // Write out split f0 + t (internal node) and leaf f0 + t with their ropes
-  // where right(r) is known here; the frame's right edge split only resets
-  // its exchange slot for the next level.
-  const int32_t p = f0 + t;
-  // right child of split q if it was finished in this frame, else -2
-  auto known_right = [&](int32_t q) -> int32_t {
-    if (q == last || s_cut[q - f0 + 1]) return SENTINEL;  // right-most path of the set
-    if (q < f0 || q > f1 - 2) return -2;
-    return s_right[q - f0] != SENTINEL ? s_right[q - f0] : -2;
-  };
-  bool fix_leaf = false, fix_node = false;
-  int32_t node_end = -1;
-  if (t < m && n > 1) {
-    const int32_t lr = known_right(p);
-    lv.write_out(p, s_leaf[t], s_leafhi[t], lr == -2 ? SENTINEL : lr);
-    fix_leaf = lr == -2;
-    if (p < last) {
-      if (t == m - 1) {
-        other[p] = -1;
-      } else {
-        other[p] = s_other[t];
-        if (s_right[t] != SENTINEL) right[p] = s_right[t];
-        if (s_end[t] >= 0) {
-          node_end = s_end[t];
-          const int32_t nr = known_right(node_end);
-          fix_node = nr == -2;
-          const float4 lo = s_lo[t], hi = s_hi[t];
-          reinterpret_cast<float4*>(nodes + p)[0] =
-              make_float4(lo.x, lo.y, lo.z, __int_as_float(s_left[t]));
-          reinterpret_cast<float4*>(nodes + p)[1] =
-              make_float4(hi.x, hi.y, hi.z, __int_as_float(nr == -2 ? SENTINEL : nr));
-        } else if (s_left[t] != SENTINEL) {
-          nodes[p].left = s_left[t];
+        if (bound < 0) break;  // first arrival: the sibling finishes the parent
+        s_other[k] = -2;
+        if (is_left) r = bound;
+        else l = bound;
+        // the sibling: the other child of split par, [par+1, r] or [l, par]
+        const int32_t sl = is_left ? par + 1 : l, sr = is_left ? r : par;
+        if (sl < f0 || sr > f1 - 1 || sl > sr) { atomicOr(err, STATUS_TREE); break; }
+        if (sl == sr) {
+          grow(lo, hi, s_leaf[sl - f0], s_leafhi[sl - f0]);
+        } else {
+          const int32_t sk = (is_left ? sl : sr) - f0;  // right child: first leaf; left: last
+          grow(lo, hi, s_lo[sk], s_hi[sk]);
+        }
+        g = par;
+        if (l == 0 && r == last) {  // the root, number 0: this frame holds every leaf
+          s_lo[0] = lo;
+          s_hi[0] = hi;
+          s_left[0] = left_ref(l, g);
+          s_end[0] = r;
+          if (spans(l, r)) set_root[set_of(keys, l, set_shift)] = 0;
+          break;
         }
       }
     }
   }
-  int2* mine = fix_frame + size_t(blockIdx.x) * FIX_PER_FRAME;
-  wave_append(mine, &s_fix_cnt, fix_leaf, make_int2(leaf_ref(p), p));
-  wave_append(mine, &s_fix_cnt, fix_node, make_int2(p, node_end));
   __syncthreads();
-  if (t == 0) fix_cnt[blockIdx.x] = s_fix_cnt;  // later levels add to it
+  // leaf f0+t and node number f0+t, whole, with their ropes; the exchange
+  // slot of split f0+t unless it is finished (the frame's right edge split
+  // is never touched here: -1)
+  const int32_t p = f0 + t;
+  if (t < m && n > 1) {
+    lv.write_out(p, s_leaf[t], s_leafhi[t], rope_of(p, last, s_cut[t + 1], D(p), D(p + 1)));
+    const int32_t r = s_end[t];
+    if (r >= 0)
+      write_node(nodes, p, s_lo[t], s_hi[t], s_left[t],
+                 rope_of(r, last, s_cut[r - f0 + 1], D(r), D(r + 1)));
+    if (p < last && s_other[t] != -2) other[p] = s_other[t];
+  }
 }
 
 // Levels k > 1 of the build: thread = one of the 2 * 128 nodes handed up by
-// the 128 level-(k-1) frames inside this block's frame.  nodes/right/other
+// the 128 level-(k-1) frames inside this block's frame.  nodes and other
 // are written and read by different threads of the same launch, ordered by
 // the exchange: no __restrict__ on them.
 template <class Leaves>
 __global__ __launch_bounds__(BUILD_BLOCK) void k_build_level(
     const uint64_t* __restrict__ keys, Leaves lv, uint32_t n, int level, int set_shift,
-    Node* nodes, int32_t* right, int32_t* other, int32_t* set_root,
-    const int4* __restrict__ pend_in, int4* __restrict__ pend_out, int2* fix_frame,
-    uint32_t* fix_cnt, uint32_t* err) {
-  const FixList fx{fix_frame, fix_cnt, err};
+    Node* nodes, int32_t* other, int32_t* set_root, const int4* __restrict__ pend_in,
+    int4* __restrict__ pend_out, uint32_t* err) {
   const int32_t last = int32_t(n) - 1;
   const uint64_t frame = uint64_t(BUILD_LEAVES) << (BUILD_FANOUT_LOG2 * (level - 1));
   const int64_t f0 = int64_t(blockIdx.x) * int64_t(frame);
   const int64_t f1 = min(f0 + int64_t(frame), int64_t(n));
-  int32_t node, l, r;
-  float lox, loy, loz, hix, hiy, hiz;
-  {
-    const int4 e = pend_in[size_t(blockIdx.x) * BUILD_BLOCK + threadIdx.x];
-    node = e.x;
-    if (node == SENTINEL) return;
-    l = e.y;
-    r = e.z;
-    if (is_leaf(node)) {
-      float4 ql, qh;
-      lv.load(leaf_index(node), ql, qh);
-      lox = ql.x; loy = ql.y; loz = ql.z; hix = qh.x; hiy = qh.y; hiz = qh.z;
-    } else {
-      const Node& nd = nodes[node];
-      lox = nd.lox; loy = nd.loy; loz = nd.loz; hix = nd.hix; hiy = nd.hiy; hiz = nd.hiz;
-    }
-  }
-  for (;;) {
-    const bool is_left = (l == 0) || (r != last && delta(keys, r) < delta(keys, l - 1));
-    const int32_t par = is_left ? r : l - 1;
-    if (par < f0 || par > f1 - 2) {
-      // the split is a frame edge: hand the node to the next level
-      pend_out[size_t(blockIdx.x) * 2 + (is_left ? 1 : 0)] = make_int4(node, l, r, 0);
-      return;
-    }
-    if (!climb_step(lv, nodes, right, other, fx, err, keys, set_shift, set_root, last,
-                    is_left, par, node, l, r, lox, loy, loz, hix, hiy, hiz))
-      return;
-    if (l == 0 && r == last) return;
-  }
-}
-
-// One wave per level-1 frame: set the ropes of the frame's fix-up entries.
-template <class Leaves>
-__global__ __launch_bounds__(256) void k_ropes(Node* __restrict__ nodes, Leaves lv,
-                                              const uint64_t* __restrict__ keys, int set_shift,
-                                              const int32_t* __restrict__ right,
-                                              const int2* __restrict__ fix_frame,
-                                              const uint32_t* __restrict__ fix_cnt, uint32_t n,
-                                              uint32_t* __restrict__ err) {
-  const uint32_t frames = (n + BUILD_LEAVES - 1) / BUILD_LEAVES;
-  const uint32_t f = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-  if (f >= frames) return;
-  const uint32_t count = min(fix_cnt[f], uint32_t(FIX_PER_FRAME));
-  const int2* list = fix_frame + size_t(f) * FIX_PER_FRAME;
-  const int32_t last = int32_t(n) - 1;
   const uint64_t mask = set_mask_of(set_shift);
-  for (uint32_t k = threadIdx.x & 63; k < count; k += 64) {
-    const int2 e = list[k];
-    int32_t r = e.y;
-    if (r < 0 || r > last) {  // only if the build failed
-      atomicOr(err, STATUS_TREE);
-      r = last;
+  const int4 e = pend_in[size_t(blockIdx.x) * BUILD_BLOCK + threadIdx.x];
+  int32_t ref = e.x, l = e.y, r = e.z, g = -1;
+  if (ref == SENTINEL) return;
+  float4 lo, hi;
+  if (is_leaf(ref)) {
+    lv.load(leaf_index(ref), lo, hi);
+  } else {
+    const float4* q = reinterpret_cast<const float4*>(nodes + ref);
+    lo = q[0];
+    hi = q[1];
+  }
+  auto spans = [&](int32_t a, int32_t b) {
+    return (a == 0 || set_cut(keys, a - 1, mask)) && (b == last || set_cut(keys, b, mask));
+  };
+  for (;;) {
+    const bool is_left = left_side(l, r, last, r != last ? delta(keys, r) : 0ull,
+                                   l > 0 ? delta(keys, l - 1) : 0ull);
+    if (g >= 0) {  // finished in this launch: write it under its number
+      ref = is_left ? r : l;
+      const bool cut = r != last && set_cut(keys, r, mask);
+      const uint64_t d_r = r != last ? delta(keys, r) : 0ull;
+      const uint64_t d_r1 = r + 1 < last ? delta(keys, r + 1) : 0ull;
+      write_node(nodes, ref, lo, hi, left_ref(l, g), rope_of(r, last, cut, d_r, d_r1));
+      if (spans(l, r)) set_root[set_of(keys, l, set_shift)] = ref;
+      g = -1;
     }
-    const int32_t rope = (r == last || set_cut(keys, r, mask)) ? SENTINEL : right[r];
-    if (is_leaf(e.x)) lv.set_rope(leaf_index(e.x), rope);
-    else nodes[e.x].rope = rope;
+    const int32_t par = is_left ? r : l - 1;
+    if (par < f0 || par > f1 - 2) {  // the split is a frame edge: to the next level
+      pend_out[size_t(blockIdx.x) * 2 + (is_left ? 1 : 0)] = make_int4(ref, l, r, 0);
+      return;
+    }
+    const int32_t bound = __hip_atomic_exchange(other + par, is_left ? l : r, __ATOMIC_ACQ_REL,
+                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (bound < 0) return;  // first arrival
+    if (is_left) r = bound;
+    else l = bound;
+    const int32_t sl = is_left ? par + 1 : l, sr = is_left ? r : par;
+    if (sl < 0 || sr > last || sl > sr || l > par || par >= r) {
+      atomicOr(err, STATUS_TREE);
+      return;
+    }
+    float4 slo, shi;
+    if (sl == sr) {
+      lv.load(sl, slo, shi);
+    } else {
+      const float4* q = reinterpret_cast<const float4*>(nodes + (is_left ? sl : sr));
+      slo = q[0];
+      shi = q[1];
+    }
+    grow(lo, hi, slo, shi);
+    g = par;
+    if (l == 0 && r == last) {  // the root, number 0
+      write_node(nodes, 0, lo, hi, left_ref(l, g), SENTINEL);
+      if (spans(l, r)) set_root[set_of(keys, l, set_shift)] = 0;
+      return;
+    }
   }
 }
 
@@ -395,9 +341,8 @@ size_t build_pending_entries(uint32_t n) {
 namespace {
 template <class Leaves>
 void build_impl(const uint64_t* keys, int set_shift, Leaves lv, uint32_t n, Node* nodes,
-                int32_t* right, int32_t* other, int32_t* root, int4* pending, int2* fixups,
-                uint32_t* fix_cnt, uint32_t* err, hipStream_t s, void (*after_level)(void*, int),
-                void* arg) {
+                int32_t* other, int32_t* root, int4* pending, uint32_t* err, hipStream_t s,
+                void (*after_level)(void*, int), void* arg) {
   if (n == 0) return;
   const int levels = build_levels(n);
   uint64_t frame = BUILD_LEAVES;
@@ -407,11 +352,10 @@ void build_impl(const uint64_t* keys, int set_shift, Leaves lv, uint32_t n, Node
     const uint32_t frames = uint32_t((n + frame - 1) / frame);
     if (lv_i == 1)
       hipLaunchKernelGGL(k_build_frame<Leaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys, lv,
-                         n, set_shift, nodes, right, other, root, pout, fixups, fix_cnt, err);
+                         n, set_shift, nodes, other, root, pout, err);
     else
       hipLaunchKernelGGL(k_build_level<Leaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys, lv,
-                         n, lv_i, set_shift, nodes, right, other, root, pin, pout, fixups,
-                         fix_cnt, err);
+                         n, lv_i, set_shift, nodes, other, root, pin, pout, err);
     if (after_level) after_level(arg, lv_i);
     pin = pout;
     pout += level_region(frames);
@@ -419,42 +363,20 @@ void build_impl(const uint64_t* keys, int set_shift, Leaves lv, uint32_t n, Node
   }
 }
 
-template <class Leaves>
-void ropes_impl(Node* nodes, Leaves lv, const uint64_t* keys, int set_shift,
-                const int32_t* right, const int2* fixups, const uint32_t* fix_cnt, uint32_t n,
-                uint32_t* err, hipStream_t s) {
-  if (n < 2) return;
-  const uint32_t frames = (n + BUILD_LEAVES - 1) / BUILD_LEAVES;
-  hipLaunchKernelGGL(k_ropes<Leaves>, dim3((frames + 3) / 4), dim3(256), 0, s, nodes, lv, keys,
-                     set_shift, right, fixups, fix_cnt, n, err);
-}
 }  // namespace
 
 void launch_build(const uint64_t* keys, int set_shift, float4* leaf, uint32_t n, Node* nodes,
-                  int32_t* right, int32_t* other, int32_t* set_root, int4* pending,
-                  int2* fixups, uint32_t* fix_cnt, uint32_t* err, hipStream_t s,
+                  int32_t* other, int32_t* set_root, int4* pending, uint32_t* err, hipStream_t s,
                   void (*after_level)(void*, int), void* arg) {
-  build_impl(keys, set_shift, PointLeaves{leaf}, n, nodes, right, other, set_root, pending,
-             fixups, fix_cnt, err, s, after_level, arg);
+  build_impl(keys, set_shift, PointLeaves{leaf}, n, nodes, other, set_root, pending, err, s,
+             after_level, arg);
 }
 
 void launch_build_boxes(const uint64_t* keys, Node* prims, uint32_t n, Node* nodes,
-                        int32_t* right, int32_t* other, int32_t* root, int4* pending,
-                        int2* fixups, uint32_t* fix_cnt, uint32_t* err, hipStream_t s) {
-  build_impl(keys, 64, BoxLeaves{prims}, n, nodes, right, other, root, pending, fixups, fix_cnt,
-             err, s, nullptr, nullptr);
-}
-
-void launch_ropes(const uint64_t* keys, int set_shift, Node* nodes, float4* leaf,
-                  const int32_t* right, const int2* fixups, const uint32_t* fix_cnt, uint32_t n,
-                  uint32_t* err, hipStream_t s) {
-  ropes_impl(nodes, PointLeaves{leaf}, keys, set_shift, right, fixups, fix_cnt, n, err, s);
-}
-
-void launch_ropes_boxes(const uint64_t* keys, Node* nodes, Node* prims, const int32_t* right,
-                        const int2* fixups, const uint32_t* fix_cnt, uint32_t n, uint32_t* err,
+                        int32_t* other, int32_t* root, int4* pending, uint32_t* err,
                         hipStream_t s) {
-  ropes_impl(nodes, BoxLeaves{prims}, keys, 64, right, fixups, fix_cnt, n, err, s);
+  build_impl(keys, 64, BoxLeaves{prims}, n, nodes, other, root, pending, err, s, nullptr,
+             nullptr);
 }
 
 }  // namespace dbx

@@ -118,29 +118,6 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ pts, u
   }
 }
 
-// spread the low 21 bits of v to every third bit of a 64-bit word
-__device__ __forceinline__ uint64_t spread3(uint32_t v) {
-  uint64_t x = v & 0x1fffffu;
-  x = (x | (x << 32)) & 0x001f00000000ffffull;
-  x = (x | (x << 16)) & 0x001f0000ff0000ffull;
-  x = (x | (x << 8)) & 0x100f00f00f00f00full;
-  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
-  x = (x | (x << 2)) & 0x1249249249249249ull;
-  return x;
-}
-
-__device__ __forceinline__ uint32_t quantise(float p, float lo, float s) {
-#pragma clang fp contract(off)
-  float t = (p - lo) * s;
-  t = fminf(fmaxf(floorf(t), 0.0f), float((1u << MORTON_BITS) - 1));  // NaN -> 0
-  return uint32_t(t);
-}
-
-__device__ __forceinline__ uint64_t morton_of(float x, float y, float z, const float* lo,
-                                              const float* s) {
-  return (spread3(quantise(x, lo[0], s[0])) << 2) | (spread3(quantise(y, lo[1], s[1])) << 1) |
-         spread3(quantise(z, lo[2], s[2]));
-}
 
 __device__ __forceinline__ void count_digits(uint32_t* sh, uint64_t code) {
 #pragma unroll
@@ -157,13 +134,8 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
                                                uint32_t* __restrict__ hist) {
   __shared__ uint32_t sh[SORT_PASSES * RADIX];
   for (int t = threadIdx.x; t < SORT_PASSES * RADIX; t += blockDim.x) sh[t] = 0;
-  float lo[3], s[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = ord2f(bounds[a]);
-    float ext = ord2f(bounds[3 + a]) - lo[a];
-    s[a] = ext > 0.0f ? float(1u << MORTON_BITS) / ext : 0.0f;  // IEEE division
-  }
+  MortonGrid grid;
+  grid.load(bounds);
   __syncthreads();
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -173,10 +145,10 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
     const float4* p4 = reinterpret_cast<const float4*>(pts);
     ulonglong2* k2 = reinterpret_cast<ulonglong2*>(keys);
     auto code4 = [&](uint32_t g, const float4& a, const float4& b, const float4& c) {
-      const uint64_t c0 = morton_of(a.x, a.y, a.z, lo, s);
-      const uint64_t c1 = morton_of(a.w, b.x, b.y, lo, s);
-      const uint64_t c2 = morton_of(b.z, b.w, c.x, lo, s);
-      const uint64_t c3 = morton_of(c.y, c.z, c.w, lo, s);
+      const uint64_t c0 = grid.code(a.x, a.y, a.z);
+      const uint64_t c1 = grid.code(a.w, b.x, b.y);
+      const uint64_t c2 = grid.code(b.z, b.w, c.x);
+      const uint64_t c3 = grid.code(c.y, c.z, c.w);
       k2[2 * size_t(g)] = make_ulonglong2(c0, c1);
       k2[2 * size_t(g) + 1] = make_ulonglong2(c2, c3);
       count_digits(sh, c0);
@@ -201,7 +173,7 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
   }
   for (uint32_t i = first_scalar + gid; i < n; i += stride) {
     const float* p = pts + size_t(3) * i;
-    const uint64_t code = morton_of(p[0], p[1], p[2], lo, s);
+    const uint64_t code = grid.code(p[0], p[1], p[2]);
     keys[i] = code;
     count_digits(sh, code);
   }

@@ -77,57 +77,45 @@ constexpr int BUILD_LEAVES = 256;        // leaves per level-1 frame
 constexpr int BUILD_FANOUT_LOG2 = 7;     // frames per next-level frame: 128
 constexpr int BUILD_BLOCK = 256;         // = BUILD_LEAVES = 2 << BUILD_FANOUT_LOG2
 static_assert(BUILD_BLOCK == BUILD_LEAVES && BUILD_BLOCK == (2 << BUILD_FANOUT_LOG2), "");
-constexpr int FIX_PER_FRAME = 2 * BUILD_LEAVES;  // fix-up entries per level-1 frame
 int build_levels(uint32_t n);
-inline uint32_t build_frames(uint32_t n) { return (n + BUILD_LEAVES - 1) / BUILD_LEAVES; }
-// int2 entries of the fix-up list (FIX_PER_FRAME per level-1 frame)
-inline size_t build_fix_entries(uint32_t n) { return size_t(build_frames(n)) * FIX_PER_FRAME; }
 // int4 entries of hand-over state the build needs (all levels), -1 filled
 size_t build_pending_entries(uint32_t n);
-// right[k]: right child of internal node k; other[k]: exchange slot (set
-// up by the build itself).  The build also sets every rope it can resolve
-// inside a level-1 frame; the others go on the fix-up list `fixups`
-// (build_fix_entries(n) entries: node reference, last leaf under it) with
-// one count per level-1 frame in fix_cnt[build_frames(n)] (set by the build).
-// Keys may carry a set id in bits [set_shift, 64) (batched sets; 64 = a
-// single set): ropes are then cut at set ends and set_root[s] receives the
-// root of set s's subtree (for a single set, set_root[0] = the root).
-// `after_level(arg, lv)`, if given, is called after level lv is enqueued.
+// Internal nodes in Karras' order (root = number 0), every leaf's and
+// node's rope set.  other[k] (n - 1 words): exchange slots, set up by the
+// build itself.  Keys may carry a set id in bits [set_shift, 64) (batched
+// sets; 64 = a single set): ropes are then cut at set ends and set_root[s]
+// receives the root of set s's subtree (for a single set, set_root[0] = the
+// root).  `after_level(arg, lv)`, if given, is called after level lv is
+// enqueued.
 void launch_build(const uint64_t* keys, int set_shift, float4* leaf, uint32_t n, Node* nodes,
-                  int32_t* right, int32_t* other, int32_t* set_root, int4* pending,
-                  int2* fixups, uint32_t* fix_cnt, uint32_t* err, hipStream_t s,
+                  int32_t* other, int32_t* set_root, int4* pending, uint32_t* err, hipStream_t s,
                   void (*after_level)(void*, int) = nullptr, void* arg = nullptr);
-// Sets the ropes of the nodes on the fix-up list.
-void launch_ropes(const uint64_t* keys, int set_shift, Node* nodes, float4* leaf,
-                  const int32_t* right, const int2* fixups, const uint32_t* fix_cnt, uint32_t n,
-                  uint32_t* err, hipStream_t s);
 // The same over box leaves (DenseBox primitives: Node records, payload in
 // `left`, rope in `rope`), single set.
 void launch_build_boxes(const uint64_t* keys, Node* prims, uint32_t n, Node* nodes,
-                        int32_t* right, int32_t* other, int32_t* root, int4* pending,
-                        int2* fixups, uint32_t* fix_cnt, uint32_t* err, hipStream_t s);
-void launch_ropes_boxes(const uint64_t* keys, Node* nodes, Node* prims, const int32_t* right,
-                        const int2* fixups, const uint32_t* fix_cnt, uint32_t n, uint32_t* err,
+                        int32_t* other, int32_t* root, int4* pending, uint32_t* err,
                         hipStream_t s);
 
 // ---- traversals (traverse.hip) ---------------------------------------------
-void launch_count(const Node* nodes, const float4* leaf, uint32_t n,
-                  const int32_t* root, float e2, int32_t min_pts,
-                  uint8_t* is_core, uint32_t* err, int block, hipStream_t s);
+// keys: the sorted Morton codes; bounds: the scene bounds words they were
+// made with (both for the walks' early end).
+void launch_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
+                  const uint32_t* bounds, uint32_t n, const int32_t* root, float e2,
+                  int32_t min_pts, uint8_t* is_core, uint32_t* err, int block, hipStream_t s);
 // minPts <= 2: every point with a neighbour is core; union every pair.
-void launch_pairs_fof(const Node* nodes, const float4* leaf, uint32_t n,
-                      float e2, int32_t* parent, uint8_t* member, uint32_t* err,
-                      int block, hipStream_t s);
+void launch_pairs_fof(const Node* nodes, const float4* leaf, const uint64_t* keys,
+                      const uint32_t* bounds, uint32_t n, float e2, int32_t* parent,
+                      uint8_t* member, uint32_t* err, int block, hipStream_t s);
 // minPts > 2: union core pairs, record each non-core point's smallest-index
 // core neighbour.
-void launch_pairs_core(const Node* nodes, const float4* leaf, uint32_t n,
-                       float e2, const uint8_t* is_core, const uint32_t* perm,
-                       int32_t* parent, unsigned long long* bestcore,
+void launch_pairs_core(const Node* nodes, const float4* leaf, const uint64_t* keys,
+                       const uint32_t* bounds, uint32_t n, float e2, const uint8_t* is_core,
+                       const uint32_t* perm, int32_t* parent, unsigned long long* bestcore,
                        uint32_t* err, int block, hipStream_t s);
 // Pair traversal with F(i, j) = count: every pair exactly once.
-void launch_pairs_count(const Node* nodes, const float4* leaf, uint32_t n,
-                        float e2, unsigned long long* count, uint32_t* err,
-                        int block, hipStream_t s);
+void launch_pairs_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
+                        const uint32_t* bounds, uint32_t n, float e2, unsigned long long* count,
+                        uint32_t* err, int block, hipStream_t s);
 
 // ---- labels (finalize.hip) --------------------------------------------------
 // 1) cluster root per point (written over parent; -1 = noise), the

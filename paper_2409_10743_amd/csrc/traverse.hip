@@ -22,10 +22,18 @@ namespace {
 
 // counting: walk from the root, stop at minPts neighbours
 struct CountCore {
+  static constexpr bool kBounded = true;
   int32_t root, min_pts, cnt;
   float r2;
   uint8_t* is_core;
-  __device__ int32_t begin(uint32_t, const float4&) { cnt = 0; return root; }
+  MortonGrid grid;
+  uint64_t hi;
+  __device__ int32_t begin(uint32_t, const float4& q) {
+    cnt = 0;
+    hi = grid.upper_code(q, r2);
+    return root;
+  }
+  __device__ uint64_t khi() const { return hi; }
   __device__ float e2() const { return r2; }
   __device__ void visit(bool, bool) {}
   __device__ bool hit(uint32_t, int32_t, const float4&) { return ++cnt >= min_pts; }
@@ -33,11 +41,12 @@ struct CountCore {
 };
 
 __global__ void k_count(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
-                        uint32_t n, WalkCfg wc,
-                        const int32_t* __restrict__ root, float e2, int32_t min_pts,
-                        uint8_t* __restrict__ is_core, uint32_t* err) {
-  CountCore v{*root, min_pts, 0, e2, is_core};
-  wave_walks(nodes, leaf, n, wc, v, err);
+                        const uint64_t* __restrict__ keys, const uint32_t* __restrict__ bounds,
+                        uint32_t n, WalkCfg wc, const int32_t* __restrict__ root, float e2,
+                        int32_t min_pts, uint8_t* __restrict__ is_core, uint32_t* err) {
+  CountCore v{*root, min_pts, 0, e2, is_core, {}, 0};
+  v.grid.load(bounds);
+  wave_walks(nodes, leaf, keys, n, wc, v, err);
 }
 
 enum PairMode { FOF = 0, CORE = 1, COUNT = 2 };
@@ -45,6 +54,7 @@ enum PairMode { FOF = 0, CORE = 1, COUNT = 2 };
 // pair traversal: query i starts at its own leaf's rope (leaves j > i only)
 template <int MODE>
 struct PairVisit {
+  static constexpr bool kBounded = true;
   float r2;
   const uint8_t* is_core;
   const uint32_t* perm;
@@ -54,8 +64,12 @@ struct PairVisit {
   bool ci, found;
   uint32_t pairs, visits, descents, leaves;  // COUNT only: this query's counts
   unsigned long long tot[4];                 // COUNT only: this lane's totals
+  MortonGrid grid;
+  uint64_t hi;
+  __device__ uint64_t khi() const { return hi; }
   __device__ int32_t begin(uint32_t i, const float4& q) {
     found = false;
+    hi = grid.upper_code(q, r2);
     if (MODE == COUNT) pairs = visits = descents = leaves = 0;
     if (MODE == CORE) ci = is_core[i] != 0;
     return __float_as_int(q.w);
@@ -103,13 +117,15 @@ __device__ __forceinline__ void wave_add(unsigned long long* dst, unsigned long 
 
 template <int MODE>
 __global__ void k_pairs(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
+                        const uint64_t* __restrict__ keys, const uint32_t* __restrict__ bounds,
                         uint32_t n, WalkCfg wc, float e2,
                         const uint8_t* __restrict__ is_core, const uint32_t* __restrict__ perm,
                         int32_t* parent, uint8_t* member, unsigned long long* bestcore,
                         unsigned long long* count, uint32_t* err) {
   PairVisit<MODE> v{e2, is_core, perm, parent, member, bestcore, true, false, 0, 0, 0, 0,
-                    {0, 0, 0, 0}};
-  wave_walks(nodes, leaf, n, wc, v, err);
+                    {0, 0, 0, 0}, {}, 0};
+  v.grid.load(bounds);
+  wave_walks(nodes, leaf, keys, n, wc, v, err);
   if (MODE == COUNT) {  // pairs, internal visits, descents, leaf tests
     wave_add(count, v.tot[0]);
     wave_add(count + 1, v.tot[1]);
@@ -139,35 +155,40 @@ uint32_t walk_refill_at() {
   return r;
 }
 
-void launch_count(const Node* nodes, const float4* leaf, uint32_t n, const int32_t* root,
-                  float e2, int32_t min_pts, uint8_t* is_core, uint32_t* err, int block,
-                  hipStream_t s) {
+void launch_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
+                  const uint32_t* bounds, uint32_t n, const int32_t* root, float e2,
+                  int32_t min_pts, uint8_t* is_core, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_count, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf, n,
-                     walk_cfg(n), root,
-                     e2, min_pts, is_core, err);
+  hipLaunchKernelGGL(k_count, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf, keys,
+                     bounds, n, walk_cfg(n), root, e2, min_pts, is_core, err);
 }
 
-void launch_pairs_fof(const Node* nodes, const float4* leaf, uint32_t n, float e2,
-                      int32_t* parent, uint8_t* member, uint32_t* err, int block, hipStream_t s) {
+void launch_pairs_fof(const Node* nodes, const float4* leaf, const uint64_t* keys,
+                      const uint32_t* bounds, uint32_t n, float e2, int32_t* parent,
+                      uint8_t* member, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_pairs<FOF>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf, n,
-                     walk_cfg(n), e2, nullptr, nullptr, parent, member, nullptr, nullptr, err);
+  hipLaunchKernelGGL(k_pairs<FOF>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
+                     keys, bounds, n, walk_cfg(n), e2, nullptr, nullptr, parent, member, nullptr,
+                     nullptr, err);
 }
 
-void launch_pairs_core(const Node* nodes, const float4* leaf, uint32_t n, float e2,
-                       const uint8_t* is_core, const uint32_t* perm, int32_t* parent,
-                       unsigned long long* bestcore, uint32_t* err, int block, hipStream_t s) {
+void launch_pairs_core(const Node* nodes, const float4* leaf, const uint64_t* keys,
+                       const uint32_t* bounds, uint32_t n, float e2, const uint8_t* is_core,
+                       const uint32_t* perm, int32_t* parent, unsigned long long* bestcore,
+                       uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_pairs<CORE>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf, n,
-                     walk_cfg(n), e2, is_core, perm, parent, nullptr, bestcore, nullptr, err);
+  hipLaunchKernelGGL(k_pairs<CORE>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
+                     keys, bounds, n, walk_cfg(n), e2, is_core, perm, parent, nullptr, bestcore,
+                     nullptr, err);
 }
 
-void launch_pairs_count(const Node* nodes, const float4* leaf, uint32_t n, float e2,
-                        unsigned long long* count, uint32_t* err, int block, hipStream_t s) {
+void launch_pairs_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
+                        const uint32_t* bounds, uint32_t n, float e2, unsigned long long* count,
+                        uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<COUNT>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     n, walk_cfg(n), e2, nullptr, nullptr, nullptr, nullptr, nullptr, count, err);
+                     keys, bounds, n, walk_cfg(n), e2, nullptr, nullptr, nullptr, nullptr,
+                     nullptr, count, err);
 }
 
 }  // namespace dbx

@@ -11,8 +11,17 @@
 // point's squared distance), so the lanes of a wave never split into a leaf
 // path and a node path, each paying its own memory latency.
 //
+// Early end.  Internal nodes are in Karras' order, so the node a rope leads
+// to has its first leaf's number, and the walk, going right, meets leaves
+// in increasing order.  Every neighbour's Morton code is at most
+// khi = MortonGrid::upper_code(q): once a rope leads to a subtree whose
+// first key exceeds khi, no leaf left in the walk can be a neighbour, and
+// it ends.  (The first key is read with the node, in the same step.)
+//
 // The visitor V holds the per-lane state of the lane's current query:
 //   int32_t begin(uint32_t i, const float4& q)  first node of query i
+//   uint64_t khi() const                        the early-end bound (all
+//                                               ones: never end early)
 //   float   e2() const                          squared radius (this query)
 //   void    visit(bool leaf, bool near)         every step (statistics)
 //   bool    hit(uint32_t i, int32_t j, const float4& q)
@@ -79,9 +88,11 @@ inline WalkCfg walk_cfg(uint32_t n) { return WalkCfg{walk_chunk_size(n), walk_re
 
 // `leaf` must have one readable float4 past leaf n-1 (a leaf step reads 32
 // bytes, like a node step, and ignores the second half).
+// keys: the sorted Morton codes (read only when V::kBounded).
 template <class V>
 __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
-                                           const float4* __restrict__ leaf, uint32_t n,
+                                           const float4* __restrict__ leaf,
+                                           const uint64_t* __restrict__ keys, uint32_t n,
                                            WalkCfg wc, V& v, uint32_t* err) {
   uint32_t c0, c1;
   walk_chunk(n, wc.chunk, c0, c1);
@@ -93,6 +104,7 @@ __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
   bool have = false;   // lane holds query i whose end() is still due
   int32_t node = SENTINEL;
   uint32_t steps = 0;
+  bool by_rope = true;  // node was reached through a rope (or is the start)
   float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
   for (;;) {
     // hand the chunk's next queries to the idle lanes
@@ -107,6 +119,7 @@ __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
         q = leaf[i];
         node = v.begin(i, q);
         steps = 0;
+        by_rope = true;
       }
     }
     const uint32_t h = head + uint32_t(__popcll(m));
@@ -134,13 +147,23 @@ __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
                              : reinterpret_cast<const float4*>(nodes + node);
       const float4 a = p[0], p1 = p[1];
       const float4 b = lf ? a : p1;
+      if (V::kBounded) {  // a rope target's number is its first leaf
+        const uint32_t first = lf ? uint32_t(leaf_index(node)) : uint32_t(node);
+        const uint64_t kf = keys[act && by_rope ? first : 0u];
+        if (act && by_rope && kf > v.khi()) {
+          node = SENTINEL;
+          act = false;
+        }
+      }
       if (act) {
         const bool near = box_sq_dist4(q, a, b) <= v.e2();
         v.visit(lf, near);
         // internal: left child (a.w) or rope (b.w); leaf: its rope (a.w = b.w)
-        int32_t next = (near && !lf) ? __float_as_int(a.w) : __float_as_int(b.w);
+        const bool down = near && !lf;
+        int32_t next = down ? __float_as_int(a.w) : __float_as_int(b.w);
         if (near && lf && v.hit(i, leaf_index(node), q)) next = SENTINEL;
         node = next;
+        by_rope = !down;
       }
       const uint32_t busy = uint32_t(__popcll(__ballot(node != SENTINEL)));
       if (busy == 0 || (head < c1 && busy < refill_at)) break;

@@ -159,6 +159,28 @@ def test_tree_structure(ctx, n):
             np.testing.assert_array_equal(nodes[k, 4:7], np.maximum(a1, b1))
         np.testing.assert_array_equal(nodes[root, 0:3], p.min(0))
         np.testing.assert_array_equal(nodes[root, 4:7], p.max(0))
+        # Karras order: the root is number 0, and every rope leads to the
+        # subtree starting right after the last leaf of the one it leaves,
+        # numbered (leaf or node) by that first leaf
+        assert root == 0
+        first = np.full(n - 1, -1, np.int64)
+        last = np.full(n - 1, -1, np.int64)
+        order = [s for s in seq if s >= 0]
+        for k in reversed(order):  # children before parents
+            lc = int(left[k])
+            rc = int(lrope[lc & 0x7FFFFFFF]) if lc < -1 else int(rope[lc])
+            first[k] = (lc & 0x7FFFFFFF) if lc < -1 else first[lc]
+            last[k] = (rc & 0x7FFFFFFF) if rc < -1 else last[rc]
+            assert k in (first[k], last[k]) or k == 0
+        for k in range(n - 1):
+            t = int(rope[k])
+            if t != -1:
+                assert (t & 0x7FFFFFFF if t < -1 else t) == last[k] + 1
+                assert t < -1 or first[t] == last[k] + 1
+        for j in range(n):
+            t = int(lrope[j])
+            if t != -1:
+                assert (t & 0x7FFFFFFF if t < -1 else t) == j + 1
 
 
 @pytest.mark.parametrize("n,eps", [(2, 0.5), (4097, 0.03), (50001, 0.02), (300007, 0.01)])
