@@ -64,14 +64,18 @@ struct Layout {
   size_t zero;        // start of the region zeroed by k_prep
   size_t hist, tile_ctr, status, count, sort_status;
   size_t zero_words;  // 32-bit words from `zero`
-  size_t bounds, root;
+  size_t bounds, drop, root;
   size_t total;
 };
 
 Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
   Layout L{};
   size_t o = 0;
-  auto take = [&](size_t bytes) { size_t at = o; o += align_up(std::max<size_t>(bytes, 4)); return at; };
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align_up(std::max<size_t>(bytes, 4));
+    return at;
+  };
   L.keys_a = take(size_t(n) * 8);
   L.keys_b = take(size_t(n) * 8);  // after the sort: union-find scratch of the build
   L.vals_a = take(size_t(n) * 4);
@@ -98,6 +102,7 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
     L.pkey = take(size_t(n) * 8);
   }
   L.bounds = take(8 * 4);
+  L.drop = take(4);
   L.root = take(4);
   // zeroed region: hist | tile counters | status word | pair count | look-back
   L.zero = o;
@@ -201,6 +206,7 @@ struct Index {
   Layout L;
   uint64_t* keys;
   uint32_t* bounds;
+  uint32_t* drop;  // device word: the low code bits the keys cleared
   uint32_t* perm;
   float4* leaf;
   Node* nodes;
@@ -236,7 +242,7 @@ void build_mark(void* arg, int level) {  // level 1 = the frame kernel
 }
 
 int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore, bool timing,
-                hipStream_t s, Index* out) {
+                hipStream_t s, Index* out, float code_eps) {
   Layout L = make_layout(n, need_bestcore);
   int st = ensure_arena(c, L.total);
   if (st != DBSCAN_OK) return st;
@@ -255,15 +261,16 @@ int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore,
   mark(c, timing, PH_PREP, s);
   launch_bounds(pts, n, bounds, status, s);
   mark(c, timing, PH_BOUNDS, s);
-  launch_morton(pts, n, bounds, ka, sc.hist, s);
+  // codes as fine as eps needs (decided on the device: no host round trip)
+  uint32_t* drop = at<uint32_t>(c, L.drop);
+  launch_morton(pts, n, bounds, code_eps, ka, kb, drop, sc.hist, s);
   mark(c, timing, PH_MORTON, s);
   SortMarks sm{c, s};
-  bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, s,
-                                timing ? sort_mark : nullptr, &sm);
-  uint64_t* keys = in_a ? ka : kb;
-  uint32_t* perm = in_a ? va : vb;
+  launch_radix_sort_dropped(ka, kb, va, vb, n, drop, sc, s, timing ? sort_mark : nullptr, &sm);
+  uint64_t* keys = ka;  // where that sort always ends
+  uint32_t* perm = va;
   // the other key buffer is free now: the build's scratch
-  int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
+  int32_t* other = reinterpret_cast<int32_t*>(kb);
   launch_gather(pts, perm, n, at<float4>(c, L.leaf), at<int32_t>(c, L.parent),
                 at<int32_t>(c, L.minlab), at<uint8_t>(c, L.flag),
                 need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr,
@@ -275,6 +282,7 @@ int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore,
   mark(c, timing, PH_BUILD_LEVELS, s);
   out->keys = keys;
   out->bounds = bounds;
+  out->drop = drop;
   out->perm = perm;
   out->leaf = at<float4>(c, L.leaf);
   out->nodes = at<Node>(c, L.nodes);
@@ -316,22 +324,22 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
   const float e2 = eps * eps;
   const bool core_mode = min_pts > 2;
   Index ix;
-  int st = build_index(c, pts, n, core_mode, timing, s, &ix);
+  int st = build_index(c, pts, n, core_mode, timing, s, &ix, eps);
   if (st != DBSCAN_OK) return st;
   const Layout& L = ix.L;
   uint8_t* flag = at<uint8_t>(c, L.flag);
   int32_t* parent = at<int32_t>(c, L.parent);
   unsigned long long* bestcore = core_mode ? at<unsigned long long>(c, L.bestcore) : nullptr;
   if (core_mode)
-    launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, n, ix.root, e2, min_pts, flag,
-                 ix.status, block, s);
+    launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, ix.root, e2, min_pts,
+                 flag, ix.status, block, s);
   mark(c, timing, PH_COUNT, s);
   if (core_mode)
-    launch_pairs_core(ix.nodes, ix.leaf, ix.keys, ix.bounds, n, e2, flag, ix.perm, parent,
-                      bestcore, ix.status, block, s);
+    launch_pairs_core(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, flag,
+                      ix.perm, parent, bestcore, ix.status, block, s);
   else
-    launch_pairs_fof(ix.nodes, ix.leaf, ix.keys, ix.bounds, n, e2, parent, flag, ix.status,
-                     block, s);
+    launch_pairs_fof(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, parent, flag,
+                     ix.status, block, s);
   mark(c, timing, PH_PAIRS, s);
   int32_t* minlab = at<int32_t>(c, L.minlab);
   launch_final_roots(n, min_pts, flag, bestcore, ix.perm, parent, minlab, labels, s);
@@ -754,7 +762,8 @@ int dbscan_morton_codes(dbscan_ctx* c, const float* points, int64_t n, uint64_t*
   uint32_t* status = at<uint32_t>(c, L.status);
   launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, s);
   launch_bounds(points, uint32_t(n), bounds, status, s);
-  launch_morton(points, uint32_t(n), bounds, codes, at<uint32_t>(c, L.hist), s);
+  launch_morton(points, uint32_t(n), bounds, 0.0f, codes, codes, nullptr, at<uint32_t>(c, L.hist),
+                s);
   HIP_TRY(hipGetLastError());
   return finish(c, status, false, s);
 }
@@ -796,12 +805,13 @@ int dbscan_build_tree(dbscan_ctx* c, const float* points, int64_t n, uint32_t* p
   DeviceGuard g(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index ix;
-  st = build_index(c, points, uint32_t(n), false, false, s, &ix);
+  st = build_index(c, points, uint32_t(n), false, false, s, &ix, 0.0f);
   if (st != DBSCAN_OK) return st;
   HIP_TRY(hipMemcpyAsync(perm, ix.perm, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemcpyAsync(leaf, ix.leaf, size_t(n) * 16, hipMemcpyDeviceToDevice, s));
   if (n > 1)
-    HIP_TRY(hipMemcpyAsync(nodes, ix.nodes, size_t(n - 1) * sizeof(Node), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(nodes, ix.nodes, size_t(n - 1) * sizeof(Node),
+                           hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemcpyAsync(root, ix.root, 4, hipMemcpyDeviceToDevice, s));
   return finish(c, ix.status, false, s);
 }
@@ -814,11 +824,11 @@ int dbscan_core_flags(dbscan_ctx* c, const float* points, int64_t n, float eps, 
   DeviceGuard g(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index ix;
-  st = build_index(c, points, uint32_t(n), false, false, s, &ix);
+  st = build_index(c, points, uint32_t(n), false, false, s, &ix, eps);
   if (st != DBSCAN_OK) return st;
   uint8_t* flag = at<uint8_t>(c, ix.L.flag);
-  launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, uint32_t(n), ix.root, eps * eps, min_pts,
-               flag, ix.status, 256, s);
+  launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, uint32_t(n), ix.root,
+               eps * eps, min_pts, flag, ix.status, 256, s);
   launch_scatter_u8(flag, ix.perm, uint32_t(n), core, s);
   HIP_TRY(hipGetLastError());
   return finish(c, ix.status, false, s);
@@ -842,11 +852,11 @@ int dbscan_traversal_stats(dbscan_ctx* c, const float* points, int64_t n, float 
   DeviceGuard g(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index ix;
-  st = build_index(c, points, uint32_t(n), false, false, s, &ix);
+  st = build_index(c, points, uint32_t(n), false, false, s, &ix, eps);
   if (st != DBSCAN_OK) return st;
   unsigned long long* dcount = at<unsigned long long>(c, ix.L.count);
-  launch_pairs_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, uint32_t(n), eps * eps, dcount,
-                     ix.status, 256, s);
+  launch_pairs_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, uint32_t(n),
+                     eps * eps, dcount, ix.status, 256, s);
   unsigned long long* h = reinterpret_cast<unsigned long long*>(c->host_status + 2);
   HIP_TRY(hipMemcpyAsync(h, dcount, 32, hipMemcpyDeviceToHost, s));
   st = finish(c, ix.status, false, s);

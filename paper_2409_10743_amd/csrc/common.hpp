@@ -152,6 +152,28 @@ __host__ __device__ inline float ord2f(uint32_t u) {
   return f;
 }
 
+// Low code bits a clustering call may drop (0, 8, 16 or 24: whole sort
+// passes).  The codes only shape the tree; the walks prune with exact boxes.
+// Codes stay fine enough that a grid cell is at most eps/2 wide on every
+// axis, so points that come to share a code lie within 0.87 eps of each
+// other: mutual neighbours, which the walks meet together anyway.  Bit b of
+// a code belongs to axis z, y, x for b % 3 = 0, 1, 2.  eps <= 0: none.
+__device__ inline int droppable_code_bits(const uint32_t* bounds, float eps) {
+  if (!(eps > 0.0f)) return 0;
+  int best = 0;
+  for (int d = 8; d <= 24; d += 8) {
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {  // x, y, z
+      const int off = 2 - a;       // the axis' bit position within a triple
+      const int dropped = d > off ? (d - off + 2) / 3 : 0;
+      const double ext = double(ord2f(bounds[3 + a])) - double(ord2f(bounds[a]));
+      ok = ok && ext * ldexp(1.0, dropped - MORTON_BITS) <= 0.5 * double(eps);
+    }
+    if (ok) best = d;
+  }
+  return best;
+}
+
 // The grid the Morton codes quantise to, from the scene bounds words
 // (bounds[0..2] lo, [3..5] hi, ordered ints).
 struct MortonGrid {

@@ -119,23 +119,39 @@ __global__ __launch_bounds__(256) void k_bounds(const float* __restrict__ pts, u
 }
 
 
-__device__ __forceinline__ void count_digits(uint32_t* sh, uint64_t code) {
+// Digit counts of the passes the sort runs (digits below `first` are all
+// zero and their passes skipped: counting them would pile every lane of a
+// wave onto one LDS bin).
+__device__ __forceinline__ void count_digits(uint32_t* sh, uint64_t code, int first) {
 #pragma unroll
-  for (int q = 0; q < SORT_PASSES; ++q) atomicAdd(&sh[q * RADIX + ((code >> (8 * q)) & 0xff)], 1u);
+  for (int q = 0; q < SORT_PASSES; ++q)
+    if (q >= first) atomicAdd(&sh[q * RADIX + ((code >> (8 * q)) & 0xff)], 1u);
 }
 
 // Codes of all points plus the digit counts of every sort pass.  With a
 // 16-byte aligned point array a thread codes 4 points from 3 float4 loads
 // and writes their keys as two 16-byte stores.
+// The lowest `drop` code bits are cleared, drop = droppable_code_bits(eps)
+// (all blocks compute the same value; block 0 also stores it for the sort
+// and the walks).  The sort then skips drop / 8 passes and always ends in
+// the first key buffer, so the codes go to the first buffer if it skips an
+// even number of passes, else to the second.
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, uint32_t n,
-                                               const uint32_t* __restrict__ bounds,
-                                               uint64_t* __restrict__ keys,
+                                               const uint32_t* __restrict__ bounds, float eps,
+                                               uint64_t* __restrict__ keys_a,
+                                               uint64_t* __restrict__ keys_b,
+                                               uint32_t* __restrict__ drop_out,
                                                uint32_t* __restrict__ hist) {
   __shared__ uint32_t sh[SORT_PASSES * RADIX];
   for (int t = threadIdx.x; t < SORT_PASSES * RADIX; t += blockDim.x) sh[t] = 0;
   MortonGrid grid;
   grid.load(bounds);
+  const int drop = droppable_code_bits(bounds, eps);
+  const uint64_t mask = ~0ull << drop;
+  const int first = drop / 8;  // first sort pass that runs
+  uint64_t* keys = (first % 2 == 0) ? keys_a : keys_b;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && drop_out) *drop_out = uint32_t(drop);
   __syncthreads();
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -145,16 +161,16 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
     const float4* p4 = reinterpret_cast<const float4*>(pts);
     ulonglong2* k2 = reinterpret_cast<ulonglong2*>(keys);
     auto code4 = [&](uint32_t g, const float4& a, const float4& b, const float4& c) {
-      const uint64_t c0 = grid.code(a.x, a.y, a.z);
-      const uint64_t c1 = grid.code(a.w, b.x, b.y);
-      const uint64_t c2 = grid.code(b.z, b.w, c.x);
-      const uint64_t c3 = grid.code(c.y, c.z, c.w);
+      const uint64_t c0 = grid.code(a.x, a.y, a.z) & mask;
+      const uint64_t c1 = grid.code(a.w, b.x, b.y) & mask;
+      const uint64_t c2 = grid.code(b.z, b.w, c.x) & mask;
+      const uint64_t c3 = grid.code(c.y, c.z, c.w) & mask;
       k2[2 * size_t(g)] = make_ulonglong2(c0, c1);
       k2[2 * size_t(g) + 1] = make_ulonglong2(c2, c3);
-      count_digits(sh, c0);
-      count_digits(sh, c1);
-      count_digits(sh, c2);
-      count_digits(sh, c3);
+      count_digits(sh, c0, first);
+      count_digits(sh, c1, first);
+      count_digits(sh, c2, first);
+      count_digits(sh, c3, first);
     };
     // two groups (six loads) in flight per thread
     uint32_t g = gid;
@@ -173,9 +189,9 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
   }
   for (uint32_t i = first_scalar + gid; i < n; i += stride) {
     const float* p = pts + size_t(3) * i;
-    const uint64_t code = grid.code(p[0], p[1], p[2]);
+    const uint64_t code = grid.code(p[0], p[1], p[2]) & mask;
     keys[i] = code;
-    count_digits(sh, code);
+    count_digits(sh, code, first);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < SORT_PASSES * RADIX; t += blockDim.x)
@@ -223,16 +239,20 @@ void launch_bounds(const float* pts, uint32_t n, uint32_t* bounds, uint32_t* sta
                        status);
 }
 
-void launch_morton(const float* pts, uint32_t n, const uint32_t* bounds, uint64_t* keys,
-                   uint32_t* hist, hipStream_t s) {
+void launch_morton(const float* pts, uint32_t n, const uint32_t* bounds, float eps,
+                   uint64_t* keys_a, uint64_t* keys_b, uint32_t* drop_out, uint32_t* hist,
+                   hipStream_t s) {
   if (n == 0) return;
-  // keys come from the arena (256-byte aligned); the points may not be
-  if (reinterpret_cast<uintptr_t>(pts) % 16 == 0 && reinterpret_cast<uintptr_t>(keys) % 16 == 0)
+  // the point array may not be 16-byte aligned (arena buffers are)
+  const bool vec = reinterpret_cast<uintptr_t>(pts) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(keys_a) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(keys_b) % 16 == 0;
+  if (vec)
     hipLaunchKernelGGL(k_morton<true>, dim3(reduce_blocks(n)), dim3(256), 0, s, pts, n, bounds,
-                       keys, hist);
+                       eps, keys_a, keys_b, drop_out, hist);
   else
     hipLaunchKernelGGL(k_morton<false>, dim3(reduce_blocks(n)), dim3(256), 0, s, pts, n, bounds,
-                       keys, hist);
+                       eps, keys_a, keys_b, drop_out, hist);
 }
 
 void launch_gather(const float* pts, const uint32_t* perm, uint32_t n, float4* leaf,

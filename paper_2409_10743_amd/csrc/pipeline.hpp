@@ -42,6 +42,14 @@ struct SortScratch {
   uint32_t* err;       // status word, STATUS_SORT_STALL set on a stalled wait
 };
 
+// The same sort with the first *drop / 8 passes skipped (the number is
+// read on the device): the result always ends in the A buffers, and the
+// first pass that runs takes the values to be 0..n-1.
+void launch_radix_sort_dropped(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
+                               uint32_t n, const uint32_t* drop, const SortScratch& sc,
+                               hipStream_t s, void (*after_pass)(void*, int) = nullptr,
+                               void* arg = nullptr);
+
 // Digit histograms of keys already in memory (the morton kernel computes
 // them itself while writing the keys).
 void launch_digit_histogram(const uint64_t* keys, uint32_t n, uint32_t* hist,
@@ -62,8 +70,13 @@ void launch_prep(uint32_t* zero_region, size_t zero_words, uint32_t* bounds,
                  hipStream_t s);
 void launch_bounds(const float* pts, uint32_t n, uint32_t* bounds,
                    uint32_t* status, hipStream_t s);
-void launch_morton(const float* pts, uint32_t n, const uint32_t* bounds,
-                   uint64_t* keys, uint32_t* hist, hipStream_t s);
+// Codes with their lowest droppable_code_bits(bounds, eps) bits cleared
+// (eps <= 0: full 63-bit codes), written to keys_a if that drops an even
+// number of whole sort passes, else to keys_b; the bit count goes to
+// *drop_out (if not null) for launch_radix_sort_dropped and the walks.
+void launch_morton(const float* pts, uint32_t n, const uint32_t* bounds, float eps,
+                   uint64_t* keys_a, uint64_t* keys_b, uint32_t* drop_out, uint32_t* hist,
+                   hipStream_t s);
 // Sorted leaves, leaf[i] = point perm[i] (rope unset), plus the padding
 // record leaf[n] (leaf holds n + 1 records); also initialises the
 // per-point state and fills the build's hand-over entries with -1.
@@ -98,24 +111,26 @@ void launch_build_boxes(const uint64_t* keys, Node* prims, uint32_t n, Node* nod
 
 // ---- traversals (traverse.hip) ---------------------------------------------
 // keys: the sorted Morton codes; bounds: the scene bounds words they were
-// made with (both for the walks' early end).
+// made with; drop: the number of low code bits the keys cleared (null: 0)
+// (all three for the walks' early end).
 void launch_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
-                  const uint32_t* bounds, uint32_t n, const int32_t* root, float e2,
-                  int32_t min_pts, uint8_t* is_core, uint32_t* err, int block, hipStream_t s);
+                  const uint32_t* bounds, const uint32_t* drop, uint32_t n, const int32_t* root,
+                  float e2, int32_t min_pts, uint8_t* is_core, uint32_t* err, int block,
+                  hipStream_t s);
 // minPts <= 2: every point with a neighbour is core; union every pair.
 void launch_pairs_fof(const Node* nodes, const float4* leaf, const uint64_t* keys,
-                      const uint32_t* bounds, uint32_t n, float e2, int32_t* parent,
-                      uint8_t* member, uint32_t* err, int block, hipStream_t s);
+                      const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
+                      int32_t* parent, uint8_t* member, uint32_t* err, int block, hipStream_t s);
 // minPts > 2: union core pairs, record each non-core point's smallest-index
 // core neighbour.
 void launch_pairs_core(const Node* nodes, const float4* leaf, const uint64_t* keys,
-                       const uint32_t* bounds, uint32_t n, float e2, const uint8_t* is_core,
-                       const uint32_t* perm, int32_t* parent, unsigned long long* bestcore,
-                       uint32_t* err, int block, hipStream_t s);
+                       const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
+                       const uint8_t* is_core, const uint32_t* perm, int32_t* parent,
+                       unsigned long long* bestcore, uint32_t* err, int block, hipStream_t s);
 // Pair traversal with F(i, j) = count: every pair exactly once.
 void launch_pairs_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
-                        const uint32_t* bounds, uint32_t n, float e2, unsigned long long* count,
-                        uint32_t* err, int block, hipStream_t s);
+                        const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
+                        unsigned long long* count, uint32_t* err, int block, hipStream_t s);
 
 // ---- labels (finalize.hip) --------------------------------------------------
 // 1) cluster root per point (written over parent; -1 = noise), the

@@ -58,12 +58,16 @@ __global__ __launch_bounds__(256) void k_digit_hist(const uint64_t* __restrict__
     if (sh[t]) atomicAdd(&hist[t], sh[t]);
 }
 
+// With `drop` (not null) the pass reads the number of low code bits the
+// keys cleared: a pass below it returns at once, and the passes that run
+// alternate between the two buffer pairs so that the last ends in (ka, va):
+// the codes start in ka if an even number of passes is skipped, else in kb.
 template <bool IOTA, int ITEMS>
 __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
-    const uint64_t* __restrict__ kin, uint64_t* __restrict__ kout,
-    const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout, uint32_t n,
-    int shift, const uint32_t* __restrict__ ghist, uint32_t* __restrict__ status,
-    uint32_t* __restrict__ tile_ctr, uint32_t* __restrict__ err) {
+    uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb, uint32_t n, int shift,
+    const uint32_t* __restrict__ drop, const uint32_t* __restrict__ ghist,
+    uint32_t* __restrict__ status, uint32_t* __restrict__ tile_ctr,
+    uint32_t* __restrict__ err) {
   constexpr int TILE = SORT_THREADS * ITEMS;
   __shared__ uint64_t s_keys[TILE];           // keys and values in digit order
   __shared__ uint32_t s_vals[TILE];
@@ -72,6 +76,24 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
   __shared__ uint32_t s_whist[WAVES][RADIX];
   __shared__ uint32_t s_tmp[WAVES];
   __shared__ uint32_t s_tile;
+
+  const uint64_t* kin = ka;  // without `drop`: (ka, va) -> (kb, vb)
+  uint64_t* kout = kb;
+  const uint32_t* vin = va;
+  uint32_t* vout = vb;
+  bool iota = IOTA;
+  if (drop) {
+    const int skip = int(*drop) / 8, pass = shift / 8;
+    if (pass < skip) return;
+    const bool from_a = ((pass - skip) % 2 == 0) == (skip % 2 == 0);
+    if (!from_a) {
+      kin = kb;
+      kout = ka;
+      vin = vb;
+      vout = va;
+    }
+    iota = pass == skip;
+  }
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
@@ -90,7 +112,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
   for (int k = 0; k < ITEMS; ++k) {
     uint32_t idx = wbase + k * 64 + lane;
     key[k] = idx < n ? kin[idx] : ~0ull;
-    val[k] = IOTA ? idx : (idx < n ? vin[idx] : 0u);
+    val[k] = iota ? idx : (idx < n ? vin[idx] : 0u);
   }
 
   // rank each key among the keys of this wave with the same digit; the
@@ -201,20 +223,25 @@ int sort_items() {
 }
 
 namespace {
+// one pass from (kin, vin) to (kout, vout); with `drop`, the kernel picks
+// the direction itself (see k_onesweep)
 template <int ITEMS>
 void sort_pass(bool iota, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
-               uint32_t* vout, uint32_t n, int p, const SortScratch& sc, uint32_t* st,
-               hipStream_t s) {
+               uint32_t* vout, uint32_t n, int p, const uint32_t* drop, const SortScratch& sc,
+               uint32_t* st, hipStream_t s) {
   const uint32_t tiles = sort_tiles(n, ITEMS);
+  uint64_t* ka = const_cast<uint64_t*>(kin);  // read-only in this direction
+  uint32_t* va = const_cast<uint32_t*>(vin);
   if (iota)
-    hipLaunchKernelGGL((k_onesweep<true, ITEMS>), dim3(tiles), dim3(SORT_THREADS), 0, s, kin,
-                       kout, vin, vout, n, 8 * p, sc.hist + p * RADIX, st, sc.tile_ctr + p,
-                       sc.err);
+    hipLaunchKernelGGL((k_onesweep<true, ITEMS>), dim3(tiles), dim3(SORT_THREADS), 0, s, ka,
+                       kout, va, vout, n, 8 * p, drop, sc.hist + p * RADIX, st,
+                       sc.tile_ctr + p, sc.err);
   else
-    hipLaunchKernelGGL((k_onesweep<false, ITEMS>), dim3(tiles), dim3(SORT_THREADS), 0, s, kin,
-                       kout, vin, vout, n, 8 * p, sc.hist + p * RADIX, st, sc.tile_ctr + p,
-                       sc.err);
+    hipLaunchKernelGGL((k_onesweep<false, ITEMS>), dim3(tiles), dim3(SORT_THREADS), 0, s, ka,
+                       kout, va, vout, n, 8 * p, drop, sc.hist + p * RADIX, st,
+                       sc.tile_ctr + p, sc.err);
 }
+
 }  // namespace
 
 bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
@@ -232,13 +259,28 @@ bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
     uint32_t* vout = in_a ? vb : va;
     uint32_t* st = sc.status + size_t(p) * words;
     const bool iota = p == first_pass && iota_vals;
-    if (items == 8) sort_pass<8>(iota, kin, kout, vin, vout, n, p, sc, st, s);
-    else if (items == 12) sort_pass<12>(iota, kin, kout, vin, vout, n, p, sc, st, s);
-    else sort_pass<16>(iota, kin, kout, vin, vout, n, p, sc, st, s);
+    if (items == 8) sort_pass<8>(iota, kin, kout, vin, vout, n, p, nullptr, sc, st, s);
+    else if (items == 12) sort_pass<12>(iota, kin, kout, vin, vout, n, p, nullptr, sc, st, s);
+    else sort_pass<16>(iota, kin, kout, vin, vout, n, p, nullptr, sc, st, s);
     if (after_pass) after_pass(arg, p);
     in_a = !in_a;
   }
   return in_a;
+}
+
+void launch_radix_sort_dropped(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
+                               uint32_t n, const uint32_t* drop, const SortScratch& sc,
+                               hipStream_t s, void (*after_pass)(void*, int), void* arg) {
+  if (n == 0) return;
+  const int items = sort_items();
+  const uint32_t words = sort_tiles(n, items) * RADIX;
+  for (int p = 0; p < SORT_PASSES; ++p) {
+    uint32_t* st = sc.status + size_t(p) * words;
+    if (items == 8) sort_pass<8>(false, ka, kb, va, vb, n, p, drop, sc, st, s);
+    else if (items == 12) sort_pass<12>(false, ka, kb, va, vb, n, p, drop, sc, st, s);
+    else sort_pass<16>(false, ka, kb, va, vb, n, p, drop, sc, st, s);
+    if (after_pass) after_pass(arg, p);
+  }
 }
 
 }  // namespace dbx

@@ -27,10 +27,10 @@ struct CountCore {
   float r2;
   uint8_t* is_core;
   MortonGrid grid;
-  uint64_t hi;
+  uint64_t hi, mask;
   __device__ int32_t begin(uint32_t, const float4& q) {
     cnt = 0;
-    hi = grid.upper_code(q, r2);
+    hi = grid.upper_code(q, r2) & mask;
     return root;
   }
   __device__ uint64_t khi() const { return hi; }
@@ -42,9 +42,10 @@ struct CountCore {
 
 __global__ void k_count(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
                         const uint64_t* __restrict__ keys, const uint32_t* __restrict__ bounds,
-                        uint32_t n, WalkCfg wc, const int32_t* __restrict__ root, float e2,
-                        int32_t min_pts, uint8_t* __restrict__ is_core, uint32_t* err) {
-  CountCore v{*root, min_pts, 0, e2, is_core, {}, 0};
+                        const uint32_t* drop, uint32_t n, WalkCfg wc,
+                        const int32_t* __restrict__ root, float e2, int32_t min_pts,
+                        uint8_t* __restrict__ is_core, uint32_t* err) {
+  CountCore v{*root, min_pts, 0, e2, is_core, {}, 0, ~0ull << (drop ? *drop : 0u)};
   v.grid.load(bounds);
   wave_walks(nodes, leaf, keys, n, wc, v, err);
 }
@@ -65,11 +66,11 @@ struct PairVisit {
   uint32_t pairs, visits, descents, leaves;  // COUNT only: this query's counts
   unsigned long long tot[4];                 // COUNT only: this lane's totals
   MortonGrid grid;
-  uint64_t hi;
+  uint64_t hi, mask;
   __device__ uint64_t khi() const { return hi; }
   __device__ int32_t begin(uint32_t i, const float4& q) {
     found = false;
-    hi = grid.upper_code(q, r2);
+    hi = grid.upper_code(q, r2) & mask;
     if (MODE == COUNT) pairs = visits = descents = leaves = 0;
     if (MODE == CORE) ci = is_core[i] != 0;
     return __float_as_int(q.w);
@@ -118,12 +119,12 @@ __device__ __forceinline__ void wave_add(unsigned long long* dst, unsigned long 
 template <int MODE>
 __global__ void k_pairs(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
                         const uint64_t* __restrict__ keys, const uint32_t* __restrict__ bounds,
-                        uint32_t n, WalkCfg wc, float e2,
+                        const uint32_t* drop, uint32_t n, WalkCfg wc, float e2,
                         const uint8_t* __restrict__ is_core, const uint32_t* __restrict__ perm,
                         int32_t* parent, uint8_t* member, unsigned long long* bestcore,
                         unsigned long long* count, uint32_t* err) {
   PairVisit<MODE> v{e2, is_core, perm, parent, member, bestcore, true, false, 0, 0, 0, 0,
-                    {0, 0, 0, 0}, {}, 0};
+                    {0, 0, 0, 0}, {}, 0, ~0ull << (drop ? *drop : 0u)};
   v.grid.load(bounds);
   wave_walks(nodes, leaf, keys, n, wc, v, err);
   if (MODE == COUNT) {  // pairs, internal visits, descents, leaf tests
@@ -156,39 +157,40 @@ uint32_t walk_refill_at() {
 }
 
 void launch_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
-                  const uint32_t* bounds, uint32_t n, const int32_t* root, float e2,
-                  int32_t min_pts, uint8_t* is_core, uint32_t* err, int block, hipStream_t s) {
+                  const uint32_t* bounds, const uint32_t* drop, uint32_t n, const int32_t* root,
+                  float e2, int32_t min_pts, uint8_t* is_core, uint32_t* err, int block,
+                  hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_count, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf, keys,
-                     bounds, n, walk_cfg(n), root, e2, min_pts, is_core, err);
+                     bounds, drop, n, walk_cfg(n), root, e2, min_pts, is_core, err);
 }
 
 void launch_pairs_fof(const Node* nodes, const float4* leaf, const uint64_t* keys,
-                      const uint32_t* bounds, uint32_t n, float e2, int32_t* parent,
-                      uint8_t* member, uint32_t* err, int block, hipStream_t s) {
+                      const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
+                      int32_t* parent, uint8_t* member, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<FOF>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     keys, bounds, n, walk_cfg(n), e2, nullptr, nullptr, parent, member, nullptr,
-                     nullptr, err);
+                     keys, bounds, drop, n, walk_cfg(n), e2, nullptr, nullptr, parent,
+                     member, nullptr, nullptr, err);
 }
 
 void launch_pairs_core(const Node* nodes, const float4* leaf, const uint64_t* keys,
-                       const uint32_t* bounds, uint32_t n, float e2, const uint8_t* is_core,
-                       const uint32_t* perm, int32_t* parent, unsigned long long* bestcore,
-                       uint32_t* err, int block, hipStream_t s) {
+                       const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
+                       const uint8_t* is_core, const uint32_t* perm, int32_t* parent,
+                       unsigned long long* bestcore, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<CORE>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     keys, bounds, n, walk_cfg(n), e2, is_core, perm, parent, nullptr, bestcore,
-                     nullptr, err);
+                     keys, bounds, drop, n, walk_cfg(n), e2, is_core, perm, parent, nullptr,
+                     bestcore, nullptr, err);
 }
 
 void launch_pairs_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
-                        const uint32_t* bounds, uint32_t n, float e2, unsigned long long* count,
-                        uint32_t* err, int block, hipStream_t s) {
+                        const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
+                        unsigned long long* count, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<COUNT>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     keys, bounds, n, walk_cfg(n), e2, nullptr, nullptr, nullptr, nullptr,
-                     nullptr, count, err);
+                     keys, bounds, drop, n, walk_cfg(n), e2, nullptr, nullptr, nullptr,
+                     nullptr, nullptr, count, err);
 }
 
 }  // namespace dbx
