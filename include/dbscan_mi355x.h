@@ -113,10 +113,16 @@ int dbscan_cluster_host(const float* host_points, int64_t n, float eps,
  * were written (at most max). */
 int dbscan_phase_times(const dbscan_ctx* ctx, float* ms, int32_t max);
 /* Name of timing slot k (one per kernel launch of a run: "prep", "bounds",
- * "morton", "sort0".."sort7", "scatter", "cells", "build_frame", "build_levels",
- * "ropes", "count", "pairs", "final_roots", "final_labels"; a slot a run does
- * not use reads 0 ms), NULL past the last. */
+ * "morton", "sort0".."sort7", "gather", "cells", "build_frame", "build_levels",
+ * "count", "pairs", "final_roots", "final_labels"; a slot a run does not use
+ * reads 0 ms), NULL past the last. */
 const char* dbscan_phase_name(int32_t k);
+
+/* Sort passes the context's last plain clustering call ran: 8 minus the
+ * low-digit passes it skipped because eps does not need those code bits
+ * (the skipped passes are the first ones, "sort0".., and launch a kernel
+ * that returns at once).  -1 for a null context. */
+int dbscan_sort_passes(const dbscan_ctx* ctx);
 
 /* ---- autotuning ---------------------------------------------------------------- */
 /* Run the call on the given input once per candidate option set (traversal

@@ -86,6 +86,7 @@ def load_library() -> ctypes.CDLL:
                                    ctypes.c_int),
         "dbscan_phase_times": ([vp, ctypes.POINTER(f32), i32], ctypes.c_int),
         "dbscan_phase_name": ([i32], ctypes.c_char_p),
+        "dbscan_sort_passes": ([vp], ctypes.c_int),
         "dbscan_morton_codes": ([vp, vp, i64, vp, vp], ctypes.c_int),
         "dbscan_sort_pairs": ([vp, vp, vp, i64, vp], ctypes.c_int),
         "dbscan_build_tree": ([vp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
@@ -240,6 +241,10 @@ class Context:
             m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.c_void_p(lab.data_ptr()),
             ctypes.byref(o), ctypes.byref(ms), _stream(p.device)))
         return {"block_size": o.block_size, "ms": ms.value}
+
+    def sort_passes(self) -> int:
+        """Sort passes the last plain clustering call ran (the rest skipped)."""
+        return int(load_library().dbscan_sort_passes(self.handle))
 
     def phase_times(self) -> dict:
         buf = (ctypes.c_float * len(PHASES))()

@@ -137,6 +137,7 @@ struct dbscan_ctx {
   float times[NPHASES] = {};
   int ntimes = 0;
   bool recorded[NPHASES + 1] = {};
+  int sort_passes = SORT_PASSES;  // sort passes the last clustering call ran
 };
 
 namespace {
@@ -293,9 +294,14 @@ int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore,
 }
 
 // Wait for the stream and turn the device status word into a status code.
-int finish(dbscan_ctx* c, const uint32_t* dev_status, bool timing, hipStream_t s) {
+// dev_drop (may be null): the code bits the sort dropped, read back for
+// dbscan_sort_passes.
+int finish(dbscan_ctx* c, const uint32_t* dev_status, bool timing, hipStream_t s,
+           const uint32_t* dev_drop = nullptr) {
   HIP_TRY(hipMemcpyAsync(c->host_status, dev_status, 4, hipMemcpyDeviceToHost, s));
+  if (dev_drop) HIP_TRY(hipMemcpyAsync(c->host_status + 1, dev_drop, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  c->sort_passes = dev_drop ? SORT_PASSES - int(c->host_status[1] / 8) : SORT_PASSES;
   HIP_TRY(hipGetLastError());
   if (timing) {
     int prev = 0;
@@ -347,7 +353,7 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
   launch_final_labels(n, ix.perm, parent, minlab, labels, s);
   mark(c, timing, PH_FINAL_LABELS, s);
   HIP_TRY(hipGetLastError());
-  return finish(c, ix.status, timing, s);
+  return finish(c, ix.status, timing, s, ix.drop);
 }
 
 // FDBSCAN-DenseBox (section 4.3.4): cells of side eps/sqrt(3), dense cells
@@ -743,6 +749,8 @@ int dbscan_phase_times(const dbscan_ctx* c, float* ms, int32_t max) {
   for (int i = 0; i < k; ++i) ms[i] = c->times[i];
   return k;
 }
+
+int dbscan_sort_passes(const dbscan_ctx* c) { return c ? c->sort_passes : -1; }
 
 const char* dbscan_phase_name(int32_t k) {
   return (k >= 0 && k < NPHASES) ? kPhaseNames[k] : nullptr;
