@@ -59,6 +59,14 @@ extern "C" {
 #define DBSCAN_ALGO_DENSEBOX 2  /* section 4.3.4 */
 
 #define DBSCAN_FLAG_TIMING 1u   /* record per-phase times (dbscan_phase_times) */
+/* Enqueue the call's work as a HIP graph: captured on first use, replayed by
+ * later calls of the same shape (same point and label buffers, sizes, eps
+ * and minPts for a plain call; same sets count and total for a batched one,
+ * whose per-set values are re-read at each replay) while the context's
+ * scratch has not moved.  A context keeps up to 4 graphs.  Ignored with the
+ * null stream and by DenseBox (which reads a count back mid-call); no
+ * timing in this mode. */
+#define DBSCAN_FLAG_GRAPH 2u
 
 typedef struct dbscan_options {
   int32_t algorithm;        /* DBSCAN_ALGO_* */

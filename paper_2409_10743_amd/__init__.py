@@ -23,6 +23,7 @@ _LIB_NAME = "libdbscan_mi355x.so"
 
 ALGO = {"auto": 0, "fdbscan": 1, "densebox": 2}
 FLAG_TIMING = 1
+FLAG_GRAPH = 2
 STATUS = {0: "ok", -1: "invalid argument", -2: "non-finite coordinate",
           -3: "out of device memory", -4: "device error", -5: "job exceeds budget"}
 
@@ -171,20 +172,23 @@ class Context:
 
     def cluster(self, points, eps: float, min_pts: int, algorithm: str = "auto",
                 block_size: int = 0, dense_threshold: int = 0, timing: bool = False,
-                out=None):
+                out=None, graph: bool = False):
+        """``graph``: enqueue as a HIP graph replayed by later calls of the
+        same shape (needs a non-default current stream; see
+        DBSCAN_FLAG_GRAPH)."""
         torch = _torch()
         p = _points(points)
         n = p.shape[0]
         labels = out if out is not None else torch.empty(n, dtype=torch.int32, device=p.device)
         o = _Options(ALGO[algorithm], int(dense_threshold), int(block_size),
-                     FLAG_TIMING if timing else 0)
+                     (FLAG_TIMING if timing else 0) | (FLAG_GRAPH if graph else 0))
         _check(load_library().dbscan_cluster_ex(
             self.handle, ctypes.c_void_p(p.data_ptr()), n, ctypes.c_float(eps), int(min_pts),
             ctypes.c_void_p(labels.data_ptr()), _stream(p.device), ctypes.byref(o)))
         return labels
 
     def cluster_batched(self, points, offsets, eps, min_pts, block_size: int = 0,
-                        timing: bool = False, out=None):
+                        timing: bool = False, out=None, graph: bool = False):
         """Cluster the sets points[offsets[k]:offsets[k+1]] independently in
         one pass; ``eps`` and ``min_pts`` are scalars or one value per set.
         Labels are set-local (-1 noise, else the smallest index within the
@@ -201,7 +205,8 @@ class Context:
                                  dtype=np.int32)
         labels = out if out is not None else torch.empty(p.shape[0], dtype=torch.int32,
                                                          device=p.device)
-        o = _Options(ALGO["fdbscan"], 0, int(block_size), FLAG_TIMING if timing else 0)
+        o = _Options(ALGO["fdbscan"], 0, int(block_size),
+                     (FLAG_TIMING if timing else 0) | (FLAG_GRAPH if graph else 0))
         _check(load_library().dbscan_cluster_batched(
             self.handle, ctypes.c_void_p(p.data_ptr()),
             off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), k,

@@ -138,6 +138,15 @@ struct dbscan_ctx {
   int ntimes = 0;
   bool recorded[NPHASES + 1] = {};
   int sort_passes = SORT_PASSES;  // sort passes the last clustering call ran
+  // captured call sequences (DBSCAN_FLAG_GRAPH), replayed while the key
+  // matches; the oldest is replaced
+  struct Graph {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+  };
+  Graph graphs[4];
+  uint64_t graph_clock = 0;
 };
 
 namespace {
@@ -323,42 +332,102 @@ int finish(dbscan_ctx* c, const uint32_t* dev_status, bool timing, hipStream_t s
   return DBSCAN_OK;
 }
 
+// Enqueue a call's kernels with `enqueue(s)`: directly, or (graph) as a HIP
+// graph captured on first use and replayed while `key` (every host value
+// the enqueued work depends on) matches.  Nothing inside `enqueue` may
+// allocate, synchronise or record timing events when graph is set; clears
+// go through kernels, not hipMemsetAsync.  A stream that cannot be
+// captured (the null stream) runs the work directly.
+template <class F>
+int run_enqueued(dbscan_ctx* c, hipStream_t s, bool graph, const std::vector<uint64_t>& key,
+                 F&& enqueue) {
+  if (!graph || s == nullptr) return enqueue(s);
+  dbscan_ctx::Graph* g = nullptr;
+  for (auto& e : c->graphs)
+    if (e.exec && e.key == key) g = &e;
+  if (!g) {
+    dbscan_ctx::Graph* slot = &c->graphs[0];
+    for (auto& e : c->graphs)
+      if (!e.exec || e.used < slot->used) slot = &e;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const int st = enqueue(s);
+    hipGraph_t captured = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &captured);
+    if (st != DBSCAN_OK || e != hipSuccess) {
+      if (captured) (void)hipGraphDestroy(captured);
+      (void)hipGetLastError();
+      return st != DBSCAN_OK ? st : fail(DBSCAN_EDEVICE, "graph capture failed");
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, captured, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(captured);
+    if (ie != hipSuccess) return fail(DBSCAN_EDEVICE, "graph instantiation failed");
+    if (slot->exec) (void)hipGraphExecDestroy(slot->exec);
+    slot->exec = exec;
+    slot->key = key;
+    g = slot;
+  }
+  g->used = ++c->graph_clock;
+  HIP_TRY(hipGraphLaunch(g->exec, s));
+  return DBSCAN_OK;
+}
+
+// Host values a plain call's enqueued work depends on.
+uint64_t bits_of(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return u;
+}
+
 int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t min_pts,
                 int32_t* labels, hipStream_t s, const dbscan_options& o) {
-  const bool timing = (o.flags & DBSCAN_FLAG_TIMING) != 0;
+  const bool graph = (o.flags & DBSCAN_FLAG_GRAPH) != 0;
+  const bool timing = !graph && (o.flags & DBSCAN_FLAG_TIMING) != 0;
   const int block = o.block_size ? o.block_size : 256;
   const float e2 = eps * eps;
   const bool core_mode = min_pts > 2;
-  Index ix;
-  int st = build_index(c, pts, n, core_mode, timing, s, &ix, eps);
+  const Layout L = make_layout(n, core_mode);
+  int st = ensure_arena(c, L.total);  // before any capture
   if (st != DBSCAN_OK) return st;
-  const Layout& L = ix.L;
-  uint8_t* flag = at<uint8_t>(c, L.flag);
-  int32_t* parent = at<int32_t>(c, L.parent);
-  unsigned long long* bestcore = core_mode ? at<unsigned long long>(c, L.bestcore) : nullptr;
-  if (core_mode)
-    launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, ix.root, e2, min_pts,
-                 flag, ix.status, block, s);
-  mark(c, timing, PH_COUNT, s);
-  if (core_mode)
-    launch_pairs_core(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, flag,
-                      ix.perm, parent, bestcore, ix.status, block, s);
-  else
-    launch_pairs_fof(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, parent, flag,
-                     ix.status, block, s);
-  mark(c, timing, PH_PAIRS, s);
-  int32_t* minlab = at<int32_t>(c, L.minlab);
-  launch_final_roots(n, min_pts, flag, bestcore, ix.perm, parent, minlab, labels, s);
-  mark(c, timing, PH_FINAL_ROOTS, s);
-  launch_final_labels(n, ix.perm, parent, minlab, labels, s);
-  mark(c, timing, PH_FINAL_LABELS, s);
-  HIP_TRY(hipGetLastError());
-  return finish(c, ix.status, timing, s, ix.drop);
+  const std::vector<uint64_t> key = {1,
+                                     reinterpret_cast<uint64_t>(pts),
+                                     reinterpret_cast<uint64_t>(labels),
+                                     reinterpret_cast<uint64_t>(c->arena),
+                                     n,
+                                     bits_of(eps),
+                                     uint64_t(uint32_t(min_pts)),
+                                     uint64_t(block)};
+  st = run_enqueued(c, s, graph, key, [&](hipStream_t gs) {
+    Index ix;
+    int r = build_index(c, pts, n, core_mode, timing, gs, &ix, eps);
+    if (r != DBSCAN_OK) return r;
+    uint8_t* flag = at<uint8_t>(c, L.flag);
+    int32_t* parent = at<int32_t>(c, L.parent);
+    unsigned long long* bestcore =
+        core_mode ? at<unsigned long long>(c, L.bestcore) : nullptr;
+    if (core_mode)
+      launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, ix.root, e2, min_pts,
+                   flag, ix.status, block, gs);
+    mark(c, timing, PH_COUNT, gs);
+    if (core_mode)
+      launch_pairs_core(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, flag,
+                        ix.perm, parent, bestcore, ix.status, block, gs);
+    else
+      launch_pairs_fof(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, parent, flag,
+                       ix.status, block, gs);
+    mark(c, timing, PH_PAIRS, gs);
+    int32_t* minlab = at<int32_t>(c, L.minlab);
+    launch_final_roots(n, min_pts, flag, bestcore, ix.perm, parent, minlab, labels, gs);
+    mark(c, timing, PH_FINAL_ROOTS, gs);
+    launch_final_labels(n, ix.perm, parent, minlab, labels, gs);
+    mark(c, timing, PH_FINAL_LABELS, gs);
+    HIP_TRY(hipGetLastError());
+    return int(DBSCAN_OK);
+  });
+  if (st != DBSCAN_OK) return st;
+  return finish(c, at<uint32_t>(c, L.status), timing, s, at<uint32_t>(c, L.drop));
 }
 
-// FDBSCAN-DenseBox (section 4.3.4): cells of side eps/sqrt(3), dense cells
-// taken whole, a BVH over dense cells and the remaining points.  One host
-// wait (for the number of primitives) sizes the build.
 int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t min_pts,
                  int32_t* labels, hipStream_t s, const dbscan_options& o) {
   const bool timing = (o.flags & DBSCAN_FLAG_TIMING) != 0;
@@ -457,7 +526,8 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
 int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t num_sets,
                 const float* h_eps, const int32_t* h_minpts, int32_t* labels, hipStream_t s,
                 const dbscan_options& o) {
-  const bool timing = (o.flags & DBSCAN_FLAG_TIMING) != 0;
+  const bool graph = (o.flags & DBSCAN_FLAG_GRAPH) != 0;
+  const bool timing = !graph && (o.flags & DBSCAN_FLAG_TIMING) != 0;
   const int block = o.block_size ? o.block_size : 256;
   const uint32_t n = uint32_t(h_off[num_sets]);
   int set_bits = 1;
@@ -498,54 +568,70 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
   float* d_e2 = at<float>(c, e2_b);
   int32_t* d_mp = at<int32_t>(c, mp_b);
   int32_t* d_root = at<int32_t>(c, root_b);
-  HIP_TRY(hipMemcpyAsync(d_off, s_off, (size_t(num_sets) + 1) * 8, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(d_e2, s_e2, size_t(num_sets) * 4, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(d_mp, s_mp, size_t(num_sets) * 4, hipMemcpyHostToDevice, s));
-
-  uint64_t* ka = at<uint64_t>(c, L.keys_a);
-  uint64_t* kb = at<uint64_t>(c, L.keys_b);
-  uint32_t* va = at<uint32_t>(c, L.vals_a);
-  uint32_t* vb = at<uint32_t>(c, L.vals_b);
-  uint32_t* bounds = at<uint32_t>(c, L.bounds);
   uint32_t* status = at<uint32_t>(c, L.status);
-  SortScratch sc{at<uint32_t>(c, L.hist), at<uint32_t>(c, L.tile_ctr),
-                 at<uint32_t>(c, L.sort_status), status};
-  float4* leaf = at<float4>(c, L.leaf);
-  int32_t* parent = at<int32_t>(c, L.parent);
-  uint8_t* flag = at<uint8_t>(c, L.flag);
-  int32_t* minlab = at<int32_t>(c, L.minlab);
-  unsigned long long* bestcore = any_core ? at<unsigned long long>(c, L.bestcore) : nullptr;
+  const std::vector<uint64_t> key = {2,
+                                     reinterpret_cast<uint64_t>(pts),
+                                     reinterpret_cast<uint64_t>(labels),
+                                     reinterpret_cast<uint64_t>(c->arena),
+                                     reinterpret_cast<uint64_t>(c->stage),
+                                     n,
+                                     num_sets,
+                                     uint64_t(any_core),
+                                     uint64_t(block)};
+  st = run_enqueued(c, s, graph, key, [&](hipStream_t gs) {
+    // the per-set parameters are read from the pinned staging buffer when
+    // the copies run, so a replayed graph picks up this call's values
+    HIP_TRY(hipMemcpyAsync(d_off, s_off, (size_t(num_sets) + 1) * 8, hipMemcpyHostToDevice, gs));
+    HIP_TRY(hipMemcpyAsync(d_e2, s_e2, size_t(num_sets) * 4, hipMemcpyHostToDevice, gs));
+    HIP_TRY(hipMemcpyAsync(d_mp, s_mp, size_t(num_sets) * 4, hipMemcpyHostToDevice, gs));
 
-  start_timing(c, timing, s);
-  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, s);
-  mark(c, timing, PH_PREP, s);
-  mark(c, timing, PH_BOUNDS, s);
-  launch_set_morton(pts, d_off, num_sets, bits, set_shift, ka, sc.hist, d_root, status, s);
-  mark(c, timing, PH_MORTON, s);
-  SortMarks sm{c, s};
-  const bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, s,
-                                      timing ? sort_mark : nullptr, &sm);
-  const uint64_t* keys = in_a ? ka : kb;
-  const uint32_t* perm = in_a ? va : vb;
-  int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
-  launch_gather(pts, perm, n, leaf, parent, minlab, flag, bestcore, at<int4>(c, L.pending),
-                L.pending_entries, s);
-  mark(c, timing, PH_GATHER, s);
-  mark(c, timing, PH_CELLS, s);
-  Node* nodes = at<Node>(c, L.nodes);
-  launch_build(keys, set_shift, leaf, n, nodes, other, d_root, at<int4>(c, L.pending), status, s,
-               timing ? build_mark : nullptr, &sm);
-  mark(c, timing, PH_BUILD_LEVELS, s);
-  if (any_core)
-    launch_count_sets(nodes, leaf, n, keys, set_shift, d_root, d_e2, d_mp, flag, status, block, s);
-  mark(c, timing, PH_COUNT, s);
-  launch_pairs_sets(nodes, leaf, n, keys, set_shift, d_e2, d_mp, perm, parent, flag, bestcore,
-                    status, block, s);
-  mark(c, timing, PH_PAIRS, s);
-  launch_final_sets(n, keys, set_shift, d_mp, d_off, flag, bestcore, perm, parent, minlab, labels,
-                    s);
-  mark(c, timing, PH_FINAL_LABELS, s);
-  HIP_TRY(hipGetLastError());
+    uint64_t* ka = at<uint64_t>(c, L.keys_a);
+    uint64_t* kb = at<uint64_t>(c, L.keys_b);
+    uint32_t* va = at<uint32_t>(c, L.vals_a);
+    uint32_t* vb = at<uint32_t>(c, L.vals_b);
+    uint32_t* bounds = at<uint32_t>(c, L.bounds);
+    SortScratch sc{at<uint32_t>(c, L.hist), at<uint32_t>(c, L.tile_ctr),
+                   at<uint32_t>(c, L.sort_status), status};
+    float4* leaf = at<float4>(c, L.leaf);
+    int32_t* parent = at<int32_t>(c, L.parent);
+    uint8_t* flag = at<uint8_t>(c, L.flag);
+    int32_t* minlab = at<int32_t>(c, L.minlab);
+    unsigned long long* bestcore = any_core ? at<unsigned long long>(c, L.bestcore) : nullptr;
+
+    start_timing(c, timing, gs);
+    launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, gs);
+    mark(c, timing, PH_PREP, gs);
+    mark(c, timing, PH_BOUNDS, gs);
+    launch_set_morton(pts, d_off, num_sets, bits, set_shift, ka, sc.hist, d_root, status, gs);
+    mark(c, timing, PH_MORTON, gs);
+    SortMarks sm{c, gs};
+    const bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, gs,
+                                        timing ? sort_mark : nullptr, &sm);
+    const uint64_t* keys = in_a ? ka : kb;
+    const uint32_t* perm = in_a ? va : vb;
+    int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
+    launch_gather(pts, perm, n, leaf, parent, minlab, flag, bestcore, at<int4>(c, L.pending),
+                  L.pending_entries, gs);
+    mark(c, timing, PH_GATHER, gs);
+    mark(c, timing, PH_CELLS, gs);
+    Node* nodes = at<Node>(c, L.nodes);
+    launch_build(keys, set_shift, leaf, n, nodes, other, d_root, at<int4>(c, L.pending), status,
+                 gs, timing ? build_mark : nullptr, &sm);
+    mark(c, timing, PH_BUILD_LEVELS, gs);
+    if (any_core)
+      launch_count_sets(nodes, leaf, n, keys, set_shift, d_root, d_e2, d_mp, flag, status, block,
+                        gs);
+    mark(c, timing, PH_COUNT, gs);
+    launch_pairs_sets(nodes, leaf, n, keys, set_shift, d_e2, d_mp, perm, parent, flag, bestcore,
+                      status, block, gs);
+    mark(c, timing, PH_PAIRS, gs);
+    launch_final_sets(n, keys, set_shift, d_mp, d_off, flag, bestcore, perm, parent, minlab,
+                      labels, gs);
+    mark(c, timing, PH_FINAL_LABELS, gs);
+    HIP_TRY(hipGetLastError());
+    return int(DBSCAN_OK);
+  });
+  if (st != DBSCAN_OK) return st;
   return finish(c, status, timing, s);
 }
 
@@ -653,6 +739,8 @@ int dbscan_ctx_create(int device, uint64_t hbm_budget_bytes, dbscan_ctx** out) {
 int dbscan_ctx_destroy(dbscan_ctx* c) {
   if (!c) return DBSCAN_OK;
   DeviceGuard g(c->device);
+  for (auto& e : c->graphs)
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
   if (c->arena) (void)hipFree(c->arena);
   if (c->host_status) (void)hipHostFree(c->host_status);
   if (c->stage) (void)hipHostFree(c->stage);
