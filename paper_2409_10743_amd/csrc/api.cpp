@@ -543,7 +543,8 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
   const size_t e2_b = off_b + align_up((size_t(num_sets) + 1) * 8);
   const size_t mp_b = e2_b + align_up(size_t(num_sets) * 4);
   const size_t root_b = mp_b + align_up(size_t(num_sets) * 4);
-  const size_t total = root_b + align_up(size_t(num_sets) * 4);
+  const size_t grid_b = root_b + align_up(size_t(num_sets) * 4);
+  const size_t total = grid_b + align_up(size_t(num_sets) * sizeof(MortonGrid));
   int st = ensure_arena(c, total);
   if (st != DBSCAN_OK) return st;
   const size_t stage_bytes = (size_t(num_sets) + 1) * 8 + size_t(num_sets) * 8;
@@ -568,6 +569,7 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
   float* d_e2 = at<float>(c, e2_b);
   int32_t* d_mp = at<int32_t>(c, mp_b);
   int32_t* d_root = at<int32_t>(c, root_b);
+  MortonGrid* d_grid = at<MortonGrid>(c, grid_b);
   uint32_t* status = at<uint32_t>(c, L.status);
   const std::vector<uint64_t> key = {2,
                                      reinterpret_cast<uint64_t>(pts),
@@ -602,7 +604,8 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
     launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, gs);
     mark(c, timing, PH_PREP, gs);
     mark(c, timing, PH_BOUNDS, gs);
-    launch_set_morton(pts, d_off, num_sets, bits, set_shift, ka, sc.hist, d_root, status, gs);
+    launch_set_morton(pts, d_off, num_sets, bits, set_shift, ka, sc.hist, d_root, d_grid, status,
+                      gs);
     mark(c, timing, PH_MORTON, gs);
     SortMarks sm{c, gs};
     const bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, gs,
@@ -619,11 +622,11 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
                  gs, timing ? build_mark : nullptr, &sm);
     mark(c, timing, PH_BUILD_LEVELS, gs);
     if (any_core)
-      launch_count_sets(nodes, leaf, n, keys, set_shift, d_root, d_e2, d_mp, flag, status, block,
-                        gs);
+      launch_count_sets(nodes, leaf, n, keys, set_shift, d_root, d_e2, d_mp, d_grid, flag, status,
+                        block, gs);
     mark(c, timing, PH_COUNT, gs);
-    launch_pairs_sets(nodes, leaf, n, keys, set_shift, d_e2, d_mp, perm, parent, flag, bestcore,
-                      status, block, gs);
+    launch_pairs_sets(nodes, leaf, n, keys, set_shift, d_e2, d_mp, d_grid, perm, parent, flag,
+                      bestcore, status, block, gs);
     mark(c, timing, PH_PAIRS, gs);
     launch_final_sets(n, keys, set_shift, d_mp, d_off, flag, bestcore, perm, parent, minlab,
                       labels, gs);

@@ -38,12 +38,14 @@ __device__ __forceinline__ float block_max(float v, float* s_red) {
 
 // One workgroup per set: the set's bounding box, then its keys (set id in
 // the top bits, `bits` per axis of Morton code below) and digit histograms.
+// The set's grid goes to grids[set] for the walks' early end.
 __global__ __launch_bounds__(256) void k_set_morton(const float* __restrict__ pts,
                                                    const int64_t* __restrict__ offsets,
                                                    int bits, int set_shift,
                                                    uint64_t* __restrict__ keys,
                                                    uint32_t* __restrict__ hist,
                                                    int32_t* __restrict__ set_root,
+                                                   MortonGrid* __restrict__ grids,
                                                    uint32_t* __restrict__ status) {
   __shared__ uint32_t sh[SORT_PASSES * RADIX];
   __shared__ float s_red[4];
@@ -64,54 +66,60 @@ __global__ __launch_bounds__(256) void k_set_morton(const float* __restrict__ pt
     }
   }
   if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(status, STATUS_NONFINITE);
-  float s[3];
-  const float cells = float((1u << bits) - 1u);
+  MortonGrid g;
+  g.maxc = float((1u << bits) - 1u);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    lo[a] = block_min(lo[a], s_red);
-    hi[a] = block_max(hi[a], s_red);
-    const float ext = hi[a] - lo[a];
-    s[a] = ext > 0.0f ? float(1u << bits) / ext : 0.0f;
+    g.lo[a] = block_min(lo[a], s_red);
+    const float top = block_max(hi[a], s_red);
+    const float ext = top - g.lo[a];
+    g.s[a] = ext > 0.0f ? float(1u << bits) / ext : 0.0f;
   }
+  if (threadIdx.x == 0) grids[set] = g;
   const uint64_t tag = uint64_t(set) << set_shift;
   for (uint32_t i = b + threadIdx.x; i < e; i += blockDim.x) {
-    uint32_t q[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-#pragma clang fp contract(off)
-      float t = (pts[size_t(3) * i + a] - lo[a]) * s[a];
-      t = fminf(fmaxf(floorf(t), 0.0f), cells);  // NaN -> 0
-      q[a] = uint32_t(t);
-    }
-    const uint64_t code = tag | (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    const float* p = pts + size_t(3) * i;
+    const uint64_t code = tag | g.code(p[0], p[1], p[2]);
     keys[i] = code;
 #pragma unroll
-    for (int p = 0; p < SORT_PASSES; ++p)
-      atomicAdd(&sh[p * RADIX + ((code >> (8 * p)) & 0xff)], 1u);
+    for (int q = 0; q < SORT_PASSES; ++q)
+      atomicAdd(&sh[q * RADIX + ((code >> (8 * q)) & 0xff)], 1u);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < SORT_PASSES * RADIX; t += blockDim.x)
     if (sh[t]) atomicAdd(&hist[t], sh[t]);
 }
 
+// the early-end bound of a query of set `set` (its codes carry the set id)
+__device__ __forceinline__ uint64_t set_upper_code(const MortonGrid* grids, uint32_t set,
+                                                   int set_shift, const float4& q, float e2) {
+  const MortonGrid g = grids[set];
+  return (uint64_t(set) << set_shift) | g.upper_code(q, e2);
+}
+
 // Counting for the points of sets with minPts > 2, from their set's root.
 struct CountSets {
-  static constexpr bool kBounded = false;
-  __device__ uint64_t khi() const { return ~0ull; }
+  static constexpr bool kBounded = true;
+  static constexpr bool kStartIsRope = false;  // the set's root
+  __device__ uint64_t khi() const { return hi; }
   const uint64_t* keys;
   int set_shift;
   const int32_t* set_root;
   const float* set_e2;
   const int32_t* set_minpts;
   uint8_t* flag;
+  const MortonGrid* grids;
   float r2;
   int32_t min_pts, cnt;
-  __device__ int32_t begin(uint32_t i, const float4&) {
+  uint64_t hi;
+  __device__ int32_t begin(uint32_t i, const float4& q) {
     const uint32_t set = uint32_t(keys[i] >> set_shift);
     min_pts = set_minpts[set];
     r2 = set_e2[set];
     cnt = 0;
-    return min_pts > 2 ? set_root[set] : SENTINEL;
+    if (min_pts <= 2) return SENTINEL;
+    hi = set_upper_code(grids, set, set_shift, q, r2);
+    return set_root[set];
   }
   __device__ float e2() const { return r2; }
   __device__ void visit(bool, bool) {}
@@ -127,16 +135,18 @@ __global__ void k_count_sets(const Node* __restrict__ nodes, const float4* __res
                              int set_shift, const int32_t* __restrict__ set_root,
                              const float* __restrict__ set_e2,
                              const int32_t* __restrict__ set_minpts,
+                             const MortonGrid* __restrict__ grids,
                              uint8_t* __restrict__ flag, uint32_t* __restrict__ err) {
-  CountSets v{keys, set_shift, set_root, set_e2, set_minpts, flag, 0.f, 0, 0};
+  CountSets v{keys, set_shift, set_root, set_e2, set_minpts, flag, grids, 0.f, 0, 0, 0};
   wave_walks(nodes, leaf, keys, n, wc, v, err);
 }
 
 // Pair traversal; each lane runs the minPts <= 2 or the minPts > 2 rule of
 // its own set (both ends of a pair are always in the same set).
 struct PairSets {
-  static constexpr bool kBounded = false;
-  __device__ uint64_t khi() const { return ~0ull; }
+  static constexpr bool kBounded = true;
+  static constexpr bool kStartIsRope = true;  // the query leaf's rope
+  __device__ uint64_t khi() const { return hi; }
   const uint64_t* keys;
   int set_shift;
   const float* set_e2;
@@ -145,14 +155,19 @@ struct PairSets {
   int32_t* parent;
   uint8_t* flag;
   unsigned long long* bestcore;
+  const MortonGrid* grids;
   float r2;
   bool core_mode, ci, found;
+  uint64_t hi;
+  int32_t ri;  // an ancestor of the query's point in the union-find forest
   __device__ int32_t begin(uint32_t i, const float4& q) {
     const uint32_t set = uint32_t(keys[i] >> set_shift);
     r2 = set_e2[set];
+    hi = set_upper_code(grids, set, set_shift, q, r2);
     core_mode = set_minpts[set] > 2;
     ci = core_mode ? flag[i] != 0 : true;
     found = false;
+    ri = int32_t(i);
     return __float_as_int(q.w);
   }
   __device__ float e2() const { return r2; }
@@ -160,12 +175,12 @@ struct PairSets {
   __device__ bool hit(uint32_t i, int32_t j, const float4&) {
     if (!core_mode) {
       found = true;
-      uf_union(parent, int32_t(i), j);
+      ri = uf_union(parent, ri, j);
       flag[j] = 1;
       return false;
     }
     const bool cj = flag[j] != 0;
-    if (ci && cj) uf_union(parent, int32_t(i), j);
+    if (ci && cj) ri = uf_union(parent, ri, j);
     else if (ci) atomicMin(bestcore + j, (static_cast<unsigned long long>(perm[i]) << 32) | i);
     else if (cj)
       atomicMin(bestcore + i, (static_cast<unsigned long long>(perm[j]) << 32) | uint32_t(j));
@@ -182,19 +197,14 @@ __global__ void k_pairs_sets(const Node* __restrict__ nodes, const float4* __res
                              int set_shift,
                              const float* __restrict__ set_e2,
                              const int32_t* __restrict__ set_minpts,
+                             const MortonGrid* __restrict__ grids,
                              const uint32_t* __restrict__ perm, int32_t* parent, uint8_t* flag,
                              unsigned long long* bestcore, uint32_t* err) {
-  PairSets v{keys, set_shift, set_e2, set_minpts, perm, parent, flag, bestcore,
-             0.f, false, true, false};
+  PairSets v{keys, set_shift, set_e2, set_minpts, perm, parent, flag, bestcore, grids,
+             0.f, false, true, false, 0, 0};
   wave_walks(nodes, leaf, keys, n, wc, v, err);
 }
 
-// Find without compression (the forest no longer changes).
-__device__ __forceinline__ int32_t root_of(const int32_t* parent, int32_t x) {
-  int32_t p = parent[x];
-  while (p != x) { x = p; p = parent[x]; }
-  return x;
-}
 
 __global__ __launch_bounds__(256) void k_final_roots_sets(
     uint32_t n, const uint64_t* __restrict__ keys, int set_shift,
@@ -202,20 +212,22 @@ __global__ __launch_bounds__(256) void k_final_roots_sets(
     const unsigned long long* __restrict__ bestcore, const uint32_t* __restrict__ perm,
     int32_t* parent, int32_t* __restrict__ minlab, int32_t* __restrict__ labels) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  labels[i] = -1;  // the second pass writes clustered points only
-  const int32_t mp = set_minpts[uint32_t(keys[i] >> set_shift)];
-  int32_t r;
-  if (mp <= 2) {
-    r = (mp == 1 || flag[i]) ? root_of(parent, int32_t(i)) : -1;
-  } else if (flag[i]) {
-    r = root_of(parent, int32_t(i));
-  } else {
-    const unsigned long long b = bestcore[i];
-    r = b == ~0ull ? -1 : root_of(parent, int32_t(uint32_t(b)));
+  const bool ok = i < n;  // no early return: the wave combines its minima
+  int32_t r = -1;
+  if (ok) {
+    labels[i] = -1;  // the second pass writes clustered points only
+    const int32_t mp = set_minpts[uint32_t(keys[i] >> set_shift)];
+    if (mp <= 2) {
+      r = (mp == 1 || flag[i]) ? uf_root_final(parent, int32_t(i)) : -1;
+    } else if (flag[i]) {
+      r = uf_root_final(parent, int32_t(i));
+    } else {
+      const unsigned long long b = bestcore[i];
+      r = b == ~0ull ? -1 : uf_root_final(parent, int32_t(uint32_t(b)));
+    }
   }
-  if (r >= 0) atomicMin(minlab + r, int32_t(perm[i]));
-  parent[i] = r;
+  wave_min_by_key(minlab, r, r >= 0 ? int32_t(perm[i]) : 0);
+  if (ok) parent[i] = r;
 }
 
 __global__ __launch_bounds__(256) void k_final_labels_sets(
@@ -236,28 +248,31 @@ __global__ __launch_bounds__(256) void k_final_labels_sets(
 
 void launch_set_morton(const float* pts, const int64_t* offsets, uint32_t num_sets, int bits,
                        int set_shift, uint64_t* keys, uint32_t* hist, int32_t* set_root,
-                       uint32_t* status, hipStream_t s) {
+                       MortonGrid* grids, uint32_t* status, hipStream_t s) {
   if (num_sets == 0) return;
   hipLaunchKernelGGL(k_set_morton, dim3(num_sets), dim3(256), 0, s, pts, offsets, bits, set_shift,
-                     keys, hist, set_root, status);
+                     keys, hist, set_root, grids, status);
 }
 
 void launch_count_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
                        int set_shift, const int32_t* set_root, const float* set_e2,
-                       const int32_t* set_minpts, uint8_t* flag, uint32_t* err, int block,
-                       hipStream_t s) {
+                       const int32_t* set_minpts, const MortonGrid* grids, uint8_t* flag,
+                       uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_count_sets, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     n, walk_cfg(n), keys, set_shift, set_root, set_e2, set_minpts, flag, err);
+                     n, walk_cfg(n), keys, set_shift, set_root, set_e2, set_minpts, grids, flag,
+                     err);
 }
 
 void launch_pairs_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
                        int set_shift, const float* set_e2, const int32_t* set_minpts,
-                       const uint32_t* perm, int32_t* parent, uint8_t* flag,
-                       unsigned long long* bestcore, uint32_t* err, int block, hipStream_t s) {
+                       const MortonGrid* grids, const uint32_t* perm, int32_t* parent,
+                       uint8_t* flag, unsigned long long* bestcore, uint32_t* err, int block,
+                       hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs_sets, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     n, walk_cfg(n), keys, set_shift, set_e2, set_minpts, perm, parent, flag,
+                     n, walk_cfg(n), keys, set_shift, set_e2, set_minpts, grids, perm, parent,
+                     flag,
                      bestcore, err);
 }
 

@@ -78,6 +78,14 @@ __device__ __forceinline__ void st_agent(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <class T>
+__device__ __forceinline__ T ld_wg(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <class T>
+__device__ __forceinline__ void st_wg(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <class T>
 __device__ __forceinline__ T cas_agent(T* p, T expected, T desired) {
   __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -90,27 +98,78 @@ __device__ __forceinline__ T cas_agent(T* p, T expected, T desired) {
 // land in, and every value ever stored is an ancestor.  Roots are hooked by
 // CAS (larger root under smaller); path halving uses plain relaxed stores,
 // which only ever touch non-roots and so never undo a hook.
+//
+// The finds read and halve at workgroup scope: a load may hit a stale line
+// in the CU's own cache.  That is safe.  Every value parent[x] ever held is
+// a node of x's set, smaller than x, so a stale read still moves down a
+// strictly decreasing chain of x's set, and a stale "root" r is still in
+// the set.  A union that ends because both finds met the same node joins
+// two nodes that are already connected; one whose CAS expects a stale root
+// fails (the CAS is at agent scope and sees the true value) and continues
+// from the value it found, which is smaller: so every union ends.  Finds
+// after the kernel (label finalisation) run in a later launch and see the
+// final forest.
 __device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
   for (;;) {
-    int32_t p = ld_agent(parent + x);
+    int32_t p = ld_wg(parent + x);
     if (p == x) return x;
-    int32_t gp = ld_agent(parent + p);
+    int32_t gp = ld_wg(parent + p);
     if (gp == p) return p;
-    st_agent(parent + x, gp);
+    st_wg(parent + x, gp);
     x = gp;
   }
 }
 
-__device__ __forceinline__ void uf_union(int32_t* parent, int32_t a, int32_t b) {
+// Union of the sets of a and b.  Returns a node that is, at return, an
+// ancestor of both (the merged root or, if others hooked it meanwhile, one
+// of its descendants): a walk that unions one point with many neighbours
+// passes it back as `a` and so starts each find from high up its chain.
+__device__ __forceinline__ int32_t uf_union(int32_t* parent, int32_t a, int32_t b) {
   for (;;) {
     a = uf_find(parent, a);
     b = uf_find(parent, b);
-    if (a == b) return;
+    if (a == b) return a;
     if (a > b) { int32_t t = a; a = b; b = t; }
     int32_t seen = cas_agent(parent + b, b, a);
-    if (seen == b) return;
+    if (seen == b) return a;
     b = seen;  // b was hooked under `seen` meanwhile: continue from there
   }
+}
+
+// atomicMin(dst + key, v) for every lane with key >= 0; every lane of the
+// wave must call it.  In a dense cluster most of a wave's points share one
+// root, and one atomic per member on that single address serialises; so
+// while the key of the lowest pending lane is held by at least 4 lanes,
+// those lanes' minimum goes out as one atomic (at most 4 such rounds), and
+// the rest take one atomic each.
+__device__ __forceinline__ void wave_min_by_key(int32_t* dst, int32_t key, int32_t v) {
+  const int lane = threadIdx.x & 63;
+  int32_t k = key;
+  for (int round = 0; round < 4; ++round) {
+    const uint64_t pend = __ballot(k >= 0);
+    if (pend == 0) return;
+    const int leader = __ffsll(static_cast<long long>(pend)) - 1;
+    const int32_t kl = __builtin_amdgcn_readlane(k, leader);
+    const bool mine = k == kl;
+    if (__popcll(__ballot(mine)) < 4) break;
+    const int32_t m = __ockl_wfred_min_i32(mine ? v : 0x7fffffff);
+    if (lane == leader) atomicMin(dst + kl, m);
+    if (mine) k = -1;
+  }
+  if (k >= 0) atomicMin(dst + k, v);
+}
+
+// Root of x once the forest no longer changes, compressing x's chain onto
+// it (plain loads and stores: every value written is the final root).
+__device__ __forceinline__ int32_t uf_root_final(int32_t* parent, int32_t x) {
+  int32_t r = x, p = parent[r];
+  while (p != r) { r = p; p = parent[r]; }
+  while (x != r) {
+    const int32_t nx = parent[x];
+    parent[x] = r;
+    x = nx;
+  }
+  return r;
 }
 
 // ---- Morton codes (section 4.2.2) ------------------------------------------
@@ -125,19 +184,22 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
   return x;
 }
 
-// grid coordinate of p on one axis: min(floor((p - lo) * s), 2^21 - 1) in
-// binary32, s = 2^21 / extent (0 for a zero extent); monotone in p
-__device__ __forceinline__ uint32_t quantise(float p, float lo, float s) {
+// grid coordinate of p on one axis: min(floor((p - lo) * s), maxc) in
+// binary32, s = (maxc + 1) / extent (0 for a zero extent), maxc = 2^b - 1
+// for b bits per axis; monotone in p
+__device__ __forceinline__ uint32_t quantise(float p, float lo, float s,
+                                             float maxc = float((1u << MORTON_BITS) - 1)) {
 #pragma clang fp contract(off)
   float t = (p - lo) * s;
-  t = fminf(fmaxf(floorf(t), 0.0f), float((1u << MORTON_BITS) - 1));  // NaN -> 0
+  t = fminf(fmaxf(floorf(t), 0.0f), maxc);  // NaN -> 0
   return uint32_t(t);
 }
 
 __device__ __forceinline__ uint64_t morton_of(float x, float y, float z, const float* lo,
-                                              const float* s) {
-  return (spread3(quantise(x, lo[0], s[0])) << 2) | (spread3(quantise(y, lo[1], s[1])) << 1) |
-         spread3(quantise(z, lo[2], s[2]));
+                                              const float* s,
+                                              float maxc = float((1u << MORTON_BITS) - 1)) {
+  return (spread3(quantise(x, lo[0], s[0], maxc)) << 2) |
+         (spread3(quantise(y, lo[1], s[1], maxc)) << 1) | spread3(quantise(z, lo[2], s[2], maxc));
 }
 
 // Ordered-integer view of a float for atomic min/max of scene bounds.
@@ -176,16 +238,21 @@ __device__ inline int droppable_code_bits(const uint32_t* bounds, float eps) {
 
 // The grid the Morton codes quantise to, from the scene bounds words
 // (bounds[0..2] lo, [3..5] hi, ordered ints).
+// (Batched sets: one grid per set, b bits per axis, maxc = 2^b - 1.)
 struct MortonGrid {
   float lo[3], s[3];
+  float maxc;
   __device__ void load(const uint32_t* bounds) {
     for (int a = 0; a < 3; ++a) {
       lo[a] = ord2f(bounds[a]);
       const float ext = ord2f(bounds[3 + a]) - lo[a];
       s[a] = ext > 0.0f ? float(1u << MORTON_BITS) / ext : 0.0f;  // IEEE division
     }
+    maxc = float((1u << MORTON_BITS) - 1);
   }
-  __device__ uint64_t code(float x, float y, float z) const { return morton_of(x, y, z, lo, s); }
+  __device__ uint64_t code(float x, float y, float z) const {
+    return morton_of(x, y, z, lo, s, maxc);
+  }
   // A code no smaller than that of any point p with sq_dist(q, p) <= e2.
   // Such a p has |p_a - q_a| <= sqrt(e2) (1 + 3u) on every axis (u = 2^-24),
   // so p_a <= h_a = q_a + pad (pad covers that and the rounding of the sum,

@@ -14,17 +14,10 @@ namespace dbx {
 
 namespace {
 
-// Find without compression: after the pair phase the forest no longer
-// changes, so plain loads see a consistent ancestor chain.
-__device__ __forceinline__ int32_t root_of(const int32_t* parent, int32_t x) {
-  int32_t p = parent[x];
-  while (p != x) { x = p; p = parent[x]; }
-  return x;
-}
-
-// First pass: cluster root of every point (or -1), and the smallest input
-// index per root.  The root is written over parent[i]; that only shortens
-// other points' chains (a root is an ancestor), and noise points are
+// First pass: cluster root of every point (or -1; the chains are
+// compressed onto it on the way), and the smallest input index per root.
+// The root is written over parent[i]; that only shortens other points'
+// chains (a root is an ancestor), and noise points are
 // singletons nobody else's chain passes through.  It also sets every label
 // to -1 (coalesced: input index i, whatever point sits at sorted position
 // i), so the second pass only writes the labels of clustered points: for
@@ -35,19 +28,21 @@ __global__ __launch_bounds__(256) void k_final_roots(
     const unsigned long long* __restrict__ bestcore, const uint32_t* __restrict__ perm,
     int32_t* parent, int32_t* __restrict__ minlab, int32_t* __restrict__ labels) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  labels[i] = -1;
-  int32_t r;
-  if (min_pts <= 2) {
-    r = (min_pts == 1 || flag[i]) ? root_of(parent, int32_t(i)) : -1;
-  } else if (flag[i]) {  // core
-    r = root_of(parent, int32_t(i));
-  } else {
-    unsigned long long b = bestcore[i];
-    r = b == ~0ull ? -1 : root_of(parent, int32_t(uint32_t(b)));
+  const bool ok = i < n;  // no early return: the wave combines its minima
+  int32_t r = -1;
+  if (ok) {
+    labels[i] = -1;
+    if (min_pts <= 2) {
+      r = (min_pts == 1 || flag[i]) ? uf_root_final(parent, int32_t(i)) : -1;
+    } else if (flag[i]) {  // core
+      r = uf_root_final(parent, int32_t(i));
+    } else {
+      unsigned long long b = bestcore[i];
+      r = b == ~0ull ? -1 : uf_root_final(parent, int32_t(uint32_t(b)));
+    }
   }
-  if (r >= 0) atomicMin(minlab + r, int32_t(perm[i]));
-  parent[i] = r;
+  wave_min_by_key(minlab, r, r >= 0 ? int32_t(perm[i]) : 0);
+  if (ok) parent[i] = r;
 }
 
 __global__ __launch_bounds__(256) void k_final_labels(uint32_t n, const uint32_t* __restrict__ perm,

@@ -180,18 +180,20 @@ void launch_pairs_db(const Node* nodes, const Node* prims, uint32_t nprims, cons
 
 // ---- batched sets (batched.hip) -----------------------------------------------
 // Keys of every set: (set id << set_shift) | Morton code with `bits` bits per
-// axis inside the set's own bounding box; set_root[s] = -1 for every set.
+// axis inside the set's own bounding box; set_root[s] = -1 for every set;
+// grids[s] = set s's quantisation grid (for the walks' early end).
 void launch_set_morton(const float* pts, const int64_t* offsets, uint32_t num_sets, int bits,
                        int set_shift, uint64_t* keys, uint32_t* hist, int32_t* set_root,
-                       uint32_t* status, hipStream_t s);
+                       MortonGrid* grids, uint32_t* status, hipStream_t s);
 void launch_count_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
                        int set_shift, const int32_t* set_root, const float* set_e2,
-                       const int32_t* set_minpts, uint8_t* flag, uint32_t* err, int block,
-                       hipStream_t s);
+                       const int32_t* set_minpts, const MortonGrid* grids, uint8_t* flag,
+                       uint32_t* err, int block, hipStream_t s);
 void launch_pairs_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
                        int set_shift, const float* set_e2, const int32_t* set_minpts,
-                       const uint32_t* perm, int32_t* parent, uint8_t* flag,
-                       unsigned long long* bestcore, uint32_t* err, int block, hipStream_t s);
+                       const MortonGrid* grids, const uint32_t* perm, int32_t* parent,
+                       uint8_t* flag, unsigned long long* bestcore, uint32_t* err, int block,
+                       hipStream_t s);
 // labels are set-local: smallest input index in the cluster minus the
 // set's offset
 void launch_final_sets(uint32_t n, const uint64_t* keys, int set_shift, const int32_t* set_minpts,

@@ -23,6 +23,7 @@ namespace {
 // counting: walk from the root, stop at minPts neighbours
 struct CountCore {
   static constexpr bool kBounded = true;
+  static constexpr bool kStartIsRope = false;  // the root
   int32_t root, min_pts, cnt;
   float r2;
   uint8_t* is_core;
@@ -56,6 +57,7 @@ enum PairMode { FOF = 0, CORE = 1, COUNT = 2 };
 template <int MODE>
 struct PairVisit {
   static constexpr bool kBounded = true;
+  static constexpr bool kStartIsRope = true;  // the query leaf's rope
   float r2;
   const uint8_t* is_core;
   const uint32_t* perm;
@@ -63,6 +65,7 @@ struct PairVisit {
   uint8_t* member;
   unsigned long long* bestcore;
   bool ci, found;
+  int32_t ri;  // an ancestor of the query's point in the union-find forest
   uint32_t pairs, visits, descents, leaves;  // COUNT only: this query's counts
   unsigned long long tot[4];                 // COUNT only: this lane's totals
   MortonGrid grid;
@@ -70,6 +73,7 @@ struct PairVisit {
   __device__ uint64_t khi() const { return hi; }
   __device__ int32_t begin(uint32_t i, const float4& q) {
     found = false;
+    ri = int32_t(i);
     hi = grid.upper_code(q, r2) & mask;
     if (MODE == COUNT) pairs = visits = descents = leaves = 0;
     if (MODE == CORE) ci = is_core[i] != 0;
@@ -89,11 +93,11 @@ struct PairVisit {
   __device__ bool hit(uint32_t i, int32_t j, const float4&) {
     if (MODE == FOF) {
       found = true;
-      uf_union(parent, int32_t(i), j);
+      ri = uf_union(parent, ri, j);
       member[j] = 1;
     } else if (MODE == CORE) {
       const bool cj = is_core[j] != 0;
-      if (ci && cj) uf_union(parent, int32_t(i), j);
+      if (ci && cj) ri = uf_union(parent, ri, j);
       else if (ci) atomicMin(bestcore + j, (static_cast<unsigned long long>(perm[i]) << 32) | i);
       else if (cj)
         atomicMin(bestcore + i, (static_cast<unsigned long long>(perm[j]) << 32) | uint32_t(j));
@@ -123,7 +127,7 @@ __global__ void k_pairs(const Node* __restrict__ nodes, const float4* __restrict
                         const uint8_t* __restrict__ is_core, const uint32_t* __restrict__ perm,
                         int32_t* parent, uint8_t* member, unsigned long long* bestcore,
                         unsigned long long* count, uint32_t* err) {
-  PairVisit<MODE> v{e2, is_core, perm, parent, member, bestcore, true, false, 0, 0, 0, 0,
+  PairVisit<MODE> v{e2, is_core, perm, parent, member, bestcore, true, false, 0, 0, 0, 0, 0,
                     {0, 0, 0, 0}, {}, 0, ~0ull << (drop ? *drop : 0u)};
   v.grid.load(bounds);
   wave_walks(nodes, leaf, keys, n, wc, v, err);

@@ -18,7 +18,10 @@
 // first key exceeds khi, no leaf left in the walk can be a neighbour, and
 // it ends.  (The first key is read with the node, in the same step.)
 //
-// The visitor V holds the per-lane state of the lane's current query:
+// The visitor V says whether its walks start at a rope target (pair walks:
+// the query leaf's rope; a walk from a set's root does not, that node may
+// be numbered by its last leaf), kStartIsRope, and holds the per-lane state
+// of the lane's current query:
 //   int32_t begin(uint32_t i, const float4& q)  first node of query i
 //   uint64_t khi() const                        the early-end bound (all
 //                                               ones: never end early)
@@ -104,7 +107,7 @@ __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
   bool have = false;   // lane holds query i whose end() is still due
   int32_t node = SENTINEL;
   uint32_t steps = 0;
-  bool by_rope = true;  // node was reached through a rope (or is the start)
+  bool by_rope = false;  // node was reached through a rope: its number is its first leaf
   float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
   for (;;) {
     // hand the chunk's next queries to the idle lanes
@@ -119,7 +122,7 @@ __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
         q = leaf[i];
         node = v.begin(i, q);
         steps = 0;
-        by_rope = true;
+        by_rope = V::kStartIsRope;
       }
     }
     const uint32_t h = head + uint32_t(__popcll(m));
