@@ -107,7 +107,10 @@ int dbscan_cluster_ex(dbscan_ctx* ctx, const float* points, int64_t n, float eps
  * build in which every set is a subtree, one traversal.  labels (device
  * int32[offsets[num_sets]]) are set-local: -1 or the smallest index within
  * the set of the point's cluster, exactly what dbscan_cluster returns for
- * that set alone.  FDBSCAN only (DENSEBOX is EINVAL); num_sets <= 2^20. */
+ * that set alone.  Both algorithms: with DENSEBOX every set gets its own
+ * grid of cells (side eps[k]/sqrt(3)) and dense threshold
+ * (opts->dense_threshold, 0 = each set's min_pts; below any set's min_pts is
+ * EINVAL).  num_sets <= 2^20. */
 int dbscan_cluster_batched(dbscan_ctx* ctx, const float* points, const int64_t* offsets,
                            int32_t num_sets, const float* eps, const int32_t* min_pts,
                            int32_t* labels, void* stream, const dbscan_options* opts);
@@ -137,7 +140,10 @@ int dbscan_sort_passes(const dbscan_ctx* ctx);
  * workgroup sizes 64/128/256/512; for DenseBox also dense thresholds minPts,
  * 2*minPts, 4*minPts), time each (best of two after a warm-up, HIP events on
  * `stream`) and return the fastest in *best (its time in *best_ms).  The
- * candidates cannot change the labels, which end in `labels` (device). */
+ * candidates cannot change the labels, which end in `labels` (device).
+ * The batched tuner tries both algorithms: FDBSCAN at each workgroup size,
+ * and DenseBox at each workgroup size with thresholds 0 (each set's minPts),
+ * 2 and 4 times the largest minPts. */
 int dbscan_autotune(dbscan_ctx* ctx, const float* points, int64_t n, float eps,
                     int32_t min_pts, int32_t algorithm, int32_t* labels,
                     dbscan_options* best, float* best_ms, void* stream);

@@ -22,6 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libdbscan_mi355x.so"
 
 ALGO = {"auto": 0, "fdbscan": 1, "densebox": 2}
+ALGO_NAME = {v: k for k, v in ALGO.items()}
 FLAG_TIMING = 1
 FLAG_GRAPH = 2
 STATUS = {0: "ok", -1: "invalid argument", -2: "non-finite coordinate",
@@ -188,11 +189,13 @@ class Context:
         return labels
 
     def cluster_batched(self, points, offsets, eps, min_pts, block_size: int = 0,
-                        timing: bool = False, out=None, graph: bool = False):
+                        timing: bool = False, out=None, graph: bool = False,
+                        algorithm: str = "auto", dense_threshold: int = 0):
         """Cluster the sets points[offsets[k]:offsets[k+1]] independently in
         one pass; ``eps`` and ``min_pts`` are scalars or one value per set.
         Labels are set-local (-1 noise, else the smallest index within the
-        set of the point's cluster)."""
+        set of the point's cluster).  ``algorithm``: "auto"/"fdbscan" or
+        "densebox" (``dense_threshold`` 0 = each set's min_pts)."""
         import numpy as np
         torch = _torch()
         p = _points(points)
@@ -205,7 +208,7 @@ class Context:
                                  dtype=np.int32)
         labels = out if out is not None else torch.empty(p.shape[0], dtype=torch.int32,
                                                          device=p.device)
-        o = _Options(ALGO["fdbscan"], 0, int(block_size),
+        o = _Options(ALGO[algorithm], int(dense_threshold), int(block_size),
                      (FLAG_TIMING if timing else 0) | (FLAG_GRAPH if graph else 0))
         _check(load_library().dbscan_cluster_batched(
             self.handle, ctypes.c_void_p(p.data_ptr()),
@@ -245,7 +248,8 @@ class Context:
             e.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
             m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.c_void_p(lab.data_ptr()),
             ctypes.byref(o), ctypes.byref(ms), _stream(p.device)))
-        return {"block_size": o.block_size, "ms": ms.value}
+        return {"algorithm": ALGO_NAME[o.algorithm], "block_size": o.block_size,
+                "dense_threshold": o.dense_threshold, "ms": ms.value}
 
     def sort_passes(self) -> int:
         """Sort passes the last plain clustering call ran (the rest skipped)."""

@@ -60,6 +60,7 @@ struct Layout {
   // DenseBox only (0 otherwise)
   size_t cid, head, cell_start, cell_lo, cell_hi, cell_minorig, cell_dense, prim_count,
       prim_start, prims, pkey, scan1, scan2, scan_ctr, ncells, nprims;
+  size_t set_e2, set_mp, set_th, grid;  // the one-set table of a plain DenseBox call
   uint32_t pending_entries;
   size_t zero;        // start of the region zeroed by k_prep
   size_t hist, tile_ctr, status, count, sort_status;
@@ -100,6 +101,10 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
     L.prim_start = take(size_t(n) * 4);
     L.prims = take(size_t(n) * sizeof(Node));
     L.pkey = take(size_t(n) * 8);
+    L.set_e2 = take(4);
+    L.set_mp = take(4);
+    L.set_th = take(4);
+    L.grid = take(sizeof(MortonGrid));
   }
   L.bounds = take(8 * 4);
   L.drop = take(4);
@@ -428,26 +433,18 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
   return finish(c, at<uint32_t>(c, L.status), timing, s, at<uint32_t>(c, L.drop));
 }
 
-int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t min_pts,
-                 int32_t* labels, hipStream_t s, const dbscan_options& o) {
-  const bool timing = (o.flags & DBSCAN_FLAG_TIMING) != 0;
-  const int block = o.block_size ? o.block_size : 256;
-  const float e2 = eps * eps;
-  const bool core_mode = min_pts > 2;
-  const int32_t thresh = o.dense_threshold ? o.dense_threshold : min_pts;
-  // side h = eps / sqrt(3), shrunk a little so rounding rarely makes a full
-  // cell's diagonal exceed eps (the dense test on the actual box decides)
-  const double h = double(eps) / std::sqrt(3.0) * (1.0 - 1e-4);
-  const float inv_h = h > 0 ? float(1.0 / h) : INFINITY;
-
-  Layout L = make_layout(n, core_mode, true);
-  int st = ensure_arena(c, L.total);
-  if (st != DBSCAN_OK) return st;
+// DenseBox from the (unsorted) cell keys in keys_a, their digit counts in
+// hist and the set table on: sort, cells, primitives, build, walks, labels.
+// One host synchronisation reads the primitive count, which sizes the build.
+// d_off: the sets' offsets (batched calls; labels set-local), else null
+// and min_pts is the plain call's.
+int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_t n,
+                       DbSets S, bool any_core, const int64_t* d_off, int32_t min_pts,
+                       int32_t* labels, int block, bool timing, hipStream_t s) {
   uint64_t* ka = at<uint64_t>(c, L.keys_a);
   uint64_t* kb = at<uint64_t>(c, L.keys_b);
   uint32_t* va = at<uint32_t>(c, L.vals_a);
   uint32_t* vb = at<uint32_t>(c, L.vals_b);
-  uint32_t* bounds = at<uint32_t>(c, L.bounds);
   uint32_t* status = at<uint32_t>(c, L.status);
   SortScratch sc{at<uint32_t>(c, L.hist), at<uint32_t>(c, L.tile_ctr),
                  at<uint32_t>(c, L.sort_status), status};
@@ -455,15 +452,8 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
   int32_t* parent = at<int32_t>(c, L.parent);
   uint8_t* flag = at<uint8_t>(c, L.flag);
   int32_t* minlab = at<int32_t>(c, L.minlab);
-  unsigned long long* bestcore = core_mode ? at<unsigned long long>(c, L.bestcore) : nullptr;
+  unsigned long long* bestcore = any_core ? at<unsigned long long>(c, L.bestcore) : nullptr;
 
-  start_timing(c, timing, s);
-  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, s);
-  mark(c, timing, PH_PREP, s);
-  launch_bounds(pts, n, bounds, status, s);
-  mark(c, timing, PH_BOUNDS, s);
-  launch_cell_keys(pts, n, bounds, inv_h, ka, sc.hist, s);
-  mark(c, timing, PH_MORTON, s);
   SortMarks sm{c, s};
   const bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, s,
                                       timing ? sort_mark : nullptr, &sm);
@@ -482,14 +472,14 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
   launch_cells(keys, n, at<uint32_t>(c, L.head), cid, ncells, cell_start,
                at<uint32_t>(c, L.scan1), scan_ctr, status, s);
   unsigned long long* cell_minorig =
-      core_mode ? at<unsigned long long>(c, L.cell_minorig) : nullptr;
+      any_core ? at<unsigned long long>(c, L.cell_minorig) : nullptr;
   float4* cell_lo = at<float4>(c, L.cell_lo);
   float4* cell_hi = at<float4>(c, L.cell_hi);
   uint8_t* cell_dense = at<uint8_t>(c, L.cell_dense);
   uint32_t* prim_count = at<uint32_t>(c, L.prim_count);
   uint32_t* prim_start = at<uint32_t>(c, L.prim_start);
-  launch_cell_stats(spts, perm, n, ncells, cell_start, e2, thresh, cell_lo, cell_hi,
-                    cell_minorig, cell_dense, prim_count, s);
+  launch_cell_stats(spts, perm, keys, n, ncells, cell_start, S, cell_lo, cell_hi, cell_minorig,
+                    cell_dense, prim_count, s);
   launch_scan(prim_count, prim_start, n, nprims, at<uint32_t>(c, L.scan2), scan_ctr + 1, status,
               s);
   HIP_TRY(hipMemcpyAsync(c->host_status + 4, ncells, 8, hipMemcpyDeviceToHost, s));
@@ -504,29 +494,76 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
   mark(c, timing, PH_CELLS, s);
 
   Node* nodes = at<Node>(c, L.nodes);
-  int32_t* root = at<int32_t>(c, L.root);
-  launch_build_boxes(pkey, prims, np, nodes, other, root, at<int4>(c, L.pending), status, s);
+  launch_build_boxes(pkey, S.shift, prims, np, nodes, other, const_cast<int32_t*>(S.root),
+                     at<int4>(c, L.pending), status, s);
   mark(c, timing, PH_BUILD_LEVELS, s);
-  if (core_mode)
-    launch_count_db(nodes, prims, np, spts, n, cell_start, root, e2, min_pts, flag, status, block,
-                    s);
+  const DbTables T{spts, cell_start, perm, cell_minorig, cell_lo, cell_hi, parent, flag,
+                   bestcore};
+  if (any_core) launch_count_db(nodes, prims, pkey, np, S, T, status, block, s);
   mark(c, timing, PH_COUNT, s);
-  launch_pairs_db(nodes, prims, np, spts, n, cell_start, perm, cell_minorig, e2, core_mode,
-                  parent, flag, bestcore, status, block, s);
+  launch_pairs_db(nodes, prims, pkey, np, S, T, status, block, s);
   mark(c, timing, PH_PAIRS, s);
-  launch_final_roots(n, min_pts, flag, bestcore, perm, parent, minlab, labels, s);
-  mark(c, timing, PH_FINAL_ROOTS, s);
-  launch_final_labels(n, perm, parent, minlab, labels, s);
-  mark(c, timing, PH_FINAL_LABELS, s);
+  if (d_off) {
+    launch_final_sets(n, keys, S.shift, S.minpts, d_off, flag, bestcore, perm, parent, minlab,
+                      labels, s);
+    mark(c, timing, PH_FINAL_LABELS, s);
+  } else {
+    launch_final_roots(n, min_pts, flag, bestcore, perm, parent, minlab, labels, s);
+    mark(c, timing, PH_FINAL_ROOTS, s);
+    launch_final_labels(n, perm, parent, minlab, labels, s);
+    mark(c, timing, PH_FINAL_LABELS, s);
+  }
+  return DBSCAN_OK;
+}
+
+// side of a DenseBox cell: eps / sqrt(3), shrunk a little so rounding rarely
+// makes a full cell's diagonal exceed eps (the dense test on the actual box
+// decides); its inverse, infinite for eps = 0
+float inv_cell_side(float eps) {
+  const double h = double(eps) / std::sqrt(3.0) * (1.0 - 1e-4);
+  return h > 0 ? float(1.0 / h) : INFINITY;
+}
+
+int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t min_pts,
+                 int32_t* labels, hipStream_t s, const dbscan_options& o) {
+  const bool timing = (o.flags & DBSCAN_FLAG_TIMING) != 0;
+  const int block = o.block_size ? o.block_size : 256;
+  const bool core_mode = min_pts > 2;
+  const int32_t thresh = o.dense_threshold ? o.dense_threshold : min_pts;
+
+  Layout L = make_layout(n, core_mode, true);
+  int st = ensure_arena(c, L.total);
+  if (st != DBSCAN_OK) return st;
+  uint32_t* bounds = at<uint32_t>(c, L.bounds);
+  uint32_t* status = at<uint32_t>(c, L.status);
+  MortonGrid* grid = at<MortonGrid>(c, L.grid);
+  const DbSets S{at<float>(c, L.set_e2), at<int32_t>(c, L.set_mp), at<int32_t>(c, L.set_th),
+                 grid, at<int32_t>(c, L.root), 64};
+
+  start_timing(c, timing, s);
+  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, s);
+  launch_one_set(eps * eps, min_pts, thresh, const_cast<float*>(S.e2),
+                 const_cast<int32_t*>(S.minpts), const_cast<int32_t*>(S.thresh), s);
+  mark(c, timing, PH_PREP, s);
+  launch_bounds(pts, n, bounds, status, s);
+  mark(c, timing, PH_BOUNDS, s);
+  launch_cell_keys(pts, n, bounds, inv_cell_side(eps), at<uint64_t>(c, L.keys_a),
+                   at<uint32_t>(c, L.hist), grid, s);
+  mark(c, timing, PH_MORTON, s);
+  st = densebox_from_keys(c, L, pts, n, S, core_mode, nullptr, min_pts, labels, block, timing,
+                          s);
+  if (st != DBSCAN_OK) return st;
   HIP_TRY(hipGetLastError());
   return finish(c, status, timing, s);
 }
 
 // Many independent sets in one pass (keys tagged with the set id).
+// DenseBox: no graph (a host synchronisation sizes the build).
 int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t num_sets,
                 const float* h_eps, const int32_t* h_minpts, int32_t* labels, hipStream_t s,
                 const dbscan_options& o) {
-  const bool graph = (o.flags & DBSCAN_FLAG_GRAPH) != 0;
+  const bool db = o.algorithm == DBSCAN_ALGO_DENSEBOX;
+  const bool graph = !db && (o.flags & DBSCAN_FLAG_GRAPH) != 0;
   const bool timing = !graph && (o.flags & DBSCAN_FLAG_TIMING) != 0;
   const int block = o.block_size ? o.block_size : 256;
   const uint32_t n = uint32_t(h_off[num_sets]);
@@ -537,17 +574,20 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
   bool any_core = false;
   for (uint32_t k = 0; k < num_sets; ++k) any_core |= h_minpts[k] > 2;
 
-  Layout L = make_layout(n, any_core);
-  // per-set arrays after the job's buffers: offsets, e2, minPts, roots
+  Layout L = make_layout(n, any_core, db);
+  // per-set arrays after the job's buffers: offsets, e2, minPts, dense
+  // threshold, inverse cell side, roots, grids
   const size_t off_b = align_up(L.total);
   const size_t e2_b = off_b + align_up((size_t(num_sets) + 1) * 8);
   const size_t mp_b = e2_b + align_up(size_t(num_sets) * 4);
-  const size_t root_b = mp_b + align_up(size_t(num_sets) * 4);
+  const size_t th_b = mp_b + align_up(size_t(num_sets) * 4);
+  const size_t ih_b = th_b + align_up(size_t(num_sets) * 4);
+  const size_t root_b = ih_b + align_up(size_t(num_sets) * 4);
   const size_t grid_b = root_b + align_up(size_t(num_sets) * 4);
   const size_t total = grid_b + align_up(size_t(num_sets) * sizeof(MortonGrid));
   int st = ensure_arena(c, total);
   if (st != DBSCAN_OK) return st;
-  const size_t stage_bytes = (size_t(num_sets) + 1) * 8 + size_t(num_sets) * 8;
+  const size_t stage_bytes = (size_t(num_sets) + 1) * 8 + size_t(num_sets) * 16;
   if (c->stage_cap < stage_bytes) {
     HIP_TRY(hipStreamSynchronize(s));  // the old staging buffer may still be read
     if (c->stage) (void)hipHostFree(c->stage);
@@ -560,10 +600,14 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
   int64_t* s_off = reinterpret_cast<int64_t*>(c->stage);
   float* s_e2 = reinterpret_cast<float*>(s_off + num_sets + 1);
   int32_t* s_mp = reinterpret_cast<int32_t*>(s_e2 + num_sets);
+  int32_t* s_th = s_mp + num_sets;
+  float* s_ih = reinterpret_cast<float*>(s_th + num_sets);
   std::memcpy(s_off, h_off, (size_t(num_sets) + 1) * 8);
   for (uint32_t k = 0; k < num_sets; ++k) {
     s_e2[k] = h_eps[k] * h_eps[k];
     s_mp[k] = h_minpts[k];
+    s_th[k] = o.dense_threshold ? o.dense_threshold : h_minpts[k];
+    s_ih[k] = inv_cell_side(h_eps[k]);
   }
   int64_t* d_off = at<int64_t>(c, off_b);
   float* d_e2 = at<float>(c, e2_b);
@@ -571,6 +615,26 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
   int32_t* d_root = at<int32_t>(c, root_b);
   MortonGrid* d_grid = at<MortonGrid>(c, grid_b);
   uint32_t* status = at<uint32_t>(c, L.status);
+  if (db) {
+    int32_t* d_th = at<int32_t>(c, th_b);
+    float* d_ih = at<float>(c, ih_b);
+    HIP_TRY(hipMemcpyAsync(d_off, s_off, (size_t(num_sets) + 1) * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_e2, s_e2, size_t(num_sets) * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_mp, s_mp, size_t(num_sets) * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_th, s_th, size_t(num_sets) * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_ih, s_ih, size_t(num_sets) * 4, hipMemcpyHostToDevice, s));
+    start_timing(c, timing, s);
+    launch_prep(at<uint32_t>(c, L.zero), L.zero_words, at<uint32_t>(c, L.bounds), s);
+    mark(c, timing, PH_PREP, s);
+    launch_set_morton(pts, d_off, num_sets, bits, set_shift, d_ih, at<uint64_t>(c, L.keys_a),
+                      at<uint32_t>(c, L.hist), d_root, d_grid, status, s);
+    mark(c, timing, PH_MORTON, s);
+    const DbSets S{d_e2, d_mp, d_th, d_grid, d_root, set_shift};
+    st = densebox_from_keys(c, L, pts, n, S, any_core, d_off, 0, labels, block, timing, s);
+    if (st != DBSCAN_OK) return st;
+    HIP_TRY(hipGetLastError());
+    return finish(c, status, timing, s);
+  }
   const std::vector<uint64_t> key = {2,
                                      reinterpret_cast<uint64_t>(pts),
                                      reinterpret_cast<uint64_t>(labels),
@@ -604,8 +668,8 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
     launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, gs);
     mark(c, timing, PH_PREP, gs);
     mark(c, timing, PH_BOUNDS, gs);
-    launch_set_morton(pts, d_off, num_sets, bits, set_shift, ka, sc.hist, d_root, d_grid, status,
-                      gs);
+    launch_set_morton(pts, d_off, num_sets, bits, set_shift, nullptr, ka, sc.hist, d_root, d_grid,
+                      status, gs);
     mark(c, timing, PH_MORTON, gs);
     SortMarks sm{c, gs};
     const bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, gs,
@@ -793,8 +857,6 @@ int dbscan_cluster_batched(dbscan_ctx* c, const float* points, const int64_t* of
     st = check_opts(o, min_pts[k]);
     if (st != DBSCAN_OK) return st;
   }
-  if (o.algorithm == DBSCAN_ALGO_DENSEBOX)
-    return fail(DBSCAN_EINVAL, "batched calls run FDBSCAN");
   if (n == 0) return DBSCAN_OK;
   DeviceGuard g(c->device);
   return run_batched(c, points, offsets, uint32_t(num_sets), eps, min_pts, labels,
@@ -989,8 +1051,19 @@ int dbscan_autotune_batched(dbscan_ctx* c, const float* points, const int64_t* o
                             int32_t* labels, dbscan_options* best, float* best_ms,
                             void* stream) {
   if (!c || !best) return fail(DBSCAN_EINVAL, "null pointer");
+  if (num_sets < 0 || (num_sets > 0 && (!offsets || !min_pts)))
+    return fail(DBSCAN_EINVAL, "null pointer");
+  // DenseBox thresholds are absolute: multiples of the largest minPts
+  int32_t mp_max = 1;
+  for (int32_t k = 0; k < num_sets; ++k) mp_max = std::max(mp_max, min_pts[k]);
+  std::vector<dbscan_options> cands = candidates(DBSCAN_ALGO_FDBSCAN, 1);
+  for (const dbscan_options& d : candidates(DBSCAN_ALGO_DENSEBOX, mp_max)) {
+    dbscan_options o = d;
+    if (o.dense_threshold == mp_max) o.dense_threshold = 0;  // each set's own minPts
+    cands.push_back(o);
+  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return tune(c, s, candidates(DBSCAN_ALGO_FDBSCAN, 1), best, best_ms,
+  return tune(c, s, cands, best, best_ms,
               [&](const dbscan_options& o) {
                 return dbscan_cluster_batched(c, points, offsets, num_sets, eps, min_pts, labels,
                                               stream, &o);

@@ -38,10 +38,13 @@ __device__ __forceinline__ float block_max(float v, float* s_red) {
 
 // One workgroup per set: the set's bounding box, then its keys (set id in
 // the top bits, `bits` per axis of Morton code below) and digit histograms.
-// The set's grid goes to grids[set] for the walks' early end.
+// The set's grid goes to grids[set] for the walks' early end.  With
+// set_inv_h (DenseBox) the grid is that of the set's cells, side
+// max(1 / set_inv_h[set], extent / 2^bits).
 __global__ __launch_bounds__(256) void k_set_morton(const float* __restrict__ pts,
                                                    const int64_t* __restrict__ offsets,
                                                    int bits, int set_shift,
+                                                   const float* __restrict__ set_inv_h,
                                                    uint64_t* __restrict__ keys,
                                                    uint32_t* __restrict__ hist,
                                                    int32_t* __restrict__ set_root,
@@ -74,6 +77,7 @@ __global__ __launch_bounds__(256) void k_set_morton(const float* __restrict__ pt
     const float top = block_max(hi[a], s_red);
     const float ext = top - g.lo[a];
     g.s[a] = ext > 0.0f ? float(1u << bits) / ext : 0.0f;
+    if (set_inv_h && ext > 0.0f) g.s[a] = fminf(set_inv_h[set], g.s[a]);  // DenseBox cells
   }
   if (threadIdx.x == 0) grids[set] = g;
   const uint64_t tag = uint64_t(set) << set_shift;
@@ -247,11 +251,11 @@ __global__ __launch_bounds__(256) void k_final_labels_sets(
 }  // namespace
 
 void launch_set_morton(const float* pts, const int64_t* offsets, uint32_t num_sets, int bits,
-                       int set_shift, uint64_t* keys, uint32_t* hist, int32_t* set_root,
-                       MortonGrid* grids, uint32_t* status, hipStream_t s) {
+                       int set_shift, const float* set_inv_h, uint64_t* keys, uint32_t* hist,
+                       int32_t* set_root, MortonGrid* grids, uint32_t* status, hipStream_t s) {
   if (num_sets == 0) return;
   hipLaunchKernelGGL(k_set_morton, dim3(num_sets), dim3(256), 0, s, pts, offsets, bits, set_shift,
-                     keys, hist, set_root, grids, status);
+                     set_inv_h, keys, hist, set_root, grids, status);
 }
 
 void launch_count_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,

@@ -23,7 +23,7 @@
 // are already in one cluster, else joined on the first pair within eps.
 #include <algorithm>
 
-#include "pipeline.hpp"
+#include "walk.hpp"
 
 namespace dbx {
 
@@ -39,30 +39,28 @@ constexpr uint32_t ST_VAL = (1u << 30) - 1;
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
 // Cell key: Morton code of the cell coordinates, so sorting by it orders
-// the cells along the Z-curve.  Side max(h, extent / 2^21) per axis.
+// the cells along the Z-curve.  Side max(h, extent / 2^21) per axis.  The
+// grid goes to *grid for the walks' early end.
 __global__ __launch_bounds__(256) void k_cell_keys(const float* __restrict__ pts, uint32_t n,
                                                   const uint32_t* __restrict__ bounds, float inv_h,
                                                   uint64_t* __restrict__ keys,
-                                                  uint32_t* __restrict__ hist) {
+                                                  uint32_t* __restrict__ hist,
+                                                  MortonGrid* __restrict__ grid) {
   __shared__ uint32_t sh[SORT_PASSES * RADIX];
   for (int t = threadIdx.x; t < SORT_PASSES * RADIX; t += blockDim.x) sh[t] = 0;
-  float lo[3], s[3];
+  MortonGrid g;
+  g.maxc = float((1u << MORTON_BITS) - 1);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    lo[a] = ord2f(bounds[a]);
-    const float ext = ord2f(bounds[3 + a]) - lo[a];
-    s[a] = fminf(inv_h, float(1u << MORTON_BITS) / ext);  // ext = 0 gives inv_h
+    g.lo[a] = ord2f(bounds[a]);
+    const float ext = ord2f(bounds[3 + a]) - g.lo[a];
+    g.s[a] = ext > 0.0f ? fminf(inv_h, float(1u << MORTON_BITS) / ext) : 0.0f;
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *grid = g;
   __syncthreads();
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    uint32_t c[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      float t = (pts[size_t(3) * i + a] - lo[a]) * s[a];
-      t = fminf(fmaxf(floorf(t), 0.0f), float((1u << MORTON_BITS) - 1));  // NaN -> 0
-      c[a] = uint32_t(t);
-    }
-    const uint64_t code = (spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]);
+    const float* p = pts + size_t(3) * i;
+    const uint64_t code = g.code(p[0], p[1], p[2]);
     keys[i] = code;
 #pragma unroll
     for (int q = 0; q < SORT_PASSES; ++q)
@@ -166,15 +164,16 @@ __global__ __launch_bounds__(256) void k_cell_start(const uint32_t* __restrict__
   if (i == 0) cell_start[*ncells] = n;
 }
 
-// Per cell: box, denseness, smallest (input index, position) over its
-// points, and how many primitives it contributes (1 if dense, else one per
-// point).  Threads past the last cell write a zero count.
+// Per cell: box, denseness (its set's eps and threshold), smallest (input
+// index, position) over its points, and how many primitives it contributes
+// (1 if dense, else one per point).  Threads past the last cell write a zero
+// count.
 __global__ __launch_bounds__(256) void k_cell_stats(
-    const float4* __restrict__ pts, const uint32_t* __restrict__ perm, uint32_t n,
-    const uint32_t* __restrict__ ncells_p, const uint32_t* __restrict__ cell_start, float e2,
-    int32_t thresh, float4* __restrict__ cell_lo, float4* __restrict__ cell_hi,
-    unsigned long long* __restrict__ cell_minorig, uint8_t* __restrict__ cell_dense,
-    uint32_t* __restrict__ prim_count) {
+    const float4* __restrict__ pts, const uint32_t* __restrict__ perm,
+    const uint64_t* __restrict__ keys, uint32_t n, const uint32_t* __restrict__ ncells_p,
+    const uint32_t* __restrict__ cell_start, DbSets S, float4* __restrict__ cell_lo,
+    float4* __restrict__ cell_hi, unsigned long long* __restrict__ cell_minorig,
+    uint8_t* __restrict__ cell_dense, uint32_t* __restrict__ prim_count) {
   const uint32_t ncells = *ncells_p;
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
     if (c >= ncells) { prim_count[c] = 0; continue; }
@@ -189,8 +188,9 @@ __global__ __launch_bounds__(256) void k_cell_stats(
       mo = o < mo ? o : mo;
     }
     const uint32_t cnt = e - b;
-    const bool dense =
-        int64_t(cnt) >= thresh && sq_dist(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z) <= e2;
+    const uint32_t set = S.shift < 64 ? uint32_t(keys[b] >> S.shift) : 0u;
+    const bool dense = int64_t(cnt) >= S.thresh[set] &&
+                       sq_dist(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z) <= S.e2[set];
     cell_lo[c] = lo;
     cell_hi[c] = hi;
     if (cell_minorig) cell_minorig[c] = mo;
@@ -234,215 +234,431 @@ __global__ __launch_bounds__(256) void k_make_prims(
   }
 }
 
-// ---- traversal helpers ------------------------------------------------------
+// ---- the DenseBox walk --------------------------------------------------------
+// The walk of walk.hpp over a tree whose leaves are primitives (32-byte
+// records: box, payload, rope) and whose query is a box (a point is the box
+// [p, p]; for two points the box bound is exactly the predicate's sq_dist,
+// since fl(q - p) = -fl(p - q)).  Work that needs a scan of a dense cell's
+// points is not done by the lane that meets it: the lane queues it in its
+// wave's LDS queue, and the wave drains the queue together, 64 lanes over
+// the cell's points, once it holds 64 entries and before the wave ends.  A
+// lane queues at most one entry per step, so 128 slots never overflow.
 
-__device__ __forceinline__ Node load_node(const Node* __restrict__ nodes, int32_t k) {
-  const float4* p = reinterpret_cast<const float4*>(nodes + k);
-  const float4 a = p[0], b = p[1];
-  Node nd;
-  nd.lox = a.x; nd.loy = a.y; nd.loz = a.z; nd.left = __float_as_int(a.w);
-  nd.hix = b.x; nd.hiy = b.y; nd.hiz = b.z; nd.rope = __float_as_int(b.w);
-  return nd;
-}
+constexpr uint32_t QCAP = 128;
+constexpr int32_t Q_JOIN = 0;    // core point vs cell: join on the first hit
+constexpr int32_t Q_BORDER = 1;  // non-core point vs cell: smallest core hit
+constexpr int32_t Q_CELLS = 2;   // cell vs cell: join on the first close pair
+constexpr int32_t Q_COUNT = 3;   // point vs cell: count hits for the owner lane
+constexpr int32_t Q_MARK = 1 << 10;  // Q_JOIN: mark the point a member on a hit
+constexpr uint32_t Q_ALL = 0xffffu;  // Q_COUNT: no early stop
 
-// lower bound of sq_dist between any point of box a and any point of box b
-__device__ __forceinline__ float box_box_near(const Node& a, const Node& b) {
+// lower bound of sq_dist between a point of box [al, ah] and one of [bl, bh]
+__device__ __forceinline__ float box_box_near4(const float4& al, const float4& ah,
+                                               const float4& bl, const float4& bh) {
 #pragma clang fp contract(off)
-  const float gx = fmaxf(fmaxf(b.lox - a.hix, a.lox - b.hix), 0.0f);
-  const float gy = fmaxf(fmaxf(b.loy - a.hiy, a.loy - b.hiy), 0.0f);
-  const float gz = fmaxf(fmaxf(b.loz - a.hiz, a.loz - b.hiz), 0.0f);
+  const float gx = fmaxf(fmaxf(bl.x - ah.x, al.x - bh.x), 0.0f);
+  const float gy = fmaxf(fmaxf(bl.y - ah.y, al.y - bh.y), 0.0f);
+  const float gz = fmaxf(fmaxf(bl.z - ah.z, al.z - bh.z), 0.0f);
   const float xx = gx * gx, yy = gy * gy, zz = gz * gz;
   const float s = xx + yy;
   return s + zz;
 }
 
-// upper bound of sq_dist between any point of box a and any point of box b
-// (a point is a box with lo = hi)
-__device__ __forceinline__ float box_box_far(const Node& a, const Node& b) {
+// upper bound of the same (farthest corners)
+__device__ __forceinline__ float box_box_far4(const float4& al, const float4& ah,
+                                              const float4& bl, const float4& bh) {
 #pragma clang fp contract(off)
-  const float dx = fmaxf(fabsf(a.hix - b.lox), fabsf(b.hix - a.lox));
-  const float dy = fmaxf(fabsf(a.hiy - b.loy), fabsf(b.hiy - a.loy));
-  const float dz = fmaxf(fabsf(a.hiz - b.loz), fabsf(b.hiz - a.loz));
+  const float dx = fmaxf(fabsf(ah.x - bl.x), fabsf(bh.x - al.x));
+  const float dy = fmaxf(fabsf(ah.y - bl.y), fabsf(bh.y - al.y));
+  const float dz = fmaxf(fabsf(ah.z - bl.z), fabsf(bh.z - al.z));
   const float xx = dx * dx, yy = dy * dy, zz = dz * dz;
   const float s = xx + yy;
   return s + zz;
 }
 
-__device__ __forceinline__ bool bad_ref(int32_t node, uint32_t n, uint32_t& steps) {
-  if (++steps > 2 * n) return true;
-  return is_leaf(node) ? uint32_t(leaf_index(node)) >= n : uint32_t(node) >= n - 1;
+__device__ __forceinline__ float sq_dist4(const float4& a, const float4& b) {
+  return sq_dist(a.x, a.y, a.z, b.x, b.y, b.z);
 }
 
-__device__ __forceinline__ uint32_t query_index() {
-  return xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+__device__ __forceinline__ uint32_t set_id(const DbSets& S, uint64_t key) {
+  return S.shift < 64 ? uint32_t(key >> S.shift) : 0u;
 }
 
-// Counting (minPts > 2) for the points outside dense cells (theirs are core
-// already): a full walk from the root, early exit at minPts.
-__global__ void k_count_db(const Node* __restrict__ nodes, const Node* __restrict__ prims,
-                           uint32_t nprims, const float4* __restrict__ pts, uint32_t n,
-                           const uint32_t* __restrict__ cell_start, const int32_t* __restrict__ root,
-                           float e2, int32_t min_pts, uint8_t* __restrict__ flag,
-                           uint32_t* __restrict__ err) {
-  const uint32_t i = query_index();
-  if (i >= n || flag[i]) return;
-  const float4 q4 = pts[i];
-  Node q;
-  q.lox = q.hix = q4.x; q.loy = q.hiy = q4.y; q.loz = q.hiz = q4.z;
-  int32_t cnt = 0;
-  int32_t node = *root;
-  uint32_t steps = 0;
-  while (node != SENTINEL && cnt < min_pts) {
-    if (bad_ref(node, nprims, steps)) { atomicOr(err, STATUS_TREE); break; }
-    if (!is_leaf(node)) {
-      const Node nd = load_node(nodes, node);
-      node = box_box_near(q, nd) <= e2 ? nd.left : nd.rope;
-      continue;
-    }
-    const Node pr = load_node(prims, leaf_index(node));
-    node = pr.rope;
-    if (box_box_near(q, pr) > e2) continue;
-    if (pr.left >= 0) {  // a point: its box is the point
-      cnt += 1;
-    } else {
-      const uint32_t c = uint32_t(pr.left & 0x7fffffff);
-      const uint32_t b = cell_start[c], e = cell_start[c + 1];
-      if (box_box_far(q, pr) <= e2) {
-        cnt += int32_t(e - b);
-      } else {
-        for (uint32_t k = b; k < e && cnt < min_pts; ++k) {
-          const float4 p = pts[k];
-          cnt += sq_dist(q.lox, q.loy, q.loz, p.x, p.y, p.z) <= e2;
-        }
-      }
-    }
-  }
-  flag[i] = cnt >= min_pts;
+// the early-end bound of a query box of set `set`: every primitive within
+// eps of the box has a cell key at most this (cell coordinates are monotone
+// in the position, and a cell's box corner is one of its points)
+__device__ __forceinline__ uint64_t set_upper(const DbSets& S, uint32_t set, const float4& hi,
+                                              float e2) {
+  const uint64_t tag = S.shift < 64 ? uint64_t(set) << S.shift : 0ull;
+  return tag | S.grid[set].upper_code(hi, e2);
 }
 
-struct DbArgs {
-  const Node* nodes;
-  const Node* prims;
-  uint32_t nprims;
-  const float4* pts;
-  uint32_t n;
+// What a queue drain reads and writes.
+struct DbData {
+  const float4* pts;  // points in cell order
   const uint32_t* cell_start;
   const uint32_t* perm;
   const unsigned long long* cell_minorig;
-  float e2;
-  bool core_mode;     // minPts > 2
+  const float4* cell_lo;
+  const float4* cell_hi;
   int32_t* parent;
-  uint8_t* flag;      // core (minPts > 2) or member (minPts <= 2)
+  uint8_t* flag;
   unsigned long long* bestcore;
-  uint32_t* err;
 };
 
-__device__ __forceinline__ unsigned long long orig_key(const DbArgs& A, uint32_t pos) {
-  return (static_cast<unsigned long long>(A.perm[pos]) << 32) | pos;
+// One wave's queue in LDS.
+struct DbQueue {
+  int4* q;
+  uint32_t* n;
+  __device__ void push(int32_t meta, int32_t a, int32_t b, float e2) const {
+    const uint32_t k = atomicAdd(n, 1u);
+    q[k] = make_int4(meta | ((threadIdx.x & 63) << 4), a, b, __float_as_int(e2));
+  }
+  __device__ uint32_t size() const {
+    return __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT));
+  }
+};
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long t = __shfl_xor(v, o, 64);
+    v = t < v ? t : v;
+  }
+  return v;
 }
 
-// Point x (sorted position xp, coordinates in box form) against dense cell c.
-__device__ void point_cell(const DbArgs& A, uint32_t xp, const Node& xb, const Node& cb,
-                           uint32_t c) {
-  const uint32_t b = A.cell_start[c], e = A.cell_start[c + 1];
-  const bool all_in = box_box_far(xb, cb) <= A.e2;
-  const bool x_core = !A.core_mode || A.flag[xp];
-  if (x_core) {
-    bool hit = all_in;
-    for (uint32_t k = b; k < e && !hit; ++k) {
-      const float4 p = A.pts[k];
-      hit = sq_dist(xb.lox, xb.loy, xb.loz, p.x, p.y, p.z) <= A.e2;
+// Drain the wave's queue; every lane of the wave calls it.  Returns the
+// points counted for this lane's Q_COUNT entries.
+__device__ uint32_t drain(const DbData& D, const DbQueue& Q) {
+  const int lane = threadIdx.x & 63;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the lanes' pushes are in
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t m = Q.size();
+  uint32_t added = 0;
+  for (uint32_t e = 0; e < m; ++e) {
+    const int4 en = Q.q[e];
+    const int32_t meta = __builtin_amdgcn_readfirstlane(en.x);
+    const int32_t a = __builtin_amdgcn_readfirstlane(en.y);
+    const int32_t b = __builtin_amdgcn_readfirstlane(en.z);
+    const float e2 = __int_as_float(__builtin_amdgcn_readfirstlane(en.w));
+    const int32_t kind = meta & 15;
+    if (kind == Q_CELLS) {
+      const int32_t ra = int32_t(D.cell_start[a]), rb = int32_t(D.cell_start[b]);
+      if (uf_find(D.parent, ra) == uf_find(D.parent, rb)) continue;
+      // lanes over the larger cell's points (only those near the smaller
+      // cell's box), the smaller cell's points in turn for all lanes
+      const uint32_t na = D.cell_start[a + 1] - uint32_t(ra);
+      const uint32_t nb = D.cell_start[b + 1] - uint32_t(rb);
+      const int32_t co = na >= nb ? a : b, ci = na >= nb ? b : a;
+      const uint32_t os = D.cell_start[co], oe = D.cell_start[co + 1];
+      const uint32_t is = D.cell_start[ci], ie = D.cell_start[ci + 1];
+      const float4 ilo = D.cell_lo[ci], ihi = D.cell_hi[ci];
+      bool hit = false;
+      for (uint32_t o0 = os; o0 < oe && !hit; o0 += 64) {
+        const uint32_t k = o0 + uint32_t(lane);
+        const float4 p = D.pts[k < oe ? k : os];
+        const bool act = k < oe && box_sq_dist4(p, ilo, ihi) <= e2;
+        if (__ballot(act) == 0ull) continue;
+        for (uint32_t j = is; j < ie; ++j) {
+          const float4 r = D.pts[j];
+          if (__ballot(act && sq_dist4(p, r) <= e2) != 0ull) { hit = true; break; }
+        }
+      }
+      if (hit && lane == 0) uf_union(D.parent, ra, rb);
+      continue;
     }
-    if (hit) {
-      uf_union(A.parent, int32_t(xp), int32_t(b));
-      if (!A.core_mode) A.flag[xp] = 1;
-    }
-  } else {  // border candidate: smallest input index among cell points in range
-    unsigned long long best = ~0ull;
-    if (all_in) {
-      best = A.cell_minorig[c];
-    } else {
-      for (uint32_t k = b; k < e; ++k) {
-        const float4 p = A.pts[k];
-        if (sq_dist(xb.lox, xb.loy, xb.loz, p.x, p.y, p.z) <= A.e2) {
-          const unsigned long long o = orig_key(A, k);
+    const float4 p = D.pts[a];
+    const uint32_t cb = D.cell_start[b], ce = D.cell_start[b + 1];
+    if (kind == Q_JOIN) {
+      const int32_t rep = int32_t(cb);
+      if (uf_find(D.parent, a) == uf_find(D.parent, rep)) continue;
+      bool hit = false;
+      for (uint32_t k0 = cb; k0 < ce && !hit; k0 += 64) {
+        const uint32_t k = k0 + uint32_t(lane);
+        hit = __ballot(k < ce && sq_dist4(p, D.pts[k < ce ? k : cb]) <= e2) != 0ull;
+      }
+      if (hit && lane == 0) {
+        uf_union(D.parent, a, rep);
+        if (meta & Q_MARK) D.flag[a] = 1;
+      }
+    } else if (kind == Q_BORDER) {
+      if (D.bestcore[a] <= D.cell_minorig[b]) continue;  // no point here can lower it
+      unsigned long long best = ~0ull;
+      for (uint32_t k = cb + uint32_t(lane); k < ce; k += 64) {
+        if (sq_dist4(p, D.pts[k]) <= e2) {
+          const unsigned long long o = (static_cast<unsigned long long>(D.perm[k]) << 32) | k;
           best = o < best ? o : best;
         }
       }
-    }
-    if (best != ~0ull) atomicMin(A.bestcore + xp, best);
-  }
-}
-
-__device__ void cell_cell(const DbArgs& A, const Node& ab, uint32_t ca, const Node& bb,
-                          uint32_t cbi) {
-  const uint32_t ra = A.cell_start[ca], rb = A.cell_start[cbi];
-  if (uf_find(A.parent, int32_t(ra)) == uf_find(A.parent, int32_t(rb))) return;
-  bool hit = box_box_far(ab, bb) <= A.e2;
-  const uint32_t ea = A.cell_start[ca + 1], eb = A.cell_start[cbi + 1];
-  for (uint32_t i = ra; i < ea && !hit; ++i) {
-    const float4 p = A.pts[i];
-    for (uint32_t k = rb; k < eb && !hit; ++k) {
-      const float4 q = A.pts[k];
-      hit = sq_dist(p.x, p.y, p.z, q.x, q.y, q.z) <= A.e2;
+      best = wave_min_u64(best);
+      if (lane == 0 && best != ~0ull) atomicMin(D.bestcore + a, best);
+    } else {  // Q_COUNT
+      const uint32_t need = uint32_t(meta) >> 16;
+      uint32_t tot = 0;
+      for (uint32_t k0 = cb; k0 < ce && (need == Q_ALL || tot < need); k0 += 64) {
+        const uint32_t k = k0 + uint32_t(lane);
+        tot += uint32_t(__popcll(__ballot(k < ce && sq_dist4(p, D.pts[k < ce ? k : cb]) <= e2)));
+      }
+      if (lane == ((meta >> 4) & 63)) added += tot;
     }
   }
-  if (hit) uf_union(A.parent, int32_t(ra), int32_t(rb));
+  __builtin_amdgcn_wave_barrier();
+  if (lane == 0) *Q.n = 0;
+  __builtin_amdgcn_wave_barrier();
+  return added;
 }
 
-__device__ void point_point(const DbArgs& A, uint32_t ip, const Node& ib, uint32_t jp,
-                            const Node& jb, bool& found) {
-  if (sq_dist(ib.lox, ib.loy, ib.loz, jb.lox, jb.loy, jb.loz) > A.e2) return;
-  found = true;
-  if (!A.core_mode) {
-    uf_union(A.parent, int32_t(ip), int32_t(jp));
-    A.flag[jp] = 1;
-    return;
-  }
-  const bool ci = A.flag[ip] != 0, cj = A.flag[jp] != 0;
-  if (ci && cj) uf_union(A.parent, int32_t(ip), int32_t(jp));
-  else if (ci) atomicMin(A.bestcore + jp, orig_key(A, ip));
-  else if (cj) atomicMin(A.bestcore + ip, orig_key(A, jp));
-}
-
-// Pair traversal over primitives: lane i starts at its primitive's rope and
-// sees every primitive j > i whose box is within eps of its own.
-__global__ void k_pairs_db(DbArgs A) {
-  const uint32_t i = query_index();
-  if (i >= A.nprims) return;
-  const Node me = load_node(A.prims, int32_t(i));
-  const bool me_cell = me.left < 0;
-  const uint32_t me_idx = uint32_t(me.left & 0x7fffffff);
-  bool found = false;
-  int32_t node = me.rope;
-  uint32_t steps = 0;
-  while (node != SENTINEL) {
-    if (bad_ref(node, A.nprims, steps)) { atomicOr(A.err, STATUS_TREE); break; }
-    if (!is_leaf(node)) {
-      const Node nd = load_node(A.nodes, node);
-      node = box_box_near(me, nd) <= A.e2 ? nd.left : nd.rope;
+// The walks of one wave (the chunk scheme of wave_walks in walk.hpp).  The
+// visitor V gives kStartIsRope and kDrainBeforeEnd (drain the queue before a
+// lane's end(), so that queued counts are in), and
+//   int32_t begin(uint32_t i, const float4& lo, const float4& hi)
+//   uint64_t khi() const, float e2() const
+//   bool hit(int32_t j, const float4& lo, const float4& hi)   true: walk over
+//   bool drain()                                              true: walk over
+//   void end()
+template <class V>
+__device__ __forceinline__ void db_walks(const Node* __restrict__ nodes,
+                                         const Node* __restrict__ prims,
+                                         const uint64_t* __restrict__ pkey, uint32_t np,
+                                         WalkCfg wc, V& v, const DbQueue& Q, uint32_t* err) {
+  uint32_t c0, c1;
+  walk_chunk(np, wc.chunk, c0, c1);
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  uint32_t head = c0, i = 0, steps = 0;
+  bool have = false, by_rope = false;
+  int32_t node = SENTINEL;
+  float4 ql = make_float4(0.f, 0.f, 0.f, 0.f), qh = ql;
+  for (;;) {
+    if (V::kDrainBeforeEnd && v.drain()) node = SENTINEL;
+    const bool need = node == SENTINEL;
+    const uint64_t m = __ballot(need);
+    if (need) {
+      if (have) { v.end(); have = false; }
+      const uint32_t idx = head + uint32_t(__popcll(m & lt));
+      if (idx < c1) {
+        i = idx;
+        have = true;
+        const float4* r = reinterpret_cast<const float4*>(prims + i);
+        ql = r[0];
+        qh = r[1];
+        node = v.begin(i, ql, qh);
+        steps = 0;
+        by_rope = V::kStartIsRope;
+      }
+    }
+    const uint32_t h = head + uint32_t(__popcll(m));
+    head = h < c1 ? h : c1;
+    if (__ballot(node != SENTINEL) == 0) {
+      if (head >= c1) break;
       continue;
     }
-    const Node pr = load_node(A.prims, leaf_index(node));
-    node = pr.rope;
-    if (box_box_near(me, pr) > A.e2) continue;
-    const bool pr_cell = pr.left < 0;
-    const uint32_t pr_idx = uint32_t(pr.left & 0x7fffffff);
-    if (!me_cell && !pr_cell) point_point(A, me_idx, me, pr_idx, pr, found);
-    else if (!me_cell) point_cell(A, me_idx, me, pr, pr_idx);
-    else if (!pr_cell) point_cell(A, pr_idx, pr, me, me_idx);
-    else cell_cell(A, me, me_idx, pr, pr_idx);
+    for (;;) {
+      bool act = node != SENTINEL;
+      const bool lf = is_leaf(node);
+      if (act && (++steps > 2 * np ||
+                  (lf ? uint32_t(leaf_index(node)) >= np : uint32_t(node) >= np - 1))) {
+        atomicOr(err, STATUS_TREE);
+        node = SENTINEL;
+        act = false;
+      }
+      const Node* rec = !act ? prims : lf ? prims + leaf_index(node) : nodes + node;
+      const float4 a = reinterpret_cast<const float4*>(rec)[0];
+      const float4 b = reinterpret_cast<const float4*>(rec)[1];
+      // a rope target's number is its first leaf: past the bound, stop
+      const uint32_t first = lf ? uint32_t(leaf_index(node)) : uint32_t(node);
+      const uint64_t kf = pkey[act && by_rope ? first : 0u];
+      if (act && by_rope && kf > v.khi()) {
+        node = SENTINEL;
+        act = false;
+      }
+      if (act) {
+        const bool near = box_box_near4(ql, qh, a, b) <= v.e2();
+        const bool down = near && !lf;
+        int32_t next = down ? __float_as_int(a.w) : __float_as_int(b.w);
+        if (near && lf && v.hit(leaf_index(node), a, b)) next = SENTINEL;
+        node = next;
+        by_rope = !down;
+      }
+      if (Q.size() >= QCAP / 2 && v.drain()) node = SENTINEL;
+      const uint32_t busy = uint32_t(__popcll(__ballot(node != SENTINEL)));
+      if (busy == 0 || (head < c1 && busy < wc.refill_at)) break;
+    }
   }
-  if (!A.core_mode && !me_cell && found) A.flag[me_idx] = 1;
+  v.drain();
+  if (have) v.end();
+}
+
+// Counting (sets with minPts > 2) for the points outside dense cells (those
+// inside are core already): a walk from the set's root, ended at minPts.
+struct CountDb {
+  static constexpr bool kStartIsRope = false;
+  static constexpr bool kDrainBeforeEnd = true;
+  DbSets S;
+  DbData D;
+  DbQueue Q;
+  const uint64_t* pkey;
+  float r2;
+  int32_t mp, x;  // x: the query point (sorted position), -1: nothing to count
+  uint32_t cnt;
+  uint64_t hi;
+  float4 qp;
+  __device__ int32_t begin(uint32_t i, const float4& lo, const float4& h) {
+    x = -1;
+    const int32_t pay = __float_as_int(lo.w);
+    if (pay < 0) return SENTINEL;  // a dense cell
+    const uint32_t set = set_id(S, pkey[i]);
+    mp = S.minpts[set];
+    if (mp <= 2) return SENTINEL;
+    x = pay;
+    r2 = S.e2[set];
+    cnt = 0;
+    qp = lo;
+    hi = set_upper(S, set, h, r2);
+    return S.root[set];
+  }
+  __device__ uint64_t khi() const { return hi; }
+  __device__ float e2() const { return r2; }
+  __device__ bool hit(int32_t, const float4& a, const float4& b) {
+    const int32_t pay = __float_as_int(a.w);
+    if (pay >= 0) return ++cnt >= uint32_t(mp);
+    const uint32_t c = uint32_t(pay & 0x7fffffff);
+    if (box_box_far4(qp, qp, a, b) <= r2) {
+      cnt += D.cell_start[c + 1] - D.cell_start[c];
+      return cnt >= uint32_t(mp);
+    }
+    const uint32_t need = mp < int32_t(Q_ALL) ? uint32_t(mp) : Q_ALL;
+    Q.push(Q_COUNT | int32_t(need << 16), x, int32_t(c), r2);
+    return false;
+  }
+  __device__ bool drain() {
+    cnt += dbx::drain(D, Q);
+    return x >= 0 && cnt >= uint32_t(mp);
+  }
+  __device__ void end() {
+    if (x >= 0) D.flag[x] = cnt >= uint32_t(mp);
+  }
+};
+
+// Pair traversal over primitives: lane i starts at primitive i's rope and
+// meets every primitive j > i of its set whose box is within eps of its own.
+struct PairDb {
+  static constexpr bool kStartIsRope = true;
+  static constexpr bool kDrainBeforeEnd = false;
+  DbSets S;
+  DbData D;
+  DbQueue Q;
+  const uint64_t* pkey;
+  float r2;
+  bool core_mode, me_core;
+  int32_t me;  // payload: sorted position of a point, or cell | CELL_BIT
+  uint64_t hi;
+  float4 ql, qh;
+  __device__ int32_t begin(uint32_t i, const float4& lo, const float4& h) {
+    me = __float_as_int(lo.w);
+    const uint32_t set = set_id(S, pkey[i]);
+    r2 = S.e2[set];
+    core_mode = S.minpts[set] > 2;
+    me_core = me < 0 || !core_mode || D.flag[me] != 0;  // dense cells are core
+    ql = lo;
+    qh = h;
+    hi = set_upper(S, set, h, r2);
+    return __float_as_int(h.w);
+  }
+  __device__ uint64_t khi() const { return hi; }
+  __device__ float e2() const { return r2; }
+  __device__ unsigned long long okey(int32_t p) const {
+    return (static_cast<unsigned long long>(D.perm[p]) << 32) | uint32_t(p);
+  }
+  __device__ bool hit(int32_t, const float4& a, const float4& b) {
+    const int32_t pr = __float_as_int(a.w);
+    if (me >= 0 && pr >= 0) {  // two points: the box bound was the predicate
+      if (!core_mode) {
+        uf_union(D.parent, me, pr);
+        D.flag[me] = 1;
+        D.flag[pr] = 1;
+        return false;
+      }
+      const bool cj = D.flag[pr] != 0;
+      if (me_core && cj) uf_union(D.parent, me, pr);
+      else if (me_core) atomicMin(D.bestcore + pr, okey(me));
+      else if (cj) atomicMin(D.bestcore + me, okey(pr));
+      return false;
+    }
+    const bool all_in = box_box_far4(ql, qh, a, b) <= r2;
+    if (me < 0 && pr < 0) {  // two dense cells
+      const int32_t ca = me & 0x7fffffff, cb = pr & 0x7fffffff;
+      if (all_in) uf_union(D.parent, int32_t(D.cell_start[ca]), int32_t(D.cell_start[cb]));
+      else Q.push(Q_CELLS, ca, cb, r2);
+      return false;
+    }
+    const int32_t x = me >= 0 ? me : pr;
+    const int32_t c = (me >= 0 ? pr : me) & 0x7fffffff;
+    const bool x_core = me >= 0 ? me_core : (!core_mode || D.flag[x] != 0);
+    if (x_core) {
+      if (all_in) {
+        uf_union(D.parent, x, int32_t(D.cell_start[c]));
+        if (!core_mode) D.flag[x] = 1;
+      } else {
+        Q.push(Q_JOIN | (core_mode ? 0 : Q_MARK), x, c, r2);
+      }
+    } else if (all_in) {
+      atomicMin(D.bestcore + x, D.cell_minorig[c]);
+    } else {
+      Q.push(Q_BORDER, x, c, r2);
+    }
+    return false;
+  }
+  __device__ bool drain() {
+    dbx::drain(D, Q);
+    return false;
+  }
+  __device__ void end() {}
+};
+
+// the wave's queue in dynamic LDS: QCAP entries per wave, then the counts
+__device__ __forceinline__ DbQueue wave_queue() {
+  extern __shared__ int4 s_dyn[];
+  const uint32_t waves = blockDim.x / 64, w = threadIdx.x / 64;
+  DbQueue Q{s_dyn + size_t(w) * QCAP, reinterpret_cast<uint32_t*>(s_dyn + waves * QCAP) + w};
+  if ((threadIdx.x & 63) == 0) *Q.n = 0;
+  __builtin_amdgcn_wave_barrier();
+  return Q;
+}
+
+__global__ void k_count_db(const Node* __restrict__ nodes, const Node* __restrict__ prims,
+                           const uint64_t* __restrict__ pkey, uint32_t np, WalkCfg wc, DbSets S,
+                           DbData D, uint32_t* __restrict__ err) {
+  const DbQueue Q = wave_queue();
+  CountDb v{S, D, Q, pkey, 0.f, 0, -1, 0u, 0ull, make_float4(0.f, 0.f, 0.f, 0.f)};
+  db_walks(nodes, prims, pkey, np, wc, v, Q, err);
+}
+
+__global__ void k_pairs_db(const Node* __restrict__ nodes, const Node* __restrict__ prims,
+                           const uint64_t* __restrict__ pkey, uint32_t np, WalkCfg wc, DbSets S,
+                           DbData D, uint32_t* __restrict__ err) {
+  const DbQueue Q = wave_queue();
+  PairDb v{S, D, Q, pkey, 0.f, false, false, 0, 0ull, make_float4(0.f, 0.f, 0.f, 0.f),
+           make_float4(0.f, 0.f, 0.f, 0.f)};
+  db_walks(nodes, prims, pkey, np, wc, v, Q, err);
+}
+
+__global__ void k_one_set(float e2, int32_t min_pts, int32_t thresh, float* __restrict__ e2o,
+                          int32_t* __restrict__ mpo, int32_t* __restrict__ tho) {
+  *e2o = e2;
+  *mpo = min_pts;
+  *tho = thresh;
 }
 
 }  // namespace
 
 void launch_cell_keys(const float* pts, uint32_t n, const uint32_t* bounds, float inv_h,
-                      uint64_t* keys, uint32_t* hist, hipStream_t s) {
+                      uint64_t* keys, uint32_t* hist, MortonGrid* grid, hipStream_t s) {
   if (n == 0) return;
   const uint32_t blocks = std::max(1u, std::min((n + 255) / 256, 4096u));
-  hipLaunchKernelGGL(k_cell_keys, dim3(blocks), dim3(256), 0, s, pts, n, bounds, inv_h, keys, hist);
+  hipLaunchKernelGGL(k_cell_keys, dim3(blocks), dim3(256), 0, s, pts, n, bounds, inv_h, keys, hist,
+                     grid);
 }
 
 size_t scan_status_words(uint32_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE; }
@@ -465,16 +681,14 @@ void launch_cells(const uint64_t* sorted_keys, uint32_t n, uint32_t* head, uint3
   hipLaunchKernelGGL(k_cell_start, dim3(g), dim3(256), 0, s, head, cid, n, ncells, cell_start);
 }
 
-void launch_cell_stats(const float4* pts, const uint32_t* perm, uint32_t n,
-                       const uint32_t* ncells, const uint32_t* cell_start, float e2,
-                       int32_t thresh, float4* cell_lo, float4* cell_hi,
-                       unsigned long long* cell_minorig, uint8_t* cell_dense,
-                       uint32_t* prim_count, hipStream_t s) {
+void launch_cell_stats(const float4* pts, const uint32_t* perm, const uint64_t* keys, uint32_t n,
+                       const uint32_t* ncells, const uint32_t* cell_start, const DbSets& sets,
+                       float4* cell_lo, float4* cell_hi, unsigned long long* cell_minorig,
+                       uint8_t* cell_dense, uint32_t* prim_count, hipStream_t s) {
   if (n == 0) return;
   const uint32_t blocks = std::max(1u, std::min((n + 255) / 256, 8192u));
-  hipLaunchKernelGGL(k_cell_stats, dim3(blocks), dim3(256), 0, s, pts, perm, n, ncells,
-                     cell_start, e2, thresh, cell_lo, cell_hi, cell_minorig, cell_dense,
-                     prim_count);
+  hipLaunchKernelGGL(k_cell_stats, dim3(blocks), dim3(256), 0, s, pts, perm, keys, n, ncells,
+                     cell_start, sets, cell_lo, cell_hi, cell_minorig, cell_dense, prim_count);
 }
 
 void launch_make_prims(const float4* pts, const uint64_t* keys, uint32_t n, const uint32_t* cid,
@@ -488,23 +702,34 @@ void launch_make_prims(const float4* pts, const uint64_t* keys, uint32_t n, cons
                      flag);
 }
 
-void launch_count_db(const Node* nodes, const Node* prims, uint32_t nprims, const float4* pts,
-                     uint32_t n, const uint32_t* cell_start, const int32_t* root, float e2,
-                     int32_t min_pts, uint8_t* flag, uint32_t* err, int block, hipStream_t s) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(k_count_db, dim3((n + block - 1) / block), dim3(block), 0, s, nodes, prims,
-                     nprims, pts, n, cell_start, root, e2, min_pts, flag, err);
+void launch_one_set(float e2, int32_t min_pts, int32_t thresh, float* e2o, int32_t* mpo,
+                    int32_t* tho, hipStream_t s) {
+  hipLaunchKernelGGL(k_one_set, dim3(1), dim3(1), 0, s, e2, min_pts, thresh, e2o, mpo, tho);
 }
 
-void launch_pairs_db(const Node* nodes, const Node* prims, uint32_t nprims, const float4* pts,
-                     uint32_t n, const uint32_t* cell_start, const uint32_t* perm,
-                     const unsigned long long* cell_minorig, float e2, bool core_mode,
-                     int32_t* parent, uint8_t* flag, unsigned long long* bestcore, uint32_t* err,
-                     int block, hipStream_t s) {
+static size_t queue_lds(int block) {
+  const size_t waves = size_t(block) / 64;
+  return waves * QCAP * sizeof(int4) + waves * sizeof(uint32_t);
+}
+
+void launch_count_db(const Node* nodes, const Node* prims, const uint64_t* pkey, uint32_t nprims,
+                     const DbSets& sets, const DbTables& t, uint32_t* err, int block,
+                     hipStream_t s) {
   if (nprims == 0) return;
-  DbArgs A{nodes, prims, nprims, pts, n, cell_start, perm, cell_minorig, e2, core_mode,
-           parent, flag, bestcore, err};
-  hipLaunchKernelGGL(k_pairs_db, dim3((nprims + block - 1) / block), dim3(block), 0, s, A);
+  const DbData D{t.pts, t.cell_start, t.perm, t.cell_minorig, t.cell_lo, t.cell_hi, t.parent,
+                 t.flag, t.bestcore};
+  hipLaunchKernelGGL(k_count_db, dim3(walk_grid(nprims, block)), dim3(block), queue_lds(block), s,
+                     nodes, prims, pkey, nprims, walk_cfg(nprims), sets, D, err);
+}
+
+void launch_pairs_db(const Node* nodes, const Node* prims, const uint64_t* pkey, uint32_t nprims,
+                     const DbSets& sets, const DbTables& t, uint32_t* err, int block,
+                     hipStream_t s) {
+  if (nprims == 0) return;
+  const DbData D{t.pts, t.cell_start, t.perm, t.cell_minorig, t.cell_lo, t.cell_hi, t.parent,
+                 t.flag, t.bestcore};
+  hipLaunchKernelGGL(k_pairs_db, dim3(walk_grid(nprims, block)), dim3(block), queue_lds(block), s,
+                     nodes, prims, pkey, nprims, walk_cfg(nprims), sets, D, err);
 }
 
 }  // namespace dbx

@@ -372,11 +372,11 @@ void launch_build(const uint64_t* keys, int set_shift, float4* leaf, uint32_t n,
              after_level, arg);
 }
 
-void launch_build_boxes(const uint64_t* keys, Node* prims, uint32_t n, Node* nodes,
-                        int32_t* other, int32_t* root, int4* pending, uint32_t* err,
+void launch_build_boxes(const uint64_t* keys, int set_shift, Node* prims, uint32_t n, Node* nodes,
+                        int32_t* other, int32_t* set_root, int4* pending, uint32_t* err,
                         hipStream_t s) {
-  build_impl(keys, 64, BoxLeaves{prims}, n, nodes, other, root, pending, err, s, nullptr,
-             nullptr);
+  build_impl(keys, set_shift, BoxLeaves{prims}, n, nodes, other, set_root, pending, err, s,
+             nullptr, nullptr);
 }
 
 }  // namespace dbx

@@ -104,9 +104,9 @@ void launch_build(const uint64_t* keys, int set_shift, float4* leaf, uint32_t n,
                   int32_t* other, int32_t* set_root, int4* pending, uint32_t* err, hipStream_t s,
                   void (*after_level)(void*, int) = nullptr, void* arg = nullptr);
 // The same over box leaves (DenseBox primitives: Node records, payload in
-// `left`, rope in `rope`), single set.
-void launch_build_boxes(const uint64_t* keys, Node* prims, uint32_t n, Node* nodes,
-                        int32_t* other, int32_t* root, int4* pending, uint32_t* err,
+// `left`, rope in `rope`); sets as in launch_build.
+void launch_build_boxes(const uint64_t* keys, int set_shift, Node* prims, uint32_t n, Node* nodes,
+                        int32_t* other, int32_t* set_root, int4* pending, uint32_t* err,
                         hipStream_t s);
 
 // ---- traversals (traverse.hip) ---------------------------------------------
@@ -146,10 +146,32 @@ void launch_scatter_u8(const uint8_t* src, const uint32_t* perm, uint32_t n,
                        uint8_t* dst, hipStream_t s);
 
 // ---- DenseBox (densebox.hip) -----------------------------------------------
+// Per-set parameters of a DenseBox call, device arrays indexed by set id (a
+// plain call is one set: shift 64, arrays of one).
+struct DbSets {
+  const float* e2;         // eps^2
+  const int32_t* minpts;
+  const int32_t* thresh;   // dense threshold T (>= minPts)
+  const MortonGrid* grid;  // the cell grid (the walks' early end)
+  const int32_t* root;     // subtree root of the set (written by the build)
+  int shift;               // set id = key >> shift; 64: a single set
+};
+// The per-point and per-cell arrays the DenseBox walks read and write.
+struct DbTables {
+  const float4* pts;  // points in cell order
+  const uint32_t* cell_start;
+  const uint32_t* perm;
+  const unsigned long long* cell_minorig;  // minPts > 2 only
+  const float4* cell_lo;
+  const float4* cell_hi;
+  int32_t* parent;
+  uint8_t* flag;
+  unsigned long long* bestcore;  // minPts > 2 only
+};
 // Cell keys (Morton code of the grid cell, side max(1/inv_h, extent/2^21))
-// plus the digit histograms of the sort.
+// plus the digit histograms of the sort; *grid = the cell grid.
 void launch_cell_keys(const float* pts, uint32_t n, const uint32_t* bounds, float inv_h,
-                      uint64_t* keys, uint32_t* hist, hipStream_t s);
+                      uint64_t* keys, uint32_t* hist, MortonGrid* grid, hipStream_t s);
 // words of look-back state of one exclusive scan of n values (zeroed)
 size_t scan_status_words(uint32_t n);
 void launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total,
@@ -159,32 +181,36 @@ void launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total,
 void launch_cells(const uint64_t* sorted_keys, uint32_t n, uint32_t* head, uint32_t* cid,
                   uint32_t* ncells, uint32_t* cell_start, uint32_t* scan_status,
                   uint32_t* scan_ctr, uint32_t* err, hipStream_t s);
-void launch_cell_stats(const float4* pts, const uint32_t* perm, uint32_t n,
-                       const uint32_t* ncells, const uint32_t* cell_start, float e2,
-                       int32_t thresh, float4* cell_lo, float4* cell_hi,
-                       unsigned long long* cell_minorig, uint8_t* cell_dense,
-                       uint32_t* prim_count, hipStream_t s);
+// keys: the sorted cell keys (their set ids pick each cell's eps and T)
+void launch_cell_stats(const float4* pts, const uint32_t* perm, const uint64_t* keys, uint32_t n,
+                       const uint32_t* ncells, const uint32_t* cell_start, const DbSets& sets,
+                       float4* cell_lo, float4* cell_hi, unsigned long long* cell_minorig,
+                       uint8_t* cell_dense, uint32_t* prim_count, hipStream_t s);
 void launch_make_prims(const float4* pts, const uint64_t* keys, uint32_t n, const uint32_t* cid,
                        const uint32_t* cell_start, const uint32_t* prim_start,
                        const uint8_t* cell_dense, const float4* cell_lo, const float4* cell_hi,
                        Node* prims, uint64_t* pkey, int32_t* parent, uint8_t* flag,
                        hipStream_t s);
-void launch_count_db(const Node* nodes, const Node* prims, uint32_t nprims, const float4* pts,
-                     uint32_t n, const uint32_t* cell_start, const int32_t* root, float e2,
-                     int32_t min_pts, uint8_t* flag, uint32_t* err, int block, hipStream_t s);
-void launch_pairs_db(const Node* nodes, const Node* prims, uint32_t nprims, const float4* pts,
-                     uint32_t n, const uint32_t* cell_start, const uint32_t* perm,
-                     const unsigned long long* cell_minorig, float e2, bool core_mode,
-                     int32_t* parent, uint8_t* flag, unsigned long long* bestcore, uint32_t* err,
-                     int block, hipStream_t s);
+// the one-set parameter table of a plain call
+void launch_one_set(float e2, int32_t min_pts, int32_t thresh, float* e2o, int32_t* mpo,
+                    int32_t* tho, hipStream_t s);
+// block: a multiple of 64, at most 1024
+void launch_count_db(const Node* nodes, const Node* prims, const uint64_t* pkey, uint32_t nprims,
+                     const DbSets& sets, const DbTables& t, uint32_t* err, int block,
+                     hipStream_t s);
+void launch_pairs_db(const Node* nodes, const Node* prims, const uint64_t* pkey, uint32_t nprims,
+                     const DbSets& sets, const DbTables& t, uint32_t* err, int block,
+                     hipStream_t s);
 
 // ---- batched sets (batched.hip) -----------------------------------------------
 // Keys of every set: (set id << set_shift) | Morton code with `bits` bits per
 // axis inside the set's own bounding box; set_root[s] = -1 for every set;
 // grids[s] = set s's quantisation grid (for the walks' early end).
+// With set_inv_h (DenseBox), the codes are those of grid cells of side
+// max(1 / set_inv_h[s], extent / 2^bits) per axis instead.
 void launch_set_morton(const float* pts, const int64_t* offsets, uint32_t num_sets, int bits,
-                       int set_shift, uint64_t* keys, uint32_t* hist, int32_t* set_root,
-                       MortonGrid* grids, uint32_t* status, hipStream_t s);
+                       int set_shift, const float* set_inv_h, uint64_t* keys, uint32_t* hist,
+                       int32_t* set_root, MortonGrid* grids, uint32_t* status, hipStream_t s);
 void launch_count_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
                        int set_shift, const int32_t* set_root, const float* set_e2,
                        const int32_t* set_minpts, const MortonGrid* grids, uint8_t* flag,

@@ -1,5 +1,6 @@
 """GPU parity of the batched path: many independent sets in one pass, each
-result bit-identical to the oracle's clustering of that set alone."""
+result bit-identical to the oracle's clustering of that set alone, with
+FDBSCAN and with DenseBox (per-set cell grids and thresholds)."""
 import numpy as np
 import pytest
 
@@ -11,6 +12,7 @@ import paper_2409_10743_amd as dbx  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 F32 = np.float32
+ALGOS = ["fdbscan", "densebox"]
 
 
 @pytest.fixture(scope="module")
@@ -35,12 +37,15 @@ def check(ctx, pts, off, eps, mp, **kw):
         np.testing.assert_array_equal(got[a:b], ref, err_msg=f"set {s}")
 
 
-def test_subhalo_sets_small(ctx):
+@pytest.mark.parametrize("algo", ALGOS)
+def test_subhalo_sets_small(ctx, algo):
     pts, off = datagen.subhalo_sets(64, 4, nmin=64, nmax=8192)
-    check(ctx, pts, off, 0.05, 5)
+    check(ctx, pts, off, 0.05, 5, algorithm=algo)
 
 
-def test_mixed_params_and_empty_sets(ctx):
+@pytest.mark.parametrize("algo,thresh", [("fdbscan", 0), ("densebox", 0), ("densebox", 10),
+                                         ("densebox", 40)])
+def test_mixed_params_and_empty_sets(ctx, algo, thresh):
     rng = np.random.Generator(np.random.PCG64(3))
     sizes = [0, 1, 2, 700, 0, 5000, 33, 4096, 4097, 1]
     parts = [datagen.clumps(max(s, 1), 10 + i)[:s] for i, s in enumerate(sizes)]
@@ -48,27 +53,57 @@ def test_mixed_params_and_empty_sets(ctx):
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     eps = rng.uniform(0.005, 0.05, len(sizes)).astype(F32)
     mp = np.array([1, 2, 3, 5, 10, 2, 1, 4, 2, 7], np.int32)
-    check(ctx, pts, off, eps, mp)
+    check(ctx, pts, off, eps, mp, algorithm=algo, dense_threshold=thresh)
 
 
-def test_overlapping_identical_sets(ctx):
+@pytest.mark.parametrize("algo", ALGOS)
+def test_overlapping_identical_sets(ctx, algo):
     """Sets occupying the same space (ropes must not leak across sets)."""
     p = datagen.clumps(3000, 9)
     pts = np.concatenate([p, p, p]).astype(F32)
     off = np.array([0, 3000, 6000, 9000], np.int64)
-    check(ctx, pts, off, [0.01, 0.02, 0.01], [2, 5, 3])
+    check(ctx, pts, off, [0.01, 0.02, 0.01], [2, 5, 3], algorithm=algo)
 
 
-def test_single_set_equals_plain_call(ctx):
+def test_dense_sets_mixed_with_sparse(ctx):
+    """DenseBox: sets of piled-up duplicates (one dense cell each), tight
+    balls and sparse sets in one call, minPts on both sides of 2."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    parts = [np.repeat(rng.uniform(0, 1, (1, 3)), 500, 0),
+             rng.normal(0.5, 0.002, (3000, 3)),
+             rng.uniform(0, 1, (2000, 3)),
+             np.repeat(rng.uniform(0, 1, (1, 3)), 3, 0),
+             rng.normal(0.2, 0.01, (4000, 3))]
+    pts = np.concatenate(parts).astype(F32)
+    off = np.concatenate([[0], np.cumsum([len(q) for q in parts])]).astype(np.int64)
+    check(ctx, pts, off, [0.01, 0.003, 0.05, 0.0, 0.004], [5, 2, 3, 4, 1],
+          algorithm="densebox")
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_single_set_equals_plain_call(ctx, algo):
     p = datagen.config_points("clumps32k")
-    got = ctx.cluster_batched(dev(p), [0, p.shape[0]], 0.006, 2).cpu().numpy()
-    np.testing.assert_array_equal(got, ctx.cluster(dev(p), 0.006, 2).cpu().numpy())
+    got = ctx.cluster_batched(dev(p), [0, p.shape[0]], 0.006, 2, algorithm=algo).cpu().numpy()
+    np.testing.assert_array_equal(got, ctx.cluster(dev(p), 0.006, 2,
+                                                   algorithm=algo).cpu().numpy())
 
 
-def test_many_sets_block_sizes(ctx):
+@pytest.mark.parametrize("algo", ALGOS)
+def test_many_sets_block_sizes(ctx, algo):
     pts, off = datagen.subhalo_sets(300, 8, nmin=64, nmax=20000)
-    for bs in (64, 256):
-        check(ctx, pts, off, 0.05, 5, block_size=bs)
+    for bs in (64, 256, 1024):
+        check(ctx, pts, off, 0.05, 5, block_size=bs, algorithm=algo)
+
+
+def test_autotune_batched_keeps_labels(ctx):
+    pts, off = datagen.subhalo_sets(40, 5, nmin=64, nmax=20000)
+    best = ctx.autotune_batched(dev(pts), off, 0.05, 5)
+    assert best["algorithm"] in ALGOS and best["block_size"] in (64, 128, 256, 512)
+    assert best["dense_threshold"] in (0, 10, 20) and best["ms"] > 0
+    if best["algorithm"] == "fdbscan":
+        assert best["dense_threshold"] == 0
+    check(ctx, pts, off, 0.05, 5, algorithm=best["algorithm"], block_size=best["block_size"],
+          dense_threshold=best["dense_threshold"])
 
 
 def test_invalid_offsets(ctx):
@@ -80,11 +115,15 @@ def test_invalid_offsets(ctx):
 
 
 def test_subhalo4096_full(ctx):
-    """The full 4,096-set workload (~133M points); every set is checked
-    against the oracle on a deterministic sample of 200 sets plus the
-    largest and smallest."""
+    """The full 4,096-set workload (~133M points), both algorithms: every
+    label equal between them, and every set checked against the oracle on a
+    deterministic sample of 200 sets plus the largest and smallest."""
     pts, off = datagen.subhalo_sets(4096, 4)
-    got = ctx.cluster_batched(dev(pts), off, 0.05, 5).cpu().numpy()
+    d = dev(pts)
+    got = ctx.cluster_batched(d, off, 0.05, 5).cpu().numpy()
+    got_db = ctx.cluster_batched(d, off, 0.05, 5, algorithm="densebox").cpu().numpy()
+    del d
+    np.testing.assert_array_equal(got_db, got)
     sizes = np.diff(off)
     pick = set(np.random.Generator(np.random.PCG64(0)).choice(4096, 200, replace=False).tolist())
     pick |= {int(sizes.argmax()), int(sizes.argmin())}
