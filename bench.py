@@ -22,7 +22,9 @@ Besides the headline line (plain FDBSCAN on the 2^24-point field) the same
 JSON line carries, unless switched off:
   "densebox": the DenseBox variant on the same field;
   "batched":  4,096 independent single-halo sets (~133M points, eps 0.05,
-              minPts 5) in one batched call vs one plain call per set;
+              minPts 5) in one batched call (FDBSCAN, DenseBox, and the
+              autotuner's pick, which "batched_ms" times) vs one plain call
+              per set;
   "serving":  an open-loop replay of Poisson arrivals (200 jobs/s, sizes
               log-uniform in [1e3, 2^24], minPts in {2,5,10}) through the
               continuous-batching server: p50/p99 latency and Mpoints/s,
@@ -280,7 +282,8 @@ def bench_densebox(ctx, d, eps, mp, steps, ref_labels):
 
 
 def bench_batched(ctx, steps=3):
-    """4,096 sets in one batched call vs one plain call per set."""
+    """4,096 sets in one batched call (FDBSCAN, DenseBox, and the option set
+    the batched autotuner picks) vs one plain call per set."""
     import torch
 
     import datagen
@@ -292,14 +295,27 @@ def bench_batched(ctx, steps=3):
     d = torch.from_numpy(pts).cuda()
     del pts
     lab = torch.empty(n, dtype=torch.int32, device="cuda")
-    ctx.cluster_batched(d, off, eps, mp, out=lab)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ctx.cluster_batched(d, off, eps, mp, out=lab)
-    torch.cuda.synchronize()
-    t_b = (time.perf_counter() - t0) / steps
+
+    def timed(**kw):
+        ctx.cluster_batched(d, off, eps, mp, out=lab, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.cluster_batched(d, off, eps, mp, out=lab, **kw)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    t_f = timed(algorithm="fdbscan")
+    lab_f = lab.clone()
+    t_d = timed(algorithm="densebox")
+    same_d = bool(torch.equal(lab, lab_f))
+    log("[bench] batched autotuner ...")
+    tuned = ctx.autotune_batched(d, off, eps, mp)
+    t_b = timed(algorithm=tuned["algorithm"], block_size=tuned["block_size"],
+                dense_threshold=tuned["dense_threshold"])
+    same_t = bool(torch.equal(lab, lab_f))
     # one call per set, in sequence on one stream (launch overheads included)
+    log("[bench] one plain call per set ...")
     lab2 = torch.empty_like(lab)
     for s in range(8):
         ctx.cluster(d[off[s]:off[s + 1]], eps, mp, out=lab2[off[s]:off[s + 1]])
@@ -310,13 +326,17 @@ def bench_batched(ctx, steps=3):
     torch.cuda.synchronize()
     t_p = time.perf_counter() - t0
     # per-set labels are set-local in both
-    same = bool(torch.equal(lab, lab2))
+    same = bool(torch.equal(lab_f, lab2))
     return {"workload": "subhalo4096", "sets": len(off) - 1, "points": n, "eps": eps,
-            "min_pts": mp, "batched_ms": round(t_b * 1e3, 3),
+            "min_pts": mp, "autotuned": {k: tuned[k] for k in
+                                         ("algorithm", "block_size", "dense_threshold")},
+            "batched_ms": round(t_b * 1e3, 3),
             "batched_mpoints_per_s": round(n / t_b / 1e6, 2),
+            "fdbscan_batched_ms": round(t_f * 1e3, 3),
+            "densebox_batched_ms": round(t_d * 1e3, 3),
             "per_set_calls_ms": round(t_p * 1e3, 3),
             "per_set_calls_mpoints_per_s": round(n / t_p / 1e6, 2),
-            "speedup": round(t_p / t_b, 2), "labels_equal": same}
+            "speedup": round(t_p / t_b, 2), "labels_equal": same and same_d and same_t}
 
 
 def _replay(server, jobs, pools, seconds, pinned_labels):
