@@ -54,10 +54,11 @@ BYTES_PER_POINT = {
     "bounds": 12.0,                 # read xyz
     "morton": 12.0 + 8.0,           # read xyz, write code
     "sort": 24.0,                   # per pass: read code+index, write code+index
-    "gather": 4 + 12 + 16 + 4 + 4 + 1,  # read index, xyz; write leaf, parent,
-                                        # minlab, flag
-    "build_frame": 8 + 16 + 16 + 32 + 4,  # codes, leaves in, leaves and nodes out (with
-                                          # ropes), exchange slots of pending splits
+    "gather": 4 + 12 + 16 + 4 + 4 + 1,  # DenseBox: read index, xyz; write point,
+                                        # parent, minlab, flag
+    "build_frame": 4 + 12 + 8 + 16 + 32 + 4 + 4 + 4 + 1,  # index, xyz (gathered), codes;
+                                  # leaves and nodes out (with ropes), exchange slots of
+                                  # pending splits, parent, minlab, flag
     "build_levels": 0.0,            # a few nodes per 256-leaf frame
     "cells": 0.0,                   # DenseBox only
     "count": 16 + 32 + 1,           # leaves, nodes, core flag

@@ -272,7 +272,8 @@ int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore,
                  at<uint32_t>(c, L.sort_status), status};
 
   start_timing(c, timing, s);
-  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, s);
+  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, at<int4>(c, L.pending),
+              L.pending_entries, s);
   mark(c, timing, PH_PREP, s);
   launch_bounds(pts, n, bounds, status, s);
   mark(c, timing, PH_BOUNDS, s);
@@ -286,14 +287,12 @@ int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore,
   uint32_t* perm = va;
   // the other key buffer is free now: the build's scratch
   int32_t* other = reinterpret_cast<int32_t*>(kb);
-  launch_gather(pts, perm, n, at<float4>(c, L.leaf), at<int32_t>(c, L.parent),
-                at<int32_t>(c, L.minlab), at<uint8_t>(c, L.flag),
-                need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr,
-                at<int4>(c, L.pending), L.pending_entries, s);
-  mark(c, timing, PH_GATHER, s);
-  launch_build(keys, 64, at<float4>(c, L.leaf), n, at<Node>(c, L.nodes), other,
-               at<int32_t>(c, L.root), at<int4>(c, L.pending), status, s,
-               timing ? build_mark : nullptr, &sm);
+  // the build's first level gathers the leaves and sets up the union-find
+  launch_build(keys, 64, pts, perm, at<float4>(c, L.leaf), at<int32_t>(c, L.parent),
+               at<int32_t>(c, L.minlab), at<uint8_t>(c, L.flag),
+               need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr, n,
+               at<Node>(c, L.nodes), other, at<int32_t>(c, L.root), at<int4>(c, L.pending),
+               status, s, timing ? build_mark : nullptr, &sm);
   mark(c, timing, PH_BUILD_LEVELS, s);
   out->keys = keys;
   out->bounds = bounds;
@@ -460,8 +459,7 @@ int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_
   const uint64_t* keys = in_a ? ka : kb;
   const uint32_t* perm = in_a ? va : vb;
   int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
-  launch_gather(pts, perm, n, spts, parent, minlab, flag, bestcore, at<int4>(c, L.pending),
-                L.pending_entries, s);
+  launch_gather(pts, perm, n, spts, parent, minlab, flag, bestcore, s);
   mark(c, timing, PH_GATHER, s);
 
   uint32_t* scan_ctr = at<uint32_t>(c, L.scan_ctr);
@@ -541,7 +539,8 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
                  grid, at<int32_t>(c, L.root), 64};
 
   start_timing(c, timing, s);
-  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, s);
+  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, at<int4>(c, L.pending),
+              L.pending_entries, s);
   launch_one_set(eps * eps, min_pts, thresh, const_cast<float*>(S.e2),
                  const_cast<int32_t*>(S.minpts), const_cast<int32_t*>(S.thresh), s);
   mark(c, timing, PH_PREP, s);
@@ -624,7 +623,8 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
     HIP_TRY(hipMemcpyAsync(d_th, s_th, size_t(num_sets) * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(d_ih, s_ih, size_t(num_sets) * 4, hipMemcpyHostToDevice, s));
     start_timing(c, timing, s);
-    launch_prep(at<uint32_t>(c, L.zero), L.zero_words, at<uint32_t>(c, L.bounds), s);
+    launch_prep(at<uint32_t>(c, L.zero), L.zero_words, at<uint32_t>(c, L.bounds),
+                at<int4>(c, L.pending), L.pending_entries, s);
     mark(c, timing, PH_PREP, s);
     launch_set_morton(pts, d_off, num_sets, bits, set_shift, d_ih, at<uint64_t>(c, L.keys_a),
                       at<uint32_t>(c, L.hist), d_root, d_grid, status, s);
@@ -665,7 +665,8 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
     unsigned long long* bestcore = any_core ? at<unsigned long long>(c, L.bestcore) : nullptr;
 
     start_timing(c, timing, gs);
-    launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, gs);
+    launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, at<int4>(c, L.pending),
+              L.pending_entries, gs);
     mark(c, timing, PH_PREP, gs);
     mark(c, timing, PH_BOUNDS, gs);
     launch_set_morton(pts, d_off, num_sets, bits, set_shift, nullptr, ka, sc.hist, d_root, d_grid,
@@ -677,13 +678,10 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
     const uint64_t* keys = in_a ? ka : kb;
     const uint32_t* perm = in_a ? va : vb;
     int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
-    launch_gather(pts, perm, n, leaf, parent, minlab, flag, bestcore, at<int4>(c, L.pending),
-                  L.pending_entries, gs);
-    mark(c, timing, PH_GATHER, gs);
-    mark(c, timing, PH_CELLS, gs);
     Node* nodes = at<Node>(c, L.nodes);
-    launch_build(keys, set_shift, leaf, n, nodes, other, d_root, at<int4>(c, L.pending), status,
-                 gs, timing ? build_mark : nullptr, &sm);
+    launch_build(keys, set_shift, pts, perm, leaf, parent, minlab, flag, bestcore, n, nodes,
+                 other, d_root, at<int4>(c, L.pending), status, gs,
+                 timing ? build_mark : nullptr, &sm);
     mark(c, timing, PH_BUILD_LEVELS, gs);
     if (any_core)
       launch_count_sets(nodes, leaf, n, keys, set_shift, d_root, d_e2, d_mp, d_grid, flag, status,
@@ -921,7 +919,8 @@ int dbscan_morton_codes(dbscan_ctx* c, const float* points, int64_t n, uint64_t*
   if (st != DBSCAN_OK) return st;
   uint32_t* bounds = at<uint32_t>(c, L.bounds);
   uint32_t* status = at<uint32_t>(c, L.status);
-  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, s);
+  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, at<int4>(c, L.pending),
+              L.pending_entries, s);
   launch_bounds(points, uint32_t(n), bounds, status, s);
   launch_morton(points, uint32_t(n), bounds, 0.0f, codes, codes, nullptr, at<uint32_t>(c, L.hist),
                 s);
@@ -942,7 +941,8 @@ int dbscan_sort_pairs(dbscan_ctx* c, uint64_t* keys, uint32_t* vals, int64_t n, 
   uint32_t* status = at<uint32_t>(c, L.status);
   SortScratch sc{at<uint32_t>(c, L.hist), at<uint32_t>(c, L.tile_ctr),
                  at<uint32_t>(c, L.sort_status), status};
-  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, at<uint32_t>(c, L.bounds), s);
+  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, at<uint32_t>(c, L.bounds),
+              at<int4>(c, L.pending), L.pending_entries, s);
   launch_digit_histogram(keys, uint32_t(n), sc.hist, s);
   bool in_a = launch_radix_sort(keys, at<uint64_t>(c, L.keys_b), vals, at<uint32_t>(c, L.vals_b),
                                 uint32_t(n), 0, false, sc, s);

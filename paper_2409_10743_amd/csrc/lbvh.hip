@@ -63,15 +63,38 @@ namespace dbx {
 namespace {
 
 // Leaves are points (FDBSCAN: float4 x, y, z, rope) or boxes (DenseBox
-// primitives: Node records whose `left` holds the payload).
+// primitives: Node records whose `left` holds the payload).  The levels
+// above the first only load leaves.
 struct PointLeaves {
   float4* leaf;
   __device__ void load(int32_t j, float4& lo, float4& hi) const { lo = hi = leaf[j]; }
-  // whole record, coalesced, when the frame writes its leaves out
+};
+// FDBSCAN's level-1 frames: leaf j is gathered from input point perm[j]
+// here (a random 12-byte read) and written once, with its rope, together
+// with the point's union-find state; later levels read the written leaves.
+struct GatherLeaves {
+  const float* pts;
+  const uint32_t* perm;
+  uint32_t n;
+  float4* leaf;
+  int32_t* parent;
+  int32_t* minlab;
+  uint8_t* flag;
+  unsigned long long* bestcore;  // null unless minPts > 2
+  __device__ void load(int32_t j, float4& lo, float4& hi) const {
+    const uint32_t o = min(perm[j], n - 1);  // a permutation unless the sort failed
+    const float* p = pts + size_t(3) * o;
+    lo = hi = make_float4(p[0], p[1], p[2], 0.0f);
+  }
   __device__ void write_out(int32_t j, const float4& lo, const float4&, int32_t rope) const {
     leaf[j] = make_float4(lo.x, lo.y, lo.z, __int_as_float(rope));
+    parent[j] = j;
+    minlab[j] = 0x7fffffff;
+    flag[j] = 0;
+    if (bestcore) bestcore[j] = ~0ull;
+    if (uint32_t(j) == n - 1)  // the walks read one record past the last leaf
+      leaf[n] = make_float4(0.f, 0.f, 0.f, __int_as_float(SENTINEL));
   }
-  __device__ void set_rope(int32_t j, int32_t rope) const { leaf[j].w = __int_as_float(rope); }
 };
 struct BoxLeaves {
   Node* prim;
@@ -83,7 +106,6 @@ struct BoxLeaves {
   __device__ void write_out(int32_t j, const float4&, const float4&, int32_t rope) const {
     prim[j].rope = rope;
   }
-  __device__ void set_rope(int32_t j, int32_t rope) const { prim[j].rope = rope; }
 };
 
 __device__ __forceinline__ uint64_t set_mask_of(int set_shift) {
@@ -230,7 +252,7 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
   // slot of split f0+t unless it is finished (the frame's right edge split
   // is never touched here: -1)
   const int32_t p = f0 + t;
-  if (t < m && n > 1) {
+  if (t < m) {  // n = 1 too: the one leaf still goes out
     lv.write_out(p, s_leaf[t], s_leafhi[t], rope_of(p, last, s_cut[t + 1], D(p), D(p + 1)));
     const int32_t r = s_end[t];
     if (r >= 0)
@@ -339,10 +361,12 @@ size_t build_pending_entries(uint32_t n) {
 }
 
 namespace {
-template <class Leaves>
-void build_impl(const uint64_t* keys, int set_shift, Leaves lv, uint32_t n, Node* nodes,
-                int32_t* other, int32_t* root, int4* pending, uint32_t* err, hipStream_t s,
-                void (*after_level)(void*, int), void* arg) {
+// FrameLeaves: the leaves as level 1 reads and writes them; Leaves: as the
+// later levels read them
+template <class FrameLeaves, class Leaves>
+void build_impl(const uint64_t* keys, int set_shift, FrameLeaves flv, Leaves lv, uint32_t n,
+                Node* nodes, int32_t* other, int32_t* root, int4* pending, uint32_t* err,
+                hipStream_t s, void (*after_level)(void*, int), void* arg) {
   if (n == 0) return;
   const int levels = build_levels(n);
   uint64_t frame = BUILD_LEAVES;
@@ -351,8 +375,8 @@ void build_impl(const uint64_t* keys, int set_shift, Leaves lv, uint32_t n, Node
   for (int lv_i = 1; lv_i <= levels; ++lv_i) {
     const uint32_t frames = uint32_t((n + frame - 1) / frame);
     if (lv_i == 1)
-      hipLaunchKernelGGL(k_build_frame<Leaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys, lv,
-                         n, set_shift, nodes, other, root, pout, err);
+      hipLaunchKernelGGL(k_build_frame<FrameLeaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys,
+                         flv, n, set_shift, nodes, other, root, pout, err);
     else
       hipLaunchKernelGGL(k_build_level<Leaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys, lv,
                          n, lv_i, set_shift, nodes, other, root, pin, pout, err);
@@ -365,18 +389,20 @@ void build_impl(const uint64_t* keys, int set_shift, Leaves lv, uint32_t n, Node
 
 }  // namespace
 
-void launch_build(const uint64_t* keys, int set_shift, float4* leaf, uint32_t n, Node* nodes,
-                  int32_t* other, int32_t* set_root, int4* pending, uint32_t* err, hipStream_t s,
+void launch_build(const uint64_t* keys, int set_shift, const float* pts, const uint32_t* perm,
+                  float4* leaf, int32_t* parent, int32_t* minlab, uint8_t* flag,
+                  unsigned long long* bestcore, uint32_t n, Node* nodes, int32_t* other,
+                  int32_t* set_root, int4* pending, uint32_t* err, hipStream_t s,
                   void (*after_level)(void*, int), void* arg) {
-  build_impl(keys, set_shift, PointLeaves{leaf}, n, nodes, other, set_root, pending, err, s,
-             after_level, arg);
+  build_impl(keys, set_shift, GatherLeaves{pts, perm, n, leaf, parent, minlab, flag, bestcore},
+             PointLeaves{leaf}, n, nodes, other, set_root, pending, err, s, after_level, arg);
 }
 
 void launch_build_boxes(const uint64_t* keys, int set_shift, Node* prims, uint32_t n, Node* nodes,
                         int32_t* other, int32_t* set_root, int4* pending, uint32_t* err,
                         hipStream_t s) {
-  build_impl(keys, set_shift, BoxLeaves{prims}, n, nodes, other, set_root, pending, err, s,
-             nullptr, nullptr);
+  build_impl(keys, set_shift, BoxLeaves{prims}, BoxLeaves{prims}, n, nodes, other, set_root,
+             pending, err, s, nullptr, nullptr);
 }
 
 }  // namespace dbx

@@ -17,10 +17,13 @@ namespace dbx {
 
 namespace {
 
-__global__ void k_prep(uint32_t* __restrict__ z, size_t words, uint32_t* __restrict__ bounds) {
-  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  size_t stride = size_t(gridDim.x) * blockDim.x;
-  for (; i < words; i += stride) z[i] = 0u;
+__global__ void k_prep(uint32_t* __restrict__ z, size_t words, uint32_t* __restrict__ bounds,
+                       int4* __restrict__ pending, uint32_t pending_entries) {
+  const size_t i0 = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = i0; i < words; i += stride) z[i] = 0u;
+  // build hand-over entries: empty until a frame hands a node up
+  for (size_t i = i0; i < pending_entries; i += stride) pending[i] = make_int4(SENTINEL, 0, 0, 0);
   if (blockIdx.x == 0 && threadIdx.x < 6)
     bounds[threadIdx.x] = threadIdx.x < 3 ? 0xffffffffu : 0u;  // lo = +max, hi = -max
 }
@@ -201,11 +204,8 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
 __global__ __launch_bounds__(256) void k_gather(
     const float* __restrict__ pts, const uint32_t* __restrict__ perm, uint32_t n,
     float4* __restrict__ leaf, int32_t* __restrict__ parent, int32_t* __restrict__ minlab,
-    uint8_t* __restrict__ flag, unsigned long long* __restrict__ bestcore,
-    int4* __restrict__ pending, uint32_t pending_entries) {
+    uint8_t* __restrict__ flag, unsigned long long* __restrict__ bestcore) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  for (uint32_t k = i; k < pending_entries; k += gridDim.x * blockDim.x)
-    pending[k] = make_int4(SENTINEL, 0, 0, 0);
   if (i == 0) leaf[n] = make_float4(0.f, 0.f, 0.f, __int_as_float(SENTINEL));  // padding
   if (i >= n) return;
   const uint32_t o = min(perm[i], n - 1);  // a permutation unless the sort failed
@@ -223,9 +223,12 @@ uint32_t reduce_blocks(uint32_t n) { return std::max(1u, std::min((n + 1023) / 1
 
 }  // namespace
 
-void launch_prep(uint32_t* zero_region, size_t zero_words, uint32_t* bounds, hipStream_t s) {
-  uint32_t blocks = uint32_t(std::min<size_t>((zero_words + 255) / 256 + 1, 4096));
-  hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, s, zero_region, zero_words, bounds);
+void launch_prep(uint32_t* zero_region, size_t zero_words, uint32_t* bounds, int4* pending,
+                 uint32_t pending_entries, hipStream_t s) {
+  const size_t work = std::max<size_t>(zero_words, pending_entries);
+  uint32_t blocks = uint32_t(std::min<size_t>((work + 255) / 256 + 1, 4096));
+  hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(256), 0, s, zero_region, zero_words, bounds,
+                     pending, pending_entries);
 }
 
 void launch_bounds(const float* pts, uint32_t n, uint32_t* bounds, uint32_t* status,
@@ -257,11 +260,10 @@ void launch_morton(const float* pts, uint32_t n, const uint32_t* bounds, float e
 
 void launch_gather(const float* pts, const uint32_t* perm, uint32_t n, float4* leaf,
                    int32_t* parent, int32_t* minlab, uint8_t* flag,
-                   unsigned long long* bestcore, int4* pending, uint32_t pending_entries,
-                   hipStream_t s) {
+                   unsigned long long* bestcore, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, s, pts, perm, n, leaf,
-                     parent, minlab, flag, bestcore, pending, pending_entries);
+                     parent, minlab, flag, bestcore);
 }
 
 }  // namespace dbx

@@ -66,8 +66,10 @@ bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
 
 // ---- bounds, Morton codes, leaf scatter (morton.hip) -----------------------
 // bounds[0..2] lo (ordered-int encoding), bounds[3..5] hi
-void launch_prep(uint32_t* zero_region, size_t zero_words, uint32_t* bounds,
-                 hipStream_t s);
+// Zero the region, reset the bounds words, empty the build hand-over
+// entries.
+void launch_prep(uint32_t* zero_region, size_t zero_words, uint32_t* bounds, int4* pending,
+                 uint32_t pending_entries, hipStream_t s);
 void launch_bounds(const float* pts, uint32_t n, uint32_t* bounds,
                    uint32_t* status, hipStream_t s);
 // Codes with their lowest droppable_code_bits(bounds, eps) bits cleared
@@ -82,8 +84,7 @@ void launch_morton(const float* pts, uint32_t n, const uint32_t* bounds, float e
 // per-point state and fills the build's hand-over entries with -1.
 void launch_gather(const float* pts, const uint32_t* perm, uint32_t n,
                    float4* leaf, int32_t* parent, int32_t* minlab,
-                   uint8_t* flag, unsigned long long* bestcore,
-                   int4* pending, uint32_t pending_entries, hipStream_t s);
+                   uint8_t* flag, unsigned long long* bestcore, hipStream_t s);
 
 // ---- LBVH (lbvh.hip) --------------------------------------------------------
 constexpr int BUILD_LEAVES = 256;        // leaves per level-1 frame
@@ -99,9 +100,15 @@ size_t build_pending_entries(uint32_t n);
 // sets; 64 = a single set): ropes are then cut at set ends and set_root[s]
 // receives the root of set s's subtree (for a single set, set_root[0] = the
 // root).  `after_level(arg, lv)`, if given, is called after level lv is
-// enqueued.
-void launch_build(const uint64_t* keys, int set_shift, float4* leaf, uint32_t n, Node* nodes,
-                  int32_t* other, int32_t* set_root, int4* pending, uint32_t* err, hipStream_t s,
+// enqueued.  The level-1 frames gather their leaves: leaf j = input point
+// perm[j] (with its rope; leaf[n] is a padding record), and they set up the
+// union-find state of their points (parent[j] = j, minlab[j] = INT_MAX,
+// flag[j] = 0, bestcore[j] = ~0 if bestcore is given).  pending must have
+// been emptied (launch_prep).
+void launch_build(const uint64_t* keys, int set_shift, const float* pts, const uint32_t* perm,
+                  float4* leaf, int32_t* parent, int32_t* minlab, uint8_t* flag,
+                  unsigned long long* bestcore, uint32_t n, Node* nodes, int32_t* other,
+                  int32_t* set_root, int4* pending, uint32_t* err, hipStream_t s,
                   void (*after_level)(void*, int) = nullptr, void* arg = nullptr);
 // The same over box leaves (DenseBox primitives: Node records, payload in
 // `left`, rope in `rope`); sets as in launch_build.
