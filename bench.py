@@ -56,15 +56,16 @@ BYTES_PER_POINT = {
     "sort": 24.0,                   # per pass: read code+index, write code+index
     "gather": 4 + 12 + 16 + 4 + 4 + 1,  # DenseBox: read index, xyz; write point,
                                         # parent, minlab, flag
-    "build_frame": 4 + 12 + 8 + 16 + 32 + 4 + 4 + 4 + 1,  # index, xyz (gathered), codes;
+    "build_frame": 4 + 12 + 8 + 16 + 32 + 4 + 4 + 1 + 4,  # index, xyz (gathered), codes;
                                   # leaves and nodes out (with ropes), exchange slots of
-                                  # pending splits, parent, minlab, flag
+                                  # pending splits, parent, flag, label -1
     "build_levels": 0.0,            # a few nodes per 256-leaf frame
     "cells": 0.0,                   # DenseBox only
     "count": 16 + 32 + 1,           # leaves, nodes, core flag
     "pairs": 16 + 32 + 4 + 4 + 1,   # leaves, nodes, parent read/write, member flag
-    "final_roots": 1 + 4 + 4 + 4 + 4,  # flag, parent, perm + minlab (clustered), root, label -1
-    "final_labels": 4.0,            # root; + perm, minlab, label for clustered points only
+    "final_roots": 0.0,             # (the label pass is one kernel with minPts <= 2)
+    "final_labels": 1.0,            # member flag; + parent, perm, label for clustered
+                                    # points only (labels start at -1 from the build)
 }
 # the first sort pass reads no values (they are the identity)
 FIRST_SORT_PASS_BYTES = 20.0

@@ -126,7 +126,9 @@ int dbscan_phase_times(const dbscan_ctx* ctx, float* ms, int32_t max);
 /* Name of timing slot k (one per kernel launch of a run: "prep", "bounds",
  * "morton", "sort0".."sort7", "gather", "cells", "build_frame", "build_levels",
  * "count", "pairs", "final_roots", "final_labels"; a slot a run does not use
- * reads 0 ms), NULL past the last. */
+ * reads 0 ms: FDBSCAN gathers inside "build_frame", only DenseBox has
+ * "gather" and "cells", and the whole label pass is timed as
+ * "final_labels"), NULL past the last. */
 const char* dbscan_phase_name(int32_t k);
 
 /* Sort passes the context's last plain clustering call ran: 8 minus the

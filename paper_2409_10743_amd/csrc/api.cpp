@@ -84,7 +84,7 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
   L.leaf = take((size_t(n) + 1) * 16);  // + one padding record read by the walks
   L.nodes = take(size_t(n > 1 ? n - 1 : 1) * sizeof(Node));
   L.parent = take(size_t(n) * 4);
-  L.minlab = take(size_t(n) * 4);
+  L.minlab = need_bestcore ? take(size_t(n) * 4) : 0;  // border points' label minima
   L.flag = take(size_t(n));
   L.bestcore = need_bestcore ? take(size_t(n) * 8) : 0;
   L.pending_entries = uint32_t(build_pending_entries(n));
@@ -95,7 +95,7 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
     L.cell_start = take((size_t(n) + 1) * 4);
     L.cell_lo = take(size_t(n) * 16);
     L.cell_hi = take(size_t(n) * 16);
-    L.cell_minorig = need_bestcore ? take(size_t(n) * 8) : 0;
+    L.cell_minorig = take(size_t(n) * 8);
     L.cell_dense = take(size_t(n));
     L.prim_count = take(size_t(n) * 4);
     L.prim_start = take(size_t(n) * 4);
@@ -256,8 +256,9 @@ void build_mark(void* arg, int level) {  // level 1 = the frame kernel
   if (level == 1) mark(m->c, true, PH_BUILD_FRAME, m->s);
 }
 
+// labels (or null): set to -1 here, by the build's first level.
 int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore, bool timing,
-                hipStream_t s, Index* out, float code_eps) {
+                hipStream_t s, Index* out, float code_eps, int32_t* labels) {
   Layout L = make_layout(n, need_bestcore);
   int st = ensure_arena(c, L.total);
   if (st != DBSCAN_OK) return st;
@@ -289,8 +290,8 @@ int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore,
   int32_t* other = reinterpret_cast<int32_t*>(kb);
   // the build's first level gathers the leaves and sets up the union-find
   launch_build(keys, 64, pts, perm, at<float4>(c, L.leaf), at<int32_t>(c, L.parent),
-               at<int32_t>(c, L.minlab), at<uint8_t>(c, L.flag),
-               need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr, n,
+               need_bestcore ? at<int32_t>(c, L.minlab) : nullptr, at<uint8_t>(c, L.flag),
+               need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr, labels, n,
                at<Node>(c, L.nodes), other, at<int32_t>(c, L.root), at<int4>(c, L.pending),
                status, s, timing ? build_mark : nullptr, &sm);
   mark(c, timing, PH_BUILD_LEVELS, s);
@@ -403,7 +404,7 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
                                      uint64_t(block)};
   st = run_enqueued(c, s, graph, key, [&](hipStream_t gs) {
     Index ix;
-    int r = build_index(c, pts, n, core_mode, timing, gs, &ix, eps);
+    int r = build_index(c, pts, n, core_mode, timing, gs, &ix, eps, labels);
     if (r != DBSCAN_OK) return r;
     uint8_t* flag = at<uint8_t>(c, L.flag);
     int32_t* parent = at<int32_t>(c, L.parent);
@@ -417,13 +418,11 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
       launch_pairs_core(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, flag,
                         ix.perm, parent, bestcore, ix.status, block, gs);
     else
-      launch_pairs_fof(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, parent, flag,
+      launch_pairs_fof(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, ix.perm, parent, flag,
                        ix.status, block, gs);
     mark(c, timing, PH_PAIRS, gs);
-    int32_t* minlab = at<int32_t>(c, L.minlab);
-    launch_final_roots(n, min_pts, flag, bestcore, ix.perm, parent, minlab, labels, gs);
-    mark(c, timing, PH_FINAL_ROOTS, gs);
-    launch_final_labels(n, ix.perm, parent, minlab, labels, gs);
+    int32_t* minlab = core_mode ? at<int32_t>(c, L.minlab) : nullptr;
+    launch_final(n, min_pts, flag, bestcore, ix.perm, parent, minlab, labels, gs);
     mark(c, timing, PH_FINAL_LABELS, gs);
     HIP_TRY(hipGetLastError());
     return int(DBSCAN_OK);
@@ -450,7 +449,7 @@ int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_
   float4* spts = at<float4>(c, L.leaf);  // points in cell order
   int32_t* parent = at<int32_t>(c, L.parent);
   uint8_t* flag = at<uint8_t>(c, L.flag);
-  int32_t* minlab = at<int32_t>(c, L.minlab);
+  int32_t* minlab = any_core ? at<int32_t>(c, L.minlab) : nullptr;
   unsigned long long* bestcore = any_core ? at<unsigned long long>(c, L.bestcore) : nullptr;
 
   SortMarks sm{c, s};
@@ -459,7 +458,7 @@ int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_
   const uint64_t* keys = in_a ? ka : kb;
   const uint32_t* perm = in_a ? va : vb;
   int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
-  launch_gather(pts, perm, n, spts, parent, minlab, flag, bestcore, s);
+  launch_gather(pts, perm, n, spts, parent, minlab, flag, bestcore, labels, s);
   mark(c, timing, PH_GATHER, s);
 
   uint32_t* scan_ctr = at<uint32_t>(c, L.scan_ctr);
@@ -469,8 +468,7 @@ int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_
   uint32_t* cid = at<uint32_t>(c, L.cid);
   launch_cells(keys, n, at<uint32_t>(c, L.head), cid, ncells, cell_start,
                at<uint32_t>(c, L.scan1), scan_ctr, status, s);
-  unsigned long long* cell_minorig =
-      any_core ? at<unsigned long long>(c, L.cell_minorig) : nullptr;
+  unsigned long long* cell_minorig = at<unsigned long long>(c, L.cell_minorig);
   float4* cell_lo = at<float4>(c, L.cell_lo);
   float4* cell_hi = at<float4>(c, L.cell_hi);
   uint8_t* cell_dense = at<uint8_t>(c, L.cell_dense);
@@ -488,7 +486,7 @@ int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_
   Node* prims = at<Node>(c, L.prims);
   uint64_t* pkey = at<uint64_t>(c, L.pkey);
   launch_make_prims(spts, keys, n, cid, cell_start, prim_start, cell_dense, cell_lo, cell_hi,
-                    prims, pkey, parent, flag, s);
+                    cell_minorig, prims, pkey, parent, flag, s);
   mark(c, timing, PH_CELLS, s);
 
   Node* nodes = at<Node>(c, L.nodes);
@@ -506,9 +504,7 @@ int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_
                       labels, s);
     mark(c, timing, PH_FINAL_LABELS, s);
   } else {
-    launch_final_roots(n, min_pts, flag, bestcore, perm, parent, minlab, labels, s);
-    mark(c, timing, PH_FINAL_ROOTS, s);
-    launch_final_labels(n, perm, parent, minlab, labels, s);
+    launch_final(n, min_pts, flag, bestcore, perm, parent, minlab, labels, s);
     mark(c, timing, PH_FINAL_LABELS, s);
   }
   return DBSCAN_OK;
@@ -661,7 +657,7 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
     float4* leaf = at<float4>(c, L.leaf);
     int32_t* parent = at<int32_t>(c, L.parent);
     uint8_t* flag = at<uint8_t>(c, L.flag);
-    int32_t* minlab = at<int32_t>(c, L.minlab);
+    int32_t* minlab = any_core ? at<int32_t>(c, L.minlab) : nullptr;
     unsigned long long* bestcore = any_core ? at<unsigned long long>(c, L.bestcore) : nullptr;
 
     start_timing(c, timing, gs);
@@ -679,8 +675,8 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
     const uint32_t* perm = in_a ? va : vb;
     int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
     Node* nodes = at<Node>(c, L.nodes);
-    launch_build(keys, set_shift, pts, perm, leaf, parent, minlab, flag, bestcore, n, nodes,
-                 other, d_root, at<int4>(c, L.pending), status, gs,
+    launch_build(keys, set_shift, pts, perm, leaf, parent, minlab, flag, bestcore, labels, n,
+                 nodes, other, d_root, at<int4>(c, L.pending), status, gs,
                  timing ? build_mark : nullptr, &sm);
     mark(c, timing, PH_BUILD_LEVELS, gs);
     if (any_core)
@@ -966,7 +962,7 @@ int dbscan_build_tree(dbscan_ctx* c, const float* points, int64_t n, uint32_t* p
   DeviceGuard g(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index ix;
-  st = build_index(c, points, uint32_t(n), false, false, s, &ix, 0.0f);
+  st = build_index(c, points, uint32_t(n), false, false, s, &ix, 0.0f, nullptr);
   if (st != DBSCAN_OK) return st;
   HIP_TRY(hipMemcpyAsync(perm, ix.perm, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemcpyAsync(leaf, ix.leaf, size_t(n) * 16, hipMemcpyDeviceToDevice, s));
@@ -985,7 +981,7 @@ int dbscan_core_flags(dbscan_ctx* c, const float* points, int64_t n, float eps, 
   DeviceGuard g(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index ix;
-  st = build_index(c, points, uint32_t(n), false, false, s, &ix, eps);
+  st = build_index(c, points, uint32_t(n), false, false, s, &ix, eps, nullptr);
   if (st != DBSCAN_OK) return st;
   uint8_t* flag = at<uint8_t>(c, ix.L.flag);
   launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, uint32_t(n), ix.root,
@@ -1013,7 +1009,7 @@ int dbscan_traversal_stats(dbscan_ctx* c, const float* points, int64_t n, float 
   DeviceGuard g(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index ix;
-  st = build_index(c, points, uint32_t(n), false, false, s, &ix, eps);
+  st = build_index(c, points, uint32_t(n), false, false, s, &ix, eps, nullptr);
   if (st != DBSCAN_OK) return st;
   unsigned long long* dcount = at<unsigned long long>(c, ix.L.count);
   launch_pairs_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, uint32_t(n),

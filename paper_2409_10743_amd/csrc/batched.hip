@@ -179,12 +179,12 @@ struct PairSets {
   __device__ bool hit(uint32_t i, int32_t j, const float4&) {
     if (!core_mode) {
       found = true;
-      ri = uf_union(parent, ri, j);
+      ri = uf_union(parent, perm, ri, j);
       flag[j] = 1;
       return false;
     }
     const bool cj = flag[j] != 0;
-    if (ci && cj) ri = uf_union(parent, ri, j);
+    if (ci && cj) ri = uf_union(parent, perm, ri, j);
     else if (ci) atomicMin(bestcore + j, (static_cast<unsigned long long>(perm[i]) << 32) | i);
     else if (cj)
       atomicMin(bestcore + i, (static_cast<unsigned long long>(perm[j]) << 32) | uint32_t(j));
@@ -210,31 +210,50 @@ __global__ void k_pairs_sets(const Node* __restrict__ nodes, const float4* __res
 }
 
 
+// Labels as in finalize.hip, each point by its own set's minPts: a
+// clustered point's label is the smallest input index of its cluster (the
+// root's, or a border point's, collected in minlab) minus the set's offset;
+// noise keeps the -1 the build wrote.
+__device__ __forceinline__ int32_t set_cluster_root(uint32_t i, int32_t mp,
+                                                    const uint8_t* __restrict__ flag,
+                                                    const unsigned long long* __restrict__ bestcore,
+                                                    int32_t* parent) {
+  if (mp <= 2) return (mp == 1 || flag[i]) ? uf_root_final(parent, int32_t(i)) : -1;
+  if (flag[i]) return uf_root_final(parent, int32_t(i));
+  const unsigned long long b = bestcore[i];
+  return b == ~0ull ? -1 : uf_root_final(parent, int32_t(uint32_t(b)));
+}
+
+// no set with minPts > 2: one pass
+__global__ __launch_bounds__(256) void k_final_labels_sets(
+    uint32_t n, const uint64_t* __restrict__ keys, int set_shift,
+    const int32_t* __restrict__ set_minpts, const int64_t* __restrict__ offsets,
+    const uint8_t* __restrict__ flag, const uint32_t* __restrict__ perm, int32_t* parent,
+    int32_t* __restrict__ labels) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t set = uint32_t(keys[i] >> set_shift);
+  const int32_t r = set_cluster_root(i, set_minpts[set], flag, nullptr, parent);
+  if (r < 0) return;
+  const uint32_t o = perm[i];
+  if (o < n) labels[o] = int32_t(perm[r]) - int32_t(offsets[set]);
+}
+
+// some set with minPts > 2: roots and border minima, then labels
 __global__ __launch_bounds__(256) void k_final_roots_sets(
     uint32_t n, const uint64_t* __restrict__ keys, int set_shift,
     const int32_t* __restrict__ set_minpts, const uint8_t* __restrict__ flag,
     const unsigned long long* __restrict__ bestcore, const uint32_t* __restrict__ perm,
-    int32_t* parent, int32_t* __restrict__ minlab, int32_t* __restrict__ labels) {
+    int32_t* parent, int32_t* __restrict__ minlab) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool ok = i < n;  // no early return: the wave combines its minima
-  int32_t r = -1;
-  if (ok) {
-    labels[i] = -1;  // the second pass writes clustered points only
-    const int32_t mp = set_minpts[uint32_t(keys[i] >> set_shift)];
-    if (mp <= 2) {
-      r = (mp == 1 || flag[i]) ? uf_root_final(parent, int32_t(i)) : -1;
-    } else if (flag[i]) {
-      r = uf_root_final(parent, int32_t(i));
-    } else {
-      const unsigned long long b = bestcore[i];
-      r = b == ~0ull ? -1 : uf_root_final(parent, int32_t(uint32_t(b)));
-    }
-  }
-  wave_min_by_key(minlab, r, r >= 0 ? int32_t(perm[i]) : 0);
-  if (ok) parent[i] = r;
+  if (i >= n) return;
+  const int32_t mp = set_minpts[uint32_t(keys[i] >> set_shift)];
+  const int32_t r = set_cluster_root(i, mp, flag, bestcore, parent);
+  if (r >= 0 && mp > 2 && !flag[i]) atomicMin(minlab + r, int32_t(perm[i]));
+  parent[i] = r;
 }
 
-__global__ __launch_bounds__(256) void k_final_labels_sets(
+__global__ __launch_bounds__(256) void k_final_border_labels_sets(
     uint32_t n, const uint64_t* __restrict__ keys, int set_shift,
     const int64_t* __restrict__ offsets, const uint32_t* __restrict__ perm,
     const int32_t* __restrict__ root, const int32_t* __restrict__ minlab,
@@ -245,7 +264,7 @@ __global__ __launch_bounds__(256) void k_final_labels_sets(
   if (r < 0) return;  // noise: already -1
   const uint32_t o = perm[i];
   const int32_t base = int32_t(offsets[uint32_t(keys[i] >> set_shift)]);
-  if (o < n) labels[o] = minlab[r] - base;
+  if (o < n) labels[o] = min(int32_t(perm[r]), minlab[r]) - base;
 }
 
 }  // namespace
@@ -286,10 +305,15 @@ void launch_final_sets(uint32_t n, const uint64_t* keys, int set_shift, const in
                        int32_t* minlab, int32_t* labels, hipStream_t s) {
   if (n == 0) return;
   const uint32_t g = (n + 255) / 256;
+  if (!bestcore) {  // no set with minPts > 2
+    hipLaunchKernelGGL(k_final_labels_sets, dim3(g), dim3(256), 0, s, n, keys, set_shift,
+                       set_minpts, offsets, flag, perm, parent, labels);
+    return;
+  }
   hipLaunchKernelGGL(k_final_roots_sets, dim3(g), dim3(256), 0, s, n, keys, set_shift,
-                     set_minpts, flag, bestcore, perm, parent, minlab, labels);
-  hipLaunchKernelGGL(k_final_labels_sets, dim3(g), dim3(256), 0, s, n, keys, set_shift, offsets,
-                     perm, parent, minlab, labels);
+                     set_minpts, flag, bestcore, perm, parent, minlab);
+  hipLaunchKernelGGL(k_final_border_labels_sets, dim3(g), dim3(256), 0, s, n, keys, set_shift,
+                     offsets, perm, parent, minlab, labels);
 }
 
 }  // namespace dbx

@@ -93,22 +93,25 @@ __device__ __forceinline__ T cas_agent(T* p, T expected, T desired) {
 }
 
 // ---- lock-free union-find (section 4.3, disjoint sets) --------------------
-// parent[] over Morton-sorted positions.  Invariant: a non-root x always has
-// parent[x] < x, so the forest stays acyclic whatever order racing writes
-// land in, and every value ever stored is an ancestor.  Roots are hooked by
-// CAS (larger root under smaller); path halving uses plain relaxed stores,
-// which only ever touch non-roots and so never undo a hook.
+// parent[] over Morton-sorted positions, roots ordered by key[] (the sort's
+// permutation: a position's input index).  Invariant: a non-root x always
+// has key[parent[x]] < key[x], so the forest stays acyclic whatever order
+// racing writes land in, every value ever stored is an ancestor, and the
+// root of a set is its member with the smallest input index: the cluster's
+// label.  Roots are hooked by CAS (the one with the larger key under the
+// other); path halving uses plain relaxed stores, which only ever touch
+// non-roots and so never undo a hook.
 //
 // The finds read and halve at workgroup scope: a load may hit a stale line
 // in the CU's own cache.  That is safe.  Every value parent[x] ever held is
-// a node of x's set, smaller than x, so a stale read still moves down a
-// strictly decreasing chain of x's set, and a stale "root" r is still in
-// the set.  A union that ends because both finds met the same node joins
-// two nodes that are already connected; one whose CAS expects a stale root
-// fails (the CAS is at agent scope and sees the true value) and continues
-// from the value it found, which is smaller: so every union ends.  Finds
-// after the kernel (label finalisation) run in a later launch and see the
-// final forest.
+// a node of x's set with a smaller key, so a stale read still moves down a
+// chain of x's set with strictly decreasing keys, and a stale "root" r is
+// still in the set.  A union that ends because both finds met the same node
+// joins two nodes that are already connected; one whose CAS expects a stale
+// root fails (the CAS is at agent scope and sees the true value) and
+// continues from the value it found, whose key is smaller: so every union
+// ends.  Finds after the kernel (label finalisation) run in a later launch
+// and see the final forest.
 __device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
   for (;;) {
     int32_t p = ld_wg(parent + x);
@@ -124,39 +127,17 @@ __device__ __forceinline__ int32_t uf_find(int32_t* parent, int32_t x) {
 // ancestor of both (the merged root or, if others hooked it meanwhile, one
 // of its descendants): a walk that unions one point with many neighbours
 // passes it back as `a` and so starts each find from high up its chain.
-__device__ __forceinline__ int32_t uf_union(int32_t* parent, int32_t a, int32_t b) {
+__device__ __forceinline__ int32_t uf_union(int32_t* parent, const uint32_t* __restrict__ key,
+                                            int32_t a, int32_t b) {
   for (;;) {
     a = uf_find(parent, a);
     b = uf_find(parent, b);
     if (a == b) return a;
-    if (a > b) { int32_t t = a; a = b; b = t; }
+    if (key[a] > key[b]) { int32_t t = a; a = b; b = t; }
     int32_t seen = cas_agent(parent + b, b, a);
     if (seen == b) return a;
     b = seen;  // b was hooked under `seen` meanwhile: continue from there
   }
-}
-
-// atomicMin(dst + key, v) for every lane with key >= 0; every lane of the
-// wave must call it.  In a dense cluster most of a wave's points share one
-// root, and one atomic per member on that single address serialises; so
-// while the key of the lowest pending lane is held by at least 4 lanes,
-// those lanes' minimum goes out as one atomic (at most 4 such rounds), and
-// the rest take one atomic each.
-__device__ __forceinline__ void wave_min_by_key(int32_t* dst, int32_t key, int32_t v) {
-  const int lane = threadIdx.x & 63;
-  int32_t k = key;
-  for (int round = 0; round < 4; ++round) {
-    const uint64_t pend = __ballot(k >= 0);
-    if (pend == 0) return;
-    const int leader = __ffsll(static_cast<long long>(pend)) - 1;
-    const int32_t kl = __builtin_amdgcn_readlane(k, leader);
-    const bool mine = k == kl;
-    if (__popcll(__ballot(mine)) < 4) break;
-    const int32_t m = __ockl_wfred_min_i32(mine ? v : 0x7fffffff);
-    if (lane == leader) atomicMin(dst + kl, m);
-    if (mine) k = -1;
-  }
-  if (k >= 0) atomicMin(dst + k, v);
 }
 
 // Root of x once the forest no longer changes, compressing x's chain onto

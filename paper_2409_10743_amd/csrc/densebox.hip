@@ -193,29 +193,30 @@ __global__ __launch_bounds__(256) void k_cell_stats(
                        sq_dist(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z) <= S.e2[set];
     cell_lo[c] = lo;
     cell_hi[c] = hi;
-    if (cell_minorig) cell_minorig[c] = mo;
+    cell_minorig[c] = mo;
     cell_dense[c] = dense;
     prim_count[c] = dense ? 1u : cnt;
   }
 }
 
 // Primitive records (Node layout: box, payload in `left`), their keys for
-// the build, and the state of dense-cell points: joined to the cell's first
-// point, marked core (or member, for minPts <= 2).
+// the build, and the state of dense-cell points: joined to the cell's
+// representative (its point with the smallest input index, which keeps the
+// union-find's key order), marked core (or member, for minPts <= 2).
 __global__ __launch_bounds__(256) void k_make_prims(
     const float4* __restrict__ pts, const uint64_t* __restrict__ keys, uint32_t n,
     const uint32_t* __restrict__ cid, const uint32_t* __restrict__ cell_start,
     const uint32_t* __restrict__ prim_start, const uint8_t* __restrict__ cell_dense,
     const float4* __restrict__ cell_lo, const float4* __restrict__ cell_hi,
-    Node* __restrict__ prims, uint64_t* __restrict__ pkey, int32_t* __restrict__ parent,
-    uint8_t* __restrict__ flag) {
+    const unsigned long long* __restrict__ cell_minorig, Node* __restrict__ prims,
+    uint64_t* __restrict__ pkey, int32_t* __restrict__ parent, uint8_t* __restrict__ flag) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t c = cid[i];
   const uint32_t b = cell_start[c];
   float4* out;
   if (cell_dense[c]) {
-    parent[i] = int32_t(b);
+    parent[i] = int32_t(uint32_t(cell_minorig[c]));
     flag[i] = 1;
     if (i != b) return;
     const uint32_t j = prim_start[c];
@@ -320,6 +321,11 @@ struct DbQueue {
   }
 };
 
+// a dense cell's union-find representative (its smallest input index)
+__device__ __forceinline__ int32_t cell_rep(const DbData& D, uint32_t c) {
+  return int32_t(uint32_t(D.cell_minorig[c]));
+}
+
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
   for (int o = 32; o > 0; o >>= 1) {
     const unsigned long long t = __shfl_xor(v, o, 64);
@@ -344,12 +350,12 @@ __device__ uint32_t drain(const DbData& D, const DbQueue& Q) {
     const float e2 = __int_as_float(__builtin_amdgcn_readfirstlane(en.w));
     const int32_t kind = meta & 15;
     if (kind == Q_CELLS) {
-      const int32_t ra = int32_t(D.cell_start[a]), rb = int32_t(D.cell_start[b]);
+      const int32_t ra = cell_rep(D, uint32_t(a)), rb = cell_rep(D, uint32_t(b));
       if (uf_find(D.parent, ra) == uf_find(D.parent, rb)) continue;
       // lanes over the larger cell's points (only those near the smaller
       // cell's box), the smaller cell's points in turn for all lanes
-      const uint32_t na = D.cell_start[a + 1] - uint32_t(ra);
-      const uint32_t nb = D.cell_start[b + 1] - uint32_t(rb);
+      const uint32_t na = D.cell_start[a + 1] - D.cell_start[a];
+      const uint32_t nb = D.cell_start[b + 1] - D.cell_start[b];
       const int32_t co = na >= nb ? a : b, ci = na >= nb ? b : a;
       const uint32_t os = D.cell_start[co], oe = D.cell_start[co + 1];
       const uint32_t is = D.cell_start[ci], ie = D.cell_start[ci + 1];
@@ -365,13 +371,13 @@ __device__ uint32_t drain(const DbData& D, const DbQueue& Q) {
           if (__ballot(act && sq_dist4(p, r) <= e2) != 0ull) { hit = true; break; }
         }
       }
-      if (hit && lane == 0) uf_union(D.parent, ra, rb);
+      if (hit && lane == 0) uf_union(D.parent, D.perm, ra, rb);
       continue;
     }
     const float4 p = D.pts[a];
     const uint32_t cb = D.cell_start[b], ce = D.cell_start[b + 1];
     if (kind == Q_JOIN) {
-      const int32_t rep = int32_t(cb);
+      const int32_t rep = cell_rep(D, uint32_t(b));
       if (uf_find(D.parent, a) == uf_find(D.parent, rep)) continue;
       bool hit = false;
       for (uint32_t k0 = cb; k0 < ce && !hit; k0 += 64) {
@@ -379,7 +385,7 @@ __device__ uint32_t drain(const DbData& D, const DbQueue& Q) {
         hit = __ballot(k < ce && sq_dist4(p, D.pts[k < ce ? k : cb]) <= e2) != 0ull;
       }
       if (hit && lane == 0) {
-        uf_union(D.parent, a, rep);
+        uf_union(D.parent, D.perm, a, rep);
         if (meta & Q_MARK) D.flag[a] = 1;
       }
     } else if (kind == Q_BORDER) {
@@ -575,13 +581,13 @@ struct PairDb {
     const int32_t pr = __float_as_int(a.w);
     if (me >= 0 && pr >= 0) {  // two points: the box bound was the predicate
       if (!core_mode) {
-        uf_union(D.parent, me, pr);
+        uf_union(D.parent, D.perm, me, pr);
         D.flag[me] = 1;
         D.flag[pr] = 1;
         return false;
       }
       const bool cj = D.flag[pr] != 0;
-      if (me_core && cj) uf_union(D.parent, me, pr);
+      if (me_core && cj) uf_union(D.parent, D.perm, me, pr);
       else if (me_core) atomicMin(D.bestcore + pr, okey(me));
       else if (cj) atomicMin(D.bestcore + me, okey(pr));
       return false;
@@ -589,7 +595,7 @@ struct PairDb {
     const bool all_in = box_box_far4(ql, qh, a, b) <= r2;
     if (me < 0 && pr < 0) {  // two dense cells
       const int32_t ca = me & 0x7fffffff, cb = pr & 0x7fffffff;
-      if (all_in) uf_union(D.parent, int32_t(D.cell_start[ca]), int32_t(D.cell_start[cb]));
+      if (all_in) uf_union(D.parent, D.perm, cell_rep(D, uint32_t(ca)), cell_rep(D, uint32_t(cb)));
       else Q.push(Q_CELLS, ca, cb, r2);
       return false;
     }
@@ -598,7 +604,7 @@ struct PairDb {
     const bool x_core = me >= 0 ? me_core : (!core_mode || D.flag[x] != 0);
     if (x_core) {
       if (all_in) {
-        uf_union(D.parent, x, int32_t(D.cell_start[c]));
+        uf_union(D.parent, D.perm, x, cell_rep(D, uint32_t(c)));
         if (!core_mode) D.flag[x] = 1;
       } else {
         Q.push(Q_JOIN | (core_mode ? 0 : Q_MARK), x, c, r2);
@@ -694,12 +700,12 @@ void launch_cell_stats(const float4* pts, const uint32_t* perm, const uint64_t* 
 void launch_make_prims(const float4* pts, const uint64_t* keys, uint32_t n, const uint32_t* cid,
                        const uint32_t* cell_start, const uint32_t* prim_start,
                        const uint8_t* cell_dense, const float4* cell_lo, const float4* cell_hi,
-                       Node* prims, uint64_t* pkey, int32_t* parent, uint8_t* flag,
-                       hipStream_t s) {
+                       const unsigned long long* cell_minorig, Node* prims, uint64_t* pkey,
+                       int32_t* parent, uint8_t* flag, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_make_prims, dim3((n + 255) / 256), dim3(256), 0, s, pts, keys, n, cid,
-                     cell_start, prim_start, cell_dense, cell_lo, cell_hi, prims, pkey, parent,
-                     flag);
+                     cell_start, prim_start, cell_dense, cell_lo, cell_hi, cell_minorig, prims,
+                     pkey, parent, flag);
 }
 
 void launch_one_set(float e2, int32_t min_pts, int32_t thresh, float* e2o, int32_t* mpo,

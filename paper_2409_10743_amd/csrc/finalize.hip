@@ -14,47 +14,61 @@ namespace dbx {
 
 namespace {
 
-// First pass: cluster root of every point (or -1; the chains are
-// compressed onto it on the way), and the smallest input index per root.
-// The root is written over parent[i]; that only shortens other points'
-// chains (a root is an ancestor), and noise points are
-// singletons nobody else's chain passes through.  It also sets every label
-// to -1 (coalesced: input index i, whatever point sits at sorted position
-// i), so the second pass only writes the labels of clustered points: for
-// sparse fields most points are noise, and those scattered 4-byte writes
-// are the expensive part.
+// The cluster root of point i: its own (core, or every member with
+// minPts <= 2), its smallest-index core neighbour's (border), or -1.
+__device__ __forceinline__ int32_t cluster_root(uint32_t i, int32_t min_pts,
+                                                const uint8_t* __restrict__ flag,
+                                                const unsigned long long* __restrict__ bestcore,
+                                                int32_t* parent) {
+  if (min_pts <= 2) return (min_pts == 1 || flag[i]) ? uf_root_final(parent, int32_t(i)) : -1;
+  if (flag[i]) return uf_root_final(parent, int32_t(i));
+  const unsigned long long b = bestcore[i];
+  return b == ~0ull ? -1 : uf_root_final(parent, int32_t(uint32_t(b)));
+}
+
+// minPts <= 2, one pass: every member is in the union-find, whose root is
+// the member with the smallest input index, i.e. the label.  Noise keeps
+// the -1 the build wrote (coalesced, by input index), so only clustered
+// points are written, scattered to input order: in sparse fields most
+// points are noise.
+__global__ __launch_bounds__(256) void k_final_labels(
+    uint32_t n, int32_t min_pts, const uint8_t* __restrict__ flag, const uint32_t* __restrict__ perm,
+    int32_t* parent, int32_t* __restrict__ labels) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t r = cluster_root(i, min_pts, flag, nullptr, parent);
+  if (r < 0) return;
+  const uint32_t o = perm[i];
+  if (o < n) labels[o] = int32_t(perm[r]);
+}
+
+// minPts > 2: border points are not in the union-find and may have the
+// smallest index of their cluster.  First pass: every point's root (written
+// over parent[i], or -1; a root is an ancestor, so other points' chains only
+// get shorter) and, for border points, atomicMin of the input index into
+// minlab[root].  Second pass: label = min(input index of the root, minlab).
 __global__ __launch_bounds__(256) void k_final_roots(
     uint32_t n, int32_t min_pts, const uint8_t* __restrict__ flag,
     const unsigned long long* __restrict__ bestcore, const uint32_t* __restrict__ perm,
-    int32_t* parent, int32_t* __restrict__ minlab, int32_t* __restrict__ labels) {
+    int32_t* parent, int32_t* __restrict__ minlab) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool ok = i < n;  // no early return: the wave combines its minima
-  int32_t r = -1;
-  if (ok) {
-    labels[i] = -1;
-    if (min_pts <= 2) {
-      r = (min_pts == 1 || flag[i]) ? uf_root_final(parent, int32_t(i)) : -1;
-    } else if (flag[i]) {  // core
-      r = uf_root_final(parent, int32_t(i));
-    } else {
-      unsigned long long b = bestcore[i];
-      r = b == ~0ull ? -1 : uf_root_final(parent, int32_t(uint32_t(b)));
-    }
-  }
-  wave_min_by_key(minlab, r, r >= 0 ? int32_t(perm[i]) : 0);
-  if (ok) parent[i] = r;
+  if (i >= n) return;
+  const int32_t r = cluster_root(i, min_pts, flag, bestcore, parent);
+  if (r >= 0 && !flag[i]) atomicMin(minlab + r, int32_t(perm[i]));
+  parent[i] = r;
 }
 
-__global__ __launch_bounds__(256) void k_final_labels(uint32_t n, const uint32_t* __restrict__ perm,
-                                                     const int32_t* __restrict__ root,
-                                                     const int32_t* __restrict__ minlab,
-                                                     int32_t* __restrict__ labels) {
+__global__ __launch_bounds__(256) void k_final_border_labels(uint32_t n,
+                                                            const uint32_t* __restrict__ perm,
+                                                            const int32_t* __restrict__ root,
+                                                            const int32_t* __restrict__ minlab,
+                                                            int32_t* __restrict__ labels) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int32_t r = root[i];
   if (r < 0) return;  // noise: already -1
   const uint32_t o = perm[i];
-  if (o < n) labels[o] = minlab[r];
+  if (o < n) labels[o] = min(int32_t(perm[r]), minlab[r]);
 }
 
 __global__ __launch_bounds__(256) void k_scatter_u8(const uint8_t* __restrict__ src,
@@ -72,19 +86,20 @@ void launch_scatter_u8(const uint8_t* src, const uint32_t* perm, uint32_t n, uin
   hipLaunchKernelGGL(k_scatter_u8, dim3((n + 255) / 256), dim3(256), 0, s, src, perm, n, dst);
 }
 
-void launch_final_roots(uint32_t n, int32_t min_pts, const uint8_t* flag,
-                        const unsigned long long* bestcore, const uint32_t* perm,
-                        int32_t* parent, int32_t* minlab, int32_t* labels, hipStream_t s) {
+void launch_final(uint32_t n, int32_t min_pts, const uint8_t* flag,
+                  const unsigned long long* bestcore, const uint32_t* perm, int32_t* parent,
+                  int32_t* minlab, int32_t* labels, hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_final_roots, dim3((n + 255) / 256), dim3(256), 0, s, n, min_pts, flag,
-                     bestcore, perm, parent, minlab, labels);
-}
-
-void launch_final_labels(uint32_t n, const uint32_t* perm, const int32_t* root,
-                         const int32_t* minlab, int32_t* labels, hipStream_t s) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(k_final_labels, dim3((n + 255) / 256), dim3(256), 0, s, n, perm, root,
-                     minlab, labels);
+  const uint32_t g = (n + 255) / 256;
+  if (min_pts <= 2) {
+    hipLaunchKernelGGL(k_final_labels, dim3(g), dim3(256), 0, s, n, min_pts, flag, perm, parent,
+                       labels);
+    return;
+  }
+  hipLaunchKernelGGL(k_final_roots, dim3(g), dim3(256), 0, s, n, min_pts, flag, bestcore, perm,
+                     parent, minlab);
+  hipLaunchKernelGGL(k_final_border_labels, dim3(g), dim3(256), 0, s, n, perm, parent, minlab,
+                     labels);
 }
 
 }  // namespace dbx

@@ -71,16 +71,18 @@ struct PointLeaves {
 };
 // FDBSCAN's level-1 frames: leaf j is gathered from input point perm[j]
 // here (a random 12-byte read) and written once, with its rope, together
-// with the point's union-find state; later levels read the written leaves.
+// with the point's union-find state and label -1; later levels read the
+// written leaves.
 struct GatherLeaves {
   const float* pts;
   const uint32_t* perm;
   uint32_t n;
   float4* leaf;
   int32_t* parent;
-  int32_t* minlab;
+  int32_t* minlab;               // null unless minPts > 2
   uint8_t* flag;
   unsigned long long* bestcore;  // null unless minPts > 2
+  int32_t* labels;               // output, input order; null: none
   __device__ void load(int32_t j, float4& lo, float4& hi) const {
     const uint32_t o = min(perm[j], n - 1);  // a permutation unless the sort failed
     const float* p = pts + size_t(3) * o;
@@ -89,9 +91,10 @@ struct GatherLeaves {
   __device__ void write_out(int32_t j, const float4& lo, const float4&, int32_t rope) const {
     leaf[j] = make_float4(lo.x, lo.y, lo.z, __int_as_float(rope));
     parent[j] = j;
-    minlab[j] = 0x7fffffff;
+    if (minlab) minlab[j] = 0x7fffffff;
     flag[j] = 0;
     if (bestcore) bestcore[j] = ~0ull;
+    if (labels) labels[j] = -1;  // by input index: every index once
     if (uint32_t(j) == n - 1)  // the walks read one record past the last leaf
       leaf[n] = make_float4(0.f, 0.f, 0.f, __int_as_float(SENTINEL));
   }
@@ -391,10 +394,11 @@ void build_impl(const uint64_t* keys, int set_shift, FrameLeaves flv, Leaves lv,
 
 void launch_build(const uint64_t* keys, int set_shift, const float* pts, const uint32_t* perm,
                   float4* leaf, int32_t* parent, int32_t* minlab, uint8_t* flag,
-                  unsigned long long* bestcore, uint32_t n, Node* nodes, int32_t* other,
-                  int32_t* set_root, int4* pending, uint32_t* err, hipStream_t s,
+                  unsigned long long* bestcore, int32_t* labels, uint32_t n, Node* nodes,
+                  int32_t* other, int32_t* set_root, int4* pending, uint32_t* err, hipStream_t s,
                   void (*after_level)(void*, int), void* arg) {
-  build_impl(keys, set_shift, GatherLeaves{pts, perm, n, leaf, parent, minlab, flag, bestcore},
+  build_impl(keys, set_shift,
+             GatherLeaves{pts, perm, n, leaf, parent, minlab, flag, bestcore, labels},
              PointLeaves{leaf}, n, nodes, other, set_root, pending, err, s, after_level, arg);
 }
 

@@ -204,7 +204,8 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
 __global__ __launch_bounds__(256) void k_gather(
     const float* __restrict__ pts, const uint32_t* __restrict__ perm, uint32_t n,
     float4* __restrict__ leaf, int32_t* __restrict__ parent, int32_t* __restrict__ minlab,
-    uint8_t* __restrict__ flag, unsigned long long* __restrict__ bestcore) {
+    uint8_t* __restrict__ flag, unsigned long long* __restrict__ bestcore,
+    int32_t* __restrict__ labels) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) leaf[n] = make_float4(0.f, 0.f, 0.f, __int_as_float(SENTINEL));  // padding
   if (i >= n) return;
@@ -212,9 +213,10 @@ __global__ __launch_bounds__(256) void k_gather(
   const float* p = pts + size_t(3) * o;
   leaf[i] = make_float4(p[0], p[1], p[2], __int_as_float(SENTINEL));
   parent[i] = int32_t(i);
-  minlab[i] = 0x7fffffff;
+  if (minlab) minlab[i] = 0x7fffffff;
   flag[i] = 0;
   if (bestcore) bestcore[i] = ~0ull;
+  if (labels) labels[i] = -1;  // by input index: every index once
 }
 
 // Reductions into a few global words (bounds, digit counts): 1024 blocks of
@@ -260,10 +262,10 @@ void launch_morton(const float* pts, uint32_t n, const uint32_t* bounds, float e
 
 void launch_gather(const float* pts, const uint32_t* perm, uint32_t n, float4* leaf,
                    int32_t* parent, int32_t* minlab, uint8_t* flag,
-                   unsigned long long* bestcore, hipStream_t s) {
+                   unsigned long long* bestcore, int32_t* labels, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, s, pts, perm, n, leaf,
-                     parent, minlab, flag, bestcore);
+                     parent, minlab, flag, bestcore, labels);
 }
 
 }  // namespace dbx

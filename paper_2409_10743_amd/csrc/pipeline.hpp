@@ -82,9 +82,12 @@ void launch_morton(const float* pts, uint32_t n, const uint32_t* bounds, float e
 // Sorted leaves, leaf[i] = point perm[i] (rope unset), plus the padding
 // record leaf[n] (leaf holds n + 1 records); also initialises the
 // per-point state and fills the build's hand-over entries with -1.
+// leaf[i] = point perm[i], union-find state (parent[i] = i, flag 0;
+// minlab INT_MAX and bestcore ~0 where given) and labels[i] = -1 (if given).
 void launch_gather(const float* pts, const uint32_t* perm, uint32_t n,
                    float4* leaf, int32_t* parent, int32_t* minlab,
-                   uint8_t* flag, unsigned long long* bestcore, hipStream_t s);
+                   uint8_t* flag, unsigned long long* bestcore, int32_t* labels,
+                   hipStream_t s);
 
 // ---- LBVH (lbvh.hip) --------------------------------------------------------
 constexpr int BUILD_LEAVES = 256;        // leaves per level-1 frame
@@ -102,12 +105,13 @@ size_t build_pending_entries(uint32_t n);
 // root).  `after_level(arg, lv)`, if given, is called after level lv is
 // enqueued.  The level-1 frames gather their leaves: leaf j = input point
 // perm[j] (with its rope; leaf[n] is a padding record), and they set up the
-// union-find state of their points (parent[j] = j, minlab[j] = INT_MAX,
-// flag[j] = 0, bestcore[j] = ~0 if bestcore is given).  pending must have
-// been emptied (launch_prep).
+// union-find state of their points (parent[j] = j, flag[j] = 0; minlab[j] =
+// INT_MAX and bestcore[j] = ~0 where given) and labels[j] = -1 (if given).
+// pending must have been emptied (launch_prep).
 void launch_build(const uint64_t* keys, int set_shift, const float* pts, const uint32_t* perm,
                   float4* leaf, int32_t* parent, int32_t* minlab, uint8_t* flag,
-                  unsigned long long* bestcore, uint32_t n, Node* nodes, int32_t* other,
+                  unsigned long long* bestcore, int32_t* labels, uint32_t n, Node* nodes,
+                  int32_t* other,
                   int32_t* set_root, int4* pending, uint32_t* err, hipStream_t s,
                   void (*after_level)(void*, int) = nullptr, void* arg = nullptr);
 // The same over box leaves (DenseBox primitives: Node records, payload in
@@ -127,7 +131,8 @@ void launch_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
 // minPts <= 2: every point with a neighbour is core; union every pair.
 void launch_pairs_fof(const Node* nodes, const float4* leaf, const uint64_t* keys,
                       const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
-                      int32_t* parent, uint8_t* member, uint32_t* err, int block, hipStream_t s);
+                      const uint32_t* perm, int32_t* parent, uint8_t* member, uint32_t* err,
+                      int block, hipStream_t s);
 // minPts > 2: union core pairs, record each non-core point's smallest-index
 // core neighbour.
 void launch_pairs_core(const Node* nodes, const float4* leaf, const uint64_t* keys,
@@ -140,14 +145,12 @@ void launch_pairs_count(const Node* nodes, const float4* leaf, const uint64_t* k
                         unsigned long long* count, uint32_t* err, int block, hipStream_t s);
 
 // ---- labels (finalize.hip) --------------------------------------------------
-// 1) cluster root per point (written over parent; -1 = noise), the
-//    smallest input index per root, and every label set to -1;
-// 2) labels of the clustered points, in input order.
-void launch_final_roots(uint32_t n, int32_t min_pts, const uint8_t* flag,
-                        const unsigned long long* bestcore, const uint32_t* perm,
-                        int32_t* parent, int32_t* minlab, int32_t* labels, hipStream_t s);
-void launch_final_labels(uint32_t n, const uint32_t* perm, const int32_t* root,
-                         const int32_t* minlab, int32_t* labels, hipStream_t s);
+// Labels of the sorted points into input order; labels must hold -1 for
+// every point (the build or the gather writes it).  minlab (minPts > 2
+// only) must hold INT_MAX per point.
+void launch_final(uint32_t n, int32_t min_pts, const uint8_t* flag,
+                  const unsigned long long* bestcore, const uint32_t* perm, int32_t* parent,
+                  int32_t* minlab, int32_t* labels, hipStream_t s);
 // dst[perm[i]] = src[i]: from sorted order back to input order
 void launch_scatter_u8(const uint8_t* src, const uint32_t* perm, uint32_t n,
                        uint8_t* dst, hipStream_t s);
@@ -168,7 +171,7 @@ struct DbTables {
   const float4* pts;  // points in cell order
   const uint32_t* cell_start;
   const uint32_t* perm;
-  const unsigned long long* cell_minorig;  // minPts > 2 only
+  const unsigned long long* cell_minorig;  // (input index << 32) | position, smallest
   const float4* cell_lo;
   const float4* cell_hi;
   int32_t* parent;
@@ -193,11 +196,13 @@ void launch_cell_stats(const float4* pts, const uint32_t* perm, const uint64_t* 
                        const uint32_t* ncells, const uint32_t* cell_start, const DbSets& sets,
                        float4* cell_lo, float4* cell_hi, unsigned long long* cell_minorig,
                        uint8_t* cell_dense, uint32_t* prim_count, hipStream_t s);
+// a dense cell's points are joined directly to its representative, the
+// point with the smallest input index (cell_minorig's low word)
 void launch_make_prims(const float4* pts, const uint64_t* keys, uint32_t n, const uint32_t* cid,
                        const uint32_t* cell_start, const uint32_t* prim_start,
                        const uint8_t* cell_dense, const float4* cell_lo, const float4* cell_hi,
-                       Node* prims, uint64_t* pkey, int32_t* parent, uint8_t* flag,
-                       hipStream_t s);
+                       const unsigned long long* cell_minorig, Node* prims, uint64_t* pkey,
+                       int32_t* parent, uint8_t* flag, hipStream_t s);
 // the one-set parameter table of a plain call
 void launch_one_set(float e2, int32_t min_pts, int32_t thresh, float* e2o, int32_t* mpo,
                     int32_t* tho, hipStream_t s);
@@ -228,7 +233,8 @@ void launch_pairs_sets(const Node* nodes, const float4* leaf, uint32_t n, const 
                        uint8_t* flag, unsigned long long* bestcore, uint32_t* err, int block,
                        hipStream_t s);
 // labels are set-local: smallest input index in the cluster minus the
-// set's offset
+// set's offset (labels -1 and, with bestcore, minlab INT_MAX beforehand;
+// bestcore null: no set has minPts > 2)
 void launch_final_sets(uint32_t n, const uint64_t* keys, int set_shift, const int32_t* set_minpts,
                        const int64_t* offsets, const uint8_t* flag,
                        const unsigned long long* bestcore, const uint32_t* perm, int32_t* parent,

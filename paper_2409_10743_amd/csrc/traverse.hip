@@ -93,11 +93,11 @@ struct PairVisit {
   __device__ bool hit(uint32_t i, int32_t j, const float4&) {
     if (MODE == FOF) {
       found = true;
-      ri = uf_union(parent, ri, j);
+      ri = uf_union(parent, perm, ri, j);
       member[j] = 1;
     } else if (MODE == CORE) {
       const bool cj = is_core[j] != 0;
-      if (ci && cj) ri = uf_union(parent, ri, j);
+      if (ci && cj) ri = uf_union(parent, perm, ri, j);
       else if (ci) atomicMin(bestcore + j, (static_cast<unsigned long long>(perm[i]) << 32) | i);
       else if (cj)
         atomicMin(bestcore + i, (static_cast<unsigned long long>(perm[j]) << 32) | uint32_t(j));
@@ -171,10 +171,11 @@ void launch_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
 
 void launch_pairs_fof(const Node* nodes, const float4* leaf, const uint64_t* keys,
                       const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
-                      int32_t* parent, uint8_t* member, uint32_t* err, int block, hipStream_t s) {
+                      const uint32_t* perm, int32_t* parent, uint8_t* member, uint32_t* err,
+                      int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<FOF>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     keys, bounds, drop, n, walk_cfg(n), e2, nullptr, nullptr, parent,
+                     keys, bounds, drop, n, walk_cfg(n), e2, nullptr, perm, parent,
                      member, nullptr, nullptr, err);
 }
 
