@@ -66,8 +66,11 @@ namespace {
 // primitives: Node records whose `left` holds the payload).  The levels
 // above the first only load leaves.
 struct PointLeaves {
+  static constexpr bool kPoint = true;  // a record is one float4, its box [p, p]
   float4* leaf;
   __device__ void load(int32_t j, float4& lo, float4& hi) const { lo = hi = leaf[j]; }
+  // 32 bytes from leaf j (the array has one record past the last leaf)
+  __device__ const float4* rec(int32_t j) const { return leaf + j; }
 };
 // FDBSCAN's level-1 frames: leaf j is gathered from input point perm[j]
 // here (a random 12-byte read) and written once, with its rope, together
@@ -100,7 +103,11 @@ struct GatherLeaves {
   }
 };
 struct BoxLeaves {
+  static constexpr bool kPoint = false;
   Node* prim;
+  __device__ const float4* rec(int32_t j) const {
+    return reinterpret_cast<const float4*>(prim + j);
+  }
   __device__ void load(int32_t j, float4& lo, float4& hi) const {
     const float4* q = reinterpret_cast<const float4*>(prim + j);
     lo = q[0];
@@ -265,21 +272,64 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
   }
 }
 
-// Levels k > 1 of the build: thread = one of the 2 * 128 nodes handed up by
-// the 128 level-(k-1) frames inside this block's frame.  nodes and other
-// are written and read by different threads of the same launch, ordered by
-// the exchange: no __restrict__ on them.
+// What a climbing thread keeps about the two ends of its node [l, r]: the
+// deltas and set cuts there (so a step needs no key loads before its
+// exchange).  cl: l = 0 or a set ends at l - 1; cr: r = last or a set ends
+// at r.
+struct Ends {
+  uint64_t dl, dr, dr1;  // delta(l - 1), delta(r), delta(r + 1) where they exist
+  bool cl, cr;
+};
+
+__device__ __forceinline__ uint64_t delta_of(uint64_t a, uint64_t b, int32_t i) {
+  return a == b ? uint64_t(uint32_t(i) ^ uint32_t(i + 1)) : ((a ^ b) + (1ull << 32));
+}
+// the left end becomes l (keys l - 1, l)
+__device__ __forceinline__ void set_left(Ends& E, const uint64_t* __restrict__ keys, int32_t l,
+                                         uint64_t mask) {
+  if (l == 0) {
+    E.dl = 0;
+    E.cl = true;
+    return;
+  }
+  const uint64_t a = keys[l - 1], b = keys[l];
+  E.dl = delta_of(a, b, l - 1);
+  E.cl = ((a ^ b) & mask) != 0;
+}
+// the right end becomes r (keys r .. r + 2)
+__device__ __forceinline__ void set_right(Ends& E, const uint64_t* __restrict__ keys, int32_t r,
+                                          int32_t last, uint64_t mask) {
+  if (r == last) {
+    E.dr = E.dr1 = 0;
+    E.cr = true;
+    return;
+  }
+  const uint64_t a = keys[r], b = keys[r + 1];
+  const uint64_t c = r + 1 < last ? keys[r + 2] : 0ull;
+  E.dr = delta_of(a, b, r);
+  E.dr1 = r + 1 < last ? delta_of(b, c, r + 1) : 0ull;
+  E.cr = ((a ^ b) & mask) != 0;
+}
+
+// Levels k > 1 of the build: thread = one of the nodes handed up by the
+// level-(k-1) frames inside this block's frame of `frame` leaves (two per
+// frame; 2 * 128 per 256-thread block, or, for the top launch, one block
+// over every leaf).  nodes and other are written and read by different
+// threads of the same launch, ordered by the exchange: no __restrict__ on
+// them.  The loads a step needs after its exchange (the sibling's box, the
+// keys at the node's new end) go out together.
 template <class Leaves>
-__global__ __launch_bounds__(BUILD_BLOCK) void k_build_level(
-    const uint64_t* __restrict__ keys, Leaves lv, uint32_t n, int level, int set_shift,
-    Node* nodes, int32_t* other, int32_t* set_root, const int4* __restrict__ pend_in,
-    int4* __restrict__ pend_out, uint32_t* err) {
+__global__ __launch_bounds__(1024) void k_build_level(
+    const uint64_t* __restrict__ keys, Leaves lv, uint32_t n, uint64_t frame, uint32_t entries,
+    int set_shift, Node* nodes, int32_t* other, int32_t* set_root,
+    const int4* __restrict__ pend_in, int4* __restrict__ pend_out, uint32_t* err) {
   const int32_t last = int32_t(n) - 1;
-  const uint64_t frame = uint64_t(BUILD_LEAVES) << (BUILD_FANOUT_LOG2 * (level - 1));
   const int64_t f0 = int64_t(blockIdx.x) * int64_t(frame);
   const int64_t f1 = min(f0 + int64_t(frame), int64_t(n));
   const uint64_t mask = set_mask_of(set_shift);
-  const int4 e = pend_in[size_t(blockIdx.x) * BUILD_BLOCK + threadIdx.x];
+  const size_t slot = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (slot >= entries) return;
+  const int4 e = pend_in[slot];
   int32_t ref = e.x, l = e.y, r = e.z, g = -1;
   if (ref == SENTINEL) return;
   float4 lo, hi;
@@ -290,19 +340,15 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_level(
     lo = q[0];
     hi = q[1];
   }
-  auto spans = [&](int32_t a, int32_t b) {
-    return (a == 0 || set_cut(keys, a - 1, mask)) && (b == last || set_cut(keys, b, mask));
-  };
+  Ends E;
+  set_left(E, keys, l, mask);
+  set_right(E, keys, r, last, mask);
   for (;;) {
-    const bool is_left = left_side(l, r, last, r != last ? delta(keys, r) : 0ull,
-                                   l > 0 ? delta(keys, l - 1) : 0ull);
+    const bool is_left = left_side(l, r, last, E.dr, E.dl);
     if (g >= 0) {  // finished in this launch: write it under its number
       ref = is_left ? r : l;
-      const bool cut = r != last && set_cut(keys, r, mask);
-      const uint64_t d_r = r != last ? delta(keys, r) : 0ull;
-      const uint64_t d_r1 = r + 1 < last ? delta(keys, r + 1) : 0ull;
-      write_node(nodes, ref, lo, hi, left_ref(l, g), rope_of(r, last, cut, d_r, d_r1));
-      if (spans(l, r)) set_root[set_of(keys, l, set_shift)] = ref;
+      write_node(nodes, ref, lo, hi, left_ref(l, g), rope_of(r, last, E.cr, E.dr, E.dr1));
+      if (E.cl && E.cr) set_root[set_of(keys, l, set_shift)] = ref;  // spans a whole set
       g = -1;
     }
     const int32_t par = is_left ? r : l - 1;
@@ -320,19 +366,32 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_level(
       atomicOr(err, STATUS_TREE);
       return;
     }
-    float4 slo, shi;
-    if (sl == sr) {
-      lv.load(sl, slo, shi);
-    } else {
-      const float4* q = reinterpret_cast<const float4*>(nodes + (is_left ? sl : sr));
-      slo = q[0];
-      shi = q[1];
-    }
-    grow(lo, hi, slo, shi);
+    // the sibling's box and the keys around the new end, loaded together
+    // (no branch between the loads: a leaf is read as 32 bytes too)
+    const bool sleaf = sl == sr;
+    const float4* sp =
+        sleaf ? lv.rec(sl) : reinterpret_cast<const float4*>(nodes + (is_left ? sl : sr));
+    const float4 sa = sp[0], sb = sp[1];
+    const int32_t x = bound;
+    const uint64_t k0 = keys[x > 0 ? x - 1 : 0], k1 = keys[x];
+    const uint64_t k2 = keys[x < last ? x + 1 : last], k3 = keys[x + 1 < last ? x + 2 : last];
+    // both readings computed, one kept: selects, so that every load above
+    // is issued before the first wait
+    const uint64_t dr = x < last ? delta_of(k1, k2, x) : 0ull;
+    const uint64_t dr1 = x + 1 < last ? delta_of(k2, k3, x + 1) : 0ull;
+    const bool cr = x == last || ((k1 ^ k2) & mask) != 0;
+    const uint64_t dl = x > 0 ? delta_of(k0, k1, x - 1) : 0ull;
+    const bool cl = x == 0 || ((k0 ^ k1) & mask) != 0;
+    E.dr = is_left ? dr : E.dr;  // the right end is now x
+    E.dr1 = is_left ? dr1 : E.dr1;
+    E.cr = is_left ? cr : E.cr;
+    E.dl = is_left ? E.dl : dl;  // the left end is now x
+    E.cl = is_left ? E.cl : cl;
+    grow(lo, hi, sa, sleaf && Leaves::kPoint ? sa : sb);
     g = par;
     if (l == 0 && r == last) {  // the root, number 0
       write_node(nodes, 0, lo, hi, left_ref(l, g), SENTINEL);
-      if (spans(l, r)) set_root[set_of(keys, l, set_shift)] = 0;
+      if (E.cl && E.cr) set_root[set_of(keys, l, set_shift)] = 0;
       return;
     }
   }
@@ -375,17 +434,29 @@ void build_impl(const uint64_t* keys, int set_shift, FrameLeaves flv, Leaves lv,
   uint64_t frame = BUILD_LEAVES;
   const int4* pin = nullptr;
   int4* pout = pending;
+  uint32_t entries = 0;  // hand-over entries the previous level wrote (its region)
   for (int lv_i = 1; lv_i <= levels; ++lv_i) {
     const uint32_t frames = uint32_t((n + frame - 1) / frame);
-    if (lv_i == 1)
+    if (lv_i == 1) {
       hipLaunchKernelGGL(k_build_frame<FrameLeaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys,
                          flv, n, set_shift, nodes, other, root, pout, err);
-    else
+    } else if (entries <= 1024) {
+      // few enough nodes left for one workgroup: it climbs them all to the
+      // root (one frame over every leaf), in place of the remaining levels
+      const uint32_t threads = (entries + 63) / 64 * 64;
+      hipLaunchKernelGGL(k_build_level<Leaves>, dim3(1), dim3(threads), 0, s, keys, lv, n,
+                         uint64_t(n), entries, set_shift, nodes, other, root, pin, pout, err);
+      if (after_level) after_level(arg, lv_i);
+      return;
+    } else {
       hipLaunchKernelGGL(k_build_level<Leaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys, lv,
-                         n, lv_i, set_shift, nodes, other, root, pin, pout, err);
+                         n, frame, uint32_t(frames) * BUILD_BLOCK, set_shift, nodes, other, root,
+                         pin, pout, err);
+    }
     if (after_level) after_level(arg, lv_i);
     pin = pout;
-    pout += level_region(frames);
+    entries = uint32_t(level_region(frames));
+    pout += entries;
     frame <<= BUILD_FANOUT_LOG2;
   }
 }
