@@ -248,6 +248,25 @@ struct MortonGrid {
   }
 };
 
+// Digit counts of the sort passes for one key per active lane, into the LDS
+// table sh[pass][digit].  Where every active lane has the same digit (code
+// bits that are constant across the points, or a batched set's id) the wave
+// adds its count with one atomic instead of piling 64 onto one bin.
+__device__ __forceinline__ void count_digits_wave(uint32_t* sh, uint64_t code, int passes) {
+  const uint64_t active = __ballot(true);
+  const int first = __ffsll(static_cast<long long>(active)) - 1;
+  const int lane = threadIdx.x & 63;
+  for (int q = 0; q < passes; ++q) {
+    const uint32_t d = uint32_t(code >> (8 * q)) & 0xffu;
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+    if (__ballot(d == d0) == active) {
+      if (lane == first) atomicAdd(&sh[q * 256 + d0], uint32_t(__popcll(active)));
+    } else {
+      atomicAdd(&sh[q * 256 + d], 1u);
+    }
+  }
+}
+
 // XCD-aware block order: the hardware deals consecutive workgroups to the
 // 8 XCDs round-robin; remap so each XCD works on one contiguous stretch of
 // tiles (Morton-adjacent queries share tree nodes in that XCD's L2).

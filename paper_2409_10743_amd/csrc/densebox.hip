@@ -62,9 +62,7 @@ __global__ __launch_bounds__(256) void k_cell_keys(const float* __restrict__ pts
     const float* p = pts + size_t(3) * i;
     const uint64_t code = g.code(p[0], p[1], p[2]);
     keys[i] = code;
-#pragma unroll
-    for (int q = 0; q < SORT_PASSES; ++q)
-      atomicAdd(&sh[q * RADIX + ((code >> (8 * q)) & 0xff)], 1u);
+    count_digits_wave(sh, code, SORT_PASSES);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < SORT_PASSES * RADIX; t += blockDim.x)

@@ -96,9 +96,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
   }
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t gcount = ghist[tid];  // this pass's count of digit tid
   if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
   for (int w = 0; w < WAVES; ++w) s_whist[w][tid] = 0;
-  __syncthreads();
+  // one digit for every key (constant code bits, or a set id shared by all
+  // keys): the pass keeps the order, so each tile only copies itself
+  const bool trivial = __syncthreads_or(gcount == n);
   const uint32_t tile = s_tile;
   const uint32_t tile_base = tile * TILE;
   const uint32_t wbase = tile_base + wave * (64 * ITEMS);
@@ -113,6 +116,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
     uint32_t idx = wbase + k * 64 + lane;
     key[k] = idx < n ? kin[idx] : ~0ull;
     val[k] = iota ? idx : (idx < n ? vin[idx] : 0u);
+  }
+  if (trivial) {  // all loads above are in flight: write them back where they were
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const uint32_t idx = wbase + k * 64 + lane;
+      if (idx < n) {
+        kout[idx] = key[k];
+        vout[idx] = val[k];
+      }
+    }
+    return;
   }
 
   // rank each key among the keys of this wave with the same digit; the
@@ -171,7 +185,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
     st_agent(st, ST_INC | ((excl + total) & ST_VAL));
   }
   // global digit start for this pass: exclusive scan of the digit counts
-  uint32_t gstart = block_exclusive_scan(ghist[d], s_tmp);
+  uint32_t gstart = block_exclusive_scan(gcount, s_tmp);
   uint32_t loff = block_exclusive_scan(total, s_tmp);
   for (int w = 0; w < WAVES; ++w) s_whist[w][d] += loff;
   __syncthreads();

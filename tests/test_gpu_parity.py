@@ -110,6 +110,30 @@ def test_sort_is_stable_and_complete(ctx, n):
     np.testing.assert_array_equal(v.cpu().numpy(), vals[order])
 
 
+@pytest.mark.parametrize("n", [3000, 4096 * 5 + 17])
+@pytest.mark.parametrize("spread", ["low_bits", "middle_constant", "all_equal"])
+def test_sort_with_constant_digits(ctx, n, spread):
+    """Passes whose digit is the same for every key only copy their tile:
+    keys confined to the low 20 bits, keys whose bits 24..47 are constant,
+    and all keys equal (every pass a copy; values must keep their order)."""
+    rng = np.random.Generator(np.random.PCG64(n + len(spread)))
+    if spread == "low_bits":
+        keys = rng.integers(0, 2 ** 20, n, dtype=np.uint64)
+    elif spread == "middle_constant":
+        lo = rng.integers(0, 2 ** 24, n, dtype=np.uint64)
+        hi = rng.integers(0, 2 ** 16, n, dtype=np.uint64) << np.uint64(48)
+        keys = lo | hi | (np.uint64(0xA5) << np.uint64(32))
+    else:
+        keys = np.full(n, np.uint64(0x0123456789ABCDEF))
+    vals = np.arange(n, dtype=np.int32)[rng.permutation(n)]
+    k = torch.from_numpy(keys.view(np.int64).copy()).cuda()
+    v = torch.from_numpy(vals.copy()).cuda()
+    ctx.sort_pairs(k, v)
+    order = np.argsort(keys, kind="stable")
+    np.testing.assert_array_equal(k.cpu().numpy().view(np.uint64), keys[order])
+    np.testing.assert_array_equal(v.cpu().numpy(), vals[order])
+
+
 def _walk(nodes, leaf, root, n):
     """Pre-order walk that always descends: internal -> left child, leaf ->
     its rope.  Returns the visit sequence (node refs)."""
