@@ -25,6 +25,7 @@ JSON line carries, unless switched off:
               minPts 5) in one batched call (FDBSCAN, DenseBox, and the
               autotuner's pick, which "batched_ms" times) vs one plain call
               per set;
+  "halo134M": the 2^27-point field at minPts 2 and 10 (--no-large skips it);
   "serving":  an open-loop replay of Poisson arrivals (200 jobs/s, sizes
               log-uniform in [1e3, 2^24], minPts in {2,5,10}) through the
               continuous-batching server: p50/p99 latency and Mpoints/s,
@@ -148,6 +149,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline plain FDBSCAN measurement")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 2^27-point field (about a minute of host-side generation)")
     ap.add_argument("--serving-seconds", type=float, default=60.0)
     ap.add_argument("--baseline-seconds", type=float, default=20.0)
     args = ap.parse_args()
@@ -235,6 +238,23 @@ def main():
         "sort_passes": passes,
     }
 
+    # the same call replayed as a captured HIP graph (DBSCAN_FLAG_GRAPH) on a
+    # side stream: what repeated calls of one shape cost without launch gaps
+    # (no per-kernel events in this mode, so the headline stays the eager run)
+    gs = torch.cuda.Stream()
+    with torch.cuda.stream(gs):
+        for _ in range(2):
+            ctx.cluster(d, float(eps), mp, algorithm=args.algorithm, block_size=args.block_size,
+                        out=labels, graph=True)
+        gs.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.cluster(d, float(eps), mp, algorithm=args.algorithm, block_size=args.block_size,
+                        out=labels, graph=True)
+        gs.synchronize()
+        gms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    out["graph_replay"] = {"ms_per_step": round(gms, 4), "mpoints_per_s": round(n / gms / 1e3, 2)}
+
     # node visits of one pair traversal (outside the timed region): what the
     # pairs kernel's time is spent on
     ts = ctx.traversal_stats(d, float(eps))
@@ -263,8 +283,37 @@ def main():
         torch.cuda.empty_cache()
         out["batched"] = bench_batched(ctx)
         torch.cuda.empty_cache()
+        if not args.no_large:
+            out["halo134M"] = bench_large(ctx)
+            torch.cuda.empty_cache()
         out["serving"] = bench_serving(args.serving_seconds, args.baseline_seconds)
     print(json.dumps(out), flush=True)
+
+
+def bench_large(ctx, steps=3):
+    """The 2^27-point halo field (one GPU's share at production shape) at
+    minPts 2 and 10, plain FDBSCAN, points resident in device memory."""
+    import torch
+
+    import datagen
+    log("[bench] generating halo134M ...")
+    cfg = datagen.CONFIGS["halo134M"]
+    d = torch.from_numpy(datagen.config_points("halo134M")).cuda()
+    n = d.shape[0]
+    lab = torch.empty(n, dtype=torch.int32, device="cuda")
+    res = {"workload": "halo134M", "n": n, "eps": float(cfg["eps"])}
+    for mp in (2, 10):
+        ctx.cluster(d, float(cfg["eps"]), mp, out=lab)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.cluster(d, float(cfg["eps"]), mp, out=lab)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / steps
+        res[f"min_pts_{mp}"] = {"ms_per_step": round(ms, 3),
+                                "mpoints_per_s": round(n / ms / 1e3, 2),
+                                "clustered_fraction": round(float((lab >= 0).float().mean()), 4)}
+    return res
 
 
 def bench_densebox(ctx, d, eps, mp, steps, ref_labels):
