@@ -461,18 +461,19 @@ __device__ __forceinline__ void db_walks(const Node* __restrict__ nodes,
     for (;;) {
       bool act = node != SENTINEL;
       const bool lf = is_leaf(node);
-      if (act && (++steps > 2 * np ||
-                  (lf ? uint32_t(leaf_index(node)) >= np : uint32_t(node) >= np - 1))) {
-        atomicOr(err, STATUS_TREE);
-        node = SENTINEL;
-        act = false;
+      const uint32_t idx = lf ? uint32_t(leaf_index(node)) : uint32_t(node);
+      steps += act ? 1u : 0u;  // bounds checked without a branch, as in wave_walks
+      const bool bad = act && (steps > 2 * np || idx >= (lf ? np : np - 1));
+      if (__builtin_expect(__ballot(bad) != 0ull, 0)) {
+        if (bad) atomicOr(err, STATUS_TREE);
+        node = bad ? SENTINEL : node;
       }
-      const Node* rec = !act ? prims : lf ? prims + leaf_index(node) : nodes + node;
+      act = act && !bad;
+      const Node* rec = !act ? prims : lf ? prims + idx : nodes + idx;
       const float4 a = reinterpret_cast<const float4*>(rec)[0];
       const float4 b = reinterpret_cast<const float4*>(rec)[1];
       // a rope target's number is its first leaf: past the bound, stop
-      const uint32_t first = lf ? uint32_t(leaf_index(node)) : uint32_t(node);
-      const uint64_t kf = pkey[act && by_rope ? first : 0u];
+      const uint64_t kf = pkey[act && by_rope ? idx : 0u];
       if (act && by_rope && kf > v.khi()) {
         node = SENTINEL;
         act = false;

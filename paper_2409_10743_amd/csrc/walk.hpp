@@ -137,21 +137,24 @@ __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
     for (;;) {
       bool act = node != SENTINEL;
       const bool lf = is_leaf(node);
+      const uint32_t idx = lf ? uint32_t(leaf_index(node)) : uint32_t(node);
       // a walk visits every node at most once: more than 2n steps, or a
-      // reference outside the arrays, means a malformed tree
-      if (act && (++steps > 2 * n ||
-                  (lf ? uint32_t(leaf_index(node)) >= n : uint32_t(node) >= n - 1))) {
-        atomicOr(err, STATUS_TREE);
-        node = SENTINEL;
-        act = false;
+      // reference outside the arrays, means a malformed tree (checked
+      // without a branch; the rare failure takes one wave-uniform branch)
+      steps += act ? 1u : 0u;
+      const bool bad = act && (steps > 2 * n || idx >= (lf ? n : n - 1));
+      if (__builtin_expect(__ballot(bad) != 0ull, 0)) {
+        if (bad) atomicOr(err, STATUS_TREE);
+        node = bad ? SENTINEL : node;
       }
+      act = act && !bad;
       const float4* p = !act ? leaf
-                        : lf ? leaf + leaf_index(node)
-                             : reinterpret_cast<const float4*>(nodes + node);
+                        : lf ? leaf + idx
+                             : reinterpret_cast<const float4*>(nodes + idx);
       const float4 a = p[0], p1 = p[1];
       const float4 b = lf ? a : p1;
       if (V::kBounded) {  // a rope target's number is its first leaf
-        const uint32_t first = lf ? uint32_t(leaf_index(node)) : uint32_t(node);
+        const uint32_t first = idx;
         const uint64_t kf = keys[act && by_rope ? first : 0u];
         if (act && by_rope && kf > v.khi()) {
           node = SENTINEL;
