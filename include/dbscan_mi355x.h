@@ -63,9 +63,9 @@ extern "C" {
  * later calls of the same shape (same point and label buffers, sizes, eps
  * and minPts for a plain call; same sets count and total for a batched one,
  * whose per-set values are re-read at each replay) while the context's
- * scratch has not moved.  A context keeps up to 4 graphs.  Ignored with the
- * null stream and by DenseBox (which reads a count back mid-call); no
- * timing in this mode. */
+ * scratch has not moved.  A context keeps up to 4 graphs.  Both algorithms
+ * (DenseBox keeps its primitive count on the device).  Ignored with the null
+ * stream; no timing in this mode. */
 #define DBSCAN_FLAG_GRAPH 2u
 
 typedef struct dbscan_options {

@@ -433,7 +433,7 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
 
 // DenseBox from the (unsorted) cell keys in keys_a, their digit counts in
 // hist and the set table on: sort, cells, primitives, build, walks, labels.
-// One host synchronisation reads the primitive count, which sizes the build.
+// Nothing is read back: the call can be captured as a graph.
 // d_off: the sets' offsets (batched calls; labels set-local), else null
 // and min_pts is the plain call's.
 int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_t n,
@@ -478,11 +478,8 @@ int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_
                     cell_dense, prim_count, s);
   launch_scan(prim_count, prim_start, n, nprims, at<uint32_t>(c, L.scan2), scan_ctr + 1, status,
               s);
-  HIP_TRY(hipMemcpyAsync(c->host_status + 4, ncells, 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  const uint32_t np = c->host_status[5];
-  if (np == 0 || np > n || c->host_status[4] > n)
-    return fail(DBSCAN_EDEVICE, "cell construction produced an invalid count");
+  // the primitive count (at most n) stays on the device: the build and the
+  // walks read it there, launched for n
   Node* prims = at<Node>(c, L.prims);
   uint64_t* pkey = at<uint64_t>(c, L.pkey);
   launch_make_prims(spts, keys, n, cid, cell_start, prim_start, cell_dense, cell_lo, cell_hi,
@@ -490,14 +487,14 @@ int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_
   mark(c, timing, PH_CELLS, s);
 
   Node* nodes = at<Node>(c, L.nodes);
-  launch_build_boxes(pkey, S.shift, prims, np, nodes, other, const_cast<int32_t*>(S.root),
+  launch_build_boxes(pkey, S.shift, prims, n, nprims, nodes, other, const_cast<int32_t*>(S.root),
                      at<int4>(c, L.pending), status, s);
   mark(c, timing, PH_BUILD_LEVELS, s);
   const DbTables T{spts, cell_start, perm, cell_minorig, cell_lo, cell_hi, parent, flag,
                    bestcore};
-  if (any_core) launch_count_db(nodes, prims, pkey, np, S, T, status, block, s);
+  if (any_core) launch_count_db(nodes, prims, pkey, n, nprims, S, T, status, block, s);
   mark(c, timing, PH_COUNT, s);
-  launch_pairs_db(nodes, prims, pkey, np, S, T, status, block, s);
+  launch_pairs_db(nodes, prims, pkey, n, nprims, S, T, status, block, s);
   mark(c, timing, PH_PAIRS, s);
   if (d_off) {
     launch_final_sets(n, keys, S.shift, S.minpts, d_off, flag, bestcore, perm, parent, minlab,
@@ -520,45 +517,57 @@ float inv_cell_side(float eps) {
 
 int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t min_pts,
                  int32_t* labels, hipStream_t s, const dbscan_options& o) {
-  const bool timing = (o.flags & DBSCAN_FLAG_TIMING) != 0;
+  const bool graph = (o.flags & DBSCAN_FLAG_GRAPH) != 0;
+  const bool timing = !graph && (o.flags & DBSCAN_FLAG_TIMING) != 0;
   const int block = o.block_size ? o.block_size : 256;
   const bool core_mode = min_pts > 2;
   const int32_t thresh = o.dense_threshold ? o.dense_threshold : min_pts;
 
   Layout L = make_layout(n, core_mode, true);
-  int st = ensure_arena(c, L.total);
+  int st = ensure_arena(c, L.total);  // before any capture
   if (st != DBSCAN_OK) return st;
   uint32_t* bounds = at<uint32_t>(c, L.bounds);
   uint32_t* status = at<uint32_t>(c, L.status);
   MortonGrid* grid = at<MortonGrid>(c, L.grid);
   const DbSets S{at<float>(c, L.set_e2), at<int32_t>(c, L.set_mp), at<int32_t>(c, L.set_th),
                  grid, at<int32_t>(c, L.root), 64};
-
-  start_timing(c, timing, s);
-  launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, at<int4>(c, L.pending),
-              L.pending_entries, s);
-  launch_one_set(eps * eps, min_pts, thresh, const_cast<float*>(S.e2),
-                 const_cast<int32_t*>(S.minpts), const_cast<int32_t*>(S.thresh), s);
-  mark(c, timing, PH_PREP, s);
-  launch_bounds(pts, n, bounds, status, s);
-  mark(c, timing, PH_BOUNDS, s);
-  launch_cell_keys(pts, n, bounds, inv_cell_side(eps), at<uint64_t>(c, L.keys_a),
-                   at<uint32_t>(c, L.hist), grid, s);
-  mark(c, timing, PH_MORTON, s);
-  st = densebox_from_keys(c, L, pts, n, S, core_mode, nullptr, min_pts, labels, block, timing,
-                          s);
+  const std::vector<uint64_t> key = {3,
+                                     reinterpret_cast<uint64_t>(pts),
+                                     reinterpret_cast<uint64_t>(labels),
+                                     reinterpret_cast<uint64_t>(c->arena),
+                                     n,
+                                     bits_of(eps),
+                                     uint64_t(uint32_t(min_pts)),
+                                     uint64_t(uint32_t(thresh)),
+                                     uint64_t(block)};
+  st = run_enqueued(c, s, graph, key, [&](hipStream_t gs) {
+    start_timing(c, timing, gs);
+    launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, at<int4>(c, L.pending),
+                L.pending_entries, gs);
+    launch_one_set(eps * eps, min_pts, thresh, const_cast<float*>(S.e2),
+                   const_cast<int32_t*>(S.minpts), const_cast<int32_t*>(S.thresh), gs);
+    mark(c, timing, PH_PREP, gs);
+    launch_bounds(pts, n, bounds, status, gs);
+    mark(c, timing, PH_BOUNDS, gs);
+    launch_cell_keys(pts, n, bounds, inv_cell_side(eps), at<uint64_t>(c, L.keys_a),
+                     at<uint32_t>(c, L.hist), grid, gs);
+    mark(c, timing, PH_MORTON, gs);
+    int r = densebox_from_keys(c, L, pts, n, S, core_mode, nullptr, min_pts, labels, block,
+                               timing, gs);
+    if (r != DBSCAN_OK) return r;
+    HIP_TRY(hipGetLastError());
+    return int(DBSCAN_OK);
+  });
   if (st != DBSCAN_OK) return st;
-  HIP_TRY(hipGetLastError());
   return finish(c, status, timing, s);
 }
 
 // Many independent sets in one pass (keys tagged with the set id).
-// DenseBox: no graph (a host synchronisation sizes the build).
 int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t num_sets,
                 const float* h_eps, const int32_t* h_minpts, int32_t* labels, hipStream_t s,
                 const dbscan_options& o) {
   const bool db = o.algorithm == DBSCAN_ALGO_DENSEBOX;
-  const bool graph = !db && (o.flags & DBSCAN_FLAG_GRAPH) != 0;
+  const bool graph = (o.flags & DBSCAN_FLAG_GRAPH) != 0;
   const bool timing = !graph && (o.flags & DBSCAN_FLAG_TIMING) != 0;
   const int block = o.block_size ? o.block_size : 256;
   const uint32_t n = uint32_t(h_off[num_sets]);
@@ -610,28 +619,7 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
   int32_t* d_root = at<int32_t>(c, root_b);
   MortonGrid* d_grid = at<MortonGrid>(c, grid_b);
   uint32_t* status = at<uint32_t>(c, L.status);
-  if (db) {
-    int32_t* d_th = at<int32_t>(c, th_b);
-    float* d_ih = at<float>(c, ih_b);
-    HIP_TRY(hipMemcpyAsync(d_off, s_off, (size_t(num_sets) + 1) * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_e2, s_e2, size_t(num_sets) * 4, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_mp, s_mp, size_t(num_sets) * 4, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_th, s_th, size_t(num_sets) * 4, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_ih, s_ih, size_t(num_sets) * 4, hipMemcpyHostToDevice, s));
-    start_timing(c, timing, s);
-    launch_prep(at<uint32_t>(c, L.zero), L.zero_words, at<uint32_t>(c, L.bounds),
-                at<int4>(c, L.pending), L.pending_entries, s);
-    mark(c, timing, PH_PREP, s);
-    launch_set_morton(pts, d_off, num_sets, bits, set_shift, d_ih, at<uint64_t>(c, L.keys_a),
-                      at<uint32_t>(c, L.hist), d_root, d_grid, status, s);
-    mark(c, timing, PH_MORTON, s);
-    const DbSets S{d_e2, d_mp, d_th, d_grid, d_root, set_shift};
-    st = densebox_from_keys(c, L, pts, n, S, any_core, d_off, 0, labels, block, timing, s);
-    if (st != DBSCAN_OK) return st;
-    HIP_TRY(hipGetLastError());
-    return finish(c, status, timing, s);
-  }
-  const std::vector<uint64_t> key = {2,
+  const std::vector<uint64_t> key = {db ? 4u : 2u,
                                      reinterpret_cast<uint64_t>(pts),
                                      reinterpret_cast<uint64_t>(labels),
                                      reinterpret_cast<uint64_t>(c->arena),
@@ -640,6 +628,33 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
                                      num_sets,
                                      uint64_t(any_core),
                                      uint64_t(block)};
+  if (db) {
+    int32_t* d_th = at<int32_t>(c, th_b);
+    float* d_ih = at<float>(c, ih_b);
+    st = run_enqueued(c, s, graph, key, [&](hipStream_t gs) {
+      // per-set values come from the pinned staging buffer at each replay
+      HIP_TRY(hipMemcpyAsync(d_off, s_off, (size_t(num_sets) + 1) * 8, hipMemcpyHostToDevice,
+                             gs));
+      HIP_TRY(hipMemcpyAsync(d_e2, s_e2, size_t(num_sets) * 4, hipMemcpyHostToDevice, gs));
+      HIP_TRY(hipMemcpyAsync(d_mp, s_mp, size_t(num_sets) * 4, hipMemcpyHostToDevice, gs));
+      HIP_TRY(hipMemcpyAsync(d_th, s_th, size_t(num_sets) * 4, hipMemcpyHostToDevice, gs));
+      HIP_TRY(hipMemcpyAsync(d_ih, s_ih, size_t(num_sets) * 4, hipMemcpyHostToDevice, gs));
+      start_timing(c, timing, gs);
+      launch_prep(at<uint32_t>(c, L.zero), L.zero_words, at<uint32_t>(c, L.bounds),
+                  at<int4>(c, L.pending), L.pending_entries, gs);
+      mark(c, timing, PH_PREP, gs);
+      launch_set_morton(pts, d_off, num_sets, bits, set_shift, d_ih, at<uint64_t>(c, L.keys_a),
+                        at<uint32_t>(c, L.hist), d_root, d_grid, status, gs);
+      mark(c, timing, PH_MORTON, gs);
+      const DbSets S{d_e2, d_mp, d_th, d_grid, d_root, set_shift};
+      int r = densebox_from_keys(c, L, pts, n, S, any_core, d_off, 0, labels, block, timing, gs);
+      if (r != DBSCAN_OK) return r;
+      HIP_TRY(hipGetLastError());
+      return int(DBSCAN_OK);
+    });
+    if (st != DBSCAN_OK) return st;
+    return finish(c, status, timing, s);
+  }
   st = run_enqueued(c, s, graph, key, [&](hipStream_t gs) {
     // the per-set parameters are read from the pinned staging buffer when
     // the copies run, so a replayed graph picks up this call's values

@@ -633,16 +633,20 @@ __device__ __forceinline__ DbQueue wave_queue() {
 }
 
 __global__ void k_count_db(const Node* __restrict__ nodes, const Node* __restrict__ prims,
-                           const uint64_t* __restrict__ pkey, uint32_t np, WalkCfg wc, DbSets S,
-                           DbData D, uint32_t* __restrict__ err) {
+                           const uint64_t* __restrict__ pkey, uint32_t np_bound,
+                           const uint32_t* __restrict__ np_dev, WalkCfg wc, DbSets S, DbData D,
+                           uint32_t* __restrict__ err) {
+  const uint32_t np = min(*np_dev, np_bound);
   const DbQueue Q = wave_queue();
   CountDb v{S, D, Q, pkey, 0.f, 0, -1, 0u, 0ull, make_float4(0.f, 0.f, 0.f, 0.f)};
   db_walks(nodes, prims, pkey, np, wc, v, Q, err);
 }
 
 __global__ void k_pairs_db(const Node* __restrict__ nodes, const Node* __restrict__ prims,
-                           const uint64_t* __restrict__ pkey, uint32_t np, WalkCfg wc, DbSets S,
-                           DbData D, uint32_t* __restrict__ err) {
+                           const uint64_t* __restrict__ pkey, uint32_t np_bound,
+                           const uint32_t* __restrict__ np_dev, WalkCfg wc, DbSets S, DbData D,
+                           uint32_t* __restrict__ err) {
+  const uint32_t np = min(*np_dev, np_bound);
   const DbQueue Q = wave_queue();
   PairDb v{S, D, Q, pkey, 0.f, false, false, 0, 0ull, make_float4(0.f, 0.f, 0.f, 0.f),
            make_float4(0.f, 0.f, 0.f, 0.f)};
@@ -717,24 +721,24 @@ static size_t queue_lds(int block) {
   return waves * QCAP * sizeof(int4) + waves * sizeof(uint32_t);
 }
 
-void launch_count_db(const Node* nodes, const Node* prims, const uint64_t* pkey, uint32_t nprims,
-                     const DbSets& sets, const DbTables& t, uint32_t* err, int block,
-                     hipStream_t s) {
-  if (nprims == 0) return;
+void launch_count_db(const Node* nodes, const Node* prims, const uint64_t* pkey,
+                     uint32_t np_bound, const uint32_t* np_dev, const DbSets& sets,
+                     const DbTables& t, uint32_t* err, int block, hipStream_t s) {
+  if (np_bound == 0) return;
   const DbData D{t.pts, t.cell_start, t.perm, t.cell_minorig, t.cell_lo, t.cell_hi, t.parent,
                  t.flag, t.bestcore};
-  hipLaunchKernelGGL(k_count_db, dim3(walk_grid(nprims, block)), dim3(block), queue_lds(block), s,
-                     nodes, prims, pkey, nprims, walk_cfg(nprims), sets, D, err);
+  hipLaunchKernelGGL(k_count_db, dim3(walk_grid(np_bound, block)), dim3(block), queue_lds(block),
+                     s, nodes, prims, pkey, np_bound, np_dev, walk_cfg(np_bound), sets, D, err);
 }
 
-void launch_pairs_db(const Node* nodes, const Node* prims, const uint64_t* pkey, uint32_t nprims,
-                     const DbSets& sets, const DbTables& t, uint32_t* err, int block,
-                     hipStream_t s) {
-  if (nprims == 0) return;
+void launch_pairs_db(const Node* nodes, const Node* prims, const uint64_t* pkey,
+                     uint32_t np_bound, const uint32_t* np_dev, const DbSets& sets,
+                     const DbTables& t, uint32_t* err, int block, hipStream_t s) {
+  if (np_bound == 0) return;
   const DbData D{t.pts, t.cell_start, t.perm, t.cell_minorig, t.cell_lo, t.cell_hi, t.parent,
                  t.flag, t.bestcore};
-  hipLaunchKernelGGL(k_pairs_db, dim3(walk_grid(nprims, block)), dim3(block), queue_lds(block), s,
-                     nodes, prims, pkey, nprims, walk_cfg(nprims), sets, D, err);
+  hipLaunchKernelGGL(k_pairs_db, dim3(walk_grid(np_bound, block)), dim3(block), queue_lds(block),
+                     s, nodes, prims, pkey, np_bound, np_dev, walk_cfg(np_bound), sets, D, err);
 }
 
 }  // namespace dbx

@@ -179,9 +179,10 @@ __device__ __forceinline__ void grow(float4& lo, float4& hi, const float4& slo,
 // with the exchange slots later levels still need.
 template <class Leaves>
 __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
-    const uint64_t* __restrict__ keys, Leaves lv, uint32_t n, int set_shift,
-    Node* __restrict__ nodes, int32_t* __restrict__ other, int32_t* __restrict__ set_root,
-    int4* __restrict__ pend_out, uint32_t* __restrict__ err) {
+    const uint64_t* __restrict__ keys, Leaves lv, uint32_t n_bound,
+    const uint32_t* __restrict__ n_dev, int set_shift, Node* __restrict__ nodes,
+    int32_t* __restrict__ other, int32_t* __restrict__ set_root, int4* __restrict__ pend_out,
+    uint32_t* __restrict__ err) {
   __shared__ uint64_t s_delta[BUILD_LEAVES + 2];  // delta of boundary f0-1+j at j
   __shared__ uint8_t s_cut[BUILD_LEAVES + 2];     // a set ends at boundary f0-1+j
   __shared__ float4 s_leaf[BUILD_LEAVES], s_leafhi[BUILD_LEAVES];
@@ -189,8 +190,10 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
   __shared__ int32_t s_left[BUILD_LEAVES], s_end[BUILD_LEAVES];  // its left child, last leaf
   __shared__ int32_t s_other[BUILD_LEAVES];  // exchange slot of split f0+k; -2 once finished
   const int32_t t = threadIdx.x;
+  const uint32_t n = n_dev ? min(*n_dev, n_bound) : n_bound;
   const int32_t last = int32_t(n) - 1;
   const int32_t f0 = int32_t(blockIdx.x) * BUILD_LEAVES;
+  if (f0 >= int32_t(n)) return;  // launched for the bound: the whole block
   const int32_t f1 = min(f0 + BUILD_LEAVES, int32_t(n));
   const int32_t m = f1 - f0;
   const uint64_t mask = set_mask_of(set_shift);
@@ -320,9 +323,11 @@ __device__ __forceinline__ void set_right(Ends& E, const uint64_t* __restrict__ 
 // keys at the node's new end) go out together.
 template <class Leaves>
 __global__ __launch_bounds__(1024) void k_build_level(
-    const uint64_t* __restrict__ keys, Leaves lv, uint32_t n, uint64_t frame, uint32_t entries,
-    int set_shift, Node* nodes, int32_t* other, int32_t* set_root,
-    const int4* __restrict__ pend_in, int4* __restrict__ pend_out, uint32_t* err) {
+    const uint64_t* __restrict__ keys, Leaves lv, uint32_t n_bound,
+    const uint32_t* __restrict__ n_dev, uint64_t frame, uint32_t entries, int set_shift,
+    Node* nodes, int32_t* other, int32_t* set_root, const int4* __restrict__ pend_in,
+    int4* __restrict__ pend_out, uint32_t* err) {
+  const uint32_t n = n_dev ? min(*n_dev, n_bound) : n_bound;
   const int32_t last = int32_t(n) - 1;
   const int64_t f0 = int64_t(blockIdx.x) * int64_t(frame);
   const int64_t f1 = min(f0 + int64_t(frame), int64_t(n));
@@ -425,10 +430,14 @@ size_t build_pending_entries(uint32_t n) {
 namespace {
 // FrameLeaves: the leaves as level 1 reads and writes them; Leaves: as the
 // later levels read them
+// n: the leaf count, or with n_dev an upper bound of the count held in
+// device memory at *n_dev (the launches are sized for the bound; frames past
+// the count exit at once)
 template <class FrameLeaves, class Leaves>
 void build_impl(const uint64_t* keys, int set_shift, FrameLeaves flv, Leaves lv, uint32_t n,
-                Node* nodes, int32_t* other, int32_t* root, int4* pending, uint32_t* err,
-                hipStream_t s, void (*after_level)(void*, int), void* arg) {
+                const uint32_t* n_dev, Node* nodes, int32_t* other, int32_t* root,
+                int4* pending, uint32_t* err, hipStream_t s, void (*after_level)(void*, int),
+                void* arg) {
   if (n == 0) return;
   const int levels = build_levels(n);
   uint64_t frame = BUILD_LEAVES;
@@ -439,19 +448,19 @@ void build_impl(const uint64_t* keys, int set_shift, FrameLeaves flv, Leaves lv,
     const uint32_t frames = uint32_t((n + frame - 1) / frame);
     if (lv_i == 1) {
       hipLaunchKernelGGL(k_build_frame<FrameLeaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys,
-                         flv, n, set_shift, nodes, other, root, pout, err);
+                         flv, n, n_dev, set_shift, nodes, other, root, pout, err);
     } else if (entries <= 1024) {
       // few enough nodes left for one workgroup: it climbs them all to the
       // root (one frame over every leaf), in place of the remaining levels
       const uint32_t threads = (entries + 63) / 64 * 64;
-      hipLaunchKernelGGL(k_build_level<Leaves>, dim3(1), dim3(threads), 0, s, keys, lv, n,
+      hipLaunchKernelGGL(k_build_level<Leaves>, dim3(1), dim3(threads), 0, s, keys, lv, n, n_dev,
                          uint64_t(n), entries, set_shift, nodes, other, root, pin, pout, err);
       if (after_level) after_level(arg, lv_i);
       return;
     } else {
       hipLaunchKernelGGL(k_build_level<Leaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys, lv,
-                         n, frame, uint32_t(frames) * BUILD_BLOCK, set_shift, nodes, other, root,
-                         pin, pout, err);
+                         n, n_dev, frame, uint32_t(frames) * BUILD_BLOCK, set_shift, nodes, other,
+                         root, pin, pout, err);
     }
     if (after_level) after_level(arg, lv_i);
     pin = pout;
@@ -470,14 +479,15 @@ void launch_build(const uint64_t* keys, int set_shift, const float* pts, const u
                   void (*after_level)(void*, int), void* arg) {
   build_impl(keys, set_shift,
              GatherLeaves{pts, perm, n, leaf, parent, minlab, flag, bestcore, labels},
-             PointLeaves{leaf}, n, nodes, other, set_root, pending, err, s, after_level, arg);
+             PointLeaves{leaf}, n, nullptr, nodes, other, set_root, pending, err, s, after_level,
+             arg);
 }
 
-void launch_build_boxes(const uint64_t* keys, int set_shift, Node* prims, uint32_t n, Node* nodes,
-                        int32_t* other, int32_t* set_root, int4* pending, uint32_t* err,
-                        hipStream_t s) {
-  build_impl(keys, set_shift, BoxLeaves{prims}, BoxLeaves{prims}, n, nodes, other, set_root,
-             pending, err, s, nullptr, nullptr);
+void launch_build_boxes(const uint64_t* keys, int set_shift, Node* prims, uint32_t n_bound,
+                        const uint32_t* n_dev, Node* nodes, int32_t* other, int32_t* set_root,
+                        int4* pending, uint32_t* err, hipStream_t s) {
+  build_impl(keys, set_shift, BoxLeaves{prims}, BoxLeaves{prims}, n_bound, n_dev, nodes, other,
+             set_root, pending, err, s, nullptr, nullptr);
 }
 
 }  // namespace dbx

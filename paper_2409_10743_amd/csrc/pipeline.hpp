@@ -115,10 +115,12 @@ void launch_build(const uint64_t* keys, int set_shift, const float* pts, const u
                   int32_t* set_root, int4* pending, uint32_t* err, hipStream_t s,
                   void (*after_level)(void*, int) = nullptr, void* arg = nullptr);
 // The same over box leaves (DenseBox primitives: Node records, payload in
-// `left`, rope in `rope`); sets as in launch_build.
-void launch_build_boxes(const uint64_t* keys, int set_shift, Node* prims, uint32_t n, Node* nodes,
-                        int32_t* other, int32_t* set_root, int4* pending, uint32_t* err,
-                        hipStream_t s);
+// `left`, rope in `rope`); sets as in launch_build.  The primitive count is
+// read from *n_dev (at most n_bound, which sizes the launches), so no host
+// round trip is needed between the primitives and the build.
+void launch_build_boxes(const uint64_t* keys, int set_shift, Node* prims, uint32_t n_bound,
+                        const uint32_t* n_dev, Node* nodes, int32_t* other, int32_t* set_root,
+                        int4* pending, uint32_t* err, hipStream_t s);
 
 // ---- traversals (traverse.hip) ---------------------------------------------
 // keys: the sorted Morton codes; bounds: the scene bounds words they were
@@ -206,13 +208,14 @@ void launch_make_prims(const float4* pts, const uint64_t* keys, uint32_t n, cons
 // the one-set parameter table of a plain call
 void launch_one_set(float e2, int32_t min_pts, int32_t thresh, float* e2o, int32_t* mpo,
                     int32_t* tho, hipStream_t s);
-// block: a multiple of 64, at most 1024
-void launch_count_db(const Node* nodes, const Node* prims, const uint64_t* pkey, uint32_t nprims,
-                     const DbSets& sets, const DbTables& t, uint32_t* err, int block,
-                     hipStream_t s);
-void launch_pairs_db(const Node* nodes, const Node* prims, const uint64_t* pkey, uint32_t nprims,
-                     const DbSets& sets, const DbTables& t, uint32_t* err, int block,
-                     hipStream_t s);
+// block: a multiple of 64, at most 1024; the primitive count is *np_dev, at
+// most np_bound (which sizes the launch)
+void launch_count_db(const Node* nodes, const Node* prims, const uint64_t* pkey,
+                     uint32_t np_bound, const uint32_t* np_dev, const DbSets& sets,
+                     const DbTables& t, uint32_t* err, int block, hipStream_t s);
+void launch_pairs_db(const Node* nodes, const Node* prims, const uint64_t* pkey,
+                     uint32_t np_bound, const uint32_t* np_dev, const DbSets& sets,
+                     const DbTables& t, uint32_t* err, int block, hipStream_t s);
 
 // ---- batched sets (batched.hip) -----------------------------------------------
 // Keys of every set: (set id << set_shift) | Morton code with `bits` bits per
