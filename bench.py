@@ -292,7 +292,8 @@ def main():
 
 def bench_large(ctx, steps=3):
     """The 2^27-point halo field (one GPU's share at production shape) at
-    minPts 2 and 10, plain FDBSCAN, points resident in device memory."""
+    minPts 2 and 10 (the latter also with core points found by pair
+    traversal), plain FDBSCAN, points resident in device memory."""
     import torch
 
     import datagen
@@ -302,17 +303,17 @@ def bench_large(ctx, steps=3):
     n = d.shape[0]
     lab = torch.empty(n, dtype=torch.int32, device="cuda")
     res = {"workload": "halo134M", "n": n, "eps": float(cfg["eps"])}
-    for mp in (2, 10):
-        ctx.cluster(d, float(cfg["eps"]), mp, out=lab)
+    for mp, pc in ((2, False), (10, False), (10, True)):
+        ctx.cluster(d, float(cfg["eps"]), mp, out=lab, pair_count=pc)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            ctx.cluster(d, float(cfg["eps"]), mp, out=lab)
+            ctx.cluster(d, float(cfg["eps"]), mp, out=lab, pair_count=pc)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1000.0 / steps
-        res[f"min_pts_{mp}"] = {"ms_per_step": round(ms, 3),
-                                "mpoints_per_s": round(n / ms / 1e3, 2),
-                                "clustered_fraction": round(float((lab >= 0).float().mean()), 4)}
+        res[f"min_pts_{mp}" + ("_pair_count" if pc else "")] = {
+            "ms_per_step": round(ms, 3), "mpoints_per_s": round(n / ms / 1e3, 2),
+            "clustered_fraction": round(float((lab >= 0).float().mean()), 4)}
     return res
 
 

@@ -67,6 +67,13 @@ extern "C" {
  * (DenseBox keeps its primitive count on the device).  Ignored with the null
  * stream; no timing in this mode. */
 #define DBSCAN_FLAG_GRAPH 2u
+/* Plain FDBSCAN with min_pts > 2: find the core points by pair traversal
+ * (every pair adds one to both points' neighbour counts; section 4.2.3
+ * applied to counting) instead of a walk per point from the root that stops
+ * at min_pts (section 4.1.2).  Faster where points have few neighbours (no
+ * walk from the root), slower in dense regions (no early exit); labels are
+ * the same.  The autotuner tries both.  Ignored otherwise. */
+#define DBSCAN_FLAG_PAIR_COUNT 4u
 
 typedef struct dbscan_options {
   int32_t algorithm;        /* DBSCAN_ALGO_* */

@@ -25,6 +25,7 @@ ALGO = {"auto": 0, "fdbscan": 1, "densebox": 2}
 ALGO_NAME = {v: k for k, v in ALGO.items()}
 FLAG_TIMING = 1
 FLAG_GRAPH = 2
+FLAG_PAIR_COUNT = 4
 STATUS = {0: "ok", -1: "invalid argument", -2: "non-finite coordinate",
           -3: "out of device memory", -4: "device error", -5: "job exceeds budget"}
 
@@ -173,16 +174,18 @@ class Context:
 
     def cluster(self, points, eps: float, min_pts: int, algorithm: str = "auto",
                 block_size: int = 0, dense_threshold: int = 0, timing: bool = False,
-                out=None, graph: bool = False):
+                out=None, graph: bool = False, pair_count: bool = False):
         """``graph``: enqueue as a HIP graph replayed by later calls of the
         same shape (needs a non-default current stream; see
-        DBSCAN_FLAG_GRAPH)."""
+        DBSCAN_FLAG_GRAPH).  ``pair_count``: core points by pair traversal
+        (DBSCAN_FLAG_PAIR_COUNT)."""
         torch = _torch()
         p = _points(points)
         n = p.shape[0]
         labels = out if out is not None else torch.empty(n, dtype=torch.int32, device=p.device)
         o = _Options(ALGO[algorithm], int(dense_threshold), int(block_size),
-                     (FLAG_TIMING if timing else 0) | (FLAG_GRAPH if graph else 0))
+                     (FLAG_TIMING if timing else 0) | (FLAG_GRAPH if graph else 0) |
+                     (FLAG_PAIR_COUNT if pair_count else 0))
         _check(load_library().dbscan_cluster_ex(
             self.handle, ctypes.c_void_p(p.data_ptr()), n, ctypes.c_float(eps), int(min_pts),
             ctypes.c_void_p(labels.data_ptr()), _stream(p.device), ctypes.byref(o)))
@@ -230,7 +233,7 @@ class Context:
             int(min_pts), ALGO[algorithm], ctypes.c_void_p(lab.data_ptr()), ctypes.byref(o),
             ctypes.byref(ms), _stream(p.device)))
         return {"block_size": o.block_size, "dense_threshold": o.dense_threshold,
-                "ms": ms.value}
+                "pair_count": bool(o.flags & FLAG_PAIR_COUNT), "ms": ms.value}
 
     def autotune_batched(self, points, offsets, eps, min_pts):
         import numpy as np

@@ -56,7 +56,8 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Byte offsets of every buffer of a job inside the arena.
 struct Layout {
-  size_t keys_a, keys_b, vals_a, vals_b, leaf, nodes, parent, minlab, flag, bestcore, pending;
+  size_t keys_a, keys_b, vals_a, vals_b, leaf, nodes, parent, minlab, flag, bestcore, deg,
+      pending;
   // DenseBox only (0 otherwise)
   size_t cid, head, cell_start, cell_lo, cell_hi, cell_minorig, cell_dense, prim_count,
       prim_start, prims, pkey, scan1, scan2, scan_ctr, ncells, nprims;
@@ -87,6 +88,7 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
   L.minlab = need_bestcore ? take(size_t(n) * 4) : 0;  // border points' label minima
   L.flag = take(size_t(n));
   L.bestcore = need_bestcore ? take(size_t(n) * 8) : 0;
+  L.deg = need_bestcore ? take(size_t(n) * 4) : 0;  // pair counts (DBSCAN_FLAG_PAIR_COUNT)
   L.pending_entries = uint32_t(build_pending_entries(n));
   L.pending = take(size_t(L.pending_entries) * 16);
   if (densebox) {
@@ -256,9 +258,10 @@ void build_mark(void* arg, int level) {  // level 1 = the frame kernel
   if (level == 1) mark(m->c, true, PH_BUILD_FRAME, m->s);
 }
 
-// labels (or null): set to -1 here, by the build's first level.
+// labels (or null): set to -1 here, by the build's first level; so is deg
+// to 0 (or null).
 int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore, bool timing,
-                hipStream_t s, Index* out, float code_eps, int32_t* labels) {
+                hipStream_t s, Index* out, float code_eps, int32_t* labels, uint32_t* deg) {
   Layout L = make_layout(n, need_bestcore);
   int st = ensure_arena(c, L.total);
   if (st != DBSCAN_OK) return st;
@@ -291,7 +294,7 @@ int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore,
   // the build's first level gathers the leaves and sets up the union-find
   launch_build(keys, 64, pts, perm, at<float4>(c, L.leaf), at<int32_t>(c, L.parent),
                need_bestcore ? at<int32_t>(c, L.minlab) : nullptr, at<uint8_t>(c, L.flag),
-               need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr, labels, n,
+               need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr, labels, deg, n,
                at<Node>(c, L.nodes), other, at<int32_t>(c, L.root), at<int4>(c, L.pending),
                status, s, timing ? build_mark : nullptr, &sm);
   mark(c, timing, PH_BUILD_LEVELS, s);
@@ -391,6 +394,7 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
   const int block = o.block_size ? o.block_size : 256;
   const float e2 = eps * eps;
   const bool core_mode = min_pts > 2;
+  const bool pair_count = core_mode && (o.flags & DBSCAN_FLAG_PAIR_COUNT) != 0;
   const Layout L = make_layout(n, core_mode);
   int st = ensure_arena(c, L.total);  // before any capture
   if (st != DBSCAN_OK) return st;
@@ -401,16 +405,21 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
                                      n,
                                      bits_of(eps),
                                      uint64_t(uint32_t(min_pts)),
-                                     uint64_t(block)};
+                                     uint64_t(block),
+                                     uint64_t(pair_count)};
   st = run_enqueued(c, s, graph, key, [&](hipStream_t gs) {
     Index ix;
-    int r = build_index(c, pts, n, core_mode, timing, gs, &ix, eps, labels);
+    uint32_t* deg = pair_count ? at<uint32_t>(c, L.deg) : nullptr;
+    int r = build_index(c, pts, n, core_mode, timing, gs, &ix, eps, labels, deg);
     if (r != DBSCAN_OK) return r;
     uint8_t* flag = at<uint8_t>(c, L.flag);
     int32_t* parent = at<int32_t>(c, L.parent);
     unsigned long long* bestcore =
         core_mode ? at<unsigned long long>(c, L.bestcore) : nullptr;
-    if (core_mode)
+    if (pair_count)
+      launch_count_pairs(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, min_pts, deg,
+                         flag, ix.status, block, gs);
+    else if (core_mode)
       launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, ix.root, e2, min_pts,
                    flag, ix.status, block, gs);
     mark(c, timing, PH_COUNT, gs);
@@ -690,8 +699,8 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
     const uint32_t* perm = in_a ? va : vb;
     int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
     Node* nodes = at<Node>(c, L.nodes);
-    launch_build(keys, set_shift, pts, perm, leaf, parent, minlab, flag, bestcore, labels, n,
-                 nodes, other, d_root, at<int4>(c, L.pending), status, gs,
+    launch_build(keys, set_shift, pts, perm, leaf, parent, minlab, flag, bestcore, labels,
+                 nullptr, n, nodes, other, d_root, at<int4>(c, L.pending), status, gs,
                  timing ? build_mark : nullptr, &sm);
     mark(c, timing, PH_BUILD_LEVELS, gs);
     if (any_core)
@@ -781,6 +790,10 @@ std::vector<dbscan_options> candidates(int32_t algorithm, int32_t min_pts) {
       }
     } else {
       v.push_back(o);
+      if (min_pts > 2) {  // core flags by pair traversal too
+        o.flags = DBSCAN_FLAG_PAIR_COUNT;
+        v.push_back(o);
+      }
     }
   }
   return v;
@@ -977,7 +990,7 @@ int dbscan_build_tree(dbscan_ctx* c, const float* points, int64_t n, uint32_t* p
   DeviceGuard g(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index ix;
-  st = build_index(c, points, uint32_t(n), false, false, s, &ix, 0.0f, nullptr);
+  st = build_index(c, points, uint32_t(n), false, false, s, &ix, 0.0f, nullptr, nullptr);
   if (st != DBSCAN_OK) return st;
   HIP_TRY(hipMemcpyAsync(perm, ix.perm, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipMemcpyAsync(leaf, ix.leaf, size_t(n) * 16, hipMemcpyDeviceToDevice, s));
@@ -996,7 +1009,7 @@ int dbscan_core_flags(dbscan_ctx* c, const float* points, int64_t n, float eps, 
   DeviceGuard g(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index ix;
-  st = build_index(c, points, uint32_t(n), false, false, s, &ix, eps, nullptr);
+  st = build_index(c, points, uint32_t(n), false, false, s, &ix, eps, nullptr, nullptr);
   if (st != DBSCAN_OK) return st;
   uint8_t* flag = at<uint8_t>(c, ix.L.flag);
   launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, uint32_t(n), ix.root,
@@ -1024,7 +1037,7 @@ int dbscan_traversal_stats(dbscan_ctx* c, const float* points, int64_t n, float 
   DeviceGuard g(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index ix;
-  st = build_index(c, points, uint32_t(n), false, false, s, &ix, eps, nullptr);
+  st = build_index(c, points, uint32_t(n), false, false, s, &ix, eps, nullptr, nullptr);
   if (st != DBSCAN_OK) return st;
   unsigned long long* dcount = at<unsigned long long>(c, ix.L.count);
   launch_pairs_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, uint32_t(n),

@@ -86,6 +86,7 @@ struct GatherLeaves {
   uint8_t* flag;
   unsigned long long* bestcore;  // null unless minPts > 2
   int32_t* labels;               // output, input order; null: none
+  uint32_t* deg;                 // pair counts (core flags by pair traversal); null: none
   __device__ void load(int32_t j, float4& lo, float4& hi) const {
     const uint32_t o = min(perm[j], n - 1);  // a permutation unless the sort failed
     const float* p = pts + size_t(3) * o;
@@ -98,6 +99,7 @@ struct GatherLeaves {
     flag[j] = 0;
     if (bestcore) bestcore[j] = ~0ull;
     if (labels) labels[j] = -1;  // by input index: every index once
+    if (deg) deg[j] = 0;
     if (uint32_t(j) == n - 1)  // the walks read one record past the last leaf
       leaf[n] = make_float4(0.f, 0.f, 0.f, __int_as_float(SENTINEL));
   }
@@ -474,11 +476,11 @@ void build_impl(const uint64_t* keys, int set_shift, FrameLeaves flv, Leaves lv,
 
 void launch_build(const uint64_t* keys, int set_shift, const float* pts, const uint32_t* perm,
                   float4* leaf, int32_t* parent, int32_t* minlab, uint8_t* flag,
-                  unsigned long long* bestcore, int32_t* labels, uint32_t n, Node* nodes,
-                  int32_t* other, int32_t* set_root, int4* pending, uint32_t* err, hipStream_t s,
-                  void (*after_level)(void*, int), void* arg) {
+                  unsigned long long* bestcore, int32_t* labels, uint32_t* deg, uint32_t n,
+                  Node* nodes, int32_t* other, int32_t* set_root, int4* pending, uint32_t* err,
+                  hipStream_t s, void (*after_level)(void*, int), void* arg) {
   build_impl(keys, set_shift,
-             GatherLeaves{pts, perm, n, leaf, parent, minlab, flag, bestcore, labels},
+             GatherLeaves{pts, perm, n, leaf, parent, minlab, flag, bestcore, labels, deg},
              PointLeaves{leaf}, n, nullptr, nodes, other, set_root, pending, err, s, after_level,
              arg);
 }

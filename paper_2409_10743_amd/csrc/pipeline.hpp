@@ -106,12 +106,13 @@ size_t build_pending_entries(uint32_t n);
 // enqueued.  The level-1 frames gather their leaves: leaf j = input point
 // perm[j] (with its rope; leaf[n] is a padding record), and they set up the
 // union-find state of their points (parent[j] = j, flag[j] = 0; minlab[j] =
-// INT_MAX and bestcore[j] = ~0 where given) and labels[j] = -1 (if given).
+// INT_MAX, bestcore[j] = ~0 and deg[j] = 0 where given) and labels[j] = -1
+// (if given).
 // pending must have been emptied (launch_prep).
 void launch_build(const uint64_t* keys, int set_shift, const float* pts, const uint32_t* perm,
                   float4* leaf, int32_t* parent, int32_t* minlab, uint8_t* flag,
-                  unsigned long long* bestcore, int32_t* labels, uint32_t n, Node* nodes,
-                  int32_t* other,
+                  unsigned long long* bestcore, int32_t* labels, uint32_t* deg, uint32_t n,
+                  Node* nodes, int32_t* other,
                   int32_t* set_root, int4* pending, uint32_t* err, hipStream_t s,
                   void (*after_level)(void*, int) = nullptr, void* arg = nullptr);
 // The same over box leaves (DenseBox primitives: Node records, payload in
@@ -130,6 +131,13 @@ void launch_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
                   const uint32_t* bounds, const uint32_t* drop, uint32_t n, const int32_t* root,
                   float e2, int32_t min_pts, uint8_t* is_core, uint32_t* err, int block,
                   hipStream_t s);
+// Core flags by pair traversal: each pair adds one to both points' counts
+// in deg (zero beforehand), then is_core[i] = deg[i] + 1 >= min_pts.  No
+// early exit: for fields where points have few neighbours.
+void launch_count_pairs(const Node* nodes, const float4* leaf, const uint64_t* keys,
+                        const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
+                        int32_t min_pts, uint32_t* deg, uint8_t* is_core, uint32_t* err,
+                        int block, hipStream_t s);
 // minPts <= 2: every point with a neighbour is core; union every pair.
 void launch_pairs_fof(const Node* nodes, const float4* leaf, const uint64_t* keys,
                       const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,

@@ -11,7 +11,10 @@
 //    (early termination, section 4.1.2);
 //  * main phase (Algorithm 2, pair loop) with pair traversal (section
 //    4.2.3): lane i starts at the rope of its own leaf, which visits exactly
-//    the leaves j > i in pre-order, so every pair is handled once.
+//    the leaves j > i in pre-order, so every pair is handled once;
+//  * counting by pair traversal (an option): every pair adds one to both
+//    points' neighbour counts.  No early exit, but no walk from the root
+//    either: cheaper where points have few neighbours.
 #include <cstdlib>
 
 #include "walk.hpp"
@@ -51,7 +54,7 @@ __global__ void k_count(const Node* __restrict__ nodes, const float4* __restrict
   wave_walks(nodes, leaf, keys, n, wc, v, err);
 }
 
-enum PairMode { FOF = 0, CORE = 1, COUNT = 2 };
+enum PairMode { FOF = 0, CORE = 1, COUNT = 2, DEGREE = 3 };
 
 // pair traversal: query i starts at its own leaf's rope (leaves j > i only)
 template <int MODE>
@@ -70,12 +73,13 @@ struct PairVisit {
   unsigned long long tot[4];                 // COUNT only: this lane's totals
   MortonGrid grid;
   uint64_t hi, mask;
+  uint32_t* deg;  // DEGREE only: neighbour counts (self excluded)
   __device__ uint64_t khi() const { return hi; }
   __device__ int32_t begin(uint32_t i, const float4& q) {
     found = false;
     ri = int32_t(i);
     hi = grid.upper_code(q, r2) & mask;
-    if (MODE == COUNT) pairs = visits = descents = leaves = 0;
+    if (MODE == COUNT || MODE == DEGREE) pairs = visits = descents = leaves = 0;
     if (MODE == CORE) ci = is_core[i] != 0;
     return __float_as_int(q.w);
   }
@@ -101,6 +105,9 @@ struct PairVisit {
       else if (ci) atomicMin(bestcore + j, (static_cast<unsigned long long>(perm[i]) << 32) | i);
       else if (cj)
         atomicMin(bestcore + i, (static_cast<unsigned long long>(perm[j]) << 32) | uint32_t(j));
+    } else if (MODE == DEGREE) {
+      ++pairs;
+      atomicAdd(deg + j, 1u);
     } else {
       ++pairs;
     }
@@ -108,6 +115,7 @@ struct PairVisit {
   }
   __device__ void end(uint32_t i) {
     if (MODE == FOF && found) member[i] = 1;
+    if (MODE == DEGREE && pairs) atomicAdd(deg + i, pairs);  // others may add to it too
     if (MODE == COUNT) {  // a query's counts are below 2n, so 32 bits hold them
       tot[0] += pairs; tot[1] += visits; tot[2] += descents; tot[3] += leaves;
     }
@@ -126,9 +134,9 @@ __global__ void k_pairs(const Node* __restrict__ nodes, const float4* __restrict
                         const uint32_t* drop, uint32_t n, WalkCfg wc, float e2,
                         const uint8_t* __restrict__ is_core, const uint32_t* __restrict__ perm,
                         int32_t* parent, uint8_t* member, unsigned long long* bestcore,
-                        unsigned long long* count, uint32_t* err) {
+                        unsigned long long* count, uint32_t* deg, uint32_t* err) {
   PairVisit<MODE> v{e2, is_core, perm, parent, member, bestcore, true, false, 0, 0, 0, 0, 0,
-                    {0, 0, 0, 0}, {}, 0, ~0ull << (drop ? *drop : 0u)};
+                    {0, 0, 0, 0}, {}, 0, ~0ull << (drop ? *drop : 0u), deg};
   v.grid.load(bounds);
   wave_walks(nodes, leaf, keys, n, wc, v, err);
   if (MODE == COUNT) {  // pairs, internal visits, descents, leaf tests
@@ -137,6 +145,13 @@ __global__ void k_pairs(const Node* __restrict__ nodes, const float4* __restrict
     wave_add(count + 2, v.tot[2]);
     wave_add(count + 3, v.tot[3]);
   }
+}
+
+// core flags from the pair counts: the point itself counts too
+__global__ __launch_bounds__(256) void k_degree_flags(uint32_t n, const uint32_t* __restrict__ deg,
+                                                     int32_t min_pts, uint8_t* __restrict__ flag) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = int64_t(deg[i]) + 1 >= int64_t(min_pts);
 }
 
 }  // namespace
@@ -176,7 +191,7 @@ void launch_pairs_fof(const Node* nodes, const float4* leaf, const uint64_t* key
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<FOF>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
                      keys, bounds, drop, n, walk_cfg(n), e2, nullptr, perm, parent,
-                     member, nullptr, nullptr, err);
+                     member, nullptr, nullptr, nullptr, err);
 }
 
 void launch_pairs_core(const Node* nodes, const float4* leaf, const uint64_t* keys,
@@ -186,7 +201,7 @@ void launch_pairs_core(const Node* nodes, const float4* leaf, const uint64_t* ke
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<CORE>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
                      keys, bounds, drop, n, walk_cfg(n), e2, is_core, perm, parent, nullptr,
-                     bestcore, nullptr, err);
+                     bestcore, nullptr, nullptr, err);
 }
 
 void launch_pairs_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
@@ -195,7 +210,19 @@ void launch_pairs_count(const Node* nodes, const float4* leaf, const uint64_t* k
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<COUNT>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
                      keys, bounds, drop, n, walk_cfg(n), e2, nullptr, nullptr, nullptr,
-                     nullptr, nullptr, count, err);
+                     nullptr, nullptr, count, nullptr, err);
+}
+
+void launch_count_pairs(const Node* nodes, const float4* leaf, const uint64_t* keys,
+                        const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
+                        int32_t min_pts, uint32_t* deg, uint8_t* is_core, uint32_t* err,
+                        int block, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_pairs<DEGREE>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
+                     keys, bounds, drop, n, walk_cfg(n), e2, nullptr, nullptr, nullptr,
+                     nullptr, nullptr, nullptr, deg, err);
+  hipLaunchKernelGGL(k_degree_flags, dim3((n + 255) / 256), dim3(256), 0, s, n, deg, min_pts,
+                     is_core);
 }
 
 }  // namespace dbx

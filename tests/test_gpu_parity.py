@@ -327,6 +327,19 @@ def test_random_clumpy_labels(ctx, seed, mp):
     np.testing.assert_array_equal(run(ctx, p, eps, mp), oracle.dbscan(p, eps, mp))
 
 
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("mp", [3, 5, 10, 40])
+def test_pair_count_core_flags(ctx, seed, mp):
+    """Core points found by pair traversal (DBSCAN_FLAG_PAIR_COUNT): the same
+    labels as the oracle, across sizes that span tiles and a ragged tail."""
+    rng = np.random.Generator(np.random.PCG64(100 + seed))
+    n = int(rng.integers(10, 70000))
+    p = clumpy(n, 100 + seed)
+    eps = F32(rng.uniform(0.004, 0.04))
+    np.testing.assert_array_equal(run(ctx, p, eps, mp, pair_count=True),
+                                  oracle.dbscan(p, eps, mp))
+
+
 @pytest.mark.parametrize("mp", [2, 5, 10])
 def test_clumps32k(ctx, mp):
     p = datagen.config_points("clumps32k")
@@ -389,6 +402,15 @@ def test_halo16m_minpts2_bit_exact(ctx, halo16m):
     np.testing.assert_array_equal(run(ctx, p, F32(0.2), 2), ref)
 
 
+def test_halo16m_pair_count_equals_walk_count(ctx, halo16m):
+    p, _ = halo16m
+    d = dev(p)
+    a = ctx.cluster(d, 0.2, 3).cpu().numpy()
+    b = ctx.cluster(d, 0.2, 3, pair_count=True).cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+    assert (a >= 0).any()
+
+
 def test_autotune_returns_options_that_keep_labels(ctx):
     p = clumpy(60000, 21)
     ref = oracle.dbscan(p, F32(0.01), 4)
@@ -396,5 +418,5 @@ def test_autotune_returns_options_that_keep_labels(ctx):
         best = ctx.autotune(dev(p), 0.01, 4, algorithm=algo)
         assert best["block_size"] in (64, 128, 256, 512) and best["ms"] > 0
         got = run(ctx, p, 0.01, 4, algorithm=algo, block_size=best["block_size"],
-                  dense_threshold=best["dense_threshold"])
+                  dense_threshold=best["dense_threshold"], pair_count=best["pair_count"])
         np.testing.assert_array_equal(got, ref)
