@@ -59,7 +59,7 @@ struct Layout {
   size_t keys_a, keys_b, vals_a, vals_b, leaf, nodes, parent, minlab, flag, bestcore, deg,
       pending;
   // DenseBox only (0 otherwise)
-  size_t cid, head, cell_start, cell_lo, cell_hi, cell_minorig, cell_dense, prim_count,
+  size_t cid, cell_start, cell_lo, cell_hi, cell_minorig, cell_dense, prim_count,
       prim_start, prims, pkey, scan1, scan2, scan_ctr, ncells, nprims;
   size_t set_e2, set_mp, set_th, grid;  // the one-set table of a plain DenseBox call
   uint32_t pending_entries;
@@ -93,7 +93,6 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
   L.pending = take(size_t(L.pending_entries) * 16);
   if (densebox) {
     L.cid = take(size_t(n) * 4);
-    L.head = take(size_t(n) * 4);
     L.cell_start = take((size_t(n) + 1) * 4);
     L.cell_lo = take(size_t(n) * 16);
     L.cell_hi = take(size_t(n) * 16);
@@ -475,8 +474,7 @@ int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_
   uint32_t* nprims = at<uint32_t>(c, L.nprims);
   uint32_t* cell_start = at<uint32_t>(c, L.cell_start);
   uint32_t* cid = at<uint32_t>(c, L.cid);
-  launch_cells(keys, n, at<uint32_t>(c, L.head), cid, ncells, cell_start,
-               at<uint32_t>(c, L.scan1), scan_ctr, status, s);
+  launch_cells(keys, n, cid, ncells, cell_start, at<uint32_t>(c, L.scan1), scan_ctr, status, s);
   unsigned long long* cell_minorig = at<unsigned long long>(c, L.cell_minorig);
   float4* cell_lo = at<float4>(c, L.cell_lo);
   float4* cell_hi = at<float4>(c, L.cell_hi);

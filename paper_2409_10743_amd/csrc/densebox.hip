@@ -69,16 +69,38 @@ __global__ __launch_bounds__(256) void k_cell_keys(const float* __restrict__ pts
     if (sh[t]) atomicAdd(&hist[t], sh[t]);
 }
 
-__global__ __launch_bounds__(256) void k_cell_heads(const uint64_t* __restrict__ keys, uint32_t n,
-                                                   uint32_t* __restrict__ head) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) head[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
-}
+// What the scan below sums and where it puts the result.
+// A plain exclusive prefix sum of u32 values:
+struct ValueScan {
+  const uint32_t* in;
+  uint32_t* out;
+  __device__ uint32_t load(uint32_t i) const { return in[i]; }
+  __device__ void store(uint32_t i, uint32_t excl, uint32_t) const { out[i] = excl; }
+  __device__ void finish(uint32_t, uint32_t) const {}
+};
+// The cells of the sorted cell keys: point i starts a cell where its key
+// differs from point i-1's; cid[i] = its cell, cell_start[c] = the cell's
+// first point, cell_start[ncells] = n (run heads, their scan and the starts
+// in one pass).
+struct CellScan {
+  const uint64_t* keys;
+  uint32_t* cid;
+  uint32_t* cell_start;
+  __device__ uint32_t load(uint32_t i) const {
+    return (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+  }
+  __device__ void store(uint32_t i, uint32_t excl, uint32_t head) const {
+    const uint32_t c = excl + head - 1;  // heads before i, plus its own
+    cid[i] = c;
+    if (head) cell_start[c] = i;
+  }
+  __device__ void finish(uint32_t total, uint32_t n) const { cell_start[total] = n; }
+};
 
-// Exclusive prefix sum of u32 with the total, one pass: tiles take ids from
-// a counter and find their offset by decoupled look-back (bounded waits).
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan(const uint32_t* __restrict__ in,
-                                                      uint32_t* __restrict__ out, uint32_t n,
+// Exclusive prefix sum with the total, one pass: tiles take ids from a
+// counter and find their offset by decoupled look-back (bounded waits).
+template <class P>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan(P sc, uint32_t n,
                                                       uint32_t* __restrict__ total,
                                                       uint32_t* __restrict__ status,
                                                       uint32_t* __restrict__ tile_ctr,
@@ -93,7 +115,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(const uint32_t* __restric
   uint32_t sum = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    v[k] = base + k < n ? in[base + k] : 0u;
+    v[k] = base + k < n ? sc.load(base + k) : 0u;
     sum += v[k];
   }
   // block exclusive scan of the thread sums
@@ -136,30 +158,18 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan(const uint32_t* __restric
       st_agent(st, ST_INC | ((excl + agg) & ST_VAL));
     }
     s_prefix = excl;
-    if ((tile + 1) * uint32_t(SCAN_TILE) >= n) *total = excl + agg;
+    if ((tile + 1) * uint32_t(SCAN_TILE) >= n) {
+      *total = excl + agg;
+      sc.finish(excl + agg, n);
+    }
   }
   __syncthreads();
   uint32_t run = s_prefix + texcl;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    if (base + k < n) out[base + k] = run;
+    if (base + k < n) sc.store(base + k, run, v[k]);
     run += v[k];
   }
-}
-
-// cid[i] = cell of sorted point i; cell_start[c] = first point of cell c,
-// cell_start[ncells] = n.
-__global__ __launch_bounds__(256) void k_cell_start(const uint32_t* __restrict__ head,
-                                                   uint32_t* __restrict__ cid, uint32_t n,
-                                                   const uint32_t* __restrict__ ncells,
-                                                   uint32_t* __restrict__ cell_start) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t h = head[i];
-  const uint32_t c = cid[i] + h - 1;  // exclusive count of heads before i, plus own
-  cid[i] = c;
-  if (h) cell_start[c] = i;
-  if (i == 0) cell_start[*ncells] = n;
 }
 
 // Per cell: box, denseness (its set's eps and threshold), smallest (input
@@ -176,6 +186,13 @@ __global__ __launch_bounds__(256) void k_cell_stats(
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
     if (c >= ncells) { prim_count[c] = 0; continue; }
     const uint32_t b = cell_start[c], e = cell_start[c + 1];
+    const uint32_t cnt = e - b;
+    const uint32_t set = S.shift < 64 ? uint32_t(keys[b] >> S.shift) : 0u;
+    if (int64_t(cnt) < S.thresh[set]) {  // too few points: its points are primitives
+      cell_dense[c] = 0;
+      prim_count[c] = cnt;
+      continue;
+    }
     float4 lo = pts[b], hi = lo;
     unsigned long long mo = (static_cast<unsigned long long>(perm[b]) << 32) | b;
     for (uint32_t i = b + 1; i < e; ++i) {
@@ -185,10 +202,7 @@ __global__ __launch_bounds__(256) void k_cell_stats(
       const unsigned long long o = (static_cast<unsigned long long>(perm[i]) << 32) | i;
       mo = o < mo ? o : mo;
     }
-    const uint32_t cnt = e - b;
-    const uint32_t set = S.shift < 64 ? uint32_t(keys[b] >> S.shift) : 0u;
-    const bool dense = int64_t(cnt) >= S.thresh[set] &&
-                       sq_dist(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z) <= S.e2[set];
+    const bool dense = sq_dist(lo.x, lo.y, lo.z, hi.x, hi.y, hi.z) <= S.e2[set];
     cell_lo[c] = lo;
     cell_hi[c] = hi;
     cell_minorig[c] = mo;
@@ -676,18 +690,18 @@ void launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total,
                  uint32_t* status, uint32_t* tile_ctr, uint32_t* err, hipStream_t s) {
   if (n == 0) return;
   const uint32_t tiles = uint32_t(scan_status_words(n));
-  hipLaunchKernelGGL(k_scan, dim3(tiles), dim3(SCAN_THREADS), 0, s, in, out, n, total, status,
-                     tile_ctr, err);
+  hipLaunchKernelGGL(k_scan<ValueScan>, dim3(tiles), dim3(SCAN_THREADS), 0, s,
+                     ValueScan{in, out}, n, total, status, tile_ctr, err);
 }
 
-void launch_cells(const uint64_t* sorted_keys, uint32_t n, uint32_t* head, uint32_t* cid,
-                  uint32_t* ncells, uint32_t* cell_start, uint32_t* scan_status,
-                  uint32_t* scan_ctr, uint32_t* err, hipStream_t s) {
+void launch_cells(const uint64_t* sorted_keys, uint32_t n, uint32_t* cid, uint32_t* ncells,
+                  uint32_t* cell_start, uint32_t* scan_status, uint32_t* scan_ctr, uint32_t* err,
+                  hipStream_t s) {
   if (n == 0) return;
-  const uint32_t g = (n + 255) / 256;
-  hipLaunchKernelGGL(k_cell_heads, dim3(g), dim3(256), 0, s, sorted_keys, n, head);
-  launch_scan(head, cid, n, ncells, scan_status, scan_ctr, err, s);
-  hipLaunchKernelGGL(k_cell_start, dim3(g), dim3(256), 0, s, head, cid, n, ncells, cell_start);
+  const uint32_t tiles = uint32_t(scan_status_words(n));
+  hipLaunchKernelGGL(k_scan<CellScan>, dim3(tiles), dim3(SCAN_THREADS), 0, s,
+                     CellScan{sorted_keys, cid, cell_start}, n, ncells, scan_status, scan_ctr,
+                     err);
 }
 
 void launch_cell_stats(const float4* pts, const uint32_t* perm, const uint64_t* keys, uint32_t n,

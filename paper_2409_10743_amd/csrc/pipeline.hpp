@@ -196,12 +196,14 @@ void launch_cell_keys(const float* pts, uint32_t n, const uint32_t* bounds, floa
 size_t scan_status_words(uint32_t n);
 void launch_scan(const uint32_t* in, uint32_t* out, uint32_t n, uint32_t* total,
                  uint32_t* status, uint32_t* tile_ctr, uint32_t* err, hipStream_t s);
-// Run heads of the sorted cell keys -> cid (cell of each sorted point),
-// *ncells, cell_start[0..ncells] (cell_start[ncells] = n).
-void launch_cells(const uint64_t* sorted_keys, uint32_t n, uint32_t* head, uint32_t* cid,
-                  uint32_t* ncells, uint32_t* cell_start, uint32_t* scan_status,
-                  uint32_t* scan_ctr, uint32_t* err, hipStream_t s);
-// keys: the sorted cell keys (their set ids pick each cell's eps and T)
+// The cells of the sorted cell keys, in one scan: cid (cell of each sorted
+// point), *ncells, cell_start[0..ncells] (cell_start[ncells] = n).
+void launch_cells(const uint64_t* sorted_keys, uint32_t n, uint32_t* cid, uint32_t* ncells,
+                  uint32_t* cell_start, uint32_t* scan_status, uint32_t* scan_ctr, uint32_t* err,
+                  hipStream_t s);
+// keys: the sorted cell keys (their set ids pick each cell's eps and T).
+// Box and smallest index are computed, and needed, for cells with at least
+// T points only.
 void launch_cell_stats(const float4* pts, const uint32_t* perm, const uint64_t* keys, uint32_t n,
                        const uint32_t* ncells, const uint32_t* cell_start, const DbSets& sets,
                        float4* cell_lo, float4* cell_hi, unsigned long long* cell_minorig,
