@@ -150,9 +150,11 @@ int dbscan_sort_passes(const dbscan_ctx* ctx);
  * 2*minPts, 4*minPts), time each (best of two after a warm-up, HIP events on
  * `stream`) and return the fastest in *best (its time in *best_ms).  The
  * candidates cannot change the labels, which end in `labels` (device).
- * The batched tuner tries both algorithms: FDBSCAN at each workgroup size,
- * and DenseBox at each workgroup size with thresholds 0 (each set's minPts),
- * 2 and 4 times the largest minPts. */
+ * For FDBSCAN with min_pts > 2 each size is also tried with
+ * DBSCAN_FLAG_PAIR_COUNT (returned in best->flags).  The batched tuner tries
+ * both algorithms: FDBSCAN at each workgroup size, and DenseBox at each
+ * workgroup size with thresholds 0 (each set's minPts), 2 and 4 times the
+ * largest minPts. */
 int dbscan_autotune(dbscan_ctx* ctx, const float* points, int64_t n, float eps,
                     int32_t min_pts, int32_t algorithm, int32_t* labels,
                     dbscan_options* best, float* best_ms, void* stream);
