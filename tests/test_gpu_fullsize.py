@@ -31,11 +31,12 @@ def canonical_form(lab):
     assert (v >= lab[v]).all()
 
 
-@pytest.mark.parametrize("algo,mp", [("fdbscan", 2), ("fdbscan", 10), ("densebox", 2)])
-def test_halo134m(field, algo, mp):
+@pytest.mark.parametrize("algo,mp,pc", [("fdbscan", 2, False), ("fdbscan", 10, False),
+                                        ("fdbscan", 10, True), ("densebox", 2, False)])
+def test_halo134m(field, algo, mp, pc):
     p, d = field
     ctx = dbx.Context(0)
-    lab = ctx.cluster(d, 0.2, mp, algorithm=algo).cpu().numpy()
+    lab = ctx.cluster(d, 0.2, mp, algorithm=algo, pair_count=pc).cpu().numpy()
     ctx.close()
     canonical_form(lab)
     checked = 0
