@@ -64,7 +64,7 @@ struct Layout {
   size_t set_e2, set_mp, set_th, grid;  // the one-set table of a plain DenseBox call
   uint32_t pending_entries;
   size_t zero;        // start of the region zeroed by k_prep
-  size_t hist, tile_ctr, status, count, sort_status;
+  size_t hist, tile_ctr, status, count, walkq, sort_status;
   size_t zero_words;  // 32-bit words from `zero`
   size_t bounds, drop, root;
   size_t total;
@@ -116,6 +116,7 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
   L.tile_ctr = take(SORT_PASSES * 4);
   L.status = take(4);
   L.count = take(4 * 8);  // pairs, internal-node visits, descents, leaf tests
+  L.walkq = take(4 * 8 * 4);  // chunk counters of up to four persistent walks
   if (densebox) {
     L.scan_ctr = take(8);
     L.ncells = take(8);  // ncells and nprims side by side: read back together
@@ -499,9 +500,10 @@ int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_
   mark(c, timing, PH_BUILD_LEVELS, s);
   const DbTables T{spts, cell_start, perm, cell_minorig, cell_lo, cell_hi, parent, flag,
                    bestcore};
-  if (any_core) launch_count_db(nodes, prims, pkey, n, nprims, S, T, status, block, s);
+  uint32_t* walkq = at<uint32_t>(c, L.walkq);
+  if (any_core) launch_count_db(nodes, prims, pkey, n, nprims, S, T, walkq, status, block, s);
   mark(c, timing, PH_COUNT, s);
-  launch_pairs_db(nodes, prims, pkey, n, nprims, S, T, status, block, s);
+  launch_pairs_db(nodes, prims, pkey, n, nprims, S, T, walkq + 8, status, block, s);
   mark(c, timing, PH_PAIRS, s);
   if (d_off) {
     launch_final_sets(n, keys, S.shift, S.minpts, d_off, flag, bestcore, perm, parent, minlab,
@@ -702,11 +704,11 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
                  timing ? build_mark : nullptr, &sm);
     mark(c, timing, PH_BUILD_LEVELS, gs);
     if (any_core)
-      launch_count_sets(nodes, leaf, n, keys, set_shift, d_root, d_e2, d_mp, d_grid, flag, status,
-                        block, gs);
+      launch_count_sets(nodes, leaf, n, keys, set_shift, d_root, d_e2, d_mp, d_grid, flag,
+                        at<uint32_t>(c, L.walkq), status, block, gs);
     mark(c, timing, PH_COUNT, gs);
     launch_pairs_sets(nodes, leaf, n, keys, set_shift, d_e2, d_mp, d_grid, perm, parent, flag,
-                      bestcore, status, block, gs);
+                      bestcore, at<uint32_t>(c, L.walkq) + 8, status, block, gs);
     mark(c, timing, PH_PAIRS, gs);
     launch_final_sets(n, keys, set_shift, d_mp, d_off, flag, bestcore, perm, parent, minlab,
                       labels, gs);

@@ -131,6 +131,7 @@ struct CountSets {
   }
 };
 
+template <bool PERSIST>
 __global__ void k_count_sets(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
                              uint32_t n, WalkCfg wc,
                              const uint64_t* __restrict__ keys,
@@ -140,7 +141,7 @@ __global__ void k_count_sets(const Node* __restrict__ nodes, const float4* __res
                              const MortonGrid* __restrict__ grids,
                              uint8_t* __restrict__ flag, uint32_t* __restrict__ err) {
   CountSets v{keys, set_shift, set_root, set_e2, set_minpts, flag, grids, 0.f, 0, 0, 0};
-  wave_walks(nodes, leaf, keys, n, wc, v, err);
+  wave_walks<decltype(v), PERSIST>(nodes, leaf, keys, n, wc, v, err);
 }
 
 // Pair traversal; each lane runs the minPts <= 2 or the minPts > 2 rule of
@@ -193,6 +194,7 @@ struct PairSets {
   }
 };
 
+template <bool PERSIST>
 __global__ void k_pairs_sets(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
                              uint32_t n, WalkCfg wc,
                              const uint64_t* __restrict__ keys,
@@ -204,7 +206,7 @@ __global__ void k_pairs_sets(const Node* __restrict__ nodes, const float4* __res
                              unsigned long long* bestcore, uint32_t* err) {
   PairSets v{keys, set_shift, set_e2, set_minpts, perm, parent, flag, bestcore, grids,
              0.f, false, true, false, 0, 0};
-  wave_walks(nodes, leaf, keys, n, wc, v, err);
+  wave_walks<decltype(v), PERSIST>(nodes, leaf, keys, n, wc, v, err);
 }
 
 
@@ -267,6 +269,12 @@ __global__ __launch_bounds__(256) void k_final_border_labels_sets(
 
 }  // namespace
 
+// Which batched FDBSCAN walks run persistently by default (see walk.hpp):
+// neither; on the 4,096 sub-halo sets the static chunks were faster (count
+// 31 against 38 ms, pairs 147 against 155 ms).
+constexpr bool SETS_PERSIST_COUNT = false;
+constexpr bool SETS_PERSIST_PAIRS = false;
+
 void launch_set_morton(const float* pts, const int64_t* offsets, uint32_t num_sets, int bits,
                        int set_shift, const float* set_inv_h, uint64_t* keys, uint32_t* hist,
                        int32_t* set_root, MortonGrid* grids, uint32_t* status, hipStream_t s) {
@@ -278,23 +286,38 @@ void launch_set_morton(const float* pts, const int64_t* offsets, uint32_t num_se
 void launch_count_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
                        int set_shift, const int32_t* set_root, const float* set_e2,
                        const int32_t* set_minpts, const MortonGrid* grids, uint8_t* flag,
-                       uint32_t* err, int block, hipStream_t s) {
+                       uint32_t* queue, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_count_sets, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     n, walk_cfg(n), keys, set_shift, set_root, set_e2, set_minpts, grids, flag,
-                     err);
+  if (walk_persistent(SETS_PERSIST_COUNT)) {
+    const uint32_t grid = persistent_blocks(reinterpret_cast<const void*>(&k_count_sets<true>),
+                                            block, 0, walk_grid(n, block));
+    hipLaunchKernelGGL(k_count_sets<true>, dim3(grid), dim3(block), 0, s, nodes, leaf, n,
+                       walk_cfg(n, queue), keys, set_shift, set_root, set_e2, set_minpts, grids,
+                       flag, err);
+  } else {
+    hipLaunchKernelGGL(k_count_sets<false>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes,
+                       leaf, n, walk_cfg(n), keys, set_shift, set_root, set_e2, set_minpts, grids,
+                       flag, err);
+  }
 }
 
 void launch_pairs_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
                        int set_shift, const float* set_e2, const int32_t* set_minpts,
                        const MortonGrid* grids, const uint32_t* perm, int32_t* parent,
-                       uint8_t* flag, unsigned long long* bestcore, uint32_t* err, int block,
-                       hipStream_t s) {
+                       uint8_t* flag, unsigned long long* bestcore, uint32_t* queue,
+                       uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_pairs_sets, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
-                     n, walk_cfg(n), keys, set_shift, set_e2, set_minpts, grids, perm, parent,
-                     flag,
-                     bestcore, err);
+  if (walk_persistent(SETS_PERSIST_PAIRS)) {
+    const uint32_t grid = persistent_blocks(reinterpret_cast<const void*>(&k_pairs_sets<true>),
+                                            block, 0, walk_grid(n, block));
+    hipLaunchKernelGGL(k_pairs_sets<true>, dim3(grid), dim3(block), 0, s, nodes, leaf, n,
+                       walk_cfg(n, queue), keys, set_shift, set_e2, set_minpts, grids, perm,
+                       parent, flag, bestcore, err);
+  } else {
+    hipLaunchKernelGGL(k_pairs_sets<false>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes,
+                       leaf, n, walk_cfg(n), keys, set_shift, set_e2, set_minpts, grids, perm,
+                       parent, flag, bestcore, err);
+  }
 }
 
 void launch_final_sets(uint32_t n, const uint64_t* keys, int set_shift, const int32_t* set_minpts,

@@ -220,12 +220,15 @@ void launch_one_set(float e2, int32_t min_pts, int32_t thresh, float* e2o, int32
                     int32_t* tho, hipStream_t s);
 // block: a multiple of 64, at most 1024; the primitive count is *np_dev, at
 // most np_bound (which sizes the launch)
+// queue: 8 zeroed counters of the persistent walk (walk.hpp)
 void launch_count_db(const Node* nodes, const Node* prims, const uint64_t* pkey,
                      uint32_t np_bound, const uint32_t* np_dev, const DbSets& sets,
-                     const DbTables& t, uint32_t* err, int block, hipStream_t s);
+                     const DbTables& t, uint32_t* queue, uint32_t* err, int block,
+                     hipStream_t s);
 void launch_pairs_db(const Node* nodes, const Node* prims, const uint64_t* pkey,
                      uint32_t np_bound, const uint32_t* np_dev, const DbSets& sets,
-                     const DbTables& t, uint32_t* err, int block, hipStream_t s);
+                     const DbTables& t, uint32_t* queue, uint32_t* err, int block,
+                     hipStream_t s);
 
 // ---- batched sets (batched.hip) -----------------------------------------------
 // Keys of every set: (set id << set_shift) | Morton code with `bits` bits per
@@ -236,15 +239,16 @@ void launch_pairs_db(const Node* nodes, const Node* prims, const uint64_t* pkey,
 void launch_set_morton(const float* pts, const int64_t* offsets, uint32_t num_sets, int bits,
                        int set_shift, const float* set_inv_h, uint64_t* keys, uint32_t* hist,
                        int32_t* set_root, MortonGrid* grids, uint32_t* status, hipStream_t s);
+// queue: 8 zeroed counters of the persistent walk (walk.hpp)
 void launch_count_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
                        int set_shift, const int32_t* set_root, const float* set_e2,
                        const int32_t* set_minpts, const MortonGrid* grids, uint8_t* flag,
-                       uint32_t* err, int block, hipStream_t s);
+                       uint32_t* queue, uint32_t* err, int block, hipStream_t s);
 void launch_pairs_sets(const Node* nodes, const float4* leaf, uint32_t n, const uint64_t* keys,
                        int set_shift, const float* set_e2, const int32_t* set_minpts,
                        const MortonGrid* grids, const uint32_t* perm, int32_t* parent,
-                       uint8_t* flag, unsigned long long* bestcore, uint32_t* err, int block,
-                       hipStream_t s);
+                       uint8_t* flag, unsigned long long* bestcore, uint32_t* queue,
+                       uint32_t* err, int block, hipStream_t s);
 // labels are set-local: smallest input index in the cluster minus the
 // set's offset (labels -1 and, with bestcore, minlab INT_MAX beforehand;
 // bestcore null: no set has minPts > 2)

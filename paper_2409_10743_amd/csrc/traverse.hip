@@ -16,6 +16,9 @@
 //    points' neighbour counts.  No early exit, but no walk from the root
 //    either: cheaper where points have few neighbours.
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "walk.hpp"
 
@@ -164,6 +167,39 @@ uint32_t walk_queries_per_lane(uint32_t n) {
   }();
   if (forced) return uint32_t(forced);
   return n >= (1u << 23) ? 4u : n >= (1u << 22) ? 2u : 1u;
+}
+
+uint32_t persistent_blocks(const void* kernel, int block, size_t lds, uint32_t needed) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, uint32_t> cache;  // per kernel and block size
+  uint32_t fit = 0;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find({kernel, block});
+    if (it != cache.end()) fit = it->second;
+  }
+  if (fit == 0) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess ||
+        cus < 1 || per_cu < 1) {
+      (void)hipGetLastError();
+      return (needed + 7) / 8 * 8;  // every chunk group its own block: still correct
+    }
+    fit = (uint32_t(cus) * uint32_t(per_cu) + 7) / 8 * 8;
+    std::lock_guard<std::mutex> g(mu);
+    cache[{kernel, block}] = fit;
+  }
+  return std::max(8u, std::min(fit, (needed + 7) / 8 * 8));
+}
+
+bool walk_persistent(bool dflt) {
+  static const int forced = [] {
+    const char* e = std::getenv("DBX_WALK_PERSIST");
+    return e && (e[0] == '0' || e[0] == '1') && e[1] == 0 ? e[0] - '0' : -1;
+  }();
+  return forced < 0 ? dflt : forced == 1;
 }
 
 uint32_t walk_refill_at() {

@@ -86,19 +86,71 @@ uint32_t walk_refill_at();
 struct WalkCfg {
   uint32_t chunk;      // queries per wave
   uint32_t refill_at;  // refill once fewer lanes than this are walking
+  uint32_t* queue;     // persistent walks: 8 zeroed chunk counters; null: static chunks
 };
-inline WalkCfg walk_cfg(uint32_t n) { return WalkCfg{walk_chunk_size(n), walk_refill_at()}; }
+inline WalkCfg walk_cfg(uint32_t n, uint32_t* queue = nullptr) {
+  return WalkCfg{walk_chunk_size(n), walk_refill_at(), queue};
+}
+
+// Persistent walks (PERSIST, with WalkCfg::queue): the grid holds only as
+// many waves as the GPU runs at once, and every wave takes spans of
+// WALK_GRAB chunks, one after another, from eight counters, one per XCD,
+// each handing out a contiguous eighth of the spans.  A wave starts with its own XCD's counter (blockIdx % 8: blocks
+// are dealt to the XCDs in turn), so nearby queries still share an L2, and
+// takes the other counters' leftovers once its own is drained.  Query costs
+// that differ a lot (sets of very different sizes and densities) are then
+// balanced up to the end of the launch instead of per block.  Every wave
+// leaves once all eight are drained.  All lanes of the wave call it.
+// chunks a wave takes per counter increment: one (spans of 8 chunks made the
+// batched walks up to 3.5x slower: a span over a dense sub-clump kept one
+// wave busy long after the rest had finished)
+constexpr uint32_t WALK_GRAB = 1;
+__device__ __forceinline__ bool next_chunk(const WalkCfg& wc, uint32_t n, uint32_t& home,
+                                           uint32_t& c0, uint32_t& c1) {
+  const uint32_t span = wc.chunk * WALK_GRAB;  // a wave walks this many queries per take
+  const uint32_t total = (n + span - 1) / span;
+  for (uint32_t t = 0; t < 8; ++t) {
+    const uint32_t x = (home + t) & 7u;
+    const uint32_t lo = uint32_t(uint64_t(total) * x / 8);
+    const uint32_t hi = uint32_t(uint64_t(total) * (x + 1) / 8);
+    if (lo >= hi) continue;
+    uint32_t id = 0;
+    if ((threadIdx.x & 63) == 0) id = atomicAdd(wc.queue + x, 1u);
+    id = __builtin_amdgcn_readfirstlane(id);
+    if (id < hi - lo) {
+      home = x;
+      const uint64_t b = uint64_t(lo + id) * span;
+      c0 = uint32_t(b);
+      c1 = uint32_t(b + span < n ? b + span : n);
+      return true;
+    }
+  }
+  return false;
+}
+
+// Blocks of a persistent walk launch: as many as the GPU holds at once
+// (a multiple of 8), at most `needed`.
+uint32_t persistent_blocks(const void* kernel, int block, size_t lds, uint32_t needed);
+// Whether a launch walks persistently: `dflt`, unless the environment
+// variable DBX_WALK_PERSIST (0 or 1) overrides it for tuning runs.
+bool walk_persistent(bool dflt);
 
 // `leaf` must have one readable float4 past leaf n-1 (a leaf step reads 32
 // bytes, like a node step, and ignores the second half).
 // keys: the sorted Morton codes (read only when V::kBounded).
-template <class V>
+template <class V, bool PERSIST = false>
 __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
                                            const float4* __restrict__ leaf,
                                            const uint64_t* __restrict__ keys, uint32_t n,
                                            WalkCfg wc, V& v, uint32_t* err) {
   uint32_t c0, c1;
-  walk_chunk(n, wc.chunk, c0, c1);
+  uint32_t home = blockIdx.x & 7u;
+  bool drained = !PERSIST;  // no span left to take (static: the wave's one chunk)
+  if (PERSIST) {
+    if (!next_chunk(wc, n, home, c0, c1)) { c0 = c1 = n; drained = true; }
+  } else {
+    walk_chunk(n, wc.chunk, c0, c1);
+  }
   const uint32_t refill_at = wc.refill_at;
   const int lane = threadIdx.x & 63;
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -110,6 +162,10 @@ __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
   bool by_rope = false;  // node was reached through a rope: its number is its first leaf
   float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
   for (;;) {
+    if (PERSIST && head >= c1 && !drained) {  // the next span
+      if (next_chunk(wc, n, home, c0, c1)) head = c0;
+      else drained = true;
+    }
     // hand the chunk's next queries to the idle lanes
     const bool need = node == SENTINEL;
     const uint64_t m = __ballot(need);
@@ -128,7 +184,7 @@ __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
     const uint32_t h = head + uint32_t(__popcll(m));
     head = h < c1 ? h : c1;
     if (__ballot(node != SENTINEL) == 0) {
-      if (head >= c1) break;
+      if (head >= c1 && (!PERSIST || drained)) break;
       continue;  // every new walk was empty: hand out more
     }
     // walk; stop early to refill once enough lanes are idle (and there is
@@ -172,7 +228,7 @@ __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
         by_rope = !down;
       }
       const uint32_t busy = uint32_t(__popcll(__ballot(node != SENTINEL)));
-      if (busy == 0 || (head < c1 && busy < refill_at)) break;
+      if (busy == 0 || ((head < c1 || (PERSIST && !drained)) && busy < refill_at)) break;
     }
   }
   if (have) v.end(i);
