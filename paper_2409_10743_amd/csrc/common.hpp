@@ -195,24 +195,34 @@ __host__ __device__ inline float ord2f(uint32_t u) {
   return f;
 }
 
-// Low code bits a clustering call may drop (0, 8, 16 or 24: whole sort
-// passes).  The codes only shape the tree; the walks prune with exact boxes.
-// Codes stay fine enough that a grid cell is at most eps/2 wide on every
-// axis, so points that come to share a code lie within 0.87 eps of each
-// other: mutual neighbours, which the walks meet together anyway.  Bit b of
-// a code belongs to axis z, y, x for b % 3 = 0, 1, 2.  eps <= 0: none.
-__device__ inline int droppable_code_bits(const uint32_t* bounds, float eps) {
+// Low code bits a clustering call may drop (a multiple of 8 up to 40: whole
+// sort passes).  The codes only shape the tree; the walks prune with exact
+// boxes.  A drop is taken if the grid cells it leaves are
+//  * at most eps/2 wide on every axis: points that then share a code lie
+//    within 0.87 eps of each other, mutual neighbours that the walks meet
+//    together anyway; or
+//  * at most 2.5 eps wide and so small against the point density that the
+//    field holds at most 1/16 point per cell on average (n times a cell's
+//    share of the bounding box): codes are then nearly all distinct, and
+//    the tree over them is as good as over finer ones.
+// Bit b of a code belongs to axis z, y, x for b % 3 = 0, 1, 2.  eps <= 0:
+// none.
+__device__ inline int droppable_code_bits(const uint32_t* bounds, float eps, uint32_t n) {
   if (!(eps > 0.0f)) return 0;
   int best = 0;
-  for (int d = 8; d <= 24; d += 8) {
-    bool ok = true;
+  for (int d = 8; d <= 40; d += 8) {
+    bool fine = true, coarse = true;
+    double per_cell = double(n);
     for (int a = 0; a < 3; ++a) {  // x, y, z
       const int off = 2 - a;       // the axis' bit position within a triple
       const int dropped = d > off ? (d - off + 2) / 3 : 0;
+      const double share = ldexp(1.0, dropped - MORTON_BITS);  // cell / extent
       const double ext = double(ord2f(bounds[3 + a])) - double(ord2f(bounds[a]));
-      ok = ok && ext * ldexp(1.0, dropped - MORTON_BITS) <= 0.5 * double(eps);
+      fine = fine && ext * share <= 0.5 * double(eps);
+      coarse = coarse && ext * share <= 2.5 * double(eps);
+      if (ext > 0.0) per_cell *= share;
     }
-    if (ok) best = d;
+    if (fine || (coarse && per_cell <= 1.0 / 16.0)) best = d;
   }
   return best;
 }

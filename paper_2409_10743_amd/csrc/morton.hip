@@ -134,7 +134,7 @@ __device__ __forceinline__ void count_digits(uint32_t* sh, uint64_t code, int fi
 // Codes of all points plus the digit counts of every sort pass.  With a
 // 16-byte aligned point array a thread codes 4 points from 3 float4 loads
 // and writes their keys as two 16-byte stores.
-// The lowest `drop` code bits are cleared, drop = droppable_code_bits(eps)
+// The lowest `drop` code bits are cleared, drop = droppable_code_bits()
 // (all blocks compute the same value; block 0 also stores it for the sort
 // and the walks).  The sort then skips drop / 8 passes and always ends in
 // the first key buffer, so the codes go to the first buffer if it skips an
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
   for (int t = threadIdx.x; t < SORT_PASSES * RADIX; t += blockDim.x) sh[t] = 0;
   MortonGrid grid;
   grid.load(bounds);
-  const int drop = droppable_code_bits(bounds, eps);
+  const int drop = droppable_code_bits(bounds, eps, n);
   const uint64_t mask = ~0ull << drop;
   const int first = drop / 8;  // first sort pass that runs
   uint64_t* keys = (first % 2 == 0) ? keys_a : keys_b;

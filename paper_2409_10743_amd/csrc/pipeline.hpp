@@ -72,7 +72,7 @@ void launch_prep(uint32_t* zero_region, size_t zero_words, uint32_t* bounds, int
                  uint32_t pending_entries, hipStream_t s);
 void launch_bounds(const float* pts, uint32_t n, uint32_t* bounds,
                    uint32_t* status, hipStream_t s);
-// Codes with their lowest droppable_code_bits(bounds, eps) bits cleared
+// Codes with their lowest droppable_code_bits(bounds, eps, n) bits cleared
 // (eps <= 0: full 63-bit codes), written to keys_a if that drops an even
 // number of whole sort passes, else to keys_b; the bit count goes to
 // *drop_out (if not null) for launch_radix_sort_dropped and the walks.

@@ -213,12 +213,13 @@ def test_pair_traversal_finds_each_pair_once(ctx, n, eps):
     assert ctx.pair_count(dev(p), eps) == oracle.pair_count(p, F32(eps))
 
 
-@pytest.mark.parametrize("eps", [5e-6, 2e-5, 1e-4, 0.02])
-def test_code_bits_dropped_by_eps(ctx, eps):
-    """In a unit cube these radii let the clustering call clear 0, 8, 16 and
-    24 low code bits (0 to 3 skipped sort passes, odd and even): pairs and
-    labels must not change.  Near-copies of some points at several small
-    offsets give every radius some pairs."""
+@pytest.mark.parametrize("eps,passes", [(1e-6, 8), (5e-6, 7), (2e-5, 6), (1e-4, 5), (4e-4, 4),
+                                         (0.02, 3)])
+def test_code_bits_dropped_by_eps(ctx, eps, passes):
+    """In a unit cube these radii let the clustering call clear 0 to 40 low
+    code bits (0 to 5 skipped sort passes, odd and even; the last two only
+    by the sparse-cell rule): pairs and labels must not change.  Near-copies
+    of some points at several small offsets give every radius some pairs."""
     base = clumpy(40000, 123)
     rng = np.random.Generator(np.random.PCG64(5))
     extra = [base[rng.integers(0, 40000, 3000)] + rng.normal(0, d, (3000, 3)).astype(F32)
@@ -227,6 +228,7 @@ def test_code_bits_dropped_by_eps(ctx, eps):
     p = p[rng.permutation(p.shape[0])]
     assert ctx.pair_count(dev(p), eps) == oracle.pair_count(p, F32(eps))
     np.testing.assert_array_equal(run(ctx, p, eps, 2), oracle.dbscan(p, F32(eps), 2))
+    assert ctx.sort_passes() == passes
     np.testing.assert_array_equal(run(ctx, p, eps, 4), oracle.dbscan(p, F32(eps), 4))
 
 
