@@ -319,38 +319,75 @@ __device__ __forceinline__ void set_right(Ends& E, const uint64_t* __restrict__ 
 // Levels k > 1 of the build: thread = one of the nodes handed up by the
 // level-(k-1) frames inside this block's frame of `frame` leaves (two per
 // frame; 2 * 128 per 256-thread block, or, for the top launch, one block
-// over every leaf).  nodes and other are written and read by different
-// threads of the same launch, ordered by the exchange: no __restrict__ on
-// them.  The loads a step needs after its exchange (the sibling's box, the
-// keys at the node's new end) go out together.
+// over every leaf).
+//
+// Exchanges.  A split inside the frame is either half done already (one
+// child finished in an earlier launch: other[split] holds its bound, and
+// the thread finishing the other child here just reads it) or touched only
+// in this launch, where its slot lives in an LDS hash table (split -> bound)
+// instead of global memory: the exchange is an LDS atomic.  A first arrival
+// that no thread of this launch completes is carried to other[] when the
+// block ends, for a later level.  The values a step reads from other[] (at
+// both candidate parent splits of its node), the sibling's box and the keys
+// around the node's new end are loaded in one batch after each exchange, so
+// a step costs one round trip to memory.  nodes is written and read by
+// different threads of the same launch, ordered by the exchange: no
+// __restrict__ on it.
+constexpr uint32_t LEVEL_TAB_FACTOR = 4;  // table slots per thread (load <= 1/2)
+
+__device__ __forceinline__ int32_t tab_slot(int32_t* s_key, uint32_t tab_log2, int32_t split) {
+  const uint32_t m = (1u << tab_log2) - 1u;
+  uint32_t h = (uint32_t(split) * 2654435761u) >> (32 - tab_log2);
+  for (uint32_t t = 0; t <= m; ++t) {
+    const int32_t k = atomicCAS(s_key + h, -1, split);
+    if (k == -1 || k == split) return int32_t(h);
+    h = (h + 1) & m;
+  }
+  return -1;  // full: cannot happen at load 1/2
+}
+
 template <class Leaves>
 __global__ __launch_bounds__(1024) void k_build_level(
     const uint64_t* __restrict__ keys, Leaves lv, uint32_t n_bound,
-    const uint32_t* __restrict__ n_dev, uint64_t frame, uint32_t entries, int set_shift,
-    Node* nodes, int32_t* other, int32_t* set_root, const int4* __restrict__ pend_in,
-    int4* __restrict__ pend_out, uint32_t* err) {
+    const uint32_t* __restrict__ n_dev, uint64_t frame, uint32_t entries, uint32_t tab_log2,
+    int set_shift, Node* nodes, int32_t* __restrict__ other, int32_t* set_root,
+    const int4* __restrict__ pend_in, int4* __restrict__ pend_out, uint32_t* err) {
+  extern __shared__ int32_t s_tab[];  // split keys, then their bounds
+  const uint32_t tab = 1u << tab_log2;
+  int32_t* s_key = s_tab;
+  int32_t* s_val = s_tab + tab;
+  for (uint32_t h = threadIdx.x; h < tab; h += blockDim.x) {
+    s_key[h] = -1;
+    s_val[h] = -1;
+  }
+  __syncthreads();
   const uint32_t n = n_dev ? min(*n_dev, n_bound) : n_bound;
   const int32_t last = int32_t(n) - 1;
   const int64_t f0 = int64_t(blockIdx.x) * int64_t(frame);
   const int64_t f1 = min(f0 + int64_t(frame), int64_t(n));
   const uint64_t mask = set_mask_of(set_shift);
   const size_t slot = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (slot >= entries) return;
-  const int4 e = pend_in[slot];
+  int4 e = make_int4(SENTINEL, 0, 0, 0);
+  if (slot < entries) e = pend_in[slot];
   int32_t ref = e.x, l = e.y, r = e.z, g = -1;
-  if (ref == SENTINEL) return;
-  float4 lo, hi;
-  if (is_leaf(ref)) {
-    lv.load(leaf_index(ref), lo, hi);
-  } else {
-    const float4* q = reinterpret_cast<const float4*>(nodes + ref);
-    lo = q[0];
-    hi = q[1];
+  bool live = ref != SENTINEL;  // no early return: every thread reaches the carry below
+  float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+  Ends E{};
+  int32_t o_r = -1, o_l = -1;  // other[r], other[l - 1]: a half-done split there
+  if (live) {
+    if (is_leaf(ref)) {
+      lv.load(leaf_index(ref), lo, hi);
+    } else {
+      const float4* q = reinterpret_cast<const float4*>(nodes + ref);
+      lo = q[0];
+      hi = q[1];
+    }
+    set_left(E, keys, l, mask);
+    set_right(E, keys, r, last, mask);
+    o_r = r < last ? other[r] : -1;
+    o_l = l > 0 ? other[l - 1] : -1;
   }
-  Ends E;
-  set_left(E, keys, l, mask);
-  set_right(E, keys, r, last, mask);
-  for (;;) {
+  while (live) {
     const bool is_left = left_side(l, r, last, E.dr, E.dl);
     if (g >= 0) {  // finished in this launch: write it under its number
       ref = is_left ? r : l;
@@ -361,20 +398,30 @@ __global__ __launch_bounds__(1024) void k_build_level(
     const int32_t par = is_left ? r : l - 1;
     if (par < f0 || par > f1 - 2) {  // the split is a frame edge: to the next level
       pend_out[size_t(blockIdx.x) * 2 + (is_left ? 1 : 0)] = make_int4(ref, l, r, 0);
-      return;
+      break;
     }
-    const int32_t bound = __hip_atomic_exchange(other + par, is_left ? l : r, __ATOMIC_ACQ_REL,
-                                                __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (bound < 0) return;  // first arrival
+    int32_t bound = is_left ? o_r : o_l;  // the other child finished in an earlier launch
+    if (bound < 0) {
+      const int32_t h = tab_slot(s_key, tab_log2, par);
+      if (h < 0) {
+        atomicOr(err, STATUS_TREE);
+        break;
+      }
+      bound = __hip_atomic_exchange(s_val + h, is_left ? l : r, __ATOMIC_ACQ_REL,
+                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (bound < 0) break;  // first arrival: the sibling finishes the parent (or later)
+      s_val[h] = -2;         // both children met here: nothing to carry on
+    }
     if (is_left) r = bound;
     else l = bound;
     const int32_t sl = is_left ? par + 1 : l, sr = is_left ? r : par;
     if (sl < 0 || sr > last || sl > sr || l > par || par >= r) {
       atomicOr(err, STATUS_TREE);
-      return;
+      break;
     }
-    // the sibling's box and the keys around the new end, loaded together
-    // (no branch between the loads: a leaf is read as 32 bytes too)
+    // the sibling's box, the keys around the new end and other[] at the new
+    // node's candidate parent splits, loaded together (no branch between
+    // the loads: a leaf is read as 32 bytes too)
     const bool sleaf = sl == sr;
     const float4* sp =
         sleaf ? lv.rec(sl) : reinterpret_cast<const float4*>(nodes + (is_left ? sl : sr));
@@ -382,6 +429,7 @@ __global__ __launch_bounds__(1024) void k_build_level(
     const int32_t x = bound;
     const uint64_t k0 = keys[x > 0 ? x - 1 : 0], k1 = keys[x];
     const uint64_t k2 = keys[x < last ? x + 1 : last], k3 = keys[x + 1 < last ? x + 2 : last];
+    const int32_t ox = other[x < last ? x : 0], oxm = other[x > 0 ? x - 1 : 0];
     // both readings computed, one kept: selects, so that every load above
     // is issued before the first wait
     const uint64_t dr = x < last ? delta_of(k1, k2, x) : 0ull;
@@ -392,15 +440,23 @@ __global__ __launch_bounds__(1024) void k_build_level(
     E.dr = is_left ? dr : E.dr;  // the right end is now x
     E.dr1 = is_left ? dr1 : E.dr1;
     E.cr = is_left ? cr : E.cr;
+    o_r = is_left ? (x < last ? ox : -1) : o_r;
     E.dl = is_left ? E.dl : dl;  // the left end is now x
     E.cl = is_left ? E.cl : cl;
+    o_l = is_left ? o_l : (x > 0 ? oxm : -1);
     grow(lo, hi, sa, sleaf && Leaves::kPoint ? sa : sb);
     g = par;
     if (l == 0 && r == last) {  // the root, number 0
       write_node(nodes, 0, lo, hi, left_ref(l, g), SENTINEL);
       if (E.cl && E.cr) set_root[set_of(keys, l, set_shift)] = 0;
-      return;
+      break;
     }
+  }
+  // first arrivals nobody here completed: to other[], for a later level
+  __syncthreads();
+  for (uint32_t h = threadIdx.x; h < tab; h += blockDim.x) {
+    const int32_t k = s_key[h], v = s_val[h];
+    if (k >= 0 && v >= 0) other[k] = v;
   }
 }
 
@@ -430,6 +486,13 @@ size_t build_pending_entries(uint32_t n) {
 }
 
 namespace {
+// log2 of the exchange table slots of a level block of `threads` threads
+uint32_t level_tab_log2(uint32_t threads) {
+  uint32_t t = 6;
+  while ((1u << t) < threads * LEVEL_TAB_FACTOR) ++t;
+  return t;
+}
+
 // FrameLeaves: the leaves as level 1 reads and writes them; Leaves: as the
 // later levels read them
 // n: the leaf count, or with n_dev an upper bound of the count held in
@@ -455,14 +518,17 @@ void build_impl(const uint64_t* keys, int set_shift, FrameLeaves flv, Leaves lv,
       // few enough nodes left for one workgroup: it climbs them all to the
       // root (one frame over every leaf), in place of the remaining levels
       const uint32_t threads = (entries + 63) / 64 * 64;
-      hipLaunchKernelGGL(k_build_level<Leaves>, dim3(1), dim3(threads), 0, s, keys, lv, n, n_dev,
-                         uint64_t(n), entries, set_shift, nodes, other, root, pin, pout, err);
+      const uint32_t tl = level_tab_log2(threads);
+      hipLaunchKernelGGL(k_build_level<Leaves>, dim3(1), dim3(threads), size_t(8) << tl, s, keys,
+                         lv, n, n_dev, uint64_t(n), entries, tl, set_shift, nodes, other, root,
+                         pin, pout, err);
       if (after_level) after_level(arg, lv_i);
       return;
     } else {
-      hipLaunchKernelGGL(k_build_level<Leaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys, lv,
-                         n, n_dev, frame, uint32_t(frames) * BUILD_BLOCK, set_shift, nodes, other,
-                         root, pin, pout, err);
+      const uint32_t tl = level_tab_log2(BUILD_BLOCK);
+      hipLaunchKernelGGL(k_build_level<Leaves>, dim3(frames), dim3(BUILD_BLOCK), size_t(8) << tl, s,
+                         keys, lv, n, n_dev, frame, uint32_t(frames) * BUILD_BLOCK, tl, set_shift,
+                         nodes, other, root, pin, pout, err);
     }
     if (after_level) after_level(arg, lv_i);
     pin = pout;
