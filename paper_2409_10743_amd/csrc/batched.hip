@@ -214,29 +214,42 @@ __global__ void k_pairs_sets(const Node* __restrict__ nodes, const float4* __res
 // clustered point's label is the smallest input index of its cluster (the
 // root's, or a border point's, collected in minlab) minus the set's offset;
 // noise keeps the -1 the build wrote.
-__device__ __forceinline__ int32_t set_cluster_root(uint32_t i, int32_t mp,
-                                                    const uint8_t* __restrict__ flag,
-                                                    const unsigned long long* __restrict__ bestcore,
-                                                    int32_t* parent) {
-  if (mp <= 2) return (mp == 1 || flag[i]) ? uf_root_final(parent, int32_t(i)) : -1;
-  if (flag[i]) return uf_root_final(parent, int32_t(i));
+constexpr int FINAL_ITEMS = 4;  // points per thread, 256 apart: their chains climb together
+constexpr uint32_t FINAL_TILE = 256u * FINAL_ITEMS;
+
+// Where the chain of point i starts (-1: noise), by its set's minPts mp.
+__device__ __forceinline__ int32_t set_chain_start(uint32_t i, int32_t mp,
+                                                   const uint8_t* __restrict__ flag,
+                                                   const unsigned long long* __restrict__ bestcore) {
+  if (mp == 1 || flag[i]) return int32_t(i);
+  if (mp <= 2) return -1;
   const unsigned long long b = bestcore[i];
-  return b == ~0ull ? -1 : uf_root_final(parent, int32_t(uint32_t(b)));
+  return b == ~0ull ? -1 : int32_t(uint32_t(b));
 }
 
 // no set with minPts > 2: one pass
 __global__ __launch_bounds__(256) void k_final_labels_sets(
     uint32_t n, const uint64_t* __restrict__ keys, int set_shift,
     const int32_t* __restrict__ set_minpts, const int64_t* __restrict__ offsets,
-    const uint8_t* __restrict__ flag, const uint32_t* __restrict__ perm, int32_t* parent,
-    int32_t* __restrict__ labels) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint32_t set = uint32_t(keys[i] >> set_shift);
-  const int32_t r = set_cluster_root(i, set_minpts[set], flag, nullptr, parent);
-  if (r < 0) return;
-  const uint32_t o = perm[i];
-  if (o < n) labels[o] = int32_t(perm[r]) - int32_t(offsets[set]);
+    const uint8_t* __restrict__ flag, const uint32_t* __restrict__ perm,
+    const int32_t* __restrict__ parent, int32_t* __restrict__ labels) {
+  const uint32_t i0 = blockIdx.x * FINAL_TILE + threadIdx.x;
+  int32_t x[FINAL_ITEMS];
+  uint32_t set[FINAL_ITEMS];
+#pragma unroll
+  for (int k = 0; k < FINAL_ITEMS; ++k) {
+    const uint32_t i = i0 + 256u * k;
+    set[k] = i < n ? uint32_t(keys[i] >> set_shift) : 0u;
+    x[k] = i < n ? set_chain_start(i, set_minpts[set[k]], flag, nullptr) : -1;
+  }
+  uf_roots_final(parent, x);
+#pragma unroll
+  for (int k = 0; k < FINAL_ITEMS; ++k) {
+    const uint32_t i = i0 + 256u * k;
+    if (x[k] < 0) continue;
+    const uint32_t o = perm[i];
+    if (o < n) labels[o] = int32_t(perm[x[k]]) - int32_t(offsets[set[k]]);
+  }
 }
 
 // some set with minPts > 2: roots and border minima, then labels
@@ -245,12 +258,22 @@ __global__ __launch_bounds__(256) void k_final_roots_sets(
     const int32_t* __restrict__ set_minpts, const uint8_t* __restrict__ flag,
     const unsigned long long* __restrict__ bestcore, const uint32_t* __restrict__ perm,
     int32_t* parent, int32_t* __restrict__ minlab) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t mp = set_minpts[uint32_t(keys[i] >> set_shift)];
-  const int32_t r = set_cluster_root(i, mp, flag, bestcore, parent);
-  if (r >= 0 && mp > 2 && !flag[i]) atomicMin(minlab + r, int32_t(perm[i]));
-  parent[i] = r;
+  const uint32_t i0 = blockIdx.x * FINAL_TILE + threadIdx.x;
+  int32_t x[FINAL_ITEMS], mp[FINAL_ITEMS];
+#pragma unroll
+  for (int k = 0; k < FINAL_ITEMS; ++k) {
+    const uint32_t i = i0 + 256u * k;
+    mp[k] = i < n ? set_minpts[uint32_t(keys[i] >> set_shift)] : 0;
+    x[k] = i < n ? set_chain_start(i, mp[k], flag, bestcore) : -1;
+  }
+  uf_roots_final(parent, x);
+#pragma unroll
+  for (int k = 0; k < FINAL_ITEMS; ++k) {
+    const uint32_t i = i0 + 256u * k;
+    if (i >= n) continue;
+    if (x[k] >= 0 && mp[k] > 2 && !flag[i]) atomicMin(minlab + x[k], int32_t(perm[i]));
+    parent[i] = x[k];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_final_border_labels_sets(
@@ -258,13 +281,17 @@ __global__ __launch_bounds__(256) void k_final_border_labels_sets(
     const int64_t* __restrict__ offsets, const uint32_t* __restrict__ perm,
     const int32_t* __restrict__ root, const int32_t* __restrict__ minlab,
     int32_t* __restrict__ labels) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t r = root[i];
-  if (r < 0) return;  // noise: already -1
-  const uint32_t o = perm[i];
-  const int32_t base = int32_t(offsets[uint32_t(keys[i] >> set_shift)]);
-  if (o < n) labels[o] = min(int32_t(perm[r]), minlab[r]) - base;
+  const uint32_t i0 = blockIdx.x * FINAL_TILE + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < FINAL_ITEMS; ++k) {
+    const uint32_t i = i0 + 256u * k;
+    if (i >= n) break;
+    const int32_t r = root[i];
+    if (r < 0) continue;  // noise: already -1
+    const uint32_t o = perm[i];
+    const int32_t base = int32_t(offsets[uint32_t(keys[i] >> set_shift)]);
+    if (o < n) labels[o] = min(int32_t(perm[r]), minlab[r]) - base;
+  }
 }
 
 }  // namespace
@@ -325,7 +352,7 @@ void launch_final_sets(uint32_t n, const uint64_t* keys, int set_shift, const in
                        const unsigned long long* bestcore, const uint32_t* perm, int32_t* parent,
                        int32_t* minlab, int32_t* labels, hipStream_t s) {
   if (n == 0) return;
-  const uint32_t g = (n + 255) / 256;
+  const uint32_t g = (n + FINAL_TILE - 1) / FINAL_TILE;
   if (!bestcore) {  // no set with minPts > 2
     hipLaunchKernelGGL(k_final_labels_sets, dim3(g), dim3(256), 0, s, n, keys, set_shift,
                        set_minpts, offsets, flag, perm, parent, labels);

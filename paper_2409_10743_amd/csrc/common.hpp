@@ -140,17 +140,26 @@ __device__ __forceinline__ int32_t uf_union(int32_t* parent, const uint32_t* __r
   }
 }
 
-// Root of x once the forest no longer changes, compressing x's chain onto
-// it (plain loads and stores: every value written is the final root).
-__device__ __forceinline__ int32_t uf_root_final(int32_t* parent, int32_t x) {
-  int32_t r = x, p = parent[r];
-  while (p != r) { r = p; p = parent[r]; }
-  while (x != r) {
-    const int32_t nx = parent[x];
-    parent[x] = r;
-    x = nx;
+// Roots of K points at once, once the forest no longer changes: the K
+// chains climb in lockstep, so a thread keeps K independent loads in flight
+// (the chains are short; their latency, not bandwidth, bounds the final
+// pass).  x[k] < 0: no point there, left as is.  Plain loads, no writes.
+template <int K>
+__device__ __forceinline__ void uf_roots_final(const int32_t* parent, int32_t (&x)[K]) {
+  int32_t p[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) p[k] = x[k] >= 0 ? parent[x[k]] : x[k];
+  bool more = true;
+  while (more) {
+    more = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (p[k] != x[k]) {
+        x[k] = p[k];
+        p[k] = parent[x[k]];
+        more = true;
+      }
   }
-  return r;
 }
 
 // ---- Morton codes (section 4.2.2) ------------------------------------------

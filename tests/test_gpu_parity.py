@@ -50,7 +50,9 @@ SIZES = [1, 2, 3, 64, 255, 4095, 4096, 4097, 50001]
 
 # ---- stages ----------------------------------------------------------------
 
-@pytest.mark.parametrize("n", SIZES + [300007])
+# 5000011: several grid-stride rounds of the bounds pass (axis phase
+# carried across strides) and a scalar tail
+@pytest.mark.parametrize("n", SIZES + [300007, 5000011])
 def test_morton_codes_match_oracle(ctx, n):
     p = clumpy(n, n)
     got = ctx.morton_codes(dev(p)).cpu().numpy().view(np.uint64)
