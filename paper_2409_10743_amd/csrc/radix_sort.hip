@@ -24,6 +24,7 @@ constexpr uint32_t ST_AGG = 1u << 30;   // tile's own count published
 constexpr uint32_t ST_INC = 2u << 30;   // inclusive prefix published
 constexpr uint32_t ST_VAL = (1u << 30) - 1;
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
+constexpr int LOOKBACK = 4;  // predecessor tiles read per look-back round trip
 
 // Exclusive prefix sum of one value per thread over a 256-thread block.
 __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_tmp) {
@@ -168,19 +169,33 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
     st_agent(st, ST_INC | total);
   } else {
     st_agent(st, ST_AGG | total);
+    // look back LOOKBACK tiles per round trip: their words are read
+    // together, then taken in order up to the first inclusive prefix (done)
+    // or the first tile that has published nothing yet (read again from
+    // there after a pause)
     int32_t j = int32_t(tile) - 1;
     uint32_t spins = 0;
-    while (j >= 0) {
-      uint32_t v = ld_agent(status + size_t(j) * RADIX + d);
-      uint32_t f = v & ~ST_VAL;
-      if (f == 0) {
+    for (;;) {
+      uint32_t v[LOOKBACK];
+#pragma unroll
+      for (int q = 0; q < LOOKBACK; ++q)
+        v[q] = j - q >= 0 ? ld_agent(status + size_t(j - q) * RADIX + d) : ST_INC;
+      int taken = 0;
+      bool done = false;
+#pragma unroll
+      for (int q = 0; q < LOOKBACK; ++q) {
+        const uint32_t f = v[q] & ~ST_VAL;
+        if (done || f == 0 || taken < q) continue;  // stop at the first unpublished tile
+        excl += v[q] & ST_VAL;
+        done = f == ST_INC;
+        taken = q + 1;
+      }
+      if (done) break;
+      j -= taken;
+      if (taken < LOOKBACK) {
         if (++spins > SPIN_LIMIT) { atomicOr(err, STATUS_SORT_STALL); break; }
         __builtin_amdgcn_s_sleep(1);
-        continue;
       }
-      excl += v & ST_VAL;
-      if (f == ST_INC) break;
-      --j;
     }
     st_agent(st, ST_INC | ((excl + total) & ST_VAL));
   }
