@@ -82,6 +82,12 @@ typedef struct dbscan_options {
   int32_t block_size;       /* traversal workgroup size: 0 = default, else a
                                multiple of 64 in [64, 1024] */
   uint32_t flags;           /* DBSCAN_FLAG_* */
+  int32_t sort_tile;        /* keys per workgroup of each radix-sort pass:
+                               0 = default (4096), else 2048, 3072 or 4096;
+                               other values are EINVAL.  Smaller tiles put
+                               more workgroups on small inputs.  (The digit
+                               is always 8 bits: 256 look-back words per
+                               tile and pass.) */
 } dbscan_options;
 
 /* A context owns device scratch memory (grown on demand up to its budget and
@@ -148,7 +154,9 @@ int dbscan_sort_passes(const dbscan_ctx* ctx);
 /* Run the call on the given input once per candidate option set (traversal
  * workgroup sizes 64/128/256/512; for DenseBox also dense thresholds minPts,
  * 2*minPts, 4*minPts), time each (best of two after a warm-up, HIP events on
- * `stream`) and return the fastest in *best (its time in *best_ms).  The
+ * `stream`) and return the fastest in *best (its time in *best_ms); then
+ * time the fastest again with sort tiles of 3072 and 2048 keys and keep
+ * the sort tile that wins (sort_tile 0 when the default does).  The
  * candidates cannot change the labels, which end in `labels` (device).
  * For FDBSCAN with min_pts > 2 each size is also tried with
  * DBSCAN_FLAG_PAIR_COUNT (returned in best->flags).  The batched tuner tries

@@ -42,7 +42,8 @@ class DbscanError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("algorithm", ctypes.c_int32), ("dense_threshold", ctypes.c_int32),
-                ("block_size", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("block_size", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("sort_tile", ctypes.c_int32)]
 
 
 class _ServerOptions(ctypes.Structure):
@@ -174,18 +175,19 @@ class Context:
 
     def cluster(self, points, eps: float, min_pts: int, algorithm: str = "auto",
                 block_size: int = 0, dense_threshold: int = 0, timing: bool = False,
-                out=None, graph: bool = False, pair_count: bool = False):
+                out=None, graph: bool = False, pair_count: bool = False, sort_tile: int = 0):
         """``graph``: enqueue as a HIP graph replayed by later calls of the
         same shape (needs a non-default current stream; see
         DBSCAN_FLAG_GRAPH).  ``pair_count``: core points by pair traversal
-        (DBSCAN_FLAG_PAIR_COUNT)."""
+        (DBSCAN_FLAG_PAIR_COUNT).  ``sort_tile``: keys per radix-sort
+        workgroup (0 = 4096, 2048, 3072, 4096)."""
         torch = _torch()
         p = _points(points)
         n = p.shape[0]
         labels = out if out is not None else torch.empty(n, dtype=torch.int32, device=p.device)
         o = _Options(ALGO[algorithm], int(dense_threshold), int(block_size),
                      (FLAG_TIMING if timing else 0) | (FLAG_GRAPH if graph else 0) |
-                     (FLAG_PAIR_COUNT if pair_count else 0))
+                     (FLAG_PAIR_COUNT if pair_count else 0), int(sort_tile))
         _check(load_library().dbscan_cluster_ex(
             self.handle, ctypes.c_void_p(p.data_ptr()), n, ctypes.c_float(eps), int(min_pts),
             ctypes.c_void_p(labels.data_ptr()), _stream(p.device), ctypes.byref(o)))
@@ -193,7 +195,7 @@ class Context:
 
     def cluster_batched(self, points, offsets, eps, min_pts, block_size: int = 0,
                         timing: bool = False, out=None, graph: bool = False,
-                        algorithm: str = "auto", dense_threshold: int = 0):
+                        algorithm: str = "auto", dense_threshold: int = 0, sort_tile: int = 0):
         """Cluster the sets points[offsets[k]:offsets[k+1]] independently in
         one pass; ``eps`` and ``min_pts`` are scalars or one value per set.
         Labels are set-local (-1 noise, else the smallest index within the
@@ -212,7 +214,8 @@ class Context:
         labels = out if out is not None else torch.empty(p.shape[0], dtype=torch.int32,
                                                          device=p.device)
         o = _Options(ALGO[algorithm], int(dense_threshold), int(block_size),
-                     (FLAG_TIMING if timing else 0) | (FLAG_GRAPH if graph else 0))
+                     (FLAG_TIMING if timing else 0) | (FLAG_GRAPH if graph else 0),
+                     int(sort_tile))
         _check(load_library().dbscan_cluster_batched(
             self.handle, ctypes.c_void_p(p.data_ptr()),
             off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), k,
@@ -221,21 +224,43 @@ class Context:
             ctypes.c_void_p(labels.data_ptr()), _stream(p.device), ctypes.byref(o)))
         return labels
 
-    def autotune(self, points, eps: float, min_pts: int, algorithm: str = "fdbscan"):
-        """Fastest (block_size, dense_threshold) for this input, with its time
-        in ms; see dbscan_autotune."""
+    def autotune(self, points, eps: float, min_pts: int, algorithm: str = "fdbscan",
+                 cache=None):
+        """Fastest options for this input (block_size, dense_threshold,
+        pair_count, sort_tile), with its time in ms; see dbscan_autotune.
+        ``cache``: a TuneCache or a JSON file path; a workload of the same
+        device, size class, eps, minPts and algorithm found there is not
+        tuned again (the result then has ``"cached": True``)."""
         torch = _torch()
         p = _points(points)
+        key = None
+        if cache is not None:
+            from .tuning import TuneCache, plain_key
+            cache = cache if isinstance(cache, TuneCache) else TuneCache(cache)
+            key = plain_key(torch.cuda.get_device_name(p.device), p.shape[0], eps, min_pts,
+                            algorithm)
+            hit = cache.get(key)
+            if hit is not None:
+                return dict(hit, cached=True)
         lab = torch.empty(p.shape[0], dtype=torch.int32, device=p.device)
         o, ms = _Options(), ctypes.c_float(0)
         _check(load_library().dbscan_autotune(
             self.handle, ctypes.c_void_p(p.data_ptr()), p.shape[0], ctypes.c_float(eps),
             int(min_pts), ALGO[algorithm], ctypes.c_void_p(lab.data_ptr()), ctypes.byref(o),
             ctypes.byref(ms), _stream(p.device)))
-        return {"block_size": o.block_size, "dense_threshold": o.dense_threshold,
-                "pair_count": bool(o.flags & FLAG_PAIR_COUNT), "ms": ms.value}
+        res = {"block_size": o.block_size, "dense_threshold": o.dense_threshold,
+               "pair_count": bool(o.flags & FLAG_PAIR_COUNT), "sort_tile": o.sort_tile,
+               "ms": ms.value}
+        if key is not None:
+            cache.put(key, res)
+        return dict(res, cached=False) if key is not None else res
 
-    def autotune_batched(self, points, offsets, eps, min_pts):
+    def autotune_batched(self, points, offsets, eps, min_pts, cache=None):
+        """Fastest options for this batch (algorithm, block_size,
+        dense_threshold, sort_tile), with its time in ms; see
+        dbscan_autotune_batched.  ``cache`` as for autotune, keyed by the
+        device, the set count, the size class of the total and the exact
+        per-set eps and minPts."""
         import numpy as np
         torch = _torch()
         p = _points(points)
@@ -243,6 +268,14 @@ class Context:
         k = off.size - 1
         e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.float32), (k,)))
         m = np.ascontiguousarray(np.broadcast_to(np.asarray(min_pts, np.int32), (k,)))
+        key = None
+        if cache is not None:
+            from .tuning import TuneCache, batched_key
+            cache = cache if isinstance(cache, TuneCache) else TuneCache(cache)
+            key = batched_key(torch.cuda.get_device_name(p.device), off, e, m)
+            hit = cache.get(key)
+            if hit is not None:
+                return dict(hit, cached=True)
         lab = torch.empty(p.shape[0], dtype=torch.int32, device=p.device)
         o, ms = _Options(), ctypes.c_float(0)
         _check(load_library().dbscan_autotune_batched(
@@ -251,8 +284,12 @@ class Context:
             e.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
             m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.c_void_p(lab.data_ptr()),
             ctypes.byref(o), ctypes.byref(ms), _stream(p.device)))
-        return {"algorithm": ALGO_NAME[o.algorithm], "block_size": o.block_size,
-                "dense_threshold": o.dense_threshold, "ms": ms.value}
+        res = {"algorithm": ALGO_NAME[o.algorithm], "block_size": o.block_size,
+               "dense_threshold": o.dense_threshold, "sort_tile": o.sort_tile,
+               "ms": ms.value}
+        if key is not None:
+            cache.put(key, res)
+        return dict(res, cached=False) if key is not None else res
 
     def sort_passes(self) -> int:
         """Sort passes the last plain clustering call ran (the rest skipped)."""

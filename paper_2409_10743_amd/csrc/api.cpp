@@ -145,6 +145,7 @@ struct dbscan_ctx {
   int ntimes = 0;
   bool recorded[NPHASES + 1] = {};
   int sort_passes = SORT_PASSES;  // sort passes the last clustering call ran
+  int sort_items = 0;             // keys per sort thread of the current call (0: default)
   // captured call sequences (DBSCAN_FLAG_GRAPH), replayed while the key
   // matches; the oldest is replaced
   struct Graph {
@@ -210,6 +211,8 @@ int check_opts(const dbscan_options& o, int32_t min_pts) {
     return fail(DBSCAN_EINVAL, "dense_threshold below min_pts");
   if (o.block_size != 0 && (o.block_size < 64 || o.block_size > 1024 || o.block_size % 64))
     return fail(DBSCAN_EINVAL, "block_size must be a multiple of 64 in [64, 1024]");
+  if (o.sort_tile != 0 && o.sort_tile != 2048 && o.sort_tile != 3072 && o.sort_tile != 4096)
+    return fail(DBSCAN_EINVAL, "sort_tile must be 0, 2048, 3072 or 4096");
   return DBSCAN_OK;
 }
 
@@ -286,7 +289,8 @@ int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore,
   launch_morton(pts, n, bounds, code_eps, ka, kb, drop, sc.hist, s);
   mark(c, timing, PH_MORTON, s);
   SortMarks sm{c, s};
-  launch_radix_sort_dropped(ka, kb, va, vb, n, drop, sc, s, timing ? sort_mark : nullptr, &sm);
+  launch_radix_sort_dropped(ka, kb, va, vb, n, drop, sc, s, timing ? sort_mark : nullptr, &sm,
+                            c->sort_items);
   uint64_t* keys = ka;  // where that sort always ends
   uint32_t* perm = va;
   // the other key buffer is free now: the build's scratch
@@ -406,7 +410,8 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
                                      bits_of(eps),
                                      uint64_t(uint32_t(min_pts)),
                                      uint64_t(block),
-                                     uint64_t(pair_count)};
+                                     uint64_t(pair_count),
+                                     uint64_t(c->sort_items)};
   st = run_enqueued(c, s, graph, key, [&](hipStream_t gs) {
     Index ix;
     uint32_t* deg = pair_count ? at<uint32_t>(c, L.deg) : nullptr;
@@ -463,7 +468,7 @@ int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_
 
   SortMarks sm{c, s};
   const bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, s,
-                                      timing ? sort_mark : nullptr, &sm);
+                                      timing ? sort_mark : nullptr, &sm, c->sort_items);
   const uint64_t* keys = in_a ? ka : kb;
   const uint32_t* perm = in_a ? va : vb;
   int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
@@ -548,7 +553,8 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
                                      bits_of(eps),
                                      uint64_t(uint32_t(min_pts)),
                                      uint64_t(uint32_t(thresh)),
-                                     uint64_t(block)};
+                                     uint64_t(block),
+                                     uint64_t(c->sort_items)};
   st = run_enqueued(c, s, graph, key, [&](hipStream_t gs) {
     start_timing(c, timing, gs);
     launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, at<int4>(c, L.pending),
@@ -636,7 +642,8 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
                                      n,
                                      num_sets,
                                      uint64_t(any_core),
-                                     uint64_t(block)};
+                                     uint64_t(block),
+                                     uint64_t(c->sort_items)};
   if (db) {
     int32_t* d_th = at<int32_t>(c, th_b);
     float* d_ih = at<float>(c, ih_b);
@@ -694,7 +701,7 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
     mark(c, timing, PH_MORTON, gs);
     SortMarks sm{c, gs};
     const bool in_a = launch_radix_sort(ka, kb, va, vb, n, 0, true, sc, gs,
-                                        timing ? sort_mark : nullptr, &sm);
+                                        timing ? sort_mark : nullptr, &sm, c->sort_items);
     const uint64_t* keys = in_a ? ka : kb;
     const uint32_t* perm = in_a ? va : vb;
     int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
@@ -777,6 +784,18 @@ int tune(dbscan_ctx* c, hipStream_t s, const std::vector<dbscan_options>& cands,
   return DBSCAN_OK;
 }
 
+// the second stage: the first stage's pick with each sort tile (the default
+// first, so that a tie keeps it)
+std::vector<dbscan_options> sort_tiles_of(const dbscan_options& best) {
+  std::vector<dbscan_options> v;
+  for (int t : {0, 3072, 2048}) {
+    dbscan_options o = best;
+    o.sort_tile = t;
+    v.push_back(o);
+  }
+  return v;
+}
+
 std::vector<dbscan_options> candidates(int32_t algorithm, int32_t min_pts) {
   std::vector<dbscan_options> v;
   for (int bs : {64, 128, 256, 512}) {
@@ -854,6 +873,7 @@ int dbscan_cluster_ex(dbscan_ctx* c, const float* points, int64_t n, float eps, 
   if (st != DBSCAN_OK) return st;
   if (n == 0) return DBSCAN_OK;
   DeviceGuard g(c->device);
+  c->sort_items = o.sort_tile / SORT_THREADS;
   if (o.algorithm == DBSCAN_ALGO_DENSEBOX)
     return run_densebox(c, points, uint32_t(n), eps, min_pts, labels,
                         reinterpret_cast<hipStream_t>(stream), o);
@@ -881,6 +901,7 @@ int dbscan_cluster_batched(dbscan_ctx* c, const float* points, const int64_t* of
   }
   if (n == 0) return DBSCAN_OK;
   DeviceGuard g(c->device);
+  c->sort_items = o.sort_tile / SORT_THREADS;
   return run_batched(c, points, offsets, uint32_t(num_sets), eps, min_pts, labels,
                      reinterpret_cast<hipStream_t>(stream), o);
 }
@@ -1065,9 +1086,12 @@ int dbscan_autotune(dbscan_ctx* c, const float* points, int64_t n, float eps, in
     return DBSCAN_OK;
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return tune(c, s, candidates(algo, min_pts), best, best_ms, [&](const dbscan_options& o) {
+  auto run = [&](const dbscan_options& o) {
     return dbscan_cluster_ex(c, points, n, eps, min_pts, labels, stream, &o);
-  });
+  };
+  st = tune(c, s, candidates(algo, min_pts), best, best_ms, run);
+  if (st != DBSCAN_OK) return st;
+  return tune(c, s, sort_tiles_of(*best), best, best_ms, run);
 }
 
 int dbscan_autotune_batched(dbscan_ctx* c, const float* points, const int64_t* offsets,
@@ -1087,11 +1111,13 @@ int dbscan_autotune_batched(dbscan_ctx* c, const float* points, const int64_t* o
     cands.push_back(o);
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return tune(c, s, cands, best, best_ms,
-              [&](const dbscan_options& o) {
-                return dbscan_cluster_batched(c, points, offsets, num_sets, eps, min_pts, labels,
-                                              stream, &o);
-              });
+  auto run = [&](const dbscan_options& o) {
+    return dbscan_cluster_batched(c, points, offsets, num_sets, eps, min_pts, labels, stream,
+                                  &o);
+  };
+  int st = tune(c, s, cands, best, best_ms, run);
+  if (st != DBSCAN_OK) return st;
+  return tune(c, s, sort_tiles_of(*best), best, best_ms, run);
 }
 
 const char* dbscan_strerror(int status) {

@@ -48,7 +48,7 @@ struct SortScratch {
 void launch_radix_sort_dropped(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
                                uint32_t n, const uint32_t* drop, const SortScratch& sc,
                                hipStream_t s, void (*after_pass)(void*, int) = nullptr,
-                               void* arg = nullptr);
+                               void* arg = nullptr, int items = 0);
 
 // Digit histograms of keys already in memory (the morton kernel computes
 // them itself while writing the keys).
@@ -59,10 +59,12 @@ void launch_digit_histogram(const uint64_t* keys, uint32_t n, uint32_t* hist,
 // the input values are taken to be 0..n-1 and `va` is not read.  Returns
 // true when the result ends in the A buffers.
 // `after_pass(arg, p)`, if given, is called after pass p is enqueued.
+// items: keys per thread of a tile (8, 12 or 16; 0 = sort_items()).
 bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
                        uint32_t n, int first_pass, bool iota_vals,
                        const SortScratch& sc, hipStream_t s,
-                       void (*after_pass)(void*, int) = nullptr, void* arg = nullptr);
+                       void (*after_pass)(void*, int) = nullptr, void* arg = nullptr,
+                       int items = 0);
 
 // ---- bounds, Morton codes, leaf scatter (morton.hip) -----------------------
 // bounds[0..2] lo (ordered-int encoding), bounds[3..5] hi

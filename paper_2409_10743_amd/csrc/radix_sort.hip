@@ -276,10 +276,10 @@ void sort_pass(bool iota, const uint64_t* kin, uint64_t* kout, const uint32_t* v
 bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
                        uint32_t n, int first_pass, bool iota_vals,
                        const SortScratch& sc, hipStream_t s,
-                       void (*after_pass)(void*, int), void* arg) {
+                       void (*after_pass)(void*, int), void* arg, int tile_items) {
   bool in_a = true;
   if (n == 0) return true;
-  const int items = sort_items();
+  const int items = tile_items ? tile_items : sort_items();
   const uint32_t words = sort_tiles(n, items) * RADIX;
   for (int p = first_pass; p < SORT_PASSES; ++p) {
     const uint64_t* kin = in_a ? ka : kb;
@@ -299,9 +299,10 @@ bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
 
 void launch_radix_sort_dropped(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
                                uint32_t n, const uint32_t* drop, const SortScratch& sc,
-                               hipStream_t s, void (*after_pass)(void*, int), void* arg) {
+                               hipStream_t s, void (*after_pass)(void*, int), void* arg,
+                               int tile_items) {
   if (n == 0) return;
-  const int items = sort_items();
+  const int items = tile_items ? tile_items : sort_items();
   const uint32_t words = sort_tiles(n, items) * RADIX;
   for (int p = 0; p < SORT_PASSES; ++p) {
     uint32_t* st = sc.status + size_t(p) * words;

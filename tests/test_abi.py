@@ -84,3 +84,33 @@ def test_python_binding_rejects_host_tensors():
     with pytest.raises(TypeError):
         dbx.cluster(torch.zeros((4, 3)), 1.0, 2)
     assert np is not None
+
+
+def test_python_structs_match_the_header(tmp_path):
+    """The binding's ctypes structures have the header's layout: a C program
+    built with the host compiler prints sizeof and every field offset."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"dbscan_options": dbx._Options, "dbscan_server_options": dbx._ServerOptions,
+               "dbscan_serving_stats": dbx._ServingStats}
+    lines = []
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"dbscan_mi355x.h\"\n"
+                   "int main(void) {\n" + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], check=True,
+                                                          capture_output=True,
+                                                          text=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[f"{cname} size"]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, f"{cname}.{f}"

@@ -102,8 +102,30 @@ def test_autotune_batched_keeps_labels(ctx):
     assert best["dense_threshold"] in (0, 10, 20) and best["ms"] > 0
     if best["algorithm"] == "fdbscan":
         assert best["dense_threshold"] == 0
+    assert best["sort_tile"] in (0, 2048, 3072)
     check(ctx, pts, off, 0.05, 5, algorithm=best["algorithm"], block_size=best["block_size"],
-          dense_threshold=best["dense_threshold"])
+          dense_threshold=best["dense_threshold"], sort_tile=best["sort_tile"])
+
+
+@pytest.mark.parametrize("tile", [2048, 3072, 4096])
+def test_sort_tiles_keep_labels(ctx, tile):
+    """Every radix-sort tile size gives the same set-local labels (sets of
+    ragged sizes, so the tiles end mid-set)."""
+    pts, off = datagen.subhalo_sets(30, 13, nmin=1, nmax=9000)
+    for algo in ALGOS:
+        check(ctx, pts, off, 0.05, 3, algorithm=algo, sort_tile=tile)
+
+
+def test_autotune_batched_cache(ctx, tmp_path):
+    pts, off = datagen.subhalo_sets(16, 6, nmin=64, nmax=5000)
+    path = tmp_path / "tune.json"
+    a = ctx.autotune_batched(dev(pts), off, 0.05, 5, cache=path)
+    b = ctx.autotune_batched(dev(pts), off, 0.05, 5, cache=path)
+    assert a["cached"] is False and b["cached"] is True
+    assert {k: a[k] for k in a if k != "cached"} == {k: b[k] for k in b if k != "cached"}
+    # other per-set parameters: tuned again
+    c = ctx.autotune_batched(dev(pts), off, 0.06, 5, cache=path)
+    assert c["cached"] is False
 
 
 def test_invalid_offsets(ctx):

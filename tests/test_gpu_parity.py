@@ -421,6 +421,39 @@ def test_autotune_returns_options_that_keep_labels(ctx):
     for algo in ("fdbscan", "densebox"):
         best = ctx.autotune(dev(p), 0.01, 4, algorithm=algo)
         assert best["block_size"] in (64, 128, 256, 512) and best["ms"] > 0
+        assert best["sort_tile"] in (0, 2048, 3072)
         got = run(ctx, p, 0.01, 4, algorithm=algo, block_size=best["block_size"],
-                  dense_threshold=best["dense_threshold"], pair_count=best["pair_count"])
+                  dense_threshold=best["dense_threshold"], pair_count=best["pair_count"],
+                  sort_tile=best["sort_tile"])
         np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("tile", [2048, 3072, 4096])
+@pytest.mark.parametrize("n", [1, 3071, 3073, 50001])
+def test_sort_tiles_keep_labels(ctx, tile, n):
+    """Each radix-sort tile size (one tile, a ragged last tile, many tiles)
+    gives the oracle's labels with both algorithms."""
+    p = clumpy(n, 300 + n)
+    ref = oracle.dbscan(p, F32(0.02), 3)
+    for algo in ("fdbscan", "densebox"):
+        np.testing.assert_array_equal(run(ctx, p, 0.02, 3, algorithm=algo, sort_tile=tile), ref)
+
+
+def test_sort_tile_rejected(ctx):
+    p = dev(clumpy(100, 1))
+    for t in (-1, 1024, 4097, 8192):
+        with pytest.raises(dbx.DbscanError) as e:
+            ctx.cluster(p, 0.02, 2, sort_tile=t)
+        assert e.value.code == -1
+
+
+def test_autotune_cache(ctx, tmp_path):
+    p = clumpy(40000, 23)
+    path = tmp_path / "tune.json"
+    a = ctx.autotune(dev(p), 0.01, 4, cache=path)
+    b = ctx.autotune(dev(p), 0.01, 4, cache=path)
+    assert a["cached"] is False and b["cached"] is True
+    assert {k: a[k] for k in a if k != "cached"} == {k: b[k] for k in b if k != "cached"}
+    # same size class, same parameters: the cached pick; another minPts: tuned
+    assert ctx.autotune(dev(clumpy(41000, 24)), 0.01, 4, cache=path)["cached"] is True
+    assert ctx.autotune(dev(p), 0.01, 5, cache=path)["cached"] is False
