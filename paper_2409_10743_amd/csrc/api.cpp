@@ -110,7 +110,8 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
   L.bounds = take(8 * 4);
   L.drop = take(4);
   L.root = take(4);
-  // zeroed region: hist | tile counters | status word | pair count | look-back
+  // zeroed region: hist | tile counters | status word | pair count | walk
+  // queues | (DenseBox scans) | the first sort pass's look-back words
   L.zero = o;
   L.hist = take(SORT_PASSES * RADIX * 4);
   L.tile_ctr = take(SORT_PASSES * 4);
@@ -125,7 +126,9 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
     L.scan2 = take(scan_status_words(n) * 4);
   }
   L.sort_status = take(sort_status_words(n) * 4);
-  L.zero_words = (o - L.zero) / 4;
+  // zeroed up to the first sort pass's look-back words (each pass clears
+  // the next pass's)
+  L.zero_words = (L.sort_status - L.zero) / 4 + sort_first_status_words(n);
   L.total = o;
   return L;
 }

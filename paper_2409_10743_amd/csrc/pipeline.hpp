@@ -34,11 +34,18 @@ inline uint32_t sort_tiles(uint32_t n, int items) {
 inline size_t sort_status_words(uint32_t n) {
   return size_t(SORT_PASSES) * sort_tiles(n, SORT_ITEMS_MIN) * RADIX;
 }
+// the words of pass 0 (any variant) at the start of that state: what must be
+// zero when a sort starts
+inline size_t sort_first_status_words(uint32_t n) {
+  return size_t(sort_tiles(n, SORT_ITEMS_MIN)) * RADIX;
+}
 
 struct SortScratch {
   uint32_t* hist;      // [SORT_PASSES][RADIX] digit counts, zeroed
   uint32_t* tile_ctr;  // [SORT_PASSES] dynamic tile ids, zeroed
-  uint32_t* status;    // [SORT_PASSES][tiles][RADIX] look-back words, zeroed
+  uint32_t* status;    // [SORT_PASSES][tiles][RADIX] look-back words: the first
+                       // pass's zeroed (sort_first_status_words), each pass
+                       // clears the next pass's
   uint32_t* err;       // status word, STATUS_SORT_STALL set on a stalled wait
 };
 

@@ -67,8 +67,8 @@ template <bool IOTA, int ITEMS>
 __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
     uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb, uint32_t n, int shift,
     const uint32_t* __restrict__ drop, const uint32_t* __restrict__ ghist,
-    uint32_t* __restrict__ status, uint32_t* __restrict__ tile_ctr,
-    uint32_t* __restrict__ err) {
+    uint32_t* __restrict__ status, uint32_t* __restrict__ next_status,
+    uint32_t* __restrict__ tile_ctr, uint32_t* __restrict__ err) {
   constexpr int TILE = SORT_THREADS * ITEMS;
   __shared__ uint64_t s_keys[TILE];           // keys and values in digit order
   __shared__ uint32_t s_vals[TILE];
@@ -78,6 +78,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
   __shared__ uint32_t s_tmp[WAVES];
   __shared__ uint32_t s_tile;
 
+  // the next pass's look-back words start at zero: each workgroup clears
+  // one tile's row of them (the grid has one workgroup per tile), also in a
+  // pass that returns at once below
+  if (next_status) next_status[size_t(blockIdx.x) * RADIX + threadIdx.x] = 0u;
   const uint64_t* kin = ka;  // without `drop`: (ka, va) -> (kb, vb)
   uint64_t* kout = kb;
   const uint32_t* vin = va;
@@ -254,20 +258,23 @@ int sort_items() {
 namespace {
 // one pass from (kin, vin) to (kout, vout); with `drop`, the kernel picks
 // the direction itself (see k_onesweep)
+// st: this pass's look-back words (zero); the next pass's, if any, follow
+// them and are cleared here
 template <int ITEMS>
 void sort_pass(bool iota, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
                uint32_t* vout, uint32_t n, int p, const uint32_t* drop, const SortScratch& sc,
                uint32_t* st, hipStream_t s) {
+  uint32_t* next = p + 1 < SORT_PASSES ? st + size_t(sort_tiles(n, ITEMS)) * RADIX : nullptr;
   const uint32_t tiles = sort_tiles(n, ITEMS);
   uint64_t* ka = const_cast<uint64_t*>(kin);  // read-only in this direction
   uint32_t* va = const_cast<uint32_t*>(vin);
   if (iota)
     hipLaunchKernelGGL((k_onesweep<true, ITEMS>), dim3(tiles), dim3(SORT_THREADS), 0, s, ka,
-                       kout, va, vout, n, 8 * p, drop, sc.hist + p * RADIX, st,
+                       kout, va, vout, n, 8 * p, drop, sc.hist + p * RADIX, st, next,
                        sc.tile_ctr + p, sc.err);
   else
     hipLaunchKernelGGL((k_onesweep<false, ITEMS>), dim3(tiles), dim3(SORT_THREADS), 0, s, ka,
-                       kout, va, vout, n, 8 * p, drop, sc.hist + p * RADIX, st,
+                       kout, va, vout, n, 8 * p, drop, sc.hist + p * RADIX, st, next,
                        sc.tile_ctr + p, sc.err);
 }
 
@@ -286,7 +293,7 @@ bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
     uint64_t* kout = in_a ? kb : ka;
     const uint32_t* vin = in_a ? va : vb;
     uint32_t* vout = in_a ? vb : va;
-    uint32_t* st = sc.status + size_t(p) * words;
+    uint32_t* st = sc.status + size_t(p - first_pass) * words;  // the first pass's: zeroed
     const bool iota = p == first_pass && iota_vals;
     if (items == 8) sort_pass<8>(iota, kin, kout, vin, vout, n, p, nullptr, sc, st, s);
     else if (items == 12) sort_pass<12>(iota, kin, kout, vin, vout, n, p, nullptr, sc, st, s);
