@@ -157,7 +157,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path "
-              "is single-GPU by design and multi-GPU runs are not part of this build",
+              "is single-GPU by design: run it with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
