@@ -1014,6 +1014,7 @@ int dbscan_build_tree(dbscan_ctx* c, const float* points, int64_t n, uint32_t* p
   DeviceGuard g(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index ix;
+  c->sort_items = 0;  // the default sort tile
   st = build_index(c, points, uint32_t(n), false, false, s, &ix, 0.0f, nullptr, nullptr);
   if (st != DBSCAN_OK) return st;
   HIP_TRY(hipMemcpyAsync(perm, ix.perm, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
@@ -1033,6 +1034,7 @@ int dbscan_core_flags(dbscan_ctx* c, const float* points, int64_t n, float eps, 
   DeviceGuard g(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index ix;
+  c->sort_items = 0;  // the default sort tile
   st = build_index(c, points, uint32_t(n), false, false, s, &ix, eps, nullptr, nullptr);
   if (st != DBSCAN_OK) return st;
   uint8_t* flag = at<uint8_t>(c, ix.L.flag);
@@ -1061,6 +1063,7 @@ int dbscan_traversal_stats(dbscan_ctx* c, const float* points, int64_t n, float 
   DeviceGuard g(c->device);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Index ix;
+  c->sort_items = 0;  // the default sort tile
   st = build_index(c, points, uint32_t(n), false, false, s, &ix, eps, nullptr, nullptr);
   if (st != DBSCAN_OK) return st;
   unsigned long long* dcount = at<unsigned long long>(c, ix.L.count);
