@@ -18,6 +18,12 @@ morton_order(codes)               stable sort permutation of the codes
 
 Status codes mirror the library's: 0 ok, -1 invalid argument, -2 non-finite
 coordinate, -3 out of memory.
+
+Pins: the C functions by tests/test_oracle_pins.py (brute force, hand cases,
+binary32 boundary cases, metamorphic relations, planted mistakes); the
+Morton functions by tests/test_oracle_morton_pins.py (codes worked out by
+hand, binary32 grid coordinates decided with exact rationals, a de-interleave
+round trip, planted mistakes).
 """
 from __future__ import annotations
 
