@@ -142,6 +142,62 @@ def _points(points):
     return points.contiguous()
 
 
+def _labels_out(out, n: int, device):
+    """The label buffer of a call: a new int32 tensor, or the caller's `out`,
+    which must be an int32 tensor on the points' device, contiguous and
+    holding at least n elements (the library writes n labels through the
+    bare pointer and cannot check its size)."""
+    torch = _torch()
+    if out is None:
+        return torch.empty(n, dtype=torch.int32, device=device)
+    if not isinstance(out, torch.Tensor):
+        raise TypeError("out must be a torch tensor")
+    if out.dtype != torch.int32:
+        raise TypeError(f"out must be int32, not {out.dtype}")
+    if out.device != torch.device(device):
+        raise ValueError(f"out is on {out.device}, the points on {device}")
+    if not out.is_contiguous():
+        raise ValueError("out must be contiguous")
+    if out.numel() < n:
+        raise ValueError(f"out holds {out.numel()} labels, {n} are written")
+    return out
+
+
+def _offsets(offsets, npoints: int):
+    """CSR set offsets as int64: offsets[0] = 0, non-decreasing, and the last
+    equal to the number of points (the library reads points and writes
+    labels up to offsets[-1])."""
+    import numpy as np
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    if off.ndim != 1 or off.size < 1:
+        raise ValueError("offsets must be a 1-D array of num_sets + 1 values")
+    if off[0] != 0:
+        raise ValueError("offsets[0] must be 0")
+    if off.size > 1 and bool((np.diff(off) < 0).any()):
+        raise ValueError("offsets must not decrease")
+    if int(off[-1]) != int(npoints):
+        raise ValueError(f"offsets[-1] = {int(off[-1])} but there are {npoints} points")
+    return off
+
+
+def _host_labels_out(out, n: int):
+    """A host label buffer for the server: numpy int32, C-contiguous,
+    writable, at least n elements (results land there after submit
+    returns, through its bare pointer)."""
+    import numpy as np
+    if out is None:
+        return np.empty(n, dtype=np.int32)
+    if not isinstance(out, np.ndarray):
+        raise TypeError("out must be a numpy array")
+    if out.dtype != np.int32:
+        raise TypeError(f"out must be int32, not {out.dtype}")
+    if not out.flags.c_contiguous or not out.flags.writeable:
+        raise ValueError("out must be C-contiguous and writable")
+    if out.size < n:
+        raise ValueError(f"out holds {out.size} labels, {n} are written")
+    return out
+
+
 def _stream(device) -> ctypes.c_void_p:
     return ctypes.c_void_p(_torch().cuda.current_stream(device).cuda_stream)
 
@@ -181,10 +237,9 @@ class Context:
         DBSCAN_FLAG_GRAPH).  ``pair_count``: core points by pair traversal
         (DBSCAN_FLAG_PAIR_COUNT).  ``sort_tile``: keys per radix-sort
         workgroup (0 = 4096, 2048, 3072, 4096)."""
-        torch = _torch()
         p = _points(points)
         n = p.shape[0]
-        labels = out if out is not None else torch.empty(n, dtype=torch.int32, device=p.device)
+        labels = _labels_out(out, n, p.device)
         o = _Options(ALGO[algorithm], int(dense_threshold), int(block_size),
                      (FLAG_TIMING if timing else 0) | (FLAG_GRAPH if graph else 0) |
                      (FLAG_PAIR_COUNT if pair_count else 0), int(sort_tile))
@@ -202,17 +257,15 @@ class Context:
         set of the point's cluster).  ``algorithm``: "auto"/"fdbscan" or
         "densebox" (``dense_threshold`` 0 = each set's min_pts)."""
         import numpy as np
-        torch = _torch()
         p = _points(points)
-        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        off = _offsets(offsets, p.shape[0])
         k = off.size - 1
         e = np.ascontiguousarray(np.broadcast_to(np.float32(eps) if np.ndim(eps) == 0
                                                  else np.asarray(eps, np.float32), (k,)),
                                  dtype=np.float32)
         m = np.ascontiguousarray(np.broadcast_to(np.asarray(min_pts, np.int32), (k,)),
                                  dtype=np.int32)
-        labels = out if out is not None else torch.empty(p.shape[0], dtype=torch.int32,
-                                                         device=p.device)
+        labels = _labels_out(out, p.shape[0], p.device)
         o = _Options(ALGO[algorithm], int(dense_threshold), int(block_size),
                      (FLAG_TIMING if timing else 0) | (FLAG_GRAPH if graph else 0),
                      int(sort_tile))
@@ -264,7 +317,7 @@ class Context:
         import numpy as np
         torch = _torch()
         p = _points(points)
-        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        off = _offsets(offsets, p.shape[0])
         k = off.size - 1
         e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.float32), (k,)))
         m = np.ascontiguousarray(np.broadcast_to(np.asarray(min_pts, np.int32), (k,)))
@@ -313,8 +366,12 @@ class Context:
     def sort_pairs(self, keys, vals):
         """Sort int64 keys (as unsigned) with int32 values, in place."""
         torch = _torch()
-        assert keys.dtype == torch.int64 and vals.dtype == torch.int32
-        assert keys.is_contiguous() and vals.is_contiguous() and keys.numel() == vals.numel()
+        if keys.dtype != torch.int64 or vals.dtype != torch.int32:
+            raise TypeError("keys must be int64 and vals int32")
+        if not (keys.is_cuda and vals.device == keys.device):
+            raise TypeError("keys and vals must be on the same HIP device")
+        if not (keys.is_contiguous() and vals.is_contiguous()) or keys.numel() != vals.numel():
+            raise ValueError("keys and vals must be contiguous and of equal length")
         _check(load_library().dbscan_sort_pairs(
             self.handle, ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()),
             keys.numel(), _stream(keys.device)))
@@ -385,7 +442,7 @@ class Server:
         p = np.ascontiguousarray(points, dtype=np.float32)
         if p.ndim != 2 or p.shape[1] != 3:
             raise TypeError("points must be float32 [N, 3]")
-        lab = out if out is not None else np.empty(p.shape[0], dtype=np.int32)
+        lab = _host_labels_out(out, p.shape[0])
         t = ctypes.c_uint64(0)
         _check(load_library().dbscan_server_submit(
             self.handle, ctypes.c_void_p(p.ctypes.data), p.shape[0], ctypes.c_float(eps),
@@ -440,10 +497,9 @@ def cluster(points, eps: float, min_pts: int, out=None):
     """Labels (int32 CUDA tensor, input order): -1 for noise, otherwise the
     smallest input index in the point's cluster.  Uses the device's default
     context."""
-    torch = _torch()
     p = _points(points)
     n = p.shape[0]
-    labels = out if out is not None else torch.empty(n, dtype=torch.int32, device=p.device)
+    labels = _labels_out(out, n, p.device)
     _check(load_library().dbscan_cluster(
         ctypes.c_void_p(p.data_ptr()), n, ctypes.c_float(eps), int(min_pts),
         ctypes.c_void_p(labels.data_ptr()), _stream(p.device)))

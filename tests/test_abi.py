@@ -114,3 +114,47 @@ def test_python_structs_match_the_header(tmp_path):
         assert int(got[f"{cname} size"]) == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, f"{cname}.{f}"
+
+
+def test_binding_checks_label_buffers_before_any_call():
+    """A caller's `out` is checked before the library gets its bare pointer:
+    int32, on the points' device, contiguous, at least n elements."""
+    torch = pytest.importorskip("torch")
+    dev = torch.device("cpu")  # the checks themselves need no GPU
+    ok = torch.empty(10, dtype=torch.int32)
+    assert dbx._labels_out(ok, 10, dev) is ok
+    assert dbx._labels_out(None, 7, dev).shape == (7,)
+    bad = [(torch.empty(10, dtype=torch.int64), TypeError),
+           (np.empty(10, np.int32), TypeError),
+           (torch.empty(9, dtype=torch.int32), ValueError),
+           (torch.empty(20, dtype=torch.int32)[::2], ValueError)]
+    for out, err in bad:
+        with pytest.raises(err):
+            dbx._labels_out(out, 10, dev)
+    with pytest.raises(ValueError):  # another device
+        dbx._labels_out(torch.empty(10, dtype=torch.int32), 10, torch.device("cuda", 0))
+
+
+def test_binding_checks_offsets():
+    np.testing.assert_array_equal(dbx._offsets([0, 3, 3, 10], 10), [0, 3, 3, 10])
+    for off in ([1, 10], [0, 6, 5, 10], [0, 11], [0, 9], [], [[0, 10]]):
+        with pytest.raises(ValueError):
+            dbx._offsets(off, 10)
+
+
+def test_server_checks_host_label_buffers():
+    s = dbx.Server(slots=1, fake_us_per_mpoint=10.0)
+    p = np.zeros((10, 3), np.float32)
+    for out, err in [(np.empty(10, np.int64), TypeError), (np.empty(9, np.int32), ValueError),
+                     (np.empty(20, np.int32)[::2], ValueError), ([0] * 10, TypeError)]:
+        with pytest.raises(err):
+            s.submit(p, 0.1, 2, out=out)
+    ro = np.empty(10, np.int32)
+    ro.flags.writeable = False
+    with pytest.raises(ValueError):
+        s.submit(p, 0.1, 2, out=ro)
+    good = np.zeros(12, np.int32)
+    t = s.submit(p, 0.1, 2, out=good)
+    assert s.wait(t, 10.0) == 0
+    assert (good[:10] == -1).all()
+    s.close()
