@@ -11,6 +11,8 @@ dbscan(points, eps, min_pts)      labels, section 3.1 definition (C, grid +
 core_flags(points, eps, min_pts)  |N_eps(x)| >= minPts per point (C)
 neighbour_counts(points, eps)     |N_eps(x)| per point, self included (C)
 pair_count(points, eps)           number of unordered eps-pairs (C)
+set_threads(t)                    host threads of the counting and border
+                                  steps (default 1)
 morton63(points)                  the 63-bit Morton code of every point,
                                   section 4.2.2 (numpy, plain definition)
 morton_order(codes)               stable sort permutation of the codes
@@ -40,7 +42,7 @@ _LIB = os.path.join(_HERE, "_build", "liboracle.so")
 # The predicate must be evaluated exactly as written: no contraction into
 # fused multiply-adds, no fast-math, subnormals kept (x86-64 SSE, no -m flags).
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-          "-fPIC", "-shared", "-Wall", "-Wextra"]
+          "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra"]
 
 
 def build(extra_flags=(), out=None) -> str:
@@ -78,6 +80,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
                                       ctypes.POINTER(ctypes.c_int64)]
     lib.oracle_pair_count.restype = ctypes.c_int
     lib.oracle_version.restype = ctypes.c_char_p
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_threads.restype = ctypes.c_int
+    lib.oracle_set_threads(1)  # sequential unless asked otherwise
     return lib
 
 
@@ -115,6 +120,12 @@ def dbscan(points, eps, min_pts, lib=None, return_core=False):
     if st != 0:
         raise OracleError(st)
     return (lab, core.astype(bool)) if return_core else lab
+
+
+def set_threads(t: int, lib=None) -> int:
+    """Host threads of the counting and border steps (the union-find merge is
+    always sequential); 1 by default.  Labels do not depend on it."""
+    return int((lib or _get()).oracle_set_threads(int(t)))
 
 
 def core_flags(points, eps, min_pts, lib=None) -> np.ndarray:

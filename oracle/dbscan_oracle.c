@@ -30,6 +30,11 @@
  *   eps-neighbour lies in one of the 27 surrounding cells; core points found
  *   neighbours of each other are merged with a sequential union-find.
  *
+ * Threads.  Counting neighbours and attaching border points read shared
+ * data and write one entry per point, so they may run on several host
+ * threads (OpenMP, oracle_set_threads); the union-find merge always runs
+ * sequentially.  The result does not depend on the thread count.
+ *
  * Parity status: pinned by the CPU tests (O(N^2) brute force with
  * scipy connected components, hand-built boundary cases, exact
  * metamorphic relations, the minPts = 2 / connected-components reduction).
@@ -38,6 +43,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_OK 0
 #define OR_EINVAL (-1)
@@ -223,6 +231,31 @@ static void neighbourhood(const grid_t *g, int64_t c, int64_t cur[9], nbhd_t *nb
         }
 }
 
+/* Column cursors for a walk over the cells that starts at cell c: each one
+ * at the first cell whose key is not below its column's lowest key (binary
+ * search), where neighbourhood() would have left it after cells 0..c-1. */
+static void cursors_at(const grid_t *g, int64_t c, int64_t cur[9])
+{
+    uint64_t key = g->cell_key[c];
+    int64_t cx = (int64_t)(key >> 42), cy = (int64_t)((key >> 21) & 0x1FFFFF),
+            cz = (int64_t)(key & 0x1FFFFF);
+    int col = 0;
+    for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy, ++col) {
+            cur[col] = 0;
+            if (cx + dx < 0 || cy + dy < 0) continue;
+            uint64_t lo = cell_pack((uint64_t)(cx + dx), (uint64_t)(cy + dy),
+                                    (uint64_t)(cz > 0 ? cz - 1 : 0));
+            int64_t a = 0, b = g->ncells; /* first index with key >= lo */
+            while (a < b) {
+                int64_t m = a + (b - a) / 2;
+                if (g->cell_key[m] < lo) a = m + 1;
+                else b = m;
+            }
+            cur[col] = a;
+        }
+}
+
 /* ---- sequential union-find (Tarjan), section 4.3 -------------------------- */
 
 static int64_t uf_find(int64_t *parent, int64_t x)
@@ -247,24 +280,34 @@ static void uf_union(int64_t *parent, int64_t a, int64_t b)
 
 /* ---- the clustering ------------------------------------------------------ */
 
+/* Cells are handed to threads in contiguous blocks; each block sets its own
+ * column cursors at its first cell (cursors_at). */
+#define CELL_BLOCK 4096
+
 /* Neighbour counts |N_eps(i)| (self included) for every point. */
 static void count_neighbours(const grid_t *g, const float *pts, float e2,
                              int64_t *cnt)
 {
-    int64_t cur[9] = {0};
-    for (int64_t c = 0; c < g->ncells; ++c) {
-        nbhd_t nb;
-        neighbourhood(g, c, cur, &nb);
-        for (int64_t k = g->cell_start[c]; k < g->cell_start[c + 1]; ++k) {
-            int64_t i = g->order[k].idx;
-            int64_t s = 0;
-            for (int t = 0; t < nb.m; ++t)
-                for (int64_t q = nb.begin[t]; q < nb.end[t]; ++q)
-                    s += is_neighbour(pts + 3 * i, pts + 3 * g->order[q].idx, e2);
+    const int64_t nblocks = (g->ncells + CELL_BLOCK - 1) / CELL_BLOCK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < nblocks; ++b) {
+        int64_t cur[9];
+        cursors_at(g, b * CELL_BLOCK, cur);
+        const int64_t c1 = (b + 1) * CELL_BLOCK < g->ncells ? (b + 1) * CELL_BLOCK : g->ncells;
+        for (int64_t c = b * CELL_BLOCK; c < c1; ++c) {
+            nbhd_t nb;
+            neighbourhood(g, c, cur, &nb);
+            for (int64_t k = g->cell_start[c]; k < g->cell_start[c + 1]; ++k) {
+                int64_t i = g->order[k].idx;
+                int64_t s = 0;
+                for (int t = 0; t < nb.m; ++t)
+                    for (int64_t q = nb.begin[t]; q < nb.end[t]; ++q)
+                        s += is_neighbour(pts + 3 * i, pts + 3 * g->order[q].idx, e2);
 #ifdef ORACLE_MUTANT_NOSELF
-            s -= 1;
+                s -= 1;
 #endif
-            cnt[i] = s;
+                cnt[i] = s;
+            }
         }
     }
 }
@@ -324,8 +367,7 @@ int oracle_dbscan(const float *pts, int64_t n, float eps, int32_t min_pts,
     count_neighbours(&g, pts, e2, cnt);
     for (int64_t i = 0; i < n; ++i) core[i] = cnt[i] >= min_pts;
 
-    /* 2. merge core points that are eps-neighbours (union-find), and
-     * 3. attach every non-core point to its smallest-index core neighbour */
+    /* 2. merge core points that are eps-neighbours (union-find, sequential) */
     for (int64_t i = 0; i < n; ++i) parent[i] = i;
     int64_t cur[9] = {0};
     for (int64_t c = 0; c < g.ncells; ++c) {
@@ -333,22 +375,43 @@ int oracle_dbscan(const float *pts, int64_t n, float eps, int32_t min_pts,
         neighbourhood(&g, c, cur, &nb);
         for (int64_t k = g.cell_start[c]; k < g.cell_start[c + 1]; ++k) {
             int64_t i = g.order[k].idx;
-            attach[i] = -1;
+            if (!core[i]) continue;
             for (int t = 0; t < nb.m; ++t)
                 for (int64_t q = nb.begin[t]; q < nb.end[t]; ++q) {
                     int64_t j = g.order[q].idx;
-                    if (!core[j] || !is_neighbour(pts + 3 * i, pts + 3 * j, e2))
-                        continue;
-                    if (core[i]) {
-                        if (j > i) uf_union(parent, i, j);
-#ifdef ORACLE_MUTANT_BORDER_MAX
-                    } else if (attach[i] < 0 || j > attach[i]) {
-#else
-                    } else if (attach[i] < 0 || j < attach[i]) {
-#endif
-                        attach[i] = j;
-                    }
+                    if (j > i && core[j] && is_neighbour(pts + 3 * i, pts + 3 * j, e2))
+                        uf_union(parent, i, j);
                 }
+        }
+    }
+
+    /* 3. attach every non-core point to its smallest-index core neighbour */
+    const int64_t nblocks = (g.ncells + CELL_BLOCK - 1) / CELL_BLOCK;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < nblocks; ++b) {
+        int64_t bcur[9];
+        cursors_at(&g, b * CELL_BLOCK, bcur);
+        const int64_t c1 = (b + 1) * CELL_BLOCK < g.ncells ? (b + 1) * CELL_BLOCK : g.ncells;
+        for (int64_t c = b * CELL_BLOCK; c < c1; ++c) {
+            nbhd_t nb;
+            neighbourhood(&g, c, bcur, &nb);
+            for (int64_t k = g.cell_start[c]; k < g.cell_start[c + 1]; ++k) {
+                int64_t i = g.order[k].idx;
+                attach[i] = -1;
+                if (core[i]) continue;
+                for (int t = 0; t < nb.m; ++t)
+                    for (int64_t q = nb.begin[t]; q < nb.end[t]; ++q) {
+                        int64_t j = g.order[q].idx;
+                        if (!core[j] || !is_neighbour(pts + 3 * i, pts + 3 * j, e2))
+                            continue;
+#ifdef ORACLE_MUTANT_BORDER_MAX
+                        if (attach[i] < 0 || j > attach[i])
+#else
+                        if (attach[i] < 0 || j < attach[i])
+#endif
+                            attach[i] = j;
+                    }
+            }
         }
     }
 
@@ -377,6 +440,19 @@ done:
     free(minidx);
     free(core);
     return st;
+}
+
+/* Host threads for the counting and border steps (1 = sequential; values
+ * below 1 are taken as 1).  Returns the number in effect. */
+int oracle_set_threads(int t)
+{
+    if (t < 1) t = 1;
+#ifdef _OPENMP
+    omp_set_num_threads(t);
+    return t;
+#else
+    return 1;
+#endif
 }
 
 const char *oracle_version(void)

@@ -365,3 +365,22 @@ def test_local_check_agrees_with_whole_field_oracle():
         bad[k] = -1 if full[k] >= 0 else int(k)  # a clustered point as noise, or vice versa
         with pytest.raises(AssertionError):
             localcheck.check_cube(p, bad, (10, 10, 10), (30, 30, 30), 0.2, mp, 4.0)
+
+
+# ---- threads do not change the result ----------------------------------------
+
+def test_thread_count_does_not_change_labels():
+    """The counting and border steps may run on several host threads; the
+    labels and core flags are the same as with one."""
+    p = datagen.halo_field(1 << 18, 256.0 * (1 / 64) ** (1 / 3), 8)
+    try:
+        for mp in (2, 3, 5):
+            oracle.set_threads(1)
+            ref, ref_core = oracle.dbscan(p, F32(0.2), mp, return_core=True)
+            oracle.set_threads(4)
+            got, got_core = oracle.dbscan(p, F32(0.2), mp, return_core=True)
+            np.testing.assert_array_equal(got, ref)
+            np.testing.assert_array_equal(got_core, ref_core)
+            np.testing.assert_array_equal(oracle.neighbour_counts(p, F32(0.2)) >= mp, ref_core)
+    finally:
+        oracle.set_threads(1)
