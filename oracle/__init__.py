@@ -13,6 +13,8 @@ neighbour_counts(points, eps)     |N_eps(x)| per point, self included (C)
 pair_count(points, eps)           number of unordered eps-pairs (C)
 set_threads(t)                    host threads of the counting and border
                                   steps (default 1)
+dbscan_sets(points, offsets, ...) independent sets, each clustered alone,
+                                  sets spread over host threads
 morton63(points)                  the 63-bit Morton code of every point,
                                   section 4.2.2 (numpy, plain definition)
 morton_order(codes)               stable sort permutation of the codes
@@ -120,6 +122,33 @@ def dbscan(points, eps, min_pts, lib=None, return_core=False):
     if st != 0:
         raise OracleError(st)
     return (lab, core.astype(bool)) if return_core else lab
+
+
+def dbscan_sets(points, offsets, eps, min_pts, workers: int = 1, lib=None) -> np.ndarray:
+    """Labels of independent sets points[offsets[k]:offsets[k+1]], each
+    clustered alone (set-local indices), with eps and min_pts scalars or one
+    value per set.  `workers` host threads take sets in turn (each call
+    sequential inside); the result does not depend on it."""
+    from concurrent.futures import ThreadPoolExecutor
+    p = _as_points(points)
+    off = np.asarray(offsets, dtype=np.int64)
+    k = off.size - 1
+    e = np.broadcast_to(np.asarray(eps, dtype=np.float32), (k,))
+    m = np.broadcast_to(np.asarray(min_pts, dtype=np.int64), (k,))
+    out = np.empty(int(off[-1]), dtype=np.int32)
+
+    def one(s):
+        a, b = int(off[s]), int(off[s + 1])
+        out[a:b] = dbscan(p[a:b], e[s], int(m[s]), lib=lib)
+
+    if workers <= 1:
+        for s in range(k):
+            one(s)
+    else:  # largest sets first, so the last ones to finish are small
+        order = np.argsort(-np.diff(off), kind="stable")
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(one, order.tolist()))
+    return out
 
 
 def set_threads(t: int, lib=None) -> int:

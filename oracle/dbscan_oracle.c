@@ -43,10 +43,6 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
-#ifdef _OPENMP
-#include <omp.h>
-#endif
-
 #define OR_OK 0
 #define OR_EINVAL (-1)
 #define OR_ENONFINITE (-2)
@@ -284,12 +280,15 @@ static void uf_union(int64_t *parent, int64_t a, int64_t b)
  * column cursors at its first cell (cursors_at). */
 #define CELL_BLOCK 4096
 
+/* threads of the counting and border steps, for every calling thread */
+static int g_threads = 1;
+
 /* Neighbour counts |N_eps(i)| (self included) for every point. */
 static void count_neighbours(const grid_t *g, const float *pts, float e2,
                              int64_t *cnt)
 {
     const int64_t nblocks = (g->ncells + CELL_BLOCK - 1) / CELL_BLOCK;
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads)
     for (int64_t b = 0; b < nblocks; ++b) {
         int64_t cur[9];
         cursors_at(g, b * CELL_BLOCK, cur);
@@ -387,7 +386,7 @@ int oracle_dbscan(const float *pts, int64_t n, float eps, int32_t min_pts,
 
     /* 3. attach every non-core point to its smallest-index core neighbour */
     const int64_t nblocks = (g.ncells + CELL_BLOCK - 1) / CELL_BLOCK;
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads)
     for (int64_t b = 0; b < nblocks; ++b) {
         int64_t bcur[9];
         cursors_at(&g, b * CELL_BLOCK, bcur);
@@ -448,7 +447,7 @@ int oracle_set_threads(int t)
 {
     if (t < 1) t = 1;
 #ifdef _OPENMP
-    omp_set_num_threads(t);
+    g_threads = t;
     return t;
 #else
     return 1;

@@ -384,3 +384,14 @@ def test_thread_count_does_not_change_labels():
             np.testing.assert_array_equal(oracle.neighbour_counts(p, F32(0.2)) >= mp, ref_core)
     finally:
         oracle.set_threads(1)
+
+
+def test_dbscan_sets_equals_one_call_per_set():
+    pts, off = datagen.subhalo_sets(24, 6, nmax=4096)
+    eps = np.full(24, 0.05, F32)
+    eps[::3] = F32(0.02)
+    mp = np.array([2, 5, 10] * 8)
+    one = np.concatenate([oracle.dbscan(pts[off[s]:off[s + 1]], eps[s], mp[s])
+                          for s in range(24)])
+    for w in (1, 4):
+        np.testing.assert_array_equal(oracle.dbscan_sets(pts, off, eps, mp, workers=w), one)
