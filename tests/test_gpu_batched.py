@@ -1,6 +1,8 @@
 """GPU parity of the batched path: many independent sets in one pass, each
 result bit-identical to the oracle's clustering of that set alone, with
 FDBSCAN and with DenseBox (per-set cell grids and thresholds)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -152,20 +154,26 @@ def test_invalid_offsets(ctx):
         assert st == -1
 
 
-def test_subhalo4096_full(ctx):
-    """The full 4,096-set workload (~133M points), both algorithms: every
-    label equal between them, and every set checked against the oracle on a
-    deterministic sample of 200 sets plus the largest and smallest."""
+@pytest.fixture(scope="module")
+def subhalo4096():
+    print("[batched] generating the 4,096 sets", flush=True)
     pts, off = datagen.subhalo_sets(4096, 4)
+    print("[batched] oracle on every set", flush=True)
+    ref = oracle.dbscan_sets(pts, off, F32(0.05), 5, workers=min(16, os.cpu_count() or 1))
+    return pts, off, ref
+
+
+def _first_bad_sets(got, ref, off, limit=5):
+    bad = np.flatnonzero(got != ref)
+    return sorted(set(np.searchsorted(off, bad, side="right") - 1))[:limit]
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_subhalo4096_every_set_bit_exact(ctx, subhalo4096, algo):
+    """The full 4,096-set workload (~133M points): every set's labels
+    against the oracle's clustering of that set alone."""
+    pts, off, ref = subhalo4096
     d = dev(pts)
-    got = ctx.cluster_batched(d, off, 0.05, 5).cpu().numpy()
-    got_db = ctx.cluster_batched(d, off, 0.05, 5, algorithm="densebox").cpu().numpy()
+    got = ctx.cluster_batched(d, off, 0.05, 5, algorithm=algo).cpu().numpy()
     del d
-    np.testing.assert_array_equal(got_db, got)
-    sizes = np.diff(off)
-    pick = set(np.random.Generator(np.random.PCG64(0)).choice(4096, 200, replace=False).tolist())
-    pick |= {int(sizes.argmax()), int(sizes.argmin())}
-    for s in sorted(pick):
-        a, b = off[s], off[s + 1]
-        np.testing.assert_array_equal(got[a:b], oracle.dbscan(pts[a:b], F32(0.05), 5),
-                                      err_msg=f"set {s}")
+    assert np.array_equal(got, ref), f"sets differ: {_first_bad_sets(got, ref, off)}"

@@ -395,10 +395,20 @@ def test_budget_too_small():
 
 # ---- full size -----------------------------------------------------------------
 
+def oracle_threads(fn):
+    """Run an oracle call with its counting and border steps on the host's
+    cores (at most 16, the box's share); labels do not depend on it."""
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    try:
+        return fn()
+    finally:
+        oracle.set_threads(1)
+
+
 @pytest.fixture(scope="module")
 def halo16m():
     p = datagen.config_points("halo16M")
-    return p, oracle.dbscan(p, F32(0.2), 2)
+    return p, oracle_threads(lambda: oracle.dbscan(p, F32(0.2), 2))
 
 
 def test_halo16m_minpts2_bit_exact(ctx, halo16m):
@@ -406,13 +416,15 @@ def test_halo16m_minpts2_bit_exact(ctx, halo16m):
     np.testing.assert_array_equal(run(ctx, p, F32(0.2), 2), ref)
 
 
-def test_halo16m_pair_count_equals_walk_count(ctx, halo16m):
+def test_halo16m_minpts3_both_core_modes_bit_exact(ctx, halo16m):
+    """minPts 3 on the 2^24-point field: core points from the counting walk
+    and from the pair traversal, each against the oracle."""
     p, _ = halo16m
+    ref = oracle_threads(lambda: oracle.dbscan(p, F32(0.2), 3))
+    assert (ref >= 0).any() and (ref < 0).any()
     d = dev(p)
-    a = ctx.cluster(d, 0.2, 3).cpu().numpy()
-    b = ctx.cluster(d, 0.2, 3, pair_count=True).cpu().numpy()
-    np.testing.assert_array_equal(a, b)
-    assert (a >= 0).any()
+    np.testing.assert_array_equal(ctx.cluster(d, 0.2, 3).cpu().numpy(), ref)
+    np.testing.assert_array_equal(ctx.cluster(d, 0.2, 3, pair_count=True).cpu().numpy(), ref)
 
 
 def test_autotune_returns_options_that_keep_labels(ctx):
