@@ -26,9 +26,10 @@
  *     current device, "host" pointers ordinary host memory;
  *   - the caller owns every buffer; the library keeps no pointer after a
  *     call returns;
- *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
- *     on it and the call returns once it has completed, so every status is
- *     synchronous;
+ *   - `stream` is a hipStream_t; NULL means the context's own stream (made
+ *     with default flags, so it is ordered with the null stream).  Work is
+ *     enqueued on it and the call returns once it has completed, so every
+ *     status is synchronous;
  *   - the return value is a status code (DBSCAN_OK or a negative error),
  *     never an exception; dbscan_last_error() gives a message for the
  *     calling thread's last failure.
@@ -45,8 +46,10 @@ extern "C" {
 /* ---- status codes ---------------------------------------------------------- */
 #define DBSCAN_OK 0
 #define DBSCAN_EINVAL (-1)     /* bad argument: null pointer with n > 0, n < 0,
-                                  n >= 2^30, eps NaN/inf/negative, eps*eps not
-                                  finite, min_pts < 1, bad option; labels untouched */
+                                  n >= 2^30 (the radix sort's look-back words
+                                  hold a 30-bit count), eps NaN/inf/negative,
+                                  eps*eps not finite, min_pts < 1, bad
+                                  option; labels untouched */
 #define DBSCAN_ENONFINITE (-2) /* a coordinate is NaN or infinite; labels unspecified */
 #define DBSCAN_ENOMEM (-3)     /* device memory allocation failed */
 #define DBSCAN_EDEVICE (-4)    /* HIP runtime error or a kernel-side failure */
@@ -64,8 +67,8 @@ extern "C" {
  * and minPts for a plain call; same sets count and total for a batched one,
  * whose per-set values are re-read at each replay) while the context's
  * scratch has not moved.  A context keeps up to 4 graphs.  Both algorithms
- * (DenseBox keeps its primitive count on the device).  Ignored with the null
- * stream; no timing in this mode. */
+ * (DenseBox keeps its primitive count on the device).  Ignored when the
+ * stream argument is NULL; no timing in this mode. */
 #define DBSCAN_FLAG_GRAPH 2u
 /* Plain FDBSCAN with min_pts > 2: find the core points by pair traversal
  * (every pair adds one to both points' neighbour counts; section 4.2.3

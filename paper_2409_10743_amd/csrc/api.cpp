@@ -138,6 +138,7 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
 struct dbscan_ctx {
   int device = 0;
   uint64_t budget = 0;
+  hipStream_t stream = nullptr;  // the context's own stream: where a NULL stream argument goes
   char* arena = nullptr;
   size_t cap = 0;
   uint32_t* host_status = nullptr;  // pinned
@@ -173,6 +174,11 @@ struct DeviceGuard {
     if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
   }
 };
+
+// The stream a call runs on: the caller's, or the context's own for NULL.
+hipStream_t stream_of(const dbscan_ctx* c, void* stream) {
+  return stream ? reinterpret_cast<hipStream_t>(stream) : c->stream;
+}
 
 int ensure_arena(dbscan_ctx* c, size_t bytes) {
   if (c->budget && bytes > c->budget)
@@ -843,6 +849,13 @@ int dbscan_ctx_create(int device, uint64_t hbm_budget_bytes, dbscan_ctx** out) {
       return fail(DBSCAN_EDEVICE, "hipEventCreate failed");
     }
   }
+  // default flags: ordered with the null stream, so NULL-stream work the
+  // caller enqueued before a call is finished when the call starts
+  if (hipStreamCreate(&c->stream) != hipSuccess) {
+    c->stream = nullptr;
+    dbscan_ctx_destroy(c);
+    return fail(DBSCAN_EDEVICE, "hipStreamCreate failed");
+  }
   *out = c;
   return DBSCAN_OK;
 }
@@ -857,6 +870,7 @@ int dbscan_ctx_destroy(dbscan_ctx* c) {
   if (c->stage) (void)hipHostFree(c->stage);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return DBSCAN_OK;
 }
@@ -877,11 +891,10 @@ int dbscan_cluster_ex(dbscan_ctx* c, const float* points, int64_t n, float eps, 
   if (n == 0) return DBSCAN_OK;
   DeviceGuard g(c->device);
   c->sort_items = o.sort_tile / SORT_THREADS;
+  if (!stream) o.flags &= ~DBSCAN_FLAG_GRAPH;  // graphs only on a stream the caller names
   if (o.algorithm == DBSCAN_ALGO_DENSEBOX)
-    return run_densebox(c, points, uint32_t(n), eps, min_pts, labels,
-                        reinterpret_cast<hipStream_t>(stream), o);
-  return run_fdbscan(c, points, uint32_t(n), eps, min_pts, labels,
-                     reinterpret_cast<hipStream_t>(stream), o);
+    return run_densebox(c, points, uint32_t(n), eps, min_pts, labels, stream_of(c, stream), o);
+  return run_fdbscan(c, points, uint32_t(n), eps, min_pts, labels, stream_of(c, stream), o);
 }
 
 int dbscan_cluster_batched(dbscan_ctx* c, const float* points, const int64_t* offsets,
@@ -905,8 +918,9 @@ int dbscan_cluster_batched(dbscan_ctx* c, const float* points, const int64_t* of
   if (n == 0) return DBSCAN_OK;
   DeviceGuard g(c->device);
   c->sort_items = o.sort_tile / SORT_THREADS;
+  if (!stream) o.flags &= ~DBSCAN_FLAG_GRAPH;  // graphs only on a stream the caller names
   return run_batched(c, points, offsets, uint32_t(num_sets), eps, min_pts, labels,
-                     reinterpret_cast<hipStream_t>(stream), o);
+                     stream_of(c, stream), o);
 }
 
 int dbscan_cluster(const float* points, int64_t n, float eps, int32_t min_pts, int32_t* labels,
@@ -961,7 +975,7 @@ int dbscan_morton_codes(dbscan_ctx* c, const float* points, int64_t n, uint64_t*
   int st = check_args(points, n, 0.0f, 1, codes);
   if (st != DBSCAN_OK || n == 0) return st;
   DeviceGuard g(c->device);
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipStream_t s = stream_of(c, stream);
   Layout L = make_layout(uint32_t(n), false);
   st = ensure_arena(c, L.total);
   if (st != DBSCAN_OK) return st;
@@ -982,7 +996,7 @@ int dbscan_sort_pairs(dbscan_ctx* c, uint64_t* keys, uint32_t* vals, int64_t n, 
   if (n > 0 && (!keys || !vals)) return fail(DBSCAN_EINVAL, "null pointer");
   if (n == 0) return DBSCAN_OK;
   DeviceGuard g(c->device);
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipStream_t s = stream_of(c, stream);
   Layout L = make_layout(uint32_t(n), false);
   int st = ensure_arena(c, L.total);
   if (st != DBSCAN_OK) return st;
@@ -1012,7 +1026,7 @@ int dbscan_build_tree(dbscan_ctx* c, const float* points, int64_t n, uint32_t* p
   if (n > 0 && (!leaf || !root || (n > 1 && !nodes))) return fail(DBSCAN_EINVAL, "null pointer");
   if (n == 0) return DBSCAN_OK;
   DeviceGuard g(c->device);
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipStream_t s = stream_of(c, stream);
   Index ix;
   c->sort_items = 0;  // the default sort tile
   st = build_index(c, points, uint32_t(n), false, false, s, &ix, 0.0f, nullptr, nullptr);
@@ -1032,7 +1046,7 @@ int dbscan_core_flags(dbscan_ctx* c, const float* points, int64_t n, float eps, 
   int st = check_args(points, n, eps, min_pts, core);
   if (st != DBSCAN_OK || n == 0) return st;
   DeviceGuard g(c->device);
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipStream_t s = stream_of(c, stream);
   Index ix;
   c->sort_items = 0;  // the default sort tile
   st = build_index(c, points, uint32_t(n), false, false, s, &ix, eps, nullptr, nullptr);
@@ -1061,7 +1075,7 @@ int dbscan_traversal_stats(dbscan_ctx* c, const float* points, int64_t n, float 
   if (st != DBSCAN_OK) return st;
   if (n == 0) { count[0] = count[1] = count[2] = count[3] = 0; return DBSCAN_OK; }
   DeviceGuard g(c->device);
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipStream_t s = stream_of(c, stream);
   Index ix;
   c->sort_items = 0;  // the default sort tile
   st = build_index(c, points, uint32_t(n), false, false, s, &ix, eps, nullptr, nullptr);
@@ -1091,7 +1105,7 @@ int dbscan_autotune(dbscan_ctx* c, const float* points, int64_t n, float eps, in
     if (best_ms) *best_ms = 0;
     return DBSCAN_OK;
   }
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipStream_t s = stream_of(c, stream);
   auto run = [&](const dbscan_options& o) {
     return dbscan_cluster_ex(c, points, n, eps, min_pts, labels, stream, &o);
   };
@@ -1116,7 +1130,7 @@ int dbscan_autotune_batched(dbscan_ctx* c, const float* points, const int64_t* o
     if (o.dense_threshold == mp_max) o.dense_threshold = 0;  // each set's own minPts
     cands.push_back(o);
   }
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipStream_t s = stream_of(c, stream);
   auto run = [&](const dbscan_options& o) {
     return dbscan_cluster_batched(c, points, offsets, num_sets, eps, min_pts, labels, stream,
                                   &o);
