@@ -15,6 +15,9 @@ set_threads(t)                    host threads of the counting and border
                                   steps (default 1)
 dbscan_sets(points, offsets, ...) independent sets, each clustered alone,
                                   sets spread over host threads
+knn(points, k, queries)           k nearest neighbours, self included, ties
+                                  to the smaller index (C, brute force)
+core_distances(points, min_pts)   squared distance to the min_pts-th nearest
 morton63(points)                  the 63-bit Morton code of every point,
                                   section 4.2.2 (numpy, plain definition)
 morton_order(codes)               stable sort permutation of the codes
@@ -39,6 +42,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dbscan_oracle.c")
+_KNN_SRC = os.path.join(_HERE, "knn_oracle.c")
 _LIB = os.path.join(_HERE, "_build", "liboracle.so")
 
 # The predicate must be evaluated exactly as written: no contraction into
@@ -52,7 +56,7 @@ def build(extra_flags=(), out=None) -> str:
     out = out or _LIB
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = ["gcc", *CFLAGS, *extra_flags, _SRC, "-o", tmp, "-lm"]
+    cmd = ["gcc", *CFLAGS, *extra_flags, _SRC, _KNN_SRC, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
     return out
@@ -82,6 +86,13 @@ def load(path: str | None = None) -> ctypes.CDLL:
                                       ctypes.POINTER(ctypes.c_int64)]
     lib.oracle_pair_count.restype = ctypes.c_int
     lib.oracle_version.restype = ctypes.c_char_p
+    lib.oracle_knn.argtypes = [f32p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                               ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                               f32p]
+    lib.oracle_knn.restype = ctypes.c_int
+    lib.knn_set_threads.argtypes = [ctypes.c_int]
+    lib.knn_set_threads.restype = ctypes.c_int
+    lib.knn_set_threads(1)
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_set_threads.restype = ctypes.c_int
     lib.oracle_set_threads(1)  # sequential unless asked otherwise
@@ -153,8 +164,36 @@ def dbscan_sets(points, offsets, eps, min_pts, workers: int = 1, lib=None) -> np
 
 def set_threads(t: int, lib=None) -> int:
     """Host threads of the counting and border steps (the union-find merge is
-    always sequential); 1 by default.  Labels do not depend on it."""
-    return int((lib or _get()).oracle_set_threads(int(t)))
+    always sequential) and of the kNN queries; 1 by default.  Results do not
+    depend on it."""
+    lib = lib or _get()
+    lib.knn_set_threads(int(t))
+    return int(lib.oracle_set_threads(int(t)))
+
+
+def knn(points, k: int, queries=None, lib=None):
+    """k nearest neighbours of each query (all points, or the given point
+    indices), the query itself included: (indices int32[nq, k], squared
+    distances float32[nq, k]) in increasing (D, index) order; -1 / inf past
+    the number of points.  See knn_oracle.c."""
+    lib = lib or _get()
+    p = _as_points(points)
+    q = None if queries is None else np.ascontiguousarray(queries, dtype=np.int64)
+    nq = p.shape[0] if q is None else q.size
+    idx = np.empty((nq, int(k)), dtype=np.int32)
+    d2 = np.empty((nq, int(k)), dtype=np.float32)
+    st = lib.oracle_knn(_ptr(p, ctypes.c_float), p.shape[0],
+                        None if q is None else _ptr(q, ctypes.c_int64), nq, int(k),
+                        _ptr(idx, ctypes.c_int32), _ptr(d2, ctypes.c_float))
+    if st != 0:
+        raise OracleError(st)
+    return idx, d2
+
+
+def core_distances(points, min_pts: int, queries=None, lib=None) -> np.ndarray:
+    """HDBSCAN*'s core distance, squared: D to the min_pts-th nearest
+    neighbour, the point itself counted (inf if there are fewer points)."""
+    return knn(points, min_pts, queries, lib)[1][:, int(min_pts) - 1].copy()
 
 
 def core_flags(points, eps, min_pts, lib=None) -> np.ndarray:
