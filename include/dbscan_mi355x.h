@@ -135,6 +135,7 @@ int dbscan_cluster_batched(dbscan_ctx* ctx, const float* points, const int64_t* 
 int dbscan_cluster_host(const float* host_points, int64_t n, float eps,
                         int32_t min_pts, int32_t* host_labels);
 
+
 /* Per-phase device times (ms) of the context's last call made with
  * DBSCAN_FLAG_TIMING, in the order of dbscan_phase_name(); returns how many
  * were written (at most max). */
@@ -179,9 +180,12 @@ int dbscan_autotune_batched(dbscan_ctx* ctx, const float* points, const int64_t*
  * Work of several jobs is on the device at once (`slots` worker threads, each
  * with its own stream and resident device arena); small jobs (n < batch_cut)
  * waiting in the queue are clustered together in one batched call (the
- * batched entry point above); a job starts only when the device bytes it
- * needs fit in hbm_budget_bytes next to the jobs in flight.  Results are
- * identical to dbscan_cluster on each job alone.  Thread-safe. */
+ * batched entry point above).  hbm_budget_bytes bounds the device memory the
+ * slots hold, which they keep between jobs: a job starts on a slot only if
+ * that slot's memory after the job fits next to what the other slots hold
+ * (idle slots give theirs back first); a job that could never fit fails with
+ * DBSCAN_ETOOBIG.  Results are identical to dbscan_cluster on each job
+ * alone.  Thread-safe. */
 typedef struct dbscan_server dbscan_server;
 
 typedef struct dbscan_server_options {
@@ -200,7 +204,8 @@ typedef struct dbscan_server_options {
 typedef struct dbscan_serving_stats {
   uint64_t submitted, completed, failed, points;
   uint64_t batches, batched_jobs;   /* batched calls made, jobs they held */
-  uint64_t peak_in_flight_bytes;
+  uint64_t peak_in_flight_bytes;    /* most device bytes the slots held (arenas and
+                                       I/O buffers, kept between jobs) or had reserved */
   double p50_ms, p99_ms, mean_ms, max_ms;  /* latency: completion - submit */
   double mpoints_per_s;             /* points / (last completion - first submit) */
 } dbscan_serving_stats;
@@ -263,6 +268,26 @@ int dbscan_pair_count(dbscan_ctx* ctx, const float* points, int64_t n, float eps
  * was within eps (the walk descended), out4[3] leaf tests. */
 int dbscan_traversal_stats(dbscan_ctx* ctx, const float* points, int64_t n, float eps,
                            int64_t* out4, void* stream);
+
+/* ---- nearest neighbours and core distances ---------------------------------- */
+/* The k nearest neighbours of every point (section 3.2, the nearest search:
+ * a given number of the closest points, whatever their distance), the point
+ * itself included, over the same linear BVH (built with full 63-bit codes).
+ * Neighbours are ranked by (D, input index), D the binary32 squared distance
+ * of the clustering predicate ((dx*dx + dy*dy) + dz*dz, no fused
+ * multiply-add), so the answer is unique.  1 <= k <= 32, else EINVAL.
+ *   indices  device int32[n][k], row i = point i's neighbours in rank order,
+ *            -1 past the n-th;
+ *   sq_dists device float[n][k], their D (+inf past the n-th).
+ * Errors as for dbscan_cluster_ex (non-finite coordinates: ENONFINITE). */
+int dbscan_knn(dbscan_ctx* ctx, const float* points, int64_t n, int32_t k,
+               int32_t* indices, float* sq_dists, void* stream);
+/* HDBSCAN*'s core distance of every point (section 5 names HDBSCAN* as the
+ * next algorithm on this tree), squared: D to the min_pts-th nearest
+ * neighbour, the point itself counted (+inf when n < min_pts); sq_dists:
+ * device float[n], input order.  1 <= min_pts <= 32. */
+int dbscan_core_distances(dbscan_ctx* ctx, const float* points, int64_t n, int32_t min_pts,
+                          float* sq_dists, void* stream);
 
 /* ---- diagnostics ------------------------------------------------------------ */
 const char* dbscan_strerror(int status);

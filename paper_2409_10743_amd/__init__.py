@@ -111,6 +111,8 @@ def load_library() -> ctypes.CDLL:
         "dbscan_autotune_batched": ([vp, vp, ctypes.POINTER(i64), i32, ctypes.POINTER(f32),
                                      ctypes.POINTER(i32), vp, ctypes.POINTER(_Options),
                                      ctypes.POINTER(f32), vp], ctypes.c_int),
+        "dbscan_knn": ([vp, vp, i64, i32, vp, vp, vp], ctypes.c_int),
+        "dbscan_core_distances": ([vp, vp, i64, i32, vp, vp], ctypes.c_int),
         "dbscan_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "dbscan_last_error": ([], ctypes.c_char_p),
         "dbscan_version": ([], ctypes.c_char_p),
@@ -410,6 +412,31 @@ class Context:
         return {"pairs": out[0], "internal_visits": out[1], "descents": out[2],
                 "leaf_tests": out[3]}
 
+    def knn(self, points, k: int):
+        """k nearest neighbours of every point, itself included: (indices
+        int32 [n, k], squared distances float32 [n, k]) on the points'
+        device, ranked by (squared distance, index); -1 / inf past n."""
+        torch = _torch()
+        p = _points(points)
+        n = p.shape[0]
+        idx = torch.empty((n, int(k)), dtype=torch.int32, device=p.device)
+        d2 = torch.empty((n, int(k)), dtype=torch.float32, device=p.device)
+        _check(load_library().dbscan_knn(
+            self.handle, ctypes.c_void_p(p.data_ptr()), n, int(k),
+            ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(d2.data_ptr()), _stream(p.device)))
+        return idx, d2
+
+    def core_distances(self, points, min_pts: int):
+        """HDBSCAN*'s squared core distance of every point: the squared
+        distance to its min_pts-th nearest neighbour, itself counted."""
+        torch = _torch()
+        p = _points(points)
+        d2 = torch.empty(p.shape[0], dtype=torch.float32, device=p.device)
+        _check(load_library().dbscan_core_distances(
+            self.handle, ctypes.c_void_p(p.data_ptr()), p.shape[0], int(min_pts),
+            ctypes.c_void_p(d2.data_ptr()), _stream(p.device)))
+        return d2
+
     def pair_count(self, points, eps: float) -> int:
         p = _points(points)
         out = ctypes.c_int64(0)
@@ -504,3 +531,4 @@ def cluster(points, eps: float, min_pts: int, out=None):
         ctypes.c_void_p(p.data_ptr()), n, ctypes.c_float(eps), int(min_pts),
         ctypes.c_void_p(labels.data_ptr()), _stream(p.device)))
     return labels
+

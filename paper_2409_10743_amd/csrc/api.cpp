@@ -79,7 +79,7 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
     return at;
   };
   L.keys_a = take(size_t(n) * 8);
-  L.keys_b = take(size_t(n) * 8);  // after the sort: union-find scratch of the build
+  L.keys_b = take(size_t(n) * 8);  // after the sort: the build's exchange slots
   L.vals_a = take(size_t(n) * 4);
   L.vals_b = take(size_t(n) * 4);
   L.leaf = take((size_t(n) + 1) * 16);  // + one padding record read by the walks
@@ -431,18 +431,18 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
     unsigned long long* bestcore =
         core_mode ? at<unsigned long long>(c, L.bestcore) : nullptr;
     if (pair_count)
-      launch_count_pairs(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, min_pts, deg,
-                         flag, ix.status, block, gs);
+      launch_count_pairs(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, min_pts,
+                         deg, flag, ix.status, block, gs);
     else if (core_mode)
-      launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, ix.root, e2, min_pts,
-                   flag, ix.status, block, gs);
+      launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, ix.root, e2,
+                   min_pts, flag, ix.status, block, gs);
     mark(c, timing, PH_COUNT, gs);
     if (core_mode)
       launch_pairs_core(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, flag,
                         ix.perm, parent, bestcore, ix.status, block, gs);
     else
-      launch_pairs_fof(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, ix.perm, parent, flag,
-                       ix.status, block, gs);
+      launch_pairs_fof(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, ix.perm,
+                       parent, flag, ix.status, block, gs);
     mark(c, timing, PH_PAIRS, gs);
     int32_t* minlab = core_mode ? at<int32_t>(c, L.minlab) : nullptr;
     launch_final(n, min_pts, flag, bestcore, ix.perm, parent, minlab, labels, gs);
@@ -586,6 +586,24 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
   return finish(c, status, timing, s);
 }
 
+// Byte offsets of a batched call's per-set arrays, after the job's buffers:
+// offsets, e2, minPts, dense threshold, inverse cell side, roots, grids.
+struct SetLayout {
+  size_t off, e2, mp, th, ih, root, grid, total;
+};
+SetLayout make_set_layout(const Layout& L, uint32_t num_sets) {
+  SetLayout S{};
+  S.off = align_up(L.total);
+  S.e2 = S.off + align_up((size_t(num_sets) + 1) * 8);
+  S.mp = S.e2 + align_up(size_t(num_sets) * 4);
+  S.th = S.mp + align_up(size_t(num_sets) * 4);
+  S.ih = S.th + align_up(size_t(num_sets) * 4);
+  S.root = S.ih + align_up(size_t(num_sets) * 4);
+  S.grid = S.root + align_up(size_t(num_sets) * 4);
+  S.total = S.grid + align_up(size_t(num_sets) * sizeof(MortonGrid));
+  return S;
+}
+
 // Many independent sets in one pass (keys tagged with the set id).
 int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t num_sets,
                 const float* h_eps, const int32_t* h_minpts, int32_t* labels, hipStream_t s,
@@ -603,17 +621,10 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
   for (uint32_t k = 0; k < num_sets; ++k) any_core |= h_minpts[k] > 2;
 
   Layout L = make_layout(n, any_core, db);
-  // per-set arrays after the job's buffers: offsets, e2, minPts, dense
-  // threshold, inverse cell side, roots, grids
-  const size_t off_b = align_up(L.total);
-  const size_t e2_b = off_b + align_up((size_t(num_sets) + 1) * 8);
-  const size_t mp_b = e2_b + align_up(size_t(num_sets) * 4);
-  const size_t th_b = mp_b + align_up(size_t(num_sets) * 4);
-  const size_t ih_b = th_b + align_up(size_t(num_sets) * 4);
-  const size_t root_b = ih_b + align_up(size_t(num_sets) * 4);
-  const size_t grid_b = root_b + align_up(size_t(num_sets) * 4);
-  const size_t total = grid_b + align_up(size_t(num_sets) * sizeof(MortonGrid));
-  int st = ensure_arena(c, total);
+  const SetLayout SL = make_set_layout(L, num_sets);
+  const size_t off_b = SL.off, e2_b = SL.e2, mp_b = SL.mp, th_b = SL.th, ih_b = SL.ih,
+               root_b = SL.root, grid_b = SL.grid;
+  int st = ensure_arena(c, SL.total);
   if (st != DBSCAN_OK) return st;
   const size_t stage_bytes = (size_t(num_sets) + 1) * 8 + size_t(num_sets) * 16;
   if (c->stage_cap < stage_bytes) {
@@ -828,6 +839,35 @@ std::vector<dbscan_options> candidates(int32_t algorithm, int32_t min_pts) {
 }
 }  // namespace
 
+// ---- what the job server needs to know about a context ------------------------
+namespace dbx {
+// Device bytes a context holds (its arena).
+uint64_t ctx_arena_bytes(const dbscan_ctx* c) { return c ? c->cap : 0; }
+// Cap on the context's arena (0 = none): a grow takes 1/8 headroom only
+// when that stays under it.
+void ctx_set_budget(dbscan_ctx* c, uint64_t bytes) { c->budget = bytes; }
+// Free the arena (and the graphs captured over it); the next call grows it
+// again.
+int ctx_release_arena(dbscan_ctx* c) {
+  DeviceGuard g(c->device);
+  if (c->stream) HIP_TRY(hipStreamSynchronize(c->stream));
+  for (auto& e : c->graphs) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    e = dbscan_ctx::Graph{};
+  }
+  if (c->arena) HIP_TRY(hipFree(c->arena));
+  c->arena = nullptr;
+  c->cap = 0;
+  return DBSCAN_OK;
+}
+// Arena bytes of a batched FDBSCAN call over `sets` sets of `n` points in
+// all (the per-set arrays included).
+uint64_t batched_scratch_bytes(int64_t n, uint32_t sets, bool any_core) {
+  if (n < 0 || n > int64_t(SORT_MAX_N)) return 0;
+  return make_set_layout(make_layout(uint32_t(n), any_core, false), sets).total;
+}
+}  // namespace dbx
+
 extern "C" {
 
 int dbscan_ctx_create(int device, uint64_t hbm_budget_bytes, dbscan_ctx** out) {
@@ -955,6 +995,7 @@ int dbscan_cluster_host(const float* host_points, int64_t n, float eps, int32_t 
   (void)hipFree(dl);
   return st;
 }
+
 
 int dbscan_phase_times(const dbscan_ctx* c, float* ms, int32_t max) {
   if (!c || !ms || max < 0) return 0;
@@ -1089,6 +1130,37 @@ int dbscan_traversal_stats(dbscan_ctx* c, const float* points, int64_t n, float 
   if (st == DBSCAN_OK)
     for (int k = 0; k < 4; ++k) count[k] = int64_t(h[k]);
   return st;
+}
+
+// k nearest neighbours / core distances: the tree with full 63-bit codes
+// (no eps to drop code bits for), then one walk per point.
+static int knn_common(dbscan_ctx* c, const float* points, int64_t n, int32_t k,
+                      int32_t* idx, float* d2, float* core, void* stream) {
+  if (!c) return fail(DBSCAN_EINVAL, "null context");
+  int st = check_args(points, n, 0.0f, 1, core ? static_cast<void*>(core) : idx);
+  if (st != DBSCAN_OK) return st;
+  if (k < 1 || k > KNN_MAX_K) return fail(DBSCAN_EINVAL, "k must be in [1, 32]");
+  if (n > 0 && !core && !d2) return fail(DBSCAN_EINVAL, "null pointer");
+  if (n == 0) return DBSCAN_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = stream_of(c, stream);
+  Index ix;
+  c->sort_items = 0;  // the default sort tile
+  st = build_index(c, points, uint32_t(n), false, false, s, &ix, 0.0f, nullptr, nullptr);
+  if (st != DBSCAN_OK) return st;
+  launch_knn(ix.nodes, ix.leaf, ix.perm, uint32_t(n), ix.root, k, idx, d2, core, ix.status, s);
+  HIP_TRY(hipGetLastError());
+  return finish(c, ix.status, false, s);
+}
+
+int dbscan_knn(dbscan_ctx* c, const float* points, int64_t n, int32_t k, int32_t* indices,
+               float* sq_dists, void* stream) {
+  return knn_common(c, points, n, k, indices, sq_dists, nullptr, stream);
+}
+
+int dbscan_core_distances(dbscan_ctx* c, const float* points, int64_t n, int32_t min_pts,
+                          float* sq_dists, void* stream) {
+  return knn_common(c, points, n, min_pts, nullptr, nullptr, sq_dists, stream);
 }
 
 int dbscan_autotune(dbscan_ctx* c, const float* points, int64_t n, float eps, int32_t min_pts,

@@ -315,7 +315,7 @@ void launch_count_sets(const Node* nodes, const float4* leaf, uint32_t n, const 
                        const int32_t* set_minpts, const MortonGrid* grids, uint8_t* flag,
                        uint32_t* queue, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
-  if (walk_persistent(SETS_PERSIST_COUNT)) {
+  if (SETS_PERSIST_COUNT) {
     const uint32_t grid = persistent_blocks(reinterpret_cast<const void*>(&k_count_sets<true>),
                                             block, 0, walk_grid(n, block));
     hipLaunchKernelGGL(k_count_sets<true>, dim3(grid), dim3(block), 0, s, nodes, leaf, n,
@@ -334,7 +334,7 @@ void launch_pairs_sets(const Node* nodes, const float4* leaf, uint32_t n, const 
                        uint8_t* flag, unsigned long long* bestcore, uint32_t* queue,
                        uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
-  if (walk_persistent(SETS_PERSIST_PAIRS)) {
+  if (SETS_PERSIST_PAIRS) {
     const uint32_t grid = persistent_blocks(reinterpret_cast<const void*>(&k_pairs_sets<true>),
                                             block, 0, walk_grid(n, block));
     hipLaunchKernelGGL(k_pairs_sets<true>, dim3(grid), dim3(block), 0, s, nodes, leaf, n,

@@ -762,7 +762,7 @@ void launch_count_db(const Node* nodes, const Node* prims, const uint64_t* pkey,
   if (np_bound == 0) return;
   const DbData D{t.pts, t.cell_start, t.perm, t.cell_minorig, t.cell_lo, t.cell_hi, t.parent,
                  t.flag, t.bestcore};
-  if (walk_persistent(DB_PERSIST_COUNT)) {
+  if (DB_PERSIST_COUNT) {
     const uint32_t grid = persistent_blocks(reinterpret_cast<const void*>(&k_count_db<true>), block,
                                             queue_lds(block), walk_grid(np_bound, block));
     hipLaunchKernelGGL(k_count_db<true>, dim3(grid), dim3(block), queue_lds(block), s, nodes, prims,
@@ -781,7 +781,7 @@ void launch_pairs_db(const Node* nodes, const Node* prims, const uint64_t* pkey,
   if (np_bound == 0) return;
   const DbData D{t.pts, t.cell_start, t.perm, t.cell_minorig, t.cell_lo, t.cell_hi, t.parent,
                  t.flag, t.bestcore};
-  if (walk_persistent(sets.shift < 64)) {  // batched
+  if (sets.shift < 64) {  // batched
     const uint32_t grid = persistent_blocks(reinterpret_cast<const void*>(&k_pairs_db<true>), block,
                                             queue_lds(block), walk_grid(np_bound, block));
     hipLaunchKernelGGL(k_pairs_db<true>, dim3(grid), dim3(block), queue_lds(block), s, nodes, prims,

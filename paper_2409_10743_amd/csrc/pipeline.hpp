@@ -22,9 +22,6 @@ constexpr int RADIX = 256;
 constexpr int SORT_PASSES = 8;                          // 8-bit digits of 64
 constexpr uint32_t SORT_MAX_N = (1u << 30) - 1;         // 30-bit look-back counts
 
-// Keys per thread of the sort's pass kernel: 16 unless the environment
-// variable DBX_SORT_ITEMS (8, 12 or 16) overrides it for tuning runs.
-int sort_items();
 inline uint32_t sort_tiles(uint32_t n, int items) {
   const uint32_t tile = uint32_t(SORT_THREADS * items);
   return (n + tile - 1) / tile;
@@ -66,7 +63,7 @@ void launch_digit_histogram(const uint64_t* keys, uint32_t n, uint32_t* hist,
 // the input values are taken to be 0..n-1 and `va` is not read.  Returns
 // true when the result ends in the A buffers.
 // `after_pass(arg, p)`, if given, is called after pass p is enqueued.
-// items: keys per thread of a tile (8, 12 or 16; 0 = sort_items()).
+// items: keys per thread of a tile (8, 12 or 16; 0 = SORT_ITEMS).
 bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
                        uint32_t n, int first_pass, bool iota_vals,
                        const SortScratch& sc, hipStream_t s,
@@ -137,31 +134,43 @@ void launch_build_boxes(const uint64_t* keys, int set_shift, Node* prims, uint32
 // made with; drop: the number of low code bits the keys cleared (null: 0)
 // (all three for the walks' early end).
 void launch_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
-                  const uint32_t* bounds, const uint32_t* drop, uint32_t n, const int32_t* root,
-                  float e2, int32_t min_pts, uint8_t* is_core, uint32_t* err, int block,
-                  hipStream_t s);
+                  const uint32_t* bounds, const uint32_t* drop,
+                  uint32_t n, const int32_t* root, float e2, int32_t min_pts, uint8_t* is_core,
+                  uint32_t* err, int block, hipStream_t s);
 // Core flags by pair traversal: each pair adds one to both points' counts
 // in deg (zero beforehand), then is_core[i] = deg[i] + 1 >= min_pts.  No
 // early exit: for fields where points have few neighbours.
 void launch_count_pairs(const Node* nodes, const float4* leaf, const uint64_t* keys,
-                        const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
-                        int32_t min_pts, uint32_t* deg, uint8_t* is_core, uint32_t* err,
-                        int block, hipStream_t s);
+                        const uint32_t* bounds, const uint32_t* drop,
+                        uint32_t n, float e2, int32_t min_pts, uint32_t* deg, uint8_t* is_core,
+                        uint32_t* err, int block, hipStream_t s);
 // minPts <= 2: every point with a neighbour is core; union every pair.
 void launch_pairs_fof(const Node* nodes, const float4* leaf, const uint64_t* keys,
-                      const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
-                      const uint32_t* perm, int32_t* parent, uint8_t* member, uint32_t* err,
-                      int block, hipStream_t s);
+                      const uint32_t* bounds, const uint32_t* drop,
+                      uint32_t n, float e2, const uint32_t* perm, int32_t* parent,
+                      uint8_t* member, uint32_t* err, int block, hipStream_t s);
 // minPts > 2: union core pairs, record each non-core point's smallest-index
 // core neighbour.
 void launch_pairs_core(const Node* nodes, const float4* leaf, const uint64_t* keys,
-                       const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
-                       const uint8_t* is_core, const uint32_t* perm, int32_t* parent,
-                       unsigned long long* bestcore, uint32_t* err, int block, hipStream_t s);
+                       const uint32_t* bounds, const uint32_t* drop,
+                       uint32_t n, float e2, const uint8_t* is_core, const uint32_t* perm,
+                       int32_t* parent, unsigned long long* bestcore, uint32_t* err, int block,
+                       hipStream_t s);
 // Pair traversal with F(i, j) = count: every pair exactly once.
 void launch_pairs_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
-                        const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
-                        unsigned long long* count, uint32_t* err, int block, hipStream_t s);
+                        const uint32_t* bounds, const uint32_t* drop,
+                        uint32_t n, float e2, unsigned long long* count, uint32_t* err,
+                        int block, hipStream_t s);
+
+// ---- k nearest neighbours (knn.hip) ----------------------------------------------
+constexpr int32_t KNN_MAX_K = 32;
+// k nearest neighbours (1 <= k <= KNN_MAX_K) of every point over the built
+// tree, the point itself included, by (squared distance, input index): into
+// out_idx / out_d2 (int32 / float [n][k], input order; -1 / +inf past n),
+// or, with core_d2 (float[n], input order), only the k-th squared distance.
+void launch_knn(const Node* nodes, const float4* leaf, const uint32_t* perm, uint32_t n,
+                const int32_t* root, int32_t k, int32_t* out_idx, float* out_d2, float* core_d2,
+                uint32_t* err, hipStream_t s);
 
 // ---- labels (finalize.hip) --------------------------------------------------
 // Labels of the sorted points into input order; labels must hold -1 for

@@ -246,14 +246,6 @@ void launch_digit_histogram(const uint64_t* keys, uint32_t n, uint32_t* hist,
   hipLaunchKernelGGL(k_digit_hist, dim3(blocks), dim3(256), 0, s, keys, n, hist);
 }
 
-int sort_items() {
-  static const int items = [] {
-    const char* e = std::getenv("DBX_SORT_ITEMS");
-    int v = e ? std::atoi(e) : SORT_ITEMS;
-    return (v == 8 || v == 12 || v == 16) ? v : SORT_ITEMS;
-  }();
-  return items;
-}
 
 namespace {
 // one pass from (kin, vin) to (kout, vout); with `drop`, the kernel picks
@@ -286,7 +278,7 @@ bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
                        void (*after_pass)(void*, int), void* arg, int tile_items) {
   bool in_a = true;
   if (n == 0) return true;
-  const int items = tile_items ? tile_items : sort_items();
+  const int items = tile_items ? tile_items : SORT_ITEMS;
   const uint32_t words = sort_tiles(n, items) * RADIX;
   for (int p = first_pass; p < SORT_PASSES; ++p) {
     const uint64_t* kin = in_a ? ka : kb;
@@ -309,7 +301,7 @@ void launch_radix_sort_dropped(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_
                                hipStream_t s, void (*after_pass)(void*, int), void* arg,
                                int tile_items) {
   if (n == 0) return;
-  const int items = tile_items ? tile_items : sort_items();
+  const int items = tile_items ? tile_items : SORT_ITEMS;
   const uint32_t words = sort_tiles(n, items) * RADIX;
   for (int p = 0; p < SORT_PASSES; ++p) {
     uint32_t* st = sc.status + size_t(p) * words;

@@ -9,9 +9,14 @@
 //     batch_cut) also takes every other queued small job, up to
 //     batch_max_points / batch_max_jobs, and runs them as one batched call
 //     (independent sets of one pass); large jobs run alone;
-//   * admission: a job (or batch) starts only if the device bytes it needs
-//     (scratch + points + labels) fit in the budget next to everything in
-//     flight; a job that could never fit fails with DBSCAN_ETOOBIG;
+//   * admission: the budget bounds the device memory the slots hold, which
+//     outlives the jobs (each slot keeps its arena and I/O buffers for the
+//     next one).  A job (or batch) starts on a slot only if that slot's
+//     memory after the job (grown, if needed, to the job's scratch, in the
+//     batched layout for a batch, and I/O) fits next to what the other slots
+//     hold; when it does not, idle slots give their memory back, and if it
+//     still does not fit the job waits for running ones.  A job that could
+//     never fit fails with DBSCAN_ETOOBIG;
 //   * a batch that fails on a non-finite coordinate is re-run job by job so
 //     only the offending job reports the error;
 //   * latency = completion - submit; p50/p99 over completed jobs.
@@ -33,6 +38,14 @@
 #include <vector>
 
 #include "../../include/dbscan_mi355x.h"
+
+// what the server needs from a context (api.cpp)
+namespace dbx {
+uint64_t ctx_arena_bytes(const dbscan_ctx* c);
+void ctx_set_budget(dbscan_ctx* c, uint64_t bytes);
+int ctx_release_arena(dbscan_ctx* c);
+uint64_t batched_scratch_bytes(int64_t n, uint32_t sets, bool any_core);
+}  // namespace dbx
 
 namespace {
 
@@ -59,7 +72,13 @@ struct Slot {
   hipStream_t stream = nullptr;
   float* d_pts = nullptr;
   int32_t* d_lab = nullptr;
-  size_t cap = 0;  // points the device I/O buffers hold
+  size_t cap = 0;          // points the device I/O buffers hold
+  uint64_t arena = 0;      // bytes of the context's arena
+  uint64_t held = 0;       // device bytes charged to the slot (held, or reserved while busy)
+  bool busy = false;
+  uint64_t arena_cap = 0;  // the budget the next call's arena may grow to (0: none)
+  size_t io_target = 0;    // points the I/O buffers grow to for the next call
+  uint64_t arena_target = 0;  // the arena the next call will hold (fake executor)
   std::thread th;
 };
 
@@ -72,7 +91,7 @@ struct dbscan_server {
   std::deque<Job*> queue;
   std::unordered_map<uint64_t, std::unique_ptr<Job>> jobs;
   uint64_t next_ticket = 1;
-  uint64_t in_flight_bytes = 0, peak_bytes = 0;
+  uint64_t held_bytes = 0, peak_bytes = 0;  // device bytes the slots hold or have reserved
   int running = 0;
   bool stop = false;
   std::vector<std::unique_ptr<Slot>> slots;
@@ -84,10 +103,29 @@ struct dbscan_server {
 
 namespace {
 
-uint64_t job_bytes(int64_t n, int32_t min_pts) {
-  return dbscan_scratch_bytes(n, min_pts, DBSCAN_ALGO_FDBSCAN) + uint64_t(n) * 16 + 4096;
+constexpr uint64_t IO_BYTES_PER_POINT = 16;  // points in (12) and labels out (4)
+
+// Arena bytes of a job (one set) or a batch (several sets, batched layout).
+uint64_t scratch_of(const std::vector<Job*>& b) {
+  int64_t total = 0;
+  bool any_core = false;
+  for (Job* j : b) {
+    total += j->n;
+    any_core |= j->min_pts > 2;
+  }
+  if (b.size() == 1) return dbscan_scratch_bytes(total, b[0]->min_pts, DBSCAN_ALGO_FDBSCAN);
+  return dbx::batched_scratch_bytes(total, uint32_t(b.size()), any_core);
 }
 
+// Bytes a buffer of `have` grows to for `need` within `limit` (0: none): 1/8
+// headroom when that fits, else exactly `need`; unchanged if it holds it.
+uint64_t grown(uint64_t have, uint64_t need, uint64_t limit) {
+  if (need <= have) return have;
+  const uint64_t want = need + need / 8;
+  return limit && want > limit ? need : want;
+}
+
+// I/O buffers of at least n points (s->io_target when they grow).
 int grow_io(Slot* s, size_t n) {
   if (n <= s->cap) return DBSCAN_OK;
   if (s->d_pts) (void)hipFree(s->d_pts);
@@ -95,7 +133,7 @@ int grow_io(Slot* s, size_t n) {
   s->d_pts = nullptr;
   s->d_lab = nullptr;
   s->cap = 0;
-  const size_t want = n + n / 8;
+  const size_t want = std::max(n, s->io_target);
   if (hipMalloc(&s->d_pts, want * 12) != hipSuccess || hipMalloc(&s->d_lab, want * 4) != hipSuccess) {
     (void)hipGetLastError();
     return DBSCAN_ENOMEM;
@@ -104,20 +142,78 @@ int grow_io(Slot* s, size_t n) {
   return DBSCAN_OK;
 }
 
+// Give back an idle slot's device memory (lock held; the slot runs nothing).
+void release(dbscan_server* S, Slot* s) {
+  if (!S->opt.fake_executor) {
+    if (s->ctx) (void)dbx::ctx_release_arena(s->ctx);
+    if (s->d_pts) (void)hipFree(s->d_pts);
+    if (s->d_lab) (void)hipFree(s->d_lab);
+  }
+  s->d_pts = nullptr;
+  s->d_lab = nullptr;
+  s->cap = 0;
+  s->arena = 0;
+  S->held_bytes -= s->held;
+  s->held = 0;
+}
+
+enum class Admit { RUN, WAIT, NEVER };
+
+// May slot s run a batch needing `scratch` arena bytes and `total` points of
+// I/O now (lock held)?  On RUN the slot's charge is raised to what it will
+// hold afterwards and s->arena_cap is the cap its arena may grow to.
+Admit admit(dbscan_server* S, Slot* s, uint64_t scratch, int64_t total) {
+  const uint64_t B = S->opt.hbm_budget_bytes;
+  const uint64_t io_need = uint64_t(total) * IO_BYTES_PER_POINT;
+  if (B && scratch + io_need > B) return Admit::NEVER;
+  auto others = [&] { return S->held_bytes - s->held; };
+  // what the slot holds afterwards, with no headroom: the least it can be
+  auto least = [&] {
+    return std::max(s->arena, scratch) + std::max(uint64_t(s->cap) * IO_BYTES_PER_POINT, io_need);
+  };
+  if (B && others() + least() > B) {
+    for (auto& o : S->slots)  // idle slots give their memory back
+      if (o.get() != s && !o->busy && o->held) release(S, o.get());
+  }
+  if (B && others() + least() > B) {
+    bool others_busy = false;
+    for (auto& o : S->slots) others_busy |= o.get() != s && o->busy;
+    if (others_busy) return Admit::WAIT;
+    release(S, s);  // alone on the device: start from nothing
+    if (others() + least() > B) return Admit::WAIT;  // cannot happen: checked above
+  }
+  // within what is left, the arena grows with headroom where it fits, then the I/O
+  const uint64_t room = B ? B - others() : 0;
+  const uint64_t io_after = std::max(uint64_t(s->cap) * IO_BYTES_PER_POINT, io_need);
+  const uint64_t arena_after = grown(s->arena, scratch, B ? room - io_after : 0);
+  const uint64_t io_final = grown(uint64_t(s->cap) * IO_BYTES_PER_POINT, io_need,
+                                  B ? room - arena_after : 0);
+  s->arena_cap = B ? room - io_final : 0;
+  s->arena_target = arena_after;
+  s->io_target = size_t(io_final / IO_BYTES_PER_POINT);
+  S->held_bytes += arena_after + io_final - s->held;
+  s->held = arena_after + io_final;
+  S->peak_bytes = std::max(S->peak_bytes, S->held_bytes);
+  return Admit::RUN;
+}
+
 // Runs a batch (one job = a plain call) on the slot's stream; fills each
 // job's status.  Host buffers are copied in and out on the same stream.
 void execute(dbscan_server* S, Slot* s, std::vector<Job*>& batch) {
   int64_t total = 0;
   for (Job* j : batch) total += j->n;
-  if (S->opt.fake_executor) {
+  if (S->opt.fake_executor) {  // holds what a real run would hold, allocates nothing
     const double us = S->opt.fake_us_per_mpoint * double(total) / 1e6 + 1.0;
     std::this_thread::sleep_for(std::chrono::duration<double, std::micro>(us));
     for (Job* j : batch) {
       for (int64_t i = 0; i < j->n; ++i) j->labels[i] = -1;
       j->status = DBSCAN_OK;
     }
+    s->arena = std::max(s->arena, s->arena_target);
+    s->cap = std::max(s->cap, std::max(size_t(total), s->io_target));
     return;
   }
+  dbx::ctx_set_budget(s->ctx, s->arena_cap);
   int st = grow_io(s, size_t(total));
   if (st == DBSCAN_OK) {
     int64_t o = 0;
@@ -157,8 +253,10 @@ void execute(dbscan_server* S, Slot* s, std::vector<Job*>& batch) {
     }
     if (hipStreamSynchronize(s->stream) != hipSuccess) st = DBSCAN_EDEVICE;
   }
+  s->arena = dbx::ctx_arena_bytes(s->ctx);
   if (st == DBSCAN_ENONFINITE && batch.size() > 1) {
     // isolate the offending job(s): run the batch again one job at a time
+    // (each needs less than the batch, which the slot already holds)
     for (Job* j : batch) {
       std::vector<Job*> one{j};
       execute(S, s, one);
@@ -168,63 +266,85 @@ void execute(dbscan_server* S, Slot* s, std::vector<Job*>& batch) {
   for (Job* j : batch) j->status = st;
 }
 
+// The batch a slot takes: the queue's head, plus (if it is small) every
+// other queued small job within the batch limits (lock held).
+std::vector<Job*> take_batch(dbscan_server* S) {
+  std::vector<Job*> batch;
+  Job* head = S->queue.front();
+  S->queue.pop_front();
+  batch.push_back(head);
+  int64_t total = head->n;
+  bool any_core = head->min_pts > 2;
+  const uint64_t B = S->opt.hbm_budget_bytes;
+  if (head->n < S->opt.batch_cut) {
+    for (auto it = S->queue.begin(); it != S->queue.end();) {
+      Job* j = *it;
+      const int64_t t2 = total + j->n;
+      const bool c2 = any_core || j->min_pts > 2;
+      // a batch that could never fit the budget is not formed
+      const bool fits = !B || dbx::batched_scratch_bytes(t2, uint32_t(batch.size() + 1), c2) +
+                                      uint64_t(t2) * IO_BYTES_PER_POINT <= B;
+      if (j->n < S->opt.batch_cut && t2 <= S->opt.batch_max_points &&
+          int32_t(batch.size()) < S->opt.batch_max_jobs && fits) {
+        batch.push_back(j);
+        total = t2;
+        any_core = c2;
+        it = S->queue.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  return batch;
+}
+
+void finish_job(dbscan_server* S, Job* j, double t) {
+  j->t_done = t;
+  j->done = true;
+  if (j->status == DBSCAN_OK) {
+    ++S->completed;
+    S->points += uint64_t(j->n);
+    S->latencies.push_back(t - j->t_submit);
+    S->last_done = std::max(S->last_done, t);
+  } else {
+    ++S->failed;
+  }
+}
+
 void worker(dbscan_server* S, Slot* s) {
   if (!S->opt.fake_executor) (void)hipSetDevice(S->opt.device);
   std::unique_lock<std::mutex> lk(S->mu);
   for (;;) {
-    std::vector<Job*> batch;
-    uint64_t need = 0;
-    S->cv_work.wait(lk, [&] {
-      if (S->stop) return true;
-      if (S->queue.empty()) return false;
-      Job* head = S->queue.front();
-      const uint64_t b = job_bytes(head->n, head->min_pts);
-      // start when it fits next to the work in flight, or when nothing runs
-      return S->running == 0 || !S->opt.hbm_budget_bytes ||
-             S->in_flight_bytes + b <= S->opt.hbm_budget_bytes;
-    });
-    if (S->stop && S->queue.empty()) return;
-    if (S->queue.empty()) continue;
-    Job* head = S->queue.front();
-    S->queue.pop_front();
-    batch.push_back(head);
-    int64_t total = head->n;
-    if (head->n < S->opt.batch_cut) {
-      for (auto it = S->queue.begin(); it != S->queue.end();) {
-        Job* j = *it;
-        if (j->n < S->opt.batch_cut && total + j->n <= S->opt.batch_max_points &&
-            int32_t(batch.size()) < S->opt.batch_max_jobs &&
-            (!S->opt.hbm_budget_bytes ||
-             S->in_flight_bytes + job_bytes(total + j->n, 10) <= S->opt.hbm_budget_bytes)) {
-          batch.push_back(j);
-          total += j->n;
-          it = S->queue.erase(it);
-        } else {
-          ++it;
-        }
-      }
-    }
-    int32_t mp_max = 1;
-    for (Job* j : batch) mp_max = std::max(mp_max, j->min_pts);
-    need = job_bytes(total, mp_max);
-    if (S->opt.hbm_budget_bytes && need > S->opt.hbm_budget_bytes) {
-      // can never fit: fail the job(s) that make it too big
-      for (Job* j : batch) {
-        if (job_bytes(j->n, j->min_pts) > S->opt.hbm_budget_bytes) {
-          j->status = DBSCAN_ETOOBIG;
-          j->done = true;
-          j->t_done = now_s();
-          ++S->failed;
-        } else {
-          S->queue.push_front(j);  // retry alone
-        }
-      }
-      S->cv_done.notify_all();
-      S->cv_work.notify_all();
+    S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+    if (S->queue.empty()) {
+      if (S->stop) return;
       continue;
     }
-    S->in_flight_bytes += need;
-    S->peak_bytes = std::max(S->peak_bytes, S->in_flight_bytes);
+    std::vector<Job*> batch = take_batch(S);
+    int64_t total = 0;
+    for (Job* j : batch) total += j->n;
+    Admit a = admit(S, s, scratch_of(batch), total);
+    if (a == Admit::NEVER && batch.size() > 1) {
+      // the batch is too big for the budget: its jobs go back to run alone
+      for (auto it = batch.rbegin(); it != batch.rend(); ++it) S->queue.push_front(*it);
+      S->cv_work.notify_all();
+      batch.resize(1);
+      S->queue.pop_front();
+      total = batch[0]->n;
+      a = admit(S, s, scratch_of(batch), total);
+    }
+    if (a == Admit::NEVER) {  // a job that can never fit
+      batch[0]->status = DBSCAN_ETOOBIG;
+      finish_job(S, batch[0], now_s());
+      S->cv_done.notify_all();
+      continue;
+    }
+    if (a == Admit::WAIT) {  // back to the head of the queue until a running job ends
+      for (auto it = batch.rbegin(); it != batch.rend(); ++it) S->queue.push_front(*it);
+      S->cv_work.wait(lk);
+      continue;
+    }
+    s->busy = true;
     ++S->running;
     if (batch.size() > 1) {
       ++S->batches;
@@ -234,20 +354,14 @@ void worker(dbscan_server* S, Slot* s) {
     execute(S, s, batch);
     const double t = now_s();
     lk.lock();
-    S->in_flight_bytes -= need;
+    // charge what the slot holds now
+    const uint64_t held = s->arena + uint64_t(s->cap) * IO_BYTES_PER_POINT;
+    S->held_bytes = S->held_bytes - s->held + held;
+    s->held = held;
+    S->peak_bytes = std::max(S->peak_bytes, S->held_bytes);
+    s->busy = false;
     --S->running;
-    for (Job* j : batch) {
-      j->t_done = t;
-      j->done = true;
-      if (j->status == DBSCAN_OK) {
-        ++S->completed;
-        S->points += uint64_t(j->n);
-        S->latencies.push_back(t - j->t_submit);
-        S->last_done = std::max(S->last_done, t);
-      } else {
-        ++S->failed;
-      }
-    }
+    for (Job* j : batch) finish_job(S, j, t);
     S->cv_done.notify_all();
     S->cv_work.notify_all();
   }

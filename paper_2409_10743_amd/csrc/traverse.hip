@@ -15,7 +15,6 @@
 //  * counting by pair traversal (an option): every pair adds one to both
 //    points' neighbour counts.  No early exit, but no walk from the root
 //    either: cheaper where points have few neighbours.
-#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -160,12 +159,6 @@ __global__ __launch_bounds__(256) void k_degree_flags(uint32_t n, const uint32_t
 }  // namespace
 
 uint32_t walk_queries_per_lane(uint32_t n) {
-  static const int forced = [] {
-    const char* e = std::getenv("DBX_WALK_QPL");
-    const int v = e ? std::atoi(e) : 0;
-    return (v == 1 || v == 2 || v == 4 || v == 8) ? v : 0;
-  }();
-  if (forced) return uint32_t(forced);
   return n >= (1u << 23) ? 4u : n >= (1u << 22) ? 2u : 1u;
 }
 
@@ -192,23 +185,6 @@ uint32_t persistent_blocks(const void* kernel, int block, size_t lds, uint32_t n
     cache[{kernel, block}] = fit;
   }
   return std::max(8u, std::min(fit, (needed + 7) / 8 * 8));
-}
-
-bool walk_persistent(bool dflt) {
-  static const int forced = [] {
-    const char* e = std::getenv("DBX_WALK_PERSIST");
-    return e && (e[0] == '0' || e[0] == '1') && e[1] == 0 ? e[0] - '0' : -1;
-  }();
-  return forced < 0 ? dflt : forced == 1;
-}
-
-uint32_t walk_refill_at() {
-  static const uint32_t r = [] {
-    const char* e = std::getenv("DBX_WALK_REFILL");
-    const int v = e ? std::atoi(e) : 48;
-    return uint32_t(v >= 1 && v <= 64 ? v : 48);
-  }();
-  return r;
 }
 
 void launch_count(const Node* nodes, const float4* leaf, const uint64_t* keys,

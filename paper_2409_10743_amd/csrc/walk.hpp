@@ -41,8 +41,7 @@ namespace dbx {
 // lane keeps lanes busier (a lane takes a new query when its walk ends) but
 // spreads the queries in flight over a longer stretch of the tree, which
 // costs L2 hits, and for small n it leaves CUs idle: 4 per lane from 2^23
-// queries, 2 from 2^22, else 1, unless the environment variable
-// DBX_WALK_QPL (1, 2, 4 or 8) overrides it for tuning runs.
+// queries, 2 from 2^22, else 1.
 uint32_t walk_queries_per_lane(uint32_t n);
 inline uint32_t walk_chunk_size(uint32_t n) { return 64u * walk_queries_per_lane(n); }
 
@@ -78,10 +77,9 @@ __device__ __forceinline__ void walk_chunk(uint32_t n, uint32_t chunk, uint32_t&
   c1 = uint32_t(b + chunk < n ? b + chunk : n);
 }
 
-// Lanes are refilled only once fewer than walk_refill_at() of the 64 are
-// still walking (48 unless DBX_WALK_REFILL, 1..64, overrides it); in
-// between, the wave runs a tight per-lane loop.
-uint32_t walk_refill_at();
+// Lanes are refilled only once fewer than WALK_REFILL_AT of the 64 are
+// still walking; in between, the wave runs a tight per-lane loop.
+constexpr uint32_t WALK_REFILL_AT = 48;
 
 struct WalkCfg {
   uint32_t chunk;      // queries per wave
@@ -89,7 +87,7 @@ struct WalkCfg {
   uint32_t* queue;     // persistent walks: 8 zeroed chunk counters; null: static chunks
 };
 inline WalkCfg walk_cfg(uint32_t n, uint32_t* queue = nullptr) {
-  return WalkCfg{walk_chunk_size(n), walk_refill_at(), queue};
+  return WalkCfg{walk_chunk_size(n), WALK_REFILL_AT, queue};
 }
 
 // Persistent walks (PERSIST, with WalkCfg::queue): the grid holds only as
@@ -131,9 +129,6 @@ __device__ __forceinline__ bool next_chunk(const WalkCfg& wc, uint32_t n, uint32
 // Blocks of a persistent walk launch: as many as the GPU holds at once
 // (a multiple of 8), at most `needed`.
 uint32_t persistent_blocks(const void* kernel, int block, size_t lds, uint32_t needed);
-// Whether a launch walks persistently: `dflt`, unless the environment
-// variable DBX_WALK_PERSIST (0 or 1) overrides it for tuning runs.
-bool walk_persistent(bool dflt);
 
 // `leaf` must have one readable float4 past leaf n-1 (a leaf step reads 32
 // bytes, like a node step, and ignores the second half).

@@ -77,3 +77,40 @@ def test_fifo_order_for_large_jobs():
         done.append(s.job_times(t)[1])
     assert done == sorted(done)
     s.close()
+
+
+def test_budget_bounds_memory_kept_between_jobs():
+    """Slots keep their arena and I/O buffers after a job; the budget bounds
+    that memory, not only the jobs running: jobs of growing size on four
+    slots under a budget of about two of the largest never make the slots
+    hold more than the budget (idle slots give memory back), and every job
+    completes."""
+    lib = dbx.load_library()
+    big = lib.dbscan_scratch_bytes(200000, 5, 1) + 200000 * 16
+    budget = int(big * 2.2)
+    s = dbx.Server(slots=4, budget_bytes=budget, batch_cut=1, fake_us_per_mpoint=20000.0)
+    sizes = [20000, 200000, 50000, 200000, 120000, 200000, 10000, 180000, 200000, 90000]
+    ts = [s.submit(pts(n, k), 0.01, 5) for k, n in enumerate(sizes)]
+    for t in ts:
+        assert s.wait(t, 60.0) == 0
+    st = s.stats()
+    assert st["completed"] == len(sizes) and st["failed"] == 0
+    assert 0 < st["peak_in_flight_bytes"] <= budget
+    s.close()
+
+
+def test_batches_respect_the_budget():
+    """Small jobs are batched only up to what fits the budget (batched
+    layout included); none fails."""
+    lib = dbx.load_library()
+    one = lib.dbscan_scratch_bytes(5000, 2, 1) + 5000 * 16
+    s = dbx.Server(slots=1, budget_bytes=one * 6, batch_cut=10000, fake_us_per_mpoint=50000.0)
+    first = s.submit(pts(9000, 1), 0.01, 2)
+    time.sleep(0.01)
+    ts = [s.submit(pts(5000, 10 + k), 0.01, 2) for k in range(40)]
+    for t in [first] + ts:
+        assert s.wait(t, 60.0) == 0
+    st = s.stats()
+    assert st["failed"] == 0 and st["batches"] >= 1
+    assert st["peak_in_flight_bytes"] <= one * 6
+    s.close()
