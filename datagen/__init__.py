@@ -248,3 +248,50 @@ def config_points(name: str, n: int | None = None) -> np.ndarray:
         box = c["box"] * (nn / c["n"]) ** (1.0 / 3.0)
         return halo_field(nn, box, c["seed"])
     raise KeyError(name)
+
+
+# ---- input manifest -----------------------------------------------------------
+MANIFEST = __import__("os").path.join(__import__("os").path.dirname(__file__), "manifest.json")
+
+
+def digest(*arrays) -> str:
+    """sha256 of the arrays' bytes, in order (C order, native little-endian)."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def input_digests(names=None) -> dict:
+    """sha256 of each workload's generated input: the three fields, the
+    4,096 sub-halo sets (points, offsets), the serving trace's job table
+    and its eight point pools."""
+    out = {}
+    names = names or ["clumps32k", "halo16M", "halo134M", "subhalo4096", "serving_trace",
+                      "serving_pools"]
+    for nm in names:
+        if nm in ("clumps32k", "halo16M", "halo134M"):
+            out[nm] = digest(config_points(nm))
+        elif nm == "subhalo4096":
+            c = CONFIGS[nm]
+            out[nm] = digest(*subhalo_sets(c["num_sets"], c["seed"]))
+        elif nm == "serving_trace":
+            jobs = serving_trace()
+            tab = np.array([(j.t_arrival, j.n, j.min_pts, float(j.eps), j.pool, j.start)
+                            for j in jobs], dtype=np.float64)
+            out[nm] = digest(tab)
+        elif nm == "serving_pools":
+            out[nm] = digest(*[serving_pool(k) for k in range(8)])
+    return out
+
+
+def check_manifest(name: str, *arrays) -> bool | None:
+    """True if the arrays hash to the manifest's digest for `name`, False if
+    they differ, None if the manifest has no entry."""
+    import json
+    import os
+    if not os.path.exists(MANIFEST):
+        return None
+    want = json.load(open(MANIFEST))["sha256"].get(name)
+    return None if want is None else digest(*arrays) == want

@@ -2,6 +2,7 @@
 import hashlib
 
 import numpy as np
+import pytest
 
 import datagen
 
@@ -70,3 +71,12 @@ def test_serving_trace_rate():
 def test_eps_linking_length_closed_form():
     # the paper's benchmark: eps = 0.168 * (256^3 / 1024^3)^(1/3) = 0.042
     assert abs(float(datagen.mean_spacing_eps(1024 ** 3, 0.168, 256.0 ** 3)) - 0.042) < 1e-7
+
+
+@pytest.mark.parametrize("name", ["clumps32k", "halo16M", "serving_trace"])
+def test_inputs_match_the_manifest(name):
+    """The generators give the bytes datagen/manifest.json records (the
+    same bytes on every machine that reproduces them)."""
+    import json
+    want = json.load(open(datagen.MANIFEST))["sha256"][name]
+    assert datagen.input_digests([name])[name] == want
