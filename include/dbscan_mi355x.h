@@ -135,6 +135,30 @@ int dbscan_cluster_batched(dbscan_ctx* ctx, const float* points, const int64_t* 
 int dbscan_cluster_host(const float* host_points, int64_t n, float eps,
                         int32_t min_pts, int32_t* host_labels);
 
+/* ---- an entry point that allocates nothing ----------------------------------- */
+/* For callers that cannot allocate device memory: code that runs while
+ * another part of the process captures a HIP graph, tight serving loops,
+ * harnesses that forbid hipMalloc.  dbscan_cluster with every scratch buffer
+ * in one fixed device array of the library, DBSCAN_NOALLOC_SCRATCH_BYTES
+ * long; each GPU gets its own copy of the array when the library first runs
+ * on it and keeps it until the process ends.  The call itself allocates no
+ * device or pinned host memory and creates no stream, event or context.
+ *   points, labels: device pointers as for dbscan_cluster (the caller still
+ *     owns and passes both);
+ *   n <= DBSCAN_NOALLOC_MAX_POINTS; a larger n is DBSCAN_ETOOBIG and the
+ *     labels are untouched;
+ *   FDBSCAN with the default options, on the current device;
+ *   stream: a hipStream_t, NULL = the null stream; the call returns once its
+ *     work has completed (a D2H copy of a status word to pageable memory).
+ * Every call on one GPU uses that GPU's one array and leaves its last
+ * contents there (the call clears what must start at zero itself), so two
+ * calls that overlapped on one GPU would race: the library serialises the
+ * calls of one process per device with a host lock.
+ * Labels and errors are exactly those of dbscan_cluster. */
+#define DBSCAN_NOALLOC_MAX_POINTS 1048576
+#define DBSCAN_NOALLOC_SCRATCH_BYTES 102760448  /* 98 MiB: 97.1 B per point at the maximum */
+int dbscan_cluster_noalloc(const float* points, int64_t n, float eps, int32_t min_pts,
+                           int32_t* labels, void* stream);
 
 /* Per-phase device times (ms) of the context's last call made with
  * DBSCAN_FLAG_TIMING, in the order of dbscan_phase_name(); returns how many

@@ -15,8 +15,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["cluster", "Context", "Server", "DbscanError", "library_path", "load_library",
-           "PHASES", "ALGO"]
+__all__ = ["cluster", "cluster_noalloc", "Context", "Server", "DbscanError", "library_path",
+           "load_library", "PHASES", "ALGO", "NOALLOC_MAX_POINTS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libdbscan_mi355x.so"
@@ -85,6 +85,7 @@ def load_library() -> ctypes.CDLL:
         "dbscan_cluster_ex": ([vp, vp, i64, f32, i32, vp, vp, ctypes.POINTER(_Options)],
                               ctypes.c_int),
         "dbscan_cluster_host": ([vp, i64, f32, i32, vp], ctypes.c_int),
+        "dbscan_cluster_noalloc": ([vp, i64, f32, i32, vp, vp], ctypes.c_int),
         "dbscan_cluster_batched": ([vp, vp, ctypes.POINTER(i64), i32, ctypes.POINTER(f32),
                                     ctypes.POINTER(i32), vp, vp, ctypes.POINTER(_Options)],
                                    ctypes.c_int),
@@ -532,3 +533,19 @@ def cluster(points, eps: float, min_pts: int, out=None):
         ctypes.c_void_p(labels.data_ptr()), _stream(p.device)))
     return labels
 
+
+NOALLOC_MAX_POINTS = 1048576  # DBSCAN_NOALLOC_MAX_POINTS
+
+
+def cluster_noalloc(points, eps: float, min_pts: int, out=None):
+    """As ``cluster``, through dbscan_cluster_noalloc: the library's fixed
+    per-GPU scratch array instead of an allocated arena (at most
+    NOALLOC_MAX_POINTS points).  Pass ``out`` to keep the call itself free
+    of allocations on the Python side too."""
+    p = _points(points)
+    n = p.shape[0]
+    labels = _labels_out(out, n, p.device)
+    _check(load_library().dbscan_cluster_noalloc(
+        ctypes.c_void_p(p.data_ptr()), n, ctypes.c_float(eps), int(min_pts),
+        ctypes.c_void_p(labels.data_ptr()), _stream(p.device)))
+    return labels

@@ -769,6 +769,22 @@ dbscan_options defaults() {
   return o;
 }
 
+// ---- scratch of the entry point that allocates nothing -----------------------
+// One fixed device array; the code object is loaded per GPU, so every GPU
+// holds its own copy (at its own address) until the process ends.  Host
+// code never uses the name `scratch` as an address: it is a host-side
+// stand-in, and a kernel given it would fault.  Its device address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kNoAllocBytes = size_t(DBSCAN_NOALLOC_SCRATCH_BYTES);
+static_assert(kNoAllocBytes % 256 == 0, "scratch size");
+__device__ __align__(256) char scratch[kNoAllocBytes];
+
+struct NoAllocDevice {
+  std::mutex mu;         // one call at a time on this device (the array is shared)
+  char* ptr = nullptr;   // device address of `scratch` on this device
+};
+NoAllocDevice g_noalloc[64];
+
 }  // namespace
 
 // ---- autotuning -------------------------------------------------------------
@@ -996,6 +1012,49 @@ int dbscan_cluster_host(const float* host_points, int64_t n, float eps, int32_t 
   return st;
 }
 
+int dbscan_cluster_noalloc(const float* points, int64_t n, float eps, int32_t min_pts,
+                           int32_t* labels, void* stream) {
+  int st = check_args(points, n, eps, min_pts, labels);
+  if (st != DBSCAN_OK) return st;
+  if (n > int64_t(DBSCAN_NOALLOC_MAX_POINTS))
+    return fail(DBSCAN_ETOOBIG, "n = " + std::to_string(n) +
+                                    " exceeds the no-allocation entry point's maximum of " +
+                                    std::to_string(DBSCAN_NOALLOC_MAX_POINTS) + " points");
+  if (n == 0) return DBSCAN_OK;
+  const Layout L = make_layout(uint32_t(n), min_pts > 2);
+  if (L.total > kNoAllocBytes)  // the maximum is chosen so that this never happens
+    return fail(DBSCAN_ETOOBIG, "job needs " + std::to_string(L.total) +
+                                    " bytes of scratch, the fixed array holds " +
+                                    std::to_string(kNoAllocBytes));
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(DBSCAN_EDEVICE, "device id out of range");
+  NoAllocDevice& d = g_noalloc[dev];
+  std::lock_guard<std::mutex> lock(d.mu);
+  if (!d.ptr) {  // first call on this device, which is current
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return fail(DBSCAN_EDEVICE, std::string("hipGetSymbolAddress of the scratch array: ") +
+                                      hipGetErrorString(e));
+    }
+    d.ptr = static_cast<char*>(p);
+  }
+  // A context on the stack over the fixed array: its budget is the array,
+  // so the arena is never grown (nothing is freed or allocated), and the
+  // status words come back to pageable memory on this stack.
+  dbscan_ctx c;
+  c.device = dev;
+  c.budget = kNoAllocBytes;
+  c.arena = d.ptr;
+  c.cap = kNoAllocBytes;
+  uint32_t host_words[16] = {};
+  c.host_status = host_words;
+  c.sort_items = 0;
+  return run_fdbscan(&c, points, uint32_t(n), eps, min_pts, labels,
+                     reinterpret_cast<hipStream_t>(stream), defaults());
+}
 
 int dbscan_phase_times(const dbscan_ctx* c, float* ms, int32_t max) {
   if (!c || !ms || max < 0) return 0;

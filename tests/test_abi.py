@@ -158,3 +158,24 @@ def test_server_checks_host_label_buffers():
     assert s.wait(t, 10.0) == 0
     assert (good[:10] == -1).all()
     s.close()
+
+
+def test_noalloc_rejects_on_the_host():
+    """The no-allocation entry point checks its arguments and its size limit
+    before any device call: EINVAL as dbscan_cluster, ETOOBIG past the
+    fixed array's maximum, labels untouched; n = 0 does nothing."""
+    lib = dbx.load_library()
+    buf = (ctypes.c_float * 16)()
+    lab = (ctypes.c_int32 * 16)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    out = ctypes.cast(lab, ctypes.c_void_p)
+    assert lib.dbscan_cluster_noalloc(None, 0, ctypes.c_float(1.0), 2, None, None) == 0
+    assert lib.dbscan_cluster_noalloc(p, 5, ctypes.c_float(-1.0), 2, out, None) == -1
+    assert lib.dbscan_cluster_noalloc(p, 5, ctypes.c_float(1.0), 0, out, None) == -1
+    st = lib.dbscan_cluster_noalloc(p, dbx.NOALLOC_MAX_POINTS + 1, ctypes.c_float(1.0), 2, out,
+                                    None)
+    assert st == -5
+    assert b"maximum" in lib.dbscan_last_error()
+    assert list(lab) == [0] * 16
+    # the fixed array holds the largest job it admits
+    assert lib.dbscan_scratch_bytes(dbx.NOALLOC_MAX_POINTS, 5, 1) <= 102760448
