@@ -57,7 +57,13 @@ extern "C" {
                                   context's budget allows */
 
 /* ---- algorithms and options -------------------------------------------------- */
-#define DBSCAN_ALGO_AUTO 0      /* currently FDBSCAN */
+/* AUTO picks per call: a density probe (a few thousand sampled points per
+ * call, at most 256 per set of a batch; one small kernel and one 8-byte
+ * read-back, kept for later calls on the same points, sizes, eps and minPts)
+ * estimates the mean number of eps-neighbours per point; DenseBox when it is
+ * at least 4 times minPts (point-weighted over sets), FDBSCAN otherwise.
+ * Labels do not depend on the pick. */
+#define DBSCAN_ALGO_AUTO 0
 #define DBSCAN_ALGO_FDBSCAN 1   /* section 4.3.3 */
 #define DBSCAN_ALGO_DENSEBOX 2  /* section 4.3.4 */
 

@@ -159,6 +159,11 @@ struct dbscan_ctx {
   };
   Graph graphs[4];
   uint64_t graph_clock = 0;
+  // DBSCAN_ALGO_AUTO: the density probe's device buffer and the last pick
+  char* probe = nullptr;
+  size_t probe_cap = 0;
+  std::vector<uint64_t> auto_key;
+  int32_t auto_algo = DBSCAN_ALGO_FDBSCAN;
 };
 
 namespace {
@@ -586,6 +591,20 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
   return finish(c, status, timing, s);
 }
 
+// Pinned host staging of at least `bytes` (per-set parameters on their way
+// to the device).
+int ensure_stage(dbscan_ctx* c, size_t bytes, hipStream_t s) {
+  if (c->stage_cap >= bytes) return DBSCAN_OK;
+  HIP_TRY(hipStreamSynchronize(s));  // the old staging buffer may still be read
+  if (c->stage) (void)hipHostFree(c->stage);
+  c->stage = nullptr;
+  c->stage_cap = 0;
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->stage), bytes) != hipSuccess)
+    return fail(DBSCAN_ENOMEM, "hipHostMalloc of the per-set staging buffer failed");
+  c->stage_cap = bytes;
+  return DBSCAN_OK;
+}
+
 // Byte offsets of a batched call's per-set arrays, after the job's buffers:
 // offsets, e2, minPts, dense threshold, inverse cell side, roots, grids.
 struct SetLayout {
@@ -626,16 +645,8 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
                root_b = SL.root, grid_b = SL.grid;
   int st = ensure_arena(c, SL.total);
   if (st != DBSCAN_OK) return st;
-  const size_t stage_bytes = (size_t(num_sets) + 1) * 8 + size_t(num_sets) * 16;
-  if (c->stage_cap < stage_bytes) {
-    HIP_TRY(hipStreamSynchronize(s));  // the old staging buffer may still be read
-    if (c->stage) (void)hipHostFree(c->stage);
-    c->stage = nullptr;
-    c->stage_cap = 0;
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->stage), stage_bytes) != hipSuccess)
-      return fail(DBSCAN_ENOMEM, "hipHostMalloc of the per-set staging buffer failed");
-    c->stage_cap = stage_bytes;
-  }
+  st = ensure_stage(c, (size_t(num_sets) + 1) * 8 + size_t(num_sets) * 16, s);
+  if (st != DBSCAN_OK) return st;
   int64_t* s_off = reinterpret_cast<int64_t*>(c->stage);
   float* s_e2 = reinterpret_cast<float*>(s_off + num_sets + 1);
   int32_t* s_mp = reinterpret_cast<int32_t*>(s_e2 + num_sets);
@@ -767,6 +778,80 @@ dbscan_options defaults() {
   dbscan_options o{};
   o.algorithm = DBSCAN_ALGO_AUTO;
   return o;
+}
+
+// ---- DBSCAN_ALGO_AUTO ------------------------------------------------------------
+// DenseBox is chosen when points have, on average, at least this many
+// eps-neighbours per unit of minPts (point-weighted over the sets).  On the
+// 4,096 sub-halo sets (eps 0.05, minPts 5) the mean is about 35 and DenseBox
+// takes half FDBSCAN's time; on the 2^24-point halo field (eps 0.2, minPts
+// 2) it is 0.06 and FDBSCAN takes 0.6 of DenseBox's.
+constexpr double AUTO_DENSE_FACTOR = 4.0;
+constexpr uint32_t PROBE_SAMPLES_ONE_SET = 4096;  // sample points of a plain call
+constexpr uint32_t PROBE_SAMPLES_PER_SET = 256;   // and of each set of a batch
+
+uint64_t mix(uint64_t h, uint64_t v) { return (h ^ v) * 0x100000001b3ull; }
+
+// The algorithm AUTO stands for on this input: FDBSCAN or DenseBox, from the
+// density probe (probe.hip); the pick is kept for calls with the same
+// points, sizes, eps and minPts, so graph replays need no probe.
+int resolve_auto(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t num_sets,
+                 const float* h_eps, const int32_t* h_mp, hipStream_t s, int32_t* algo) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  for (uint32_t k = 0; k < num_sets; ++k)
+    h = mix(mix(mix(h, uint64_t(h_off[k + 1])), bits_of(h_eps[k])), uint64_t(uint32_t(h_mp[k])));
+  const std::vector<uint64_t> key = {reinterpret_cast<uint64_t>(pts), num_sets, h};
+  if (key == c->auto_key) {
+    *algo = c->auto_algo;
+    return DBSCAN_OK;
+  }
+  const size_t off_b = 0, e2_b = align_up((size_t(num_sets) + 1) * 8);
+  const size_t out_b = e2_b + align_up(size_t(num_sets) * 4), total = out_b + 256;
+  if (c->probe_cap < total) {
+    if (c->probe) {
+      HIP_TRY(hipStreamSynchronize(s));
+      HIP_TRY(hipFree(c->probe));
+    }
+    c->probe = nullptr;
+    c->probe_cap = 0;
+    if (hipMalloc(&c->probe, total) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(DBSCAN_ENOMEM, "hipMalloc of the density probe's buffer failed");
+    }
+    c->probe_cap = total;
+  }
+  // the parameters go through the pinned staging buffer, laid out like the
+  // device buffer: offsets, e2, the result
+  int st = ensure_stage(c, total, s);
+  if (st != DBSCAN_OK) return st;
+  HIP_TRY(hipStreamSynchronize(s));  // earlier work may still read the staging buffer
+  int64_t* s_off = reinterpret_cast<int64_t*>(c->stage + off_b);
+  float* s_e2 = reinterpret_cast<float*>(c->stage + e2_b);
+  double* s_sum = reinterpret_cast<double*>(c->stage + out_b);
+  double n = 0, mp = 0;
+  for (uint32_t k = 0; k < num_sets; ++k) {
+    s_e2[k] = h_eps[k] * h_eps[k];
+    const double nk = double(h_off[k + 1] - h_off[k]);
+    n += nk;
+    mp += nk * double(h_mp[k]);
+  }
+  std::memcpy(s_off, h_off, (size_t(num_sets) + 1) * 8);
+  *s_sum = 0.0;
+  HIP_TRY(hipMemcpyAsync(c->probe, c->stage, total, hipMemcpyHostToDevice, s));
+  launch_density_probe(pts, reinterpret_cast<const int64_t*>(c->probe + off_b),
+                       reinterpret_cast<const float*>(c->probe + e2_b), num_sets,
+                       num_sets == 1 ? PROBE_SAMPLES_ONE_SET : PROBE_SAMPLES_PER_SET,
+                       reinterpret_cast<double*>(c->probe + out_b), s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(s_sum, c->probe + out_b, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double sum = *s_sum;
+  const double mean = n > 0 ? sum / n : 0, mp_mean = n > 0 ? mp / n : 2;
+  *algo = mean >= AUTO_DENSE_FACTOR * std::max(mp_mean, 2.0) ? DBSCAN_ALGO_DENSEBOX
+                                                              : DBSCAN_ALGO_FDBSCAN;
+  c->auto_key = key;
+  c->auto_algo = *algo;
+  return DBSCAN_OK;
 }
 
 // ---- scratch of the entry point that allocates nothing -----------------------
@@ -924,6 +1009,7 @@ int dbscan_ctx_destroy(dbscan_ctx* c) {
   if (c->arena) (void)hipFree(c->arena);
   if (c->host_status) (void)hipHostFree(c->host_status);
   if (c->stage) (void)hipHostFree(c->stage);
+  if (c->probe) (void)hipFree(c->probe);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -948,6 +1034,11 @@ int dbscan_cluster_ex(dbscan_ctx* c, const float* points, int64_t n, float eps, 
   DeviceGuard g(c->device);
   c->sort_items = o.sort_tile / SORT_THREADS;
   if (!stream) o.flags &= ~DBSCAN_FLAG_GRAPH;  // graphs only on a stream the caller names
+  if (o.algorithm == DBSCAN_ALGO_AUTO) {
+    const int64_t off[2] = {0, n};
+    st = resolve_auto(c, points, off, 1, &eps, &min_pts, stream_of(c, stream), &o.algorithm);
+    if (st != DBSCAN_OK) return st;
+  }
   if (o.algorithm == DBSCAN_ALGO_DENSEBOX)
     return run_densebox(c, points, uint32_t(n), eps, min_pts, labels, stream_of(c, stream), o);
   return run_fdbscan(c, points, uint32_t(n), eps, min_pts, labels, stream_of(c, stream), o);
@@ -975,6 +1066,11 @@ int dbscan_cluster_batched(dbscan_ctx* c, const float* points, const int64_t* of
   DeviceGuard g(c->device);
   c->sort_items = o.sort_tile / SORT_THREADS;
   if (!stream) o.flags &= ~DBSCAN_FLAG_GRAPH;  // graphs only on a stream the caller names
+  if (o.algorithm == DBSCAN_ALGO_AUTO) {
+    int st = resolve_auto(c, points, offsets, uint32_t(num_sets), eps, min_pts,
+                          stream_of(c, stream), &o.algorithm);
+    if (st != DBSCAN_OK) return st;
+  }
   return run_batched(c, points, offsets, uint32_t(num_sets), eps, min_pts, labels,
                      stream_of(c, stream), o);
 }

@@ -172,6 +172,14 @@ void launch_knn(const Node* nodes, const float4* leaf, const uint32_t* perm, uin
                 const int32_t* root, int32_t k, int32_t* out_idx, float* out_d2, float* core_d2,
                 uint32_t* err, hipStream_t s);
 
+// ---- density probe (probe.hip) ---------------------------------------------------
+// *out += sum over sets of n_k times an unbiased estimate of set k's mean
+// eps-neighbour count (point itself left out), from min(n_k, s_max) evenly
+// spread samples of the set (offsets, set_e2: device arrays); *out must be
+// zeroed first.
+void launch_density_probe(const float* pts, const int64_t* offsets, const float* set_e2,
+                          uint32_t num_sets, uint32_t s_max, double* out, hipStream_t s);
+
 // ---- labels (finalize.hip) --------------------------------------------------
 // Labels of the sorted points into input order; labels must hold -1 for
 // every point (the build or the gather writes it).  minlab (minPts > 2
