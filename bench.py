@@ -156,11 +156,30 @@ def _col(row: dict, *names):
     raise KeyError(f"none of {names} in {sorted(row)}")
 
 
+def _short(name: str) -> str:
+    """A kernel's name as rocprofv3 prints it, without the return type, the
+    namespaces and the parameter list: "k_onesweep<false, 16>"."""
+    if name.startswith("void "):
+        name = name[5:]
+    for ns in ("dbx::(anonymous namespace)::", "dbx::"):
+        name = name.replace(ns, "")
+    depth, cut = 0, len(name)
+    for k, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            cut = k
+            break
+    return name[:cut]
+
+
 def _kernel_durations(d: str):
     """kernel name -> list of launch durations (us) from a kernel trace."""
     out = {}
     for r in _csv_rows(d, "kernel_trace.csv"):
-        name = _col(r, "Kernel_Name", "Name")
+        name = _short(_col(r, "Kernel_Name", "Name"))
         t = (int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))) / 1e3
         out.setdefault(name, []).append(t)
     return out
@@ -178,7 +197,7 @@ def summarize_trace(d: str, workload: str, cmd: str, bench_line: str, out_path: 
     stats = _csv_rows(d, "kernel_stats.csv")
     rows = []
     for r in stats:
-        rows.append((_col(r, "Name", "Kernel_Name"), int(_col(r, "Calls")),
+        rows.append((_short(_col(r, "Name", "Kernel_Name")), int(_col(r, "Calls")),
                      float(_col(r, "AverageNs")) / 1e3, float(_col(r, "TotalDurationNs")) / 1e6,
                      float(_col(r, "Percentage"))))
     rows.sort(key=lambda x: -x[3])
@@ -203,7 +222,8 @@ def _pmc_per_kernel(d: str, counter: str):
     for r in _csv_rows(d, "counter_collection.csv"):
         if _col(r, "Counter_Name") != counter:
             continue
-        out.setdefault(_col(r, "Kernel_Name"), []).append(float(_col(r, "Counter_Value")))
+        out.setdefault(_short(_col(r, "Kernel_Name")), []).append(
+            float(_col(r, "Counter_Value")))
     return out
 
 
@@ -446,6 +466,8 @@ def main():
 
     if not args.no_extras and args.workload == "halo16M":
         out["densebox"] = bench_densebox(ctx, d, eps, mp, args.steps, labels)
+        log("[bench] k nearest neighbours ...")
+        out["knn"] = bench_knn(ctx, d, pts)
         del d, labels
         torch.cuda.empty_cache()
         out["batched"] = bench_batched(ctx)
@@ -601,6 +623,41 @@ def bench_large(ctx, steps=3):
     return res
 
 
+def bench_knn(ctx, d, pts, k=8, min_pts=5, steps=3, rows=300):
+    """k nearest neighbours of every point of the field and HDBSCAN*'s core
+    distances (section 3.2 nearest search; section 5), timed, with sampled
+    rows checked against the brute-force oracle."""
+    import torch
+
+    import oracle
+    n = d.shape[0]
+    res = {"k": k}
+    for name, call in (("knn", lambda: ctx.knn(d, k)),
+                       ("core_distances", lambda: ctx.core_distances(d, min_pts))):
+        out = call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = call()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[name] = {"ms_per_call": round(ms, 3), "mpoints_per_s": round(n / ms / 1e3, 2)}
+    idx, d2 = ctx.knn(d, k)
+    rng = np.random.default_rng(9)
+    q = rng.choice(n, rows, replace=False)
+    oracle.set_threads(host_threads())
+    try:
+        ri, rd = oracle.knn(pts, k, q)
+    finally:
+        oracle.set_threads(1)
+    same = bool(np.array_equal(idx.cpu().numpy()[q], ri) and
+                np.array_equal(d2.cpu().numpy()[q].view(np.uint32), rd.view(np.uint32)))
+    res["sampled_rows_bit_exact"] = same
+    res["rows_checked"] = rows
+    res["core_distances"]["min_pts"] = min_pts
+    return res
+
+
 def bench_densebox(ctx, d, eps, mp, steps, ref_labels):
     import torch
     lab = torch.empty_like(ref_labels)
@@ -644,6 +701,9 @@ def bench_batched(ctx, steps=3):
     lab_f = lab.clone()
     t_d = timed(algorithm="densebox")
     same_d = bool(torch.equal(lab, lab_f))
+    t_auto = timed(algorithm="auto")  # the density probe's pick
+    ctx.cluster_batched(d, off, eps, mp, out=lab, algorithm="auto", timing=True)
+    auto_pick = "densebox" if ctx.phase_times()["cells"] > 0 else "fdbscan"
     log("[bench] batched autotuner ...")
     tuned = ctx.autotune_batched(d, off, eps, mp)
     t_b = timed(algorithm=tuned["algorithm"], block_size=tuned["block_size"],
@@ -678,6 +738,7 @@ def bench_batched(ctx, steps=3):
             "batched_mpoints_per_s": round(n / t_b / 1e6, 2),
             "fdbscan_batched_ms": round(t_f * 1e3, 3),
             "densebox_batched_ms": round(t_d * 1e3, 3),
+            "auto_batched_ms": round(t_auto * 1e3, 3), "auto_pick": auto_pick,
             "per_set_calls_ms": round(t_p * 1e3, 3),
             "per_set_calls_mpoints_per_s": round(n / t_p / 1e6, 2),
             "speedup": round(t_p / t_b, 2),

@@ -98,3 +98,11 @@ def test_pmc_summary(tmp_path):
     # fetch counts half the bytes, write all of them
     assert int(vals["hbm_bytes_per_launch"]) == 1000 * 1024 * 2 + 100 * 1024
     assert vals["source_sha256"] == bench.source_sha("pairs")
+
+
+def test_short_kernel_names():
+    assert bench._short("void dbx::(anonymous namespace)::k_onesweep<false, 16>(unsigned long*, "
+                        "unsigned int)") == "k_onesweep<false, 16>"
+    assert bench._short("dbx::(anonymous namespace)::k_prep(unsigned int*, unsigned long)") == \
+        "k_prep"
+    assert bench._short("__amd_rocclr_copyBuffer") == "__amd_rocclr_copyBuffer"
