@@ -284,6 +284,34 @@ def summarize_pmc(fetch_dir: str, write_dir: str, copy_fetch: str, copy_write: s
             "\n".join(txt) + "\n")
 
 
+def summarize_counters(d: str, workload: str, cmd: str, out_path: str, kernels=8):
+    """Every counter of a rocprofv3 --pmc run, per kernel (sum over the
+    launches that did work, divided by their number)."""
+    import collections
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in _csv_rows(d, "counter_collection.csv"):
+        per[_short(_col(r, "Kernel_Name"))][_col(r, "Counter_Name")].append(
+            float(_col(r, "Counter_Value")))
+    names = sorted({c for k in per for c in per[k]})
+    order = sorted(per, key=lambda k: -max(max(v) for v in per[k].values()))[:kernels]
+    lines = [f"# rocprofv3 counters per launch, {workload}, one MI355X", f"# command: {cmd}",
+             "kernel" + "".join(f"  {c}" for c in names)]
+    for k in order:
+        vals = []
+        for c in names:
+            v = _did_work(per[k].get(c, [0.0]))
+            vals.append(sum(v) / len(v))
+        lines.append(k + "".join(f"  {x:.4g}" for x in vals))
+    if "TCC_HIT_sum" in names and "TCC_MISS_sum" in names:
+        for k in order:
+            h = sum(per[k]["TCC_HIT_sum"]) or 0.0
+            m = sum(per[k]["TCC_MISS_sum"]) or 0.0
+            if h + m:
+                lines.append(f"# {k}: L2 hit rate {h / (h + m):.3f}")
+    open(out_path, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def copy_calibration():
     """A plain device copy of known size, for scaling the FETCH_SIZE /
     WRITE_SIZE counters (run under rocprofv3 --pmc)."""
@@ -335,12 +363,16 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 2^27-point field (about a minute of host-side generation)")
     ap.add_argument("--serving-seconds", type=float, default=60.0)
+    ap.add_argument("--knn-only", action="store_true",
+                    help="only the k-nearest-neighbour leg on --workload (for profiling)")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="write profiles/trace_<workload>.txt from a rocprofv3 kernel trace")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH",
                                                          "COPY_WRITE"),
                     help="write profiles/hbm_traffic_<workload>.txt and pmc_*.txt from "
                          "rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs and the copy runs")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("DIR", "NAME"),
+                    help="write profiles/counters_<NAME>_<workload>.txt from any --pmc run")
     ap.add_argument("--profile-cmd", nargs="*", default=[],
                     help="the command(s) the profile came from, for the summary header")
     ap.add_argument("--bench-line", default="", help="figures of the profiled run")
@@ -352,9 +384,15 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     tag = args.workload + ("" if args.algorithm == "fdbscan" else "_" + args.algorithm)
+    tag += "_knn" if args.knn_only else ""
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, tag, " ".join(args.profile_cmd) or "?",
                         args.bench_line, os.path.join(ROOT, "profiles", f"trace_{tag}.txt"))
+        return
+    if args.summarize_counters:
+        d, name = args.summarize_counters
+        summarize_counters(d, tag, " ".join(args.profile_cmd) or "?",
+                           os.path.join(ROOT, "profiles", f"counters_{name}_{tag}.txt"))
         return
     if args.summarize_pmc:
         import datagen
@@ -396,6 +434,11 @@ def main():
             ctx.cluster_batched(d, off, float(eps), mp, algorithm=args.algorithm,
                                 block_size=args.block_size, out=labels, **kw)
 
+    if args.knn_only:
+        log("[bench] k nearest neighbours only ...")
+        print(json.dumps({"workload": args.workload, "n": n, "knn": bench_knn(ctx, d, pts)}),
+              flush=True)
+        return
     log(f"[bench] n={n} eps={float(eps)} minPts={mp} {args.algorithm}: warmup {args.warmup}")
     for _ in range(args.warmup):
         step(timing=True)
@@ -458,6 +501,13 @@ def main():
         out["traversal"].update({"internal_visits_per_point": round(ts["internal_visits"] / n, 2),
                                  "descents_per_point": round(ts["descents"] / n, 2),
                                  "leaf_tests_per_point": round(ts["leaf_tests"] / n, 2)})
+        # logical bytes of the pair walk: every record it reads (32-byte
+        # nodes, 16-byte leaves, the query's own leaf) and two union-find
+        # words per pair, against the compulsory bytes of the roofline
+        logical = (ts["internal_visits"] * 32 + ts["leaf_tests"] * 16 + n * 16 +
+                   ts["pairs"] * 8)
+        out["traversal"]["logical_bytes"] = int(logical)
+        out["traversal"]["compulsory_bytes"] = int(n * BYTES_PER_POINT["pairs"])
         out["tree"] = tree_diagnostics(ctx, d, pts)
 
     if not args.no_cpu_baseline and off is None:

@@ -229,9 +229,11 @@ def test_code_bits_dropped_by_eps(ctx, eps, passes):
     p = np.clip(np.concatenate([base] + extra), 0, 1).astype(F32)
     p = p[rng.permutation(p.shape[0])]
     assert ctx.pair_count(dev(p), eps) == oracle.pair_count(p, F32(eps))
-    np.testing.assert_array_equal(run(ctx, p, eps, 2), oracle.dbscan(p, F32(eps), 2))
+    np.testing.assert_array_equal(run(ctx, p, eps, 2, algorithm="fdbscan"),
+                                  oracle.dbscan(p, F32(eps), 2))
     assert ctx.sort_passes() == passes
-    np.testing.assert_array_equal(run(ctx, p, eps, 4), oracle.dbscan(p, F32(eps), 4))
+    np.testing.assert_array_equal(run(ctx, p, eps, 4, algorithm="fdbscan"),
+                                  oracle.dbscan(p, F32(eps), 4))
 
 
 def test_traversal_stats_counts(ctx):
