@@ -508,7 +508,7 @@ def main():
                    ts["pairs"] * 8)
         out["traversal"]["logical_bytes"] = int(logical)
         out["traversal"]["compulsory_bytes"] = int(n * BYTES_PER_POINT["pairs"])
-        out["tree"] = tree_diagnostics(ctx, d, pts)
+        out["tree"] = tree_diagnostics(ctx, d, pts, passes)
 
     if not args.no_cpu_baseline and off is None:
         out["cpu_baseline"], same = cpu_baseline(pts, eps, mp, labels.cpu().numpy())
@@ -516,6 +516,12 @@ def main():
 
     if not args.no_extras and args.workload == "halo16M":
         out["densebox"] = bench_densebox(ctx, d, eps, mp, args.steps, labels)
+        # the same figures for the strongly clustered 32,768-point field
+        c32 = datagen.config_points("clumps32k")
+        dc = torch.from_numpy(c32).cuda()
+        ctx.cluster(dc, float(datagen.CONFIGS["clumps32k"]["eps"]), 2, algorithm="fdbscan")
+        out["tree_clumps32k"] = tree_diagnostics(ctx, dc, c32, ctx.sort_passes())
+        del dc
         log("[bench] k nearest neighbours ...")
         out["knn"] = bench_knn(ctx, d, pts)
         del d, labels
@@ -586,20 +592,31 @@ def cpu_baseline(pts, eps, mp, gpu_labels):
             "cpu_model": cpu_model()}, same
 
 
-def tree_diagnostics(ctx, d, pts):
+def tree_diagnostics(ctx, d, pts, passes):
     """The figures of the paper's table on Morton code width (section
-    4.2.2), for the 63-bit codes of this field: codes that occur at least
-    twice and more than three times, points that share their code with
-    another, the largest multiplicity, and the depth of the deepest leaf
-    (edges from the root, plus one) of the tree the library builds."""
+    4.2.2): codes that occur at least twice and more than three times,
+    points that share their code with another, the largest multiplicity;
+    for the full 63-bit codes and for the codes as the clustering call sorts
+    them (the low bits eps does not need cleared: `passes` 8-bit digits
+    kept), and the depth of the deepest leaf (edges from the root, plus one)
+    of the tree over the full codes."""
     codes = ctx.morton_codes(d).cpu().numpy().view(np.uint64)
-    _, counts = np.unique(codes, return_counts=True)
+
+    def table(c):
+        _, counts = np.unique(c, return_counts=True)
+        return {"codes_at_least_twice": int((counts >= 2).sum()),
+                "codes_more_than_3_times": int((counts > 3).sum()),
+                "points_sharing_a_code": int(counts[counts >= 2].sum()),
+                "max_multiplicity": int(counts.max())}
+
+    kept = 8 * passes
+    mask = np.uint64(((1 << 64) - 1) ^ ((1 << (64 - kept)) - 1)) if kept < 64 else \
+        np.uint64((1 << 64) - 1)
     perm, leaf, nodes, root = ctx.build_tree(d)
     depth = leaf_depth(nodes.cpu().numpy(), int(root.cpu().numpy()[0]), pts.shape[0])
-    return {"codes_bits": 63, "codes_at_least_twice": int((counts >= 2).sum()),
-            "codes_more_than_3_times": int((counts > 3).sum()),
-            "points_sharing_a_code": int(counts[counts >= 2].sum()),
-            "max_multiplicity": int(counts.max()), "max_leaf_depth": depth}
+    return {"full_63_bit": table(codes),
+            "as_sorted": dict(table(codes & mask), code_bits=max(0, kept - 1)),
+            "max_leaf_depth_63_bit": depth}
 
 
 def leaf_depth(nodes, root, n):

@@ -61,7 +61,9 @@ extern "C" {
  * call, at most 256 per set of a batch; one small kernel and one 8-byte
  * read-back, kept for later calls on the same points, sizes, eps and minPts)
  * estimates the mean number of eps-neighbours per point; DenseBox when it is
- * at least 4 times minPts (point-weighted over sets), FDBSCAN otherwise.
+ * at least 4 times minPts (point-weighted over sets), FDBSCAN otherwise;
+ * a plain FDBSCAN call with min_pts > 2 also finds its core points by pair
+ * traversal (DBSCAN_FLAG_PAIR_COUNT) when the mean is below min_pts.
  * Labels do not depend on the pick. */
 #define DBSCAN_ALGO_AUTO 0
 #define DBSCAN_ALGO_FDBSCAN 1   /* section 4.3.3 */

@@ -164,6 +164,7 @@ struct dbscan_ctx {
   size_t probe_cap = 0;
   std::vector<uint64_t> auto_key;
   int32_t auto_algo = DBSCAN_ALGO_FDBSCAN;
+  bool auto_pair_count = false;
 };
 
 namespace {
@@ -787,6 +788,11 @@ dbscan_options defaults() {
 // takes half FDBSCAN's time; on the 2^24-point halo field (eps 0.2, minPts
 // 2) it is 0.06 and FDBSCAN takes 0.6 of DenseBox's.
 constexpr double AUTO_DENSE_FACTOR = 4.0;
+// With FDBSCAN and minPts > 2, core points come from the pair traversal
+// (DBSCAN_FLAG_PAIR_COUNT) when points have fewer eps-neighbours on average
+// than minPts: the counting walk from the root then seldom stops early
+// (the 2^24 field at minPts 5: 0.65 against 2.0 ms; the 2^27 field at
+// minPts 10: 21 against 33 ms per call).
 constexpr uint32_t PROBE_SAMPLES_ONE_SET = 4096;  // sample points of a plain call
 constexpr uint32_t PROBE_SAMPLES_PER_SET = 256;   // and of each set of a batch
 
@@ -796,13 +802,15 @@ uint64_t mix(uint64_t h, uint64_t v) { return (h ^ v) * 0x100000001b3ull; }
 // density probe (probe.hip); the pick is kept for calls with the same
 // points, sizes, eps and minPts, so graph replays need no probe.
 int resolve_auto(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t num_sets,
-                 const float* h_eps, const int32_t* h_mp, hipStream_t s, int32_t* algo) {
+                 const float* h_eps, const int32_t* h_mp, hipStream_t s, int32_t* algo,
+                 bool* pair_count) {
   uint64_t h = 0xcbf29ce484222325ull;
   for (uint32_t k = 0; k < num_sets; ++k)
     h = mix(mix(mix(h, uint64_t(h_off[k + 1])), bits_of(h_eps[k])), uint64_t(uint32_t(h_mp[k])));
   const std::vector<uint64_t> key = {reinterpret_cast<uint64_t>(pts), num_sets, h};
   if (key == c->auto_key) {
     *algo = c->auto_algo;
+    *pair_count = c->auto_pair_count;
     return DBSCAN_OK;
   }
   const size_t off_b = 0, e2_b = align_up((size_t(num_sets) + 1) * 8);
@@ -849,8 +857,10 @@ int resolve_auto(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t
   const double mean = n > 0 ? sum / n : 0, mp_mean = n > 0 ? mp / n : 2;
   *algo = mean >= AUTO_DENSE_FACTOR * std::max(mp_mean, 2.0) ? DBSCAN_ALGO_DENSEBOX
                                                               : DBSCAN_ALGO_FDBSCAN;
+  *pair_count = *algo == DBSCAN_ALGO_FDBSCAN && mean < mp_mean;
   c->auto_key = key;
   c->auto_algo = *algo;
+  c->auto_pair_count = *pair_count;
   return DBSCAN_OK;
 }
 
@@ -1036,8 +1046,11 @@ int dbscan_cluster_ex(dbscan_ctx* c, const float* points, int64_t n, float eps, 
   if (!stream) o.flags &= ~DBSCAN_FLAG_GRAPH;  // graphs only on a stream the caller names
   if (o.algorithm == DBSCAN_ALGO_AUTO) {
     const int64_t off[2] = {0, n};
-    st = resolve_auto(c, points, off, 1, &eps, &min_pts, stream_of(c, stream), &o.algorithm);
+    bool pair_count = false;
+    st = resolve_auto(c, points, off, 1, &eps, &min_pts, stream_of(c, stream), &o.algorithm,
+                      &pair_count);
     if (st != DBSCAN_OK) return st;
+    if (pair_count) o.flags |= DBSCAN_FLAG_PAIR_COUNT;
   }
   if (o.algorithm == DBSCAN_ALGO_DENSEBOX)
     return run_densebox(c, points, uint32_t(n), eps, min_pts, labels, stream_of(c, stream), o);
@@ -1067,8 +1080,9 @@ int dbscan_cluster_batched(dbscan_ctx* c, const float* points, const int64_t* of
   c->sort_items = o.sort_tile / SORT_THREADS;
   if (!stream) o.flags &= ~DBSCAN_FLAG_GRAPH;  // graphs only on a stream the caller names
   if (o.algorithm == DBSCAN_ALGO_AUTO) {
+    bool pair_count = false;  // (a plain-call option: batched calls count by walk)
     int st = resolve_auto(c, points, offsets, uint32_t(num_sets), eps, min_pts,
-                          stream_of(c, stream), &o.algorithm);
+                          stream_of(c, stream), &o.algorithm, &pair_count);
     if (st != DBSCAN_OK) return st;
   }
   return run_batched(c, points, offsets, uint32_t(num_sets), eps, min_pts, labels,

@@ -27,11 +27,14 @@ def ran_densebox(ctx):
 
 
 def test_sparse_field_runs_fdbscan(ctx):
+    """FDBSCAN; at minPts > 2 with core points by pair traversal (fewer
+    neighbours than minPts on average): the labels do not change."""
     p = datagen.config_points("halo16M", n=1 << 20)
     d = torch.from_numpy(p).cuda()
-    got = ctx.cluster(d, 0.2, 2, algorithm="auto", timing=True).cpu().numpy()
-    assert not ran_densebox(ctx)
-    assert np.array_equal(got, oracle.dbscan(p, F32(0.2), 2))
+    for mp in (2, 3, 5):
+        got = ctx.cluster(d, 0.2, mp, algorithm="auto", timing=True).cpu().numpy()
+        assert not ran_densebox(ctx)
+        assert np.array_equal(got, oracle.dbscan(p, F32(0.2), mp)), mp
 
 
 def test_dense_clumps_run_densebox(ctx):
