@@ -18,6 +18,9 @@ dbscan_sets(points, offsets, ...) independent sets, each clustered alone,
 knn(points, k, queries)           k nearest neighbours, self included, ties
                                   to the smaller index (C, brute force)
 core_distances(points, min_pts)   squared distance to the min_pts-th nearest
+mst(points, min_pts)              minimum spanning tree: Euclidean for
+                                  min_pts <= 1, else of HDBSCAN*'s mutual
+                                  reachability graph (C, Prim, O(n^2))
 morton63(points)                  the 63-bit Morton code of every point,
                                   section 4.2.2 (numpy, plain definition)
 morton_order(codes)               stable sort permutation of the codes
@@ -30,7 +33,9 @@ Pins: the C functions by tests/test_oracle_pins.py (brute force, hand cases,
 binary32 boundary cases, metamorphic relations, planted mistakes); the
 Morton functions by tests/test_oracle_morton_pins.py (codes worked out by
 hand, binary32 grid coordinates decided with exact rationals, a de-interleave
-round trip, planted mistakes).
+round trip, planted mistakes); the spanning trees by
+tests/test_oracle_mst_pins.py (every spanning tree of tiny inputs, scipy's
+minimum spanning tree, the cycle property, closed forms, planted mistakes).
 """
 from __future__ import annotations
 
@@ -43,6 +48,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dbscan_oracle.c")
 _KNN_SRC = os.path.join(_HERE, "knn_oracle.c")
+_MST_SRC = os.path.join(_HERE, "mst_oracle.c")
 _LIB = os.path.join(_HERE, "_build", "liboracle.so")
 
 # The predicate must be evaluated exactly as written: no contraction into
@@ -56,7 +62,7 @@ def build(extra_flags=(), out=None) -> str:
     out = out or _LIB
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp%d" % os.getpid()
-    cmd = ["gcc", *CFLAGS, *extra_flags, _SRC, _KNN_SRC, "-o", tmp, "-lm"]
+    cmd = ["gcc", *CFLAGS, *extra_flags, _SRC, _KNN_SRC, _MST_SRC, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
     return out
@@ -90,6 +96,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
                                ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                f32p]
     lib.oracle_knn.restype = ctypes.c_int
+    lib.oracle_mst.argtypes = [f32p, ctypes.c_int64, f32p, ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_int32), f32p]
+    lib.oracle_mst.restype = ctypes.c_int
     lib.knn_set_threads.argtypes = [ctypes.c_int]
     lib.knn_set_threads.restype = ctypes.c_int
     lib.knn_set_threads(1)
@@ -194,6 +203,30 @@ def core_distances(points, min_pts: int, queries=None, lib=None) -> np.ndarray:
     """HDBSCAN*'s core distance, squared: D to the min_pts-th nearest
     neighbour, the point itself counted (inf if there are fewer points)."""
     return knn(points, min_pts, queries, lib)[1][:, int(min_pts) - 1].copy()
+
+
+def mst(points, min_pts: int = 1, core=None, lib=None):
+    """Minimum spanning tree of the complete graph with weights
+    max(c_i, c_j, D(i, j)), c the squared core distances at min_pts (none
+    for min_pts <= 1: the Euclidean tree) or the given `core`.  Returns
+    (edges int32[n-1, 2] as (lo, hi) input indices, squared weights
+    float32[n-1]) in increasing (w, lo, hi) order.  See mst_oracle.c."""
+    lib = lib or _get()
+    p = _as_points(points)
+    n = p.shape[0]
+    if core is None and int(min_pts) > 1 and n > 0:
+        core = core_distances(p, int(min_pts), lib=lib)
+    c = None if core is None else np.ascontiguousarray(core, dtype=np.float32)
+    m = max(n - 1, 0)
+    lo = np.empty(m, dtype=np.int32)
+    hi = np.empty(m, dtype=np.int32)
+    w = np.empty(m, dtype=np.float32)
+    st = lib.oracle_mst(_ptr(p, ctypes.c_float), n, None if c is None else _ptr(c, ctypes.c_float),
+                        _ptr(lo, ctypes.c_int32), _ptr(hi, ctypes.c_int32),
+                        _ptr(w, ctypes.c_float))
+    if st != 0:
+        raise OracleError(st)
+    return np.stack([lo, hi], axis=1), w
 
 
 def core_flags(points, eps, min_pts, lib=None) -> np.ndarray:
