@@ -321,6 +321,26 @@ int dbscan_knn(dbscan_ctx* ctx, const float* points, int64_t n, int32_t k,
 int dbscan_core_distances(dbscan_ctx* ctx, const float* points, int64_t n, int32_t min_pts,
                           float* sq_dists, void* stream);
 
+/* Minimum spanning tree of the points over the same linear BVH: with
+ * min_pts <= 1 the Euclidean tree (one of ArborX's algorithms, section 3.2);
+ * with min_pts >= 2 the tree of HDBSCAN*'s mutual reachability graph
+ * (section 5), the graph HDBSCAN* clusters from.  An edge {i, j} weighs
+ *     w = max(c_i, c_j, D(i, j)),
+ * D the binary32 squared distance of the clustering predicate and c the
+ * squared core distances of dbscan_core_distances at min_pts (zero for
+ * min_pts = 1), so w is the square of the mutual reachability distance.
+ * Edges are ordered by (w, lo, hi), lo < hi the input indices of the ends;
+ * under that strict order the tree is unique, and it is returned in that
+ * order (the order single-linkage merges them).
+ *   edges      device int32[n-1][2]: (lo, hi) of each edge;
+ *   sq_weights device float[n-1]: w of each edge.
+ * 1 <= min_pts <= 32, else EINVAL; n < 2: nothing is written.  Errors as
+ * for dbscan_cluster_ex; EDEVICE if the Borůvka rounds stop adding edges
+ * (a malformed tree).  The context keeps a device buffer of about 120
+ * bytes per point for the rounds, on top of its arena. */
+int dbscan_mst(dbscan_ctx* ctx, const float* points, int64_t n, int32_t min_pts,
+               int32_t* edges, float* sq_weights, void* stream);
+
 /* ---- diagnostics ------------------------------------------------------------ */
 const char* dbscan_strerror(int status);
 const char* dbscan_last_error(void);

@@ -114,6 +114,7 @@ def load_library() -> ctypes.CDLL:
                                      ctypes.POINTER(f32), vp], ctypes.c_int),
         "dbscan_knn": ([vp, vp, i64, i32, vp, vp, vp], ctypes.c_int),
         "dbscan_core_distances": ([vp, vp, i64, i32, vp, vp], ctypes.c_int),
+        "dbscan_mst": ([vp, vp, i64, i32, vp, vp, vp], ctypes.c_int),
         "dbscan_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "dbscan_last_error": ([], ctypes.c_char_p),
         "dbscan_version": ([], ctypes.c_char_p),
@@ -437,6 +438,22 @@ class Context:
             self.handle, ctypes.c_void_p(p.data_ptr()), p.shape[0], int(min_pts),
             ctypes.c_void_p(d2.data_ptr()), _stream(p.device)))
         return d2
+
+    def mst(self, points, min_pts: int = 1):
+        """Minimum spanning tree: Euclidean for min_pts = 1, else of
+        HDBSCAN*'s mutual reachability graph at min_pts.  Returns (edges
+        int32 [n-1, 2] as (lo, hi) input indices, squared weights float32
+        [n-1]) on the points' device, in increasing (w, lo, hi) order."""
+        torch = _torch()
+        p = _points(points)
+        m = max(p.shape[0] - 1, 0)
+        edges = torch.empty((m, 2), dtype=torch.int32, device=p.device)
+        w = torch.empty(m, dtype=torch.float32, device=p.device)
+        _check(load_library().dbscan_mst(
+            self.handle, ctypes.c_void_p(p.data_ptr()), p.shape[0], int(min_pts),
+            ctypes.c_void_p(edges.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+            _stream(p.device)))
+        return edges, w
 
     def pair_count(self, points, eps: float) -> int:
         p = _points(points)

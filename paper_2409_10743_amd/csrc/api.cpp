@@ -165,6 +165,9 @@ struct dbscan_ctx {
   std::vector<uint64_t> auto_key;
   int32_t auto_algo = DBSCAN_ALGO_FDBSCAN;
   bool auto_pair_count = false;
+  // dbscan_mst: the Borůvka rounds' device buffer
+  char* mst = nullptr;
+  size_t mst_cap = 0;
 };
 
 namespace {
@@ -1020,6 +1023,7 @@ int dbscan_ctx_destroy(dbscan_ctx* c) {
   if (c->host_status) (void)hipHostFree(c->host_status);
   if (c->stage) (void)hipHostFree(c->stage);
   if (c->probe) (void)hipFree(c->probe);
+  if (c->mst) (void)hipFree(c->mst);
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -1330,6 +1334,161 @@ int dbscan_knn(dbscan_ctx* c, const float* points, int64_t n, int32_t k, int32_t
 int dbscan_core_distances(dbscan_ctx* c, const float* points, int64_t n, int32_t min_pts,
                           float* sq_dists, void* stream) {
   return knn_common(c, points, n, min_pts, nullptr, nullptr, sq_dists, stream);
+}
+
+// Minimum spanning tree (mst.hip): the tree with full 63-bit codes, core
+// distances by the kNN walk (min_pts > 1), then Borůvka rounds until n - 1
+// edges are written (each round's edge count is read back: the host decides
+// whether to run another), then the edges sorted by (w, lo, hi).
+namespace {
+struct MstLayout {
+  size_t comp, flag, run, ends, rec, best_w, best_j, seed, comp_best, comp_hi, comp_edge, core,
+      lo, hi, w, ka, kb, va, vb, small, hist, tile_ctr, scan_status, sort_status, total;
+};
+MstLayout mst_layout(uint32_t n) {
+  MstLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align_up(std::max<size_t>(bytes, 4));
+    return at;
+  };
+  L.comp = take(size_t(n) * 4);
+  L.flag = take(size_t(n) * 4);
+  L.run = take(size_t(n) * 4);
+  L.ends = take(size_t(n) * 4);
+  L.rec = take(size_t(n) * sizeof(MstRec));
+  L.best_w = take(size_t(n) * 4);
+  L.best_j = take(size_t(n) * 4);
+  L.seed = take(size_t(n) * 4);
+  L.comp_best = take(size_t(n) * 8);
+  L.comp_hi = take(size_t(n) * 4);
+  L.comp_edge = take(size_t(n) * 8);
+  L.core = take(size_t(n) * 4);
+  L.lo = take(size_t(n) * 4);
+  L.hi = take(size_t(n) * 4);
+  L.w = take(size_t(n) * 4);
+  L.ka = take(size_t(n) * 8);
+  L.kb = take(size_t(n) * 8);
+  L.va = take(size_t(n) * 4);
+  L.vb = take(size_t(n) * 4);
+  L.small = take(4 * 4);  // scan total, scan tile counter, edge count
+  L.hist = take(SORT_PASSES * RADIX * 4);
+  L.tile_ctr = take(SORT_PASSES * 4);
+  L.scan_status = take(scan_status_words(n) * 4);
+  L.sort_status = take(sort_status_words(n) * 4);
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+int dbscan_mst(dbscan_ctx* c, const float* points, int64_t n, int32_t min_pts, int32_t* edges,
+               float* sq_weights, void* stream) {
+  if (!c) return fail(DBSCAN_EINVAL, "null context");
+  int st = check_args(points, n, 0.0f, 1, n > 1 ? static_cast<void*>(edges) : points);
+  if (st != DBSCAN_OK) return st;
+  if (min_pts < 1 || min_pts > KNN_MAX_K) return fail(DBSCAN_EINVAL, "min_pts must be in [1, 32]");
+  if (n > 1 && !sq_weights) return fail(DBSCAN_EINVAL, "null pointer");
+  if (n < 2) return DBSCAN_OK;
+  DeviceGuard g(c->device);
+  hipStream_t s = stream_of(c, stream);
+  const uint32_t un = uint32_t(n), m = un - 1;
+  const MstLayout L = mst_layout(un);
+  if (c->mst_cap < L.total) {
+    if (c->mst) {
+      HIP_TRY(hipStreamSynchronize(s));
+      HIP_TRY(hipFree(c->mst));
+    }
+    c->mst = nullptr;
+    c->mst_cap = 0;
+    if (hipMalloc(&c->mst, L.total) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(DBSCAN_ENOMEM, "hipMalloc of the spanning tree's buffers failed");
+    }
+    c->mst_cap = L.total;
+  }
+  char* B = c->mst;
+  auto P = [&](size_t off) { return static_cast<void*>(B + off); };
+  int32_t* comp = static_cast<int32_t*>(P(L.comp));
+  uint32_t* flag = static_cast<uint32_t*>(P(L.flag));
+  uint32_t* run = static_cast<uint32_t*>(P(L.run));
+  uint32_t* ends = static_cast<uint32_t*>(P(L.ends));
+  MstRec* rec = static_cast<MstRec*>(P(L.rec));
+  float* best_w = static_cast<float*>(P(L.best_w));
+  int32_t* best_j = static_cast<int32_t*>(P(L.best_j));
+  int32_t* seed = static_cast<int32_t*>(P(L.seed));
+  auto* comp_best = static_cast<unsigned long long*>(P(L.comp_best));
+  uint32_t* comp_hi = static_cast<uint32_t*>(P(L.comp_hi));
+  int2* comp_edge = static_cast<int2*>(P(L.comp_edge));
+  float* core = static_cast<float*>(P(L.core));
+  uint32_t* lo = static_cast<uint32_t*>(P(L.lo));
+  uint32_t* hi = static_cast<uint32_t*>(P(L.hi));
+  float* w = static_cast<float*>(P(L.w));
+  uint64_t* ka = static_cast<uint64_t*>(P(L.ka));
+  uint64_t* kb = static_cast<uint64_t*>(P(L.kb));
+  uint32_t* va = static_cast<uint32_t*>(P(L.va));
+  uint32_t* vb = static_cast<uint32_t*>(P(L.vb));
+  uint32_t* small = static_cast<uint32_t*>(P(L.small));  // total, scan counter, edge count
+  uint32_t* count = small + 2;
+
+  Index ix;
+  c->sort_items = 0;  // the default sort tile
+  st = build_index(c, points, un, false, false, s, &ix, 0.0f, nullptr, nullptr);
+  if (st != DBSCAN_OK) return st;
+  if (min_pts > 1)
+    launch_knn(ix.nodes, ix.leaf, ix.perm, un, ix.root, min_pts, nullptr, nullptr, core,
+               ix.status, s);
+  int32_t* parent = at<int32_t>(c, ix.L.parent);  // every position its own root (the build)
+  launch_mst_init(un, comp, comp_best, comp_hi, seed, comp_edge, s);
+  HIP_TRY(hipMemsetAsync(small, 0, 16, s));
+  uint32_t done = 0;
+  for (int round = 0; done < m; ++round) {
+    if (round >= 64) return fail(DBSCAN_EDEVICE, "spanning tree: no convergence");
+    HIP_TRY(hipMemsetAsync(small, 0, 8, s));  // the scan's total and tile counter
+    HIP_TRY(hipMemsetAsync(P(L.scan_status), 0, scan_status_words(un) * 4, s));
+    launch_mst_runs(un, comp, flag, run, ends, small, static_cast<uint32_t*>(P(L.scan_status)),
+                    small + 1, ix.status, s);
+    launch_mst_records(un, comp, run, ends, min_pts > 1 ? core : nullptr, ix.perm, rec, s);
+    launch_mst_round(ix.nodes, ix.leaf, rec, run, ends, un, ix.root, ix.perm, parent, comp_best,
+                     comp_hi,
+                     comp_edge, best_w, best_j, seed, count, lo, hi, w, ix.status, s);
+    launch_mst_settle(un, parent, comp, comp_best, comp_hi, comp_edge, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(c->host_status, ix.status, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(c->host_status + 1, count, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c->host_status[0] != 0) return finish(c, ix.status, false, s);
+    const uint32_t now = c->host_status[1];
+    if (now <= done || now > m) return fail(DBSCAN_EDEVICE, "spanning tree: a round added no edge");
+    done = now;
+  }
+  // (w, lo, hi) order: a stable sort by hi, then by (w, lo)
+  SortScratch sc{static_cast<uint32_t*>(P(L.hist)), static_cast<uint32_t*>(P(L.tile_ctr)),
+                 static_cast<uint32_t*>(P(L.sort_status)), ix.status};
+  auto sort_prep = [&](const uint64_t* keys) -> int {
+    HIP_TRY(hipMemsetAsync(sc.hist, 0, SORT_PASSES * RADIX * 4, s));
+    HIP_TRY(hipMemsetAsync(sc.tile_ctr, 0, SORT_PASSES * 4, s));
+    HIP_TRY(hipMemsetAsync(sc.status, 0, sort_first_status_words(m) * 4, s));
+    launch_digit_histogram(keys, m, sc.hist, s);
+    return DBSCAN_OK;
+  };
+  launch_mst_sort_keys_hi(m, hi, ka, s);
+  st = sort_prep(ka);
+  if (st != DBSCAN_OK) return st;
+  const bool in_a1 = launch_radix_sort(ka, kb, va, vb, m, 4, true, sc, s);
+  const uint32_t* order1 = in_a1 ? va : vb;
+  uint32_t* vfree = in_a1 ? vb : va;
+  // keys of the second sort in the free key buffer, its values beside them
+  uint64_t* k2 = in_a1 ? kb : ka;
+  uint64_t* k2b = in_a1 ? ka : kb;
+  launch_mst_sort_keys_wlo(m, order1, lo, w, k2, vfree, s);
+  st = sort_prep(k2);
+  if (st != DBSCAN_OK) return st;
+  uint32_t* v2b = const_cast<uint32_t*>(order1);  // order1 is consumed by now
+  const bool in_a2 = launch_radix_sort(k2, k2b, vfree, v2b, m, 0, false, sc, s);
+  launch_mst_out(m, in_a2 ? vfree : v2b, lo, hi, w, edges, sq_weights, s);
+  HIP_TRY(hipGetLastError());
+  return finish(c, ix.status, false, s);
 }
 
 int dbscan_autotune(dbscan_ctx* c, const float* points, int64_t n, float eps, int32_t min_pts,

@@ -21,7 +21,7 @@ ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libdbscan_mi355x.so")
 BUILD = os.path.join(PKG, "_build")
 SOURCES = ["morton.hip", "radix_sort.hip", "lbvh.hip", "traverse.hip", "finalize.hip",
-           "densebox.hip", "batched.hip", "knn.hip", "probe.hip", "api.cpp", "server.cpp"]
+           "densebox.hip", "batched.hip", "knn.hip", "mst.hip", "probe.hip", "api.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-ffp-contract=off", "-fno-gpu-flush-denormals-to-zero",

@@ -172,6 +172,48 @@ void launch_knn(const Node* nodes, const float4* leaf, const uint32_t* perm, uin
                 const int32_t* root, int32_t k, int32_t* out_idx, float* out_d2, float* core_d2,
                 uint32_t* err, hipStream_t s);
 
+// ---- minimum spanning trees (mst.hip) -------------------------------------------
+// Per position (Morton-sorted leaf) record of a Borůvka round: the last
+// position of the run of equal components starting here, the component (a
+// union-find root position), the squared core distance and the input index.
+struct alignas(16) MstRec {
+  uint32_t run_end;
+  int32_t comp;
+  float core;
+  uint32_t orig;
+};
+// every point its own component; no minima, no seeds
+void launch_mst_init(uint32_t n, int32_t* comp, unsigned long long* comp_best, uint32_t* comp_hi,
+                     int32_t* seed, int2* comp_edge, hipStream_t s);
+// runs of equal components: run[i] = number of runs ending before i, ends[r]
+// = last position of run r (scan state zeroed; *total = the number of runs)
+void launch_mst_runs(uint32_t n, const int32_t* comp, uint32_t* flag, uint32_t* run,
+                     uint32_t* ends, uint32_t* total, uint32_t* scan_status, uint32_t* scan_ctr,
+                     uint32_t* err, hipStream_t s);
+// the round's records (core_in: squared core distances in input order, or
+// null for zero)
+void launch_mst_records(uint32_t n, const int32_t* comp, const uint32_t* run, const uint32_t* ends,
+                        const float* core_in, const uint32_t* perm, MstRec* rec, hipStream_t s);
+// one round: each component's least edge, written once (at out_*[*count++])
+// and unioned into parent
+void launch_mst_round(const Node* nodes, const float4* leaf, const MstRec* rec,
+                      const uint32_t* run, const uint32_t* ends, uint32_t n,
+                      const int32_t* root, const uint32_t* perm, int32_t* parent,
+                      unsigned long long* comp_best, uint32_t* comp_hi, int2* comp_edge,
+                      float* best_w, int32_t* best_j, int32_t* seed, uint32_t* count,
+                      uint32_t* out_lo, uint32_t* out_hi, float* out_w, uint32_t* err,
+                      hipStream_t s);
+// components = union-find roots; the round's minima cleared
+void launch_mst_settle(uint32_t n, int32_t* parent, int32_t* comp, unsigned long long* comp_best,
+                       uint32_t* comp_hi, int2* comp_edge, hipStream_t s);
+// edge order (w, lo, hi): keys for a sort by hi (top word), then by (w, lo)
+void launch_mst_sort_keys_hi(uint32_t m, const uint32_t* hi, uint64_t* key, hipStream_t s);
+void launch_mst_sort_keys_wlo(uint32_t m, const uint32_t* order, const uint32_t* lo,
+                              const float* w, uint64_t* key, uint32_t* val, hipStream_t s);
+// edges[k] = (lo, hi), weights[k] = w of edge order[k]
+void launch_mst_out(uint32_t m, const uint32_t* order, const uint32_t* lo, const uint32_t* hi,
+                    const float* w, int32_t* edges, float* weights, hipStream_t s);
+
 // ---- density probe (probe.hip) ---------------------------------------------------
 // *out += sum over sets of n_k times an unbiased estimate of set k's mean
 // eps-neighbour count (point itself left out), from min(n_k, s_max) evenly
