@@ -365,6 +365,8 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=60.0)
     ap.add_argument("--knn-only", action="store_true",
                     help="only the k-nearest-neighbour leg on --workload (for profiling)")
+    ap.add_argument("--mst-only", action="store_true",
+                    help="only the minimum-spanning-tree leg on --workload (for profiling)")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="write profiles/trace_<workload>.txt from a rocprofv3 kernel trace")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH",
@@ -385,6 +387,7 @@ def main():
         sys.exit(2)
     tag = args.workload + ("" if args.algorithm == "fdbscan" else "_" + args.algorithm)
     tag += "_knn" if args.knn_only else ""
+    tag += "_mst" if args.mst_only else ""
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, tag, " ".join(args.profile_cmd) or "?",
                         args.bench_line, os.path.join(ROOT, "profiles", f"trace_{tag}.txt"))
@@ -437,6 +440,11 @@ def main():
     if args.knn_only:
         log("[bench] k nearest neighbours only ...")
         print(json.dumps({"workload": args.workload, "n": n, "knn": bench_knn(ctx, d, pts)}),
+              flush=True)
+        return
+    if args.mst_only:
+        log("[bench] minimum spanning trees only ...")
+        print(json.dumps({"workload": args.workload, "n": n, "mst": bench_mst(ctx, d, pts)}),
               flush=True)
         return
     log(f"[bench] n={n} eps={float(eps)} minPts={mp} {args.algorithm}: warmup {args.warmup}")
@@ -524,6 +532,8 @@ def main():
         del dc
         log("[bench] k nearest neighbours ...")
         out["knn"] = bench_knn(ctx, d, pts)
+        log("[bench] minimum spanning trees ...")
+        out["mst"] = bench_mst(ctx, d, pts)
         del d, labels
         torch.cuda.empty_cache()
         out["batched"] = bench_batched(ctx)
@@ -722,6 +732,64 @@ def bench_knn(ctx, d, pts, k=8, min_pts=5, steps=3, rows=300):
     res["sampled_rows_bit_exact"] = same
     res["rows_checked"] = rows
     res["core_distances"]["min_pts"] = min_pts
+    return res
+
+
+def bench_mst(ctx, d, pts, steps=3, min_pts=5, samples=100, subset=20000):
+    """Minimum spanning trees of the field (the Euclidean tree of section
+    3.2's algorithm list; HDBSCAN*'s mutual reachability tree, section 5),
+    timed.  Checked: the Euclidean tree's weights are the binary32 D of its
+    ends, it spans the field, and the least edge at each of `samples`
+    sampled points (brute force over the whole field) is a tree edge; both
+    trees of the first `subset` points equal the oracle's (Prim) bit for bit."""
+    import torch
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    import oracle
+    n = d.shape[0]
+    res = {}
+    for name, mp in (("euclidean", 1), ("mutual_reachability", min_pts)):
+        e, w = ctx.mst(d, mp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            e, w = ctx.mst(d, mp)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[name] = {"min_pts": mp, "ms_per_call": round(ms, 2),
+                     "mpoints_per_s": round(n / ms / 1e3, 2)}
+    e, w = ctx.mst(d, 1)
+    e, w = e.cpu().numpy().astype(np.int64), w.cpu().numpy()
+    lo, hi = e[:, 0], e[:, 1]
+
+    def d2(a, b):
+        x = a - b
+        x = x * x
+        return (x[..., 0] + x[..., 1]) + x[..., 2]
+    ok = bool(np.array_equal(w.view(np.uint32), d2(pts[lo], pts[hi]).view(np.uint32)))
+    g = coo_matrix((np.ones(n - 1, np.int8), (lo, hi)), shape=(n, n))
+    ok = ok and connected_components(g, directed=False)[0] == 1
+    tree = set(zip(lo.tolist(), hi.tolist()))
+    rng = np.random.default_rng(12)
+    for u in rng.choice(n, samples, replace=False).tolist():
+        dd = d2(pts, pts[u])
+        dd[u] = np.inf
+        v = int(np.flatnonzero(dd == dd.min())[0])
+        ok = ok and (min(u, v), max(u, v)) in tree
+    res["euclidean"]["properties_hold"] = ok
+    res["euclidean"]["sampled_points"] = samples
+    sub = np.ascontiguousarray(pts[:subset])
+    ds = torch.from_numpy(sub).cuda()
+    same = True
+    t0 = time.perf_counter()
+    for mp in (1, min_pts):
+        ge, gw = ctx.mst(ds, mp)
+        re, rw = oracle.mst(sub, mp)
+        same = same and np.array_equal(ge.cpu().numpy(), re) and np.array_equal(
+            gw.cpu().numpy().view(np.uint32), rw.view(np.uint32))
+    res["oracle_subset"] = {"points": subset, "bit_exact": same,
+                            "oracle_seconds_both_trees": round(time.perf_counter() - t0, 2)}
     return res
 
 
