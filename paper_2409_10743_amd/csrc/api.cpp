@@ -1342,7 +1342,7 @@ int dbscan_core_distances(dbscan_ctx* c, const float* points, int64_t n, int32_t
 // whether to run another), then the edges sorted by (w, lo, hi).
 namespace {
 struct MstLayout {
-  size_t comp, flag, run, ends, rec, best_w, best_j, seed, comp_best, comp_hi, comp_edge, core,
+  size_t comp, flag, run, ends, rec, best_w, best_j, seed, lb, comp_best, comp_hi, comp_edge, core,
       lo, hi, w, ka, kb, va, vb, small, hist, tile_ctr, scan_status, sort_status, total;
 };
 MstLayout mst_layout(uint32_t n) {
@@ -1361,6 +1361,7 @@ MstLayout mst_layout(uint32_t n) {
   L.best_w = take(size_t(n) * 4);
   L.best_j = take(size_t(n) * 4);
   L.seed = take(size_t(n) * 4);
+  L.lb = take(size_t(n) * 4);
   L.comp_best = take(size_t(n) * 8);
   L.comp_hi = take(size_t(n) * 4);
   L.comp_edge = take(size_t(n) * 8);
@@ -1417,6 +1418,7 @@ int dbscan_mst(dbscan_ctx* c, const float* points, int64_t n, int32_t min_pts, i
   float* best_w = static_cast<float*>(P(L.best_w));
   int32_t* best_j = static_cast<int32_t*>(P(L.best_j));
   int32_t* seed = static_cast<int32_t*>(P(L.seed));
+  float* lb = static_cast<float*>(P(L.lb));
   auto* comp_best = static_cast<unsigned long long*>(P(L.comp_best));
   uint32_t* comp_hi = static_cast<uint32_t*>(P(L.comp_hi));
   int2* comp_edge = static_cast<int2*>(P(L.comp_edge));
@@ -1439,7 +1441,7 @@ int dbscan_mst(dbscan_ctx* c, const float* points, int64_t n, int32_t min_pts, i
     launch_knn(ix.nodes, ix.leaf, ix.perm, un, ix.root, min_pts, nullptr, nullptr, core,
                ix.status, s);
   int32_t* parent = at<int32_t>(c, ix.L.parent);  // every position its own root (the build)
-  launch_mst_init(un, comp, comp_best, comp_hi, seed, comp_edge, s);
+  launch_mst_init(un, comp, comp_best, comp_hi, seed, lb, comp_edge, s);
   HIP_TRY(hipMemsetAsync(small, 0, 16, s));
   uint32_t done = 0;
   for (int round = 0; done < m; ++round) {
@@ -1451,7 +1453,7 @@ int dbscan_mst(dbscan_ctx* c, const float* points, int64_t n, int32_t min_pts, i
     launch_mst_records(un, comp, run, ends, min_pts > 1 ? core : nullptr, ix.perm, rec, s);
     launch_mst_round(ix.nodes, ix.leaf, rec, run, ends, un, ix.root, ix.perm, parent, comp_best,
                      comp_hi,
-                     comp_edge, best_w, best_j, seed, count, lo, hi, w, ix.status, s);
+                     comp_edge, best_w, best_j, seed, lb, count, lo, hi, w, ix.status, s);
     launch_mst_settle(un, parent, comp, comp_best, comp_hi, comp_edge, s);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(c->host_status, ix.status, 4, hipMemcpyDeviceToHost, s));

@@ -44,6 +44,13 @@ namespace {
 
 constexpr unsigned long long NO_EDGE = ~0ull;
 
+// atomicMin into a component's minimum, skipped when the value read there
+// is already no larger (minima only fall, so a skipped key could not have
+// lowered it): in the last rounds millions of points share a few minima
+__device__ __forceinline__ void min_into(unsigned long long* at, unsigned long long key) {
+  if (key < __hip_atomic_load(at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(at, key);
+}
+
 // first position of the range a rope leads past: the node's last leaf + 1
 __device__ __forceinline__ uint32_t past_end(int32_t rope, uint32_t n) {
   return rope == SENTINEL ? n : uint32_t(rope < -1 ? leaf_index(rope) : rope);
@@ -60,7 +67,7 @@ __device__ __forceinline__ unsigned long long wlo_key(float w, uint32_t lo) {
 
 __global__ __launch_bounds__(256) void k_mst_init(uint32_t n, int32_t* comp,
                                                   unsigned long long* comp_best,
-                                                  uint32_t* comp_hi, int32_t* seed,
+                                                  uint32_t* comp_hi, int32_t* seed, float* lb,
                                                   int2* comp_edge) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -68,6 +75,7 @@ __global__ __launch_bounds__(256) void k_mst_init(uint32_t n, int32_t* comp,
   comp_best[i] = NO_EDGE;
   comp_hi[i] = ~0u;
   seed[i] = -1;
+  lb[i] = 0.0f;
   comp_edge[i] = make_int2(-1, -1);
 }
 
@@ -102,6 +110,100 @@ __global__ __launch_bounds__(256) void k_mst_records(
   rec[i] = r;
 }
 
+// the seeds of a point: last round's edge and the positions just past
+// either end of its run (its own position where there is none)
+__device__ __forceinline__ void seeds_of(uint32_t i, uint32_t n, const MstRec& r,
+                                         const int32_t* __restrict__ seed,
+                                         const uint32_t* __restrict__ run,
+                                         const uint32_t* __restrict__ ends, uint32_t sj[3]) {
+  const int32_t s0 = seed[i];
+  const uint32_t ri = run[i];
+  sj[0] = s0 >= 0 ? uint32_t(s0) : i;
+  sj[1] = r.run_end + 1 < n ? r.run_end + 1 : i;
+  sj[2] = ri > 0 ? ends[ri - 1] : i;
+}
+
+// Before the walks: every point's best seed edge goes into its component's
+// minimum, so that every walk starts with a bound for its whole component
+// (and may find that it cannot beat it, below).  In the last rounds a few
+// components hold millions of points: the keys of a block whose points
+// share one component are combined first (one atomic per block).
+__global__ __launch_bounds__(256) void k_mst_seed(uint32_t n, const float4* __restrict__ leaf,
+                                                  const MstRec* __restrict__ rec,
+                                                  const int32_t* __restrict__ seed,
+                                                  const uint32_t* __restrict__ run,
+                                                  const uint32_t* __restrict__ ends,
+                                                  unsigned long long* comp_best) {
+  __shared__ unsigned long long s_min[4];
+  __shared__ int32_t s_comp[4];
+  __shared__ int s_mixed;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = i < n;
+  const uint32_t k = in ? i : blockIdx.x * blockDim.x;  // the block's first point: in range
+  const MstRec r = rec[k];
+  const float4 q = leaf[k];
+  uint32_t sj[3];
+  seeds_of(k, n, r, seed, run, ends, sj);
+  unsigned long long best = NO_EDGE;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const MstRec rs = rec[sj[t]];
+    const float4 p = leaf[sj[t]];
+    if (rs.comp != r.comp) {
+      const float w = fmaxf(fmaxf(r.core, rs.core), sq_dist(q.x, q.y, q.z, p.x, p.y, p.z));
+      const unsigned long long key = wlo_key(w, min(r.orig, rs.orig));
+      best = key < best ? key : best;
+    }
+  }
+  if (!in) best = NO_EDGE;
+  if (threadIdx.x == 0) s_mixed = 0;
+  __syncthreads();
+  const int32_t c0 = __builtin_amdgcn_readfirstlane(r.comp);
+  const bool wave_one = __ballot(r.comp != c0) == 0ull;  // out-of-range lanes hold the first point
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long x = __shfl_xor(best, o, 64);
+    best = x < best ? x : best;
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_min[w] = best;
+    s_comp[w] = c0;
+    if (!wave_one) s_mixed = 1;
+  }
+  __syncthreads();
+  if (s_mixed) {  // per point, as found
+    unsigned long long mine = NO_EDGE;
+    if (in) {
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const MstRec rs = rec[sj[t]];
+        const float4 p = leaf[sj[t]];
+        if (rs.comp != r.comp) {
+          const float ww = fmaxf(fmaxf(r.core, rs.core), sq_dist(q.x, q.y, q.z, p.x, p.y, p.z));
+          const unsigned long long key = wlo_key(ww, min(r.orig, rs.orig));
+          mine = key < mine ? key : mine;
+        }
+      }
+    }
+    if (mine != NO_EDGE) min_into(comp_best + r.comp, mine);
+    return;
+  }
+  if (threadIdx.x == 0) {
+    unsigned long long m = s_min[0];
+    bool one = true;
+    for (int t = 1; t < int(blockDim.x >> 6); ++t) {
+      m = s_min[t] < m ? s_min[t] : m;
+      one = one && s_comp[t] == s_comp[0];
+    }
+    if (one) {
+      if (m != NO_EDGE) min_into(comp_best + s_comp[0], m);
+    } else {
+      for (int t = 0; t < int(blockDim.x >> 6); ++t)
+        if (s_min[t] != NO_EDGE) min_into(comp_best + s_comp[t], s_min[t]);
+    }
+  }
+}
+
 // The least edge from each point to another component (see the file
 // comment).  One lane per point at a time, the chunk scheme of wave_walks.
 __global__ __launch_bounds__(256) void k_mst_walk(
@@ -109,7 +211,7 @@ __global__ __launch_bounds__(256) void k_mst_walk(
     const MstRec* __restrict__ rec, const uint32_t* __restrict__ run,
     const uint32_t* __restrict__ ends, uint32_t n, WalkCfg wc, const int32_t* __restrict__ root_p,
     unsigned long long* comp_best, float* __restrict__ best_w, int32_t* __restrict__ best_j,
-    int32_t* __restrict__ seed, uint32_t* err) {
+    int32_t* __restrict__ seed, float* __restrict__ lb, uint32_t* err) {
   uint32_t c0, c1;
   walk_chunk(n, wc.chunk, c0, c1);
   const int32_t root = *root_p;
@@ -142,8 +244,9 @@ __global__ __launch_bounds__(256) void k_mst_walk(
       if (have) {
         best_w[i] = bw;
         best_j[i] = bj;
-        seed[i] = bj;
-        if (bj >= 0) atomicMin(comp_best + mycomp, wlo_key(bw, blo));
+        if (bj >= 0) seed[i] = bj;
+        lb[i] = fminf(bw, cw);
+        if (bj >= 0) min_into(comp_best + mycomp, wlo_key(bw, blo));
         have = false;
       }
       const uint32_t idx = head + uint32_t(__popcll(m & lt));
@@ -158,22 +261,29 @@ __global__ __launch_bounds__(256) void k_mst_walk(
         bw = INFINITY;
         blo = bhi = ~0u;
         bj = -1;
-        // seeds: last round's edge (if it still leaves the component) and
-        // the nearest positions of other components in Morton order, just
-        // past either end of the point's run
-        const int32_t s0 = seed[i];
-        const uint32_t ri = run[i];
-        const uint32_t sj[3] = {s0 >= 0 ? uint32_t(s0) : i, r.run_end + 1 < n ? r.run_end + 1 : i,
-                                ri > 0 ? ends[ri - 1] : i};
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-          const MstRec rs = rec[sj[t]];
-          const float4 ps = leaf[sj[t]];
-          if (rs.comp != mycomp) offer(sj[t], rs, ps);
-        }
         const unsigned long long cb = comp_best[mycomp];
         cw = cb == NO_EDGE ? INFINITY : __uint_as_float(uint32_t(cb >> 32));
         node = n > 1 ? root : SENTINEL;
+        if (lb[i] > cw) {
+          // every edge of this point weighs at least lb (other components
+          // only merge, and the last walk saw every edge up to lb), more
+          // than an edge its component already has: nothing to find
+          node = SENTINEL;
+          best_j[i] = -1;
+          have = false;
+        } else {
+          // seeds: last round's edge (if it still leaves the component) and
+          // the nearest positions of other components in Morton order, just
+          // past either end of the point's run
+          uint32_t sj[3];
+          seeds_of(i, n, r, seed, run, ends, sj);
+#pragma unroll
+          for (int t = 0; t < 3; ++t) {
+            const MstRec rs = rec[sj[t]];
+            const float4 ps = leaf[sj[t]];
+            if (rs.comp != mycomp) offer(sj[t], rs, ps);
+          }
+        }
         f = 0;
         steps = 0;
       }
@@ -226,8 +336,9 @@ __global__ __launch_bounds__(256) void k_mst_walk(
   if (have) {
     best_w[i] = bw;
     best_j[i] = bj;
-    seed[i] = bj;
-    if (bj >= 0) atomicMin(comp_best + mycomp, wlo_key(bw, blo));
+    if (bj >= 0) seed[i] = bj;
+    lb[i] = fminf(bw, cw);
+    if (bj >= 0) min_into(comp_best + mycomp, wlo_key(bw, blo));
   }
 }
 
@@ -345,9 +456,9 @@ inline dim3 grid_of(uint32_t n) { return dim3((n + 255) / 256); }
 }  // namespace
 
 void launch_mst_init(uint32_t n, int32_t* comp, unsigned long long* comp_best, uint32_t* comp_hi,
-                     int32_t* seed, int2* comp_edge, hipStream_t s) {
+                     int32_t* seed, float* lb, int2* comp_edge, hipStream_t s) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_mst_init, grid_of(n), dim3(256), 0, s, n, comp, comp_best, comp_hi, seed,
+  hipLaunchKernelGGL(k_mst_init, grid_of(n), dim3(256), 0, s, n, comp, comp_best, comp_hi, seed, lb,
                      comp_edge);
 }
 
@@ -371,12 +482,14 @@ void launch_mst_round(const Node* nodes, const float4* leaf, const MstRec* rec,
                       const uint32_t* run, const uint32_t* ends, uint32_t n,
                       const int32_t* root, const uint32_t* perm, int32_t* parent,
                       unsigned long long* comp_best, uint32_t* comp_hi, int2* comp_edge,
-                      float* best_w, int32_t* best_j, int32_t* seed, uint32_t* count,
+                      float* best_w, int32_t* best_j, int32_t* seed, float* lb, uint32_t* count,
                       uint32_t* out_lo, uint32_t* out_hi, float* out_w, uint32_t* err,
                       hipStream_t s) {
   if (n < 2) return;
+  hipLaunchKernelGGL(k_mst_seed, grid_of(n), dim3(256), 0, s, n, leaf, rec, seed, run, ends,
+                     comp_best);
   hipLaunchKernelGGL(k_mst_walk, dim3(walk_grid(n, 256)), dim3(256), 0, s, nodes, leaf, rec, run,
-                     ends, n, walk_cfg(n), root, comp_best, best_w, best_j, seed, err);
+                     ends, n, walk_cfg(n), root, comp_best, best_w, best_j, seed, lb, err);
   hipLaunchKernelGGL(k_mst_hi, grid_of(n), dim3(256), 0, s, n, rec, best_w, best_j, comp_best,
                      comp_hi);
   hipLaunchKernelGGL(k_mst_pick, grid_of(n), dim3(256), 0, s, n, rec, best_w, best_j, comp_best,

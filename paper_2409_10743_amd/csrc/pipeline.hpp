@@ -184,7 +184,7 @@ struct alignas(16) MstRec {
 };
 // every point its own component; no minima, no seeds
 void launch_mst_init(uint32_t n, int32_t* comp, unsigned long long* comp_best, uint32_t* comp_hi,
-                     int32_t* seed, int2* comp_edge, hipStream_t s);
+                     int32_t* seed, float* lb, int2* comp_edge, hipStream_t s);
 // runs of equal components: run[i] = number of runs ending before i, ends[r]
 // = last position of run r (scan state zeroed; *total = the number of runs)
 void launch_mst_runs(uint32_t n, const int32_t* comp, uint32_t* flag, uint32_t* run,
@@ -200,7 +200,7 @@ void launch_mst_round(const Node* nodes, const float4* leaf, const MstRec* rec,
                       const uint32_t* run, const uint32_t* ends, uint32_t n,
                       const int32_t* root, const uint32_t* perm, int32_t* parent,
                       unsigned long long* comp_best, uint32_t* comp_hi, int2* comp_edge,
-                      float* best_w, int32_t* best_j, int32_t* seed, uint32_t* count,
+                      float* best_w, int32_t* best_j, int32_t* seed, float* lb, uint32_t* count,
                       uint32_t* out_lo, uint32_t* out_hi, float* out_w, uint32_t* err,
                       hipStream_t s);
 // components = union-find roots; the round's minima cleared
