@@ -309,16 +309,19 @@ int build_index(dbscan_ctx* c, const float* pts, uint32_t n, bool need_bestcore,
   SortMarks sm{c, s};
   launch_radix_sort_dropped(ka, kb, va, vb, n, drop, sc, s, timing ? sort_mark : nullptr, &sm,
                             c->sort_items);
-  uint64_t* keys = ka;  // where that sort always ends
+  // the sort moved 32-bit halves of the codes and leaves none: the build's
+  // first level recomputes the codes into ka (where the sort ended)
+  uint64_t* keys = ka;
   uint32_t* perm = va;
   // the other key buffer is free now: the build's scratch
   int32_t* other = reinterpret_cast<int32_t*>(kb);
   // the build's first level gathers the leaves and sets up the union-find
-  launch_build(keys, 64, pts, perm, at<float4>(c, L.leaf), at<int32_t>(c, L.parent),
-               need_bestcore ? at<int32_t>(c, L.minlab) : nullptr, at<uint8_t>(c, L.flag),
-               need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr, labels, deg, n,
-               at<Node>(c, L.nodes), other, at<int32_t>(c, L.root), at<int4>(c, L.pending),
-               status, s, timing ? build_mark : nullptr, &sm);
+  launch_build_coded(keys, bounds, drop, pts, perm, at<float4>(c, L.leaf),
+                     at<int32_t>(c, L.parent), need_bestcore ? at<int32_t>(c, L.minlab) : nullptr,
+                     at<uint8_t>(c, L.flag),
+                     need_bestcore ? at<unsigned long long>(c, L.bestcore) : nullptr, labels, deg,
+                     n, at<Node>(c, L.nodes), other, at<int32_t>(c, L.root),
+                     at<int4>(c, L.pending), status, s, timing ? build_mark : nullptr, &sm);
   mark(c, timing, PH_BUILD_LEVELS, s);
   out->keys = keys;
   out->bounds = bounds;

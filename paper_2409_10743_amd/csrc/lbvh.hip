@@ -55,6 +55,7 @@
 // and the node spanning exactly a set is recorded as that set's root.  With
 // no set bits (set_shift = 64) the only such node is the root.
 #include <algorithm>
+#include <type_traits>
 
 #include "pipeline.hpp"
 
@@ -104,6 +105,22 @@ struct GatherLeaves {
       leaf[n] = make_float4(0.f, 0.f, 0.f, __int_as_float(SENTINEL));
   }
 };
+// The clustering call's level-1 frames: as GatherLeaves, and each leaf's
+// Morton code is computed here from its point with the grid and dropped
+// bits the Morton kernel used (the same function of the same floats, so
+// the same code): that call's sort moves 32-bit halves of the codes and
+// does not write them.  The frame takes its deltas from these codes and
+// writes them to `keys_out` for the upper levels and the walks' early end.
+struct GatherCoded : GatherLeaves {
+  const uint32_t* bounds;  // scene bounds words
+  const uint32_t* drop;    // low code bits cleared
+  uint64_t* keys_out;
+};
+template <class L>
+struct codes_here : std::false_type {};
+template <>
+struct codes_here<GatherCoded> : std::true_type {};
+
 struct BoxLeaves {
   static constexpr bool kPoint = false;
   Node* prim;
@@ -133,9 +150,11 @@ __device__ __forceinline__ uint32_t set_of(const uint64_t* __restrict__ keys, in
   return set_shift < 64 ? uint32_t(keys[l] >> set_shift) : 0u;
 }
 
-__device__ __forceinline__ uint64_t delta(const uint64_t* __restrict__ keys, int32_t i) {
-  uint64_t a = keys[i], b = keys[i + 1];
+__device__ __forceinline__ uint64_t delta_of(uint64_t a, uint64_t b, int32_t i) {
   return a == b ? uint64_t(uint32_t(i) ^ uint32_t(i + 1)) : ((a ^ b) + (1ull << 32));
+}
+__device__ __forceinline__ uint64_t delta(const uint64_t* __restrict__ keys, int32_t i) {
+  return delta_of(keys[i], keys[i + 1], i);
 }
 
 // Is [l, r] the left child of its parent (split at r) rather than the right
@@ -199,13 +218,45 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
   const int32_t f1 = min(f0 + BUILD_LEAVES, int32_t(n));
   const int32_t m = f1 - f0;
   const uint64_t mask = set_mask_of(set_shift);
-  for (int32_t j = t; j <= m + 1; j += BUILD_BLOCK) {
-    const int32_t b = f0 - 1 + j;
-    const bool ok = b >= 0 && b < last;
-    s_delta[j] = ok ? delta(keys, b) : 0ull;
-    s_cut[j] = ok ? set_cut(keys, b, mask) : 1;
+  if constexpr (codes_here<Leaves>::value) {
+    // codes of leaves f0-1 .. f1+1 (at j = 0 .. m+2) from their points;
+    // no set bits here
+    __shared__ uint64_t s_code[BUILD_LEAVES + 3];
+    MortonGrid grid;
+    grid.load(lv.bounds);
+    const uint64_t cmask = ~0ull << *lv.drop;
+    if (t < m) {
+      lv.load(f0 + t, s_leaf[t], s_leafhi[t]);
+      const uint64_t c = grid.code(s_leaf[t].x, s_leaf[t].y, s_leaf[t].z) & cmask;
+      s_code[t + 1] = c;
+      lv.keys_out[f0 + t] = c;
+    }
+    if (t < 3) {  // leaves f0-1, f1 and f1+1, where they exist
+      const int32_t b = t == 0 ? f0 - 1 : f1 - 1 + t;
+      uint64_t c = 0;
+      if (b >= 0 && b <= last) {
+        float4 a, h;
+        lv.load(b, a, h);
+        c = grid.code(a.x, a.y, a.z) & cmask;
+      }
+      s_code[t == 0 ? 0 : m + t] = c;
+    }
+    __syncthreads();
+    for (int32_t j = t; j <= m + 1; j += BUILD_BLOCK) {
+      const int32_t b = f0 - 1 + j;
+      const bool ok = b >= 0 && b < last;
+      s_delta[j] = ok ? delta_of(s_code[j], s_code[j + 1], b) : 0ull;
+      s_cut[j] = ok ? 0 : 1;
+    }
+  } else {
+    for (int32_t j = t; j <= m + 1; j += BUILD_BLOCK) {
+      const int32_t b = f0 - 1 + j;
+      const bool ok = b >= 0 && b < last;
+      s_delta[j] = ok ? delta(keys, b) : 0ull;
+      s_cut[j] = ok ? set_cut(keys, b, mask) : 1;
+    }
+    if (t < m) lv.load(f0 + t, s_leaf[t], s_leafhi[t]);
   }
-  if (t < m) lv.load(f0 + t, s_leaf[t], s_leafhi[t]);
   s_other[t] = -1;
   s_end[t] = -1;
   __syncthreads();
@@ -286,9 +337,6 @@ struct Ends {
   bool cl, cr;
 };
 
-__device__ __forceinline__ uint64_t delta_of(uint64_t a, uint64_t b, int32_t i) {
-  return a == b ? uint64_t(uint32_t(i) ^ uint32_t(i + 1)) : ((a ^ b) + (1ull << 32));
-}
 // the left end becomes l (keys l - 1, l)
 __device__ __forceinline__ void set_left(Ends& E, const uint64_t* __restrict__ keys, int32_t l,
                                          uint64_t mask) {
@@ -549,6 +597,22 @@ void launch_build(const uint64_t* keys, int set_shift, const float* pts, const u
              GatherLeaves{pts, perm, n, leaf, parent, minlab, flag, bestcore, labels, deg},
              PointLeaves{leaf}, n, nullptr, nodes, other, set_root, pending, err, s, after_level,
              arg);
+}
+
+void launch_build_coded(uint64_t* keys, const uint32_t* bounds, const uint32_t* drop,
+                        const float* pts, const uint32_t* perm, float4* leaf, int32_t* parent,
+                        int32_t* minlab, uint8_t* flag, unsigned long long* bestcore,
+                        int32_t* labels, uint32_t* deg, uint32_t n, Node* nodes, int32_t* other,
+                        int32_t* root, int4* pending, uint32_t* err, hipStream_t s,
+                        void (*after_level)(void*, int), void* arg) {
+  GatherCoded g;
+  static_cast<GatherLeaves&>(g) =
+      GatherLeaves{pts, perm, n, leaf, parent, minlab, flag, bestcore, labels, deg};
+  g.bounds = bounds;
+  g.drop = drop;
+  g.keys_out = keys;
+  build_impl(keys, 64, g, PointLeaves{leaf}, n, nullptr, nodes, other, root, pending, err, s,
+             after_level, arg);
 }
 
 void launch_build_boxes(const uint64_t* keys, int set_shift, Node* prims, uint32_t n_bound,

@@ -138,7 +138,11 @@ __device__ __forceinline__ void count_digits(uint32_t* sh, uint64_t code, int fi
 // (all blocks compute the same value; block 0 also stores it for the sort
 // and the walks).  The sort then skips drop / 8 passes and always ends in
 // the first key buffer, so the codes go to the first buffer if it skips an
-// even number of passes, else to the second.
+// even number of passes, else to the second.  With `drop_out` (the
+// clustering call's sort, which moves 32-bit words) a code is written as
+// its two halves, the low one to 32-bit word i of that buffer and the high
+// one to word n + i, or, when the low half is all dropped, the high half
+// alone to word i.
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, uint32_t n,
                                                const uint32_t* __restrict__ bounds, float eps,
@@ -155,6 +159,22 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
   const int first = drop / 8;  // first sort pass that runs
   uint64_t* keys = (first % 2 == 0) ? keys_a : keys_b;
   if (blockIdx.x == 0 && threadIdx.x == 0 && drop_out) *drop_out = uint32_t(drop);
+  // 32-bit words for the clustering call's sort: lo[i] and hi[i] (hi = lo + n),
+  // or the high half alone in lo[i] once the low half is dropped
+  const bool split = drop_out != nullptr;
+  const bool halves = split && first < 4;
+  uint32_t* lo32 = reinterpret_cast<uint32_t*>(keys);
+  uint32_t* hi32 = lo32 + n;
+  auto put = [&](uint32_t i, uint64_t c) {
+    if (!split) {
+      keys[i] = c;
+    } else if (halves) {
+      lo32[i] = uint32_t(c);
+      hi32[i] = uint32_t(c >> 32);
+    } else {
+      lo32[i] = uint32_t(c >> 32);
+    }
+  };
   __syncthreads();
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -168,8 +188,16 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
       const uint64_t c1 = grid.code(a.w, b.x, b.y) & mask;
       const uint64_t c2 = grid.code(b.z, b.w, c.x) & mask;
       const uint64_t c3 = grid.code(c.y, c.z, c.w) & mask;
-      k2[2 * size_t(g)] = make_ulonglong2(c0, c1);
-      k2[2 * size_t(g) + 1] = make_ulonglong2(c2, c3);
+      if (!split) {
+        k2[2 * size_t(g)] = make_ulonglong2(c0, c1);
+        k2[2 * size_t(g) + 1] = make_ulonglong2(c2, c3);
+      } else if (halves) {  // 4-aligned word groups: n may be odd, so no 16-byte stores at n + i
+        put(4 * g, c0); put(4 * g + 1, c1); put(4 * g + 2, c2); put(4 * g + 3, c3);
+      } else {
+        reinterpret_cast<uint4*>(lo32)[g] =
+            make_uint4(uint32_t(c0 >> 32), uint32_t(c1 >> 32), uint32_t(c2 >> 32),
+                       uint32_t(c3 >> 32));
+      }
       count_digits(sh, c0, first);
       count_digits(sh, c1, first);
       count_digits(sh, c2, first);
@@ -193,7 +221,7 @@ __global__ __launch_bounds__(256) void k_morton(const float* __restrict__ pts, u
   for (uint32_t i = first_scalar + gid; i < n; i += stride) {
     const float* p = pts + size_t(3) * i;
     const uint64_t code = grid.code(p[0], p[1], p[2]) & mask;
-    keys[i] = code;
+    put(i, code);
     count_digits(sh, code, first);
   }
   __syncthreads();

@@ -121,6 +121,16 @@ void launch_build(const uint64_t* keys, int set_shift, const float* pts, const u
                   Node* nodes, int32_t* other,
                   int32_t* set_root, int4* pending, uint32_t* err, hipStream_t s,
                   void (*after_level)(void*, int) = nullptr, void* arg = nullptr);
+// The clustering call's build: as launch_build without set bits, with each
+// leaf's Morton code recomputed from its point (grid from `bounds`, the low
+// *drop bits cleared, as the Morton kernel made them) and written to `keys`
+// by the first level; the sort before it moved 32-bit halves of the codes.
+void launch_build_coded(uint64_t* keys, const uint32_t* bounds, const uint32_t* drop,
+                        const float* pts, const uint32_t* perm, float4* leaf, int32_t* parent,
+                        int32_t* minlab, uint8_t* flag, unsigned long long* bestcore,
+                        int32_t* labels, uint32_t* deg, uint32_t n, Node* nodes, int32_t* other,
+                        int32_t* root, int4* pending, uint32_t* err, hipStream_t s,
+                        void (*after_level)(void*, int) = nullptr, void* arg = nullptr);
 // The same over box leaves (DenseBox primitives: Node records, payload in
 // `left`, rope in `rope`); sets as in launch_build.  The primitive count is
 // read from *n_dev (at most n_bound, which sizes the launches), so no host

@@ -2,6 +2,14 @@
 // of section 4.2.2 (64-bit codes make the sort "slightly" slower than 32-bit
 // ones; here it is 8 passes of 8-bit digits over 63 used bits).
 //
+// The clustering call's sort moves 32-bit key words instead: the passes
+// over the low half of the codes carry the high half as a second 32-bit
+// word beside the value, the last of them keeps only the high half, and
+// the passes over the high half move it alone (8 instead of 12 bytes per
+// element and pass, and 36 instead of 53 KB of LDS per block: four blocks
+// per CU instead of three).  The sorted codes themselves are not written:
+// the build's first level recomputes each leaf's code from its point.
+//
 // One kernel per digit pass ("onesweep"): every workgroup takes the next
 // tile id from an atomic counter, ranks its 4096 keys by digit in LDS,
 // publishes its per-digit counts, and finds the counts of all earlier tiles
@@ -12,6 +20,7 @@
 // so the global writes go out as runs of consecutive addresses.
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #include "pipeline.hpp"
 
@@ -63,15 +72,25 @@ __global__ __launch_bounds__(256) void k_digit_hist(const uint64_t* __restrict__
 // keys cleared: a pass below it returns at once, and the passes that run
 // alternate between the two buffer pairs so that the last ends in (ka, va):
 // the codes start in ka if an even number of passes is skipped, else in kb.
-template <bool IOTA, int ITEMS>
+//
+// KIN is the key word the pass reads (the whole u64 code, or a 32-bit half
+// of it); `shift` is the digit's position in that word and `pass` the
+// digit's number in the 64-bit code.  PAY: a second 32-bit word travels
+// with each key (u32 words n..2n-1 of the key buffers: the high half while
+// the low half is sorted).  NARROW: the pass writes that word as the
+// output key and no second word (the last pass over the low half).
+template <bool IOTA, int ITEMS, class KIN, bool PAY, bool NARROW>
 __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
-    uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb, uint32_t n, int shift,
+    uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb, uint32_t n, int shift, int pass_no,
     const uint32_t* __restrict__ drop, const uint32_t* __restrict__ ghist,
     uint32_t* __restrict__ status, uint32_t* __restrict__ next_status,
     uint32_t* __restrict__ tile_ctr, uint32_t* __restrict__ err) {
+  static_assert(!NARROW || PAY, "a narrowing pass writes the carried word");
+  using KOUT = typename std::conditional<NARROW, uint32_t, KIN>::type;
   constexpr int TILE = SORT_THREADS * ITEMS;
-  __shared__ uint64_t s_keys[TILE];           // keys and values in digit order
+  __shared__ KIN s_keys[TILE];                // keys and values in digit order
   __shared__ uint32_t s_vals[TILE];
+  __shared__ uint32_t s_pay[PAY ? TILE : 1];  // the carried words, likewise
   // per-wave digit counts, then each wave's first slot per digit in the
   // tile; after staging, row 0 holds the global offset minus the tile offset
   __shared__ uint32_t s_whist[WAVES][RADIX];
@@ -82,23 +101,27 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
   // one tile's row of them (the grid has one workgroup per tile), also in a
   // pass that returns at once below
   if (next_status) next_status[size_t(blockIdx.x) * RADIX + threadIdx.x] = 0u;
-  const uint64_t* kin = ka;  // without `drop`: (ka, va) -> (kb, vb)
-  uint64_t* kout = kb;
+  uint64_t* bin = ka;  // without `drop`: (ka, va) -> (kb, vb)
+  uint64_t* bout = kb;
   const uint32_t* vin = va;
   uint32_t* vout = vb;
   bool iota = IOTA;
   if (drop) {
-    const int skip = int(*drop) / 8, pass = shift / 8;
-    if (pass < skip) return;
-    const bool from_a = ((pass - skip) % 2 == 0) == (skip % 2 == 0);
+    const int skip = int(*drop) / 8;
+    if (pass_no < skip) return;
+    const bool from_a = ((pass_no - skip) % 2 == 0) == (skip % 2 == 0);
     if (!from_a) {
-      kin = kb;
-      kout = ka;
+      bin = kb;
+      bout = ka;
       vin = vb;
       vout = va;
     }
-    iota = pass == skip;
+    iota = pass_no == skip;
   }
+  const KIN* kin = reinterpret_cast<const KIN*>(bin);
+  KOUT* kout = reinterpret_cast<KOUT*>(bout);
+  const uint32_t* pin = reinterpret_cast<const uint32_t*>(bin) + n;
+  uint32_t* pout = reinterpret_cast<uint32_t*>(bout) + n;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t gcount = ghist[tid];  // this pass's count of digit tid
@@ -111,24 +134,27 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
   const uint32_t tile_base = tile * TILE;
   const uint32_t wbase = tile_base + wave * (64 * ITEMS);
 
-  uint64_t key[ITEMS];
+  KIN key[ITEMS];
   uint32_t val[ITEMS];  // loaded with the keys, early: its latency hides behind the ranking
+  uint32_t pay[ITEMS];
   uint32_t rank[ITEMS];
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     uint32_t idx = wbase + k * 64 + lane;
-    key[k] = idx < n ? kin[idx] : ~0ull;
+    key[k] = idx < n ? kin[idx] : KIN(~KIN(0));
     val[k] = iota ? idx : (idx < n ? vin[idx] : 0u);
+    pay[k] = PAY && idx < n ? pin[idx] : 0u;
   }
   if (trivial) {  // all loads above are in flight: write them back where they were
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const uint32_t idx = wbase + k * 64 + lane;
       if (idx < n) {
-        kout[idx] = key[k];
+        kout[idx] = NARROW ? KOUT(pay[k]) : KOUT(key[k]);
         vout[idx] = val[k];
+        if (PAY && !NARROW) pout[idx] = pay[k];
       }
     }
     return;
@@ -218,21 +244,23 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
       const uint32_t p = s_whist[wave][dd] + rank[k];
       s_keys[p] = key[k];
       s_vals[p] = val[k];
+      if (PAY) s_pay[p] = pay[k];
     }
   }
   __syncthreads();
   // the per-wave slots are no longer needed: row 0 now holds the offsets
-  // (keeps LDS at 53 KB, three blocks per CU)
+  // (keeps LDS at 53 KB for 64-bit keys, three blocks per CU)
   s_whist[0][d] = gstart + excl - loff;
   __syncthreads();
   const uint32_t* s_base = s_whist[0];
   const uint32_t tile_n = min(uint32_t(TILE), n - tile_base);
   for (uint32_t p = tid; p < tile_n; p += SORT_THREADS) {
-    const uint64_t kk = s_keys[p];
+    const KIN kk = s_keys[p];
     const uint32_t dst = s_base[uint32_t(kk >> shift) & 0xff] + p;
     if (dst < n) {  // always true unless a look-back wait was cut short
-      kout[dst] = kk;
+      kout[dst] = NARROW ? KOUT(s_pay[p]) : KOUT(kk);
       vout[dst] = s_vals[p];
+      if (PAY && !NARROW) pout[dst] = s_pay[p];
     }
   }
 }
@@ -248,12 +276,36 @@ void launch_digit_histogram(const uint64_t* keys, uint32_t n, uint32_t* hist,
 
 
 namespace {
+// The word layouts a pass can move (see k_onesweep): whole 64-bit codes;
+// the low half with the high half carried (LO), the last such pass (LO_LAST,
+// which keeps only the high half); the high half alone (HI).
+enum PassWords { WIDE = 0, LO = 1, LO_LAST = 2, HI = 3 };
+
+template <bool IOTA, int ITEMS>
+void launch_pass(int words, dim3 grid, uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
+                 uint32_t n, int p, const uint32_t* drop, const uint32_t* ghist, uint32_t* st,
+                 uint32_t* next, uint32_t* ctr, uint32_t* err, hipStream_t s) {
+  const dim3 block(SORT_THREADS);
+  if (words == LO)
+    hipLaunchKernelGGL((k_onesweep<IOTA, ITEMS, uint32_t, true, false>), grid, block, 0, s, ka,
+                       kb, va, vb, n, 8 * p, p, drop, ghist, st, next, ctr, err);
+  else if (words == LO_LAST)
+    hipLaunchKernelGGL((k_onesweep<IOTA, ITEMS, uint32_t, true, true>), grid, block, 0, s, ka,
+                       kb, va, vb, n, 8 * p, p, drop, ghist, st, next, ctr, err);
+  else if (words == HI)
+    hipLaunchKernelGGL((k_onesweep<IOTA, ITEMS, uint32_t, false, false>), grid, block, 0, s, ka,
+                       kb, va, vb, n, 8 * p - 32, p, drop, ghist, st, next, ctr, err);
+  else
+    hipLaunchKernelGGL((k_onesweep<IOTA, ITEMS, uint64_t, false, false>), grid, block, 0, s, ka,
+                       kb, va, vb, n, 8 * p, p, drop, ghist, st, next, ctr, err);
+}
+
 // one pass from (kin, vin) to (kout, vout); with `drop`, the kernel picks
 // the direction itself (see k_onesweep)
 // st: this pass's look-back words (zero); the next pass's, if any, follow
 // them and are cleared here
 template <int ITEMS>
-void sort_pass(bool iota, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
+void sort_pass(bool iota, int words, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
                uint32_t* vout, uint32_t n, int p, const uint32_t* drop, const SortScratch& sc,
                uint32_t* st, hipStream_t s) {
   uint32_t* next = p + 1 < SORT_PASSES ? st + size_t(sort_tiles(n, ITEMS)) * RADIX : nullptr;
@@ -261,13 +313,11 @@ void sort_pass(bool iota, const uint64_t* kin, uint64_t* kout, const uint32_t* v
   uint64_t* ka = const_cast<uint64_t*>(kin);  // read-only in this direction
   uint32_t* va = const_cast<uint32_t*>(vin);
   if (iota)
-    hipLaunchKernelGGL((k_onesweep<true, ITEMS>), dim3(tiles), dim3(SORT_THREADS), 0, s, ka,
-                       kout, va, vout, n, 8 * p, drop, sc.hist + p * RADIX, st, next,
-                       sc.tile_ctr + p, sc.err);
+    launch_pass<true, ITEMS>(words, dim3(tiles), ka, kout, va, vout, n, p, drop,
+                             sc.hist + p * RADIX, st, next, sc.tile_ctr + p, sc.err, s);
   else
-    hipLaunchKernelGGL((k_onesweep<false, ITEMS>), dim3(tiles), dim3(SORT_THREADS), 0, s, ka,
-                       kout, va, vout, n, 8 * p, drop, sc.hist + p * RADIX, st, next,
-                       sc.tile_ctr + p, sc.err);
+    launch_pass<false, ITEMS>(words, dim3(tiles), ka, kout, va, vout, n, p, drop,
+                              sc.hist + p * RADIX, st, next, sc.tile_ctr + p, sc.err, s);
 }
 
 }  // namespace
@@ -287,9 +337,9 @@ bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
     uint32_t* vout = in_a ? vb : va;
     uint32_t* st = sc.status + size_t(p - first_pass) * words;  // the first pass's: zeroed
     const bool iota = p == first_pass && iota_vals;
-    if (items == 8) sort_pass<8>(iota, kin, kout, vin, vout, n, p, nullptr, sc, st, s);
-    else if (items == 12) sort_pass<12>(iota, kin, kout, vin, vout, n, p, nullptr, sc, st, s);
-    else sort_pass<16>(iota, kin, kout, vin, vout, n, p, nullptr, sc, st, s);
+    if (items == 8) sort_pass<8>(iota, WIDE, kin, kout, vin, vout, n, p, nullptr, sc, st, s);
+    else if (items == 12) sort_pass<12>(iota, WIDE, kin, kout, vin, vout, n, p, nullptr, sc, st, s);
+    else sort_pass<16>(iota, WIDE, kin, kout, vin, vout, n, p, nullptr, sc, st, s);
     if (after_pass) after_pass(arg, p);
     in_a = !in_a;
   }
@@ -305,9 +355,10 @@ void launch_radix_sort_dropped(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_
   const uint32_t words = sort_tiles(n, items) * RADIX;
   for (int p = 0; p < SORT_PASSES; ++p) {
     uint32_t* st = sc.status + size_t(p) * words;
-    if (items == 8) sort_pass<8>(false, ka, kb, va, vb, n, p, drop, sc, st, s);
-    else if (items == 12) sort_pass<12>(false, ka, kb, va, vb, n, p, drop, sc, st, s);
-    else sort_pass<16>(false, ka, kb, va, vb, n, p, drop, sc, st, s);
+    const int w = p < 3 ? LO : p == 3 ? LO_LAST : HI;
+    if (items == 8) sort_pass<8>(false, w, ka, kb, va, vb, n, p, drop, sc, st, s);
+    else if (items == 12) sort_pass<12>(false, w, ka, kb, va, vb, n, p, drop, sc, st, s);
+    else sort_pass<16>(false, w, ka, kb, va, vb, n, p, drop, sc, st, s);
     if (after_pass) after_pass(arg, p);
   }
 }
