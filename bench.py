@@ -53,8 +53,10 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 BYTES_PER_POINT = {
     "prep": 0.0,
     "bounds": 12.0,                 # read xyz
-    "morton": 12.0 + 8.0,           # read xyz, write code
-    "sort": 24.0,                   # per pass: read code+index, write code+index
+    "morton": 12.0 + 4.0,           # read xyz, write the code's high half (the halves
+                                    # when more than 32 code bits are kept: sort_bytes)
+    "sort": 16.0,                   # per pass over the code's high half: read and
+                                    # write a 32-bit code word and the index
     "gather": 4 + 12 + 16 + 4 + 4 + 1,  # DenseBox: read index, xyz; write point,
                                         # parent, minlab, flag
     "build_frame": 4 + 12 + 8 + 16 + 32 + 4 + 4 + 1 + 4,  # index, xyz (gathered), codes;
@@ -68,8 +70,26 @@ BYTES_PER_POINT = {
     "final_labels": 1.0,            # member flag; + parent, perm, label for clustered
                                     # points only (labels start at -1 from the build)
 }
-# the first sort pass reads no values (they are the identity)
-FIRST_SORT_PASS_BYTES = 20.0
+
+
+def sort_bytes(passes: int) -> float:
+    """Algorithmic bytes per point of the clustering call's sort with
+    `passes` working 8-bit passes (the last ones of 8): a pass over the low
+    half of the codes moves a 32-bit code word, the high half and the index
+    (24 bytes read and written), the last of them drops the low word (20),
+    a pass over the high half moves the high word and the index (16); the
+    first pass that runs reads no index (they are the identity)."""
+    total = 0.0
+    for p in range(8 - passes, 8):
+        b = 24.0 if p < 3 else 20.0 if p == 3 else 16.0
+        total += b - (4.0 if p == 8 - passes else 0.0)
+    return total
+
+
+def morton_bytes(passes: int) -> float:
+    """Read xyz, write the code: both 32-bit halves when the sort runs
+    passes over the low half, else the high half alone."""
+    return 12.0 + (8.0 if passes > 4 else 4.0)
 
 KERNEL_OF_PHASE = {f"sort{p}": "sort" for p in range(8)}
 KERNEL_NAME = {  # device function names, as rocprofv3 reports them
@@ -163,6 +183,7 @@ def _short(name: str) -> str:
         name = name[5:]
     for ns in ("dbx::(anonymous namespace)::", "dbx::"):
         name = name.replace(ns, "")
+    name = name.replace("unsigned long", "u64").replace("unsigned int", "u32")
     depth, cut = 0, len(name)
     for k, ch in enumerate(name):
         if ch == "<":
@@ -204,9 +225,9 @@ def summarize_trace(d: str, workload: str, cmd: str, bench_line: str, out_path: 
     lines = [f"# rocprofv3 kernel statistics, {workload}, one MI355X",
              f"# command: {cmd}",
              f"# bench line of the same build: {bench_line}",
-             f"{'kernel':<36}{'calls':>7}{'avg_us':>11}{'total_ms':>11}{'pct':>8}"]
+             f"{'kernel':<44}{'calls':>7}{'avg_us':>11}{'total_ms':>11}{'pct':>8}"]
     for name, calls, avg, tot, pct in rows[:16]:
-        lines.append(f"{name[:35]:<36}{calls:>7}{avg:>11.2f}{tot:>11.3f}{pct:>8.2f}")
+        lines.append(f"{name[:43]:<44}{calls:>7}{avg:>11.2f}{tot:>11.3f}{pct:>8.2f}")
     dur = _kernel_durations(d)
     for name in sorted(dur, key=lambda k: -sum(dur[k]))[:6]:
         w = _did_work(dur[name])
@@ -249,7 +270,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, copy_fetch: str, copy_write: s
             f"written = WRITE_SIZE KiB * 1024 * {w_scale:.4f}",
             "# per launch: averaged over the launches that did work (a skipped sort pass "
             "returns at once)"]
-    table = [f"{'kernel':<36}{'launches':>9}{'fetch_KiB':>13}{'write_KiB':>13}{'hbm_MB':>10}"
+    table = [f"{'kernel':<44}{'launches':>9}{'fetch_KiB':>13}{'write_KiB':>13}{'hbm_MB':>10}"
              f"{'B/point':>9}"]
     per = {}
     for name in sorted(fetch, key=lambda k: -sum(fetch[k])):
@@ -258,7 +279,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, copy_fetch: str, copy_write: s
         fk, wk = sum(fw) / len(fw), sum(ww) / len(ww)
         b = fk * 1024 * f_scale + wk * 1024 * w_scale
         per[name] = (len(fw), fk, wk, b)
-        table.append(f"{name[:35]:<36}{len(fw):>9}{fk:>13.1f}{wk:>13.1f}{b / 1e6:>10.1f}"
+        table.append(f"{name[:43]:<44}{len(fw):>9}{fk:>13.1f}{wk:>13.1f}{b / 1e6:>10.1f}"
                      f"{b / n:>9.1f}")
     open(os.path.join(out_dir, f"hbm_traffic_{workload}.txt"), "w").write(
         "\n".join(head + table) + "\n")
@@ -561,7 +582,9 @@ def roofline(phases, passes, n, workload):
     dom = max(per_kernel, key=per_kernel.get)
     launch_ms = per_kernel[dom] / max(1, launches.get(dom, 1))
     if dom == "sort":
-        bytes_launch = n * (FIRST_SORT_PASS_BYTES + (passes - 1) * BYTES_PER_POINT["sort"]) / passes
+        bytes_launch = n * sort_bytes(passes) / passes
+    elif dom == "morton":
+        bytes_launch = n * morton_bytes(passes)
     else:
         bytes_launch = n * BYTES_PER_POINT[dom]
     achieved = bytes_launch / (launch_ms / 1000.0) / 1e9
