@@ -62,8 +62,9 @@ extern "C" {
  * read-back, kept for later calls on the same points, sizes, eps and minPts)
  * estimates the mean number of eps-neighbours per point; DenseBox when it is
  * at least 4 times minPts (point-weighted over sets), FDBSCAN otherwise;
- * a plain FDBSCAN call with min_pts > 2 also finds its core points by pair
- * traversal (DBSCAN_FLAG_PAIR_COUNT) when the mean is below min_pts.
+ * with min_pts > 2 the core points come from the pair traversal
+ * (DBSCAN_FLAG_PAIR_COUNT) with DenseBox, and with plain FDBSCAN when the
+ * mean is below min_pts.
  * Labels do not depend on the pick. */
 #define DBSCAN_ALGO_AUTO 0
 #define DBSCAN_ALGO_FDBSCAN 1   /* section 4.3.3 */
@@ -78,12 +79,14 @@ extern "C" {
  * (DenseBox keeps its primitive count on the device).  Ignored when the
  * stream argument is NULL; no timing in this mode. */
 #define DBSCAN_FLAG_GRAPH 2u
-/* Plain FDBSCAN with min_pts > 2: find the core points by pair traversal
- * (every pair adds one to both points' neighbour counts; section 4.2.3
- * applied to counting) instead of a walk per point from the root that stops
- * at min_pts (section 4.1.2).  Faster where points have few neighbours (no
- * walk from the root), slower in dense regions (no early exit); labels are
- * the same.  The autotuner tries both.  Ignored otherwise. */
+/* With min_pts > 2 (plain FDBSCAN, and DenseBox plain or batched): find
+ * the core points by pair traversal (every pair adds one to both points'
+ * neighbour counts; section 4.2.3 applied to counting; with DenseBox a point
+ * and a dense cell add the cell's points within eps to the point) instead
+ * of a walk per point from the root (of its set) that stops at min_pts
+ * (section 4.1.2).  Faster where points have few neighbours (no walk from
+ * the root), slower in dense regions (no early exit); labels are the same.
+ * The autotuners try both.  Ignored otherwise (batched FDBSCAN). */
 #define DBSCAN_FLAG_PAIR_COUNT 4u
 
 typedef struct dbscan_options {
@@ -198,7 +201,8 @@ int dbscan_sort_passes(const dbscan_ctx* ctx);
  * DBSCAN_FLAG_PAIR_COUNT (returned in best->flags).  The batched tuner tries
  * both algorithms: FDBSCAN at each workgroup size, and DenseBox at each
  * workgroup size with thresholds 0 (each set's minPts), 2 and 4 times the
- * largest minPts. */
+ * largest minPts.  A DenseBox pick with min_pts > 2 (the largest, for a
+ * batch) is then timed again with DBSCAN_FLAG_PAIR_COUNT toggled. */
 int dbscan_autotune(dbscan_ctx* ctx, const float* points, int64_t n, float eps,
                     int32_t min_pts, int32_t algorithm, int32_t* labels,
                     dbscan_options* best, float* best_ms, void* stream);

@@ -254,12 +254,15 @@ class Context:
 
     def cluster_batched(self, points, offsets, eps, min_pts, block_size: int = 0,
                         timing: bool = False, out=None, graph: bool = False,
-                        algorithm: str = "auto", dense_threshold: int = 0, sort_tile: int = 0):
+                        algorithm: str = "auto", dense_threshold: int = 0, sort_tile: int = 0,
+                        pair_count: bool = False):
         """Cluster the sets points[offsets[k]:offsets[k+1]] independently in
         one pass; ``eps`` and ``min_pts`` are scalars or one value per set.
         Labels are set-local (-1 noise, else the smallest index within the
         set of the point's cluster).  ``algorithm``: "auto"/"fdbscan" or
-        "densebox" (``dense_threshold`` 0 = each set's min_pts)."""
+        "densebox" (``dense_threshold`` 0 = each set's min_pts).
+        ``pair_count``: DenseBox core points by pair traversal
+        (DBSCAN_FLAG_PAIR_COUNT)."""
         import numpy as np
         p = _points(points)
         off = _offsets(offsets, p.shape[0])
@@ -271,8 +274,8 @@ class Context:
                                  dtype=np.int32)
         labels = _labels_out(out, p.shape[0], p.device)
         o = _Options(ALGO[algorithm], int(dense_threshold), int(block_size),
-                     (FLAG_TIMING if timing else 0) | (FLAG_GRAPH if graph else 0),
-                     int(sort_tile))
+                     (FLAG_TIMING if timing else 0) | (FLAG_GRAPH if graph else 0) |
+                     (FLAG_PAIR_COUNT if pair_count else 0), int(sort_tile))
         _check(load_library().dbscan_cluster_batched(
             self.handle, ctypes.c_void_p(p.data_ptr()),
             off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), k,

@@ -471,9 +471,12 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
 // Nothing is read back: the call can be captured as a graph.
 // d_off: the sets' offsets (batched calls; labels set-local), else null
 // and min_pts is the plain call's.
+// pair_count: core flags by pair traversal (DBSCAN_FLAG_PAIR_COUNT) instead
+// of the counting walk from each set's root.
 int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_t n,
                        DbSets S, bool any_core, const int64_t* d_off, int32_t min_pts,
-                       int32_t* labels, int block, bool timing, hipStream_t s) {
+                       int32_t* labels, int block, bool timing, hipStream_t s,
+                       bool pair_count) {
   uint64_t* ka = at<uint64_t>(c, L.keys_a);
   uint64_t* kb = at<uint64_t>(c, L.keys_b);
   uint32_t* va = at<uint32_t>(c, L.vals_a);
@@ -493,6 +496,8 @@ int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_
   const uint64_t* keys = in_a ? ka : kb;
   const uint32_t* perm = in_a ? va : vb;
   int32_t* other = reinterpret_cast<int32_t*>(in_a ? kb : ka);
+  // the other value buffer is free after the sort: the pair counts
+  uint32_t* deg = any_core && pair_count ? (in_a ? vb : va) : nullptr;
   launch_gather(pts, perm, n, spts, parent, minlab, flag, bestcore, labels, s);
   mark(c, timing, PH_GATHER, s);
 
@@ -517,7 +522,7 @@ int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_
   Node* prims = at<Node>(c, L.prims);
   uint64_t* pkey = at<uint64_t>(c, L.pkey);
   launch_make_prims(spts, keys, n, cid, cell_start, prim_start, cell_dense, cell_lo, cell_hi,
-                    cell_minorig, prims, pkey, parent, flag, s);
+                    cell_minorig, prims, pkey, parent, flag, deg, s);
   mark(c, timing, PH_CELLS, s);
 
   Node* nodes = at<Node>(c, L.nodes);
@@ -527,7 +532,10 @@ int densebox_from_keys(dbscan_ctx* c, const Layout& L, const float* pts, uint32_
   const DbTables T{spts, cell_start, perm, cell_minorig, cell_lo, cell_hi, parent, flag,
                    bestcore};
   uint32_t* walkq = at<uint32_t>(c, L.walkq);
-  if (any_core) launch_count_db(nodes, prims, pkey, n, nprims, S, T, walkq, status, block, s);
+  if (any_core && deg)
+    launch_count_pairs_db(nodes, prims, pkey, n, nprims, S, T, deg, walkq, status, block, s);
+  else if (any_core)
+    launch_count_db(nodes, prims, pkey, n, nprims, S, T, walkq, status, block, s);
   mark(c, timing, PH_COUNT, s);
   launch_pairs_db(nodes, prims, pkey, n, nprims, S, T, walkq + 8, status, block, s);
   mark(c, timing, PH_PAIRS, s);
@@ -556,6 +564,7 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
   const bool timing = !graph && (o.flags & DBSCAN_FLAG_TIMING) != 0;
   const int block = o.block_size ? o.block_size : 256;
   const bool core_mode = min_pts > 2;
+  const bool pair_count = core_mode && (o.flags & DBSCAN_FLAG_PAIR_COUNT) != 0;
   const int32_t thresh = o.dense_threshold ? o.dense_threshold : min_pts;
 
   Layout L = make_layout(n, core_mode, true);
@@ -575,7 +584,8 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
                                      uint64_t(uint32_t(min_pts)),
                                      uint64_t(uint32_t(thresh)),
                                      uint64_t(block),
-                                     uint64_t(c->sort_items)};
+                                     uint64_t(c->sort_items),
+                                     uint64_t(pair_count)};
   st = run_enqueued(c, s, graph, key, [&](hipStream_t gs) {
     start_timing(c, timing, gs);
     launch_prep(at<uint32_t>(c, L.zero), L.zero_words, bounds, at<int4>(c, L.pending),
@@ -589,7 +599,7 @@ int run_densebox(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t
                      at<uint32_t>(c, L.hist), grid, gs);
     mark(c, timing, PH_MORTON, gs);
     int r = densebox_from_keys(c, L, pts, n, S, core_mode, nullptr, min_pts, labels, block,
-                               timing, gs);
+                               timing, gs, pair_count);
     if (r != DBSCAN_OK) return r;
     HIP_TRY(hipGetLastError());
     return int(DBSCAN_OK);
@@ -645,6 +655,8 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
   const int set_shift = 3 * bits;
   bool any_core = false;
   for (uint32_t k = 0; k < num_sets; ++k) any_core |= h_minpts[k] > 2;
+  // core flags by pair traversal: DenseBox only (batched FDBSCAN counts by walks)
+  const bool pair_count = db && any_core && (o.flags & DBSCAN_FLAG_PAIR_COUNT) != 0;
 
   Layout L = make_layout(n, any_core, db);
   const SetLayout SL = make_set_layout(L, num_sets);
@@ -681,7 +693,8 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
                                      num_sets,
                                      uint64_t(any_core),
                                      uint64_t(block),
-                                     uint64_t(c->sort_items)};
+                                     uint64_t(c->sort_items),
+                                     uint64_t(pair_count)};
   if (db) {
     int32_t* d_th = at<int32_t>(c, th_b);
     float* d_ih = at<float>(c, ih_b);
@@ -701,7 +714,8 @@ int run_batched(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t 
                         at<uint32_t>(c, L.hist), d_root, d_grid, status, gs);
       mark(c, timing, PH_MORTON, gs);
       const DbSets S{d_e2, d_mp, d_th, d_grid, d_root, set_shift};
-      int r = densebox_from_keys(c, L, pts, n, S, any_core, d_off, 0, labels, block, timing, gs);
+      int r = densebox_from_keys(c, L, pts, n, S, any_core, d_off, 0, labels, block, timing, gs,
+                                 pair_count);
       if (r != DBSCAN_OK) return r;
       HIP_TRY(hipGetLastError());
       return int(DBSCAN_OK);
@@ -863,7 +877,10 @@ int resolve_auto(dbscan_ctx* c, const float* pts, const int64_t* h_off, uint32_t
   const double mean = n > 0 ? sum / n : 0, mp_mean = n > 0 ? mp / n : 2;
   *algo = mean >= AUTO_DENSE_FACTOR * std::max(mp_mean, 2.0) ? DBSCAN_ALGO_DENSEBOX
                                                               : DBSCAN_ALGO_FDBSCAN;
-  *pair_count = *algo == DBSCAN_ALGO_FDBSCAN && mean < mp_mean;
+  // DenseBox counts by pair traversal: what is dense is in dense cells,
+  // which need no count, and the walk from each set's root dominates the
+  // counting walk elsewhere (the 4,096 sub-halo sets: 33 against 25.6 ms)
+  *pair_count = *algo == DBSCAN_ALGO_DENSEBOX || mean < mp_mean;
   c->auto_key = key;
   c->auto_algo = *algo;
   c->auto_pair_count = *pair_count;
@@ -1087,10 +1104,11 @@ int dbscan_cluster_batched(dbscan_ctx* c, const float* points, const int64_t* of
   c->sort_items = o.sort_tile / SORT_THREADS;
   if (!stream) o.flags &= ~DBSCAN_FLAG_GRAPH;  // graphs only on a stream the caller names
   if (o.algorithm == DBSCAN_ALGO_AUTO) {
-    bool pair_count = false;  // (a plain-call option: batched calls count by walk)
+    bool pair_count = false;  // (used by DenseBox: batched FDBSCAN counts by walk)
     int st = resolve_auto(c, points, offsets, uint32_t(num_sets), eps, min_pts,
                           stream_of(c, stream), &o.algorithm, &pair_count);
     if (st != DBSCAN_OK) return st;
+    if (pair_count) o.flags |= DBSCAN_FLAG_PAIR_COUNT;
   }
   return run_batched(c, points, offsets, uint32_t(num_sets), eps, min_pts, labels,
                      stream_of(c, stream), o);
@@ -1496,6 +1514,20 @@ int dbscan_mst(dbscan_ctx* c, const float* points, int64_t n, int32_t min_pts, i
   return finish(c, ix.status, false, s);
 }
 
+namespace {
+// the autotuner's last stage for a DenseBox pick with core points to find:
+// the same options with counting by pair traversal instead of walks
+std::vector<dbscan_options> pair_count_of(const dbscan_options& best, bool any_core) {
+  std::vector<dbscan_options> v{best};
+  if (best.algorithm == DBSCAN_ALGO_DENSEBOX && any_core) {
+    dbscan_options o = best;
+    o.flags ^= DBSCAN_FLAG_PAIR_COUNT;
+    v.push_back(o);
+  }
+  return v;
+}
+}  // namespace
+
 int dbscan_autotune(dbscan_ctx* c, const float* points, int64_t n, float eps, int32_t min_pts,
                     int32_t algorithm, int32_t* labels, dbscan_options* best, float* best_ms,
                     void* stream) {
@@ -1515,6 +1547,8 @@ int dbscan_autotune(dbscan_ctx* c, const float* points, int64_t n, float eps, in
     return dbscan_cluster_ex(c, points, n, eps, min_pts, labels, stream, &o);
   };
   st = tune(c, s, candidates(algo, min_pts), best, best_ms, run);
+  if (st != DBSCAN_OK) return st;
+  st = tune(c, s, pair_count_of(*best, min_pts > 2), best, best_ms, run);
   if (st != DBSCAN_OK) return st;
   return tune(c, s, sort_tiles_of(*best), best, best_ms, run);
 }
@@ -1541,6 +1575,8 @@ int dbscan_autotune_batched(dbscan_ctx* c, const float* points, const int64_t* o
                                   &o);
   };
   int st = tune(c, s, cands, best, best_ms, run);
+  if (st != DBSCAN_OK) return st;
+  st = tune(c, s, pair_count_of(*best, mp_max > 2), best, best_ms, run);
   if (st != DBSCAN_OK) return st;
   return tune(c, s, sort_tiles_of(*best), best, best_ms, run);
 }

@@ -221,9 +221,11 @@ __global__ __launch_bounds__(256) void k_make_prims(
     const uint32_t* __restrict__ prim_start, const uint8_t* __restrict__ cell_dense,
     const float4* __restrict__ cell_lo, const float4* __restrict__ cell_hi,
     const unsigned long long* __restrict__ cell_minorig, Node* __restrict__ prims,
-    uint64_t* __restrict__ pkey, int32_t* __restrict__ parent, uint8_t* __restrict__ flag) {
+    uint64_t* __restrict__ pkey, int32_t* __restrict__ parent, uint8_t* __restrict__ flag,
+    uint32_t* __restrict__ deg) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (deg) deg[i] = 0;  // pair counts start here (core flags by pair traversal)
   const uint32_t c = cid[i];
   const uint32_t b = cell_start[c];
   float4* out;
@@ -262,6 +264,7 @@ constexpr int32_t Q_JOIN = 0;    // core point vs cell: join on the first hit
 constexpr int32_t Q_BORDER = 1;  // non-core point vs cell: smallest core hit
 constexpr int32_t Q_CELLS = 2;   // cell vs cell: join on the first close pair
 constexpr int32_t Q_COUNT = 3;   // point vs cell: count hits for the owner lane
+constexpr int32_t Q_DEG = 4;     // point vs cell: add the hits to the point's count
 constexpr int32_t Q_MARK = 1 << 10;  // Q_JOIN: mark the point a member on a hit
 constexpr uint32_t Q_ALL = 0xffffu;  // Q_COUNT: no early stop
 
@@ -317,6 +320,7 @@ struct DbData {
   int32_t* parent;
   uint8_t* flag;
   unsigned long long* bestcore;
+  uint32_t* deg;  // neighbour counts (core flags by pair traversal), else null
 };
 
 // One wave's queue in LDS.
@@ -411,6 +415,14 @@ __device__ uint32_t drain(const DbData& D, const DbQueue& Q) {
       }
       best = wave_min_u64(best);
       if (lane == 0 && best != ~0ull) atomicMin(D.bestcore + a, best);
+    } else if (kind == Q_DEG) {
+      const uint32_t need = uint32_t(meta) >> 16;
+      uint32_t tot = 0;
+      for (uint32_t k0 = cb; k0 < ce && tot < need; k0 += 64) {
+        const uint32_t k = k0 + uint32_t(lane);
+        tot += uint32_t(__popcll(__ballot(k < ce && sq_dist4(p, D.pts[k < ce ? k : cb]) <= e2)));
+      }
+      if (lane == 0 && tot) atomicAdd(D.deg + a, tot);
     } else {  // Q_COUNT
       const uint32_t need = uint32_t(meta) >> 16;
       uint32_t tot = 0;
@@ -570,6 +582,83 @@ struct CountDb {
   }
 };
 
+// Counting by pair traversal (an option, sets with minPts > 2): lane i
+// starts at primitive i's rope, so every pair of primitives within eps is
+// met once, from the lower one, and adds to the counts of the points in it:
+// two points, one to each; a point and a dense cell, the cell's points
+// within eps of the point, to the point (a dense cell's own points are core
+// and need no count; two cells add nothing).  No early exit at minPts, but
+// no walk from the set's root either, which is most of the counting walk's
+// cost where points have few neighbours.  The counts go to deg[], and
+// k_degree_flags_db sets the flags once every walk is over.  A point only
+// needs minPts - 1 neighbours, so a scan of a cell's points stops once the
+// point's count (as far as it is known: deg[] only grows, so a stale read
+// is smaller and the scan at most longer) reaches that; then deg[x] >=
+// min(true count, minPts - 1), which gives the same flag.
+struct PairCountDb {
+  static constexpr bool kStartIsRope = true;
+  static constexpr bool kDrainBeforeEnd = true;  // queued counts are this lane's
+  DbSets S;
+  DbData D;
+  DbQueue Q;
+  const uint64_t* pkey;
+  float r2;
+  int32_t me;    // payload: sorted position of a point, or cell | CELL_BIT
+  bool live;     // a query of a set with minPts > 2
+  uint32_t cnt;  // this point's neighbours met so far (itself excluded)
+  uint32_t want; // minPts - 1 of the query's set: neighbours a point needs
+  uint64_t hi;
+  float4 ql, qh;
+  __device__ int32_t begin(uint32_t i, const float4& lo, const float4& h) {
+    me = __float_as_int(lo.w);
+    const uint32_t set = set_id(S, pkey[i]);
+    live = S.minpts[set] > 2;
+    if (!live) return SENTINEL;
+    want = uint32_t(S.minpts[set]) - 1u;
+    r2 = S.e2[set];
+    cnt = 0;
+    ql = lo;
+    qh = h;
+    hi = set_upper(S, set, h, r2);
+    return __float_as_int(h.w);
+  }
+  __device__ uint64_t khi() const { return hi; }
+  __device__ float e2() const { return r2; }
+  __device__ bool hit(int32_t, const float4& a, const float4& b) {
+    const int32_t pr = __float_as_int(a.w);
+    if (me >= 0 && pr >= 0) {  // two points: the box bound was the predicate
+      ++cnt;
+      atomicAdd(D.deg + pr, 1u);
+      return false;
+    }
+    if (me < 0 && pr < 0) return false;  // two dense cells
+    const bool all_in = box_box_far4(ql, qh, a, b) <= r2;
+    const int32_t c = (me >= 0 ? pr : me) & 0x7fffffff;
+    const uint32_t size = D.cell_start[c + 1] - D.cell_start[c];
+    if (me >= 0) {  // this point against a cell
+      if (all_in) {
+        cnt += size;
+      } else {
+        const uint32_t have = cnt + ld_wg(D.deg + me);
+        if (have < want) Q.push(Q_COUNT | int32_t(min(want - have, Q_ALL - 1u) << 16), me, c, r2);
+      }
+    } else if (all_in) {  // this cell against a point
+      atomicAdd(D.deg + pr, size);
+    } else {
+      const uint32_t have = ld_wg(D.deg + pr);
+      if (have < want) Q.push(Q_DEG | int32_t(min(want - have, Q_ALL - 1u) << 16), pr, c, r2);
+    }
+    return false;
+  }
+  __device__ bool drain() {
+    cnt += dbx::drain(D, Q);
+    return false;
+  }
+  __device__ void end() {
+    if (live && me >= 0 && cnt) atomicAdd(D.deg + me, cnt);  // others add to it too
+  }
+};
+
 // Pair traversal over primitives: lane i starts at primitive i's rope and
 // meets every primitive j > i of its set whose box is within eps of its own.
 struct PairDb {
@@ -668,6 +757,34 @@ __global__ void k_count_db(const Node* __restrict__ nodes, const Node* __restric
 }
 
 template <bool PERSIST>
+__global__ void k_count_pairs_db(const Node* __restrict__ nodes, const Node* __restrict__ prims,
+                                 const uint64_t* __restrict__ pkey, uint32_t np_bound,
+                                 const uint32_t* __restrict__ np_dev, WalkCfg wc, DbSets S,
+                                 DbData D, uint32_t* __restrict__ err) {
+  const uint32_t np = min(*np_dev, np_bound);
+  const DbQueue Q = wave_queue();
+  PairCountDb v{S, D, Q, pkey, 0.f, 0, false, 0u, 0u, 0ull, make_float4(0.f, 0.f, 0.f, 0.f),
+                make_float4(0.f, 0.f, 0.f, 0.f)};
+  db_walks<decltype(v), PERSIST>(nodes, prims, pkey, np, wc, v, Q, err);
+}
+
+// core flags of the points outside dense cells from their pair counts (the
+// point itself counts too), in sets with minPts > 2
+__global__ __launch_bounds__(256) void k_degree_flags_db(const Node* __restrict__ prims,
+                                                        const uint64_t* __restrict__ pkey,
+                                                        uint32_t np_bound,
+                                                        const uint32_t* __restrict__ np_dev,
+                                                        DbSets S, const uint32_t* __restrict__ deg,
+                                                        uint8_t* __restrict__ flag) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= min(*np_dev, np_bound)) return;
+  const int32_t x = prims[j].left;
+  if (x < 0) return;  // a dense cell
+  const int32_t mp = S.minpts[set_id(S, pkey[j])];
+  if (mp > 2) flag[x] = int64_t(deg[x]) + 1 >= int64_t(mp);
+}
+
+template <bool PERSIST>
 __global__ void k_pairs_db(const Node* __restrict__ nodes, const Node* __restrict__ prims,
                            const uint64_t* __restrict__ pkey, uint32_t np_bound,
                            const uint32_t* __restrict__ np_dev, WalkCfg wc, DbSets S, DbData D,
@@ -730,11 +847,11 @@ void launch_make_prims(const float4* pts, const uint64_t* keys, uint32_t n, cons
                        const uint32_t* cell_start, const uint32_t* prim_start,
                        const uint8_t* cell_dense, const float4* cell_lo, const float4* cell_hi,
                        const unsigned long long* cell_minorig, Node* prims, uint64_t* pkey,
-                       int32_t* parent, uint8_t* flag, hipStream_t s) {
+                       int32_t* parent, uint8_t* flag, uint32_t* deg, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_make_prims, dim3((n + 255) / 256), dim3(256), 0, s, pts, keys, n, cid,
                      cell_start, prim_start, cell_dense, cell_lo, cell_hi, cell_minorig, prims,
-                     pkey, parent, flag);
+                     pkey, parent, flag, deg);
 }
 
 void launch_one_set(float e2, int32_t min_pts, int32_t thresh, float* e2o, int32_t* mpo,
@@ -772,6 +889,27 @@ void launch_count_db(const Node* nodes, const Node* prims, const uint64_t* pkey,
                        queue_lds(block), s, nodes, prims, pkey, np_bound, np_dev,
                        walk_cfg(np_bound), sets, D, err);
   }
+}
+
+void launch_count_pairs_db(const Node* nodes, const Node* prims, const uint64_t* pkey,
+                           uint32_t np_bound, const uint32_t* np_dev, const DbSets& sets,
+                           const DbTables& t, uint32_t* deg, uint32_t* queue, uint32_t* err,
+                           int block, hipStream_t s) {
+  if (np_bound == 0) return;
+  const DbData D{t.pts, t.cell_start, t.perm, t.cell_minorig, t.cell_lo, t.cell_hi, t.parent,
+                 t.flag, t.bestcore, deg};
+  if (sets.shift < 64) {  // batched: the sets differ in cost per query, as in the pair walk
+    const uint32_t grid = persistent_blocks(reinterpret_cast<const void*>(&k_count_pairs_db<true>),
+                                            block, queue_lds(block), walk_grid(np_bound, block));
+    hipLaunchKernelGGL(k_count_pairs_db<true>, dim3(grid), dim3(block), queue_lds(block), s, nodes,
+                       prims, pkey, np_bound, np_dev, walk_cfg(np_bound, queue), sets, D, err);
+  } else {
+    hipLaunchKernelGGL(k_count_pairs_db<false>, dim3(walk_grid(np_bound, block)), dim3(block),
+                       queue_lds(block), s, nodes, prims, pkey, np_bound, np_dev,
+                       walk_cfg(np_bound), sets, D, err);
+  }
+  hipLaunchKernelGGL(k_degree_flags_db, dim3((np_bound + 255) / 256), dim3(256), 0, s, prims, pkey,
+                     np_bound, np_dev, sets, deg, t.flag);
 }
 
 void launch_pairs_db(const Node* nodes, const Node* prims, const uint64_t* pkey,

@@ -292,7 +292,7 @@ void launch_make_prims(const float4* pts, const uint64_t* keys, uint32_t n, cons
                        const uint32_t* cell_start, const uint32_t* prim_start,
                        const uint8_t* cell_dense, const float4* cell_lo, const float4* cell_hi,
                        const unsigned long long* cell_minorig, Node* prims, uint64_t* pkey,
-                       int32_t* parent, uint8_t* flag, hipStream_t s);
+                       int32_t* parent, uint8_t* flag, uint32_t* deg, hipStream_t s);
 // the one-set parameter table of a plain call
 void launch_one_set(float e2, int32_t min_pts, int32_t thresh, float* e2o, int32_t* mpo,
                     int32_t* tho, hipStream_t s);
@@ -303,6 +303,15 @@ void launch_count_db(const Node* nodes, const Node* prims, const uint64_t* pkey,
                      uint32_t np_bound, const uint32_t* np_dev, const DbSets& sets,
                      const DbTables& t, uint32_t* queue, uint32_t* err, int block,
                      hipStream_t s);
+// Core flags by pair traversal instead (the option): every pair of
+// primitives within eps adds to the points' counts in deg[] (n words, zeroed
+// by launch_make_prims), then the flags of the points outside dense cells
+// are set from them.  queue: 8 zeroed counters (batched walks run
+// persistently).
+void launch_count_pairs_db(const Node* nodes, const Node* prims, const uint64_t* pkey,
+                           uint32_t np_bound, const uint32_t* np_dev, const DbSets& sets,
+                           const DbTables& t, uint32_t* deg, uint32_t* queue, uint32_t* err,
+                           int block, hipStream_t s);
 void launch_pairs_db(const Node* nodes, const Node* prims, const uint64_t* pkey,
                      uint32_t np_bound, const uint32_t* np_dev, const DbSets& sets,
                      const DbTables& t, uint32_t* queue, uint32_t* err, int block,

@@ -45,9 +45,17 @@ def test_subhalo_sets_small(ctx, algo):
     check(ctx, pts, off, 0.05, 5, algorithm=algo)
 
 
-@pytest.mark.parametrize("algo,thresh", [("fdbscan", 0), ("densebox", 0), ("densebox", 10),
-                                         ("densebox", 40)])
-def test_mixed_params_and_empty_sets(ctx, algo, thresh):
+def test_subhalo_sets_pair_count(ctx):
+    """DenseBox core points by pair traversal over many sets (persistent
+    walks, counts cut at set ends)."""
+    pts, off = datagen.subhalo_sets(64, 4, nmin=64, nmax=65536)
+    check(ctx, pts, off, 0.05, 5, algorithm="densebox", pair_count=True)
+
+
+@pytest.mark.parametrize("algo,thresh,pc", [("fdbscan", 0, False), ("densebox", 0, False),
+                                            ("densebox", 10, False), ("densebox", 40, False),
+                                            ("densebox", 0, True), ("densebox", 10, True)])
+def test_mixed_params_and_empty_sets(ctx, algo, thresh, pc):
     rng = np.random.Generator(np.random.PCG64(3))
     sizes = [0, 1, 2, 700, 0, 5000, 33, 4096, 4097, 1]
     parts = [datagen.clumps(max(s, 1), 10 + i)[:s] for i, s in enumerate(sizes)]
@@ -55,7 +63,7 @@ def test_mixed_params_and_empty_sets(ctx, algo, thresh):
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     eps = rng.uniform(0.005, 0.05, len(sizes)).astype(F32)
     mp = np.array([1, 2, 3, 5, 10, 2, 1, 4, 2, 7], np.int32)
-    check(ctx, pts, off, eps, mp, algorithm=algo, dense_threshold=thresh)
+    check(ctx, pts, off, eps, mp, algorithm=algo, dense_threshold=thresh, pair_count=pc)
 
 
 @pytest.mark.parametrize("algo", ALGOS)
@@ -168,12 +176,13 @@ def _first_bad_sets(got, ref, off, limit=5):
     return sorted(set(np.searchsorted(off, bad, side="right") - 1))[:limit]
 
 
-@pytest.mark.parametrize("algo", ALGOS)
-def test_subhalo4096_every_set_bit_exact(ctx, subhalo4096, algo):
+@pytest.mark.parametrize("algo,pc", [("fdbscan", False), ("densebox", False),
+                                     ("densebox", True)])
+def test_subhalo4096_every_set_bit_exact(ctx, subhalo4096, algo, pc):
     """The full 4,096-set workload (~133M points): every set's labels
     against the oracle's clustering of that set alone."""
     pts, off, ref = subhalo4096
     d = dev(pts)
-    got = ctx.cluster_batched(d, off, 0.05, 5, algorithm=algo).cpu().numpy()
+    got = ctx.cluster_batched(d, off, 0.05, 5, algorithm=algo, pair_count=pc).cpu().numpy()
     del d
     assert np.array_equal(got, ref), f"sets differ: {_first_bad_sets(got, ref, off)}"

@@ -145,3 +145,52 @@ def test_densebox_equals_fdbscan_and_block_sizes(ctx):
 def test_halo16m_densebox_bit_exact(ctx):
     p = datagen.config_points("halo16M")
     np.testing.assert_array_equal(db(ctx, p, F32(0.2), 2), oracle.dbscan(p, F32(0.2), 2))
+
+
+# ---- core points by pair traversal (DBSCAN_FLAG_PAIR_COUNT) -----------------
+# The counts come from every pair of primitives met once (point-point adds
+# one to both, a point and a dense cell add the cell's points within eps to
+# the point): the same labels as the counting walk, checked against the
+# oracle where points, cells and mixed pairs all occur.
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("mp", [3, 5, 10])
+def test_pair_count_random_clumpy(ctx, seed, mp):
+    rng = np.random.Generator(np.random.PCG64(200 + seed))
+    n = int(rng.integers(10, 30000))
+    p = clumpy(n, seed, sigma=float(rng.uniform(0.005, 0.03)))
+    eps = F32(rng.uniform(0.005, 0.05))
+    np.testing.assert_array_equal(db(ctx, p, eps, mp, pair_count=True),
+                                  oracle.dbscan(p, eps, mp))
+
+
+@pytest.mark.parametrize("thresh", [0, 6, 40])
+def test_pair_count_dense_thresholds(ctx, thresh):
+    p = clumpy(60000, 11, sigma=0.01)
+    ref = oracle.dbscan(p, F32(0.02), 5)
+    np.testing.assert_array_equal(
+        db(ctx, p, 0.02, 5, dense_threshold=thresh, pair_count=True), ref)
+
+
+def test_pair_count_hand_cases(ctx):
+    # a border point between two dense cells, and one that only reaches
+    # part of a cell (the queued count of the cell's points within eps)
+    A = [(0.0, 0, 0), (-0.1, 0, 0), (-0.2, 0, 0), (-0.3, 0, 0)]
+    B = [(2.0, 0, 0), (2.1, 0, 0), (2.2, 0, 0), (2.3, 0, 0)]
+    b = [(1.0, 0, 0)]
+    for pts in (B + A + b, A + B + b, b + B + A, b + A + B):
+        p = _pts(*pts)
+        for mp in (3, 4, 5):
+            np.testing.assert_array_equal(db(ctx, p, 1.0, mp, pair_count=True),
+                                          oracle.dbscan(p, F32(1.0), mp))
+    c = np.tile(_pts((0.3, -1.25, 7.0)), (50, 1))
+    assert (db(ctx, c, 0.0, 50, pair_count=True) == 0).all()
+    assert (db(ctx, c, 0.0, 51, pair_count=True) == -1).all()
+
+
+def test_pair_count_subhalo_sets(ctx):
+    pts, off = datagen.subhalo_sets(6, 4, nmin=20000, nmax=200000)
+    for s in range(6):
+        p = pts[off[s]:off[s + 1]]
+        np.testing.assert_array_equal(db(ctx, p, F32(0.05), 5, pair_count=True),
+                                      oracle.dbscan(p, F32(0.05), 5))
