@@ -671,10 +671,14 @@ struct PairDb {
   float r2;
   bool core_mode, me_core;
   int32_t me;  // payload: sorted position of a point, or cell | CELL_BIT
+  int32_t ri;  // an ancestor of the query (its point or its cell's representative)
+               // in the union-find forest: a union returns one, and the next
+               // union's find starts there instead of at the bottom again
   uint64_t hi;
   float4 ql, qh;
   __device__ int32_t begin(uint32_t i, const float4& lo, const float4& h) {
     me = __float_as_int(lo.w);
+    ri = me >= 0 ? me : cell_rep(D, uint32_t(me & 0x7fffffff));
     const uint32_t set = set_id(S, pkey[i]);
     r2 = S.e2[set];
     core_mode = S.minpts[set] > 2;
@@ -693,13 +697,13 @@ struct PairDb {
     const int32_t pr = __float_as_int(a.w);
     if (me >= 0 && pr >= 0) {  // two points: the box bound was the predicate
       if (!core_mode) {
-        uf_union(D.parent, D.perm, me, pr);
+        ri = uf_union(D.parent, D.perm, ri, pr);
         D.flag[me] = 1;
         D.flag[pr] = 1;
         return false;
       }
       const bool cj = D.flag[pr] != 0;
-      if (me_core && cj) uf_union(D.parent, D.perm, me, pr);
+      if (me_core && cj) ri = uf_union(D.parent, D.perm, ri, pr);
       else if (me_core) atomicMin(D.bestcore + pr, okey(me));
       else if (cj) atomicMin(D.bestcore + me, okey(pr));
       return false;
@@ -707,7 +711,7 @@ struct PairDb {
     const bool all_in = box_box_far4(ql, qh, a, b) <= r2;
     if (me < 0 && pr < 0) {  // two dense cells
       const int32_t ca = me & 0x7fffffff, cb = pr & 0x7fffffff;
-      if (all_in) uf_union(D.parent, D.perm, cell_rep(D, uint32_t(ca)), cell_rep(D, uint32_t(cb)));
+      if (all_in) ri = uf_union(D.parent, D.perm, ri, cell_rep(D, uint32_t(cb)));
       else Q.push(Q_CELLS, ca, cb, r2);
       return false;
     }
@@ -716,7 +720,9 @@ struct PairDb {
     const bool x_core = me >= 0 ? me_core : (!core_mode || D.flag[x] != 0);
     if (x_core) {
       if (all_in) {
-        uf_union(D.parent, D.perm, x, cell_rep(D, uint32_t(c)));
+        // ri is an ancestor of the query: the point x, or the cell c
+        ri = me >= 0 ? uf_union(D.parent, D.perm, ri, cell_rep(D, uint32_t(c)))
+                     : uf_union(D.parent, D.perm, x, ri);
         if (!core_mode) D.flag[x] = 1;
       } else {
         Q.push(Q_JOIN | (core_mode ? 0 : Q_MARK), x, c, r2);
@@ -791,7 +797,7 @@ __global__ void k_pairs_db(const Node* __restrict__ nodes, const Node* __restric
                            uint32_t* __restrict__ err) {
   const uint32_t np = min(*np_dev, np_bound);
   const DbQueue Q = wave_queue();
-  PairDb v{S, D, Q, pkey, 0.f, false, false, 0, 0ull, make_float4(0.f, 0.f, 0.f, 0.f),
+  PairDb v{S, D, Q, pkey, 0.f, false, false, 0, 0, 0ull, make_float4(0.f, 0.f, 0.f, 0.f),
            make_float4(0.f, 0.f, 0.f, 0.f)};
   db_walks<decltype(v), PERSIST>(nodes, prims, pkey, np, wc, v, Q, err);
 }
