@@ -375,13 +375,38 @@ __device__ __forceinline__ void set_right(Ends& E, const uint64_t* __restrict__ 
 // in this launch, where its slot lives in an LDS hash table (split -> bound)
 // instead of global memory: the exchange is an LDS atomic.  A first arrival
 // that no thread of this launch completes is carried to other[] when the
-// block ends, for a later level.  The values a step reads from other[] (at
-// both candidate parent splits of its node), the sibling's box and the keys
-// around the node's new end are loaded in one batch after each exchange, so
-// a step costs one round trip to memory.  nodes is written and read by
-// different threads of the same launch, ordered by the exchange: no
-// __restrict__ on it.
-constexpr uint32_t LEVEL_TAB_FACTOR = 4;  // table slots per thread (load <= 1/2)
+// block ends, for a later level.
+//
+// Sibling hand-over in LDS.  Before its exchange a thread leaves, in its
+// own LDS record, what the sibling will need from it: its box and what it
+// knows about its outer end (the deltas and set cut there and other[] at
+// that split).  The exchanged table value carries the thread's number with
+// its bound.  The first arrival stops (a thread arrives first at most
+// once), so its record stays put; the second arrival learns from the value
+// it gets back whose record it is and takes box and end from LDS: a step between two
+// nodes of the same launch costs no memory round trip.  Only a split whose
+// first child finished in an earlier launch (other[] holds its bound) still
+// loads the sibling's box, the keys around the node's new end and other[]
+// at its candidate parent splits from memory, in one batch.  nodes is
+// written and read by different threads of the same launch, ordered by the
+// exchange: no __restrict__ on it.
+//
+// Table load: every key in the table has its first arrival in this launch,
+// and a thread arrives first at most once, so a launch of T threads keys at
+// most T splits: 2 slots per thread keep the load at most 1/2.
+constexpr uint32_t LEVEL_TAB_FACTOR = 2;
+
+// What a first arrival leaves for its sibling (one per thread).
+struct SibRec {
+  float lox, loy, loz, hix, hiy, hiz;
+  uint64_t d0, d1;  // left child: delta(l - 1); right child: delta(r), delta(r + 1)
+  int32_t o;        // other[] at that end's split (-1: none)
+  int32_t cut;      // a set ends there
+};
+// LDS of a level launch of `threads` threads with a table of 2^tab_log2 slots
+inline size_t level_lds(uint32_t threads, uint32_t tab_log2) {
+  return (size_t(12) << tab_log2) + size_t(threads) * sizeof(SibRec);
+}
 
 __device__ __forceinline__ int32_t tab_slot(int32_t* s_key, uint32_t tab_log2, int32_t split) {
   const uint32_t m = (1u << tab_log2) - 1u;
@@ -400,10 +425,13 @@ __global__ __launch_bounds__(1024) void k_build_level(
     const uint32_t* __restrict__ n_dev, uint64_t frame, uint32_t entries, uint32_t tab_log2,
     int set_shift, Node* nodes, int32_t* __restrict__ other, int32_t* set_root,
     const int4* __restrict__ pend_in, int4* __restrict__ pend_out, uint32_t* err) {
-  extern __shared__ int32_t s_tab[];  // split keys, then their bounds
+  // split keys; their values: -1 empty, -2 both children met, else the first
+  // arrival's (thread << 32 | bound); then one SibRec per thread
+  extern __shared__ int32_t s_tab[];
   const uint32_t tab = 1u << tab_log2;
   int32_t* s_key = s_tab;
-  int32_t* s_val = s_tab + tab;
+  int64_t* s_val = reinterpret_cast<int64_t*>(s_tab + tab);
+  SibRec* s_rec = reinterpret_cast<SibRec*>(s_tab + 3 * tab);
   for (uint32_t h = threadIdx.x; h < tab; h += blockDim.x) {
     s_key[h] = -1;
     s_val[h] = -1;
@@ -449,23 +477,58 @@ __global__ __launch_bounds__(1024) void k_build_level(
       break;
     }
     int32_t bound = is_left ? o_r : o_l;  // the other child finished in an earlier launch
+    int32_t who = -1;  // the sibling's thread, when it finished in this launch
     if (bound < 0) {
       const int32_t h = tab_slot(s_key, tab_log2, par);
       if (h < 0) {
         atomicOr(err, STATUS_TREE);
         break;
       }
-      bound = __hip_atomic_exchange(s_val + h, is_left ? l : r, __ATOMIC_ACQ_REL,
-                                    __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (bound < 0) break;  // first arrival: the sibling finishes the parent (or later)
-      s_val[h] = -2;         // both children met here: nothing to carry on
+      // for the sibling, should this be the first arrival: box and outer end
+      SibRec& mine = s_rec[threadIdx.x];
+      mine.lox = lo.x; mine.loy = lo.y; mine.loz = lo.z;
+      mine.hix = hi.x; mine.hiy = hi.y; mine.hiz = hi.z;
+      mine.d0 = is_left ? E.dl : E.dr;
+      mine.d1 = E.dr1;
+      mine.o = is_left ? o_l : o_r;
+      mine.cut = is_left ? E.cl : E.cr;
+      const int64_t v = (int64_t(threadIdx.x) << 32) | int64_t(uint32_t(is_left ? l : r));
+      const int64_t got = __hip_atomic_exchange(s_val + h, v, __ATOMIC_ACQ_REL,
+                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (got < 0) break;  // first arrival: the sibling finishes the parent (or later)
+      bound = int32_t(uint32_t(got));
+      who = int32_t(got >> 32);
+      s_val[h] = -2;       // both children met here: nothing to carry on
     }
     if (is_left) r = bound;
     else l = bound;
     const int32_t sl = is_left ? par + 1 : l, sr = is_left ? r : par;
-    if (sl < 0 || sr > last || sl > sr || l > par || par >= r) {
+    if (sl < 0 || sr > last || sl > sr || l > par || par >= r ||
+        who >= int32_t(blockDim.x)) {
       atomicOr(err, STATUS_TREE);
       break;
+    }
+    if (who >= 0) {  // the sibling's box and outer end, from its record
+      const SibRec& sib = s_rec[who];
+      grow(lo, hi, make_float4(sib.lox, sib.loy, sib.loz, 0.f),
+           make_float4(sib.hix, sib.hiy, sib.hiz, 0.f));
+      if (is_left) {  // the right end is now the sibling's right end
+        E.dr = sib.d0;
+        E.dr1 = sib.d1;
+        E.cr = sib.cut != 0;
+        o_r = sib.o;
+      } else {        // the left end is now the sibling's left end
+        E.dl = sib.d0;
+        E.cl = sib.cut != 0;
+        o_l = sib.o;
+      }
+      g = par;
+      if (l == 0 && r == last) {  // the root, number 0
+        write_node(nodes, 0, lo, hi, left_ref(l, g), SENTINEL);
+        if (E.cl && E.cr) set_root[set_of(keys, l, set_shift)] = 0;
+        break;
+      }
+      continue;
     }
     // the sibling's box, the keys around the new end and other[] at the new
     // node's candidate parent splits, loaded together (no branch between
@@ -503,8 +566,9 @@ __global__ __launch_bounds__(1024) void k_build_level(
   // first arrivals nobody here completed: to other[], for a later level
   __syncthreads();
   for (uint32_t h = threadIdx.x; h < tab; h += blockDim.x) {
-    const int32_t k = s_key[h], v = s_val[h];
-    if (k >= 0 && v >= 0) other[k] = v;
+    const int32_t k = s_key[h];
+    const int64_t v = s_val[h];
+    if (k >= 0 && v >= 0) other[k] = int32_t(uint32_t(v));
   }
 }
 
@@ -567,14 +631,16 @@ void build_impl(const uint64_t* keys, int set_shift, FrameLeaves flv, Leaves lv,
       // root (one frame over every leaf), in place of the remaining levels
       const uint32_t threads = (entries + 63) / 64 * 64;
       const uint32_t tl = level_tab_log2(threads);
-      hipLaunchKernelGGL(k_build_level<Leaves>, dim3(1), dim3(threads), size_t(8) << tl, s, keys,
+      hipLaunchKernelGGL(k_build_level<Leaves>, dim3(1), dim3(threads), level_lds(threads, tl), s,
+                         keys,
                          lv, n, n_dev, uint64_t(n), entries, tl, set_shift, nodes, other, root,
                          pin, pout, err);
       if (after_level) after_level(arg, lv_i);
       return;
     } else {
       const uint32_t tl = level_tab_log2(BUILD_BLOCK);
-      hipLaunchKernelGGL(k_build_level<Leaves>, dim3(frames), dim3(BUILD_BLOCK), size_t(8) << tl, s,
+      hipLaunchKernelGGL(k_build_level<Leaves>, dim3(frames), dim3(BUILD_BLOCK),
+                         level_lds(BUILD_BLOCK, tl), s,
                          keys, lv, n, n_dev, frame, uint32_t(frames) * BUILD_BLOCK, tl, set_shift,
                          nodes, other, root, pin, pout, err);
     }
