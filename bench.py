@@ -865,7 +865,8 @@ def bench_batched(ctx, steps=3):
     log("[bench] batched autotuner ...")
     tuned = ctx.autotune_batched(d, off, eps, mp)
     t_b = timed(algorithm=tuned["algorithm"], block_size=tuned["block_size"],
-                dense_threshold=tuned["dense_threshold"], sort_tile=tuned["sort_tile"])
+                dense_threshold=tuned["dense_threshold"], sort_tile=tuned["sort_tile"],
+                pair_count=tuned["pair_count"])
     # one call per set, in sequence on one stream (launch overheads included)
     log("[bench] one plain call per set ...")
     eps = float(eps)
@@ -891,7 +892,7 @@ def bench_batched(ctx, steps=3):
     return {"workload": "subhalo4096", "sets": len(off) - 1, "points": n, "eps": float(eps),
             "min_pts": mp, "autotuned": {k: tuned[k] for k in
                                          ("algorithm", "block_size", "dense_threshold",
-                                          "sort_tile")},
+                                          "sort_tile", "pair_count")},
             "batched_ms": round(t_b * 1e3, 3),
             "batched_mpoints_per_s": round(n / t_b / 1e6, 2),
             "fdbscan_batched_ms": round(t_f * 1e3, 3),

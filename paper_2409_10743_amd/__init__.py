@@ -317,7 +317,7 @@ class Context:
 
     def autotune_batched(self, points, offsets, eps, min_pts, cache=None):
         """Fastest options for this batch (algorithm, block_size,
-        dense_threshold, sort_tile), with its time in ms; see
+        dense_threshold, sort_tile, pair_count), with its time in ms; see
         dbscan_autotune_batched.  ``cache`` as for autotune, keyed by the
         device, the set count, the size class of the total and the exact
         per-set eps and minPts."""
@@ -346,7 +346,7 @@ class Context:
             ctypes.byref(o), ctypes.byref(ms), _stream(p.device)))
         res = {"algorithm": ALGO_NAME[o.algorithm], "block_size": o.block_size,
                "dense_threshold": o.dense_threshold, "sort_tile": o.sort_tile,
-               "ms": ms.value}
+               "pair_count": bool(o.flags & FLAG_PAIR_COUNT), "ms": ms.value}
         if key is not None:
             cache.put(key, res)
         return dict(res, cached=False) if key is not None else res

@@ -113,8 +113,11 @@ def test_autotune_batched_keeps_labels(ctx):
     if best["algorithm"] == "fdbscan":
         assert best["dense_threshold"] == 0
     assert best["sort_tile"] in (0, 2048, 3072)
+    if best["algorithm"] == "fdbscan":
+        assert not best["pair_count"]  # (batched FDBSCAN counts by walk)
     check(ctx, pts, off, 0.05, 5, algorithm=best["algorithm"], block_size=best["block_size"],
-          dense_threshold=best["dense_threshold"], sort_tile=best["sort_tile"])
+          dense_threshold=best["dense_threshold"], sort_tile=best["sort_tile"],
+          pair_count=best["pair_count"])
 
 
 @pytest.mark.parametrize("tile", [2048, 3072, 4096])
