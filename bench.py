@@ -377,6 +377,8 @@ def main():
     ap.add_argument("--min-pts", type=int, default=0, help="0: the workload's own")
     ap.add_argument("--algorithm", default="fdbscan", choices=["fdbscan", "densebox"])
     ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--pair-count", action="store_true",
+                    help="core points by pair traversal (DBSCAN_FLAG_PAIR_COUNT; minPts > 2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -453,10 +455,11 @@ def main():
     def step(**kw):
         if off is None:
             ctx.cluster(d, float(eps), mp, algorithm=args.algorithm, block_size=args.block_size,
-                        out=labels, **kw)
+                        out=labels, pair_count=args.pair_count, **kw)
         else:
             ctx.cluster_batched(d, off, float(eps), mp, algorithm=args.algorithm,
-                                block_size=args.block_size, out=labels, **kw)
+                                block_size=args.block_size, out=labels,
+                                pair_count=args.pair_count, **kw)
 
     if args.knn_only:
         log("[bench] k nearest neighbours only ...")
@@ -494,7 +497,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "eps": float(eps), "min_pts": mp,
-                   "algorithm": args.algorithm, "parallelism": "single GPU"},
+                   "algorithm": args.algorithm, "pair_count": args.pair_count,
+                   "parallelism": "single GPU"},
         "roofline": None,
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "sort_passes": passes,
