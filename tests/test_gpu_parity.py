@@ -224,8 +224,10 @@ def test_code_bits_dropped_by_eps(ctx, eps, passes):
     of some points at several small offsets give every radius some pairs."""
     base = clumpy(40000, 123)
     rng = np.random.Generator(np.random.PCG64(5))
-    extra = [base[rng.integers(0, 40000, 3000)] + rng.normal(0, d, (3000, 3)).astype(F32)
-             for d in (2e-6, 1e-5, 5e-5)]
+    # 49,003 points: an odd count, so the sort's second 32-bit words (at n + i)
+    # are not 16-byte aligned
+    extra = [base[rng.integers(0, 40000, m)] + rng.normal(0, d, (m, 3)).astype(F32)
+             for d, m in ((2e-6, 3000), (1e-5, 3001), (5e-5, 3002))]
     p = np.clip(np.concatenate([base] + extra), 0, 1).astype(F32)
     p = p[rng.permutation(p.shape[0])]
     assert ctx.pair_count(dev(p), eps) == oracle.pair_count(p, F32(eps))
