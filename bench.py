@@ -144,14 +144,15 @@ def measured_traffic(kernel: str, workload: str):
 
 # ---- rocprofv3 summaries (what profiles/ holds) ------------------------------
 # The profiles are taken on the GPU with these commands (from the repository
-# root, TMPDIR=/tmp):
-#   rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/trace_<W> -o run \
+# root, TMPDIR=/tmp; <OUT> is any scratch folder, each summary names the one
+# its command used):
+#   rocprofv3 --kernel-trace --stats --output-format csv -d <OUT>/trace_<W> -o run \
 #       -- python3 -u bench.py --workload <W> [--algorithm A] --steps 5 --warmup 1 \
 #       --no-cpu-baseline --no-extras
-#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_FETCH_SIZE_<W> -o run \
+#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <OUT>/pmc_FETCH_SIZE_<W> -o run \
 #       -- python3 -u bench.py --workload <W> --steps 2 --warmup 1 --no-cpu-baseline --no-extras
 #   (the same with WRITE_SIZE), and for the calibration
-#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/copy_FETCH_SIZE -o run \
+#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <OUT>/copy_FETCH_SIZE -o run \
 #       -- python3 -u bench.py --copy-calibration        (and WRITE_SIZE)
 # and summarised with --summarize-trace / --summarize-pmc below.
 
@@ -349,7 +350,7 @@ def copy_calibration():
 
 def host_threads() -> int:
     """Host threads for the oracle legs: the CPUs this process may use, at
-    most 16 (a one-GPU machine's share)."""
+    most 16 (the host share of one GPU on a shared machine)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
