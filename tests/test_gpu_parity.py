@@ -348,6 +348,22 @@ def test_pair_count_core_flags(ctx, seed, mp):
                                   oracle.dbscan(p, eps, mp))
 
 
+@pytest.mark.parametrize("mp", [3, 6])
+def test_pair_list_fits_and_overflows(ctx, mp):
+    """With counting by pair traversal the counting walk records its pairs
+    (at most n of them) and the main phase runs over that list; where there
+    are more pairs than points the list overflows and the main phase walks
+    instead.  A sparse field (about 0.2 pairs a point: the list), a tight
+    clump (thousands of neighbours a point: the walk) and both together."""
+    rng = np.random.Generator(np.random.PCG64(77 + mp))
+    sparse = rng.random((60000, 3)).astype(F32)
+    clump = (0.5 + rng.standard_normal((8000, 3)) * 0.004).astype(F32)
+    both = np.concatenate([sparse, clump])[rng.permutation(68000)]
+    for p, eps in ((sparse, 0.012), (clump, 0.01), (both, 0.012)):
+        np.testing.assert_array_equal(run(ctx, p, eps, mp, pair_count=True),
+                                      oracle.dbscan(p, F32(eps), mp))
+
+
 @pytest.mark.parametrize("mp", [2, 5, 10])
 def test_clumps32k(ctx, mp):
     p = datagen.config_points("clumps32k")
