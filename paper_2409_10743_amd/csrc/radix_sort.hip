@@ -79,10 +79,18 @@ __global__ __launch_bounds__(256) void k_digit_hist(const uint64_t* __restrict__
 // with each key (u32 words n..2n-1 of the key buffers: the high half while
 // the low half is sorted).  NARROW: the pass writes that word as the
 // output key and no second word (the last pass over the low half).
+//
+// skip_lo (8: never): a pass from skip_lo on whose digit is the same for
+// every key is skipped, not copied, when it pairs with a neighbouring such
+// pass: in each run of consecutive one-digit passes the first and second
+// are skipped, the third and fourth, and so on (an odd run's last pass
+// still copies).  A skipped pair leaves the data where the host's
+// alternation expects it after both, so no direction changes.  ghist is
+// this pass's row of the digit counts of all passes.
 template <bool IOTA, int ITEMS, class KIN, bool PAY, bool NARROW>
 __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
     uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb, uint32_t n, int shift, int pass_no,
-    const uint32_t* __restrict__ drop, const uint32_t* __restrict__ ghist,
+    int skip_lo, const uint32_t* __restrict__ drop, const uint32_t* __restrict__ ghist,
     uint32_t* __restrict__ status, uint32_t* __restrict__ next_status,
     uint32_t* __restrict__ tile_ctr, uint32_t* __restrict__ err) {
   static_assert(!NARROW || PAY, "a narrowing pass writes the carried word");
@@ -96,6 +104,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
   __shared__ uint32_t s_whist[WAVES][RADIX];
   __shared__ uint32_t s_tmp[WAVES];
   __shared__ uint32_t s_tile;
+  __shared__ uint32_t s_one;  // bit q: every key has the same digit in pass q
 
   // the next pass's look-back words start at zero: each workgroup clears
   // one tile's row of them (the grid has one workgroup per tile), also in a
@@ -125,6 +134,24 @@ __global__ __launch_bounds__(SORT_THREADS) void k_onesweep(
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t gcount = ghist[tid];  // this pass's count of digit tid
+  if (skip_lo < SORT_PASSES) {
+    if (tid == 0) s_one = 0;
+    __syncthreads();
+    const uint32_t* all = ghist - size_t(pass_no) * RADIX;  // every pass's counts
+    uint32_t mine = 0;
+    for (int q = skip_lo; q < SORT_PASSES; ++q)
+      mine |= all[size_t(q) * RADIX + tid] == n ? (1u << q) : 0u;
+    if (mine) atomicOr(&s_one, mine);
+    __syncthreads();
+    const uint32_t one = s_one;
+    if (pass_no >= skip_lo && ((one >> pass_no) & 1u)) {
+      int a = pass_no;  // the run of one-digit passes holding this one
+      while (a - 1 >= skip_lo && ((one >> (a - 1)) & 1u)) --a;
+      const bool second = ((pass_no - a) & 1) != 0;
+      const bool paired = second || (pass_no + 1 < SORT_PASSES && ((one >> (pass_no + 1)) & 1u));
+      if (paired) return;  // (uniform: every thread reads the same bits)
+    }
+  }
   if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
   for (int w = 0; w < WAVES; ++w) s_whist[w][tid] = 0;
   // one digit for every key (constant code bits, or a set id shared by all
@@ -283,21 +310,21 @@ enum PassWords { WIDE = 0, LO = 1, LO_LAST = 2, HI = 3 };
 
 template <bool IOTA, int ITEMS>
 void launch_pass(int words, dim3 grid, uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
-                 uint32_t n, int p, const uint32_t* drop, const uint32_t* ghist, uint32_t* st,
-                 uint32_t* next, uint32_t* ctr, uint32_t* err, hipStream_t s) {
+                 uint32_t n, int p, int skip_lo, const uint32_t* drop, const uint32_t* ghist,
+                 uint32_t* st, uint32_t* next, uint32_t* ctr, uint32_t* err, hipStream_t s) {
   const dim3 block(SORT_THREADS);
   if (words == LO)
     hipLaunchKernelGGL((k_onesweep<IOTA, ITEMS, uint32_t, true, false>), grid, block, 0, s, ka,
-                       kb, va, vb, n, 8 * p, p, drop, ghist, st, next, ctr, err);
+                       kb, va, vb, n, 8 * p, p, skip_lo, drop, ghist, st, next, ctr, err);
   else if (words == LO_LAST)
     hipLaunchKernelGGL((k_onesweep<IOTA, ITEMS, uint32_t, true, true>), grid, block, 0, s, ka,
-                       kb, va, vb, n, 8 * p, p, drop, ghist, st, next, ctr, err);
+                       kb, va, vb, n, 8 * p, p, skip_lo, drop, ghist, st, next, ctr, err);
   else if (words == HI)
     hipLaunchKernelGGL((k_onesweep<IOTA, ITEMS, uint32_t, false, false>), grid, block, 0, s, ka,
-                       kb, va, vb, n, 8 * p - 32, p, drop, ghist, st, next, ctr, err);
+                       kb, va, vb, n, 8 * p - 32, p, skip_lo, drop, ghist, st, next, ctr, err);
   else
     hipLaunchKernelGGL((k_onesweep<IOTA, ITEMS, uint64_t, false, false>), grid, block, 0, s, ka,
-                       kb, va, vb, n, 8 * p, p, drop, ghist, st, next, ctr, err);
+                       kb, va, vb, n, 8 * p, p, skip_lo, drop, ghist, st, next, ctr, err);
 }
 
 // one pass from (kin, vin) to (kout, vout); with `drop`, the kernel picks
@@ -306,17 +333,17 @@ void launch_pass(int words, dim3 grid, uint64_t* ka, uint64_t* kb, uint32_t* va,
 // them and are cleared here
 template <int ITEMS>
 void sort_pass(bool iota, int words, const uint64_t* kin, uint64_t* kout, const uint32_t* vin,
-               uint32_t* vout, uint32_t n, int p, const uint32_t* drop, const SortScratch& sc,
-               uint32_t* st, hipStream_t s) {
+               uint32_t* vout, uint32_t n, int p, int skip_lo, const uint32_t* drop,
+               const SortScratch& sc, uint32_t* st, hipStream_t s) {
   uint32_t* next = p + 1 < SORT_PASSES ? st + size_t(sort_tiles(n, ITEMS)) * RADIX : nullptr;
   const uint32_t tiles = sort_tiles(n, ITEMS);
   uint64_t* ka = const_cast<uint64_t*>(kin);  // read-only in this direction
   uint32_t* va = const_cast<uint32_t*>(vin);
   if (iota)
-    launch_pass<true, ITEMS>(words, dim3(tiles), ka, kout, va, vout, n, p, drop,
+    launch_pass<true, ITEMS>(words, dim3(tiles), ka, kout, va, vout, n, p, skip_lo, drop,
                              sc.hist + p * RADIX, st, next, sc.tile_ctr + p, sc.err, s);
   else
-    launch_pass<false, ITEMS>(words, dim3(tiles), ka, kout, va, vout, n, p, drop,
+    launch_pass<false, ITEMS>(words, dim3(tiles), ka, kout, va, vout, n, p, skip_lo, drop,
                               sc.hist + p * RADIX, st, next, sc.tile_ctr + p, sc.err, s);
 }
 
@@ -337,9 +364,11 @@ bool launch_radix_sort(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_t* vb,
     uint32_t* vout = in_a ? vb : va;
     uint32_t* st = sc.status + size_t(p - first_pass) * words;  // the first pass's: zeroed
     const bool iota = p == first_pass && iota_vals;
-    if (items == 8) sort_pass<8>(iota, WIDE, kin, kout, vin, vout, n, p, nullptr, sc, st, s);
-    else if (items == 12) sort_pass<12>(iota, WIDE, kin, kout, vin, vout, n, p, nullptr, sc, st, s);
-    else sort_pass<16>(iota, WIDE, kin, kout, vin, vout, n, p, nullptr, sc, st, s);
+    // one-digit passes are skipped in pairs, never the one that makes the values
+    const int lo = first_pass + (iota_vals ? 1 : 0);
+    if (items == 8) sort_pass<8>(iota, WIDE, kin, kout, vin, vout, n, p, lo, nullptr, sc, st, s);
+    else if (items == 12) sort_pass<12>(iota, WIDE, kin, kout, vin, vout, n, p, lo, nullptr, sc, st, s);
+    else sort_pass<16>(iota, WIDE, kin, kout, vin, vout, n, p, lo, nullptr, sc, st, s);
     if (after_pass) after_pass(arg, p);
     in_a = !in_a;
   }
@@ -356,9 +385,9 @@ void launch_radix_sort_dropped(uint64_t* ka, uint64_t* kb, uint32_t* va, uint32_
   for (int p = 0; p < SORT_PASSES; ++p) {
     uint32_t* st = sc.status + size_t(p) * words;
     const int w = p < 3 ? LO : p == 3 ? LO_LAST : HI;
-    if (items == 8) sort_pass<8>(false, w, ka, kb, va, vb, n, p, drop, sc, st, s);
-    else if (items == 12) sort_pass<12>(false, w, ka, kb, va, vb, n, p, drop, sc, st, s);
-    else sort_pass<16>(false, w, ka, kb, va, vb, n, p, drop, sc, st, s);
+    if (items == 8) sort_pass<8>(false, w, ka, kb, va, vb, n, p, SORT_PASSES, drop, sc, st, s);
+    else if (items == 12) sort_pass<12>(false, w, ka, kb, va, vb, n, p, SORT_PASSES, drop, sc, st, s);
+    else sort_pass<16>(false, w, ka, kb, va, vb, n, p, SORT_PASSES, drop, sc, st, s);
     if (after_pass) after_pass(arg, p);
   }
 }
