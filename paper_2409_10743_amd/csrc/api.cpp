@@ -64,7 +64,7 @@ struct Layout {
   size_t set_e2, set_mp, set_th, grid;  // the one-set table of a plain DenseBox call
   uint32_t pending_entries;
   size_t zero;        // start of the region zeroed by k_prep
-  size_t hist, tile_ctr, status, count, walkq, plist, sort_status;
+  size_t hist, tile_ctr, status, count, walkq, ncore, sort_status;
   size_t zero_words;  // 32-bit words from `zero`
   size_t bounds, drop, root;
   size_t total;
@@ -118,7 +118,7 @@ Layout make_layout(uint32_t n, bool need_bestcore, bool densebox = false) {
   L.status = take(4);
   L.count = take(4 * 8);  // pairs, internal-node visits, descents, leaf tests
   L.walkq = take(4 * 8 * 4);  // chunk counters of up to four persistent walks
-  L.plist = take(9 * 4);      // pair list: slots reserved per region (8), overflowed
+  L.ncore = take(4);          // core points (counting by pair traversal)
   if (densebox) {
     L.scan_ctr = take(8);
     L.ncells = take(8);  // ncells and nprims side by side: read back together
@@ -443,29 +443,21 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
     int32_t* parent = at<int32_t>(c, L.parent);
     unsigned long long* bestcore =
         core_mode ? at<unsigned long long>(c, L.bestcore) : nullptr;
-    // with counting by pair traversal the counting walk also records its
-    // pairs, in the key buffer the build left free (n slots of 8 bytes), so
-    // that the main phase is a pass over them; if they do not fit, the main
-    // phase walks as without the list
-    PairList pl{};
-    if (pair_count)
-      pl = PairList{at<uint2>(c, L.keys_b), n, at<uint32_t>(c, L.plist),
-                    at<uint32_t>(c, L.plist) + 8};
+    uint32_t* ncore = pair_count ? at<uint32_t>(c, L.ncore) : nullptr;
     if (pair_count)
       launch_count_pairs(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, min_pts,
-                         deg, flag, pl, ix.status, block, gs);
+                         deg, flag, ncore, ix.status, block, gs);
     else if (core_mode)
       launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, ix.root, e2,
                    min_pts, flag, ix.status, block, gs);
     mark(c, timing, PH_COUNT, gs);
-    if (pair_count) {
-      launch_pairs_list(pl, flag, ix.perm, parent, bestcore, gs);
+    // with the counts of the pair traversal at hand, points with no
+    // neighbour (most of a sparse field) start no main-phase walk, and with
+    // no core point at all no walk starts
+    if (core_mode)
       launch_pairs_core(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, flag,
-                        ix.perm, parent, bestcore, pl.full, ix.status, block, gs);
-    } else if (core_mode) {
-      launch_pairs_core(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, flag,
-                        ix.perm, parent, bestcore, nullptr, ix.status, block, gs);
-    }
+                        ix.perm, parent, bestcore, pair_count ? deg : nullptr, ncore,
+                        ix.status, block, gs);
     else
       launch_pairs_fof(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, ix.perm,
                        parent, flag, ix.status, block, gs);

@@ -150,29 +150,11 @@ void launch_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
 // Core flags by pair traversal: each pair adds one to both points' counts
 // in deg (zero beforehand), then is_core[i] = deg[i] + 1 >= min_pts.  No
 // early exit: for fields where points have few neighbours.
-// Where a counting walk by pair traversal records the pairs it finds, so
-// that the main phase need not walk again (list null: no list).
-// The list is split into 8 equal regions, one per XCD (a wave appends to
-// the region of blockIdx % 8, the XCD its block runs on), each with its own
-// counter: the reservations of a launch do not all queue on one address.
-struct PairList {
-  uint2* list;     // cap slots
-  uint32_t cap;
-  uint32_t* ctr;   // [8] slots reserved per region (zeroed before the walk)
-  uint32_t* full;  // set (zeroed before) once the list could not hold every pair
-};
-// slots of one region: a whole number of 64-slot chunks
-inline __host__ __device__ uint32_t pair_list_region(uint32_t cap) {
-  return cap / 8u / 64u * 64u;
-}
+// ncore (may be null; zeroed before): gets the number of core points.
 void launch_count_pairs(const Node* nodes, const float4* leaf, const uint64_t* keys,
                         const uint32_t* bounds, const uint32_t* drop,
                         uint32_t n, float e2, int32_t min_pts, uint32_t* deg, uint8_t* is_core,
-                        PairList pl, uint32_t* err, int block, hipStream_t s);
-// The main phase (minPts > 2) from the pairs of `pl`; nothing if the list
-// overflowed (then launch_pairs_core with only_if = pl.full walks instead).
-void launch_pairs_list(PairList pl, const uint8_t* is_core, const uint32_t* perm,
-                       int32_t* parent, unsigned long long* bestcore, hipStream_t s);
+                        uint32_t* ncore, uint32_t* err, int block, hipStream_t s);
 // minPts <= 2: every point with a neighbour is core; union every pair.
 void launch_pairs_fof(const Node* nodes, const float4* leaf, const uint64_t* keys,
                       const uint32_t* bounds, const uint32_t* drop,
@@ -180,12 +162,14 @@ void launch_pairs_fof(const Node* nodes, const float4* leaf, const uint64_t* key
                       uint8_t* member, uint32_t* err, int block, hipStream_t s);
 // minPts > 2: union core pairs, record each non-core point's smallest-index
 // core neighbour.
-// only_if (may be null): walk only if *only_if is set on the device.
+// deg, ncore (may be null): neighbour counts and the number of core points
+// from a counting pass by pair traversal; a point with no neighbour starts
+// no walk (it is in no pair), and with no core point no walk starts.
 void launch_pairs_core(const Node* nodes, const float4* leaf, const uint64_t* keys,
                        const uint32_t* bounds, const uint32_t* drop,
                        uint32_t n, float e2, const uint8_t* is_core, const uint32_t* perm,
-                       int32_t* parent, unsigned long long* bestcore, const uint32_t* only_if,
-                       uint32_t* err, int block, hipStream_t s);
+                       int32_t* parent, unsigned long long* bestcore, const uint32_t* deg,
+                       const uint32_t* ncore, uint32_t* err, int block, hipStream_t s);
 // Pair traversal with F(i, j) = count: every pair exactly once.
 void launch_pairs_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
                         const uint32_t* bounds, const uint32_t* drop,

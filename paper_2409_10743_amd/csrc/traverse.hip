@@ -15,7 +15,6 @@
 //  * counting by pair traversal (an option): every pair adds one to both
 //    points' neighbour counts.  No early exit, but no walk from the root
 //    either: cheaper where points have few neighbours.
-#include <algorithm>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -64,7 +63,6 @@ template <int MODE>
 struct PairVisit {
   static constexpr bool kBounded = true;
   static constexpr bool kStartIsRope = true;  // the query leaf's rope
-  static constexpr bool kAppend = MODE == DEGREE;  // the counting walk records its pairs
   float r2;
   const uint8_t* is_core;
   const uint32_t* perm;
@@ -77,12 +75,12 @@ struct PairVisit {
   unsigned long long tot[4];                 // COUNT only: this lane's totals
   MortonGrid grid;
   uint64_t hi, mask;
-  uint32_t* deg;  // DEGREE only: neighbour counts (self excluded)
-  PairList plist;  // DEGREE only: where the pairs go (list null: nowhere)
+  uint32_t* deg;  // DEGREE: neighbour counts (self excluded); CORE: the same, read (or null)
   __device__ uint64_t khi() const { return hi; }
   __device__ int32_t begin(uint32_t i, const float4& q) {
     found = false;
     ri = int32_t(i);
+    if (MODE == CORE && deg && deg[i] == 0u) return SENTINEL;  // no neighbour: no pair from i
     hi = grid.upper_code(q, r2) & mask;
     if (MODE == COUNT || MODE == DEGREE) pairs = visits = descents = leaves = 0;
     if (MODE == CORE) ci = is_core[i] != 0;
@@ -133,19 +131,19 @@ __device__ __forceinline__ void wave_add(unsigned long long* dst, unsigned long 
   if ((threadIdx.x & 63) == 0 && x) atomicAdd(dst, x);
 }
 
-// only_if (not null): the walk runs only if *only_if is set (the fallback
-// of a pair list that overflowed), else every wave returns at once
 template <int MODE>
 __global__ void k_pairs(const Node* __restrict__ nodes, const float4* __restrict__ leaf,
                         const uint64_t* __restrict__ keys, const uint32_t* __restrict__ bounds,
                         const uint32_t* drop, uint32_t n, WalkCfg wc, float e2,
                         const uint8_t* __restrict__ is_core, const uint32_t* __restrict__ perm,
                         int32_t* parent, uint8_t* member, unsigned long long* bestcore,
-                        unsigned long long* count, uint32_t* deg, PairList pl,
-                        const uint32_t* only_if, uint32_t* err) {
-  if (only_if && *only_if == 0u) return;
+                        unsigned long long* count, uint32_t* deg, const uint32_t* ncore,
+                        uint32_t* err) {
+  // ncore (CORE only, may be null): the number of core points; with none
+  // there is nothing for the main phase to join or attach
+  if (MODE == CORE && ncore && *ncore == 0u) return;
   PairVisit<MODE> v{e2, is_core, perm, parent, member, bestcore, true, false, 0, 0, 0, 0, 0,
-                    {0, 0, 0, 0}, {}, 0, ~0ull << (drop ? *drop : 0u), deg, pl};
+                    {0, 0, 0, 0}, {}, 0, ~0ull << (drop ? *drop : 0u), deg};
   v.grid.load(bounds);
   wave_walks(nodes, leaf, keys, n, wc, v, err);
   if (MODE == COUNT) {  // pairs, internal visits, descents, leaf tests
@@ -156,35 +154,16 @@ __global__ void k_pairs(const Node* __restrict__ nodes, const float4* __restrict
   }
 }
 
-// The main phase from the counting walk's pair list: each recorded pair
-// (i, j) does what the pair walk's hit would (both core: union; one core:
-// the other's border candidate), unless the list overflowed, when the walk
-// runs instead.  Unused slots hold (~0, ~0).
-__global__ __launch_bounds__(256) void k_pairs_list(PairList pl, const uint8_t* __restrict__ is_core,
-                                                   const uint32_t* __restrict__ perm,
-                                                   int32_t* parent,
-                                                   unsigned long long* bestcore) {
-  if (*pl.full) return;
-  const uint32_t region = pair_list_region(pl.cap);
-  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < 8u * region;
-       t += gridDim.x * blockDim.x) {
-    const uint32_t x = t / region;
-    if (t - x * region >= min(pl.ctr[x], region)) continue;  // past the region's reservations
-    const uint2 e = pl.list[t];
-    if (e.x == ~0u) continue;
-    const int32_t i = int32_t(e.x), j = int32_t(e.y);
-    const bool ci = is_core[i] != 0, cj = is_core[j] != 0;
-    if (ci && cj) uf_union(parent, perm, i, j);
-    else if (ci) atomicMin(bestcore + j, (static_cast<unsigned long long>(perm[i]) << 32) | uint32_t(i));
-    else if (cj) atomicMin(bestcore + i, (static_cast<unsigned long long>(perm[j]) << 32) | uint32_t(j));
-  }
-}
-
 // core flags from the pair counts: the point itself counts too
+// (and the number of core points, one atomic per wave)
 __global__ __launch_bounds__(256) void k_degree_flags(uint32_t n, const uint32_t* __restrict__ deg,
-                                                     int32_t min_pts, uint8_t* __restrict__ flag) {
+                                                     int32_t min_pts, uint8_t* __restrict__ flag,
+                                                     uint32_t* __restrict__ ncore) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) flag[i] = int64_t(deg[i]) + 1 >= int64_t(min_pts);
+  const bool core = i < n && int64_t(deg[i]) + 1 >= int64_t(min_pts);
+  if (i < n) flag[i] = core;
+  const uint64_t m = __ballot(core);
+  if (ncore && m && (threadIdx.x & 63) == 0) atomicAdd(ncore, uint32_t(__popcll(m)));
 }
 
 }  // namespace
@@ -234,27 +213,18 @@ void launch_pairs_fof(const Node* nodes, const float4* leaf, const uint64_t* key
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<FOF>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
                      keys, bounds, drop, n, walk_cfg(n), e2, nullptr, perm, parent,
-                     member, nullptr, nullptr, nullptr, PairList{}, nullptr, err);
+                     member, nullptr, nullptr, nullptr, nullptr, err);
 }
 
 void launch_pairs_core(const Node* nodes, const float4* leaf, const uint64_t* keys,
                        const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
                        const uint8_t* is_core, const uint32_t* perm, int32_t* parent,
-                       unsigned long long* bestcore, const uint32_t* only_if, uint32_t* err,
-                       int block, hipStream_t s) {
+                       unsigned long long* bestcore, const uint32_t* deg,
+                       const uint32_t* ncore, uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<CORE>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
                      keys, bounds, drop, n, walk_cfg(n), e2, is_core, perm, parent, nullptr,
-                     bestcore, nullptr, nullptr, PairList{}, only_if, err);
-}
-
-void launch_pairs_list(PairList pl, const uint8_t* is_core, const uint32_t* perm,
-                       int32_t* parent, unsigned long long* bestcore, hipStream_t s) {
-  if (pair_list_region(pl.cap) == 0) return;  // (then nothing was listed: the walk runs)
-  // a bounded grid striding over the list (its length is known on the device only)
-  const uint32_t blocks = std::max(1u, std::min((pl.cap + 255) / 256, 2048u));
-  hipLaunchKernelGGL(k_pairs_list, dim3(blocks), dim3(256), 0, s, pl, is_core, perm, parent,
-                     bestcore);
+                     bestcore, nullptr, const_cast<uint32_t*>(deg), ncore, err);
 }
 
 void launch_pairs_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
@@ -263,19 +233,19 @@ void launch_pairs_count(const Node* nodes, const float4* leaf, const uint64_t* k
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<COUNT>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
                      keys, bounds, drop, n, walk_cfg(n), e2, nullptr, nullptr, nullptr,
-                     nullptr, nullptr, count, nullptr, PairList{}, nullptr, err);
+                     nullptr, nullptr, count, nullptr, nullptr, err);
 }
 
 void launch_count_pairs(const Node* nodes, const float4* leaf, const uint64_t* keys,
                         const uint32_t* bounds, const uint32_t* drop, uint32_t n, float e2,
-                        int32_t min_pts, uint32_t* deg, uint8_t* is_core, PairList pl,
+                        int32_t min_pts, uint32_t* deg, uint8_t* is_core, uint32_t* ncore,
                         uint32_t* err, int block, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_pairs<DEGREE>, dim3(walk_grid(n, block)), dim3(block), 0, s, nodes, leaf,
                      keys, bounds, drop, n, walk_cfg(n), e2, nullptr, nullptr, nullptr,
-                     nullptr, nullptr, nullptr, deg, pl, nullptr, err);
+                     nullptr, nullptr, nullptr, deg, nullptr, err);
   hipLaunchKernelGGL(k_degree_flags, dim3((n + 255) / 256), dim3(256), 0, s, n, deg, min_pts,
-                     is_core);
+                     is_core, ncore);
 }
 
 }  // namespace dbx

@@ -31,12 +31,7 @@
 //                                               leaf j within eps; true ends
 //                                               the walk early
 //   void    end(uint32_t i)                     the walk of query i is over
-//
-// A visitor with kAppend also records every pair (i, j) it is shown in its
-// PairList `plist` (below), the whole wave at once after each step.
 #pragma once
-
-#include <type_traits>
 
 #include "pipeline.hpp"
 
@@ -94,55 +89,6 @@ struct WalkCfg {
 inline WalkCfg walk_cfg(uint32_t n, uint32_t* queue = nullptr) {
   return WalkCfg{walk_chunk_size(n), WALK_REFILL_AT, queue};
 }
-
-// PairList (pipeline.hpp), the pairs (i, j), i < j in sorted order, that a
-// pair walk found (in no particular order): appended by whole waves, each
-// wave reserving PAIR_LIST_CHUNK slots at a time of its XCD's region with
-// one atomic and marking the slots it leaves unused with (~0, ~0).  When a
-// reservation would pass the region's end the list is abandoned: *full is
-// set and nothing more is written, so the list's consumer knows to fall
-// back to a walk.
-constexpr uint32_t PAIR_LIST_CHUNK = 64;
-// The appending state of one wave (uniform across it).
-struct PairListWave {
-  uint32_t base = 0, used = PAIR_LIST_CHUNK;  // no chunk yet
-  bool off = false;                           // the list was abandoned
-  // The lanes in `hm` found pairs (i, j) in this step.  All lanes call it.
-  __device__ void append(const PairList& pl, uint64_t hm, bool mine, uint32_t i, int32_t j) {
-    if (off) return;
-    const int lane = threadIdx.x & 63;
-    const uint32_t k = uint32_t(__popcll(hm));
-    if (used + k > PAIR_LIST_CHUNK) {
-      close(pl);
-      const uint32_t x = blockIdx.x & 7u, region = pair_list_region(pl.cap);
-      uint32_t b = 0;
-      if (lane == 0) b = atomicAdd(pl.ctr + x, PAIR_LIST_CHUNK);
-      b = __builtin_amdgcn_readfirstlane(b);
-      if (uint64_t(b) + PAIR_LIST_CHUNK > region) {
-        if (lane == 0) atomicOr(pl.full, 1u);
-        off = true;
-        return;
-      }
-      base = x * region + b;
-      used = 0;
-    }
-    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    if (mine) pl.list[base + used + uint32_t(__popcll(hm & lt))] = make_uint2(i, uint32_t(j));
-    used += k;
-  }
-  // mark the rest of the current chunk unused (all lanes call it)
-  __device__ void close(const PairList& pl) {
-    if (off || used >= PAIR_LIST_CHUNK) return;
-    const uint32_t t = used + uint32_t(threadIdx.x & 63);
-    if (t < PAIR_LIST_CHUNK) pl.list[base + t] = make_uint2(~0u, ~0u);
-    used = PAIR_LIST_CHUNK;
-  }
-};
-template <class V, class = void>
-struct walk_appends : std::false_type {};
-template <class V>
-struct walk_appends<V, std::void_t<decltype(V::kAppend)>>
-    : std::integral_constant<bool, V::kAppend> {};
 
 // Persistent walks (PERSIST, with WalkCfg::queue): the grid holds only as
 // many waves as the GPU runs at once, and every wave takes spans of
@@ -209,7 +155,6 @@ __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
   int32_t node = SENTINEL;
   uint32_t steps = 0;
   bool by_rope = false;  // node was reached through a rope: its number is its first leaf
-  PairListWave plw;      // (visitors that record their pairs)
   float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
   for (;;) {
     if (PERSIST && head >= c1 && !drained) {  // the next span
@@ -267,31 +212,21 @@ __device__ __forceinline__ void wave_walks(const Node* __restrict__ nodes,
           act = false;
         }
       }
-      bool found = false;  // a pair (i, leaf_index(node)) this step
-      const int32_t here = node;
       if (act) {
         const bool near = box_sq_dist4(q, a, b) <= v.e2();
         v.visit(lf, near);
         // internal: left child (a.w) or rope (b.w); leaf: its rope (a.w = b.w)
         const bool down = near && !lf;
         int32_t next = down ? __float_as_int(a.w) : __float_as_int(b.w);
-        found = near && lf;
-        if (found && v.hit(i, leaf_index(node), q)) next = SENTINEL;
+        if (near && lf && v.hit(i, leaf_index(node), q)) next = SENTINEL;
         node = next;
         by_rope = !down;
-      }
-      if constexpr (walk_appends<V>::value) {
-        const uint64_t hm = __ballot(found);
-        if (hm && v.plist.list) plw.append(v.plist, hm, found, i, leaf_index(here));
       }
       const uint32_t busy = uint32_t(__popcll(__ballot(node != SENTINEL)));
       if (busy == 0 || ((head < c1 || (PERSIST && !drained)) && busy < refill_at)) break;
     }
   }
   if (have) v.end(i);
-  if constexpr (walk_appends<V>::value) {
-    if (v.plist.list) plw.close(v.plist);
-  }
 }
 
 }  // namespace dbx

@@ -349,12 +349,10 @@ def test_pair_count_core_flags(ctx, seed, mp):
 
 
 @pytest.mark.parametrize("mp", [3, 6])
-def test_pair_list_fits_and_overflows(ctx, mp):
-    """With counting by pair traversal the counting walk records its pairs
-    (at most n of them) and the main phase runs over that list; where there
-    are more pairs than points the list overflows and the main phase walks
-    instead.  A sparse field (about 0.2 pairs a point: the list), a tight
-    clump (thousands of neighbours a point: the walk) and both together."""
+def test_pair_count_sparse_dense_and_mixed(ctx, mp):
+    """With counting by pair traversal the main phase starts no walk at a
+    point with no neighbour: a sparse field (most points have none), a tight
+    clump (thousands of neighbours a point) and both together."""
     rng = np.random.Generator(np.random.PCG64(77 + mp))
     sparse = rng.random((60000, 3)).astype(F32)
     clump = (0.5 + rng.standard_normal((8000, 3)) * 0.004).astype(F32)
@@ -362,6 +360,20 @@ def test_pair_list_fits_and_overflows(ctx, mp):
     for p, eps in ((sparse, 0.012), (clump, 0.01), (both, 0.012)):
         np.testing.assert_array_equal(run(ctx, p, eps, mp, pair_count=True),
                                       oracle.dbscan(p, F32(eps), mp))
+
+
+def test_pair_count_no_core_point(ctx):
+    """Counting by pair traversal on a field with no core point (the main
+    phase starts no walk: every label is noise), between calls that have
+    core points (the core-point count starts from zero on every call)."""
+    rng = np.random.Generator(np.random.PCG64(79))
+    sparse = rng.random((60000, 3)).astype(F32)
+    ref = oracle.dbscan(sparse, F32(0.012), 12)
+    assert (ref == -1).all()
+    for eps, mp in ((0.012, 12), (0.012, 3), (0.012, 12), (0.05, 12)):
+        np.testing.assert_array_equal(run(ctx, sparse, eps, mp, pair_count=True),
+                                      ref if mp == 12 and eps == 0.012
+                                      else oracle.dbscan(sparse, F32(eps), mp))
 
 
 @pytest.mark.parametrize("mp", [2, 5, 10])
