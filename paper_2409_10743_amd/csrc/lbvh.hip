@@ -78,6 +78,7 @@ struct PointLeaves {
 // with the point's union-find state and label -1; later levels read the
 // written leaves.
 struct GatherLeaves {
+  static constexpr bool kPoint = true;
   const float* pts;
   const uint32_t* perm;
   uint32_t n;
@@ -197,7 +198,10 @@ __device__ __forceinline__ void grow(float4& lo, float4& hi, const float4& slo,
 // every node finished here has both range ends, so its number, in the
 // frame) live in LDS; the exchange is an LDS swap.  At the end the frame's
 // leaves and nodes go out whole, ropes included, in one coalesced pass,
-// with the exchange slots later levels still need.
+// with the exchange slots later levels still need.  A point leaf's box is
+// [p, p]: only its lower corner is kept, and the frame's codes share the
+// node boxes' LDS (they are done with before the climb), so that eight
+// workgroups fit a CU's LDS.
 template <class Leaves>
 __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
     const uint64_t* __restrict__ keys, Leaves lv, uint32_t n_bound,
@@ -206,7 +210,8 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
     uint32_t* __restrict__ err) {
   __shared__ uint64_t s_delta[BUILD_LEAVES + 2];  // delta of boundary f0-1+j at j
   __shared__ uint8_t s_cut[BUILD_LEAVES + 2];     // a set ends at boundary f0-1+j
-  __shared__ float4 s_leaf[BUILD_LEAVES], s_leafhi[BUILD_LEAVES];
+  constexpr bool kPt = Leaves::kPoint;
+  __shared__ float4 s_leaf[BUILD_LEAVES], s_leafhi[kPt ? 1 : BUILD_LEAVES];
   __shared__ float4 s_lo[BUILD_LEAVES], s_hi[BUILD_LEAVES];  // node number f0+k
   __shared__ int32_t s_left[BUILD_LEAVES], s_end[BUILD_LEAVES];  // its left child, last leaf
   __shared__ int32_t s_other[BUILD_LEAVES];  // exchange slot of split f0+k; -2 once finished
@@ -218,15 +223,23 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
   const int32_t f1 = min(f0 + BUILD_LEAVES, int32_t(n));
   const int32_t m = f1 - f0;
   const uint64_t mask = set_mask_of(set_shift);
+  // upper corner of leaf f0+k
+  auto leaf_hi = [&](int32_t k) -> const float4& { return kPt ? s_leaf[k] : s_leafhi[k]; };
+  auto load_leaf = [&](int32_t k) {
+    float4 h;
+    lv.load(f0 + k, s_leaf[k], kPt ? h : s_leafhi[k]);
+  };
   if constexpr (codes_here<Leaves>::value) {
     // codes of leaves f0-1 .. f1+1 (at j = 0 .. m+2) from their points;
-    // no set bits here
-    __shared__ uint64_t s_code[BUILD_LEAVES + 3];
+    // no set bits here.  In s_lo: read before the barrier ahead of the climb,
+    // which writes s_lo.
+    static_assert(sizeof(s_lo) >= (BUILD_LEAVES + 3) * sizeof(uint64_t), "codes fit s_lo");
+    uint64_t* s_code = reinterpret_cast<uint64_t*>(s_lo);
     MortonGrid grid;
     grid.load(lv.bounds);
     const uint64_t cmask = ~0ull << *lv.drop;
     if (t < m) {
-      lv.load(f0 + t, s_leaf[t], s_leafhi[t]);
+      load_leaf(t);
       const uint64_t c = grid.code(s_leaf[t].x, s_leaf[t].y, s_leaf[t].z) & cmask;
       s_code[t + 1] = c;
       lv.keys_out[f0 + t] = c;
@@ -255,7 +268,7 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
       s_delta[j] = ok ? delta(keys, b) : 0ull;
       s_cut[j] = ok ? set_cut(keys, b, mask) : 1;
     }
-    if (t < m) lv.load(f0 + t, s_leaf[t], s_leafhi[t]);
+    if (t < m) load_leaf(t);
   }
   s_other[t] = -1;
   s_end[t] = -1;
@@ -268,7 +281,7 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
     if (spans(j0, j0)) set_root[set_of(keys, j0, set_shift)] = leaf_ref(j0);
     if (n > 1) {
       int32_t l = j0, r = j0, g = -1;  // g: split of the node, -1 for the leaf
-      float4 lo = s_leaf[t], hi = s_leafhi[t];
+      float4 lo = s_leaf[t], hi = leaf_hi(t);
       for (;;) {
         const bool is_left = left_side(l, r, last, D(r), D(l - 1));
         if (g >= 0) {  // finished here: its number is known now
@@ -296,7 +309,7 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
         const int32_t sl = is_left ? par + 1 : l, sr = is_left ? r : par;
         if (sl < f0 || sr > f1 - 1 || sl > sr) { atomicOr(err, STATUS_TREE); break; }
         if (sl == sr) {
-          grow(lo, hi, s_leaf[sl - f0], s_leafhi[sl - f0]);
+          grow(lo, hi, s_leaf[sl - f0], leaf_hi(sl - f0));
         } else {
           const int32_t sk = (is_left ? sl : sr) - f0;  // right child: first leaf; left: last
           grow(lo, hi, s_lo[sk], s_hi[sk]);
@@ -319,7 +332,7 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_build_frame(
   // is never touched here: -1)
   const int32_t p = f0 + t;
   if (t < m) {  // n = 1 too: the one leaf still goes out
-    lv.write_out(p, s_leaf[t], s_leafhi[t], rope_of(p, last, s_cut[t + 1], D(p), D(p + 1)));
+    lv.write_out(p, s_leaf[t], leaf_hi(t), rope_of(p, last, s_cut[t + 1], D(p), D(p + 1)));
     const int32_t r = s_end[t];
     if (r >= 0)
       write_node(nodes, p, s_lo[t], s_hi[t], s_left[t],
