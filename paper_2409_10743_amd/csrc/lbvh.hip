@@ -611,6 +611,12 @@ size_t build_pending_entries(uint32_t n) {
 }
 
 namespace {
+// Hand-over entries one workgroup takes to the root.  Not more: the top
+// climb is a chain of dependent memory round trips, and 1,024 entries on
+// one CU took 120 us on the 2^24-point field where a level launch of four
+// workgroups and a top block of 256 threads take 80 us.
+constexpr uint32_t BUILD_TOP_ENTRIES = 256;
+
 // log2 of the exchange table slots of a level block of `threads` threads
 uint32_t level_tab_log2(uint32_t threads) {
   uint32_t t = 6;
@@ -639,7 +645,7 @@ void build_impl(const uint64_t* keys, int set_shift, FrameLeaves flv, Leaves lv,
     if (lv_i == 1) {
       hipLaunchKernelGGL(k_build_frame<FrameLeaves>, dim3(frames), dim3(BUILD_BLOCK), 0, s, keys,
                          flv, n, n_dev, set_shift, nodes, other, root, pout, err);
-    } else if (entries <= 1024) {
+    } else if (entries <= BUILD_TOP_ENTRIES) {
       // few enough nodes left for one workgroup: it climbs them all to the
       // root (one frame over every leaf), in place of the remaining levels
       const uint32_t threads = (entries + 63) / 64 * 64;
