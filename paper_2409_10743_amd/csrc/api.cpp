@@ -451,9 +451,10 @@ int run_fdbscan(dbscan_ctx* c, const float* pts, uint32_t n, float eps, int32_t 
       launch_count(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, ix.root, e2,
                    min_pts, flag, ix.status, block, gs);
     mark(c, timing, PH_COUNT, gs);
-    // with the counts of the pair traversal at hand, points with no
-    // neighbour (most of a sparse field) start no main-phase walk, and with
-    // no core point at all no walk starts
+    // with the counts of the pair traversal at hand, points whose counting
+    // walk found no pair (most of a sparse field, and the last point of
+    // every pair) start no main-phase walk, and with no core point at all
+    // no walk starts
     if (core_mode)
       launch_pairs_core(ix.nodes, ix.leaf, ix.keys, ix.bounds, ix.drop, n, e2, flag,
                         ix.perm, parent, bestcore, pair_count ? deg : nullptr, ncore,

@@ -148,8 +148,9 @@ void launch_count(const Node* nodes, const float4* leaf, const uint64_t* keys,
                   uint32_t n, const int32_t* root, float e2, int32_t min_pts, uint8_t* is_core,
                   uint32_t* err, int block, hipStream_t s);
 // Core flags by pair traversal: each pair adds one to both points' counts
-// in deg (zero beforehand), then is_core[i] = deg[i] + 1 >= min_pts.  No
-// early exit: for fields where points have few neighbours.
+// in deg (zero beforehand; bit 31 set where the point's own walk found a
+// pair), then is_core[i] = count + 1 >= min_pts.  No early exit: for
+// fields where points have few neighbours.
 // ncore (may be null; zeroed before): gets the number of core points.
 void launch_count_pairs(const Node* nodes, const float4* leaf, const uint64_t* keys,
                         const uint32_t* bounds, const uint32_t* drop,
@@ -163,8 +164,9 @@ void launch_pairs_fof(const Node* nodes, const float4* leaf, const uint64_t* key
 // minPts > 2: union core pairs, record each non-core point's smallest-index
 // core neighbour.
 // deg, ncore (may be null): neighbour counts and the number of core points
-// from a counting pass by pair traversal; a point with no neighbour starts
-// no walk (it is in no pair), and with no core point no walk starts.
+// from a counting pass by pair traversal; a point whose counting walk found
+// no pair starts no walk (this one would find none either), and with no
+// core point no walk starts.
 void launch_pairs_core(const Node* nodes, const float4* leaf, const uint64_t* keys,
                        const uint32_t* bounds, const uint32_t* drop,
                        uint32_t n, float e2, const uint8_t* is_core, const uint32_t* perm,

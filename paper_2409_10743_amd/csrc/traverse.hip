@@ -58,6 +58,11 @@ __global__ void k_count(const Node* __restrict__ nodes, const float4* __restrict
 
 enum PairMode { FOF = 0, CORE = 1, COUNT = 2, DEGREE = 3 };
 
+// Counting by pair traversal: the top bit of a point's count marks that
+// its own walk (leaves after it) found a pair.
+constexpr uint32_t DEG_FORWARD = 1u << 31;
+static_assert(SORT_MAX_N < DEG_FORWARD / 2, "counts below 2^30 leave the bit free");
+
 // pair traversal: query i starts at its own leaf's rope (leaves j > i only)
 template <int MODE>
 struct PairVisit {
@@ -75,12 +80,15 @@ struct PairVisit {
   unsigned long long tot[4];                 // COUNT only: this lane's totals
   MortonGrid grid;
   uint64_t hi, mask;
-  uint32_t* deg;  // DEGREE: neighbour counts (self excluded); CORE: the same, read (or null)
+  // DEGREE: neighbour counts (self excluded) with DEG_FORWARD set where the
+  // point's own walk found a pair; CORE: the same, read (or null)
+  uint32_t* deg;
   __device__ uint64_t khi() const { return hi; }
   __device__ int32_t begin(uint32_t i, const float4& q) {
     found = false;
     ri = int32_t(i);
-    if (MODE == CORE && deg && deg[i] == 0u) return SENTINEL;  // no neighbour: no pair from i
+    // the counting walk from i found no pair: neither will this one
+    if (MODE == CORE && deg && !(deg[i] & DEG_FORWARD)) return SENTINEL;
     hi = grid.upper_code(q, r2) & mask;
     if (MODE == COUNT || MODE == DEGREE) pairs = visits = descents = leaves = 0;
     if (MODE == CORE) ci = is_core[i] != 0;
@@ -118,7 +126,8 @@ struct PairVisit {
   }
   __device__ void end(uint32_t i) {
     if (MODE == FOF && found) member[i] = 1;
-    if (MODE == DEGREE && pairs) atomicAdd(deg + i, pairs);  // others may add to it too
+    // others may add to it too; counts stay below 2^30 (n does)
+    if (MODE == DEGREE && pairs) atomicAdd(deg + i, pairs | DEG_FORWARD);
     if (MODE == COUNT) {  // a query's counts are below 2n, so 32 bits hold them
       tot[0] += pairs; tot[1] += visits; tot[2] += descents; tot[3] += leaves;
     }
@@ -160,7 +169,7 @@ __global__ __launch_bounds__(256) void k_degree_flags(uint32_t n, const uint32_t
                                                      int32_t min_pts, uint8_t* __restrict__ flag,
                                                      uint32_t* __restrict__ ncore) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool core = i < n && int64_t(deg[i]) + 1 >= int64_t(min_pts);
+  const bool core = i < n && int64_t(deg[i] & ~DEG_FORWARD) + 1 >= int64_t(min_pts);
   if (i < n) flag[i] = core;
   const uint64_t m = __ballot(core);
   if (ncore && m && (threadIdx.x & 63) == 0) atomicAdd(ncore, uint32_t(__popcll(m)));
