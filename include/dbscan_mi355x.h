@@ -86,7 +86,10 @@ extern "C" {
  * of a walk per point from the root (of its set) that stops at min_pts
  * (section 4.1.2).  Faster where points have few neighbours (no walk from
  * the root), slower in dense regions (no early exit); labels are the same.
- * The autotuners try both.  Ignored otherwise (batched FDBSCAN). */
+ * With plain FDBSCAN the counts also spare the main phase: it walks only
+ * from points whose counting walk found a pair, and not at all when no
+ * point is core.  The autotuners try both.  Ignored otherwise (batched
+ * FDBSCAN). */
 #define DBSCAN_FLAG_PAIR_COUNT 4u
 
 typedef struct dbscan_options {
